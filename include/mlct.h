@@ -1,0 +1,247 @@
+/*
+ * mlct.h - multilevel Chebyshev-Hutchinson trace estimation on gfx950.
+ *
+ * C ABI of libmlct.so.  The library estimates tr f(A) for a symmetric matrix
+ * A (Section 1, eq. def:trace) by Hutchinson's estimator over Rademacher
+ * probes (Section 2.1, eq. def:mcEstimate), with f replaced by its degree-n
+ * Chebyshev interpolant on an interval [a, b] that contains the spectrum
+ * (Section 2.2, eqs. eqn:recurrence and eqn:chebSeries), split into levels
+ * (Section 3, eqs. def:qlevels and eqn:decomposition) and combined by the
+ * multilevel estimator (Section 4, eq. eqn:multiEstimator).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns an mlct_status.  Arguments are validated before
+ *    any device work is enqueued; on error the outputs are left untouched and
+ *    mlct_last_error(ctx) describes the reason.  No C++ exception crosses
+ *    this boundary.
+ *  - Matrix and probe buffers passed in are DEVICE pointers owned by the
+ *    caller; they are borrowed and must stay valid (and unmodified) while an
+ *    operator handle that refers to them is in use.
+ *  - Output arrays are HOST pointers unless the parameter name ends in _dev.
+ *  - Device work is enqueued on the stream given to mlct_create.  A call that
+ *    returns host results synchronises that stream before returning.
+ *  - Calls on one context are not thread-safe; use one context per thread.
+ *  - The library allocates its own device workspace (grow-only, owned by the
+ *    context, freed by mlct_destroy).
+ */
+#ifndef MLCT_H
+#define MLCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLCT_OK = 0,
+  MLCT_EINVAL = 1,       /* invalid argument (shape, pointer, interval, CSR) */
+  MLCT_ENOMEM = 2,       /* device workspace allocation failed or over cap  */
+  MLCT_EDEVICE = 3,      /* a HIP runtime call failed                       */
+  MLCT_ESPECTRUM = 4,    /* |mu_j| > |z|^2 (1 + 1e-3): spectrum outside [a,b] */
+  MLCT_ERANGE = 5,       /* coefficients or result not representable        */
+  MLCT_EUNSUPPORTED = 6  /* valid request this build does not implement     */
+} mlct_status;
+
+/* f in tr f(A) (Section 1: log-determinant, trace of inverse, Estrada
+ * index, Schatten norms via A = X^T X; Section 5: sqrt, log, exp, x^3). */
+typedef enum {
+  MLCT_LOG = 0,   /* f(x) = log x      (needs a > 0)                  */
+  MLCT_SQRT = 1,  /* f(x) = sqrt x     (needs a >= 0)                 */
+  MLCT_EXP = 2,   /* f(x) = exp x      (result carries a log-scale)   */
+  MLCT_CUBE = 3,  /* f(x) = x^3                                       */
+  MLCT_INV = 4,   /* f(x) = 1/x        (needs 0 outside [a, b])       */
+  MLCT_POW = 5    /* f(x) = x^power    (needs a >= 0)                 */
+} mlct_func_kind;
+
+typedef struct {
+  int32_t kind;  /* mlct_func_kind */
+  double power;  /* exponent for MLCT_POW, ignored otherwise */
+} mlct_func;
+
+/* Arithmetic of the recurrence.  FP32: FP32 vectors and matrix, FP32
+ * products, FP64 moment accumulation.  FP64: everything FP64.  BF16X3: dense
+ * operators only, A and V split into bf16 hi+lo parts, three bf16 MFMA
+ * products (hi*hi + hi*lo + lo*hi) accumulated in FP32. */
+typedef enum {
+  MLCT_FP64 = 0,
+  MLCT_FP32 = 1,
+  MLCT_BF16X3 = 2
+} mlct_prec;
+
+/* How moments are formed (Section 2.2, Section 3.1).  DIRECT: n matvecs,
+ * mu_j = z . T_j(A_hat) z.  DOUBLING: ceil(n/2) matvecs, mu_{2k} =
+ * 2 v_k.v_k - mu_0 and mu_{2k+1} = 2 v_{k+1}.v_k - mu_1.  OR-ing
+ * MLCT_LEVEL_INTERP into the mode of mlct_estimate gives every level its own
+ * interpolant of degree l_k instead of truncating the top one. */
+typedef enum {
+  MLCT_DIRECT = 0,
+  MLCT_DOUBLING = 1
+} mlct_mode;
+#define MLCT_LEVEL_INTERP 0x10
+
+typedef enum {
+  MLCT_DT_F32 = 0,
+  MLCT_DT_F64 = 1,
+  MLCT_DT_PATTERN = 2  /* CSR without values: every stored entry is 1 */
+} mlct_dtype;
+
+typedef enum {
+  MLCT_PROBE_RADEMACHER = 0, /* counter-based, see mlct_probes              */
+  MLCT_PROBE_EXPLICIT = 1    /* caller's int8 entries (e.g. Hadamard, e_i)  */
+} mlct_probe_kind;
+
+/* A set of m probe vectors z^(0..m-1) of length d.
+ * RADEMACHER: z^(p) is probe id (first_id + p) of generator ``seed``:
+ *   key = SplitMix64 output number id of a stream started at seed,
+ *   word_c = SplitMix64 output number c of a stream started at key,
+ *   z_i = +1 if bit (i mod 64) of word_{i/64} is 0, else -1
+ *   (SplitMix64: Steele, Lea & Flood, OOPSLA 2014).
+ * EXPLICIT: entries_dev is a device int8 array, row-major d x ld_entries;
+ *   z^(p)_i = entries_dev[i * ld_entries + first_id + p]. */
+typedef struct {
+  int32_t kind;
+  uint64_t seed;
+  int64_t first_id;
+  int64_t m;
+  const int8_t* entries_dev;
+  int64_t ld_entries;
+} mlct_probes;
+
+#define MLCT_MAX_LEVELS 32
+
+/* Levels 0 <= degree[0] < ... < degree[L-1] = n and samples per level
+ * (Section 3, eq. eqn:decomposition; Section 4, eq. eqn:multiEstimator). */
+typedef struct {
+  int32_t L;
+  const int32_t* degree;  /* host, L entries */
+  const int64_t* m;       /* host, L entries, each >= 1 */
+} mlct_levels;
+
+/* Result of an estimate.  value = Gamma (eq. eqn:multiEstimator);
+ * estimate = value * exp(log_scale) (log_scale != 0 only for MLCT_EXP,
+ * where exp((a+b)/2) is factored out of the coefficients). */
+typedef struct {
+  double estimate;
+  double value;
+  double log_scale;
+  double est_var;                     /* sum_k s_k^2 / m_k, units of value */
+  double level_mean[MLCT_MAX_LEVELS]; /* mean of Q_{l_{k-1} l_k}          */
+  double level_var[MLCT_MAX_LEVELS];  /* unbiased sample variance s_k^2   */
+  int64_t matvecs;                    /* probe-matvecs applied            */
+  int64_t probe_degrees;              /* sum_k m_k * l_k                  */
+  double max_moment_ratio;            /* max_j |mu_j| / mu_0 over probes  */
+  uint32_t flags;                     /* MLCT_FLAG_* bits                 */
+} mlct_result;
+
+#define MLCT_FLAG_FEW_SAMPLES 0x1u /* some m_k < 2: its variance is NaN    */
+#define MLCT_FLAG_OVERFLOW 0x2u    /* estimate not finite (see log_scale)  */
+#define MLCT_FLAG_BF16 0x4u        /* BF16X3 arithmetic was used           */
+
+typedef struct mlct_ctx mlct_ctx;
+typedef struct mlct_op mlct_op;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context bound to HIP device ``device`` and stream ``hip_stream``
+ * (a hipStream_t; NULL = the null stream).  tune_cache_path may be NULL. */
+mlct_status mlct_create(int device, void* hip_stream, const char* tune_cache_path,
+                        mlct_ctx** out);
+mlct_status mlct_destroy(mlct_ctx* ctx);
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char* mlct_last_error(const mlct_ctx* ctx);
+/* Cap on the context's device workspace in bytes (0 = no cap).  A call that
+ * would exceed it fails with MLCT_ENOMEM before enqueuing any work. */
+mlct_status mlct_set_workspace_limit(mlct_ctx* ctx, uint64_t bytes);
+
+/* Per-kernel device time of the library's own launches, measured with HIP
+ * events recorded on the context stream around every launch of the kernel
+ * families below while timing is enabled (used for roofline figures).
+ * mlct_timing(ctx, 1) resets the counters and starts timing; (ctx, 0) stops.
+ * mlct_timing_read returns the launches and summed milliseconds collected by
+ * calls that completed since timing was enabled. */
+typedef enum {
+  MLCT_KERNEL_CSR_STEP = 0,   /* one recurrence step over a CSR operator   */
+  MLCT_KERNEL_DENSE_STEP = 1, /* one recurrence step over a dense operator */
+  MLCT_KERNEL_TRI_STEP = 2,   /* one integer triangle-moment SpMM          */
+  MLCT_KERNEL_GRAM = 3,       /* Gram matrix formation                     */
+  MLCT_NUM_KERNEL_IDS = 8
+} mlct_kernel_id;
+mlct_status mlct_timing(mlct_ctx* ctx, int32_t enable);
+mlct_status mlct_timing_read(const mlct_ctx* ctx, int32_t kernel, int64_t* launches,
+                             double* total_ms);
+
+/* ---- operators (the only access to A, Section 2.1) ---------------------- */
+
+/* Operators keep a pointer to their context: destroy every operator before
+ * the context it was created on. */
+
+/* Symmetric sparse A in CSR form: rowptr[d+1] and col[nnz] int32 (device),
+ * values float32 (MLCT_DT_F32) or absent (val_dev = NULL, MLCT_DT_PATTERN).
+ * Columns within a row need not be sorted; duplicates are summed.  The
+ * structure is validated on the device at creation: rowptr[0] = 0,
+ * non-decreasing, rowptr[d] = nnz, 0 <= col < d; violations give EINVAL. */
+mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* rowptr_dev,
+                        const int32_t* col_dev, const void* val_dev, int32_t dtype,
+                        mlct_op** out);
+/* Symmetric dense A, row-major d x d with leading dimension lda >= d,
+ * float64 (MLCT_DT_F64) or float32 (MLCT_DT_F32). */
+mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t d, const void* A_dev, int64_t lda,
+                          int32_t dtype, mlct_op** out);
+/* A = X^T X for X row-major rows x cols (leading dimension ldx >= cols),
+ * float32.  The Gram matrix (cols x cols) is formed once on the device, in
+ * the arithmetic ``prec`` (MLCT_FP32 or MLCT_BF16X3), and owned by the op. */
+mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t rows, int64_t cols, const void* X_dev,
+                         int64_t ldx, int32_t dtype, int32_t prec, mlct_op** out);
+mlct_status mlct_op_destroy(mlct_op* op);
+
+/* ---- building blocks ---------------------------------------------------- */
+
+/* Chebyshev coefficients c_0..c_n of f mapped from [a, b] to [-1, 1]: the
+ * interpolant at x_k = cos(k pi / n) (Section 2.2), by a type-I DCT in FP64
+ * on the device.  c_out: host, n+1 doubles.  log_scale_out (may be NULL):
+ * (a+b)/2 for MLCT_EXP (coefficients are those of exp((b-a)/2 x)), else 0. */
+mlct_status mlct_cheb_coeffs(mlct_ctx* ctx, mlct_func f, double a, double b, int32_t n,
+                             double* c_out, double* log_scale_out);
+
+/* Moments mu[p][j] = z^(p)T T_j(A_hat) z^(p), j = 0..n, p = 0..m-1, with
+ * A_hat = 2/(b-a) A - (a+b)/(b-a) I (Section 2.2).  mu_out: host, m x (n+1)
+ * row-major doubles.  mode: MLCT_DIRECT or MLCT_DOUBLING. */
+mlct_status mlct_moments(mlct_ctx* ctx, const mlct_op* op, double a, double b, int32_t n,
+                         const mlct_probes* probes, int32_t prec, int32_t mode,
+                         double* mu_out);
+
+/* Spectral interval by ``steps`` FP64 Lanczos steps with full
+ * reorthogonalisation from Rademacher probe 0 of ``seed``: extreme Ritz values
+ * widened by their residual bounds and by rel_margin * (width). */
+mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64_t seed,
+                        double rel_margin, double* a_out, double* b_out);
+
+/* ---- estimators ---------------------------------------------------------- */
+
+/* Multilevel estimate of tr f(A) (Section 4, eq. eqn:multiEstimator).  Level
+ * k uses Rademacher probe ids [off_k, off_k + m_k), off_k = sum_{k'<k} m_k',
+ * so all samples are independent; Q uses the coefficients of the single
+ * degree-n interpolant (eq. def:qlevels) unless MLCT_LEVEL_INTERP is set.
+ * Returns MLCT_ESPECTRUM if some |mu_j| exceeds |z|^2 (1 + 1e-3). */
+mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
+                          const mlct_levels* levels, uint64_t seed, int32_t prec,
+                          int32_t mode, mlct_result* out);
+
+/* Triangle count tr(A^3)/6 of a 0/1 pattern CSR graph (Section 2.1 example,
+ * Section 5.5): per probe, exact int32 y = A z and w = A y with int64
+ * w1 = z.y, w2 = y.y, w3 = y.w.  w_out (host, m x 3 int64, may be NULL). */
+typedef struct {
+  int64_t sum_w3;
+  double estimate;     /* sum w3 / (6 m) */
+  double estimate_cv;  /* control-variate estimate (Section 5.5)           */
+  double a1, a2;       /* regression coefficients of w3 on (w1, w2)        */
+} mlct_tri_result;
+
+mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t seed,
+                           int64_t* w_out, mlct_tri_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLCT_H */

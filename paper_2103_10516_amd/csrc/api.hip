@@ -1,0 +1,531 @@
+// Host side of libmlct: argument validation, workspace, planning and the
+// C-ABI entry points declared in include/mlct.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace mlct;
+
+namespace {
+
+mlct_status fail(mlct_ctx* ctx, mlct_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+#define HIPCHK(ctx, expr)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((ctx), MLCT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHECK(expr)                    \
+  do {                                 \
+    mlct_status st_ = (expr);          \
+    if (st_ != MLCT_OK) return st_;    \
+  } while (0)
+
+// Grow-only workspace slot.  Growing frees the old buffer (hipFree waits for
+// the device), so pointers from an earlier ws_get of the same slot become
+// invalid; callers take all slots they need before enqueuing work.
+mlct_status ws_get(mlct_ctx* ctx, int slot, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  DevBuf& b = ctx->slots[slot];
+  if (b.bytes >= bytes) {
+    *out = b.ptr;
+    return MLCT_OK;
+  }
+  const uint64_t new_total = ctx->ws_total - b.bytes + bytes;
+  if (ctx->ws_limit && new_total > ctx->ws_limit)
+    return fail(ctx, MLCT_ENOMEM, "workspace of %llu bytes exceeds the limit of %llu",
+                (unsigned long long)new_total, (unsigned long long)ctx->ws_limit);
+  if (b.ptr) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipFree(b.ptr));
+    ctx->ws_total -= b.bytes;
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MLCT_ENOMEM, "hipMalloc(%zu) failed", bytes);
+  }
+  b.ptr = p;
+  b.bytes = bytes;
+  ctx->ws_total += bytes;
+  *out = p;
+  return MLCT_OK;
+}
+
+// ---- kernel timing --------------------------------------------------------
+hipEvent_t pool_event(mlct_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records a start event before a launch and a stop event after it when
+// timing is enabled; durations are collected after the next synchronisation.
+struct LaunchTimer {
+  mlct_ctx* ctx;
+  int kernel;
+  hipEvent_t start = nullptr;
+  LaunchTimer(mlct_ctx* c, int k) : ctx(c), kernel(k) {
+    if (ctx->timing && (start = pool_event(ctx))) (void)hipEventRecord(start, ctx->stream);
+  }
+  void done() {
+    if (!start) return;
+    hipEvent_t stop = pool_event(ctx);
+    if (!stop) {
+      ctx->event_pool.push_back(start);
+      return;
+    }
+    (void)hipEventRecord(stop, ctx->stream);
+    ctx->pending.push_back({start, stop, kernel});
+    start = nullptr;
+  }
+};
+
+// Called after the context stream has been synchronised.
+void collect_timing(mlct_ctx* ctx) {
+  for (auto& t : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+      ctx->kernel_ms[t.kernel] += ms;
+      ctx->kernel_launches[t.kernel] += 1;
+    }
+    ctx->event_pool.push_back(t.start);
+    ctx->event_pool.push_back(t.stop);
+  }
+  ctx->pending.clear();
+}
+
+mlct_status sync_stream(mlct_ctx* ctx) {
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  collect_timing(ctx);
+  return MLCT_OK;
+}
+
+mlct_status set_device(mlct_ctx* ctx) {
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  return MLCT_OK;
+}
+
+bool finite_interval(double a, double b) { return std::isfinite(a) && std::isfinite(b) && a < b; }
+
+mlct_status check_func(mlct_ctx* ctx, mlct_func f, double a, double b) {
+  if (!finite_interval(a, b)) return fail(ctx, MLCT_EINVAL, "need finite a < b (a=%g b=%g)", a, b);
+  switch (f.kind) {
+    case MLCT_LOG:
+      if (a <= 0) return fail(ctx, MLCT_EINVAL, "log needs a > 0 (a=%g)", a);
+      break;
+    case MLCT_SQRT:
+    case MLCT_POW:
+      if (a < 0) return fail(ctx, MLCT_EINVAL, "sqrt/pow need a >= 0 (a=%g)", a);
+      if (f.kind == MLCT_POW && !std::isfinite(f.power))
+        return fail(ctx, MLCT_EINVAL, "pow needs a finite exponent");
+      break;
+    case MLCT_INV:
+      if (a <= 0 && b >= 0) return fail(ctx, MLCT_EINVAL, "1/x needs 0 outside [a, b]");
+      break;
+    case MLCT_EXP:
+      if ((b - a) / 2 > 700)
+        return fail(ctx, MLCT_ERANGE, "exp on an interval of half-width %g overflows FP64", (b - a) / 2);
+      break;
+    case MLCT_CUBE:
+      break;
+    default:
+      return fail(ctx, MLCT_EINVAL, "unknown function kind %d", f.kind);
+  }
+  return MLCT_OK;
+}
+
+constexpr int kMaxDegree = 4096;  // DCT samples live in 32 KB of LDS
+
+mlct_status check_probes(mlct_ctx* ctx, const mlct_op* op, const mlct_probes* pr) {
+  if (!pr) return fail(ctx, MLCT_EINVAL, "probes is NULL");
+  if (pr->m < 1) return fail(ctx, MLCT_EINVAL, "need m >= 1 probes");
+  if (pr->kind == MLCT_PROBE_RADEMACHER) {
+    if (pr->first_id < 0) return fail(ctx, MLCT_EINVAL, "first_id must be >= 0");
+    return MLCT_OK;
+  }
+  if (pr->kind == MLCT_PROBE_EXPLICIT) {
+    if (!pr->entries_dev) return fail(ctx, MLCT_EINVAL, "explicit probes need entries_dev");
+    if (pr->first_id < 0 || pr->ld_entries < pr->first_id + pr->m)
+      return fail(ctx, MLCT_EINVAL, "explicit probes: need 0 <= first_id and first_id + m <= ld");
+    (void)op;
+    return MLCT_OK;
+  }
+  return fail(ctx, MLCT_EINVAL, "unknown probe kind %d", pr->kind);
+}
+
+// ---- one probe block through the recurrence ------------------------------
+// Runs ``degree`` (direct) or ceil(degree/2) (symmetric form) steps on the
+// ``src.active`` probes of one block and writes their moments mu_0..mu_n
+// (n = degree) into mu_rows (device, row stride ldmu).
+template <typename T>
+mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
+                          int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu) {
+  const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
+  const CsrStepPlan plan = plan_csr(op->d);
+  const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(T);
+  const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;  // doubles per step
+  void *v0, *v1, *part, *dots;
+  CHECK(ws_get(ctx, WS_V0, vbytes, &v0));
+  CHECK(ws_get(ctx, WS_V1, vbytes, &v1));
+  CHECK(ws_get(ctx, WS_PART, pstep * (S + 1) * sizeof(double), &part));
+  CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &dots));
+  T* buf[2] = {static_cast<T*>(v0), static_cast<T*>(v1)};
+  double* P = static_cast<double*>(part);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_probe_init<T>(s, buf[0], op->d, src, plan, P));
+  const int zdirect = src.entries ? 2 : 1;
+  for (int k = 1; k <= S; ++k) {
+    // v_k = ca A v_{k-1} + cb v_{k-1} [- v_{k-2}], written over v_{k-2}
+    const T* vk = buf[(k - 1) & 1];
+    T* vm = buf[k & 1];
+    const bool first = (k == 1);
+    const T ca = (T)(first ? alpha : 2.0 * alpha);
+    const T cb = (T)(first ? beta : 2.0 * beta);
+    const int zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
+    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
+    HIPCHK(ctx, launch_csr_step<T>(s, op, vk, vm, ca, cb, !first, zmode, src, plan, P + pstep * k));
+    tm.done();
+  }
+  HIPCHK(ctx, launch_reduce_partials(s, P, S + 1, 2, plan.ngroups, kBlockProbes,
+                                     static_cast<double*>(dots)));
+  HIPCHK(ctx, launch_assemble_moments(s, static_cast<double*>(dots), S + 1, kBlockProbes,
+                                      src.active, mode, degree, mu_rows, ldmu));
+  return MLCT_OK;
+}
+
+mlct_status run_block(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta, int degree,
+                      int mode, int prec, ProbeSrc src, double* mu_rows, int64_t ldmu) {
+  if (op->kind == OP_CSR) {
+    if (prec == MLCT_FP32)
+      return run_block_csr<float>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
+    if (prec == MLCT_FP64)
+      return run_block_csr<double>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
+    return fail(ctx, MLCT_EUNSUPPORTED, "CSR operators support MLCT_FP32 and MLCT_FP64");
+  }
+  return fail(ctx, MLCT_EUNSUPPORTED, "operator kind %d not supported yet", op->kind);
+}
+
+// Moments of probes [0, m) of a probe set, in blocks of kBlockProbes.
+mlct_status run_probe_set(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
+                          int degree, int mode, int prec, const mlct_probes* pr, double* mu_dev,
+                          int64_t ldmu) {
+  for (int64_t p0 = 0; p0 < pr->m; p0 += kBlockProbes) {
+    ProbeSrc src;
+    src.seed = pr->seed;
+    src.first_id = pr->first_id + p0;
+    src.entries = pr->kind == MLCT_PROBE_EXPLICIT ? pr->entries_dev : nullptr;
+    src.ld = pr->ld_entries;
+    src.active = (int32_t)((pr->m - p0) < kBlockProbes ? (pr->m - p0) : kBlockProbes);
+    CHECK(run_block(ctx, op, alpha, beta, degree, mode, prec, src, mu_dev + p0 * ldmu, ldmu));
+  }
+  return MLCT_OK;
+}
+
+mlct_status check_mode_prec(mlct_ctx* ctx, int mode, int prec) {
+  if (mode != MLCT_DIRECT && mode != MLCT_DOUBLING)
+    return fail(ctx, MLCT_EINVAL, "unknown mode %d", mode);
+  if (prec != MLCT_FP32 && prec != MLCT_FP64 && prec != MLCT_BF16X3)
+    return fail(ctx, MLCT_EINVAL, "unknown precision %d", prec);
+  return MLCT_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+mlct_status mlct_create(int device, void* hip_stream, const char* tune_cache_path,
+                        mlct_ctx** out) {
+  (void)tune_cache_path;
+  if (!out) return MLCT_EINVAL;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return MLCT_EDEVICE;
+  }
+  mlct_ctx* ctx = new (std::nothrow) mlct_ctx();
+  if (!ctx) return MLCT_ENOMEM;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->slots.resize(WS_NSLOTS);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return MLCT_EDEVICE;
+  }
+  *out = ctx;
+  return MLCT_OK;
+}
+
+mlct_status mlct_destroy(mlct_ctx* ctx) {
+  if (!ctx) return MLCT_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& b : ctx->slots)
+    if (b.ptr) (void)hipFree(b.ptr);
+  for (auto& t : ctx->pending) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  delete ctx;
+  return MLCT_OK;
+}
+
+const char* mlct_last_error(const mlct_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mlct_status mlct_timing(mlct_ctx* ctx, int32_t enable) {
+  if (!ctx) return MLCT_EINVAL;
+  if (enable) {
+    for (int k = 0; k < MLCT_NUM_KERNEL_IDS; ++k) {
+      ctx->kernel_ms[k] = 0.0;
+      ctx->kernel_launches[k] = 0;
+    }
+  }
+  ctx->timing = enable != 0;
+  return MLCT_OK;
+}
+
+mlct_status mlct_timing_read(const mlct_ctx* ctx, int32_t kernel, int64_t* launches,
+                             double* total_ms) {
+  if (!ctx || kernel < 0 || kernel >= MLCT_NUM_KERNEL_IDS) return MLCT_EINVAL;
+  if (launches) *launches = ctx->kernel_launches[kernel];
+  if (total_ms) *total_ms = ctx->kernel_ms[kernel];
+  return MLCT_OK;
+}
+
+mlct_status mlct_set_workspace_limit(mlct_ctx* ctx, uint64_t bytes) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->ws_limit = bytes;
+  return MLCT_OK;
+}
+
+mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* rowptr_dev,
+                        const int32_t* col_dev, const void* val_dev, int32_t dtype,
+                        mlct_op** out) {
+  if (!ctx || !out) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (d < 1 || d > (int64_t)1 << 31) return fail(ctx, MLCT_EINVAL, "bad dimension d=%lld", (long long)d);
+  if (nnz < 0 || nnz > INT32_MAX) return fail(ctx, MLCT_EINVAL, "bad nnz=%lld", (long long)nnz);
+  if (!rowptr_dev || (nnz > 0 && !col_dev))
+    return fail(ctx, MLCT_EINVAL, "rowptr/col must be device pointers");
+  if (dtype == MLCT_DT_F32) {
+    if (nnz > 0 && !val_dev) return fail(ctx, MLCT_EINVAL, "MLCT_DT_F32 needs values");
+  } else if (dtype == MLCT_DT_PATTERN) {
+    if (val_dev) return fail(ctx, MLCT_EINVAL, "MLCT_DT_PATTERN takes no values");
+  } else {
+    return fail(ctx, MLCT_EUNSUPPORTED, "CSR values must be float32 or a pattern");
+  }
+  CHECK(set_device(ctx));
+  void* flags;
+  CHECK(ws_get(ctx, WS_MISC, 64, &flags));
+  HIPCHK(ctx, hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), ctx->stream));
+  HIPCHK(ctx, launch_csr_validate(ctx->stream, rowptr_dev, col_dev, d, nnz,
+                                  static_cast<int32_t*>(flags)));
+  int32_t hf[2] = {0, 0};
+  HIPCHK(ctx, hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (hf[0])
+    return fail(ctx, MLCT_EINVAL, "invalid CSR structure (flags 0x%x: 1 rowptr[0]!=0, 2 decreasing rowptr, 4 rowptr[d]!=nnz, 8 column out of range)", hf[0]);
+  mlct_op* op = new (std::nothrow) mlct_op();
+  if (!op) return fail(ctx, MLCT_ENOMEM, "out of host memory");
+  op->ctx = ctx;
+  op->device = ctx->device;
+  op->kind = OP_CSR;
+  op->d = d;
+  op->nnz = nnz;
+  op->rowptr = rowptr_dev;
+  op->col = col_dev;
+  op->val = dtype == MLCT_DT_F32 ? val_dev : nullptr;
+  op->dtype = dtype;
+  op->max_row_nnz = hf[1];
+  *out = op;
+  return MLCT_OK;
+}
+
+mlct_status mlct_op_destroy(mlct_op* op) {
+  if (!op) return MLCT_EINVAL;
+  (void)hipSetDevice(op->device);
+  void* owned[] = {op->owned, op->split_hi, op->split_lo, op->a32, op->a64};
+  for (void* p : owned)
+    if (p) (void)hipFree(p);
+  delete op;
+  return MLCT_OK;
+}
+
+mlct_status mlct_cheb_coeffs(mlct_ctx* ctx, mlct_func f, double a, double b, int32_t n,
+                             double* c_out, double* log_scale_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!c_out) return fail(ctx, MLCT_EINVAL, "c_out is NULL");
+  if (n < 1 || n > kMaxDegree) return fail(ctx, MLCT_EINVAL, "degree must be in [1, %d]", kMaxDegree);
+  CHECK(check_func(ctx, f, a, b));
+  CHECK(set_device(ctx));
+  void* c;
+  CHECK(ws_get(ctx, WS_COEF, (size_t)(n + 2) * sizeof(double), &c));
+  double* cd = static_cast<double*>(c);
+  HIPCHK(ctx, launch_cheb_dct(ctx->stream, f.kind, f.power, a, b, n, cd, cd + n + 1));
+  std::vector<double> h(n + 2);
+  HIPCHK(ctx, hipMemcpyAsync(h.data(), cd, (n + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  std::memcpy(c_out, h.data(), (n + 1) * sizeof(double));
+  if (log_scale_out) *log_scale_out = h[n + 1];
+  return MLCT_OK;
+}
+
+mlct_status mlct_moments(mlct_ctx* ctx, const mlct_op* op, double a, double b, int32_t n,
+                         const mlct_probes* probes, int32_t prec, int32_t mode,
+                         double* mu_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !mu_out) return fail(ctx, MLCT_EINVAL, "op and mu_out are required");
+  if (!finite_interval(a, b)) return fail(ctx, MLCT_EINVAL, "need finite a < b");
+  if (n < 0 || n > kMaxDegree) return fail(ctx, MLCT_EINVAL, "degree must be in [0, %d]", kMaxDegree);
+  CHECK(check_mode_prec(ctx, mode, prec));
+  CHECK(check_probes(ctx, op, probes));
+  CHECK(set_device(ctx));
+  const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  const int64_t ldmu = n + 1;
+  void* mu;
+  CHECK(ws_get(ctx, WS_MU, (size_t)probes->m * ldmu * sizeof(double), &mu));
+  CHECK(run_probe_set(ctx, op, alpha, beta, n, mode, prec, probes, static_cast<double*>(mu), ldmu));
+  HIPCHK(ctx, hipMemcpyAsync(mu_out, mu, (size_t)probes->m * ldmu * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  CHECK(sync_stream(ctx));
+  return MLCT_OK;
+}
+
+mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
+                          const mlct_levels* levels, uint64_t seed, int32_t prec, int32_t mode,
+                          mlct_result* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !levels || !out) return fail(ctx, MLCT_EINVAL, "op, levels and out are required");
+  const int interp = (mode & MLCT_LEVEL_INTERP) ? 1 : 0;
+  mode &= ~MLCT_LEVEL_INTERP;
+  CHECK(check_mode_prec(ctx, mode, prec));
+  CHECK(check_func(ctx, f, a, b));
+  const int L = levels->L;
+  if (L < 1 || L > MLCT_MAX_LEVELS || !levels->degree || !levels->m)
+    return fail(ctx, MLCT_EINVAL, "need 1..%d levels", MLCT_MAX_LEVELS);
+  LevelDesc lv{};
+  lv.L = L;
+  lv.interp = interp;
+  int64_t total = 0, mv = 0, pd = 0;
+  for (int k = 0; k < L; ++k) {
+    const int dk = levels->degree[k];
+    if (dk < 0 || dk > kMaxDegree) return fail(ctx, MLCT_EINVAL, "level degree %d out of range", dk);
+    if (k && dk <= levels->degree[k - 1]) return fail(ctx, MLCT_EINVAL, "level degrees must increase");
+    if (levels->m[k] < 1) return fail(ctx, MLCT_EINVAL, "each level needs m_k >= 1");
+    if (interp && dk < 1) return fail(ctx, MLCT_EINVAL, "separate interpolants need degrees >= 1");
+    lv.degree[k] = dk;
+    lv.m[k] = levels->m[k];
+    lv.off[k] = total;
+    total += levels->m[k];
+    mv += levels->m[k] * (int64_t)(mode == MLCT_DOUBLING ? (dk + 1) / 2 : dk);
+    pd += levels->m[k] * (int64_t)dk;
+  }
+  const int n = lv.degree[L - 1];
+  if (n < 1) return fail(ctx, MLCT_EINVAL, "top degree must be >= 1");
+  CHECK(set_device(ctx));
+  const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  const int64_t ldmu = n + 1;
+  const int ncoef = interp ? L : 1;
+  lv.coef_stride = n + 1;
+  void *mu, *coef, *qstat, *res;
+  CHECK(ws_get(ctx, WS_MU, (size_t)total * ldmu * sizeof(double), &mu));
+  CHECK(ws_get(ctx, WS_COEF, ((size_t)ncoef * (n + 1) + 1) * sizeof(double), &coef));
+  CHECK(ws_get(ctx, WS_QSTAT, ((size_t)total + 3 * MLCT_MAX_LEVELS) * sizeof(double), &qstat));
+  CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_result), &res));
+  // Block workspace is taken before any launch so that growth never frees a
+  // buffer in use.
+  {
+    const CsrStepPlan plan = plan_csr(op->d);
+    const int S = (mode == MLCT_DOUBLING) ? (n + 1) / 2 : n;
+    const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
+    void* tmp;
+    CHECK(ws_get(ctx, WS_V0, (size_t)op->d * kBlockProbes * tsz, &tmp));
+    CHECK(ws_get(ctx, WS_V1, (size_t)op->d * kBlockProbes * tsz, &tmp));
+    CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * (S + 1) * sizeof(double), &tmp));
+    CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &tmp));
+  }
+  double* cd = static_cast<double*>(coef);
+  double* ls = cd + (size_t)ncoef * (n + 1);
+  hipStream_t s = ctx->stream;
+  if (!interp) {
+    HIPCHK(ctx, launch_cheb_dct(s, f.kind, f.power, a, b, n, cd, ls));
+  } else {
+    for (int k = 0; k < L; ++k)
+      HIPCHK(ctx, launch_cheb_dct(s, f.kind, f.power, a, b, lv.degree[k], cd + (size_t)k * (n + 1), ls));
+  }
+  double* mud = static_cast<double*>(mu);
+  for (int k = 0; k < L; ++k) {
+    mlct_probes pr{};
+    pr.kind = MLCT_PROBE_RADEMACHER;
+    pr.seed = seed;
+    pr.first_id = lv.off[k];
+    pr.m = lv.m[k];
+    CHECK(run_probe_set(ctx, op, alpha, beta, lv.degree[k], mode, prec, &pr,
+                        mud + lv.off[k] * ldmu, ldmu));
+  }
+  double* q = static_cast<double*>(qstat);
+  HIPCHK(ctx, launch_level_combine(s, mud, ldmu, cd, ls, lv, q, q + total,
+                                   static_cast<mlct_result*>(res)));
+  mlct_result h;
+  HIPCHK(ctx, hipMemcpyAsync(&h, res, sizeof h, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  if (!(h.max_moment_ratio <= 1.0 + 1e-3))
+    return fail(ctx, MLCT_ESPECTRUM,
+                "max |mu_j|/|z|^2 = %g > 1: the spectrum is not inside [a, b] = [%g, %g]",
+                h.max_moment_ratio, a, b);
+  h.matvecs = mv;
+  h.probe_degrees = pd;
+  if (prec == MLCT_BF16X3) h.flags |= MLCT_FLAG_BF16;
+  *out = h;
+  return MLCT_OK;
+}
+
+mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t, const void*, int64_t, int32_t, mlct_op**) {
+  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "dense operators not built yet") : MLCT_EINVAL;
+}
+mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t, int64_t, const void*, int64_t, int32_t, int32_t,
+                         mlct_op**) {
+  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "Gram operators not built yet") : MLCT_EINVAL;
+}
+mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op*, int32_t, uint64_t, double, double*, double*) {
+  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "Lanczos bounds not built yet") : MLCT_EINVAL;
+}
+mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op*, int64_t, uint64_t, int64_t*,
+                           mlct_tri_result*) {
+  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "triangles not built yet") : MLCT_EINVAL;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// Internal declarations of libmlct: context/operator objects and the
+// launchers of the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mlct.h"
+
+namespace mlct {
+
+// Width of a probe block in the CSR recurrence: one probe per wavefront lane.
+constexpr int kBlockProbes = 64;
+
+enum OpKind { OP_CSR = 0, OP_DENSE = 1, OP_GRAM = 2 };
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace mlct
+
+struct mlct_timed_launch {
+  hipEvent_t start, stop;
+  int kernel;
+};
+
+struct mlct_ctx {
+  int device = 0;
+  // per-kernel timing (mlct_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<mlct_timed_launch> pending;
+  double kernel_ms[MLCT_NUM_KERNEL_IDS] = {};
+  int64_t kernel_launches[MLCT_NUM_KERNEL_IDS] = {};
+  hipStream_t stream = nullptr;
+  std::string err;
+  uint64_t ws_limit = 0;  // 0 = unlimited
+  uint64_t ws_total = 0;  // bytes currently held in workspace slots
+  std::vector<mlct::DevBuf> slots;  // grow-only named workspace slots
+  void* host_pinned = nullptr;      // staging for small D2H results
+  size_t host_pinned_bytes = 0;
+};
+
+// An operator refers to its context; destroy operators before the context.
+struct mlct_op {
+  mlct_ctx* ctx = nullptr;
+  int device = 0;
+  int kind = mlct::OP_CSR;
+  int64_t d = 0;
+  // CSR
+  int64_t nnz = 0;
+  const int32_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const void* val = nullptr;  // nullptr = pattern
+  int max_row_nnz = 0;
+  // dense / Gram (row-major d x d)
+  const void* A = nullptr;
+  int64_t lda = 0;
+  int dtype = MLCT_DT_F32;
+  void* owned = nullptr;      // Gram matrix or other op-owned memory
+  void* split_hi = nullptr;   // bf16 hi part of A (lazily built)
+  void* split_lo = nullptr;   // bf16 lo part of A
+  void* a32 = nullptr;        // FP32 copy of an FP64 dense A (lazily built)
+  void* a64 = nullptr;        // FP64 copy of an FP32 dense A (lazily built)
+};
+
+namespace mlct {
+
+// Workspace slot indices (each slot grows independently).
+enum Slot {
+  WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_NSLOTS
+};
+
+// ---- probe-generation constants (SplitMix64) ------------------------------
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kMul1 = 0xBF58476D1CE4E5B9ull;
+constexpr uint64_t kMul2 = 0x94D049BB133111EBull;
+
+// Probe source descriptor passed by value to kernels.
+struct ProbeSrc {
+  uint64_t seed;
+  int64_t first_id;      // id of column 0 of the current block
+  const int8_t* entries; // non-null: explicit entries [d][ld]
+  int64_t ld;
+  int32_t active;        // columns in use in the current block (<= width)
+};
+
+// ---- launchers (k_common.hip) --------------------------------------------
+hipError_t launch_cheb_dct(hipStream_t s, int kind, double power, double a, double b,
+                           int n, double* c_dev, double* log_scale_dev);
+hipError_t launch_csr_validate(hipStream_t s, const int32_t* rowptr, const int32_t* col,
+                               int64_t d, int64_t nnz, int32_t* flags_dev);
+hipError_t launch_reduce_partials(hipStream_t s, const double* part, int steps, int nslots,
+                                  int ngroups, int width, double* dots);
+hipError_t launch_assemble_moments(hipStream_t s, const double* dots, int steps, int width,
+                                   int active, int mode, int n, double* mu, int64_t ldmu);
+// Per level: Q per probe (into q_dev), mean, unbiased variance and the
+// largest |mu_j|/mu_0; then the multilevel sum into result_dev.
+struct LevelDesc {
+  int32_t degree[MLCT_MAX_LEVELS];
+  int64_t m[MLCT_MAX_LEVELS];
+  int64_t off[MLCT_MAX_LEVELS];
+  int32_t L;
+  int32_t interp;     // separate interpolant per level
+  int32_t coef_stride;
+};
+hipError_t launch_level_combine(hipStream_t s, const double* mu, int64_t ldmu,
+                                const double* coef, const double* log_scale,
+                                const LevelDesc& lv, double* q_dev, double* stats_dev,
+                                mlct_result* result_dev);
+
+// ---- CSR recurrence (k_csr.hip) -------------------------------------------
+struct CsrStepPlan {
+  int ngroups;        // workgroups per step (= partial-sum slots)
+  int rows_per_group; // contiguous rows per workgroup
+};
+CsrStepPlan plan_csr(int64_t d);
+template <typename T>
+hipError_t launch_probe_init(hipStream_t s, T* v0, int64_t d, ProbeSrc src,
+                             const CsrStepPlan& plan, double* part0);
+// zmode: 0 = dots with V_k (symmetric form), 1 = regenerated Rademacher z,
+// 2 = explicit z entries.  has_prev = false for the first step (no V_prev).
+template <typename T>
+hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
+                           bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
+                           double* part);
+
+}  // namespace mlct

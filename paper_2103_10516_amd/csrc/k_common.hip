@@ -1,0 +1,270 @@
+// Small FP64 kernels of libmlct: Chebyshev coefficients (type-I DCT),
+// CSR structure validation, fixed-order reduction of moment partials,
+// assembly of the moment table, and the multilevel level combination.
+#include <cmath>
+
+#include "device.hpp"
+
+namespace mlct {
+
+namespace {
+
+__device__ double eval_f(int kind, double power, double t) {
+  switch (kind) {
+    case MLCT_LOG: return log(t);
+    case MLCT_SQRT: return sqrt(t);
+    case MLCT_EXP: return exp(t);
+    case MLCT_CUBE: return t * t * t;
+    case MLCT_INV: return 1.0 / t;
+    default: return pow(t, power);
+  }
+}
+
+// Coefficients of the degree-n interpolant at x_k = cos(k pi / n)
+// (Section 2.2): c_j = (2/n) sum''_k f~(x_k) cos(pi (j k mod 2n) / n), with
+// the end terms of the sum and c_0, c_n halved.  For exp the factor
+// exp((a+b)/2) is returned separately as a log-scale.
+__global__ __launch_bounds__(256) void cheb_dct_kernel(int kind, double power, double a,
+                                                       double b, int n, double* __restrict__ c,
+                                                       double* __restrict__ log_scale) {
+  extern __shared__ double fk[];
+  const double half = 0.5 * (b - a), mid = 0.5 * (a + b);
+  for (int k = threadIdx.x; k <= n; k += blockDim.x) {
+    const double x = cos(M_PI * (double)k / (double)n);
+    fk[k] = (kind == MLCT_EXP) ? exp(half * x) : eval_f(kind, power, half * x + mid);
+  }
+  __syncthreads();
+  const int64_t two_n = 2 * (int64_t)n;
+  for (int j = threadIdx.x; j <= n; j += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k <= n; ++k) {
+      const int64_t r = ((int64_t)j * k) % two_n;
+      const double w = (k == 0 || k == n) ? 0.5 : 1.0;
+      s += w * fk[k] * cos(M_PI * (double)r / (double)n);
+    }
+    s *= 2.0 / (double)n;
+    if (j == 0 || j == n) s *= 0.5;
+    c[j] = s;
+  }
+  if (threadIdx.x == 0 && log_scale) *log_scale = (kind == MLCT_EXP) ? mid : 0.0;
+}
+
+// flags[0]: bit0 rowptr[0] != 0, bit1 decreasing rowptr, bit2 rowptr[d] != nnz,
+// bit3 column out of range.  flags[1]: longest row.
+__global__ void csr_validate_kernel(const int32_t* __restrict__ rowptr,
+                                    const int32_t* __restrict__ col, int64_t d, int64_t nnz,
+                                    int32_t* __restrict__ flags) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0, longest = 0;
+  for (int64_t i = tid; i < d; i += stride) {
+    const int32_t s = rowptr[i], e = rowptr[i + 1];
+    if (e < s) bad |= 2;
+    else longest = max(longest, e - s);
+  }
+  if (tid == 0) {
+    if (rowptr[0] != 0) bad |= 1;
+    if ((int64_t)rowptr[d] != nnz) bad |= 4;
+  }
+  for (int64_t t = tid; t < nnz; t += stride) {
+    const int32_t j = col[t];
+    if (j < 0 || (int64_t)j >= d) bad |= 8;
+  }
+  if (bad) atomicOr(&flags[0], bad);
+  if (longest) atomicMax(&flags[1], longest);
+}
+
+// dots[s][slot][p] = sum_{g = 0..ngroups-1} part[s][slot][g][p], summed in
+// increasing g (fixed order, so results are bitwise reproducible).
+__global__ void reduce_partials_kernel(const double* __restrict__ part, int steps, int nslots,
+                                       int ngroups, int width, double* __restrict__ dots) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)steps * nslots * width;
+  if (tid >= total) return;
+  const int64_t p = tid % width;
+  const int64_t row = tid / width;  // = s * nslots + slot
+  const double* src = part + row * ngroups * width + p;
+  double acc = 0.0;
+  for (int g = 0; g < ngroups; ++g) acc += src[(int64_t)g * width];
+  dots[tid] = acc;
+}
+
+// Moment table rows from the per-step dot products.
+// Direct form: mu_0 = z.z, mu_j = z.v_j.
+// Symmetric form: mu_1 = v_1.v_0, mu_2 = 2 v_1.v_1 - mu_0,
+// mu_{2s-1} = 2 v_s.v_{s-1} - mu_1 and mu_{2s} = 2 v_s.v_s - mu_0 for s >= 2.
+__global__ void assemble_moments_kernel(const double* __restrict__ dots, int steps, int width,
+                                        int active, int mode, int n, double* __restrict__ mu,
+                                        int64_t ldmu) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= active) return;
+  auto D = [&](int s, int slot) { return dots[((int64_t)s * 2 + slot) * width + p]; };
+  double* row = mu + (int64_t)p * ldmu;
+  const double mu0 = D(0, 0);
+  row[0] = mu0;
+  if (mode == MLCT_DIRECT) {
+    for (int j = 1; j <= n; ++j) row[j] = D(j, 0);
+    return;
+  }
+  if (n < 1) return;
+  const double mu1 = D(1, 0);
+  row[1] = mu1;
+  if (n >= 2) row[2] = 2.0 * D(1, 1) - mu0;
+  for (int s = 2; s < steps; ++s) {
+    if (2 * s - 1 <= n) row[2 * s - 1] = 2.0 * D(s, 0) - mu1;
+    if (2 * s <= n) row[2 * s] = 2.0 * D(s, 1) - mu0;
+  }
+}
+
+constexpr int kCombThreads = 256;
+
+__device__ double block_sum_fixed(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kCombThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kCombThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per level k (eq. def:qlevels):
+//   Q^{(p)} = sum_{j = l_{k-1}+1}^{l_k} c_j mu_j^{(p)}   (truncation), or
+//   Q^{(p)} = z^T p_{l_k} z - z^T p_{l_{k-1}} z          (separate interpolants),
+// then the level mean and the unbiased sample variance, and max |mu_j| / mu_0.
+__global__ __launch_bounds__(kCombThreads) void level_stats_kernel(
+    const double* __restrict__ mu, int64_t ldmu, const double* __restrict__ coef, LevelDesc lv,
+    double* __restrict__ q, double* __restrict__ stats) {
+  __shared__ double sh[kCombThreads];
+  const int k = blockIdx.x;
+  const int hi = lv.degree[k];
+  const int lo = k ? lv.degree[k - 1] : -1;
+  const int64_t mk = lv.m[k], o = lv.off[k];
+  const double* ch = lv.interp ? coef + (int64_t)k * lv.coef_stride : coef;
+  const double* cl = (lv.interp && k) ? coef + (int64_t)(k - 1) * lv.coef_stride : nullptr;
+  double s = 0.0, mr = 0.0;
+  for (int64_t p = threadIdx.x; p < mk; p += kCombThreads) {
+    const double* r = mu + (o + p) * ldmu;
+    double qv = 0.0;
+    if (!lv.interp) {
+      for (int j = lo + 1; j <= hi; ++j) qv += ch[j] * r[j];
+    } else {
+      for (int j = 0; j <= hi; ++j) qv += ch[j] * r[j];
+      if (cl) {
+        double ql = 0.0;
+        for (int j = 0; j <= lo; ++j) ql += cl[j] * r[j];
+        qv -= ql;
+      }
+    }
+    q[o + p] = qv;
+    s += qv;
+    const double inv0 = 1.0 / r[0];
+    for (int j = 0; j <= hi; ++j) mr = fmax(mr, fabs(r[j]) * inv0);
+  }
+  const double mean = block_sum_fixed(s, sh) / (double)mk;
+  double ss = 0.0;
+  for (int64_t p = threadIdx.x; p < mk; p += kCombThreads) {
+    const double dlt = q[o + p] - mean;
+    ss += dlt * dlt;
+  }
+  ss = block_sum_fixed(ss, sh);
+  mr = block_max(mr, sh);
+  if (threadIdx.x == 0) {
+    stats[3 * k + 0] = mean;
+    stats[3 * k + 1] = mk > 1 ? ss / (double)(mk - 1) : NAN;
+    stats[3 * k + 2] = mr;
+  }
+}
+
+// Multilevel estimator (eq. eqn:multiEstimator): Gamma = sum_k mean_k and
+// its variance estimate sum_k s_k^2 / m_k, summed over k in order.
+__global__ void level_finalize_kernel(const double* __restrict__ stats, LevelDesc lv,
+                                      const double* __restrict__ log_scale,
+                                      mlct_result* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double v = 0.0, var = 0.0, mr = 0.0;
+  uint32_t flags = 0;
+  for (int k = 0; k < lv.L; ++k) {
+    v += stats[3 * k];
+    if (lv.m[k] > 1) var += stats[3 * k + 1] / (double)lv.m[k];
+    else flags |= MLCT_FLAG_FEW_SAMPLES;
+    mr = fmax(mr, stats[3 * k + 2]);
+    out->level_mean[k] = stats[3 * k];
+    out->level_var[k] = stats[3 * k + 1];
+  }
+  for (int k = lv.L; k < MLCT_MAX_LEVELS; ++k) {
+    out->level_mean[k] = 0.0;
+    out->level_var[k] = 0.0;
+  }
+  const double ls = *log_scale;
+  const double est = v * exp(ls);
+  if (!isfinite(est)) flags |= MLCT_FLAG_OVERFLOW;
+  if (flags & MLCT_FLAG_FEW_SAMPLES) var = NAN;
+  out->value = v;
+  out->log_scale = ls;
+  out->estimate = est;
+  out->est_var = var;
+  out->max_moment_ratio = mr;
+  out->flags = flags;
+}
+
+}  // namespace
+
+hipError_t launch_cheb_dct(hipStream_t s, int kind, double power, double a, double b, int n,
+                           double* c_dev, double* log_scale_dev) {
+  cheb_dct_kernel<<<1, 256, (size_t)(n + 1) * sizeof(double), s>>>(kind, power, a, b, n, c_dev,
+                                                                    log_scale_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_validate(hipStream_t s, const int32_t* rowptr, const int32_t* col,
+                               int64_t d, int64_t nnz, int32_t* flags_dev) {
+  const int64_t work = d > nnz ? d : nnz;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  csr_validate_kernel<<<(int)blocks, 256, 0, s>>>(rowptr, col, d, nnz, flags_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(hipStream_t s, const double* part, int steps, int nslots,
+                                  int ngroups, int width, double* dots) {
+  const int64_t total = (int64_t)steps * nslots * width;
+  reduce_partials_kernel<<<(int)((total + 255) / 256), 256, 0, s>>>(part, steps, nslots,
+                                                                   ngroups, width, dots);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_moments(hipStream_t s, const double* dots, int steps, int width,
+                                   int active, int mode, int n, double* mu, int64_t ldmu) {
+  assemble_moments_kernel<<<(active + 63) / 64, 64, 0, s>>>(dots, steps, width, active, mode,
+                                                             n, mu, ldmu);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_combine(hipStream_t s, const double* mu, int64_t ldmu,
+                                const double* coef, const double* log_scale,
+                                const LevelDesc& lv, double* q_dev, double* stats_dev,
+                                mlct_result* result_dev) {
+  level_stats_kernel<<<lv.L, kCombThreads, 0, s>>>(mu, ldmu, coef, lv, q_dev, stats_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  level_finalize_kernel<<<1, 64, 0, s>>>(stats_dev, lv, log_scale, result_dev);
+  return hipGetLastError();
+}
+
+}  // namespace mlct

@@ -1,0 +1,248 @@
+"""Thin ctypes binding of libmlct.so (include/mlct.h).
+
+Argument marshalling only: every step of the estimator runs in the library's
+HIP kernels.  Device buffers are torch tensors on a ROCm device (PyTorch is
+used for device memory and streams); their ``data_ptr()`` is passed through.
+If the library has not been built this module raises on first use; there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import weakref
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmlct.so")
+
+# ---- enumerations (same values as include/mlct.h) -------------------------
+MLCT_OK, MLCT_EINVAL, MLCT_ENOMEM, MLCT_EDEVICE = 0, 1, 2, 3
+MLCT_ESPECTRUM, MLCT_ERANGE, MLCT_EUNSUPPORTED = 4, 5, 6
+STATUS_NAMES = {0: "MLCT_OK", 1: "MLCT_EINVAL", 2: "MLCT_ENOMEM", 3: "MLCT_EDEVICE",
+                4: "MLCT_ESPECTRUM", 5: "MLCT_ERANGE", 6: "MLCT_EUNSUPPORTED"}
+MLCT_LOG, MLCT_SQRT, MLCT_EXP, MLCT_CUBE, MLCT_INV, MLCT_POW = 0, 1, 2, 3, 4, 5
+MLCT_FP64, MLCT_FP32, MLCT_BF16X3 = 0, 1, 2
+MLCT_DIRECT, MLCT_DOUBLING = 0, 1
+MLCT_LEVEL_INTERP = 0x10
+MLCT_DT_F32, MLCT_DT_F64, MLCT_DT_PATTERN = 0, 1, 2
+MLCT_PROBE_RADEMACHER, MLCT_PROBE_EXPLICIT = 0, 1
+MLCT_MAX_LEVELS = 32
+MLCT_FLAG_FEW_SAMPLES, MLCT_FLAG_OVERFLOW, MLCT_FLAG_BF16 = 0x1, 0x2, 0x4
+MLCT_KERNEL_CSR_STEP, MLCT_KERNEL_DENSE_STEP, MLCT_KERNEL_TRI_STEP, MLCT_KERNEL_GRAM = 0, 1, 2, 3
+
+
+class mlct_func(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("power", C.c_double)]
+
+
+class mlct_probes(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("seed", C.c_uint64), ("first_id", C.c_int64),
+                ("m", C.c_int64), ("entries_dev", C.c_void_p), ("ld_entries", C.c_int64)]
+
+
+class mlct_levels(C.Structure):
+    _fields_ = [("L", C.c_int32), ("degree", C.POINTER(C.c_int32)),
+                ("m", C.POINTER(C.c_int64))]
+
+
+class mlct_result(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("value", C.c_double), ("log_scale", C.c_double),
+                ("est_var", C.c_double),
+                ("level_mean", C.c_double * MLCT_MAX_LEVELS),
+                ("level_var", C.c_double * MLCT_MAX_LEVELS),
+                ("matvecs", C.c_int64), ("probe_degrees", C.c_int64),
+                ("max_moment_ratio", C.c_double), ("flags", C.c_uint32)]
+
+
+class mlct_tri_result(C.Structure):
+    _fields_ = [("sum_w3", C.c_int64), ("estimate", C.c_double), ("estimate_cv", C.c_double),
+                ("a1", C.c_double), ("a2", C.c_double)]
+
+
+class MlctError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+_lib_handle = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2103_10516_amd.build`"
+                " (there is no fallback implementation)")
+        h = C.CDLL(LIB_PATH)
+        P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        sig = {
+            "mlct_create": [C.c_int, P, C.c_char_p, C.POINTER(P)],
+            "mlct_destroy": [P],
+            "mlct_set_workspace_limit": [P, U64],
+            "mlct_op_csr": [P, I64, I64, P, P, P, I32, C.POINTER(P)],
+            "mlct_op_dense": [P, I64, P, I64, I32, C.POINTER(P)],
+            "mlct_op_gram": [P, I64, I64, P, I64, I32, I32, C.POINTER(P)],
+            "mlct_op_destroy": [P],
+            "mlct_cheb_coeffs": [P, mlct_func, D, D, I32, P, C.POINTER(D)],
+            "mlct_moments": [P, P, D, D, I32, C.POINTER(mlct_probes), I32, I32, P],
+            "mlct_bounds": [P, P, I32, U64, D, C.POINTER(D), C.POINTER(D)],
+            "mlct_estimate": [P, P, mlct_func, D, D, C.POINTER(mlct_levels), U64, I32, I32,
+                              C.POINTER(mlct_result)],
+            "mlct_triangles": [P, P, I64, U64, P, C.POINTER(mlct_tri_result)],
+            "mlct_timing": [P, I32],
+            "mlct_timing_read": [P, I32, C.POINTER(I64), C.POINTER(D)],
+        }
+        for name, args in sig.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        h.mlct_last_error.argtypes = [P]
+        h.mlct_last_error.restype = C.c_char_p
+        _lib_handle = h
+    return _lib_handle
+
+
+def _check(ctx, status: int):
+    if status != MLCT_OK:
+        msg = lib().mlct_last_error(ctx.handle if ctx is not None else None)
+        raise MlctError(status, msg.decode() if msg else "")
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+class Context:
+    """Owns an mlct_ctx bound to a device and a HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().mlct_create(device, C.c_void_p(stream.cuda_stream), None, C.byref(h))
+        if st != MLCT_OK:
+            raise MlctError(st, "mlct_create failed")
+        self.handle = h
+        self._ops = weakref.WeakSet()
+
+    def close(self):
+        """Destroy the context; operators created on it are destroyed first."""
+        if self.handle:
+            for op in list(self._ops):
+                op.close()
+            lib().mlct_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Op:
+    """Operator handle; keeps the tensors it borrows alive."""
+
+    def __init__(self, ctx: Context, handle, keep, d: int):
+        self.ctx, self.handle, self._keep, self.d = ctx, handle, keep, d
+        ctx._ops.add(self)
+
+    def close(self):
+        if self.handle:
+            lib().mlct_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- entry points, same names as the C ABI --------------------------------
+def mlct_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def mlct_timing(ctx: Context, enable: bool):
+    _check(ctx, lib().mlct_timing(ctx.handle, 1 if enable else 0))
+
+
+def mlct_timing_read(ctx: Context, kernel: int):
+    """(launches, total_ms) of one kernel family since timing was enabled."""
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(ctx, lib().mlct_timing_read(ctx.handle, kernel, C.byref(n), C.byref(ms)))
+    return n.value, ms.value
+
+
+def mlct_set_workspace_limit(ctx: Context, nbytes: int):
+    _check(ctx, lib().mlct_set_workspace_limit(ctx.handle, int(nbytes)))
+
+
+def mlct_op_csr(ctx: Context, rowptr, col, val=None) -> Op:
+    """rowptr int32[d+1], col int32[nnz], val float32[nnz] or None (pattern),
+    all device tensors."""
+    d = rowptr.numel() - 1
+    nnz = col.numel()
+    h = C.c_void_p()
+    dt = MLCT_DT_PATTERN if val is None else MLCT_DT_F32
+    _check(ctx, lib().mlct_op_csr(ctx.handle, d, nnz, _ptr(rowptr), _ptr(col), _ptr(val), dt,
+                                  C.byref(h)))
+    return Op(ctx, h, (rowptr, col, val), d)
+
+
+def mlct_cheb_coeffs(ctx: Context, kind: int, a: float, b: float, n: int, power: float = 1.0):
+    c = np.empty(n + 1, dtype=np.float64)
+    ls = C.c_double()
+    _check(ctx, lib().mlct_cheb_coeffs(ctx.handle, mlct_func(kind, power), a, b, n,
+                                       c.ctypes.data, C.byref(ls)))
+    return c, ls.value
+
+
+def rademacher_probes(seed: int, m: int, first_id: int = 0) -> mlct_probes:
+    return mlct_probes(MLCT_PROBE_RADEMACHER, seed & ((1 << 64) - 1), first_id, m, None, 0)
+
+
+def explicit_probes(entries, m: int | None = None, first_id: int = 0) -> mlct_probes:
+    """entries: device int8 tensor [d, ld] (probe index fastest)."""
+    ld = entries.shape[1]
+    m = ld - first_id if m is None else m
+    p = mlct_probes(MLCT_PROBE_EXPLICIT, 0, first_id, m, _ptr(entries), ld)
+    p._keep = entries
+    return p
+
+
+def mlct_moments(ctx: Context, op: Op, a: float, b: float, n: int, probes: mlct_probes,
+                 prec: int = MLCT_FP32, mode: int = MLCT_DIRECT) -> np.ndarray:
+    mu = np.empty((probes.m, n + 1), dtype=np.float64)
+    _check(ctx, lib().mlct_moments(ctx.handle, op.handle, a, b, n, C.byref(probes), prec, mode,
+                                   mu.ctypes.data))
+    return mu
+
+
+def mlct_estimate(ctx: Context, op: Op, kind: int, a: float, b: float, degrees, m, seed: int,
+                  prec: int = MLCT_FP32, mode: int = MLCT_DIRECT, power: float = 1.0) -> dict:
+    L = len(degrees)
+    deg = (C.c_int32 * L)(*[int(x) for x in degrees])
+    mm = (C.c_int64 * L)(*[int(x) for x in m])
+    lv = mlct_levels(L, deg, mm)
+    r = mlct_result()
+    _check(ctx, lib().mlct_estimate(ctx.handle, op.handle, mlct_func(kind, power), a, b,
+                                    C.byref(lv), seed & ((1 << 64) - 1), prec, mode, C.byref(r)))
+    return {
+        "estimate": r.estimate, "value": r.value, "log_scale": r.log_scale,
+        "est_var": r.est_var, "level_mean": np.array(r.level_mean[:L]),
+        "level_var": np.array(r.level_var[:L]), "matvecs": r.matvecs,
+        "probe_degrees": r.probe_degrees, "max_moment_ratio": r.max_moment_ratio,
+        "flags": r.flags,
+    }

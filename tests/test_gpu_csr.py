@@ -1,0 +1,231 @@
+"""GPU parity of the CSR recurrence path against the FP64 oracle.
+
+Every test calls the HIP library through its C ABI (ctypes binding) and
+compares with ``oracle/`` on the same seeded inputs and the same probes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cheb, estimator, moments, probes
+from paper_2103_10516_amd import workloads as wl
+from tests.tolerances import U32, U64, kappa_csr, moment_tol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_2103_10516_amd import mlct
+
+    c = mlct.mlct_create(0)
+    yield c
+    c.close()
+
+
+def _dev_csr(torch, g):
+    rp = torch.from_numpy(g.rowptr).cuda()
+    cl = torch.from_numpy(g.col).cuda()
+    vl = None if g.val is None else torch.from_numpy(g.val).cuda()
+    return rp, cl, vl
+
+
+def _op(ctx, torch, g):
+    from paper_2103_10516_amd import mlct
+
+    return mlct.mlct_op_csr(ctx, *_dev_csr(torch, g))
+
+
+def _oracle_mu(g, a, b, n, ids, seed, doubling=False):
+    alpha, beta = cheb.affine_map(a, b)
+    Z = probes.rademacher(g.d, ids, seed).T
+    fn = moments.moments_doubling if doubling else moments.moments_direct
+    return fn(g.to_scipy(), Z, alpha, beta, n)
+
+
+CASES = [
+    # (name, graph builder, a, b)
+    ("lap2d_45", lambda: wl.laplacian_2d(45), 0.01, 8.01),
+    ("random_ragged", lambda: wl.random_csr(301, 0.03, 4), -7.0, 7.0),
+    ("chung_lu_pattern", lambda: wl.chung_lu(3000, seed=11), -60.0, 90.0),
+]
+
+
+@pytest.mark.parametrize("name,builder,a,b", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["direct", "doubling"])
+def test_moments_match_oracle(ctx, torch_dev, name, builder, a, b, prec, mode):
+    from paper_2103_10516_amd import mlct
+
+    g = builder()
+    if name == "chung_lu_pattern":
+        lam = np.linalg.eigvalsh(g.to_dense())
+        assert a < lam.min() and lam.max() < b
+    n, m, seed, first = 37, 100, 12345, 7
+    op = _op(ctx, torch_dev, g)
+    P = mlct.MLCT_FP64 if prec == "fp64" else mlct.MLCT_FP32
+    M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    got = mlct.mlct_moments(ctx, op, a, b, n, mlct.rademacher_probes(seed, m, first), P, M)
+    want = _oracle_mu(g, a, b, n, np.arange(first, first + m), seed)
+    alpha, beta = cheb.affine_map(a, b)
+    rn = int(np.max(np.diff(g.rowptr)))
+    tol = moment_tol(n, g.d, U64 if prec == "fp64" else U32, rn, kappa_csr(g, alpha, beta))
+    err = np.abs(got - want)
+    assert np.all(got[:, 0] == g.d)
+    worst = np.max(err / tol[None, :])
+    print(f"{name} {prec} {mode}: worst err/tol = {worst:.3g}")
+    assert worst <= 1.0
+
+
+def test_hadamard_probes_exact_trace(ctx, torch_dev):
+    """Sylvester-Hadamard probes make Hutchinson exact: (1/d) sum_p h_p^T p(A) h_p = tr p(A)."""
+    from paper_2103_10516_amd import mlct
+
+    nside = 16
+    g = wl.laplacian_2d(nside)  # d = 256
+    d = g.d
+    H = wl.hadamard_signs(d)  # [p, i]
+    ent = torch_dev.from_numpy(np.ascontiguousarray(H.T)).cuda()  # [i, p]
+    a, b, n = 0.01, 8.01, 40
+    op = _op(ctx, torch_dev, g)
+    mu = mlct.mlct_moments(ctx, op, a, b, n, mlct.explicit_probes(ent), mlct.MLCT_FP64,
+                           mlct.MLCT_DIRECT)
+    c, _ = cheb.coefficients(cheb.LOG, a, b, n)
+    tr = float(np.sum(mu @ c)) / d
+    # the operator is the FP32-valued matrix (diagonal 4.01f, not 4.01)
+    want = cheb.trace_poly(c, np.linalg.eigvalsh(g.to_dense()), a, b)
+    assert tr == pytest.approx(want, rel=1e-11)
+    # and the closed-form spectrum of the exact Laplacian is within the
+    # perturbation of rounding 4.01 to FP32
+    exact = cheb.trace_poly(c, wl.laplacian_2d_eigs(nside), a, b)
+    assert tr == pytest.approx(exact, rel=1e-6)
+
+
+def test_unit_probes_exact_trace(ctx, torch_dev):
+    from paper_2103_10516_amd import mlct
+
+    g = wl.random_csr(150, 0.05, 9)
+    d = g.d
+    ent = torch_dev.eye(d, dtype=torch_dev.int8).cuda()
+    a, b, n = -8.0, 8.0, 25
+    lam = np.linalg.eigvalsh(g.to_dense())
+    op = _op(ctx, torch_dev, g)
+    mu = mlct.mlct_moments(ctx, op, a, b, n, mlct.explicit_probes(ent), mlct.MLCT_FP64,
+                           mlct.MLCT_DIRECT)
+    c, _ = cheb.coefficients(cheb.EXP, a, b, n)
+    assert float(np.sum(mu @ c)) == pytest.approx(cheb.trace_poly(c, lam, a, b), rel=1e-11)
+
+
+@pytest.mark.parametrize("kind,a,b,n", [(cheb.LOG, 0.01, 8.01, 400), (cheb.SQRT, 1e-6, 1.0, 256),
+                                         (cheb.EXP, -216.6, 279.7, 60), (cheb.CUBE, -1, 2, 9),
+                                         (cheb.INV, 0.5, 3.0, 33), (cheb.POW, 0.1, 2.0, 17)])
+def test_cheb_coeffs_match_oracle(ctx, kind, a, b, n):
+    from paper_2103_10516_amd import mlct
+
+    got, ls = mlct.mlct_cheb_coeffs(ctx, kind, a, b, n, power=1.5)
+    want, ls_o = cheb.coefficients(kind, a, b, n, power=1.5)
+    assert ls == pytest.approx(ls_o, abs=0)
+    scale = np.max(np.abs(want))
+    np.testing.assert_allclose(got, want, rtol=0, atol=64 * (n + 1) * U64 * scale)
+
+
+@pytest.mark.parametrize("mode", ["direct", "doubling"])
+def test_estimate_matches_oracle(ctx, torch_dev, mode):
+    from paper_2103_10516_amd import mlct
+
+    g = wl.laplacian_2d(40)
+    a, b = 0.01, 8.01
+    degrees, m, seed = [5, 20, 60], [130, 70, 20], 2024
+    op = _op(ctx, torch_dev, g)
+    M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    r64 = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, degrees, m, seed, mlct.MLCT_FP64, M)
+    r32 = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, degrees, m, seed, mlct.MLCT_FP32, M)
+    o = estimator.estimate(g.to_scipy(), g.d, cheb.LOG, a, b, degrees, m, seed,
+                           doubling=(mode == "doubling"))
+    assert r64["matvecs"] == o.matvecs
+    assert r64["value"] == pytest.approx(o.value, rel=1e-11)
+    np.testing.assert_allclose(r64["level_mean"], o.level_mean, rtol=1e-10, atol=1e-9)
+    np.testing.assert_allclose(r64["level_var"], o.level_var, rtol=1e-8)
+    # FP32: the error model bounds each Q by sum_j |c_j| tol_j
+    c, _ = cheb.coefficients(cheb.LOG, a, b, 60)
+    alpha, beta = cheb.affine_map(a, b)
+    tol = moment_tol(60, g.d, U32, 5, kappa_csr(g, alpha, beta))
+    qtol = float(np.sum(np.abs(c) * tol))
+    assert abs(r32["value"] - o.value) <= qtol
+    assert r32["est_var"] == pytest.approx(o.est_var, rel=1e-2)
+    truth = cheb.trace_poly(c, wl.laplacian_2d_eigs(40), a, b)
+    assert abs(r32["value"] - truth) < 5 * math.sqrt(o.est_var)
+
+
+def test_estimate_level_interp_matches_oracle(ctx, torch_dev):
+    from paper_2103_10516_amd import mlct
+
+    g = wl.random_csr(200, 0.04, 3)
+    a, b = -8.0, 8.0
+    degrees, m, seed = [4, 11, 30], [64, 40, 10], 77
+    op = _op(ctx, torch_dev, g)
+    r = mlct.mlct_estimate(ctx, op, mlct.MLCT_EXP, a, b, degrees, m, seed, mlct.MLCT_FP64,
+                           mlct.MLCT_DIRECT | mlct.MLCT_LEVEL_INTERP)
+    o = estimator.estimate(g.to_scipy(), g.d, cheb.EXP, a, b, degrees, m, seed,
+                           level_interp=True)
+    assert r["log_scale"] == o.log_scale
+    assert r["value"] == pytest.approx(o.value, rel=1e-10)
+    np.testing.assert_allclose(r["level_var"], o.level_var, rtol=1e-8)
+
+
+def test_deterministic_bitwise(ctx, torch_dev):
+    from paper_2103_10516_amd import mlct
+
+    g = wl.chung_lu(5000, seed=2)
+    op = _op(ctx, torch_dev, g)
+    pr = mlct.rademacher_probes(5, 64)
+    m1 = mlct.mlct_moments(ctx, op, -100.0, 120.0, 20, pr, mlct.MLCT_FP32, mlct.MLCT_DIRECT)
+    m2 = mlct.mlct_moments(ctx, op, -100.0, 120.0, 20, pr, mlct.MLCT_FP32, mlct.MLCT_DIRECT)
+    assert np.array_equal(m1, m2)
+
+
+def test_error_paths(ctx, torch_dev):
+    from paper_2103_10516_amd import mlct
+
+    torch = torch_dev
+    g = wl.laplacian_2d(20)
+    rp, cl, vl = _dev_csr(torch, g)
+    bad = cl.clone()
+    bad[5] = g.d + 3
+    with pytest.raises(mlct.MlctError) as e:
+        mlct.mlct_op_csr(ctx, rp, bad, vl)
+    assert e.value.status == mlct.MLCT_EINVAL
+    rp_bad = rp.clone()
+    rp_bad[10] = rp_bad[12] + 1
+    with pytest.raises(mlct.MlctError) as e:
+        mlct.mlct_op_csr(ctx, rp_bad, cl, vl)
+    assert e.value.status == mlct.MLCT_EINVAL
+    op = mlct.mlct_op_csr(ctx, rp, cl, vl)
+    with pytest.raises(mlct.MlctError) as e:  # log needs a > 0
+        mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, 0.0, 8.01, [10], [4], 1)
+    assert e.value.status == mlct.MLCT_EINVAL
+    with pytest.raises(mlct.MlctError) as e:  # b below lambda_max: spectrum escapes
+        mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, 0.01, 5.0, [5, 40], [8, 4], 1)
+    assert e.value.status == mlct.MLCT_ESPECTRUM
+    with pytest.raises(mlct.MlctError) as e:  # levels must increase
+        mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, 0.01, 8.01, [10, 10], [4, 4], 1)
+    assert e.value.status == mlct.MLCT_EINVAL
+    ctx2 = mlct.mlct_create(0)
+    op2 = mlct.mlct_op_csr(ctx2, rp, cl, vl)
+    mlct.mlct_set_workspace_limit(ctx2, 1024)
+    with pytest.raises(mlct.MlctError) as e:
+        mlct.mlct_estimate(ctx2, op2, mlct.MLCT_LOG, 0.01, 8.01, [10], [4], 1)
+    assert e.value.status == mlct.MLCT_ENOMEM
+    op2.close()
+    ctx2.close()
+    r = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, 0.01, 8.01, [3, 10], [1, 5], 1)
+    assert r["flags"] & mlct.MLCT_FLAG_FEW_SAMPLES and math.isnan(r["est_var"])
