@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=2048, help="2D grid edge (default 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run 3 device copies of 1 GiB (a plain copy kernel of known "
+                         "size, used to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the estimator's probes shard across GPUs "
@@ -106,6 +109,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("# copy calibration: 3 x 1 GiB device copies", file=sys.stderr, flush=True)
     w = laplace2d_workload(args.grid)
     g = w["graph"]
     print(f"# workload ready: d={g.d} nnz={g.nnz}", file=sys.stderr, flush=True)
