@@ -144,20 +144,47 @@ __device__ __forceinline__ T row_dot_generic(const int32_t* __restrict__ col,
   return acc;
 }
 
-// Rows are taken in batches of 64 per wave (lane l holds the extent of row
-// b0 + l), and within a batch in groups of kGroupRows rows whose column
-// indices arrive in one coalesced load.  When every row of a group has at
-// most MAXNZ entries, the group's gathers are issued as straight-line code
-// (unused slots gather the row itself with weight 0), so all of them are in
-// flight before the first is consumed.  Other groups take the generic loop.
-constexpr int kGroupRows = 4;
+// Extent of a group of up to ROWS consecutive rows inside a 64-row batch
+// whose start offsets (rs) and lengths (rlen) sit one per lane.
+template <int ROWS>
+struct GroupExt {
+  int gs, cnt, nr, maxlen;
+  int off[ROWS], len[ROWS];
+};
 
+template <int ROWS>
+__device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int nb, int q) {
+  GroupExt<ROWS> e;
+  e.nr = min(ROWS, nb - q);
+  e.gs = read_lane(rs, q);
+  e.maxlen = 0;
+  e.cnt = 0;
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const int rr = min(q + r, nb - 1);
+    e.off[r] = read_lane(rs, rr) - e.gs;
+    e.len[r] = (r < e.nr) ? read_lane(rlen, rr) : 0;
+    e.maxlen = max(e.maxlen, e.len[r]);
+    if (r < e.nr) e.cnt = e.off[r] + e.len[r];  // static indices only
+  }
+  return e;
+}
+
+// Each wave owns a contiguous run of rows, walked in groups of ROWS rows.
+// The column indices and values of a group come in one coalesced load,
+// issued while the previous group's gathers are in flight (software
+// pipelining); row extents come in 64-row batches, prefetched one batch
+// ahead.  When every row of a group has at most MAXNZ entries, its gathers
+// are straight-line code (unused slots gather the row itself with weight 0)
+// and are all in flight before the first is consumed; other groups take the
+// generic loop.
 template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ>
 __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
     T* __restrict__ vm, T ca, T cb, ProbeSrc src, int rows_per_group, int ngroups,
     double* __restrict__ part) {
+  constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
   const int lane = lane_id(), wave = wave_id();
   const int g = xcd_band(blockIdx.x, ngroups);
   const int64_t r0 = (int64_t)g * rows_per_group;
@@ -169,67 +196,118 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
   uint64_t word = 0;
   double acc1 = 0.0, acc2 = 0.0;
 
-  for (int64_t b0 = r0 + (int64_t)wave * 64; b0 < r1; b0 += kWaves * 64) {
-    const int nb = (int)min<int64_t>(64, r1 - b0);
-    const int64_t rl = b0 + min(lane, nb - 1);
-    const int rs = rowptr[rl];
-    const int rlen = (lane < nb) ? rowptr[rl + 1] - rs : 0;
-    for (int q = 0; q < nb; q += kGroupRows) {
-      const int nr = min(kGroupRows, nb - q);
-      int off[kGroupRows], len[kGroupRows];
-      const int gs = read_lane(rs, q);
-      int maxlen = 0;
+  const int64_t span = r1 - r0;
+  const int64_t rpw = ((span + kWaves - 1) / kWaves + 63) / 64 * 64;
+  const int64_t w0 = r0 + (int64_t)wave * rpw;
+  const int64_t w1 = min<int64_t>(w0 + rpw, r1);
+
+  if (w0 < w1) {
+    auto load_batch = [&](int64_t b, int nb, int& rs, int& rlen) {
+      const int64_t rl = b + min(lane, nb - 1);
+      rs = rowptr[rl];
+      rlen = (lane < nb) ? rowptr[rl + 1] - rs : 0;
+    };
+    auto load_cols = [&](const GroupExt<ROWS>& e, int& cj, float& av) {
+      const int64_t ce = min<int64_t>((int64_t)e.gs + lane, nnz - 1);
+      cj = col[ce];
+      av = PATTERN ? 1.f : val[ce];
+    };
+    int64_t b = w0;
+    int nb = (int)min<int64_t>(64, w1 - b);
+    int rs, rlen;
+    load_batch(b, nb, rs, rlen);
+    int64_t bn = b + 64;
+    int nbn = bn < w1 ? (int)min<int64_t>(64, w1 - bn) : 0;
+    int rs_n = 0, rlen_n = 0;
+    if (nbn) load_batch(bn, nbn, rs_n, rlen_n);
+    int q = 0;
+    GroupExt<ROWS> cur = group_extent<ROWS>(rs, rlen, nb, q);
+    int cj = 0;
+    float av = 0.f;
+    if (nnz > 0) load_cols(cur, cj, av);
+
+    while (true) {
+      const bool fast = MAXNZ > 0 && nnz > 0 && cur.maxlen <= MAXNZ && cur.cnt <= 64;
+      T x[ROWS][MAXNZ > 0 ? MAXNZ : 1];
+      float wt[ROWS][MAXNZ > 0 ? MAXNZ : 1];
+      T xi[ROWS], xp[ROWS];
+      if (fast) {
+        // all gathers of the group, and the matrix values as uniform
+        // scalars, before anything else is issued
 #pragma unroll
-      for (int r = 0; r < kGroupRows; ++r) {
-        const int rr = min(q + r, nb - 1);
-        off[r] = read_lane(rs, rr) - gs;
-        len[r] = (r < nr) ? read_lane(rlen, rr) : 0;
-        maxlen = max(maxlen, len[r]);
-      }
-      const int cnt = off[nr - 1] + len[nr - 1];
-      if (MAXNZ > 0 && maxlen <= MAXNZ && cnt <= 64 && nnz > 0) {
-        // one coalesced load of the group's columns (clamped, always in bounds)
-        const int64_t ce = min<int64_t>((int64_t)gs + lane, nnz - 1);
-        const int cj = col[ce];
-        const float av = PATTERN ? 1.f : val[ce];
-        T x[kGroupRows][MAXNZ > 0 ? MAXNZ : 1];
-        T xi[kGroupRows], xp[kGroupRows];
-#pragma unroll
-        for (int r = 0; r < kGroupRows; ++r) {
-          const int64_t i = b0 + min(q + r, nb - 1);
+        for (int r = 0; r < ROWS; ++r) {
+          const int64_t i = b + min(q + r, nb - 1);
 #pragma unroll
           for (int t = 0; t < MAXNZ; ++t) {
-            const int slot = min(off[r] + t, 63);
-            const int j = (t < len[r]) ? read_lane(cj, slot) : (int)i;
+            const int slot = min(cur.off[r] + t, 63);
+            const int jj = read_lane(cj, slot);
+            const float ww = PATTERN ? 1.f : read_lane(av, slot);
+            const bool use = t < cur.len[r];
+            const int j = use ? jj : (int)i;
+            wt[r][t] = use ? ww : 0.f;
             x[r][t] = vk[(int64_t)j * 64 + lane];
           }
           xi[r] = vk[i * 64 + lane];
           xp[r] = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
         }
-#pragma unroll
-        for (int r = 0; r < kGroupRows; ++r) {
-          T acc = T(0);
-#pragma unroll
-          for (int t = 0; t < MAXNZ; ++t) {
-            const int slot = min(off[r] + t, 63);
-            const float w = (t < len[r]) ? (PATTERN ? 1.f : read_lane(av, slot)) : 0.f;
-            acc = fma((T)w, x[r][t], acc);
-          }
-          if (r < nr)
-            finish_row<T, ZMODE, HAS_PREV>(b0 + q + r, acc, xi[r], xp[r], ca, cb, vm, src,
-                                           act, key, cached, word, acc1, acc2);
-        }
-      } else {
-        for (int r = 0; r < nr; ++r) {
-          const int64_t i = b0 + q + r;
-          const int s = gs + off[r];
-          const T acc = row_dot_generic<T, PATTERN>(col, val, vk, s, s + len[r]);
-          const T xi = vk[i * 64 + lane];
-          const T xp = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
-          finish_row<T, ZMODE, HAS_PREV>(i, acc, xi, xp, ca, cb, vm, src, act, key, cached,
-                                         word, acc1, acc2);
+      }
+      // next group: position, extent and column prefetch
+      int qn = q + ROWS;
+      bool has_next = true, new_batch = false;
+      if (qn >= nb) {
+        if (nbn > 0) {
+          new_batch = true;
+          qn = 0;
+        } else {
+          has_next = false;
         }
       }
+      GroupExt<ROWS> nxt = cur;
+      int cjn = 0;
+      float avn = 0.f;
+      if (has_next) {
+        nxt = new_batch ? group_extent<ROWS>(rs_n, rlen_n, nbn, 0)
+                        : group_extent<ROWS>(rs, rlen, nb, qn);
+        if (nnz > 0) load_cols(nxt, cjn, avn);
+      }
+      if (fast) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+          T acc = T(0);
+#pragma unroll
+          for (int t = 0; t < MAXNZ; ++t) acc = fma((T)wt[r][t], x[r][t], acc);
+          if (r < cur.nr)
+            finish_row<T, ZMODE, HAS_PREV>(b + q + r, acc, xi[r], xp[r], ca, cb, vm, src, act,
+                                           key, cached, word, acc1, acc2);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {  // static indices: cur stays in registers
+          if (r < cur.nr) {
+            const int64_t i = b + q + r;
+            const int s = cur.gs + cur.off[r];
+            const T acc = row_dot_generic<T, PATTERN>(col, val, vk, s, s + cur.len[r]);
+            const T xi1 = vk[i * 64 + lane];
+            const T xp1 = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
+            finish_row<T, ZMODE, HAS_PREV>(i, acc, xi1, xp1, ca, cb, vm, src, act, key, cached,
+                                           word, acc1, acc2);
+          }
+        }
+      }
+      if (!has_next) break;
+      if (new_batch) {
+        b = bn;
+        nb = nbn;
+        rs = rs_n;
+        rlen = rlen_n;
+        bn = b + 64;
+        nbn = bn < w1 ? (int)min<int64_t>(64, w1 - bn) : 0;
+        if (nbn) load_batch(bn, nbn, rs_n, rlen_n);
+      }
+      q = qn;
+      cur = nxt;
+      cj = cjn;
+      av = avn;
     }
   }
   store_partials<T>(acc1, acc2, g, ngroups, part);
@@ -251,13 +329,15 @@ hipError_t launch_step_t(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T
   return hipGetLastError();
 }
 
-// Row capacity of the straight-line path: the smallest of {4, 8} that holds
-// the longest row, else 8 (long rows then take the generic loop).
+// Row capacity of the straight-line path: the smallest of {4, 5, 8} that
+// holds the longest row, else 8 (longer rows then take the generic loop).
 template <typename T, bool PATTERN, int ZMODE>
 hipError_t launch_step_nz(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
                           bool has_prev, ProbeSrc src, const CsrStepPlan& plan, double* part) {
   if (op->max_row_nnz <= 4)
     return launch_step_t<T, PATTERN, ZMODE, 4>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+  if (op->max_row_nnz <= 5)
+    return launch_step_t<T, PATTERN, ZMODE, 5>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
   return launch_step_t<T, PATTERN, ZMODE, 8>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
 }
 
