@@ -103,6 +103,33 @@ __device__ __forceinline__ void finish_row(int64_t i, T acc, T xi, T xp, T ca, T
   }
 }
 
+// Gathers of block rows.  With OFF32 (block under 4 GiB, FP32) they are
+// buffer loads: the block base sits in a scalar resource, the row offset
+// j * 256 in a scalar register and lane * 4 in one VGPR shared by every
+// gather, so a gather costs no address registers.  Out-of-range offsets read
+// as 0 (the resource's size is the block's size).
+template <typename T, bool OFF32>
+struct RowReader {
+  const T* base;
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t lane_off;
+  __device__ __forceinline__ RowReader(const T* b, int64_t d, int lane) : base(b) {
+    if (OFF32) {
+      rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(b), (short)0,
+                                               (int)(uint32_t)(d * 64 * sizeof(T)), 0x00020000);
+      lane_off = (uint32_t)lane * sizeof(T);
+    }
+  }
+  __device__ __forceinline__ T operator()(int64_t j, int lane) const {
+    if (OFF32) {
+      const uint32_t bits = __builtin_amdgcn_raw_buffer_load_b32(
+          rsrc, lane_off, (int)((uint32_t)j * (uint32_t)(64 * sizeof(T))), 0);
+      return __uint_as_float(bits);
+    }
+    return base[j * 64 + lane];
+  }
+};
+
 // Generic row: loop over 64-entry chunks of the row's columns.
 template <typename T, bool PATTERN>
 __device__ __forceinline__ T row_dot_generic(const int32_t* __restrict__ col,
@@ -178,7 +205,7 @@ __device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int nb,
 // are straight-line code (unused slots gather the row itself with weight 0)
 // and are all in flight before the first is consumed; other groups take the
 // generic loop.
-template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ>
+template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
 __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
@@ -200,6 +227,7 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
   const int64_t rpw = ((span + kWaves - 1) / kWaves + 63) / 64 * 64;
   const int64_t w0 = r0 + (int64_t)wave * rpw;
   const int64_t w1 = min<int64_t>(w0 + rpw, r1);
+  const RowReader<T, OFF32> rd(vk, d, lane);
 
   if (w0 < w1) {
     auto load_batch = [&](int64_t b, int nb, int& rs, int& rlen) {
@@ -229,25 +257,16 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     while (true) {
       const bool fast = MAXNZ > 0 && nnz > 0 && cur.maxlen <= MAXNZ && cur.cnt <= 64;
       T x[ROWS][MAXNZ > 0 ? MAXNZ : 1];
-      float wt[ROWS][MAXNZ > 0 ? MAXNZ : 1];
       T xi[ROWS], xp[ROWS];
       if (fast) {
-        // all gathers of the group, and the matrix values as uniform
-        // scalars, before anything else is issued
+        // all gathers of the group before anything else is issued; unused
+        // slots gather some valid row and get weight 0 below
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
           const int64_t i = b + min(q + r, nb - 1);
 #pragma unroll
-          for (int t = 0; t < MAXNZ; ++t) {
-            const int slot = min(cur.off[r] + t, 63);
-            const int jj = read_lane(cj, slot);
-            const float ww = PATTERN ? 1.f : read_lane(av, slot);
-            const bool use = t < cur.len[r];
-            const int j = use ? jj : (int)i;
-            wt[r][t] = use ? ww : 0.f;
-            x[r][t] = vk[(int64_t)j * 64 + lane];
-          }
-          xi[r] = vk[i * 64 + lane];
+          for (int t = 0; t < MAXNZ; ++t) x[r][t] = rd(read_lane(cj, min(cur.off[r] + t, 63)), lane);
+          xi[r] = rd(i, lane);
           xp[r] = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
         }
       }
@@ -275,7 +294,11 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
         for (int r = 0; r < ROWS; ++r) {
           T acc = T(0);
 #pragma unroll
-          for (int t = 0; t < MAXNZ; ++t) acc = fma((T)wt[r][t], x[r][t], acc);
+          for (int t = 0; t < MAXNZ; ++t) {
+            const float on = (t < cur.len[r]) ? 1.f : 0.f;
+            const float w = PATTERN ? on : read_lane(av, min(cur.off[r] + t, 63)) * on;
+            acc = fma((T)w, x[r][t], acc);
+          }
           if (r < cur.nr)
             finish_row<T, ZMODE, HAS_PREV>(b + q + r, acc, xi[r], xp[r], ca, cb, vm, src, act,
                                            key, cached, word, acc1, acc2);
@@ -313,17 +336,17 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
   store_partials<T>(acc1, acc2, g, ngroups, part);
 }
 
-template <typename T, bool PATTERN, int ZMODE, int MAXNZ>
+template <typename T, bool PATTERN, int ZMODE, int MAXNZ, bool OFF32>
 hipError_t launch_step_t(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, double* part) {
   const dim3 grid(plan.ngroups), block(kThreads);
   const float* val = static_cast<const float*>(op->val);
   if (has_prev)
-    csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ><<<grid, block, 0, s>>>(
+    csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32><<<grid, block, 0, s>>>(
         op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, plan.rows_per_group,
         plan.ngroups, part);
   else
-    csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ><<<grid, block, 0, s>>>(
+    csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32><<<grid, block, 0, s>>>(
         op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, plan.rows_per_group,
         plan.ngroups, part);
   return hipGetLastError();
@@ -331,14 +354,20 @@ hipError_t launch_step_t(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T
 
 // Row capacity of the straight-line path: the smallest of {4, 5, 8} that
 // holds the longest row, else 8 (longer rows then take the generic loop).
+// FP32 blocks under 4 GiB use 32-bit gather offsets; FP64 (a verification
+// precision) uses one general instantiation.
 template <typename T, bool PATTERN, int ZMODE>
 hipError_t launch_step_nz(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
                           bool has_prev, ProbeSrc src, const CsrStepPlan& plan, double* part) {
-  if (op->max_row_nnz <= 4)
-    return launch_step_t<T, PATTERN, ZMODE, 4>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-  if (op->max_row_nnz <= 5)
-    return launch_step_t<T, PATTERN, ZMODE, 5>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-  return launch_step_t<T, PATTERN, ZMODE, 8>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+  const bool off32 = (uint64_t)op->d * 64 * sizeof(T) <= 0xFFFFFFFFull;
+  if (sizeof(T) == 4 && off32) {
+    if (op->max_row_nnz <= 4)
+      return launch_step_t<T, PATTERN, ZMODE, 4, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+    if (op->max_row_nnz <= 5)
+      return launch_step_t<T, PATTERN, ZMODE, 5, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+    return launch_step_t<T, PATTERN, ZMODE, 8, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+  }
+  return launch_step_t<T, PATTERN, ZMODE, 8, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
 }
 
 template <typename T>
