@@ -19,7 +19,7 @@ namespace mlct {
 
 namespace {
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * 64;
 
 template <typename T>
@@ -171,8 +171,9 @@ __device__ __forceinline__ T row_dot_generic(const int32_t* __restrict__ col,
   return acc;
 }
 
-// Extent of a group of up to ROWS consecutive rows inside a 64-row batch
-// whose start offsets (rs) and lengths (rlen) sit one per lane.
+// Extent of one group of up to ROWS consecutive rows.  The group's rows sit
+// in lanes q .. q+ROWS-1 of a batch: rs = start of the row's columns,
+// rlen = its length (0 for lanes past the end of the matrix).
 template <int ROWS>
 struct GroupExt {
   int gs, cnt, nr, maxlen;
@@ -180,31 +181,32 @@ struct GroupExt {
 };
 
 template <int ROWS>
-__device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int nb, int q) {
+__device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int q, int nr) {
   GroupExt<ROWS> e;
-  e.nr = min(ROWS, nb - q);
+  e.nr = nr;
   e.gs = read_lane(rs, q);
   e.maxlen = 0;
   e.cnt = 0;
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
-    const int rr = min(q + r, nb - 1);
-    e.off[r] = read_lane(rs, rr) - e.gs;
-    e.len[r] = (r < e.nr) ? read_lane(rlen, rr) : 0;
+    const bool in = r < nr;
+    e.off[r] = in ? read_lane(rs, q + r) - e.gs : 0;
+    e.len[r] = in ? read_lane(rlen, q + r) : 0;
     e.maxlen = max(e.maxlen, e.len[r]);
-    if (r < e.nr) e.cnt = e.off[r] + e.len[r];  // static indices only
+    if (in) e.cnt = e.off[r] + e.len[r];  // static indices only
   }
   return e;
 }
 
-// Each wave owns a contiguous run of rows, walked in groups of ROWS rows.
-// The column indices and values of a group come in one coalesced load,
-// issued while the previous group's gathers are in flight (software
-// pipelining); row extents come in 64-row batches, prefetched one batch
-// ahead.  When every row of a group has at most MAXNZ entries, its gathers
-// are straight-line code (unused slots gather the row itself with weight 0)
-// and are all in flight before the first is consumed; other groups take the
-// generic loop.
+// Work split: a workgroup owns a contiguous band of rows cut into groups of
+// ROWS rows; wave w takes groups w, w + kWaves, w + 2 kWaves, ..., so the
+// waves of a workgroup sweep the band side by side.  A wave fetches the row
+// extents of its next 64/ROWS groups in one load (a "batch", prefetched one
+// batch ahead) and the column indices and values of a group in one coalesced
+// load, issued while the previous group's gathers are in flight.  When every
+// row of a group has at most MAXNZ entries its gathers are straight-line code
+// (unused slots gather some valid row with weight 0), all in flight before
+// the first is consumed; other groups take the generic loop.
 template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
 __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -212,6 +214,7 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     T* __restrict__ vm, T ca, T cb, ProbeSrc src, int rows_per_group, int ngroups,
     double* __restrict__ part) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
+  constexpr int GPB = 64 / ROWS;  // groups per batch
   const int lane = lane_id(), wave = wave_id();
   const int g = xcd_band(blockIdx.x, ngroups);
   const int64_t r0 = (int64_t)g * rows_per_group;
@@ -223,70 +226,65 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
   uint64_t word = 0;
   double acc1 = 0.0, acc2 = 0.0;
 
-  const int64_t span = r1 - r0;
-  const int64_t rpw = ((span + kWaves - 1) / kWaves + 63) / 64 * 64;
-  const int64_t w0 = r0 + (int64_t)wave * rpw;
-  const int64_t w1 = min<int64_t>(w0 + rpw, r1);
+  const int64_t ngrp = r1 > r0 ? (r1 - r0 + ROWS - 1) / ROWS : 0;  // groups in the band
+  const int64_t nk = ngrp > wave ? (ngrp - wave + kWaves - 1) / kWaves : 0;  // this wave's
   const RowReader<T, OFF32> rd(vk, d, lane);
+  // first row of this wave's k-th group, and its number of rows
+  auto grp_row0 = [&](int64_t k) { return r0 + (k * kWaves + wave) * ROWS; };
+  auto grp_rows = [&](int64_t k) { return (int)min<int64_t>(ROWS, r1 - grp_row0(k)); };
 
-  if (w0 < w1) {
-    auto load_batch = [&](int64_t b, int nb, int& rs, int& rlen) {
-      const int64_t rl = b + min(lane, nb - 1);
-      rs = rowptr[rl];
-      rlen = (lane < nb) ? rowptr[rl + 1] - rs : 0;
+  if (nk > 0) {
+    auto load_batch = [&](int64_t j, int& rs, int& rlen) {
+      const int64_t k = j * GPB + lane / ROWS;
+      const int64_t row = grp_row0(k) + lane % ROWS;
+      const bool ok = k < nk && row < r1;
+      const int64_t rr = ok ? row : r0;
+      rs = rowptr[rr];
+      rlen = ok ? rowptr[rr + 1] - rs : 0;
     };
     auto load_cols = [&](const GroupExt<ROWS>& e, int& cj, float& av) {
       const int64_t ce = min<int64_t>((int64_t)e.gs + lane, nnz - 1);
       cj = col[ce];
       av = PATTERN ? 1.f : val[ce];
     };
-    int64_t b = w0;
-    int nb = (int)min<int64_t>(64, w1 - b);
-    int rs, rlen;
-    load_batch(b, nb, rs, rlen);
-    int64_t bn = b + 64;
-    int nbn = bn < w1 ? (int)min<int64_t>(64, w1 - bn) : 0;
-    int rs_n = 0, rlen_n = 0;
-    if (nbn) load_batch(bn, nbn, rs_n, rlen_n);
-    int q = 0;
-    GroupExt<ROWS> cur = group_extent<ROWS>(rs, rlen, nb, q);
+    const int64_t nbatch = (nk + GPB - 1) / GPB;
+    int64_t j = 0;
+    int rs, rlen, rs_n = 0, rlen_n = 0;
+    load_batch(0, rs, rlen);
+    if (nbatch > 1) load_batch(1, rs_n, rlen_n);
+    int64_t k = 0;
+    GroupExt<ROWS> cur = group_extent<ROWS>(rs, rlen, 0, grp_rows(0));
     int cj = 0;
     float av = 0.f;
     if (nnz > 0) load_cols(cur, cj, av);
 
     while (true) {
+      const int64_t row0 = grp_row0(k);
       const bool fast = MAXNZ > 0 && nnz > 0 && cur.maxlen <= MAXNZ && cur.cnt <= 64;
       T x[ROWS][MAXNZ > 0 ? MAXNZ : 1];
       T xi[ROWS], xp[ROWS];
       if (fast) {
-        // all gathers of the group before anything else is issued; unused
-        // slots gather some valid row and get weight 0 below
+        // all gathers of the group before anything else is issued
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
-          const int64_t i = b + min(q + r, nb - 1);
+          const int64_t i = row0 + min(r, cur.nr - 1);
 #pragma unroll
           for (int t = 0; t < MAXNZ; ++t) x[r][t] = rd(read_lane(cj, min(cur.off[r] + t, 63)), lane);
           xi[r] = rd(i, lane);
           xp[r] = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
         }
       }
-      // next group: position, extent and column prefetch
-      int qn = q + ROWS;
-      bool has_next = true, new_batch = false;
-      if (qn >= nb) {
-        if (nbn > 0) {
-          new_batch = true;
-          qn = 0;
-        } else {
-          has_next = false;
-        }
-      }
+      // next group: extent and column prefetch
+      const int64_t kn = k + 1;
+      const bool has_next = kn < nk;
+      const bool new_batch = has_next && (kn % GPB) == 0;
       GroupExt<ROWS> nxt = cur;
       int cjn = 0;
       float avn = 0.f;
       if (has_next) {
-        nxt = new_batch ? group_extent<ROWS>(rs_n, rlen_n, nbn, 0)
-                        : group_extent<ROWS>(rs, rlen, nb, qn);
+        const int qn = (int)(kn % GPB) * ROWS;
+        nxt = new_batch ? group_extent<ROWS>(rs_n, rlen_n, 0, grp_rows(kn))
+                        : group_extent<ROWS>(rs, rlen, qn, grp_rows(kn));
         if (nnz > 0) load_cols(nxt, cjn, avn);
       }
       if (fast) {
@@ -300,16 +298,16 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
             acc = fma((T)w, x[r][t], acc);
           }
           if (r < cur.nr)
-            finish_row<T, ZMODE, HAS_PREV>(b + q + r, acc, xi[r], xp[r], ca, cb, vm, src, act,
+            finish_row<T, ZMODE, HAS_PREV>(row0 + r, acc, xi[r], xp[r], ca, cb, vm, src, act,
                                            key, cached, word, acc1, acc2);
         }
       } else {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {  // static indices: cur stays in registers
           if (r < cur.nr) {
-            const int64_t i = b + q + r;
-            const int s = cur.gs + cur.off[r];
-            const T acc = row_dot_generic<T, PATTERN>(col, val, vk, s, s + cur.len[r]);
+            const int64_t i = row0 + r;
+            const int s0 = cur.gs + cur.off[r];
+            const T acc = row_dot_generic<T, PATTERN>(col, val, vk, s0, s0 + cur.len[r]);
             const T xi1 = vk[i * 64 + lane];
             const T xp1 = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
             finish_row<T, ZMODE, HAS_PREV>(i, acc, xi1, xp1, ca, cb, vm, src, act, key, cached,
@@ -319,15 +317,12 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
       }
       if (!has_next) break;
       if (new_batch) {
-        b = bn;
-        nb = nbn;
         rs = rs_n;
         rlen = rlen_n;
-        bn = b + 64;
-        nbn = bn < w1 ? (int)min<int64_t>(64, w1 - bn) : 0;
-        if (nbn) load_batch(bn, nbn, rs_n, rlen_n);
+        ++j;
+        if (j + 1 < nbatch) load_batch(j + 1, rs_n, rlen_n);
       }
-      q = qn;
+      k = kn;
       cur = nxt;
       cj = cjn;
       av = avn;
