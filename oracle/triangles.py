@@ -52,17 +52,27 @@ def probe_moments(rowptr, col, Z_int: np.ndarray) -> np.ndarray:
 
 
 def control_variate(w: np.ndarray, nnz: int, trace_a: float = 0.0):
-    """(estimate_cv, a1, a2) from the per-probe moments (OLS with intercept)."""
+    """(estimate_cv, a1, a2) from the per-probe moments.
+
+    Ordinary least squares of w3 on [1, w1, w2]: with the intercept the
+    slopes solve the centred 2x2 normal equations
+    [[S11, S12], [S12, S22]] (a1, a2) = (S13, S23), S_ab = sum (w_a - mean)(w_b - mean).
+    If fewer than 3 samples or the 2x2 system is singular, no control variate
+    is used (a1 = a2 = 0)."""
     w = np.asarray(w, dtype=np.float64)
     m = w.shape[0]
-    if m < 3:
-        return float(np.mean(w[:, 2]) / 6.0), 0.0, 0.0
-    X = np.stack([np.ones(m), w[:, 0], w[:, 1]], axis=1)
-    coef, *_ = np.linalg.lstsq(X, w[:, 2], rcond=None)
-    a1, a2 = float(coef[1]), float(coef[2])
-    est = (np.mean(w[:, 2] - a1 * w[:, 0] - a2 * w[:, 1])
-           + a1 * trace_a + a2 * nnz) / 6.0
-    return float(est), a1, a2
+    mean = w.mean(axis=0)
+    a1 = a2 = 0.0
+    if m >= 3:
+        c = w - mean
+        S = c[:, :2].T @ c[:, :2]
+        rhs = c[:, :2].T @ c[:, 2]
+        det = S[0, 0] * S[1, 1] - S[0, 1] ** 2
+        if S[0, 0] > 0 and S[1, 1] > 0 and det > 1e-12 * S[0, 0] * S[1, 1]:
+            a1 = (S[1, 1] * rhs[0] - S[0, 1] * rhs[1]) / det
+            a2 = (S[0, 0] * rhs[1] - S[0, 1] * rhs[0]) / det
+    est = (mean[2] - a1 * mean[0] - a2 * mean[1] + a1 * trace_a + a2 * nnz) / 6.0
+    return float(est), float(a1), float(a2)
 
 
 def estimate(rowptr, col, m: int, seed: int, first_id: int = 0) -> TriResult:

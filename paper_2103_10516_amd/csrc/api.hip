@@ -523,9 +523,55 @@ mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t, int64_t, const void*, int64_t, 
 mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op*, int32_t, uint64_t, double, double*, double*) {
   return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "Lanczos bounds not built yet") : MLCT_EINVAL;
 }
-mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op*, int64_t, uint64_t, int64_t*,
-                           mlct_tri_result*) {
-  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "triangles not built yet") : MLCT_EINVAL;
+mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t seed,
+                           int64_t* w_out, mlct_tri_result* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !out) return fail(ctx, MLCT_EINVAL, "op and out are required");
+  if (op->kind != OP_CSR || op->val != nullptr)
+    return fail(ctx, MLCT_EINVAL, "triangle counting needs a 0/1 pattern CSR operator");
+  if (m < 1) return fail(ctx, MLCT_EINVAL, "need m >= 1 probes");
+  CHECK(set_device(ctx));
+  const CsrStepPlan plan = plan_csr(op->d);
+  const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(int32_t);
+  void *z, *y, *part, *w, *res;
+  CHECK(ws_get(ctx, WS_V0, vbytes, &z));
+  CHECK(ws_get(ctx, WS_V1, vbytes, &y));
+  CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * sizeof(long long), &part));
+  CHECK(ws_get(ctx, WS_TRI, (size_t)m * 3 * sizeof(long long), &w));
+  CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_tri_result), &res));
+  hipStream_t s = ctx->stream;
+  long long* P = static_cast<long long*>(part);
+  long long* W = static_cast<long long*>(w);
+  for (int64_t p0 = 0; p0 < m; p0 += kBlockProbes) {
+    ProbeSrc src{};
+    src.seed = seed;
+    src.first_id = p0;
+    src.active = (int32_t)((m - p0) < kBlockProbes ? (m - p0) : kBlockProbes);
+    HIPCHK(ctx, launch_tri_init(s, op, src, plan, static_cast<int32_t*>(z)));
+    {
+      LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
+      HIPCHK(ctx, launch_tri_step(s, op, 1, plan, static_cast<int32_t*>(z),
+                                  static_cast<int32_t*>(y), P));
+      tm.done();
+    }
+    HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 1, W, p0));
+    {
+      LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
+      HIPCHK(ctx, launch_tri_step(s, op, 2, plan, static_cast<int32_t*>(y), nullptr, P));
+      tm.done();
+    }
+    HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 2, W, p0));
+  }
+  HIPCHK(ctx, launch_tri_cv(s, W, m, op->nnz, static_cast<mlct_tri_result*>(res)));
+  mlct_tri_result h;
+  HIPCHK(ctx, hipMemcpyAsync(&h, res, sizeof h, hipMemcpyDeviceToHost, s));
+  if (w_out)
+    HIPCHK(ctx, hipMemcpyAsync(w_out, W, (size_t)m * 3 * sizeof(long long),
+                               hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  *out = h;
+  return MLCT_OK;
 }
 
 }  // extern "C"

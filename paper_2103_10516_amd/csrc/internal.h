@@ -131,4 +131,14 @@ hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
                            double* part);
 
+// ---- integer triangle moments (k_tri.hip) ----------------------------------
+hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
+                           const CsrStepPlan& plan, int32_t* z);
+hipError_t launch_tri_step(hipStream_t s, const mlct_op* op, int pass, const CsrStepPlan& plan,
+                           const int32_t* vin, int32_t* vout, long long* part);
+hipError_t launch_tri_reduce(hipStream_t s, const long long* part, int ngroups, int active,
+                             int pass, long long* w, int64_t p0);
+hipError_t launch_tri_cv(hipStream_t s, const long long* w, int64_t m, int64_t nnz,
+                         mlct_tri_result* out);
+
 }  // namespace mlct

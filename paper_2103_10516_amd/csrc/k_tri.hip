@@ -1,0 +1,247 @@
+// Exact triangle-count moments over a 0/1 pattern CSR (Section 2.1 example
+// and footnote, Section 5.5).  Per probe z, two integer SpMMs:
+//   pass 1: y = A z   (int32, stored), w1 += z_i y_i, w2 += y_i^2   (int64)
+//   pass 2: w = A y   (int32, never stored), w3 += y_i w_i           (int64)
+// |y_i| <= deg(i) and |w_i| <= sum of degrees = nnz < 2^31, so int32 holds
+// every vector entry and int64 every product and sum exactly.
+// Layout as in the FP recurrence: blocks are row-major d x 64, lane = probe.
+// Every workgroup owns a contiguous band of rows and writes one int64
+// partial per probe and slot; the partials are summed afterwards.
+#include "device.hpp"
+
+namespace mlct {
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = kWaves * 64;
+
+__device__ __forceinline__ void store_partials_i64(long long a1, long long a2, int g,
+                                                   int ngroups, long long* __restrict__ part) {
+  __shared__ long long sh[2][kWaves][64];
+  const int lane = lane_id(), wave = wave_id();
+  sh[0][wave][lane] = a1;
+  sh[1][wave][lane] = a2;
+  __syncthreads();
+  if (wave == 0) {
+    long long s1 = 0, s2 = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      s1 += sh[0][w][lane];
+      s2 += sh[1][w][lane];
+    }
+    part[(size_t)g * 64 + lane] = s1;
+    part[((size_t)ngroups + g) * 64 + lane] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void tri_init_kernel(int32_t* __restrict__ z, int64_t d,
+                                                            ProbeSrc src, int rows_per_group,
+                                                            int ngroups) {
+  const int lane = lane_id(), wave = wave_id();
+  const int g = xcd_band(blockIdx.x, ngroups);
+  const int64_t r0 = (int64_t)g * rows_per_group;
+  const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
+  const bool act = lane < src.active;
+  const uint64_t key = sm_output(src.seed, (uint64_t)(src.first_id + lane));
+  int64_t cached = -1;
+  uint64_t word = 0;
+  for (int64_t i = r0 + wave; i < r1; i += kWaves) {
+    int32_t v = 0;
+    if (act) {
+      const int64_t c = i >> 6;
+      if (c != cached) {
+        word = sm_output(key, (uint64_t)c);
+        cached = c;
+      }
+      v = sign_from_word<int32_t>(word, i);
+    }
+    z[i * 64 + lane] = v;
+  }
+}
+
+// Row sum of a pattern row over a block: sum_{j in row} vin[j][lane].
+__device__ __forceinline__ int32_t pattern_row_sum(const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ vin, int s, int e) {
+  const int lane = lane_id();
+  int32_t acc = 0;
+  for (int base = s; base < e; base += 64) {
+    const int c = min(64, e - base);
+    const int cj = lane < c ? col[base + lane] : 0;
+    int t = 0;
+    for (; t + 4 <= c; t += 4) {
+      const int32_t x0 = vin[(int64_t)read_lane(cj, t) * 64 + lane];
+      const int32_t x1 = vin[(int64_t)read_lane(cj, t + 1) * 64 + lane];
+      const int32_t x2 = vin[(int64_t)read_lane(cj, t + 2) * 64 + lane];
+      const int32_t x3 = vin[(int64_t)read_lane(cj, t + 3) * 64 + lane];
+      acc += (x0 + x1) + (x2 + x3);
+    }
+    for (; t < c; ++t) acc += vin[(int64_t)read_lane(cj, t) * 64 + lane];
+  }
+  return acc;
+}
+
+// PASS 1: vin = z, vout = y; slot 0 = z.y, slot 1 = y.y.
+// PASS 2: vin = y, vout unused; slot 0 = y.(A y), slot 1 = 0.
+template <int PASS>
+__global__ __launch_bounds__(kThreads) void tri_step_kernel(const int32_t* __restrict__ rowptr,
+                                                            const int32_t* __restrict__ col,
+                                                            int64_t d,
+                                                            const int32_t* __restrict__ vin,
+                                                            int32_t* __restrict__ vout,
+                                                            int rows_per_group, int ngroups,
+                                                            long long* __restrict__ part) {
+  const int lane = lane_id(), wave = wave_id();
+  const int g = xcd_band(blockIdx.x, ngroups);
+  const int64_t r0 = (int64_t)g * rows_per_group;
+  const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
+  long long a1 = 0, a2 = 0;
+  for (int64_t b0 = r0 + (int64_t)wave * 64; b0 < r1; b0 += kWaves * 64) {
+    const int nb = (int)min<int64_t>(64, r1 - b0);
+    const int64_t rl = b0 + min(lane, nb - 1);
+    const int rs = rowptr[rl];
+    const int re = rowptr[rl + 1];
+    for (int r = 0; r < nb; ++r) {
+      const int64_t i = b0 + r;
+      const int32_t s = read_lane(rs, r), e = read_lane(re, r);
+      const int32_t v = pattern_row_sum(col, vin, s, e);
+      const int32_t own = vin[i * 64 + lane];
+      if (PASS == 1) {
+        vout[i * 64 + lane] = v;
+        a1 += (long long)own * v;
+        a2 += (long long)v * v;
+      } else {
+        a1 += (long long)own * v;
+      }
+    }
+  }
+  store_partials_i64(a1, a2, g, ngroups, part);
+}
+
+// w[(p0 + p) * 3 + slot_out] = sum over groups of the partials.
+__global__ void tri_reduce_kernel(const long long* __restrict__ part, int ngroups, int active,
+                                  int pass, long long* __restrict__ w, int64_t p0) {
+  const int p = threadIdx.x;
+  if (p >= active) return;
+  long long s0 = 0, s1 = 0;
+  for (int g = 0; g < ngroups; ++g) {
+    s0 += part[(size_t)g * 64 + p];
+    s1 += part[((size_t)ngroups + g) * 64 + p];
+  }
+  if (pass == 1) {
+    w[(p0 + p) * 3 + 0] = s0;
+    w[(p0 + p) * 3 + 1] = s1;
+  } else {
+    w[(p0 + p) * 3 + 2] = s0;
+  }
+}
+
+// Control variates of Section 5.5: ordinary least squares of w3 on
+// [1, w1, w2] (centred normal equations), then
+// T_cv = (mean(w3 - a1 w1 - a2 w2) + a1 tr(A) + a2 nnz) / 6 with tr(A) = 0.
+// If the centred 2x2 system is singular no control variate is used.
+// One workgroup, fixed-order sums.
+constexpr int kCvThreads = 256;
+
+__device__ double cv_block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kCvThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ long long cv_block_sum_i(long long v, long long* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kCvThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  const long long r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kCvThreads) void tri_cv_kernel(const long long* __restrict__ w,
+                                                            int64_t m, int64_t nnz,
+                                                            mlct_tri_result* __restrict__ out) {
+  __shared__ double sh[kCvThreads];
+  __shared__ long long shi[kCvThreads];
+  long long t1 = 0, t2 = 0, t3 = 0;
+  for (int64_t p = threadIdx.x; p < m; p += kCvThreads) {
+    t1 += w[p * 3];
+    t2 += w[p * 3 + 1];
+    t3 += w[p * 3 + 2];
+  }
+  const long long s1 = cv_block_sum_i(t1, shi), s2 = cv_block_sum_i(t2, shi);
+  const long long s3 = cv_block_sum_i(t3, shi);
+  const double m1 = (double)s1 / m, m2 = (double)s2 / m, m3 = (double)s3 / m;
+  double c11 = 0, c12 = 0, c22 = 0, c13 = 0, c23 = 0;
+  for (int64_t p = threadIdx.x; p < m; p += kCvThreads) {
+    const double x1 = (double)w[p * 3] - m1, x2 = (double)w[p * 3 + 1] - m2;
+    const double x3 = (double)w[p * 3 + 2] - m3;
+    c11 += x1 * x1;
+    c12 += x1 * x2;
+    c22 += x2 * x2;
+    c13 += x1 * x3;
+    c23 += x2 * x3;
+  }
+  c11 = cv_block_sum(c11, sh);
+  c12 = cv_block_sum(c12, sh);
+  c22 = cv_block_sum(c22, sh);
+  c13 = cv_block_sum(c13, sh);
+  c23 = cv_block_sum(c23, sh);
+  if (threadIdx.x == 0) {
+    double a1 = 0.0, a2 = 0.0;
+    const double det = c11 * c22 - c12 * c12;
+    if (m >= 3 && det > 1e-12 * c11 * c22 && c11 > 0 && c22 > 0) {
+      a1 = (c22 * c13 - c12 * c23) / det;
+      a2 = (c11 * c23 - c12 * c13) / det;
+    }
+    out->sum_w3 = s3;
+    out->estimate = (double)s3 / (6.0 * (double)m);
+    out->estimate_cv = (m3 - a1 * m1 - a2 * m2 + a2 * (double)nnz) / 6.0;
+    out->a1 = a1;
+    out->a2 = a2;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
+                           const CsrStepPlan& plan, int32_t* z) {
+  tri_init_kernel<<<plan.ngroups, kThreads, 0, s>>>(z, op->d, src, plan.rows_per_group,
+                                                    plan.ngroups);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_step(hipStream_t s, const mlct_op* op, int pass, const CsrStepPlan& plan,
+                           const int32_t* vin, int32_t* vout, long long* part) {
+  if (pass == 1)
+    tri_step_kernel<1><<<plan.ngroups, kThreads, 0, s>>>(op->rowptr, op->col, op->d, vin, vout,
+                                                         plan.rows_per_group, plan.ngroups, part);
+  else
+    tri_step_kernel<2><<<plan.ngroups, kThreads, 0, s>>>(op->rowptr, op->col, op->d, vin,
+                                                         nullptr, plan.rows_per_group,
+                                                         plan.ngroups, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_reduce(hipStream_t s, const long long* part, int ngroups, int active,
+                             int pass, long long* w, int64_t p0) {
+  tri_reduce_kernel<<<1, 64, 0, s>>>(part, ngroups, active, pass, w, p0);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_cv(hipStream_t s, const long long* w, int64_t m, int64_t nnz,
+                         mlct_tri_result* out) {
+  tri_cv_kernel<<<1, kCvThreads, 0, s>>>(w, m, nnz, out);
+  return hipGetLastError();
+}
+
+}  // namespace mlct

@@ -246,3 +246,14 @@ def mlct_estimate(ctx: Context, op: Op, kind: int, a: float, b: float, degrees, 
         "probe_degrees": r.probe_degrees, "max_moment_ratio": r.max_moment_ratio,
         "flags": r.flags,
     }
+
+
+def mlct_triangles(ctx: Context, op: Op, m: int, seed: int, want_w: bool = True):
+    """Triangle-count estimate over a pattern CSR operator.  Returns
+    (result dict, w int64 [m, 3] or None)."""
+    r = mlct_tri_result()
+    w = np.empty((m, 3), dtype=np.int64) if want_w else None
+    _check(ctx, lib().mlct_triangles(ctx.handle, op.handle, m, seed & ((1 << 64) - 1),
+                                     None if w is None else w.ctypes.data, C.byref(r)))
+    return {"sum_w3": r.sum_w3, "estimate": r.estimate, "estimate_cv": r.estimate_cv,
+            "a1": r.a1, "a2": r.a2}, w
