@@ -194,6 +194,9 @@ mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t d, const void* A_dev, int64_t l
 mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t rows, int64_t cols, const void* X_dev,
                          int64_t ldx, int32_t dtype, int32_t prec, mlct_op** out);
 mlct_status mlct_op_destroy(mlct_op* op);
+/* Copy the d x d matrix of a dense or Gram operator to the host as float64,
+ * row-major (out_host: d*d doubles).  EINVAL for CSR operators. */
+mlct_status mlct_op_read_dense(mlct_ctx* ctx, const mlct_op* op, double* out_host);
 
 /* ---- building blocks ---------------------------------------------------- */
 

@@ -220,6 +220,129 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
   return MLCT_OK;
 }
 
+// Matrix operand of a dense operator in the arithmetic ``prec``: the
+// caller's A when it already has that type, else a converted or bf16-split
+// copy built once and owned by the operator.
+mlct_status dense_operand(mlct_ctx* ctx, const mlct_op* cop, int prec, const void** a0,
+                          const void** a1, int64_t* lda) {
+  mlct_op* op = const_cast<mlct_op*>(cop);
+  const int64_t d = op->d;
+  *a1 = nullptr;
+  if ((prec == MLCT_FP64 && op->dtype == MLCT_DT_F64) ||
+      (prec == MLCT_FP32 && op->dtype == MLCT_DT_F32)) {
+    *a0 = op->A;
+    *lda = op->lda;
+    return MLCT_OK;
+  }
+  *lda = d;
+  if (prec == MLCT_BF16X3) {
+    if (!op->split_hi) {
+      void *hi = nullptr, *lo = nullptr;
+      if (hipMalloc(&hi, (size_t)d * d * 2) != hipSuccess || hipMalloc(&lo, (size_t)d * d * 2) != hipSuccess) {
+        (void)hipGetLastError();
+        if (hi) (void)hipFree(hi);
+        return fail(ctx, MLCT_ENOMEM, "no memory for the bf16 split of A");
+      }
+      HIPCHK(ctx, launch_dense_split(ctx->stream, op->A, op->dtype, d, op->lda, hi, lo));
+      op->split_hi = hi;
+      op->split_lo = lo;
+    }
+    *a0 = op->split_hi;
+    *a1 = op->split_lo;
+    return MLCT_OK;
+  }
+  void** slot = prec == MLCT_FP64 ? &op->a64 : &op->a32;
+  if (!*slot) {
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)d * d * (prec == MLCT_FP64 ? 8 : 4)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, MLCT_ENOMEM, "no memory for a converted copy of A");
+    }
+    HIPCHK(ctx, launch_dense_convert(ctx->stream, op->A, op->dtype, d, op->lda, p));
+    *slot = p;
+  }
+  *a0 = *slot;
+  return MLCT_OK;
+}
+
+int64_t dense_bpad(int64_t active) { return (active + 31) / 32 * 32; }
+
+// Device workspace of one probe block (taken before any launch, so that
+// growth never frees a buffer still in use).
+mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mode, int degree,
+                             int64_t block) {
+  const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
+  void* tmp;
+  if (op->kind == OP_CSR) {
+    const CsrStepPlan plan = plan_csr(op->d);
+    const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
+    CHECK(ws_get(ctx, WS_V0, (size_t)op->d * kBlockProbes * tsz, &tmp));
+    CHECK(ws_get(ctx, WS_V1, (size_t)op->d * kBlockProbes * tsz, &tmp));
+    CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * (S + 1) * sizeof(double), &tmp));
+    CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &tmp));
+    return MLCT_OK;
+  }
+  const int64_t bpad = dense_bpad(block);
+  const int64_t ntiles = (op->d + 31) / 32;  // the smallest tile: an upper bound for any block
+  const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
+  CHECK(ws_get(ctx, WS_V0, (size_t)bpad * op->d * tsz, &tmp));
+  CHECK(ws_get(ctx, WS_V1, (size_t)bpad * op->d * tsz, &tmp));
+  CHECK(ws_get(ctx, WS_PART, (size_t)2 * ntiles * bpad * (S + 1) * sizeof(double), &tmp));
+  CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * bpad * sizeof(double), &tmp));
+  return MLCT_OK;
+}
+
+mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
+                            int degree, int mode, int prec, ProbeSrc src, double* mu_rows,
+                            int64_t ldmu) {
+  const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
+  const int64_t d = op->d, bpad = dense_bpad(src.active);
+  const DenseTile t = dense_tile(prec, d, bpad);
+  const int64_t ntiles = (d + t.bn - 1) / t.bn;
+  const void *a0, *a1;
+  int64_t lda;
+  CHECK(dense_operand(ctx, op, prec, &a0, &a1, &lda));
+  CHECK(reserve_block_ws(ctx, op, prec, mode, degree, src.active));
+  const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
+  void *v0, *v1, *part, *dots;
+  CHECK(ws_get(ctx, WS_V0, (size_t)bpad * d * tsz, &v0));
+  CHECK(ws_get(ctx, WS_V1, (size_t)bpad * d * tsz, &v1));
+  CHECK(ws_get(ctx, WS_PART, (size_t)2 * ntiles * bpad * (S + 1) * sizeof(double), &part));
+  CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * bpad * sizeof(double), &dots));
+  void* buf[2] = {v0, v1};
+  double* P = static_cast<double*>(part);
+  double* D = static_cast<double*>(dots);
+  const size_t pstep = (size_t)2 * ntiles * bpad;
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_dense_probe_init(s, prec, buf[0], d, bpad, src, D));
+  const int zdirect = src.entries ? 2 : 1;
+  for (int k = 1; k <= S; ++k) {
+    const bool first = (k == 1);
+    DenseStepArgs a;
+    a.A0 = a0;
+    a.A1 = a1;
+    a.lda = lda;
+    a.d = d;
+    a.bpad = bpad;
+    a.vk = buf[(k - 1) & 1];
+    a.vm = buf[k & 1];
+    a.ca = first ? alpha : 2.0 * alpha;
+    a.cb = first ? beta : 2.0 * beta;
+    a.has_prev = !first;
+    a.zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
+    a.src = src;
+    a.part = P + pstep * (k - 1);
+    LaunchTimer tm(ctx, MLCT_KERNEL_DENSE_STEP);
+    HIPCHK(ctx, launch_dense_step(s, prec, a));
+    tm.done();
+  }
+  if (S > 0)
+    HIPCHK(ctx, launch_reduce_partials(s, P, S, 2, (int)ntiles, (int)bpad, D + 2 * bpad));
+  HIPCHK(ctx, launch_assemble_moments(s, D, S + 1, (int)bpad, src.active, mode, degree, mu_rows,
+                                      ldmu));
+  return MLCT_OK;
+}
+
 mlct_status run_block(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta, int degree,
                       int mode, int prec, ProbeSrc src, double* mu_rows, int64_t ldmu) {
   if (op->kind == OP_CSR) {
@@ -229,20 +352,21 @@ mlct_status run_block(mlct_ctx* ctx, const mlct_op* op, double alpha, double bet
       return run_block_csr<double>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
     return fail(ctx, MLCT_EUNSUPPORTED, "CSR operators support MLCT_FP32 and MLCT_FP64");
   }
-  return fail(ctx, MLCT_EUNSUPPORTED, "operator kind %d not supported yet", op->kind);
+  return run_block_dense(ctx, op, alpha, beta, degree, mode, prec, src, mu_rows, ldmu);
 }
 
 // Moments of probes [0, m) of a probe set, in blocks of kBlockProbes.
 mlct_status run_probe_set(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                           int degree, int mode, int prec, const mlct_probes* pr, double* mu_dev,
                           int64_t ldmu) {
-  for (int64_t p0 = 0; p0 < pr->m; p0 += kBlockProbes) {
+  const int64_t width = op->kind == OP_CSR ? kBlockProbes : kDenseMaxBlock;
+  for (int64_t p0 = 0; p0 < pr->m; p0 += width) {
     ProbeSrc src;
     src.seed = pr->seed;
     src.first_id = pr->first_id + p0;
     src.entries = pr->kind == MLCT_PROBE_EXPLICIT ? pr->entries_dev : nullptr;
     src.ld = pr->ld_entries;
-    src.active = (int32_t)((pr->m - p0) < kBlockProbes ? (pr->m - p0) : kBlockProbes);
+    src.active = (int32_t)((pr->m - p0) < width ? (pr->m - p0) : width);
     CHECK(run_block(ctx, op, alpha, beta, degree, mode, prec, src, mu_dev + p0 * ldmu, ldmu));
   }
   return MLCT_OK;
@@ -416,6 +540,8 @@ mlct_status mlct_moments(mlct_ctx* ctx, const mlct_op* op, double a, double b, i
   const int64_t ldmu = n + 1;
   void* mu;
   CHECK(ws_get(ctx, WS_MU, (size_t)probes->m * ldmu * sizeof(double), &mu));
+  CHECK(reserve_block_ws(ctx, op, prec, mode, n,
+                         probes->m < kDenseMaxBlock ? probes->m : kDenseMaxBlock));
   CHECK(run_probe_set(ctx, op, alpha, beta, n, mode, prec, probes, static_cast<double*>(mu), ldmu));
   HIPCHK(ctx, hipMemcpyAsync(mu_out, mu, (size_t)probes->m * ldmu * sizeof(double),
                              hipMemcpyDeviceToHost, ctx->stream));
@@ -468,14 +594,9 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   // Block workspace is taken before any launch so that growth never frees a
   // buffer in use.
   {
-    const CsrStepPlan plan = plan_csr(op->d);
-    const int S = (mode == MLCT_DOUBLING) ? (n + 1) / 2 : n;
-    const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
-    void* tmp;
-    CHECK(ws_get(ctx, WS_V0, (size_t)op->d * kBlockProbes * tsz, &tmp));
-    CHECK(ws_get(ctx, WS_V1, (size_t)op->d * kBlockProbes * tsz, &tmp));
-    CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * (S + 1) * sizeof(double), &tmp));
-    CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &tmp));
+    int64_t maxm = 0;
+    for (int k = 0; k < L; ++k) maxm = lv.m[k] > maxm ? lv.m[k] : maxm;
+    CHECK(reserve_block_ws(ctx, op, prec, mode, n, maxm < kDenseMaxBlock ? maxm : kDenseMaxBlock));
   }
   double* cd = static_cast<double*>(coef);
   double* ls = cd + (size_t)ncoef * (n + 1);
@@ -513,13 +634,88 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   return MLCT_OK;
 }
 
-mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t, const void*, int64_t, int32_t, mlct_op**) {
-  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "dense operators not built yet") : MLCT_EINVAL;
+mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t d, const void* A_dev, int64_t lda,
+                          int32_t dtype, mlct_op** out) {
+  if (!ctx || !out) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (d < 1 || d > (int64_t)1 << 20) return fail(ctx, MLCT_EINVAL, "bad dimension d=%lld", (long long)d);
+  if (!A_dev || lda < d) return fail(ctx, MLCT_EINVAL, "need a device matrix with lda >= d");
+  if (dtype != MLCT_DT_F32 && dtype != MLCT_DT_F64)
+    return fail(ctx, MLCT_EINVAL, "dense values must be float32 or float64");
+  mlct_op* op = new (std::nothrow) mlct_op();
+  if (!op) return fail(ctx, MLCT_ENOMEM, "out of host memory");
+  op->ctx = ctx;
+  op->device = ctx->device;
+  op->kind = OP_DENSE;
+  op->d = d;
+  op->A = A_dev;
+  op->lda = lda;
+  op->dtype = dtype;
+  *out = op;
+  return MLCT_OK;
 }
-mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t, int64_t, const void*, int64_t, int32_t, int32_t,
-                         mlct_op**) {
-  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "Gram operators not built yet") : MLCT_EINVAL;
+
+mlct_status mlct_op_read_dense(mlct_ctx* ctx, const mlct_op* op, double* out_host) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !out_host || op->kind == OP_CSR)
+    return fail(ctx, MLCT_EINVAL, "need a dense or Gram operator and an output array");
+  CHECK(set_device(ctx));
+  const void *a0, *a1;
+  int64_t lda;
+  CHECK(dense_operand(ctx, op, MLCT_FP64, &a0, &a1, &lda));
+  HIPCHK(ctx, hipMemcpy2DAsync(out_host, op->d * sizeof(double), a0, lda * sizeof(double),
+                               op->d * sizeof(double), op->d, hipMemcpyDeviceToHost, ctx->stream));
+  return sync_stream(ctx);
 }
+
+mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t rows, int64_t cols, const void* X_dev,
+                         int64_t ldx, int32_t dtype, int32_t prec, mlct_op** out) {
+  if (!ctx || !out) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (rows < 1 || cols < 1 || cols > (int64_t)1 << 20 || ldx < cols || !X_dev)
+    return fail(ctx, MLCT_EINVAL, "need rows, cols >= 1, ldx >= cols and a device X");
+  if (dtype != MLCT_DT_F32) return fail(ctx, MLCT_EINVAL, "X must be float32");
+  if (prec != MLCT_FP32) return fail(ctx, MLCT_EUNSUPPORTED, "the Gram matrix is formed in FP32");
+  CHECK(set_device(ctx));
+  void* G = nullptr;
+  if (hipMalloc(&G, (size_t)cols * cols * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MLCT_ENOMEM, "no memory for the %lld x %lld Gram matrix", (long long)cols,
+                (long long)cols);
+  }
+  {
+    LaunchTimer tm(ctx, MLCT_KERNEL_GRAM);
+    hipError_t e = launch_gram(ctx->stream, static_cast<const float*>(X_dev), rows, cols, ldx,
+                               static_cast<float*>(G));
+    tm.done();
+    if (e != hipSuccess) {
+      (void)hipFree(G);
+      return fail(ctx, MLCT_EDEVICE, "Gram kernel launch failed: %s", hipGetErrorString(e));
+    }
+  }
+  mlct_status st = sync_stream(ctx);
+  if (st != MLCT_OK) {
+    (void)hipFree(G);
+    return st;
+  }
+  mlct_op* op = new (std::nothrow) mlct_op();
+  if (!op) {
+    (void)hipFree(G);
+    return fail(ctx, MLCT_ENOMEM, "out of host memory");
+  }
+  op->ctx = ctx;
+  op->device = ctx->device;
+  op->kind = OP_GRAM;
+  op->d = cols;
+  op->A = G;
+  op->owned = G;
+  op->lda = cols;
+  op->dtype = MLCT_DT_F32;
+  *out = op;
+  return MLCT_OK;
+}
+
 mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op*, int32_t, uint64_t, double, double*, double*) {
   return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "Lanczos bounds not built yet") : MLCT_EINVAL;
 }

@@ -141,4 +141,34 @@ hipError_t launch_tri_reduce(hipStream_t s, const long long* part, int ngroups, 
 hipError_t launch_tri_cv(hipStream_t s, const long long* w, int64_t m, int64_t nnz,
                          mlct_tri_result* out);
 
+// ---- dense recurrence on MFMA (k_dense.hip) --------------------------------
+// Probe blocks of the dense path are probe-major (V^T, bpad x d).
+constexpr int64_t kDenseMaxBlock = 4096;
+struct DenseStepArgs {
+  const void* A0;  // matrix (FP64 / FP32) or its bf16 hi part
+  const void* A1;  // bf16 lo part (BF16X3 only)
+  int64_t lda, d, bpad;
+  const void* vk;
+  void* vm;
+  double ca, cb;
+  bool has_prev;
+  int zmode;
+  ProbeSrc src;
+  double* part;  // [2][ntiles][bpad] for this step
+};
+struct DenseTile {
+  bool large;
+  int bm, bn;
+};
+DenseTile dense_tile(int prec, int64_t d, int64_t bpad);
+hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a);
+hipError_t launch_dense_probe_init(hipStream_t s, int prec, void* v0, int64_t d, int64_t bpad,
+                                   ProbeSrc src, double* dots0);
+hipError_t launch_dense_split(hipStream_t s, const void* a, int dtype, int64_t d, int64_t lda,
+                              void* hi, void* lo);
+hipError_t launch_dense_convert(hipStream_t s, const void* a, int src_dtype, int64_t d,
+                                int64_t lda, void* out);
+hipError_t launch_gram(hipStream_t s, const float* X, int64_t rows, int64_t cols, int64_t ldx,
+                       float* G);
+
 }  // namespace mlct

@@ -1,0 +1,463 @@
+// Block Chebyshev recurrence over a dense symmetric operator on the matrix
+// cores (Section 2.2, eq. eqn:recurrence in matrix form), with the
+// per-probe moments fused into the epilogue.
+//
+// Probe blocks are kept probe-major: V^T is B x d, row j = probe j.  Because
+// A is symmetric, (A V)^T = V^T A, and the product is
+//     C[j][n] = sum_k V^T[j][k] * A[n][k],
+// so both MFMA operands are read along contiguous k (row j of V^T and row n
+// of A).  The workgroup tile is BM probes x BN matrix rows; the epilogue
+// forms  V_new^T = ca * C + cb * V_k^T  [- V_prev^T]  in place over V_prev^T
+// and the per-probe dot products (FP64, exact products of the stored
+// values), reduced over the tile's rows in a fixed order.
+//
+// Precisions (16x16 MFMA tiles):
+//   PREC 0  FP64   v_mfma_f64_16x16x4f64
+//   PREC 1  FP32   v_mfma_f32_16x16x4f32
+//   PREC 2  BF16X3 v_mfma_f32_16x16x32_bf16 three times per tile:
+//                  V_hi A_hi + V_hi A_lo + V_lo A_hi, FP32 accumulation;
+//                  A is split once (A_hi = bf16(A), A_lo = bf16(A - A_hi)),
+//                  V is split on the way into LDS.
+#include "device.hpp"
+
+namespace mlct {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+template <int PREC>
+struct Prec;
+template <>
+struct Prec<0> {
+  using V = double;   // probe-block element
+  using M = double;   // matrix element in LDS
+  using Acc = d4;
+  static constexpr int KM = 4;  // K of one MFMA
+};
+template <>
+struct Prec<1> {
+  using V = float;
+  using M = float;
+  using Acc = f4;
+  static constexpr int KM = 4;
+};
+template <>
+struct Prec<2> {
+  using V = float;
+  using M = __bf16;
+  using Acc = f4;
+  static constexpr int KM = 32;
+};
+
+// Row (within a 16x16 tile) of accumulator value r of lane l.
+template <int PREC>
+__device__ __forceinline__ int acc_row(int l, int r) {
+  return PREC == 0 ? (l >> 4) + 4 * r : (l >> 4) * 4 + r;
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <int PREC, int WM, int WN, int TM, int TN, int BK, int ZMODE, bool HAS_PREV>
+__global__ __launch_bounds__(64 * WM * WN) void dense_step_kernel(
+    const void* __restrict__ A0, const void* __restrict__ A1, int64_t lda, int64_t d,
+    const typename Prec<PREC>::V* __restrict__ vk, typename Prec<PREC>::V* __restrict__ vm,
+    typename Prec<PREC>::V ca, typename Prec<PREC>::V cb, ProbeSrc src, int mtiles, int ntiles,
+    double* __restrict__ part) {
+  using P = Prec<PREC>;
+  using VT = typename P::V;
+  using MT = typename P::M;
+  using AccT = typename P::Acc;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  constexpr int PAD = PREC == 2 ? 8 : (PREC == 1 ? 4 : 2);
+  constexpr int LK = BK + PAD;  // LDS row length in elements
+  constexpr int NSPLIT = PREC == 2 ? 2 : 1;
+
+  __shared__ MT sV[NSPLIT][BM][LK];
+  __shared__ MT sA[NSPLIT][BN][LK];
+  __shared__ double sred[WN][2][BM];
+
+  // tile of this workgroup; workgroups of one XCD share matrix row tiles
+  const int total = mtiles * ntiles;
+  const int tiles8 = (total + 7) / 8 * 8;
+  const int L = xcd_band(blockIdx.x, tiles8);
+  if (L >= total) return;
+  const int mt = L % mtiles, nt = L / mtiles;
+  const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t ldv = d;
+
+  AccT acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = AccT{};
+
+  for (int64_t k0 = 0; k0 < d; k0 += BK) {
+    // ---- global -> LDS ------------------------------------------------------
+    for (int e = tid; e < BM * BK; e += NT) {
+      const int r = e / BK, c = e % BK;
+      const int64_t k = k0 + c;
+      const VT x = k < d ? vk[(m0 + r) * ldv + k] : VT(0);
+      if (PREC == 2) {
+        __bf16 hi, lo;
+        split_bf16((float)x, hi, lo);
+        sV[0][r][c] = hi;
+        sV[NSPLIT - 1][r][c] = lo;
+      } else {
+        sV[0][r][c] = (MT)x;
+      }
+    }
+    for (int e = tid; e < BN * BK; e += NT) {
+      const int r = e / BK, c = e % BK;
+      const int64_t k = k0 + c, n = n0 + r;
+      const bool ok = k < d && n < d;
+      const int64_t off = ok ? n * lda + k : 0;
+      if (PREC == 2) {
+        sA[0][r][c] = ok ? static_cast<const __bf16*>(A0)[off] : (__bf16)0.f;
+        sA[NSPLIT - 1][r][c] = ok ? static_cast<const __bf16*>(A1)[off] : (__bf16)0.f;
+      } else {
+        sA[0][r][c] = ok ? static_cast<const MT*>(A0)[off] : MT(0);
+      }
+    }
+    __syncthreads();
+    // ---- MFMA ---------------------------------------------------------------
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += P::KM) {
+      if constexpr (PREC == 2) {
+        bf8 ah[TM], al[TM], bh[TN], bl[TN];
+        const int kc = kk + (lane >> 4) * 8;
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          const int r = wm * TM * 16 + a * 16 + (lane & 15);
+          ah[a] = *reinterpret_cast<const bf8*>(&sV[0][r][kc]);
+          al[a] = *reinterpret_cast<const bf8*>(&sV[1][r][kc]);
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int r = wn * TN * 16 + b * 16 + (lane & 15);
+          bh[b] = *reinterpret_cast<const bf8*>(&sA[0][r][kc]);
+          bl[b] = *reinterpret_cast<const bf8*>(&sA[1][r][kc]);
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      } else {
+        MT av[TM], bv[TN];
+        const int kc = kk + (lane >> 4);
+#pragma unroll
+        for (int a = 0; a < TM; ++a) av[a] = sV[0][wm * TM * 16 + a * 16 + (lane & 15)][kc];
+#pragma unroll
+        for (int b = 0; b < TN; ++b) bv[b] = sA[0][wn * TN * 16 + b * 16 + (lane & 15)][kc];
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b) {
+            if constexpr (PREC == 0)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: recurrence, in-place store, moment partials --------------
+  double p1[TM][4], p2[TM][4];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p1[a][r] = p2[a][r] = 0.0;
+#pragma unroll
+  for (int a = 0; a < TM; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = m0 + wm * TM * 16 + a * 16 + acc_row<PREC>(lane, r);
+      const bool jact = j < src.active;
+      uint64_t key = 0;
+      if (ZMODE == 1) key = sm_output(src.seed, (uint64_t)(src.first_id + j));
+      int64_t cached = -1;
+      uint64_t word = 0;
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int64_t n = n0 + wn * TN * 16 + b * 16 + (lane & 15);
+        if (n >= d) continue;
+        const int64_t idx = j * ldv + n;
+        const VT xk = vk[idx];
+        VT vn = ca * (VT)acc[a][b][r] + cb * xk;
+        if (HAS_PREV) vn -= vm[idx];
+        vm[idx] = vn;
+        if (ZMODE == 0) {
+          p1[a][r] += (double)xk * (double)vn;
+          p2[a][r] += (double)vn * (double)vn;
+        } else if (ZMODE == 1) {
+          const int64_t c = n >> 6;
+          if (c != cached) {
+            word = sm_output(key, (uint64_t)c);
+            cached = c;
+          }
+          p1[a][r] += sign_from_word<double>(word, n) * (double)vn;
+        } else {
+          const double z = jact ? (double)src.entries[n * src.ld + src.first_id + j] : 0.0;
+          p1[a][r] += z * (double)vn;
+        }
+      }
+    }
+  }
+  // reduce over the 16 lanes that hold the same probe rows (fixed order)
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        p1[a][r] += __shfl_xor(p1[a][r], o, 64);
+        p2[a][r] += __shfl_xor(p2[a][r], o, 64);
+      }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jl = wm * TM * 16 + a * 16 + acc_row<PREC>(lane, r);
+        sred[wn][0][jl] = p1[a][r];
+        sred[wn][1][jl] = p2[a][r];
+      }
+  }
+  __syncthreads();
+  for (int e = tid; e < 2 * BM; e += NT) {
+    const int slot = e / BM, jl = e % BM;
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < WN; ++w) s += sred[w][slot][jl];
+    part[((int64_t)slot * ntiles + nt) * ((int64_t)mtiles * BM) + m0 + jl] = s;
+  }
+}
+
+// V0^T[j][n] = z_n^(j) for j < active (0 for padding rows) and the moment
+// mu_0 = z.z per probe (one workgroup per probe row, fixed-order sum).
+template <typename VT>
+__global__ __launch_bounds__(256) void dense_probe_init_kernel(VT* __restrict__ v0, int64_t d,
+                                                               ProbeSrc src,
+                                                               double* __restrict__ dots0) {
+  __shared__ double sh[256];
+  const int64_t j = blockIdx.x;
+  const bool act = j < src.active;
+  const uint64_t key = sm_output(src.seed, (uint64_t)(src.first_id + j));
+  double s = 0.0;
+  for (int64_t n = threadIdx.x; n < d; n += 256) {
+    VT z = VT(0);
+    if (act) {
+      if (src.entries)
+        z = (VT)src.entries[n * src.ld + src.first_id + j];
+      else
+        z = sign_from_word<VT>(sm_output(key, (uint64_t)(n >> 6)), n);
+    }
+    v0[j * d + n] = z;
+    s += (double)z * (double)z;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dots0[j] = sh[0];
+}
+
+// A_hi = bf16(A), A_lo = bf16(A - A_hi), from FP32 or FP64 A (row-major).
+template <typename ST>
+__global__ void split_kernel(const ST* __restrict__ a, int64_t d, int64_t lda,
+                             __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+  const int64_t total = d * d;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / d, c = e % d;
+    __bf16 h, l;
+    split_bf16((float)a[r * lda + c], h, l);
+    hi[e] = h;
+    lo[e] = l;
+  }
+}
+
+template <typename ST, typename DT>
+__global__ void convert_kernel(const ST* __restrict__ a, int64_t d, int64_t lda,
+                               DT* __restrict__ out) {
+  const int64_t total = d * d;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / d, c = e % d;
+    out[e] = (DT)a[r * lda + c];
+  }
+}
+
+// Gram matrix G = X^T X (X row-major rows x cols, FP32) on FP32 MFMA.  Only
+// tiles with nt >= mt are computed; each writes G[i][j] and G[j][i] from the
+// same accumulator, so G is exactly symmetric.
+template <int WM, int WN, int TM, int TN, int BK>
+__global__ __launch_bounds__(64 * WM * WN) void gram_kernel(const float* __restrict__ X,
+                                                            int64_t rows, int64_t cols,
+                                                            int64_t ldx, float* __restrict__ G,
+                                                            int tiles) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  static_assert(BM == BN, "square tiles");
+  __shared__ float sX[2][BK][BM + 4];
+  // upper-triangular tile pair (mt <= nt) from the linear index
+  int L = blockIdx.x, mt = 0;
+  while (L >= tiles - mt) {
+    L -= tiles - mt;
+    ++mt;
+  }
+  const int nt = mt + L;
+  const int64_t i0 = (int64_t)mt * BM, j0 = (int64_t)nt * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4{};
+  for (int64_t r0 = 0; r0 < rows; r0 += BK) {
+    for (int e = tid; e < BK * BM; e += NT) {
+      const int k = e / BM, c = e % BM;
+      const int64_t r = r0 + k;
+      sX[0][k][c] = (r < rows && i0 + c < cols) ? X[r * ldx + i0 + c] : 0.f;
+      sX[1][k][c] = (r < rows && j0 + c < cols) ? X[r * ldx + j0 + c] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      float av[TM], bv[TN];
+      const int k = kk + (lane >> 4);
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = sX[0][k][wm * TM * 16 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = sX[1][k][wn * TN * 16 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wm * TM * 16 + a * 16 + (lane >> 4) * 4 + r;
+        const int64_t j = j0 + wn * TN * 16 + b * 16 + (lane & 15);
+        if (i < cols && j < cols) {
+          G[i * cols + j] = acc[a][b][r];
+          G[j * cols + i] = acc[a][b][r];
+        }
+      }
+}
+
+template <int PREC, int WM, int WN, int TM, int TN, int BK>
+hipError_t launch_dense_cfg(hipStream_t s, const DenseStepArgs& a) {
+  using VT = typename Prec<PREC>::V;
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  const int mtiles = (int)(a.bpad / BM);
+  const int ntiles = (int)((a.d + BN - 1) / BN);
+  const int grid = (mtiles * ntiles + 7) / 8 * 8;
+  const VT ca = (VT)a.ca, cb = (VT)a.cb;
+  const VT* vk = static_cast<const VT*>(a.vk);
+  VT* vm = static_cast<VT*>(a.vm);
+#define MLCT_DENSE_LAUNCH(Z, HP)                                                           \
+  dense_step_kernel<PREC, WM, WN, TM, TN, BK, Z, HP><<<grid, 64 * WM * WN, 0, s>>>(        \
+      a.A0, a.A1, a.lda, a.d, vk, vm, ca, cb, a.src, mtiles, ntiles, a.part)
+  if (a.has_prev) {
+    if (a.zmode == 0) MLCT_DENSE_LAUNCH(0, true);
+    else if (a.zmode == 1) MLCT_DENSE_LAUNCH(1, true);
+    else MLCT_DENSE_LAUNCH(2, true);
+  } else {
+    if (a.zmode == 0) MLCT_DENSE_LAUNCH(0, false);
+    else if (a.zmode == 1) MLCT_DENSE_LAUNCH(1, false);
+    else MLCT_DENSE_LAUNCH(2, false);
+  }
+#undef MLCT_DENSE_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace
+
+DenseTile dense_tile(int prec, int64_t d, int64_t bpad) {
+  // Large tiles (128 x 128) once they still give a few hundred workgroups,
+  // else 32 x 32 tiles (small d is latency-bound; more workgroups win).
+  const int64_t big = (bpad / 128) * ((d + 127) / 128);
+  DenseTile t;
+  t.large = (bpad % 128 == 0) && big >= 256;
+  t.bm = t.large ? 128 : 32;
+  t.bn = t.large ? 128 : 32;
+  (void)prec;
+  return t;
+}
+
+hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a) {
+  const DenseTile t = dense_tile(prec, a.d, a.bpad);
+  if (prec == MLCT_FP64)
+    return t.large ? launch_dense_cfg<0, 2, 2, 4, 4, 16>(s, a) : launch_dense_cfg<0, 1, 1, 2, 2, 16>(s, a);
+  if (prec == MLCT_FP32)
+    return t.large ? launch_dense_cfg<1, 2, 2, 4, 4, 16>(s, a) : launch_dense_cfg<1, 1, 1, 2, 2, 16>(s, a);
+  return t.large ? launch_dense_cfg<2, 2, 2, 4, 4, 64>(s, a) : launch_dense_cfg<2, 1, 1, 2, 2, 32>(s, a);
+}
+
+hipError_t launch_dense_probe_init(hipStream_t s, int prec, void* v0, int64_t d, int64_t bpad,
+                                   ProbeSrc src, double* dots0) {
+  if (prec == MLCT_FP64)
+    dense_probe_init_kernel<double><<<(int)bpad, 256, 0, s>>>(static_cast<double*>(v0), d, src, dots0);
+  else
+    dense_probe_init_kernel<float><<<(int)bpad, 256, 0, s>>>(static_cast<float*>(v0), d, src, dots0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_split(hipStream_t s, const void* a, int dtype, int64_t d, int64_t lda,
+                              void* hi, void* lo) {
+  if (dtype == MLCT_DT_F64)
+    split_kernel<double><<<2048, 256, 0, s>>>(static_cast<const double*>(a), d, lda,
+                                               static_cast<__bf16*>(hi), static_cast<__bf16*>(lo));
+  else
+    split_kernel<float><<<2048, 256, 0, s>>>(static_cast<const float*>(a), d, lda,
+                                              static_cast<__bf16*>(hi), static_cast<__bf16*>(lo));
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_convert(hipStream_t s, const void* a, int src_dtype, int64_t d,
+                                int64_t lda, void* out) {
+  if (src_dtype == MLCT_DT_F64)
+    convert_kernel<double, float><<<2048, 256, 0, s>>>(static_cast<const double*>(a), d, lda,
+                                                       static_cast<float*>(out));
+  else
+    convert_kernel<float, double><<<2048, 256, 0, s>>>(static_cast<const float*>(a), d, lda,
+                                                       static_cast<double*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(hipStream_t s, const float* X, int64_t rows, int64_t cols, int64_t ldx,
+                       float* G) {
+  constexpr int T = 128;
+  const int tiles = (int)((cols + T - 1) / T);
+  const int grid = tiles * (tiles + 1) / 2;
+  gram_kernel<2, 2, 4, 4, 16><<<grid, 256, 0, s>>>(X, rows, cols, ldx, G, tiles);
+  return hipGetLastError();
+}
+
+}  // namespace mlct

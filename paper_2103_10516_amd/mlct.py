@@ -88,6 +88,7 @@ def lib() -> C.CDLL:
             "mlct_op_dense": [P, I64, P, I64, I32, C.POINTER(P)],
             "mlct_op_gram": [P, I64, I64, P, I64, I32, I32, C.POINTER(P)],
             "mlct_op_destroy": [P],
+            "mlct_op_read_dense": [P, P, P],
             "mlct_cheb_coeffs": [P, mlct_func, D, D, I32, P, C.POINTER(D)],
             "mlct_moments": [P, P, D, D, I32, C.POINTER(mlct_probes), I32, I32, P],
             "mlct_bounds": [P, P, I32, U64, D, C.POINTER(D), C.POINTER(D)],
@@ -257,3 +258,29 @@ def mlct_triangles(ctx: Context, op: Op, m: int, seed: int, want_w: bool = True)
                                      None if w is None else w.ctypes.data, C.byref(r)))
     return {"sum_w3": r.sum_w3, "estimate": r.estimate, "estimate_cv": r.estimate_cv,
             "a1": r.a1, "a2": r.a2}, w
+
+
+def mlct_op_dense(ctx: Context, A) -> Op:
+    """Dense symmetric A: device tensor [d, lda >= d] float32 or float64."""
+    import torch
+
+    d = A.shape[0]
+    dt = MLCT_DT_F64 if A.dtype == torch.float64 else MLCT_DT_F32
+    h = C.c_void_p()
+    _check(ctx, lib().mlct_op_dense(ctx.handle, d, _ptr(A), A.stride(0), dt, C.byref(h)))
+    return Op(ctx, h, (A,), d)
+
+
+def mlct_op_gram(ctx: Context, X, prec: int = MLCT_FP32) -> Op:
+    """A = X^T X for a device float32 tensor X [rows, cols] (formed on the device)."""
+    rows, cols = X.shape
+    h = C.c_void_p()
+    _check(ctx, lib().mlct_op_gram(ctx.handle, rows, cols, _ptr(X), X.stride(0), MLCT_DT_F32,
+                                   prec, C.byref(h)))
+    return Op(ctx, h, (X,), cols)
+
+
+def mlct_op_read_dense(ctx: Context, op: Op) -> np.ndarray:
+    out = np.empty((op.d, op.d), dtype=np.float64)
+    _check(ctx, lib().mlct_op_read_dense(ctx.handle, op.handle, out.ctypes.data))
+    return out
