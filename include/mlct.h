@@ -131,6 +131,7 @@ typedef struct {
   int64_t matvecs;                    /* probe-matvecs applied            */
   int64_t probe_degrees;              /* sum_k m_k * l_k                  */
   double max_moment_ratio;            /* max_j |mu_j| / mu_0 over probes  */
+  double interval_a, interval_b;      /* the [a, b] the estimate used     */
   uint32_t flags;                     /* MLCT_FLAG_* bits                 */
 } mlct_result;
 
@@ -219,6 +220,14 @@ mlct_status mlct_moments(mlct_ctx* ctx, const mlct_op* op, double a, double b, i
  * widened by their residual bounds and by rel_margin * (width). */
 mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64_t seed,
                         double rel_margin, double* a_out, double* b_out);
+/* The Lanczos tridiagonal behind mlct_bounds: alpha_out[0..k-1],
+ * beta_out[0..k-1] (beta_out[k-1] = residual norm after the last step), the
+ * number of steps k actually taken (fewer than ``steps`` after a breakdown),
+ * and info_out[0..5] = theta_min, theta_max, r_min, r_max, a, b.  Any output
+ * pointer may be NULL.  1 <= steps <= 128. */
+mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64_t seed,
+                         double rel_margin, double* alpha_out, double* beta_out,
+                         int32_t* k_out, double* info_out);
 
 /* ---- estimators ---------------------------------------------------------- */
 
@@ -226,7 +235,9 @@ mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64_
  * k uses Rademacher probe ids [off_k, off_k + m_k), off_k = sum_{k'<k} m_k',
  * so all samples are independent; Q uses the coefficients of the single
  * degree-n interpolant (eq. def:qlevels) unless MLCT_LEVEL_INTERP is set.
- * Returns MLCT_ESPECTRUM if some |mu_j| exceeds |z|^2 (1 + 1e-3). */
+ * Returns MLCT_ESPECTRUM if some |mu_j| exceeds |z|^2 (1 + 1e-3).
+ * If a and b are both NaN the interval is found first by mlct_bounds with
+ * min(64, d) steps, margin 0.01 and seed (seed + 0x9E3779B97F4A7C15). */
 mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
                           const mlct_levels* levels, uint64_t seed, int32_t prec,
                           int32_t mode, mlct_result* out);

@@ -558,6 +558,10 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   const int interp = (mode & MLCT_LEVEL_INTERP) ? 1 : 0;
   mode &= ~MLCT_LEVEL_INTERP;
   CHECK(check_mode_prec(ctx, mode, prec));
+  if (std::isnan(a) && std::isnan(b)) {
+    const int steps = op->d < 64 ? (int)op->d : 64;
+    CHECK(mlct_bounds(ctx, op, steps, seed + kGamma, 0.01, &a, &b));
+  }
   CHECK(check_func(ctx, f, a, b));
   const int L = levels->L;
   if (L < 1 || L > MLCT_MAX_LEVELS || !levels->degree || !levels->m)
@@ -629,6 +633,8 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
                 h.max_moment_ratio, a, b);
   h.matvecs = mv;
   h.probe_degrees = pd;
+  h.interval_a = a;
+  h.interval_b = b;
   if (prec == MLCT_BF16X3) h.flags |= MLCT_FLAG_BF16;
   *out = h;
   return MLCT_OK;
@@ -716,9 +722,68 @@ mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t rows, int64_t cols, const void* 
   return MLCT_OK;
 }
 
-mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op*, int32_t, uint64_t, double, double*, double*) {
-  return ctx ? fail(ctx, MLCT_EUNSUPPORTED, "Lanczos bounds not built yet") : MLCT_EINVAL;
+mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64_t seed,
+                         double rel_margin, double* alpha_out, double* beta_out,
+                         int32_t* k_out, double* info_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op) return fail(ctx, MLCT_EINVAL, "op is required");
+  if (steps < 1 || steps > kLanczosMaxSteps)
+    return fail(ctx, MLCT_EINVAL, "steps must be in [1, %d]", kLanczosMaxSteps);
+  if (!(rel_margin >= 0.0) || !std::isfinite(rel_margin))
+    return fail(ctx, MLCT_EINVAL, "rel_margin must be finite and >= 0");
+  CHECK(set_device(ctx));
+  const int64_t d = op->d;
+  const void* a64 = nullptr;
+  const void* unused;
+  int64_t lda = 0;
+  if (op->kind != OP_CSR) CHECK(dense_operand(ctx, op, MLCT_FP64, &a64, &unused, &lda));
+  const int64_t nb = (d + 255) / 256 < 1024 ? (d + 255) / 256 : 1024;
+  void *q, *misc;
+  CHECK(ws_get(ctx, WS_LANCZOS, (size_t)(steps + 2) * d * sizeof(double), &q));
+  const size_t misc_bytes = sizeof(LanczosState) + (size_t)(kLanczosMaxSteps + 1) * nb * 8 +
+                            (kLanczosMaxSteps + 1) * 8 + 64 * 8;
+  CHECK(ws_get(ctx, WS_DENSE, misc_bytes, &misc));
+  double* Q = static_cast<double*>(q);
+  double* w = Q + (size_t)(steps + 1) * d;
+  LanczosState* st = static_cast<LanczosState*>(misc);
+  double* part = reinterpret_cast<double*>(st + 1);
+  double* h = part + (size_t)(kLanczosMaxSteps + 1) * nb;
+  double* out = h + kLanczosMaxSteps + 1;
+  HIPCHK(ctx, launch_lanczos(ctx->stream, op, a64, lda, steps, seed, rel_margin, Q, w, h, part,
+                             st, out));
+  LanczosState hs;
+  double ho[8];
+  HIPCHK(ctx, hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(ho, out, sizeof ho, hipMemcpyDeviceToHost, ctx->stream));
+  CHECK(sync_stream(ctx));
+  if (!(std::isfinite(ho[0]) && std::isfinite(ho[1])))
+    return fail(ctx, MLCT_ERANGE, "Lanczos produced a non-finite interval");
+  if (alpha_out) std::memcpy(alpha_out, hs.alpha, hs.k * sizeof(double));
+  if (beta_out) std::memcpy(beta_out, hs.beta, hs.k * sizeof(double));
+  if (k_out) *k_out = hs.k;
+  if (info_out) {
+    info_out[0] = ho[2];
+    info_out[1] = ho[3];
+    info_out[2] = ho[4];
+    info_out[3] = ho[5];
+    info_out[4] = ho[0];
+    info_out[5] = ho[1];
+  }
+  return MLCT_OK;
 }
+
+mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64_t seed,
+                        double rel_margin, double* a_out, double* b_out) {
+  if (!ctx) return MLCT_EINVAL;
+  if (!a_out || !b_out) return fail(ctx, MLCT_EINVAL, "a_out and b_out are required");
+  double info[6];
+  CHECK(mlct_lanczos(ctx, op, steps, seed, rel_margin, nullptr, nullptr, nullptr, info));
+  *a_out = info[4];
+  *b_out = info[5];
+  return MLCT_OK;
+}
+
 mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t seed,
                            int64_t* w_out, mlct_tri_result* out) {
   if (!ctx) return MLCT_EINVAL;

@@ -171,4 +171,18 @@ hipError_t launch_dense_convert(hipStream_t s, const void* a, int src_dtype, int
 hipError_t launch_gram(hipStream_t s, const float* X, int64_t rows, int64_t cols, int64_t ldx,
                        float* G);
 
+// ---- Lanczos spectral interval (k_lanczos.hip) -----------------------------
+constexpr int kLanczosMaxSteps = 128;
+struct LanczosState {
+  double alpha[kLanczosMaxSteps];
+  double beta[kLanczosMaxSteps];
+  double work[3 * kLanczosMaxSteps];
+  int k;        // steps completed
+  int stopped;  // breakdown reached
+};
+// out[0..6] = a, b, theta_min, theta_max, r_min, r_max, k
+hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int64_t lda,
+                          int steps, uint64_t seed, double margin, double* Q, double* w,
+                          double* h, double* part, LanczosState* st, double* out);
+
 }  // namespace mlct

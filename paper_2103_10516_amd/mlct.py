@@ -53,7 +53,8 @@ class mlct_result(C.Structure):
                 ("level_mean", C.c_double * MLCT_MAX_LEVELS),
                 ("level_var", C.c_double * MLCT_MAX_LEVELS),
                 ("matvecs", C.c_int64), ("probe_degrees", C.c_int64),
-                ("max_moment_ratio", C.c_double), ("flags", C.c_uint32)]
+                ("max_moment_ratio", C.c_double), ("interval_a", C.c_double),
+                ("interval_b", C.c_double), ("flags", C.c_uint32)]
 
 
 class mlct_tri_result(C.Structure):
@@ -92,6 +93,7 @@ def lib() -> C.CDLL:
             "mlct_cheb_coeffs": [P, mlct_func, D, D, I32, P, C.POINTER(D)],
             "mlct_moments": [P, P, D, D, I32, C.POINTER(mlct_probes), I32, I32, P],
             "mlct_bounds": [P, P, I32, U64, D, C.POINTER(D), C.POINTER(D)],
+            "mlct_lanczos": [P, P, I32, U64, D, P, P, C.POINTER(I32), P],
             "mlct_estimate": [P, P, mlct_func, D, D, C.POINTER(mlct_levels), U64, I32, I32,
                               C.POINTER(mlct_result)],
             "mlct_triangles": [P, P, I64, U64, P, C.POINTER(mlct_tri_result)],
@@ -245,7 +247,7 @@ def mlct_estimate(ctx: Context, op: Op, kind: int, a: float, b: float, degrees, 
         "est_var": r.est_var, "level_mean": np.array(r.level_mean[:L]),
         "level_var": np.array(r.level_var[:L]), "matvecs": r.matvecs,
         "probe_degrees": r.probe_degrees, "max_moment_ratio": r.max_moment_ratio,
-        "flags": r.flags,
+        "interval": (r.interval_a, r.interval_b), "flags": r.flags,
     }
 
 
@@ -284,3 +286,24 @@ def mlct_op_read_dense(ctx: Context, op: Op) -> np.ndarray:
     out = np.empty((op.d, op.d), dtype=np.float64)
     _check(ctx, lib().mlct_op_read_dense(ctx.handle, op.handle, out.ctypes.data))
     return out
+
+
+def mlct_bounds(ctx: Context, op: Op, steps: int = 64, seed: int = 0, rel_margin: float = 0.01):
+    a, b = C.c_double(), C.c_double()
+    _check(ctx, lib().mlct_bounds(ctx.handle, op.handle, steps, seed & ((1 << 64) - 1),
+                                  rel_margin, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def mlct_lanczos(ctx: Context, op: Op, steps: int = 64, seed: int = 0, rel_margin: float = 0.01):
+    """(alpha[k], beta[k], info dict) of the Lanczos run behind mlct_bounds."""
+    al = np.zeros(steps)
+    be = np.zeros(steps)
+    k = C.c_int32()
+    info = np.zeros(6)
+    _check(ctx, lib().mlct_lanczos(ctx.handle, op.handle, steps, seed & ((1 << 64) - 1),
+                                   rel_margin, al.ctypes.data, be.ctypes.data, C.byref(k),
+                                   info.ctypes.data))
+    n = k.value
+    return al[:n], be[:n], {"theta_min": info[0], "theta_max": info[1], "r_min": info[2],
+                            "r_max": info[3], "a": info[4], "b": info[5]}
