@@ -72,10 +72,10 @@ def laplace2d_workload(n: int = 2048):
 
 def cpu_baseline(g, a, b, seed):
     """The FP64 oracle on a bounded sample of the same workload: one level of
-    16 probes to degree 24 (direct form, 24 matvecs), whole oracle path."""
+    16 probes to degree 64 (direct form, 64 matvecs), whole oracle path."""
     from oracle import cheb, estimator
 
-    m, deg = 16, 24
+    m, deg = 16, 64
     A = g.to_scipy()
     t0 = time.perf_counter()
     estimator.estimate(A, g.d, cheb.LOG, a, b, [deg], [m], seed)

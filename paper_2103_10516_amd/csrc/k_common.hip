@@ -74,19 +74,32 @@ __global__ void csr_validate_kernel(const int32_t* __restrict__ rowptr,
   if (longest) atomicMax(&flags[1], longest);
 }
 
-// dots[s][slot][p] = sum_{g = 0..ngroups-1} part[s][slot][g][p], summed in
-// increasing g (fixed order, so results are bitwise reproducible).
-__global__ void reduce_partials_kernel(const double* __restrict__ part, int steps, int nslots,
-                                       int ngroups, int width, double* __restrict__ dots) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)steps * nslots * width;
-  if (tid >= total) return;
-  const int64_t p = tid % width;
-  const int64_t row = tid / width;  // = s * nslots + slot
-  const double* src = part + row * ngroups * width + p;
-  double acc = 0.0;
-  for (int g = 0; g < ngroups; ++g) acc += src[(int64_t)g * width];
-  dots[tid] = acc;
+// dots[s][slot][p] = sum_{g = 0..ngroups-1} part[s][slot][g][p].  One
+// workgroup per (s, slot) row and chunk of 64 probes; wave w sums the
+// groups g = w, w + 4, w + 8, ... with four interleaved accumulators, and
+// the partial sums are combined in a fixed order, so the result does not
+// depend on timing.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ part,
+                                                              int ngroups, int width,
+                                                              double* __restrict__ dots) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row = blockIdx.x;
+  const int p = blockIdx.y * 64 + lane;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (p < width) {
+    const double* src = part + row * ngroups * width + p;
+    int g = wave;
+    for (; g + 12 < ngroups; g += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += src[(int64_t)(g + 4 * u) * width];
+    }
+    for (; g < ngroups; g += 4) acc[0] += src[(int64_t)g * width];
+  }
+  sh[wave][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (wave == 0 && p < width)
+    dots[row * width + p] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
 // Moment table rows from the per-step dot products.
@@ -243,9 +256,8 @@ hipError_t launch_csr_validate(hipStream_t s, const int32_t* rowptr, const int32
 
 hipError_t launch_reduce_partials(hipStream_t s, const double* part, int steps, int nslots,
                                   int ngroups, int width, double* dots) {
-  const int64_t total = (int64_t)steps * nslots * width;
-  reduce_partials_kernel<<<(int)((total + 255) / 256), 256, 0, s>>>(part, steps, nslots,
-                                                                   ngroups, width, dots);
+  const dim3 grid(steps * nslots, (width + 63) / 64);
+  reduce_partials_kernel<<<grid, 256, 0, s>>>(part, ngroups, width, dots);
   return hipGetLastError();
 }
 

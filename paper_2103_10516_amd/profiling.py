@@ -1,0 +1,100 @@
+"""Summaries of rocprofv3 output for the roofline figures.
+
+    python -m paper_2103_10516_amd.profiling stats  <kernel_stats.csv> <out.txt> <command...>
+    python -m paper_2103_10516_amd.profiling traffic <fetch.csv> <write.csv> <kernel-substring>
+                                             <workload> <out.json> <out.txt> <command...>
+
+``traffic`` turns two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+dispatch) into HBM bytes per launch of one kernel.  Each counter is scaled
+by what it reads for a plain device copy of known size run in the same
+process (``bench.py --copy-calibration``: three copies of 1 GiB each), so
+the figure is in true bytes even where a counter under-reports.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_csr.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2103_10516_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats_summary(path: str, command: str, top: int = 12) -> str:
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+           f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>7}  kernel"]
+    for r in rows[:top]:
+        out.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+                   f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                   f"{float(r['Percentage']):7.2f}  {r['Name'][:110]}")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(path: str, substr: str):
+    vals, copies = [], []
+    for r in csv.DictReader(open(path)):
+        v = float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+        name = r["Kernel_Name"]
+        if substr in name:
+            vals.append(v)
+        if "copyBuffer" in name and int(r["Grid_Size"]) >= 65536:
+            copies.append(v)
+    return vals, copies
+
+
+def traffic(fetch_csv: str, write_csv: str, substr: str):
+    f, fc = _per_kernel(fetch_csv, substr)
+    w, wc = _per_kernel(write_csv, substr)
+    if not f or not w or not fc or not wc:
+        raise SystemExit("missing kernel or copy-calibration dispatches in the counter files")
+    f_scale = COPY_BYTES / statistics.median(fc)
+    w_scale = COPY_BYTES / statistics.median(wc)
+    fetch = statistics.mean(f) * f_scale
+    write = statistics.mean(w) * w_scale
+    return {"fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+            "hbm_bytes_per_launch": fetch + write, "launches": len(f),
+            "fetch_scale": f_scale, "write_scale": w_scale,
+            "copy_fetch_raw_bytes": statistics.median(fc),
+            "copy_write_raw_bytes": statistics.median(wc)}
+
+
+def main(argv):
+    if argv[0] == "stats":
+        with open(argv[2], "w") as fh:
+            fh.write(stats_summary(argv[1], " ".join(argv[3:])))
+        return
+    if argv[0] == "traffic":
+        fetch_csv, write_csv, substr, workload, out_json, out_txt = argv[1:7]
+        cmd = " ".join(argv[7:])
+        t = traffic(fetch_csv, write_csv, substr)
+        t.update({"kernel": substr, "workload": workload,
+                  "kernel_source_hash": kernel_source_hash(), "command": cmd})
+        with open(out_json, "w") as fh:
+            json.dump(t, fh, indent=1)
+        with open(out_txt, "w") as fh:
+            fh.write(f"# HBM traffic of {substr} ({workload})\n# command: {cmd}\n"
+                     f"# counters: FETCH_SIZE and WRITE_SIZE in separate --pmc runs; each scaled\n"
+                     f"# by its reading for a 1 GiB device copy in the same run\n\n")
+            for k in ("launches", "copy_fetch_raw_bytes", "copy_write_raw_bytes", "fetch_scale",
+                      "write_scale", "fetch_bytes_per_launch", "write_bytes_per_launch",
+                      "hbm_bytes_per_launch"):
+                fh.write(f"{k:28s} {t[k]:.6g}\n")
+        return
+    raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
