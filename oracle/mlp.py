@@ -1,0 +1,132 @@
+"""Learned control-variate level: a small MLP g that predicts the fine-level
+quadratic form z^T p_n(A_hat) z from the cheap moments mu_0..mu_c of the same
+probe (a project addition, not in the paper; it is the control-variate idea
+of Section 5.5 with a learned instead of a linear map, used as one more
+multilevel term in the sense of Section 2.3).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).  FP64 throughout.
+
+Network: x in R^{F} -> h1 = tanh(W1 x + b1) (H) -> h2 = tanh(W2 h1 + b2) (H)
+-> out = w3 . h2 + b3.  Loss over a batch of N samples:
+L = (1/N) sum_i (out_i - y_i)^2.  Gradients are derived by hand
+(tanh' = 1 - tanh^2).  Optimiser: Adam (Kingma & Ba 2015) with bias
+correction.
+
+Estimator (unbiased for any fixed g): with disjoint probe sets S0 (cheap
+degree, M0 probes) and S1 (fine degree, M1 probes), both disjoint from the
+pilot that trained g,
+    Gamma = (1/M0) sum_{S0} g(x) + (1/M1) sum_{S1} (q - g(x)),
+    Var   = s0^2 / M0 + s1^2 / M1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Params:
+    W1: np.ndarray  # [H, F]
+    b1: np.ndarray  # [H]
+    W2: np.ndarray  # [H, H]
+    b2: np.ndarray  # [H]
+    w3: np.ndarray  # [H]
+    b3: float
+
+    def flat(self) -> np.ndarray:
+        return np.concatenate([self.W1.ravel(), self.b1, self.W2.ravel(), self.b2, self.w3,
+                               [self.b3]])
+
+    @staticmethod
+    def from_flat(v: np.ndarray, F: int, H: int) -> "Params":
+        v = np.asarray(v, dtype=np.float64)
+        o = 0
+        W1 = v[o:o + H * F].reshape(H, F); o += H * F
+        b1 = v[o:o + H]; o += H
+        W2 = v[o:o + H * H].reshape(H, H); o += H * H
+        b2 = v[o:o + H]; o += H
+        w3 = v[o:o + H]; o += H
+        return Params(W1.copy(), b1.copy(), W2.copy(), b2.copy(), w3.copy(), float(v[o]))
+
+
+def n_params(F: int, H: int) -> int:
+    return H * F + H + H * H + H + H + 1
+
+
+def glorot_init(F: int, H: int, rng: np.random.Generator) -> Params:
+    """Glorot-uniform weights, zero biases."""
+    def u(fan_in, fan_out, shape):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-lim, lim, size=shape)
+    return Params(u(F, H, (H, F)), np.zeros(H), u(H, H, (H, H)), np.zeros(H),
+                  u(H, 1, (H,)), 0.0)
+
+
+def forward(p: Params, X: np.ndarray):
+    """Outputs [N] and the cached activations."""
+    h1 = np.tanh(X @ p.W1.T + p.b1)
+    h2 = np.tanh(h1 @ p.W2.T + p.b2)
+    out = h2 @ p.w3 + p.b3
+    return out, (h1, h2)
+
+
+def loss_and_grad(p: Params, X: np.ndarray, y: np.ndarray):
+    """Mean squared error and its gradient (same layout as Params.flat)."""
+    N = X.shape[0]
+    out, (h1, h2) = forward(p, X)
+    r = out - y
+    L = float(np.mean(r ** 2))
+    g_out = 2.0 * r / N                          # dL/dout  [N]
+    g_w3 = h2.T @ g_out                          # [H]
+    g_b3 = float(np.sum(g_out))
+    g_h2 = np.outer(g_out, p.w3)                 # [N, H]
+    g_a2 = g_h2 * (1.0 - h2 ** 2)                # through tanh
+    g_W2 = g_a2.T @ h1                           # [H, H]
+    g_b2 = np.sum(g_a2, axis=0)
+    g_h1 = g_a2 @ p.W2                           # [N, H]
+    g_a1 = g_h1 * (1.0 - h1 ** 2)
+    g_W1 = g_a1.T @ X                            # [H, F]
+    g_b1 = np.sum(g_a1, axis=0)
+    grad = Params(g_W1, g_b1, g_W2, g_b2, g_w3, g_b3)
+    return L, grad.flat()
+
+
+@dataclasses.dataclass
+class AdamState:
+    m: np.ndarray
+    v: np.ndarray
+    t: int = 0
+
+
+def adam_step(theta: np.ndarray, grad: np.ndarray, st: AdamState, lr=1e-3, b1=0.9,
+              b2=0.999, eps=1e-8) -> np.ndarray:
+    st.t += 1
+    st.m = b1 * st.m + (1 - b1) * grad
+    st.v = b2 * st.v + (1 - b2) * grad ** 2
+    mhat = st.m / (1 - b1 ** st.t)
+    vhat = st.v / (1 - b2 ** st.t)
+    return theta - lr * mhat / (np.sqrt(vhat) + eps)
+
+
+def train(p: Params, X: np.ndarray, y: np.ndarray, epochs: int, lr: float = 1e-3):
+    """Full-batch Adam; returns trained params and the loss history."""
+    F, H = X.shape[1], p.b1.size
+    theta = p.flat()
+    st = AdamState(np.zeros_like(theta), np.zeros_like(theta))
+    hist = []
+    for _ in range(epochs):
+        L, g = loss_and_grad(Params.from_flat(theta, F, H), X, y)
+        hist.append(L)
+        theta = adam_step(theta, g, st, lr)
+    return Params.from_flat(theta, F, H), hist
+
+
+def learned_estimate(g_s0: np.ndarray, q_s1: np.ndarray, g_s1: np.ndarray):
+    """(Gamma, Var) of the two-term estimator from per-probe values."""
+    M0, M1 = len(g_s0), len(q_s1)
+    d1 = q_s1 - g_s1
+    val = float(np.mean(g_s0) + np.mean(d1))
+    var = float(np.var(g_s0, ddof=1) / M0 + np.var(d1, ddof=1) / M1)
+    return val, var

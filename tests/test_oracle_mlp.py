@@ -1,0 +1,94 @@
+"""Pins of the oracle's MLP (hand-derived gradients, Adam) and of the
+learned-level estimator's unbiasedness."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cheb, mlp, moments, probes
+from paper_2103_10516_amd import workloads as wl
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(0)
+    F, H, N = 9, 16, 40
+    p = mlp.glorot_init(F, H, rng)
+    p.b1 = rng.normal(0, 0.1, H)
+    p.b2 = rng.normal(0, 0.1, H)
+    p.b3 = 0.3
+    X = rng.normal(0, 1, (N, F))
+    y = rng.normal(0, 1, N)
+    L, g = mlp.loss_and_grad(p, X, y)
+    theta = p.flat()
+    h = 1e-6
+    for idx in rng.choice(theta.size, 60, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[idx] += h
+        tm[idx] -= h
+        Lp, _ = mlp.loss_and_grad(mlp.Params.from_flat(tp, F, H), X, y)
+        Lm, _ = mlp.loss_and_grad(mlp.Params.from_flat(tm, F, H), X, y)
+        fd = (Lp - Lm) / (2 * h)
+        assert g[idx] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_flat_roundtrip_and_count():
+    rng = np.random.default_rng(1)
+    p = mlp.glorot_init(9, 64, rng)
+    assert p.flat().size == mlp.n_params(9, 64) == 9 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+    q = mlp.Params.from_flat(p.flat(), 9, 64)
+    np.testing.assert_array_equal(q.flat(), p.flat())
+
+
+def test_adam_first_steps_closed_form():
+    # first step: m = (1-b1) g, v = (1-b2) g^2, bias-corrected to g and g^2,
+    # so the update is lr * g / (|g| + eps)
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 0.0])
+    st = mlp.AdamState(np.zeros(3), np.zeros(3))
+    t1 = mlp.adam_step(theta, g, st, lr=0.01)
+    np.testing.assert_allclose(t1, theta - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    # second step with the same gradient: m_hat = g, v_hat = g^2 again
+    t2 = mlp.adam_step(t1, g, st, lr=0.01)
+    np.testing.assert_allclose(t2, t1 - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, (256, 9))
+    y = np.tanh(X @ rng.normal(0, 1, 9)) + 0.5 * X[:, 1] ** 2
+    p = mlp.glorot_init(9, 32, rng)
+    _, hist = mlp.train(p, X, y, 400, lr=1e-2)
+    assert hist[-1] < 0.05 * hist[0]
+
+
+def test_learned_estimator_unbiased_with_any_fixed_g():
+    d = 24
+    A, lam = wl.random_symmetric(d, 4, 0.5, 4.0)
+    a, b, n, nc = 0.4, 4.2, 24, 4
+    c, _ = cheb.coefficients(cheb.LOG, a, b, n)
+    alpha, beta = cheb.affine_map(a, b)
+    truth = cheb.trace_poly(c, lam, a, b)
+    rng = np.random.default_rng(3)
+    g_net = mlp.glorot_init(nc + 1, 8, rng)  # an arbitrary (untrained) g
+
+    def g_of(mu):
+        return mlp.forward(g_net, mu[:, : nc + 1] / d)[0] * d
+
+    vals = []
+    for r in range(60):
+        Z0 = probes.rademacher(d, np.arange(0, 40) + 1000 * r, 11).T
+        Z1 = probes.rademacher(d, np.arange(40, 60) + 1000 * r, 11).T
+        mu0 = moments.moments_direct(A, Z0, alpha, beta, nc)
+        mu1 = moments.moments_direct(A, Z1, alpha, beta, n)
+        v, _ = mlp.learned_estimate(g_of(mu0), mu1 @ c, g_of(mu1))
+        vals.append(v)
+    vals = np.asarray(vals)
+    se = vals.std(ddof=1) / math.sqrt(len(vals))
+    assert abs(vals.mean() - truth) < 4 * se
+
+
+def test_learned_estimator_perfect_predictor_has_no_correction_variance():
+    q1 = np.array([1.0, 2.0, 3.0])
+    val, var = mlp.learned_estimate(np.array([2.0, 2.5, 1.5, 2.0]), q1, q1.copy())
+    assert val == pytest.approx(2.0)
+    assert var == pytest.approx(np.var([2.0, 2.5, 1.5, 2.0], ddof=1) / 4)
