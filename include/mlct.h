@@ -255,6 +255,68 @@ typedef struct {
 mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t seed,
                            int64_t* w_out, mlct_tri_result* out);
 
+/* ---- learned control-variate level (not in the paper) -------------------
+ * A small MLP g (F = n_cheap + 1 inputs x_f = mu_f / mu_0, two hidden tanh
+ * layers of 64 units, one output) predicts a probe's fine-level value
+ * q = z^T p_{n_fine}(A_hat) z from its cheap moments.  It is trained on pilot
+ * probes, then used as one more multilevel term (Section 2.3, eq.
+ * eqn:telescope; the control-variate form of Section 5.5):
+ *   Gamma = (1/M0) sum_{S0} g + (1/M1) sum_{S1} (q - g),
+ * S0 at degree n_cheap, S1 at degree n_fine, probe sets disjoint from each
+ * other and from the pilot, so Gamma is unbiased for tr p_{n_fine}(A_hat)
+ * whatever g is.  Training is FP32 (Adam, full batch), inference BF16 (bf16
+ * weights, inputs and hidden activations; FP32 accumulation), the same
+ * function for both terms.  If on the held-out pilot probes var(q - g) is not
+ * below var(q), the level falls back to the plain estimator. */
+typedef struct mlct_mlp mlct_mlp;
+
+typedef struct {
+  int32_t epochs;         /* full-batch Adam steps (default 2000)            */
+  float lr;               /* Adam learning rate (default 1e-3)               */
+  double train_fraction;  /* pilot probes used for training (default 0.75)   */
+  uint64_t init_seed;     /* weight initialisation stream (default seed^const) */
+} mlct_mlp_cfg;
+
+typedef struct {
+  double var_q;       /* variance of q on the held-out pilot probes        */
+  double var_resid;   /* variance of q - g on the same probes              */
+  double mean_resid;  /* mean of q - g on the same probes                  */
+  double ybar, ysd;   /* target standardisation (of q / mu_0)              */
+  double final_loss;  /* training loss (standardised units) after training */
+  int32_t fallback;   /* 1 if the learned level is not used                */
+  int32_t n_features, n_cheap, n_fine;
+  int64_t ntrain, nval, nparams;
+} mlct_mlp_info;
+
+#define MLCT_FLAG_LEARNED_FALLBACK 0x8u /* learned level disabled: plain used */
+
+/* Pilot: Rademacher probes [0, m_pilot) of ``seed`` at degree n_fine
+ * (symmetric moment form, arithmetic ``prec``), then training.  [a, b] as in
+ * mlct_estimate (NaN, NaN = Lanczos).  1 <= n_cheap <= 15, n_cheap < n_fine,
+ * m_pilot >= 8.  cfg may be NULL (defaults). */
+mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
+                             int32_t n_fine, int32_t n_cheap, int64_t m_pilot, uint64_t seed,
+                             int32_t prec, const mlct_mlp_cfg* cfg, mlct_mlp** out);
+/* Estimate with the learned level: S0 = probe ids [0, M0), S1 = ids
+ * [M0, M0 + M1) of ``seed`` (seed must differ from the fit seed).  In the
+ * result, level_mean/var[0] describe g over S0 and [1] describe q - g over
+ * S1 (plain fallback: [1] = q over S1, M0 unused). */
+mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* mlp,
+                                  int64_t M0, int64_t M1, uint64_t seed, mlct_result* out);
+mlct_status mlct_mlp_info_get(const mlct_mlp* mlp, mlct_mlp_info* out);
+/* Training loss after each epoch (standardised units): up to max values. */
+mlct_status mlct_mlp_loss_history(const mlct_mlp* mlp, float* out, int32_t max, int32_t* n_out);
+/* Read (get_out, nparams floats, may be NULL) and/or replace (set_in, may be
+ * NULL) the FP32 weights; layout W1[64][F], b1[64], W2[64][64], b2[64],
+ * w3[64], b3.  Replacing also refreshes the BF16 inference weights. */
+mlct_status mlct_mlp_weights(mlct_ctx* ctx, mlct_mlp* mlp, float* get_out, const float* set_in);
+/* Loss (1/N) sum (g(x_i) - y_i)^2 in standardised units and its gradient
+ * (nparams floats) at the current FP32 weights, for host inputs X[N][F], y[N],
+ * computed by the training kernels. */
+mlct_status mlct_mlp_grad(mlct_ctx* ctx, const mlct_mlp* mlp, const float* X, const float* y,
+                          int32_t N, float* grad_out, float* loss_out);
+mlct_status mlct_mlp_destroy(mlct_mlp* mlp);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -832,6 +833,331 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
                                hipMemcpyDeviceToHost, s));
   CHECK(sync_stream(ctx));
   *out = h;
+  return MLCT_OK;
+}
+
+}  // extern "C"
+
+// ---- learned control-variate level ------------------------------------------
+namespace {
+
+constexpr uint64_t kMlpInitMix = 0xD1B54A32D192ED03ull;
+
+size_t align8(size_t x) { return (x + 7) / 8 * 8; }
+
+// Carves consecutive 8-byte-aligned regions out of one workspace slot.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off = align8(off + count * sizeof(T));
+    return p;
+  }
+};
+
+void mlp_free(mlct_mlp* m) {
+  void* ps[] = {m->theta, m->adam_m, m->adam_v, m->wbf16, m->coef};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+}
+
+mlct_status mlp_malloc(mlct_ctx* ctx, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(ctx, MLCT_ENOMEM, "hipMalloc(%zu) failed", bytes);
+  }
+  return MLCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
+                             int32_t n_fine, int32_t n_cheap, int64_t m_pilot, uint64_t seed,
+                             int32_t prec, const mlct_mlp_cfg* cfg, mlct_mlp** out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !out) return fail(ctx, MLCT_EINVAL, "op and out are required");
+  if (n_cheap < 1 || n_cheap >= kMlpMaxFeatures)
+    return fail(ctx, MLCT_EINVAL, "n_cheap must be in [1, %d]", kMlpMaxFeatures - 1);
+  if (n_fine <= n_cheap || n_fine > kMaxDegree)
+    return fail(ctx, MLCT_EINVAL, "need n_cheap < n_fine <= %d", kMaxDegree);
+  if (m_pilot < 8 || m_pilot > (1 << 24)) return fail(ctx, MLCT_EINVAL, "need 8 <= m_pilot <= 2^24");
+  CHECK(check_mode_prec(ctx, MLCT_DOUBLING, prec));
+  const int epochs = cfg && cfg->epochs > 0 ? cfg->epochs : 2000;
+  const float lr = cfg && cfg->lr > 0 ? cfg->lr : 1e-3f;
+  const double frac = cfg && cfg->train_fraction > 0 && cfg->train_fraction <= 1 ? cfg->train_fraction : 0.75;
+  const uint64_t init_seed = cfg && cfg->init_seed ? cfg->init_seed : (seed ^ kMlpInitMix);
+  if (epochs > (1 << 20)) return fail(ctx, MLCT_EINVAL, "too many epochs");
+  CHECK(set_device(ctx));
+  if (std::isnan(a) && std::isnan(b)) {
+    const int steps = op->d < 64 ? (int)op->d : 64;
+    CHECK(mlct_bounds(ctx, op, steps, seed + kGamma, 0.01, &a, &b));
+  }
+  CHECK(check_func(ctx, f, a, b));
+  const int F = n_cheap + 1, P = mlp_nparams(F);
+  const int64_t ldmu = n_fine + 1;
+  const int64_t ntrain = std::max<int64_t>(2, (int64_t)(frac * m_pilot));
+  const int64_t nval = m_pilot - ntrain;
+  // workspace (all before the first launch)
+  void *mu, *scratch;
+  CHECK(ws_get(ctx, WS_MU, (size_t)m_pilot * ldmu * sizeof(double), &mu));
+  CHECK(reserve_block_ws(ctx, op, prec, MLCT_DOUBLING, n_fine,
+                         m_pilot < kDenseMaxBlock ? m_pilot : kDenseMaxBlock));
+  const size_t sbytes = align8(m_pilot * 8) + align8(ntrain * F * 4) + align8(ntrain * 4) +
+                        align8((size_t)kMlpWaves * P * 4) + align8(kMlpWaves * 4) +
+                        align8((size_t)epochs * 4) + 64 + align8(nval * 8) + 64 + 256;
+  CHECK(ws_get(ctx, WS_MLP, sbytes, &scratch));
+  Carver cv{static_cast<char*>(scratch)};
+  double* q = cv.take<double>(m_pilot);
+  float* X = cv.take<float>(ntrain * F);
+  float* y = cv.take<float>(ntrain);
+  float* part = cv.take<float>((size_t)kMlpWaves * P);
+  float* loss_part = cv.take<float>(kMlpWaves);
+  float* loss_hist = cv.take<float>(epochs);
+  double* stats = cv.take<double>(4);
+  double* gval = cv.take<double>(nval > 0 ? nval : 1);
+  double* comb = cv.take<double>(4);
+
+  mlct_mlp* m = new (std::nothrow) mlct_mlp();
+  if (!m) return fail(ctx, MLCT_ENOMEM, "out of host memory");
+  m->device = ctx->device;
+  m->F = F;
+  m->n_cheap = n_cheap;
+  m->n_fine = n_fine;
+  m->func_kind = f.kind;
+  m->power = f.power;
+  m->a = a;
+  m->b = b;
+  m->prec = prec;
+  m->seed = seed;
+  m->m_pilot = m_pilot;
+  m->ntrain = ntrain;
+  mlct_status st = MLCT_OK;
+#define MLP_TRY(expr)          \
+  do {                         \
+    st = (expr);               \
+    if (st != MLCT_OK) {       \
+      mlp_free(m);             \
+      delete m;                \
+      return st;               \
+    }                          \
+  } while (0)
+#define MLP_HIP(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      mlp_free(m);                                                                          \
+      delete m;                                                                             \
+      return fail(ctx, MLCT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    }                                                                                       \
+  } while (0)
+  MLP_TRY(mlp_malloc(ctx, (void**)&m->theta, (size_t)P * 4));
+  MLP_TRY(mlp_malloc(ctx, (void**)&m->adam_m, (size_t)P * 4));
+  MLP_TRY(mlp_malloc(ctx, (void**)&m->adam_v, (size_t)P * 4));
+  MLP_TRY(mlp_malloc(ctx, &m->wbf16, (size_t)P * 2));
+  MLP_TRY(mlp_malloc(ctx, (void**)&m->coef, (size_t)(n_fine + 2) * 8));
+  hipStream_t s = ctx->stream;
+  const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  // pilot moments and fine-level values q
+  mlct_probes pr{};
+  pr.kind = MLCT_PROBE_RADEMACHER;
+  pr.seed = seed;
+  pr.first_id = 0;
+  pr.m = m_pilot;
+  MLP_TRY(run_probe_set(ctx, op, alpha, beta, n_fine, MLCT_DOUBLING, prec, &pr,
+                        static_cast<double*>(mu), ldmu));
+  MLP_HIP(launch_cheb_dct(s, f.kind, f.power, a, b, n_fine, m->coef, m->coef + n_fine + 1));
+  MLP_HIP(launch_qvals(s, static_cast<double*>(mu), ldmu, m->coef, n_fine, m_pilot, q));
+  // training set and training
+  MLP_HIP(launch_mlp_prepare(s, static_cast<double*>(mu), ldmu, q, F, (int)ntrain, X, y, stats));
+  MLP_HIP(launch_mlp_init(s, m->theta, m->adam_m, m->adam_v, F, init_seed));
+  for (int t = 1; t <= epochs; ++t) {
+    MLP_HIP(launch_mlp_grad(s, m->theta, F, X, y, (int)ntrain, kMlpWaves, part, loss_part));
+    MLP_HIP(launch_mlp_adam(s, m->theta, m->adam_m, m->adam_v, part, kMlpWaves, F, t, lr,
+                            loss_part, (int)ntrain, loss_hist));
+  }
+  MLP_HIP(launch_mlp_to_bf16(s, m->theta, F, m->wbf16));
+  double hstats[2];
+  MLP_HIP(hipMemcpyAsync(hstats, stats, sizeof hstats, hipMemcpyDeviceToHost, s));
+  MLP_TRY(sync_stream(ctx));
+  m->ybar = hstats[0];
+  m->ysd = hstats[1];
+  // held-out pilot probes: variance of q and of q - g
+  if (nval >= 2) {
+    const double* muv = static_cast<double*>(mu) + ntrain * ldmu;
+    MLP_HIP(launch_mlp_infer(s, m->wbf16, F, muv, ldmu, nval, m->ybar, m->ysd, gval));
+    MLP_HIP(launch_mlp_combine(s, q + ntrain, nval, q + ntrain, gval, nval, comb));
+    double hc[4];
+    MLP_HIP(hipMemcpyAsync(hc, comb, sizeof hc, hipMemcpyDeviceToHost, s));
+    MLP_TRY(sync_stream(ctx));
+    m->var_q = hc[1];
+    m->var_resid = hc[3];
+    m->mean_resid = hc[2];
+    m->fallback = !(hc[3] < hc[1]);
+  }
+  m->loss_hist.resize(epochs);
+  MLP_HIP(hipMemcpyAsync(m->loss_hist.data(), loss_hist, (size_t)epochs * 4,
+                         hipMemcpyDeviceToHost, s));
+  MLP_TRY(sync_stream(ctx));
+  double ls = 0.0;
+  MLP_HIP(hipMemcpy(&ls, m->coef + n_fine + 1, 8, hipMemcpyDeviceToHost));
+  m->log_scale = ls;
+#undef MLP_TRY
+#undef MLP_HIP
+  *out = m;
+  return MLCT_OK;
+}
+
+mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* m,
+                                  int64_t M0, int64_t M1, uint64_t seed, mlct_result* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !m || !out) return fail(ctx, MLCT_EINVAL, "op, mlp and out are required");
+  if (seed == m->seed) return fail(ctx, MLCT_EINVAL, "use a seed different from the pilot's");
+  const bool learned = !m->fallback;
+  if (M1 < 2 || (learned && M0 < 2)) return fail(ctx, MLCT_EINVAL, "need M0, M1 >= 2");
+  CHECK(set_device(ctx));
+  const int nc = m->n_cheap, n = m->n_fine, F = m->F;
+  const double alpha = 2.0 / (m->b - m->a), beta = -(m->a + m->b) / (m->b - m->a);
+  const int64_t M0u = learned ? M0 : 0;
+  void *mu0, *mu1, *scratch, *res;
+  CHECK(ws_get(ctx, WS_MU2, (size_t)(M0u > 0 ? M0u : 1) * (nc + 1) * 8, &mu0));
+  CHECK(ws_get(ctx, WS_MU, (size_t)M1 * (n + 1) * 8, &mu1));
+  const int64_t mx = std::max(M0u, M1);
+  CHECK(reserve_block_ws(ctx, op, m->prec, MLCT_DOUBLING, n, mx < kDenseMaxBlock ? mx : kDenseMaxBlock));
+  CHECK(ws_get(ctx, WS_MLP, align8((M0u + 1) * 8) + 2 * align8(M1 * 8) + 64, &scratch));
+  CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_result), &res));
+  Carver cv{static_cast<char*>(scratch)};
+  double* g0 = cv.take<double>(M0u + 1);
+  double* g1 = cv.take<double>(M1);
+  double* q1 = cv.take<double>(M1);
+  double* comb = cv.take<double>(4);
+  hipStream_t s = ctx->stream;
+  mlct_probes pr{};
+  pr.kind = MLCT_PROBE_RADEMACHER;
+  pr.seed = seed;
+  if (learned) {
+    pr.first_id = 0;
+    pr.m = M0u;
+    CHECK(run_probe_set(ctx, op, alpha, beta, nc, MLCT_DOUBLING, m->prec, &pr,
+                        static_cast<double*>(mu0), nc + 1));
+    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, static_cast<double*>(mu0), nc + 1, M0u, m->ybar,
+                                 m->ysd, g0));
+  }
+  pr.first_id = M0u;
+  pr.m = M1;
+  CHECK(run_probe_set(ctx, op, alpha, beta, n, MLCT_DOUBLING, m->prec, &pr,
+                      static_cast<double*>(mu1), n + 1));
+  HIPCHK(ctx, launch_qvals(s, static_cast<double*>(mu1), n + 1, m->coef, n, M1, q1));
+  if (learned)
+    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, static_cast<double*>(mu1), n + 1, M1, m->ybar,
+                                 m->ysd, g1));
+  HIPCHK(ctx, launch_mlp_combine(s, g0, M0u, q1, learned ? g1 : nullptr, M1, comb));
+  double hc[4];
+  HIPCHK(ctx, hipMemcpyAsync(hc, comb, sizeof hc, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  mlct_result r{};
+  r.value = (learned ? hc[0] : 0.0) + hc[2];
+  r.est_var = (learned ? hc[1] / M0u : 0.0) + hc[3] / M1;
+  r.log_scale = m->log_scale;
+  r.estimate = r.value * std::exp(r.log_scale);
+  r.level_mean[0] = learned ? hc[0] : 0.0;
+  r.level_var[0] = learned ? hc[1] : 0.0;
+  r.level_mean[1] = hc[2];
+  r.level_var[1] = hc[3];
+  r.matvecs = M0u * ((nc + 1) / 2) + M1 * ((n + 1) / 2);
+  r.probe_degrees = M0u * nc + M1 * n;
+  r.interval_a = m->a;
+  r.interval_b = m->b;
+  r.max_moment_ratio = 0.0;
+  r.flags = learned ? 0u : MLCT_FLAG_LEARNED_FALLBACK;
+  if (!std::isfinite(r.estimate)) r.flags |= MLCT_FLAG_OVERFLOW;
+  *out = r;
+  return MLCT_OK;
+}
+
+mlct_status mlct_mlp_info_get(const mlct_mlp* m, mlct_mlp_info* out) {
+  if (!m || !out) return MLCT_EINVAL;
+  out->var_q = m->var_q;
+  out->var_resid = m->var_resid;
+  out->mean_resid = m->mean_resid;
+  out->ybar = m->ybar;
+  out->ysd = m->ysd;
+  out->final_loss = m->loss_hist.empty() ? NAN : m->loss_hist.back();
+  out->fallback = m->fallback;
+  out->n_features = m->F;
+  out->n_cheap = m->n_cheap;
+  out->n_fine = m->n_fine;
+  out->ntrain = m->ntrain;
+  out->nval = m->m_pilot - m->ntrain;
+  out->nparams = mlp_nparams(m->F);
+  return MLCT_OK;
+}
+
+mlct_status mlct_mlp_loss_history(const mlct_mlp* m, float* out, int32_t max, int32_t* n_out) {
+  if (!m || (!out && max > 0)) return MLCT_EINVAL;
+  const int32_t n = std::min<int32_t>(max, (int32_t)m->loss_hist.size());
+  if (n > 0) std::memcpy(out, m->loss_hist.data(), (size_t)n * 4);
+  if (n_out) *n_out = (int32_t)m->loss_hist.size();
+  return MLCT_OK;
+}
+
+mlct_status mlct_mlp_weights(mlct_ctx* ctx, mlct_mlp* m, float* get_out, const float* set_in) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!m) return fail(ctx, MLCT_EINVAL, "mlp is required");
+  CHECK(set_device(ctx));
+  const int P = mlp_nparams(m->F);
+  if (set_in) {
+    HIPCHK(ctx, hipMemcpyAsync(m->theta, set_in, (size_t)P * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, launch_mlp_to_bf16(ctx->stream, m->theta, m->F, m->wbf16));
+  }
+  if (get_out)
+    HIPCHK(ctx, hipMemcpyAsync(get_out, m->theta, (size_t)P * 4, hipMemcpyDeviceToHost, ctx->stream));
+  return sync_stream(ctx);
+}
+
+mlct_status mlct_mlp_grad(mlct_ctx* ctx, const mlct_mlp* m, const float* X, const float* y,
+                          int32_t N, float* grad_out, float* loss_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!m || !X || !y || !grad_out || N < 1) return fail(ctx, MLCT_EINVAL, "bad arguments");
+  CHECK(set_device(ctx));
+  const int F = m->F, P = mlp_nparams(F);
+  void* scratch;
+  CHECK(ws_get(ctx, WS_MLP, align8((size_t)N * F * 4) + align8((size_t)N * 4) +
+                                align8((size_t)kMlpWaves * P * 4) + align8(kMlpWaves * 4) +
+                                align8((size_t)P * 4) + 64, &scratch));
+  Carver cv{static_cast<char*>(scratch)};
+  float* dX = cv.take<float>((size_t)N * F);
+  float* dy = cv.take<float>(N);
+  float* part = cv.take<float>((size_t)kMlpWaves * P);
+  float* lp = cv.take<float>(kMlpWaves);
+  float* g = cv.take<float>(P);
+  float* loss = cv.take<float>(2);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(dX, X, (size_t)N * F * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(dy, y, (size_t)N * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, launch_mlp_grad(s, m->theta, F, dX, dy, N, kMlpWaves, part, lp));
+  HIPCHK(ctx, launch_mlp_gradsum(s, part, kMlpWaves, F, lp, N, g, loss));
+  HIPCHK(ctx, hipMemcpyAsync(grad_out, g, (size_t)P * 4, hipMemcpyDeviceToHost, s));
+  float hl = 0.f;
+  HIPCHK(ctx, hipMemcpyAsync(&hl, loss, 4, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  if (loss_out) *loss_out = hl;
+  return MLCT_OK;
+}
+
+mlct_status mlct_mlp_destroy(mlct_mlp* m) {
+  if (!m) return MLCT_EINVAL;
+  (void)hipSetDevice(m->device);
+  mlp_free(m);
+  delete m;
   return MLCT_OK;
 }
 

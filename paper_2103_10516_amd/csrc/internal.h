@@ -69,12 +69,32 @@ struct mlct_op {
   void* a64 = nullptr;        // FP64 copy of an FP32 dense A (lazily built)
 };
 
+// A trained learned level (mlct_learned_fit).  Device arrays are owned.
+struct mlct_mlp {
+  int device = 0;
+  int F = 9, n_cheap = 8, n_fine = 256;
+  int32_t func_kind = MLCT_LOG;
+  double power = 1.0, a = 0.0, b = 1.0, log_scale = 0.0;
+  int32_t prec = MLCT_FP32;
+  uint64_t seed = 0;
+  int64_t m_pilot = 0, ntrain = 0;
+  float* theta = nullptr;  // FP32 weights (device)
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  void* wbf16 = nullptr;   // bf16 inference weights (device)
+  double* coef = nullptr;  // c_0..c_{n_fine} (device)
+  double ybar = 0.0, ysd = 1.0;
+  double var_q = 0.0, var_resid = 0.0, mean_resid = 0.0;
+  int fallback = 0;
+  std::vector<float> loss_hist;
+};
+
 namespace mlct {
 
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -184,5 +204,28 @@ struct LanczosState {
 hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int64_t lda,
                           int steps, uint64_t seed, double margin, double* Q, double* w,
                           double* h, double* part, LanczosState* st, double* out);
+
+// ---- learned control-variate level (k_mlp.hip) -----------------------------
+constexpr int kMlpHidden = 64;
+constexpr int kMlpMaxFeatures = 16;
+constexpr int kMlpWaves = 32;
+int mlp_nparams(int F);
+hipError_t launch_mlp_init(hipStream_t s, float* theta, float* m, float* v, int F, uint64_t seed);
+hipError_t launch_mlp_grad(hipStream_t s, const float* theta, int F, const float* X,
+                           const float* y, int N, int nwaves, float* part, float* loss_part);
+hipError_t launch_mlp_gradsum(hipStream_t s, const float* part, int nwaves, int F,
+                              const float* loss_part, int N, float* grad, float* loss);
+hipError_t launch_mlp_adam(hipStream_t s, float* theta, float* m, float* v, const float* part,
+                           int nwaves, int F, int t, float lr, const float* loss_part, int N,
+                           float* loss_hist);
+hipError_t launch_mlp_to_bf16(hipStream_t s, const float* theta, int F, void* w);
+hipError_t launch_mlp_infer(hipStream_t s, const void* w, int F, const double* mu, int64_t ldmu,
+                            int64_t rows, double ybar, double ysd, double* g);
+hipError_t launch_qvals(hipStream_t s, const double* mu, int64_t ldmu, const double* c, int n,
+                        int64_t rows, double* q);
+hipError_t launch_mlp_prepare(hipStream_t s, const double* mu, int64_t ldmu, const double* q,
+                              int F, int ntrain, float* X, float* y, double* stats);
+hipError_t launch_mlp_combine(hipStream_t s, const double* a, int64_t na, const double* b,
+                              const double* a2, int64_t nb, double* out);
 
 }  // namespace mlct

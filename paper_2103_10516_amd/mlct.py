@@ -307,3 +307,126 @@ def mlct_lanczos(ctx: Context, op: Op, steps: int = 64, seed: int = 0, rel_margi
     n = k.value
     return al[:n], be[:n], {"theta_min": info[0], "theta_max": info[1], "r_min": info[2],
                             "r_max": info[3], "a": info[4], "b": info[5]}
+
+
+# ---- learned control-variate level ------------------------------------------
+class mlct_mlp_cfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("lr", C.c_float), ("train_fraction", C.c_double),
+                ("init_seed", C.c_uint64)]
+
+
+class mlct_mlp_info(C.Structure):
+    _fields_ = [("var_q", C.c_double), ("var_resid", C.c_double), ("mean_resid", C.c_double),
+                ("ybar", C.c_double), ("ysd", C.c_double), ("final_loss", C.c_double),
+                ("fallback", C.c_int32), ("n_features", C.c_int32), ("n_cheap", C.c_int32),
+                ("n_fine", C.c_int32), ("ntrain", C.c_int64), ("nval", C.c_int64),
+                ("nparams", C.c_int64)]
+
+
+MLCT_FLAG_LEARNED_FALLBACK = 0x8
+
+_MLP_SIGS = {
+    "mlct_learned_fit": [C.c_void_p, C.c_void_p, mlct_func, C.c_double, C.c_double, C.c_int32,
+                         C.c_int32, C.c_int64, C.c_uint64, C.c_int32, C.POINTER(mlct_mlp_cfg),
+                         C.POINTER(C.c_void_p)],
+    "mlct_estimate_learned": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                              C.c_uint64, C.POINTER(mlct_result)],
+    "mlct_mlp_info_get": [C.c_void_p, C.POINTER(mlct_mlp_info)],
+    "mlct_mlp_loss_history": [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
+    "mlct_mlp_weights": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "mlct_mlp_grad": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                      C.POINTER(C.c_float)],
+    "mlct_mlp_destroy": [C.c_void_p],
+}
+
+
+def _mlp_lib():
+    h = lib()
+    if not getattr(h, "_mlp_sigs_set", False):
+        for name, args in _MLP_SIGS.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        h._mlp_sigs_set = True
+    return h
+
+
+class Mlp:
+    """Trained learned level (owns an mlct_mlp)."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx, self.handle = ctx, handle
+        ctx._ops.add(self)
+
+    def close(self):
+        if self.handle:
+            _mlp_lib().mlct_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlct_learned_fit(ctx: Context, op: Op, kind: int, a: float, b: float, n_fine: int = 256,
+                     n_cheap: int = 8, m_pilot: int = 2048, seed: int = 1,
+                     prec: int = MLCT_FP32, epochs: int = 2000, lr: float = 1e-3,
+                     train_fraction: float = 0.75, init_seed: int = 0,
+                     power: float = 1.0) -> Mlp:
+    cfg = mlct_mlp_cfg(epochs, lr, train_fraction, init_seed & ((1 << 64) - 1))
+    h = C.c_void_p()
+    _check(ctx, _mlp_lib().mlct_learned_fit(ctx.handle, op.handle, mlct_func(kind, power), a, b,
+                                            n_fine, n_cheap, m_pilot, seed & ((1 << 64) - 1),
+                                            prec, C.byref(cfg), C.byref(h)))
+    return Mlp(ctx, h)
+
+
+def mlct_estimate_learned(ctx: Context, op: Op, mlp: Mlp, M0: int, M1: int, seed: int) -> dict:
+    r = mlct_result()
+    _check(ctx, _mlp_lib().mlct_estimate_learned(ctx.handle, op.handle, mlp.handle, M0, M1,
+                                                 seed & ((1 << 64) - 1), C.byref(r)))
+    return {"estimate": r.estimate, "value": r.value, "log_scale": r.log_scale,
+            "est_var": r.est_var, "level_mean": np.array(r.level_mean[:2]),
+            "level_var": np.array(r.level_var[:2]), "matvecs": r.matvecs,
+            "probe_degrees": r.probe_degrees, "flags": r.flags}
+
+
+def mlct_mlp_info_get(mlp: Mlp) -> dict:
+    i = mlct_mlp_info()
+    st = _mlp_lib().mlct_mlp_info_get(mlp.handle, C.byref(i))
+    if st != MLCT_OK:
+        raise MlctError(st, "mlct_mlp_info_get failed")
+    return {k: getattr(i, k) for k, _ in mlct_mlp_info._fields_}
+
+
+def mlct_mlp_loss_history(mlp: Mlp) -> np.ndarray:
+    n = C.c_int32()
+    _mlp_lib().mlct_mlp_loss_history(mlp.handle, None, 0, C.byref(n))
+    out = np.empty(n.value, dtype=np.float32)
+    _mlp_lib().mlct_mlp_loss_history(mlp.handle, out.ctypes.data, n.value, None)
+    return out
+
+
+def mlct_mlp_weights(ctx: Context, mlp: Mlp, set_to=None) -> np.ndarray:
+    P = mlct_mlp_info_get(mlp)["nparams"]
+    out = np.empty(P, dtype=np.float32)
+    src = None
+    if set_to is not None:
+        src = np.ascontiguousarray(set_to, dtype=np.float32)
+        assert src.size == P
+    _check(ctx, _mlp_lib().mlct_mlp_weights(ctx.handle, mlp.handle, out.ctypes.data,
+                                            None if src is None else src.ctypes.data))
+    return out
+
+
+def mlct_mlp_grad(ctx: Context, mlp: Mlp, X, y):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    P = mlct_mlp_info_get(mlp)["nparams"]
+    g = np.empty(P, dtype=np.float32)
+    loss = C.c_float()
+    _check(ctx, _mlp_lib().mlct_mlp_grad(ctx.handle, mlp.handle, X.ctypes.data, y.ctypes.data,
+                                         X.shape[0], g.ctypes.data, C.byref(loss)))
+    return g, loss.value
