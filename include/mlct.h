@@ -166,6 +166,7 @@ typedef enum {
   MLCT_KERNEL_DENSE_STEP = 1, /* one recurrence step over a dense operator */
   MLCT_KERNEL_TRI_STEP = 2,   /* one integer triangle-moment SpMM          */
   MLCT_KERNEL_GRAM = 3,       /* Gram matrix formation                     */
+  MLCT_KERNEL_BATCH_STEP = 4, /* one batched recurrence step (all blocks)  */
   MLCT_NUM_KERNEL_IDS = 8
 } mlct_kernel_id;
 mlct_status mlct_timing(mlct_ctx* ctx, int32_t enable);
@@ -241,6 +242,25 @@ mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64
 mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
                           const mlct_levels* levels, uint64_t seed, int32_t prec,
                           int32_t mode, mlct_result* out);
+
+/* Many estimates in shared launches: every (item, level, block of 64
+ * probes) of all items advances one recurrence step per launch, so the
+ * number of launches is the largest step count, not the sum over items.
+ * Items must use CSR operators (valued or pattern, any sizes); precision
+ * MLCT_FP32; mode MLCT_DIRECT or MLCT_DOUBLING (optionally with
+ * MLCT_LEVEL_INTERP).  Each item's result equals what mlct_estimate returns
+ * for it.  outs: host, nitems results.  Fails with MLCT_ESPECTRUM if any item's
+ * moments leave [-|z|^2, |z|^2] (that item's result is still written). */
+typedef struct {
+  const mlct_op* op;
+  mlct_func f;
+  double a, b;
+  mlct_levels levels;
+  uint64_t seed;
+} mlct_batch_item;
+
+mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems, const mlct_batch_item* items,
+                                int32_t prec, int32_t mode, mlct_result* outs);
 
 /* Triangle count tr(A^3)/6 of a 0/1 pattern CSR graph (Section 2.1 example,
  * Section 5.5): per probe, exact int32 y = A z and w = A y with int64

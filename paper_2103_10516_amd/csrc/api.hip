@@ -1162,3 +1162,226 @@ mlct_status mlct_mlp_destroy(mlct_mlp* m) {
 }
 
 }  // extern "C"
+
+// ---- batched estimates --------------------------------------------------------
+namespace {
+
+struct HostBlock {
+  int item, level;
+  int64_t first_id;
+  int active, degree, steps;
+  int variant;  // index into the variant list
+};
+
+}  // namespace
+
+extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
+                                           const mlct_batch_item* items, int32_t prec,
+                                           int32_t mode, mlct_result* outs) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (nitems < 1 || !items || !outs) return fail(ctx, MLCT_EINVAL, "need items and outs");
+  const int interp = (mode & MLCT_LEVEL_INTERP) ? 1 : 0;
+  mode &= ~MLCT_LEVEL_INTERP;
+  if (prec != MLCT_FP32) return fail(ctx, MLCT_EUNSUPPORTED, "batched estimates run in MLCT_FP32");
+  CHECK(check_mode_prec(ctx, mode, prec));
+  // ---- validate items, build level descriptors and blocks ----
+  std::vector<LevelDesc> lvs(nitems);
+  std::vector<int64_t> totals(nitems);
+  std::vector<int> top(nitems);
+  std::vector<HostBlock> blocks;
+  std::vector<std::pair<bool, int>> variants;  // (pattern, maxnz class)
+  for (int i = 0; i < nitems; ++i) {
+    const mlct_batch_item& it = items[i];
+    if (!it.op || it.op->kind != OP_CSR) return fail(ctx, MLCT_EINVAL, "item %d: need a CSR operator", i);
+    if ((uint64_t)it.op->d * 64 * 4 > 0xFFFFFFFFull)
+      return fail(ctx, MLCT_EUNSUPPORTED, "item %d: operator too large for a batch", i);
+    CHECK(check_func(ctx, it.f, it.a, it.b));
+    const int L = it.levels.L;
+    if (L < 1 || L > MLCT_MAX_LEVELS || !it.levels.degree || !it.levels.m)
+      return fail(ctx, MLCT_EINVAL, "item %d: need 1..%d levels", i, MLCT_MAX_LEVELS);
+    LevelDesc& lv = lvs[i];
+    lv = LevelDesc{};
+    lv.L = L;
+    lv.interp = interp;
+    int64_t tot = 0;
+    for (int k = 0; k < L; ++k) {
+      const int dk = it.levels.degree[k];
+      if (dk < 0 || dk > kMaxDegree || (k && dk <= it.levels.degree[k - 1]) || it.levels.m[k] < 1 ||
+          (interp && dk < 1))
+        return fail(ctx, MLCT_EINVAL, "item %d: bad levels", i);
+      lv.degree[k] = dk;
+      lv.m[k] = it.levels.m[k];
+      lv.off[k] = tot;
+      tot += it.levels.m[k];
+    }
+    totals[i] = tot;
+    top[i] = lv.degree[L - 1];
+    if (top[i] < 1) return fail(ctx, MLCT_EINVAL, "item %d: top degree must be >= 1", i);
+    lv.coef_stride = top[i] + 1;
+    const bool pat = it.op->val == nullptr;
+    const int mz = it.op->max_row_nnz <= 4 ? 4 : it.op->max_row_nnz <= 5 ? 5 : 8;
+    int var = -1;
+    for (size_t v = 0; v < variants.size(); ++v)
+      if (variants[v] == std::make_pair(pat, mz)) var = (int)v;
+    if (var < 0) {
+      variants.push_back({pat, mz});
+      var = (int)variants.size() - 1;
+    }
+    for (int k = 0; k < L; ++k)
+      for (int64_t p0 = 0; p0 < lv.m[k]; p0 += kBlockProbes) {
+        HostBlock hb;
+        hb.item = i;
+        hb.level = k;
+        hb.first_id = lv.off[k] + p0;
+        hb.active = (int)std::min<int64_t>(kBlockProbes, lv.m[k] - p0);
+        hb.degree = lv.degree[k];
+        hb.steps = mode == MLCT_DOUBLING ? (hb.degree + 1) / 2 : hb.degree;
+        hb.variant = var;
+        blocks.push_back(hb);
+      }
+  }
+  // variant-major, then by steps descending: the blocks still running at
+  // step s are a prefix of their variant's table
+  std::stable_sort(blocks.begin(), blocks.end(), [](const HostBlock& x, const HostBlock& y) {
+    return x.variant != y.variant ? x.variant < y.variant : x.steps > y.steps;
+  });
+  CHECK(set_device(ctx));
+  // ---- workspace sizes ----
+  const size_t nb = blocks.size();
+  size_t bytes = align8(nb * sizeof(BatchBlock)) + 256;
+  for (const HostBlock& hb : blocks) {
+    const int64_t d = items[hb.item].op->d;
+    const CsrStepPlan plan = plan_csr(d);
+    bytes += 2 * align8((size_t)d * 64 * 4);
+    bytes += align8((size_t)(hb.steps + 1) * 2 * plan.ngroups * 64 * 8);
+    bytes += align8((size_t)(hb.steps + 1) * 2 * 64 * 8);
+  }
+  for (int i = 0; i < nitems; ++i) {
+    const int ncoef = interp ? lvs[i].L : 1;
+    bytes += align8((size_t)totals[i] * (top[i] + 1) * 8);           // moment table
+    bytes += align8(((size_t)ncoef * (top[i] + 1) + 1) * 8);         // coefficients + log-scale
+    bytes += align8(((size_t)totals[i] + 3 * MLCT_MAX_LEVELS) * 8);  // Q and level stats
+  }
+  bytes += align8((size_t)nitems * sizeof(mlct_result));
+  void* ws;
+  CHECK(ws_get(ctx, WS_BATCH, bytes, &ws));
+  Carver cv{static_cast<char*>(ws)};
+  BatchBlock* dtab = cv.take<BatchBlock>(nb);
+  std::vector<BatchBlock> tab(nb);
+  std::vector<double*> dots(nb);
+  for (size_t bi = 0; bi < nb; ++bi) {
+    const HostBlock& hb = blocks[bi];
+    const mlct_op* op = items[hb.item].op;
+    const CsrStepPlan plan = plan_csr(op->d);
+    BatchBlock& B = tab[bi];
+    B.rowptr = op->rowptr;
+    B.col = op->col;
+    B.val = static_cast<const float*>(op->val);
+    B.d = op->d;
+    B.nnz = op->nnz;
+    B.v0 = cv.take<float>((size_t)op->d * 64);
+    B.v1 = cv.take<float>((size_t)op->d * 64);
+    B.part = cv.take<double>((size_t)(hb.steps + 1) * 2 * plan.ngroups * 64);
+    dots[bi] = cv.take<double>((size_t)(hb.steps + 1) * 2 * 64);
+    B.src = ProbeSrc{items[hb.item].seed, hb.first_id, nullptr, 0, hb.active};
+    const double a = items[hb.item].a, b = items[hb.item].b;
+    B.alpha = 2.0 / (b - a);
+    B.beta = -(a + b) / (b - a);
+    B.steps = hb.steps;
+    B.ngroups = plan.ngroups;
+    B.rows_per_group = plan.rows_per_group;
+  }
+  std::vector<double*> mu(nitems), coef(nitems), qst(nitems);
+  for (int i = 0; i < nitems; ++i) {
+    const int ncoef = interp ? lvs[i].L : 1;
+    mu[i] = cv.take<double>((size_t)totals[i] * (top[i] + 1));
+    coef[i] = cv.take<double>((size_t)ncoef * (top[i] + 1) + 1);
+    qst[i] = cv.take<double>((size_t)totals[i] + 3 * MLCT_MAX_LEVELS);
+  }
+  mlct_result* dres = cv.take<mlct_result>(nitems);
+  // group bases per variant table (each variant's blocks are contiguous)
+  std::vector<size_t> vstart(variants.size() + 1, nb);
+  for (size_t bi = nb; bi-- > 0;) vstart[blocks[bi].variant] = bi;
+  vstart[variants.size()] = nb;
+  for (size_t v = 0; v < variants.size(); ++v) {
+    int64_t base = 0;
+    for (size_t bi = vstart[v]; bi < vstart[v + 1]; ++bi) {
+      tab[bi].group_base = base;
+      base += tab[bi].ngroups;
+    }
+  }
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, hipMemcpyAsync(dtab, tab.data(), nb * sizeof(BatchBlock), hipMemcpyHostToDevice, s));
+  // ---- coefficients ----
+  for (int i = 0; i < nitems; ++i) {
+    const int n = top[i];
+    double* ls = coef[i] + (size_t)(interp ? lvs[i].L : 1) * (n + 1);
+    if (!interp) {
+      HIPCHK(ctx, launch_cheb_dct(s, items[i].f.kind, items[i].f.power, items[i].a, items[i].b, n,
+                                  coef[i], ls));
+    } else {
+      for (int k = 0; k < lvs[i].L; ++k)
+        HIPCHK(ctx, launch_cheb_dct(s, items[i].f.kind, items[i].f.power, items[i].a, items[i].b,
+                                    lvs[i].degree[k], coef[i] + (size_t)k * (n + 1), ls));
+    }
+  }
+  // ---- probes, steps ----
+  int max_steps = 0;
+  for (const HostBlock& hb : blocks) max_steps = std::max(max_steps, hb.steps);
+  for (size_t v = 0; v < variants.size(); ++v) {
+    const size_t b0 = vstart[v], cnt = vstart[v + 1] - b0;
+    if (!cnt) continue;
+    const int64_t groups = tab[b0 + cnt - 1].group_base + tab[b0 + cnt - 1].ngroups;
+    HIPCHK(ctx, launch_probe_init_batched(s, dtab + b0, (int)cnt, groups));
+  }
+  for (int st = 1; st <= max_steps; ++st) {
+    for (size_t v = 0; v < variants.size(); ++v) {
+      size_t cnt = 0;
+      while (vstart[v] + cnt < vstart[v + 1] && tab[vstart[v] + cnt].steps >= st) ++cnt;
+      if (!cnt) continue;
+      const size_t b0 = vstart[v];
+      const int64_t groups = tab[b0 + cnt - 1].group_base + tab[b0 + cnt - 1].ngroups;
+      const int zmode = (st == 1 || mode == MLCT_DOUBLING) ? 0 : 1;
+      LaunchTimer tm(ctx, MLCT_KERNEL_BATCH_STEP);
+      HIPCHK(ctx, launch_csr_step_batched(s, dtab + b0, (int)cnt, groups, st, variants[v].first,
+                                          variants[v].second, zmode));
+      tm.done();
+    }
+  }
+  // ---- moments, levels ----
+  for (size_t bi = 0; bi < nb; ++bi) {
+    const HostBlock& hb = blocks[bi];
+    HIPCHK(ctx, launch_reduce_partials(s, tab[bi].part, hb.steps + 1, 2, tab[bi].ngroups, 64,
+                                       dots[bi]));
+    HIPCHK(ctx, launch_assemble_moments(s, dots[bi], hb.steps + 1, 64, hb.active, mode, hb.degree,
+                                        mu[hb.item] + hb.first_id * (top[hb.item] + 1),
+                                        top[hb.item] + 1));
+  }
+  for (int i = 0; i < nitems; ++i) {
+    const int n = top[i];
+    double* ls = coef[i] + (size_t)(interp ? lvs[i].L : 1) * (n + 1);
+    HIPCHK(ctx, launch_level_combine(s, mu[i], n + 1, coef[i], ls, lvs[i], qst[i],
+                                     qst[i] + totals[i], dres + i));
+  }
+  std::vector<mlct_result> h(nitems);
+  HIPCHK(ctx, hipMemcpyAsync(h.data(), dres, nitems * sizeof(mlct_result), hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  bool escaped = false;
+  for (int i = 0; i < nitems; ++i) {
+    int64_t mv = 0, pd = 0;
+    for (int k = 0; k < lvs[i].L; ++k) {
+      const int dk = lvs[i].degree[k];
+      mv += lvs[i].m[k] * (int64_t)(mode == MLCT_DOUBLING ? (dk + 1) / 2 : dk);
+      pd += lvs[i].m[k] * (int64_t)dk;
+    }
+    h[i].matvecs = mv;
+    h[i].probe_degrees = pd;
+    h[i].interval_a = items[i].a;
+    h[i].interval_b = items[i].b;
+    if (!(h[i].max_moment_ratio <= 1.0 + 1e-3)) escaped = true;
+    outs[i] = h[i];
+  }
+  if (escaped) return fail(ctx, MLCT_ESPECTRUM, "an item's spectrum is not inside its [a, b]");
+  return MLCT_OK;
+}

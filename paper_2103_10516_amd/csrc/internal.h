@@ -94,7 +94,7 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -144,6 +144,26 @@ CsrStepPlan plan_csr(int64_t d);
 template <typename T>
 hipError_t launch_probe_init(hipStream_t s, T* v0, int64_t d, ProbeSrc src,
                              const CsrStepPlan& plan, double* part0);
+// One probe block of a batch (FP32, 64 probes) over one CSR operator.
+struct BatchBlock {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const float* val;  // nullptr = pattern
+  int64_t d, nnz;
+  float* v0;
+  float* v1;
+  double* part;       // [steps + 1][2][ngroups][64]
+  ProbeSrc src;
+  double alpha, beta;
+  int steps, ngroups, rows_per_group;
+  int64_t group_base;  // first workgroup of this block in the launch grid
+};
+hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
+                                     int64_t total_groups);
+// zmode 0 or 1 (regenerated probes); step >= 1
+hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
+                                   int64_t total_groups, int step, bool pattern, int maxnz,
+                                   int zmode);
 // zmode: 0 = dots with V_k (symmetric form), 1 = regenerated Rademacher z,
 // 2 = explicit z entries.  has_prev = false for the first step (no V_prev).
 template <typename T>

@@ -43,12 +43,11 @@ __device__ __forceinline__ void store_partials(double a1, double a2, int g, int 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0, int64_t d,
-                                                              ProbeSrc src, int rows_per_group,
-                                                              int ngroups,
-                                                              double* __restrict__ part) {
+__device__ __forceinline__ void probe_init_wg(T* __restrict__ v0, int64_t d, const ProbeSrc& src,
+                                              int rows_per_group, int ngroups,
+                                              double* __restrict__ part, int bid) {
   const int lane = lane_id(), wave = wave_id();
-  const int g = xcd_band(blockIdx.x, ngroups);
+  const int g = xcd_band(bid, ngroups);
   const int64_t r0 = (int64_t)g * rows_per_group;
   const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
   const bool act = lane < src.active;
@@ -74,6 +73,14 @@ __global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0
     acc += (double)z * (double)z;
   }
   store_partials<T>(acc, 0.0, g, ngroups, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0, int64_t d,
+                                                              ProbeSrc src, int rows_per_group,
+                                                              int ngroups,
+                                                              double* __restrict__ part) {
+  probe_init_wg<T>(v0, d, src, rows_per_group, ngroups, part, blockIdx.x);
 }
 
 // Per-row epilogue: V_new = ca*acc + cb*V_k[i] (- V_prev[i]), written over
@@ -208,15 +215,15 @@ __device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int q, 
 // (unused slots gather some valid row with weight 0), all in flight before
 // the first is consumed; other groups take the generic loop.
 template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
-__global__ __launch_bounds__(kThreads) void csr_step_kernel(
+__device__ __forceinline__ void csr_step_wg(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
-    T* __restrict__ vm, T ca, T cb, ProbeSrc src, int rows_per_group, int ngroups,
-    double* __restrict__ part) {
+    T* __restrict__ vm, T ca, T cb, const ProbeSrc& src, int rows_per_group, int ngroups,
+    double* __restrict__ part, int bid) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
   constexpr int GPB = 64 / ROWS;  // groups per batch
   const int lane = lane_id(), wave = wave_id();
-  const int g = xcd_band(blockIdx.x, ngroups);
+  const int g = xcd_band(bid, ngroups);
   const int64_t r0 = (int64_t)g * rows_per_group;
   const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
   const bool act = lane < src.active;
@@ -331,6 +338,54 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
   store_partials<T>(acc1, acc2, g, ngroups, part);
 }
 
+template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
+__global__ __launch_bounds__(kThreads) void csr_step_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
+    T* __restrict__ vm, T ca, T cb, ProbeSrc src, int rows_per_group, int ngroups,
+    double* __restrict__ part) {
+  csr_step_wg<T, PATTERN, ZMODE, HAS_PREV, MAXNZ, OFF32>(rowptr, col, val, d, nnz, vk, vm, ca,
+                                                         cb, src, rows_per_group, ngroups, part,
+                                                         blockIdx.x);
+}
+
+// ---- batches of probe blocks over many operators -----------------------------
+// One launch covers step s of every block in a table (blocks sorted by their
+// number of steps, so the blocks still running at step s are a prefix).  Each
+// block's workgroups are a contiguous, 8-aligned range of the grid; a
+// workgroup finds its block by binary search over the ranges' starts.
+__device__ __forceinline__ int find_block(const BatchBlock* __restrict__ tab, int n, int64_t bid) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].group_base <= bid) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ>
+__global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
+    const BatchBlock* __restrict__ tab, int nblocks, int s) {
+  const int bi = __builtin_amdgcn_readfirstlane(find_block(tab, nblocks, blockIdx.x));
+  const BatchBlock& B = tab[bi];
+  const int bid = (int)(blockIdx.x - B.group_base);
+  const float* vk = (s - 1) & 1 ? B.v1 : B.v0;
+  float* vm = s & 1 ? B.v1 : B.v0;
+  const float ca = (float)(HAS_PREV ? 2.0 * B.alpha : B.alpha);
+  const float cb = (float)(HAS_PREV ? 2.0 * B.beta : B.beta);
+  csr_step_wg<float, PATTERN, ZMODE, HAS_PREV, MAXNZ, true>(
+      B.rowptr, B.col, B.val, B.d, B.nnz, vk, vm, ca, cb, B.src, B.rows_per_group, B.ngroups,
+      B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+}
+
+__global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
+    const BatchBlock* __restrict__ tab, int nblocks) {
+  const int bi = __builtin_amdgcn_readfirstlane(find_block(tab, nblocks, blockIdx.x));
+  const BatchBlock& B = tab[bi];
+  const int bid = (int)(blockIdx.x - B.group_base);
+  probe_init_wg<float>(B.v0, B.d, B.src, B.rows_per_group, B.ngroups, B.part, bid);
+}
+
 template <typename T, bool PATTERN, int ZMODE, int MAXNZ, bool OFF32>
 hipError_t launch_step_t(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, double* part) {
@@ -406,6 +461,32 @@ hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
                            double* part) {
   return launch_step_any<T>(s, op, vk, vm, ca, cb, has_prev, zmode, src, plan, part);
+}
+
+hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
+                                     int64_t total_groups) {
+  probe_init_batched_kernel<<<(unsigned)total_groups, kThreads, 0, s>>>(tab, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
+                                   int64_t total_groups, int step, bool pattern, int maxnz,
+                                   int zmode) {
+  const bool hp = step > 1;
+  const unsigned grid = (unsigned)total_groups;
+#define MLCT_BATCH(P, Z, H, M) csr_step_batched_kernel<P, Z, H, M><<<grid, kThreads, 0, s>>>(tab, nblocks, step)
+#define MLCT_BATCH_M(P, Z, H) \
+  if (maxnz <= 4) MLCT_BATCH(P, Z, H, 4); else if (maxnz <= 5) MLCT_BATCH(P, Z, H, 5); else MLCT_BATCH(P, Z, H, 8)
+#define MLCT_BATCH_H(P, Z) \
+  if (hp) { MLCT_BATCH_M(P, Z, true); } else { MLCT_BATCH_M(P, Z, false); }
+#define MLCT_BATCH_Z(P) \
+  if (zmode == 0) { MLCT_BATCH_H(P, 0); } else { MLCT_BATCH_H(P, 1); }
+  if (pattern) { MLCT_BATCH_Z(true); } else { MLCT_BATCH_Z(false); }
+#undef MLCT_BATCH_Z
+#undef MLCT_BATCH_H
+#undef MLCT_BATCH_M
+#undef MLCT_BATCH
+  return hipGetLastError();
 }
 
 template hipError_t launch_probe_init<float>(hipStream_t, float*, int64_t, ProbeSrc,

@@ -430,3 +430,42 @@ def mlct_mlp_grad(ctx: Context, mlp: Mlp, X, y):
     _check(ctx, _mlp_lib().mlct_mlp_grad(ctx.handle, mlp.handle, X.ctypes.data, y.ctypes.data,
                                          X.shape[0], g.ctypes.data, C.byref(loss)))
     return g, loss.value
+
+
+# ---- batched estimates --------------------------------------------------------
+class mlct_batch_item(C.Structure):
+    _fields_ = [("op", C.c_void_p), ("f", mlct_func), ("a", C.c_double), ("b", C.c_double),
+                ("levels", mlct_levels), ("seed", C.c_uint64)]
+
+
+def mlct_estimate_batch(ctx: Context, items, prec: int = MLCT_FP32, mode: int = MLCT_DOUBLING):
+    """items: list of dicts with keys op, kind, a, b, degrees, m, seed (power
+    optional).  Returns one result dict per item."""
+    h = lib()
+    if not getattr(h, "_batch_sig", False):
+        h.mlct_estimate_batch.argtypes = [C.c_void_p, C.c_int32, C.POINTER(mlct_batch_item),
+                                          C.c_int32, C.c_int32, C.POINTER(mlct_result)]
+        h.mlct_estimate_batch.restype = C.c_int
+        h._batch_sig = True
+    n = len(items)
+    arr = (mlct_batch_item * n)()
+    keep = []
+    for i, it in enumerate(items):
+        L = len(it["degrees"])
+        deg = (C.c_int32 * L)(*[int(x) for x in it["degrees"]])
+        mm = (C.c_int64 * L)(*[int(x) for x in it["m"]])
+        keep += [deg, mm]
+        arr[i] = mlct_batch_item(it["op"].handle, mlct_func(it["kind"], it.get("power", 1.0)),
+                                 it["a"], it["b"], mlct_levels(L, deg, mm),
+                                 it["seed"] & ((1 << 64) - 1))
+    outs = (mlct_result * n)()
+    _check(ctx, h.mlct_estimate_batch(ctx.handle, n, arr, prec, mode, outs))
+    res = []
+    for i, it in enumerate(items):
+        r = outs[i]
+        L = len(it["degrees"])
+        res.append({"estimate": r.estimate, "value": r.value, "log_scale": r.log_scale,
+                    "est_var": r.est_var, "level_mean": np.array(r.level_mean[:L]),
+                    "level_var": np.array(r.level_var[:L]), "matvecs": r.matvecs,
+                    "probe_degrees": r.probe_degrees, "flags": r.flags})
+    return res

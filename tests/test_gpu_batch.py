@@ -1,0 +1,96 @@
+"""Batched estimates: every item of a batch must give exactly what the
+single-operator call gives (same kernels, same data, same reduction order),
+and that in turn matches the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import cheb, estimator
+from paper_2103_10516_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2103_10516_amd import mlct
+
+    assert torch.cuda.is_available()
+    c = mlct.mlct_create(0)
+    yield c
+    c.close()
+
+
+def _op(ctx, g):
+    import torch
+
+    from paper_2103_10516_amd import mlct
+
+    vl = None if g.val is None else torch.from_numpy(g.val).cuda()
+    return mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.col).cuda(), vl)
+
+
+@pytest.mark.parametrize("mode", ["doubling", "direct"])
+def test_batch_equals_single_calls(ctx, mode):
+    from paper_2103_10516_amd import mlct
+
+    M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    items = []
+    graphs = []
+    for i, n in enumerate([7, 12, 20, 33]):
+        g = wl.laplacian_3d(n) if i % 2 else wl.laplacian_2d(n * 3)
+        graphs.append(g)
+        items.append(dict(op=_op(ctx, g), kind=mlct.MLCT_LOG, a=0.01, b=12.01 if i % 2 else 8.01,
+                          degrees=[6, 20, 41][: 1 + i % 3] if i != 3 else [5, 17],
+                          m=[100, 64, 3][: 1 + i % 3] if i != 3 else [130, 70], seed=50 + i))
+    for i, d in enumerate([300, 1000, 2500]):
+        g = wl.chung_lu(d, seed=20 + i)
+        graphs.append(g)
+        lam = np.linalg.eigvalsh(g.to_dense())
+        items.append(dict(op=_op(ctx, g), kind=mlct.MLCT_EXP, a=lam.min() - 1, b=lam.max() + 1,
+                          degrees=[10, 30], m=[64 + 7 * i, 20], seed=90 + i))
+    res = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, M)
+    for it, r, g in zip(items, res, graphs):
+        one = mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"],
+                                 it["m"], it["seed"], mlct.MLCT_FP32, M)
+        assert r["value"] == one["value"]
+        assert np.array_equal(r["level_var"], one["level_var"])
+        assert r["matvecs"] == one["matvecs"]
+        o = estimator.estimate(g.to_scipy(), g.d, it["kind"], it["a"], it["b"], it["degrees"],
+                               it["m"], it["seed"], doubling=(mode == "doubling"))
+        assert r["value"] == pytest.approx(o.value, rel=2e-4, abs=1e-6 * g.d)
+
+
+def test_graph_batch_full_sizes(ctx):
+    """The 64-graph batch: Chung-Lu graphs with d_i = round(2048 * 32^(i/63)),
+    Estrada index with Lanczos intervals, levels 10/30/60, 1024 probes each
+    (here 256 per graph to keep the test short), one batched call vs 64
+    single calls."""
+    from paper_2103_10516_amd import mlct
+
+    sizes = wl.chung_lu_batch_sizes()
+    assert sizes[0] == 2048 and sizes[-1] == 65536
+    items = []
+    for i, d in enumerate(sizes):
+        g = wl.chung_lu(d, seed=wl.SEED_BASE + 4 + i)
+        op = _op(ctx, g)
+        a, b = mlct.mlct_bounds(ctx, op, 64, 7 + i, 0.01)
+        items.append(dict(op=op, kind=mlct.MLCT_EXP, a=a, b=b, degrees=[10, 30, 60],
+                          m=[192, 48, 16], seed=300 + i))
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    single = [mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"],
+                                 it["m"], it["seed"], mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
+              for it in items]
+    t_single = time.perf_counter() - t0
+    print(f"64-graph batch: {t_batch * 1e3:.1f} ms batched vs {t_single * 1e3:.1f} ms one by one")
+    for r, o in zip(res, single):
+        assert r["value"] == o["value"]
