@@ -243,6 +243,16 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
                           const mlct_levels* levels, uint64_t seed, int32_t prec,
                           int32_t mode, mlct_result* out);
 
+/* Autotuner: times the candidate launch shapes of the recurrence for this
+ * operator on the device and keeps the fastest in the operator (CSR: the cap
+ * on workgroups per step, 512 / 1024 / 2048 / 4096, FP32, 64 probes;
+ * dense: 32 x 32 or 128 x 128 tiles in arithmetic ``prec`` at block width
+ * B_max).  With a cache file given to mlct_create the decision is written
+ * there, keyed by the operator's shape, and operators of the same shape pick
+ * it up when they are created.  choice_out (may be NULL): the value kept. */
+mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t prec,
+                          int32_t* choice_out);
+
 /* Many estimates in shared launches: every (item, level, block of 64
  * probes) of all items advances one recurrence step per launch, so the
  * number of launches is the largest step count, not the sum over items.

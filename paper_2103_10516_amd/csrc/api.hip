@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -128,6 +130,55 @@ mlct_status sync_stream(mlct_ctx* ctx) {
   return MLCT_OK;
 }
 
+// ---- autotune cache (plain text, one decision per line) -------------------
+std::string tune_key(const mlct_op* op, int prec, int64_t bpad) {
+  char buf[160];
+  if (op->kind == OP_CSR)
+    snprintf(buf, sizeof buf, "csr d=%lld nnz=%lld maxrow=%d pattern=%d", (long long)op->d,
+             (long long)op->nnz, op->max_row_nnz, op->val == nullptr ? 1 : 0);
+  else
+    snprintf(buf, sizeof buf, "dense d=%lld prec=%d bpad=%lld", (long long)op->d, prec,
+             (long long)bpad);
+  return buf;
+}
+
+int tune_lookup(const mlct_ctx* ctx, const std::string& key) {
+  for (const std::string& l : ctx->tune_lines)
+    if (l.compare(0, key.size(), key) == 0 && l.size() > key.size() + 3 &&
+        l.compare(key.size(), 3, " = ") == 0)
+      return std::atoi(l.c_str() + key.size() + 3);
+  return -1;
+}
+
+void tune_store(mlct_ctx* ctx, const std::string& key, int value) {
+  const std::string line = key + " = " + std::to_string(value);
+  bool found = false;
+  for (std::string& l : ctx->tune_lines)
+    if (l.compare(0, key.size() + 3, key + " = ") == 0) {
+      l = line;
+      found = true;
+    }
+  if (!found) ctx->tune_lines.push_back(line);
+  if (ctx->tune_path.empty()) return;
+  FILE* fh = std::fopen(ctx->tune_path.c_str(), "w");
+  if (!fh) return;
+  std::fprintf(fh, "# mlct autotune cache (gfx950)\n");
+  for (const std::string& l : ctx->tune_lines) std::fprintf(fh, "%s\n", l.c_str());
+  std::fclose(fh);
+}
+
+void tune_load(mlct_ctx* ctx) {
+  FILE* fh = std::fopen(ctx->tune_path.c_str(), "r");
+  if (!fh) return;
+  char buf[256];
+  while (std::fgets(buf, sizeof buf, fh)) {
+    std::string l(buf);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    if (!l.empty() && l[0] != '#') ctx->tune_lines.push_back(l);
+  }
+  std::fclose(fh);
+}
+
 mlct_status set_device(mlct_ctx* ctx) {
   HIPCHK(ctx, hipSetDevice(ctx->device));
   return MLCT_OK;
@@ -189,7 +240,7 @@ template <typename T>
 mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                           int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
-  const CsrStepPlan plan = plan_csr(op->d);
+  const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
   const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(T);
   const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;  // doubles per step
   void *v0, *v1, *part, *dots;
@@ -275,7 +326,7 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
   void* tmp;
   if (op->kind == OP_CSR) {
-    const CsrStepPlan plan = plan_csr(op->d);
+    const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
     const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
     CHECK(ws_get(ctx, WS_V0, (size_t)op->d * kBlockProbes * tsz, &tmp));
     CHECK(ws_get(ctx, WS_V1, (size_t)op->d * kBlockProbes * tsz, &tmp));
@@ -298,7 +349,7 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
                             int64_t ldmu) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
   const int64_t d = op->d, bpad = dense_bpad(src.active);
-  const DenseTile t = dense_tile(prec, d, bpad);
+  const DenseTile t = dense_tile(prec, d, bpad, op->tuned_dense);
   const int64_t ntiles = (d + t.bn - 1) / t.bn;
   const void *a0, *a1;
   int64_t lda;
@@ -333,6 +384,7 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
     a.zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
     a.src = src;
     a.part = P + pstep * (k - 1);
+    a.tile_force = op->tuned_dense;
     LaunchTimer tm(ctx, MLCT_KERNEL_DENSE_STEP);
     HIPCHK(ctx, launch_dense_step(s, prec, a));
     tm.done();
@@ -388,7 +440,6 @@ extern "C" {
 
 mlct_status mlct_create(int device, void* hip_stream, const char* tune_cache_path,
                         mlct_ctx** out) {
-  (void)tune_cache_path;
   if (!out) return MLCT_EINVAL;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
@@ -400,6 +451,10 @@ mlct_status mlct_create(int device, void* hip_stream, const char* tune_cache_pat
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->slots.resize(WS_NSLOTS);
+  if (tune_cache_path && *tune_cache_path) {
+    ctx->tune_path = tune_cache_path;
+    tune_load(ctx);
+  }
   if (hipSetDevice(device) != hipSuccess) {
     delete ctx;
     return MLCT_EDEVICE;
@@ -491,6 +546,7 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   op->val = dtype == MLCT_DT_F32 ? val_dev : nullptr;
   op->dtype = dtype;
   op->max_row_nnz = hf[1];
+  op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
   *out = op;
   return MLCT_OK;
 }
@@ -794,7 +850,7 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
     return fail(ctx, MLCT_EINVAL, "triangle counting needs a 0/1 pattern CSR operator");
   if (m < 1) return fail(ctx, MLCT_EINVAL, "need m >= 1 probes");
   CHECK(set_device(ctx));
-  const CsrStepPlan plan = plan_csr(op->d);
+  const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
   const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(int32_t);
   void *z, *y, *part, *w, *res;
   CHECK(ws_get(ctx, WS_V0, vbytes, &z));
@@ -1252,7 +1308,7 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   size_t bytes = align8(nb * sizeof(BatchBlock)) + 256;
   for (const HostBlock& hb : blocks) {
     const int64_t d = items[hb.item].op->d;
-    const CsrStepPlan plan = plan_csr(d);
+    const CsrStepPlan plan = plan_csr(d, items[hb.item].op->tuned_groups);
     bytes += 2 * align8((size_t)d * 64 * 4);
     bytes += align8((size_t)(hb.steps + 1) * 2 * plan.ngroups * 64 * 8);
     bytes += align8((size_t)(hb.steps + 1) * 2 * 64 * 8);
@@ -1273,7 +1329,7 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   for (size_t bi = 0; bi < nb; ++bi) {
     const HostBlock& hb = blocks[bi];
     const mlct_op* op = items[hb.item].op;
-    const CsrStepPlan plan = plan_csr(op->d);
+    const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
     BatchBlock& B = tab[bi];
     B.rowptr = op->rowptr;
     B.col = op->col;
@@ -1383,5 +1439,66 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     outs[i] = h[i];
   }
   if (escaped) return fail(ctx, MLCT_ESPECTRUM, "an item's spectrum is not inside its [a, b]");
+  return MLCT_OK;
+}
+
+extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t prec,
+                                     int32_t* choice_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op) return fail(ctx, MLCT_EINVAL, "op is required");
+  CHECK(set_device(ctx));
+  const bool csr = op->kind == OP_CSR;
+  if (csr) prec = MLCT_FP32;
+  CHECK(check_mode_prec(ctx, MLCT_DIRECT, prec));
+  const int64_t block = csr ? kBlockProbes : std::max<int64_t>(32, std::min<int64_t>(B_max, kDenseMaxBlock));
+  const int degree = 8;
+  std::vector<int> cands;
+  if (csr) cands = {512, 1024, 2048, 4096};
+  else cands = {0, 1};
+  // workspace for the largest candidate
+  const int saved_g = op->tuned_groups, saved_t = op->tuned_dense;
+  op->tuned_groups = 4096;
+  void* mu;
+  CHECK(ws_get(ctx, WS_MU, (size_t)block * (degree + 1) * 8, &mu));
+  CHECK(reserve_block_ws(ctx, op, prec, MLCT_DIRECT, degree, block));
+  op->tuned_groups = saved_g;
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  ProbeSrc src{0x5EEDull, 0, nullptr, 0, (int32_t)block};
+  float best = 1e30f;
+  int choice = csr ? 2048 : -1;
+  for (int c : cands) {
+    if (!csr && c == 1 && dense_bpad(block) % 128) continue;  // large tiles need bpad % 128 == 0
+    if (csr) op->tuned_groups = c;
+    else op->tuned_dense = c;
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+      CHECK(run_block(ctx, op, 0.1, 0.0, degree, MLCT_DIRECT, prec, src, static_cast<double*>(mu),
+                      degree + 1));
+      HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+      HIPCHK(ctx, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tmin = std::min(tmin, ms);
+    }
+    if (tmin < best) {
+      best = tmin;
+      choice = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (csr) {
+    op->tuned_groups = choice;
+    op->tuned_dense = saved_t;
+  } else {
+    op->tuned_dense = choice;
+    op->tuned_groups = saved_g;
+  }
+  tune_store(ctx, tune_key(op, prec, csr ? 64 : dense_bpad(block)), choice);
+  if (choice_out) *choice_out = choice;
   return MLCT_OK;
 }

@@ -44,6 +44,8 @@ struct mlct_ctx {
   std::vector<mlct::DevBuf> slots;  // grow-only named workspace slots
   void* host_pinned = nullptr;      // staging for small D2H results
   size_t host_pinned_bytes = 0;
+  std::string tune_path;            // autotune cache file ("" = none)
+  std::vector<std::string> tune_lines;  // cached decisions, one per operator shape
 };
 
 // An operator refers to its context; destroy operators before the context.
@@ -58,6 +60,8 @@ struct mlct_op {
   const int32_t* col = nullptr;
   const void* val = nullptr;  // nullptr = pattern
   int max_row_nnz = 0;
+  int tuned_groups = 0;      // CSR: workgroup cap chosen by mlct_autotune (0 = default)
+  int tuned_dense = -1;      // dense: 1 = 128x128 tiles, 0 = 32x32 tiles, -1 = default rule
   // dense / Gram (row-major d x d)
   const void* A = nullptr;
   int64_t lda = 0;
@@ -140,7 +144,10 @@ struct CsrStepPlan {
   int ngroups;        // workgroups per step (= partial-sum slots)
   int rows_per_group; // contiguous rows per workgroup
 };
-CsrStepPlan plan_csr(int64_t d);
+// Workgroups per step: one per 256 rows, a multiple of 8 (one band per XCD),
+// at most max_groups (0 = the default cap of 2048; the autotuner's choice
+// otherwise).
+CsrStepPlan plan_csr(int64_t d, int max_groups = 0);
 template <typename T>
 hipError_t launch_probe_init(hipStream_t s, T* v0, int64_t d, ProbeSrc src,
                              const CsrStepPlan& plan, double* part0);
@@ -195,12 +202,14 @@ struct DenseStepArgs {
   int zmode;
   ProbeSrc src;
   double* part;  // [2][ntiles][bpad] for this step
+  int tile_force;  // see dense_tile
 };
 struct DenseTile {
   bool large;
   int bm, bn;
 };
-DenseTile dense_tile(int prec, int64_t d, int64_t bpad);
+// force: -1 = default rule, 0 = 32 x 32 tiles, 1 = 128 x 128 tiles (when valid)
+DenseTile dense_tile(int prec, int64_t d, int64_t bpad, int force = -1);
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a);
 hipError_t launch_dense_probe_init(hipStream_t s, int prec, void* v0, int64_t d, int64_t bpad,
                                    ProbeSrc src, double* dots0);

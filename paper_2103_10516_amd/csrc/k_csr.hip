@@ -437,10 +437,11 @@ hipError_t launch_step_any(hipStream_t s, const mlct_op* op, const T* vk, T* vm,
 
 }  // namespace
 
-CsrStepPlan plan_csr(int64_t d) {
+CsrStepPlan plan_csr(int64_t d, int max_groups) {
+  const int64_t cap = max_groups > 0 ? max_groups : 2048;
   int64_t g = (d + 255) / 256;
   g = (g + 7) / 8 * 8;
-  if (g > 2048) g = 2048;
+  if (g > cap) g = cap;
   if (g < 8) g = 8;
   CsrStepPlan p;
   p.ngroups = (int)g;

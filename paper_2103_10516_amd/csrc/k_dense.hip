@@ -399,12 +399,12 @@ hipError_t launch_dense_cfg(hipStream_t s, const DenseStepArgs& a) {
 
 }  // namespace
 
-DenseTile dense_tile(int prec, int64_t d, int64_t bpad) {
+DenseTile dense_tile(int prec, int64_t d, int64_t bpad, int force) {
   // Large tiles (128 x 128) once they still give a few hundred workgroups,
   // else 32 x 32 tiles (small d is latency-bound; more workgroups win).
   const int64_t big = (bpad / 128) * ((d + 127) / 128);
   DenseTile t;
-  t.large = (bpad % 128 == 0) && big >= 256;
+  t.large = (bpad % 128 == 0) && (force >= 0 ? force == 1 : big >= 256);
   t.bm = t.large ? 128 : 32;
   t.bn = t.large ? 128 : 32;
   (void)prec;
@@ -412,7 +412,7 @@ DenseTile dense_tile(int prec, int64_t d, int64_t bpad) {
 }
 
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a) {
-  const DenseTile t = dense_tile(prec, a.d, a.bpad);
+  const DenseTile t = dense_tile(prec, a.d, a.bpad, a.tile_force);
   if (prec == MLCT_FP64)
     return t.large ? launch_dense_cfg<0, 2, 2, 4, 4, 16>(s, a) : launch_dense_cfg<0, 1, 1, 2, 2, 16>(s, a);
   if (prec == MLCT_FP32)

@@ -123,7 +123,7 @@ def _ptr(t) -> int | None:
 class Context:
     """Owns an mlct_ctx bound to a device and a HIP stream."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, tune_cache=None):
         import torch
 
         if stream is None:
@@ -131,7 +131,9 @@ class Context:
         self.device = device
         self.stream = stream
         h = C.c_void_p()
-        st = lib().mlct_create(device, C.c_void_p(stream.cuda_stream), None, C.byref(h))
+        st = lib().mlct_create(device, C.c_void_p(stream.cuda_stream),
+                               None if tune_cache is None else str(tune_cache).encode(),
+                               C.byref(h))
         if st != MLCT_OK:
             raise MlctError(st, "mlct_create failed")
         self.handle = h
@@ -172,8 +174,8 @@ class Op:
 
 
 # ---- entry points, same names as the C ABI --------------------------------
-def mlct_create(device: int = 0, stream=None) -> Context:
-    return Context(device, stream)
+def mlct_create(device: int = 0, stream=None, tune_cache=None) -> Context:
+    return Context(device, stream, tune_cache)
 
 
 def mlct_timing(ctx: Context, enable: bool):
@@ -469,3 +471,12 @@ def mlct_estimate_batch(ctx: Context, items, prec: int = MLCT_FP32, mode: int = 
                     "level_var": np.array(r.level_var[:L]), "matvecs": r.matvecs,
                     "probe_degrees": r.probe_degrees, "flags": r.flags})
     return res
+
+
+def mlct_autotune(ctx: Context, op: Op, B_max: int = 64, prec: int = MLCT_FP32) -> int:
+    h = lib()
+    h.mlct_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    h.mlct_autotune.restype = C.c_int
+    c = C.c_int32()
+    _check(ctx, h.mlct_autotune(ctx.handle, op.handle, B_max, prec, C.byref(c)))
+    return c.value
