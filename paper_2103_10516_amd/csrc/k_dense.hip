@@ -101,34 +101,76 @@ __global__ __launch_bounds__(64 * WM * WN) void dense_step_kernel(
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = AccT{};
 
-  for (int64_t k0 = 0; k0 < d; k0 += BK) {
-    // ---- global -> LDS ------------------------------------------------------
-    for (int e = tid; e < BM * BK; e += NT) {
-      const int r = e / BK, c = e % BK;
+  // ---- k loop: 16-byte global loads of the next tile into registers while
+  // the current tile is in LDS and on the matrix cores ---------------------
+  constexpr int GV = 16 / sizeof(VT);                     // V elements per load
+  constexpr int GA = PREC == 2 ? 8 : 16 / (int)sizeof(MT);  // A elements per load
+  constexpr int NV = BM * BK / GV / NT;                   // V loads per thread
+  constexpr int NA = BN * BK / GA / NT;                   // A loads per thread (per part)
+  static_assert(NV * GV * NT == BM * BK && NA * GA * NT == BN * BK, "tile/thread mismatch");
+  typedef VT vvec __attribute__((ext_vector_type(GV)));
+  typedef MT avec __attribute__((ext_vector_type(GA)));
+  vvec rv[NV];
+  avec ra[NSPLIT][NA];
+  const bool dvec_ok = (d % GV == 0) && (lda % GA == 0);
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int e = (tid + u * NT) * GV, r = e / BK, c = e % BK;
       const int64_t k = k0 + c;
-      const VT x = k < d ? vk[(m0 + r) * ldv + k] : VT(0);
-      if (PREC == 2) {
-        __bf16 hi, lo;
-        split_bf16((float)x, hi, lo);
-        sV[0][r][c] = hi;
-        sV[NSPLIT - 1][r][c] = lo;
+      const VT* src = vk + (m0 + r) * ldv + k;
+      if (dvec_ok && k + GV <= d) {
+        rv[u] = *reinterpret_cast<const vvec*>(src);
       } else {
-        sV[0][r][c] = (MT)x;
+#pragma unroll
+        for (int q = 0; q < GV; ++q) rv[u][q] = (k + q < d) ? src[q] : VT(0);
       }
     }
-    for (int e = tid; e < BN * BK; e += NT) {
-      const int r = e / BK, c = e % BK;
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = (tid + u * NT) * GA, r = e / BK, c = e % BK;
       const int64_t k = k0 + c, n = n0 + r;
-      const bool ok = k < d && n < d;
-      const int64_t off = ok ? n * lda + k : 0;
-      if (PREC == 2) {
-        sA[0][r][c] = ok ? static_cast<const __bf16*>(A0)[off] : (__bf16)0.f;
-        sA[NSPLIT - 1][r][c] = ok ? static_cast<const __bf16*>(A1)[off] : (__bf16)0.f;
-      } else {
-        sA[0][r][c] = ok ? static_cast<const MT*>(A0)[off] : MT(0);
+#pragma unroll
+      for (int h = 0; h < NSPLIT; ++h) {
+        const MT* src = static_cast<const MT*>(h ? A1 : A0) + (n < d ? n : 0) * lda + k;
+        if (n < d && dvec_ok && k + GA <= d) {
+          ra[h][u] = *reinterpret_cast<const avec*>(src);
+        } else {
+#pragma unroll
+          for (int q = 0; q < GA; ++q) ra[h][u][q] = (n < d && k + q < d) ? src[q] : MT(0.f);
+        }
       }
     }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int e = (tid + u * NT) * GV, r = e / BK, c = e % BK;
+      if constexpr (PREC == 2) {
+#pragma unroll
+        for (int q = 0; q < GV; ++q) {
+          __bf16 hi, lo;
+          split_bf16((float)rv[u][q], hi, lo);
+          sV[0][r][c + q] = hi;
+          sV[NSPLIT - 1][r][c + q] = lo;
+        }
+      } else {
+        *reinterpret_cast<vvec*>(&sV[0][r][c]) = rv[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = (tid + u * NT) * GA, r = e / BK, c = e % BK;
+#pragma unroll
+      for (int h = 0; h < NSPLIT; ++h) *reinterpret_cast<avec*>(&sA[h][r][c]) = ra[h][u];
+    }
+  };
+
+  fetch(0);
+  for (int64_t k0 = 0; k0 < d; k0 += BK) {
+    stash();
     __syncthreads();
+    if (k0 + BK < d) fetch(k0 + BK);
     // ---- MFMA ---------------------------------------------------------------
 #pragma unroll
     for (int kk = 0; kk < BK; kk += P::KM) {
