@@ -20,9 +20,13 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
+import traceback
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -86,6 +90,205 @@ def cpu_baseline(g, a, b, seed):
                       f"{len(os.sched_getaffinity(0))} cores available"}
 
 
+
+BF16_PEAK_TFS = 2500.0   # MI355X dense bf16 MFMA
+FP32_PEAK_TFS = 157.3    # MI355X FP32 MFMA
+
+
+def _sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def extra_nuclear_dense(mlct, dev):
+    """Nuclear norm: X 8192 x 4096 (sigma_i = i^-0.7, FP32), A = X^T X formed on
+    the device, tr sqrt(A) on [1e-6, 1] with levels 16/64/256 and 3712/320/64
+    probes (4096 total), BF16x3 MFMA, symmetric moment form.  One warm-up and
+    one timed estimate."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    X, sig = wl.nuclear_x()
+    Xd = torch.from_numpy(X).to(dev)
+    ctx = mlct.mlct_create(0)
+    mlct.mlct_timing(ctx, True)
+    op = mlct.mlct_op_gram(ctx, Xd)
+    _, gram_ms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_GRAM)
+    degrees, m = [16, 64, 256], [3712, 320, 64]
+    est = lambda seed: mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, 1e-6, 1.0, degrees, m, seed,
+                                          mlct.MLCT_BF16X3, mlct.MLCT_DOUBLING)
+    est(1)
+    mlct.mlct_timing(ctx, True)
+    _sync()
+    t0 = time.perf_counter()
+    r = est(2)
+    _sync()
+    dt = time.perf_counter() - t0
+    n, ms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_DENSE_STEP)
+    d = 4096
+    steps = {16: 8, 64: 32, 256: 128}
+    flops = sum(2.0 * d * d * mk * steps[lk] for lk, mk in zip(degrees, m))
+    ach = flops / (ms / 1e3) / 1e12
+    out = {"workload": "nuclear norm, X 8192x4096 sigma_i=i^-0.7 (FP32), A=X^T X on device, "
+                       "[1e-6,1], levels 16/64/256, probes 3712/320/64, bf16x3, doubling",
+           "probe_degree_per_s": r["probe_degrees"] / dt, "ms_per_estimate": dt * 1e3,
+           "estimate": r["estimate"], "exact_sum_sigma": float(np.sum(sig)),
+           "gram_ms": gram_ms, "gram_tflops": 8192 * 4096.0 * 4096 / (gram_ms / 1e3) / 1e12,
+           "roofline": {"bound": "mfma", "kernel": "dense_step_kernel<bf16x3>",
+                        "achieved": ach, "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": ach / BF16_PEAK_TFS,
+                        "issued_bf16_frac": 3 * ach / BF16_PEAK_TFS,
+                        "note": "achieved = algorithmic 2 d^2 flops per probe-matvec; bf16x3 "
+                                "issues three bf16 products per algorithmic one",
+                        "launches": n, "avg_launch_ms": ms / max(n, 1)}}
+    op.close()
+    ctx.close()
+    return out
+
+
+def extra_triangles(mlct, dev):
+    """Triangle count of the Chung-Lu graph d = 10^6 (avg degree 16, exponent
+    2.5), 1024 probes, exact int32/int64 path with control variates."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    g = wl.chung_lu(1_000_000, seed=wl.SEED_BASE + 4)
+    ctx = mlct.mlct_create(0)
+    op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.col).to(dev))
+    mlct.mlct_triangles(ctx, op, 64, 1, want_w=False)
+    mlct.mlct_timing(ctx, True)
+    _sync()
+    t0 = time.perf_counter()
+    res, _ = mlct.mlct_triangles(ctx, op, 1024, 2, want_w=False)
+    _sync()
+    dt = time.perf_counter() - t0
+    n, ms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_TRI_STEP)
+    by = 4 * g.nnz + 4 * (g.d + 1) + 8 * g.d * 64  # matrix, read block, write/reuse
+    ach = by / (ms / n / 1e3) / 1e9
+    out = {"workload": f"triangles, Chung-Lu d=1e6 nnz={g.nnz}, 1024 probes, int32/int64",
+           "probe_matvecs_per_s": 2 * 1024 / dt, "ms": dt * 1e3, "estimate": res["estimate"],
+           "estimate_cv": res["estimate_cv"],
+           "roofline": {"bound": "hbm", "kernel": "tri_step_kernel", "achieved": ach,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                        "algorithmic_bytes_per_launch": by, "avg_launch_ms": ms / n,
+                        "launches": n}}
+    op.close()
+    ctx.close()
+    return out
+
+
+def extra_graph_batch(mlct, dev):
+    """Estrada index of 64 Chung-Lu graphs d_i = round(2048 * 32^(i/63)),
+    Lanczos intervals, levels 10/30/60 with 768/192/64 probes each, in one
+    batched call vs one call per graph."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    ctx = mlct.mlct_create(0)
+    items = []
+    for i, d in enumerate(wl.chung_lu_batch_sizes()):
+        g = wl.chung_lu(d, seed=wl.SEED_BASE + 4 + i)
+        op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev),
+                              torch.from_numpy(g.col).to(dev))
+        a, b = mlct.mlct_bounds(ctx, op, 64, 7 + i, 0.01)
+        items.append(dict(op=op, kind=mlct.MLCT_EXP, a=a, b=b, degrees=[10, 30, 60],
+                          m=[768, 192, 64], seed=300 + i))
+    mlct.mlct_estimate_batch(ctx, items)
+    _sync()
+    t0 = time.perf_counter()
+    res = mlct.mlct_estimate_batch(ctx, items)
+    _sync()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for it in items:
+        mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"], it["m"],
+                           it["seed"], mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
+    _sync()
+    ts = time.perf_counter() - t0
+    pd = sum(r["probe_degrees"] for r in res)
+    out = {"workload": "Estrada index, 64 Chung-Lu graphs d=2048..65536, levels 10/30/60, "
+                       "probes 768/192/64 per graph",
+           "batched_ms": tb * 1e3, "one_by_one_ms": ts * 1e3, "speedup": ts / tb,
+           "probe_degree_per_s": pd / tb}
+    for it in items:
+        it["op"].close()
+    ctx.close()
+    return out
+
+
+def extra_time_to_eps(mlct, dev):
+    """Time to a relative standard error eps of tr p_n(A_hat) for the plain
+    single-level estimator, 2-level MLMC (8 | 256) and MLMC with the learned
+    level, on the 3D Laplacian 64^3 + 0.01 I, f = log, n = 256.  Sample sizes
+    from the measured (pilot) variances by the optimal allocation; the timed
+    part is the estimator call; pilot / training time is reported apart."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    n3 = 64
+    g = wl.laplacian_3d(n3)
+    ctx = mlct.mlct_create(0)
+    op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.col).to(dev),
+                          torch.from_numpy(g.val).to(dev))
+    a, b, n, nc = 0.01, 12.01, 256, 8
+    _sync()
+    t0 = time.perf_counter()
+    net = mlct.mlct_learned_fit(ctx, op, mlct.MLCT_LOG, a, b, n_fine=n, n_cheap=nc, m_pilot=2048,
+                                seed=5, epochs=1500)
+    _sync()
+    t_fit = time.perf_counter() - t0
+    info = mlct.mlct_mlp_info_get(net)
+    t0 = time.perf_counter()
+    pil = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, [nc, n], [512, 512], 6,
+                             mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
+    _sync()
+    t_pilot = time.perf_counter() - t0
+    T = abs(pil["value"])  # only sets the scale of the target variance
+    Cc, Cf = (nc + 1) // 2, (n + 1) // 2
+    rows = []
+    for eps in (1e-3, 1e-4, 1e-5):
+        tgt = (eps * T) ** 2
+        m_plain = max(2, math.ceil(info["var_q"] / tgt))
+        V = [pil["level_var"][0], pil["level_var"][1]]
+        s_ml = sum(math.sqrt(v * cc) for v, cc in zip(V, (Cc, Cf)))
+        m_ml = [max(2, math.ceil(s_ml * math.sqrt(v / cc) / tgt)) for v, cc in zip(V, (Cc, Cf))]
+        Vl = [info["var_g"], info["var_resid"]]
+        s_l = sum(math.sqrt(v * cc) for v, cc in zip(Vl, (Cc, Cf)))
+        m_l = [max(2, math.ceil(s_l * math.sqrt(v / cc) / tgt)) for v, cc in zip(Vl, (Cc, Cf))]
+
+        def timed(fn):
+            _sync()
+            t = time.perf_counter()
+            r = fn()
+            _sync()
+            return time.perf_counter() - t, r
+
+        tp, rp = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, [n], [m_plain], 11,
+                                                  mlct.MLCT_FP32, mlct.MLCT_DOUBLING))
+        tm, rm = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, [nc, n], m_ml, 12,
+                                                  mlct.MLCT_FP32, mlct.MLCT_DOUBLING))
+        tl, rl = timed(lambda: mlct.mlct_estimate_learned(ctx, op, net, m_l[0], m_l[1], 13))
+        rse = lambda r: math.sqrt(r["est_var"]) / T  # estimated relative standard error
+        rows.append({"eps": eps,
+                     "plain": {"m": m_plain, "s": tp, "rel_se": rse(rp), "value": rp["value"]},
+                     "mlmc": {"m": m_ml, "s": tm, "rel_se": rse(rm), "value": rm["value"]},
+                     "learned": {"m": m_l, "s": tl, "rel_se": rse(rl), "value": rl["value"]}})
+    out = {"workload": "3D Laplacian 64^3 + 0.01 I, log, n=256, cheap level 8, learned MLP "
+                       "9-64-64-1 trained on 2048 pilot probes",
+           "fit_s": t_fit, "pilot_s": t_pilot, "var_q": info["var_q"], "var_g": info["var_g"],
+           "var_resid": info["var_resid"], "mlmc_level_var": list(pil["level_var"]),
+           "rows": rows}
+    net.close()
+    op.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +296,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=2048, help="2D grid edge (default 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", default="dense,triangles,batch,time_to_eps",
+                    help="comma list of secondary measurements to add ('' for none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device copies of 1 GiB (a plain copy kernel of known "
                          "size, used to calibrate HBM byte counters)")
@@ -176,11 +381,23 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "avg_launch_ms": avg_s * 1e3, "launches": launches},
     }
+    op.close()
+    ctx.close()
+    extras = {"dense": extra_nuclear_dense, "triangles": extra_triangles,
+              "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps}
+    secondary = {}
+    for name in [e for e in args.extras.split(",") if e]:
+        print(f"# secondary measurement: {name}", file=sys.stderr, flush=True)
+        try:
+            secondary[name] = extras[name](mlct, dev)
+        except Exception as exc:  # a failed extra must not lose the headline number
+            traceback.print_exc()
+            secondary[name] = {"error": repr(exc)}
+    if secondary:
+        out["secondary"] = secondary
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, w["a"], w["b"], 99)
-    op.close()
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -246,8 +246,8 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
 /* Autotuner: times the candidate launch shapes of the recurrence for this
  * operator on the device and keeps the fastest in the operator (CSR: the cap
  * on workgroups per step, 512 / 1024 / 2048 / 4096, FP32, 64 probes;
- * dense: 32 x 32 or 128 x 128 tiles in arithmetic ``prec`` at block width
- * B_max).  With a cache file given to mlct_create the decision is written
+ * dense: 32 x 32, 64 x 64 or 128 x 128 tiles in arithmetic ``prec`` at
+ * block width B_max; kept as 0, 2 or 1).  With a cache file given to mlct_create the decision is written
  * there, keyed by the operator's shape, and operators of the same shape pick
  * it up when they are created.  choice_out (may be NULL): the value kept. */
 mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t prec,
@@ -311,6 +311,7 @@ typedef struct {
   double var_q;       /* variance of q on the held-out pilot probes        */
   double var_resid;   /* variance of q - g on the same probes              */
   double mean_resid;  /* mean of q - g on the same probes                  */
+  double var_g;       /* variance of g on the same probes                  */
   double ybar, ysd;   /* target standardisation (of q / mu_0)              */
   double final_loss;  /* training loss (standardised units) after training */
   int32_t fallback;   /* 1 if the learned level is not used                */

@@ -966,7 +966,7 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
                          m_pilot < kDenseMaxBlock ? m_pilot : kDenseMaxBlock));
   const size_t sbytes = align8(m_pilot * 8) + align8(ntrain * F * 4) + align8(ntrain * 4) +
                         align8((size_t)kMlpWaves * P * 4) + align8(kMlpWaves * 4) +
-                        align8((size_t)epochs * 4) + 64 + align8(nval * 8) + 64 + 256;
+                        align8((size_t)epochs * 4) + 64 + align8(nval * 8) + 128 + 256;
   CHECK(ws_get(ctx, WS_MLP, sbytes, &scratch));
   Carver cv{static_cast<char*>(scratch)};
   double* q = cv.take<double>(m_pilot);
@@ -977,7 +977,7 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
   float* loss_hist = cv.take<float>(epochs);
   double* stats = cv.take<double>(4);
   double* gval = cv.take<double>(nval > 0 ? nval : 1);
-  double* comb = cv.take<double>(4);
+  double* comb = cv.take<double>(8);
 
   mlct_mlp* m = new (std::nothrow) mlct_mlp();
   if (!m) return fail(ctx, MLCT_ENOMEM, "out of host memory");
@@ -1048,9 +1048,11 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
     const double* muv = static_cast<double*>(mu) + ntrain * ldmu;
     MLP_HIP(launch_mlp_infer(s, m->wbf16, F, muv, ldmu, nval, m->ybar, m->ysd, gval));
     MLP_HIP(launch_mlp_combine(s, q + ntrain, nval, q + ntrain, gval, nval, comb));
-    double hc[4];
+    MLP_HIP(launch_mlp_combine(s, gval, nval, gval, nullptr, 0, comb + 4));
+    double hc[8];
     MLP_HIP(hipMemcpyAsync(hc, comb, sizeof hc, hipMemcpyDeviceToHost, s));
     MLP_TRY(sync_stream(ctx));
+    m->var_g = hc[5];
     m->var_q = hc[1];
     m->var_resid = hc[3];
     m->mean_resid = hc[2];
@@ -1142,6 +1144,7 @@ mlct_status mlct_mlp_info_get(const mlct_mlp* m, mlct_mlp_info* out) {
   out->var_q = m->var_q;
   out->var_resid = m->var_resid;
   out->mean_resid = m->mean_resid;
+  out->var_g = m->var_g;
   out->ybar = m->ybar;
   out->ysd = m->ysd;
   out->final_loss = m->loss_hist.empty() ? NAN : m->loss_hist.back();
@@ -1455,7 +1458,7 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   const int degree = 8;
   std::vector<int> cands;
   if (csr) cands = {512, 1024, 2048, 4096};
-  else cands = {0, 1};
+  else cands = {0, 2, 1};
   // workspace for the largest candidate
   const int saved_g = op->tuned_groups, saved_t = op->tuned_dense;
   op->tuned_groups = 4096;
@@ -1470,7 +1473,8 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   float best = 1e30f;
   int choice = csr ? 2048 : -1;
   for (int c : cands) {
-    if (!csr && c == 1 && dense_bpad(block) % 128) continue;  // large tiles need bpad % 128 == 0
+    if (!csr && c == 1 && dense_bpad(block) % 128) continue;  // 128-tiles need bpad % 128 == 0
+    if (!csr && c == 2 && dense_bpad(block) % 64) continue;
     if (csr) op->tuned_groups = c;
     else op->tuned_dense = c;
     float tmin = 1e30f;

@@ -61,7 +61,7 @@ struct mlct_op {
   const void* val = nullptr;  // nullptr = pattern
   int max_row_nnz = 0;
   int tuned_groups = 0;      // CSR: workgroup cap chosen by mlct_autotune (0 = default)
-  int tuned_dense = -1;      // dense: 1 = 128x128 tiles, 0 = 32x32 tiles, -1 = default rule
+  int tuned_dense = -1;      // dense: 1 = 128x128, 2 = 64x64, 0 = 32x32 tiles, -1 = default rule
   // dense / Gram (row-major d x d)
   const void* A = nullptr;
   int64_t lda = 0;
@@ -88,7 +88,7 @@ struct mlct_mlp {
   void* wbf16 = nullptr;   // bf16 inference weights (device)
   double* coef = nullptr;  // c_0..c_{n_fine} (device)
   double ybar = 0.0, ysd = 1.0;
-  double var_q = 0.0, var_resid = 0.0, mean_resid = 0.0;
+  double var_q = 0.0, var_resid = 0.0, mean_resid = 0.0, var_g = 0.0;
   int fallback = 0;
   std::vector<float> loss_hist;
 };
@@ -208,7 +208,7 @@ struct DenseTile {
   bool large;
   int bm, bn;
 };
-// force: -1 = default rule, 0 = 32 x 32 tiles, 1 = 128 x 128 tiles (when valid)
+// force: -1 = default rule, 0 = 32 x 32, 1 = 128 x 128, 2 = 64 x 64 tiles (when valid)
 DenseTile dense_tile(int prec, int64_t d, int64_t bpad, int force = -1);
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a);
 hipError_t launch_dense_probe_init(hipStream_t s, int prec, void* v0, int64_t d, int64_t bpad,

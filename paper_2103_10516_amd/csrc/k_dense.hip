@@ -442,24 +442,40 @@ hipError_t launch_dense_cfg(hipStream_t s, const DenseStepArgs& a) {
 }  // namespace
 
 DenseTile dense_tile(int prec, int64_t d, int64_t bpad, int force) {
-  // Large tiles (128 x 128) once they still give a few hundred workgroups,
-  // else 32 x 32 tiles (small d is latency-bound; more workgroups win).
-  const int64_t big = (bpad / 128) * ((d + 127) / 128);
-  DenseTile t;
-  t.large = (bpad % 128 == 0) && (force >= 0 ? force == 1 : big >= 256);
-  t.bm = t.large ? 128 : 32;
-  t.bn = t.large ? 128 : 32;
+  // The largest tile that still gives a few hundred workgroups: 128 x 128,
+  // then 64 x 64, else 32 x 32 (small problems are latency-bound; more
+  // workgroups win).  force: 0 = 32, 1 = 128, 2 = 64 (when bpad allows it).
   (void)prec;
+  const int64_t n128 = (bpad / 128) * ((d + 127) / 128);
+  const int64_t n64 = (bpad / 64) * ((d + 63) / 64);
+  int size = 32;
+  if (force == 1 && bpad % 128 == 0) size = 128;
+  else if (force == 2 && bpad % 64 == 0) size = 64;
+  else if (force < 0) {
+    if (bpad % 128 == 0 && n128 >= 256) size = 128;
+    else if (bpad % 64 == 0 && n64 >= 256) size = 64;
+  }
+  DenseTile t;
+  t.large = size == 128;
+  t.bm = t.bn = size;
   return t;
 }
 
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a) {
   const DenseTile t = dense_tile(prec, a.d, a.bpad, a.tile_force);
-  if (prec == MLCT_FP64)
-    return t.large ? launch_dense_cfg<0, 2, 2, 4, 4, 16>(s, a) : launch_dense_cfg<0, 1, 1, 2, 2, 16>(s, a);
-  if (prec == MLCT_FP32)
-    return t.large ? launch_dense_cfg<1, 2, 2, 4, 4, 16>(s, a) : launch_dense_cfg<1, 1, 1, 2, 2, 16>(s, a);
-  return t.large ? launch_dense_cfg<2, 2, 2, 4, 4, 64>(s, a) : launch_dense_cfg<2, 1, 1, 2, 2, 32>(s, a);
+  if (prec == MLCT_FP64) {
+    if (t.bm == 128) return launch_dense_cfg<0, 2, 2, 4, 4, 16>(s, a);
+    if (t.bm == 64) return launch_dense_cfg<0, 2, 2, 2, 2, 16>(s, a);
+    return launch_dense_cfg<0, 1, 1, 2, 2, 16>(s, a);
+  }
+  if (prec == MLCT_FP32) {
+    if (t.bm == 128) return launch_dense_cfg<1, 2, 2, 4, 4, 16>(s, a);
+    if (t.bm == 64) return launch_dense_cfg<1, 2, 2, 2, 2, 16>(s, a);
+    return launch_dense_cfg<1, 1, 1, 2, 2, 16>(s, a);
+  }
+  if (t.bm == 128) return launch_dense_cfg<2, 2, 2, 4, 4, 64>(s, a);
+  if (t.bm == 64) return launch_dense_cfg<2, 2, 2, 2, 2, 64>(s, a);
+  return launch_dense_cfg<2, 1, 1, 2, 2, 32>(s, a);
 }
 
 hipError_t launch_dense_probe_init(hipStream_t s, int prec, void* v0, int64_t d, int64_t bpad,

@@ -319,7 +319,7 @@ class mlct_mlp_cfg(C.Structure):
 
 class mlct_mlp_info(C.Structure):
     _fields_ = [("var_q", C.c_double), ("var_resid", C.c_double), ("mean_resid", C.c_double),
-                ("ybar", C.c_double), ("ysd", C.c_double), ("final_loss", C.c_double),
+                ("var_g", C.c_double), ("ybar", C.c_double), ("ysd", C.c_double), ("final_loss", C.c_double),
                 ("fallback", C.c_int32), ("n_features", C.c_int32), ("n_cheap", C.c_int32),
                 ("n_fine", C.c_int32), ("ntrain", C.c_int64), ("nval", C.c_int64),
                 ("nparams", C.c_int64)]

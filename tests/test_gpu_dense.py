@@ -189,3 +189,12 @@ def test_large_tile_block_full_size_sampled(ctx):
     Z = probes.rademacher(d, ids, seed).T
     want = moments.moments_direct(A, Z, alpha, beta, n)
     np.testing.assert_allclose(mu[ids], want, rtol=0, atol=1e-9 * d)
+    # blocks of 320 and 64 probes take the 64 x 64 and 32 x 32 tile shapes
+    for m in (320, 64):
+        mu = mlct.mlct_moments(ctx, op, a, b, n, mlct.rademacher_probes(seed, m),
+                               mlct.MLCT_FP64, mlct.MLCT_DOUBLING)
+        sel = np.r_[0:4, m - 4:m]
+        np.testing.assert_allclose(mu[sel], want[np.r_[0:4][:4].tolist() + []] if False else
+                                   moments.moments_direct(A, probes.rademacher(d, sel, seed).T,
+                                                          alpha, beta, n),
+                                   rtol=0, atol=1e-9 * d)
