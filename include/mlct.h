@@ -246,8 +246,11 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
 /* Autotuner: times the candidate launch shapes of the recurrence for this
  * operator on the device and keeps the fastest in the operator (CSR: the cap
  * on workgroups per step, 512 / 1024 / 2048 / 4096, FP32, 64 probes;
- * dense: 32 x 32, 64 x 64 or 128 x 128 tiles in arithmetic ``prec`` at
- * block width B_max; kept as 0, 2 or 1).  With a cache file given to mlct_create the decision is written
+ * dense: 32 x 32, 64 x 64 or 128 x 128 square tiles or the skinny split-K
+ * kernel (64 or 32 probes x 16 rows per workgroup) in arithmetic ``prec`` at
+ * block width B_max; kept as 0, 2, 1 or 3).  Without tuning, blocks of at
+ * most 64 probes take the skinny kernel and wider ones the largest square
+ * tile that still fills the device.  With a cache file given to mlct_create the decision is written
  * there, keyed by the operator's shape, and operators of the same shape pick
  * it up when they are created.  choice_out (may be NULL): the value kept. */
 mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t prec,
@@ -286,9 +289,10 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
                            int64_t* w_out, mlct_tri_result* out);
 
 /* ---- learned control-variate level (not in the paper) -------------------
- * A small MLP g (F = n_cheap + 1 inputs x_f = mu_f / mu_0, two hidden tanh
- * layers of 64 units, one output) predicts a probe's fine-level value
- * q = z^T p_{n_fine}(A_hat) z from its cheap moments.  It is trained on pilot
+ * g predicts a probe's fine-level value q = z^T p_{n_fine}(A_hat) z from its
+ * cheap moments: the truncation q_c = sum_{j <= n_cheap} c_j mu_j plus a
+ * small MLP correction (F = n_cheap + 1 inputs x_f = mu_f / mu_0, two hidden
+ * tanh layers of 64 units, one output) trained on the residual q - q_c.  It is trained on pilot
  * probes, then used as one more multilevel term (Section 2.3, eq.
  * eqn:telescope; the control-variate form of Section 5.5):
  *   Gamma = (1/M0) sum_{S0} g + (1/M1) sum_{S1} (q - g),

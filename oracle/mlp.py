@@ -12,6 +12,11 @@ L = (1/N) sum_i (out_i - y_i)^2.  Gradients are derived by hand
 (tanh' = 1 - tanh^2).  Optimiser: Adam (Kingma & Ba 2015) with bias
 correction.
 
+The library's g adds this network's output to the cheap truncation
+q_c = sum_{j<=c} c_j mu_j as a skip connection, g = q_c + mu_0 (ybar + ysd out),
+so the network learns the standardised residual of the truncation; the tests
+rebuild that composite from ``forward`` and the oracle's moments.
+
 Estimator (unbiased for any fixed g): with disjoint probe sets S0 (cheap
 degree, M0 probes) and S1 (fine degree, M1 probes), both disjoint from the
 pilot that trained g,

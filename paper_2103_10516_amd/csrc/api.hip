@@ -335,7 +335,7 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
     return MLCT_OK;
   }
   const int64_t bpad = dense_bpad(block);
-  const int64_t ntiles = (op->d + 31) / 32;  // the smallest tile: an upper bound for any block
+  const int64_t ntiles = (op->d + 15) / 16;  // the narrowest tile: an upper bound for any block
   const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
   CHECK(ws_get(ctx, WS_V0, (size_t)bpad * op->d * tsz, &tmp));
   CHECK(ws_get(ctx, WS_V1, (size_t)bpad * op->d * tsz, &tmp));
@@ -349,11 +349,11 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
                             int64_t ldmu) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
   const int64_t d = op->d, bpad = dense_bpad(src.active);
-  const DenseTile t = dense_tile(prec, d, bpad, op->tuned_dense);
-  const int64_t ntiles = (d + t.bn - 1) / t.bn;
   const void *a0, *a1;
   int64_t lda;
   CHECK(dense_operand(ctx, op, prec, &a0, &a1, &lda));
+  const DenseTile t = dense_tile(prec, d, lda, bpad, op->tuned_dense);
+  const int64_t ntiles = (d + t.bn - 1) / t.bn;
   CHECK(reserve_block_ws(ctx, op, prec, mode, degree, src.active));
   const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
   void *v0, *v1, *part, *dots;
@@ -1030,7 +1030,8 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
   MLP_HIP(launch_cheb_dct(s, f.kind, f.power, a, b, n_fine, m->coef, m->coef + n_fine + 1));
   MLP_HIP(launch_qvals(s, static_cast<double*>(mu), ldmu, m->coef, n_fine, m_pilot, q));
   // training set and training
-  MLP_HIP(launch_mlp_prepare(s, static_cast<double*>(mu), ldmu, q, F, (int)ntrain, X, y, stats));
+  MLP_HIP(launch_mlp_prepare(s, static_cast<double*>(mu), ldmu, q, m->coef, F, (int)ntrain, X, y,
+                             stats));
   MLP_HIP(launch_mlp_init(s, m->theta, m->adam_m, m->adam_v, F, init_seed));
   for (int t = 1; t <= epochs; ++t) {
     MLP_HIP(launch_mlp_grad(s, m->theta, F, X, y, (int)ntrain, kMlpWaves, part, loss_part));
@@ -1046,7 +1047,7 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
   // held-out pilot probes: variance of q and of q - g
   if (nval >= 2) {
     const double* muv = static_cast<double*>(mu) + ntrain * ldmu;
-    MLP_HIP(launch_mlp_infer(s, m->wbf16, F, muv, ldmu, nval, m->ybar, m->ysd, gval));
+    MLP_HIP(launch_mlp_infer(s, m->wbf16, F, m->coef, muv, ldmu, nval, m->ybar, m->ysd, gval));
     MLP_HIP(launch_mlp_combine(s, q + ntrain, nval, q + ntrain, gval, nval, comb));
     MLP_HIP(launch_mlp_combine(s, gval, nval, gval, nullptr, 0, comb + 4));
     double hc[8];
@@ -1104,7 +1105,7 @@ mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_m
     pr.m = M0u;
     CHECK(run_probe_set(ctx, op, alpha, beta, nc, MLCT_DOUBLING, m->prec, &pr,
                         static_cast<double*>(mu0), nc + 1));
-    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, static_cast<double*>(mu0), nc + 1, M0u, m->ybar,
+    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu0), nc + 1, M0u, m->ybar,
                                  m->ysd, g0));
   }
   pr.first_id = M0u;
@@ -1113,7 +1114,7 @@ mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_m
                       static_cast<double*>(mu1), n + 1));
   HIPCHK(ctx, launch_qvals(s, static_cast<double*>(mu1), n + 1, m->coef, n, M1, q1));
   if (learned)
-    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, static_cast<double*>(mu1), n + 1, M1, m->ybar,
+    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu1), n + 1, M1, m->ybar,
                                  m->ysd, g1));
   HIPCHK(ctx, launch_mlp_combine(s, g0, M0u, q1, learned ? g1 : nullptr, M1, comb));
   double hc[4];
@@ -1458,7 +1459,7 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   const int degree = 8;
   std::vector<int> cands;
   if (csr) cands = {512, 1024, 2048, 4096};
-  else cands = {0, 2, 1};
+  else cands = {0, 2, 1, 3};
   // workspace for the largest candidate
   const int saved_g = op->tuned_groups, saved_t = op->tuned_dense;
   op->tuned_groups = 4096;

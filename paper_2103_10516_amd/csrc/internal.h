@@ -61,7 +61,7 @@ struct mlct_op {
   const void* val = nullptr;  // nullptr = pattern
   int max_row_nnz = 0;
   int tuned_groups = 0;      // CSR: workgroup cap chosen by mlct_autotune (0 = default)
-  int tuned_dense = -1;      // dense: 1 = 128x128, 2 = 64x64, 0 = 32x32 tiles, -1 = default rule
+  int tuned_dense = -1;      // dense: 1 = 128x128, 2 = 64x64, 0 = 32x32 tiles, 3 = skinny, -1 = default rule
   // dense / Gram (row-major d x d)
   const void* A = nullptr;
   int64_t lda = 0;
@@ -206,10 +206,12 @@ struct DenseStepArgs {
 };
 struct DenseTile {
   bool large;
+  bool skinny;  // split-K kernel: bm probes x 16 matrix rows per workgroup
   int bm, bn;
 };
-// force: -1 = default rule, 0 = 32 x 32, 1 = 128 x 128, 2 = 64 x 64 tiles (when valid)
-DenseTile dense_tile(int prec, int64_t d, int64_t bpad, int force = -1);
+// force: -1 = default rule, 0 = 32 x 32, 1 = 128 x 128, 2 = 64 x 64 tiles,
+// 3 = skinny (each when the block and the row alignment allow it)
+DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force = -1);
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a);
 hipError_t launch_dense_probe_init(hipStream_t s, int prec, void* v0, int64_t d, int64_t bpad,
                                    ProbeSrc src, double* dots0);
@@ -248,12 +250,14 @@ hipError_t launch_mlp_adam(hipStream_t s, float* theta, float* m, float* v, cons
                            int nwaves, int F, int t, float lr, const float* loss_part, int N,
                            float* loss_hist);
 hipError_t launch_mlp_to_bf16(hipStream_t s, const float* theta, int F, void* w);
-hipError_t launch_mlp_infer(hipStream_t s, const void* w, int F, const double* mu, int64_t ldmu,
-                            int64_t rows, double ybar, double ysd, double* g);
+hipError_t launch_mlp_infer(hipStream_t s, const void* w, int F, const double* coef,
+                            const double* mu, int64_t ldmu, int64_t rows, double ybar, double ysd,
+                            double* g);
 hipError_t launch_qvals(hipStream_t s, const double* mu, int64_t ldmu, const double* c, int n,
                         int64_t rows, double* q);
 hipError_t launch_mlp_prepare(hipStream_t s, const double* mu, int64_t ldmu, const double* q,
-                              int F, int ntrain, float* X, float* y, double* stats);
+                              const double* coef, int F, int ntrain, float* X, float* y,
+                              double* stats);
 hipError_t launch_mlp_combine(hipStream_t s, const double* a, int64_t na, const double* b,
                               const double* a2, int64_t nb, double* out);
 

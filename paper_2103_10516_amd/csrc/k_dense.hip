@@ -290,6 +290,216 @@ __global__ __launch_bounds__(64 * WM * WN) void dense_step_kernel(
   }
 }
 
+// Skinny blocks (32 or 64 probes per tile).  A block-square tile would give
+// a few hundred single-wave workgroups that each walk the whole k range with
+// one load in flight, so the step would be latency-bound.  Here a workgroup
+// owns all BM probes of its tile against only 16 matrix rows, and its four
+// waves split the k range between them (split-K inside the workgroup):
+// wave w takes chunks w, w+4, ... of KC = 4E columns, with lane group
+// g = lane / 16 covering E contiguous columns of its row (64 bytes of V and
+// of each part of A per lane), the next chunk prefetched into registers
+// while the current one is on the matrix cores.  No LDS staging: the MFMA
+// operands come straight from the registers the loads filled, since the
+// assignment of columns to an MFMA's k slots only has to agree between the
+// two operands.  The four partial accumulators are summed through LDS in a
+// fixed wave order, and wave a runs the epilogue of probe tile a.
+template <int PREC, int TM, int ZMODE, bool HAS_PREV>
+__global__ __launch_bounds__(256) void dense_skinny_kernel(
+    const void* __restrict__ A0, const void* __restrict__ A1, int64_t lda, int64_t d,
+    const typename Prec<PREC>::V* __restrict__ vk, typename Prec<PREC>::V* __restrict__ vm,
+    typename Prec<PREC>::V ca, typename Prec<PREC>::V cb, ProbeSrc src, int mtiles, int ntiles,
+    double* __restrict__ part) {
+  using P = Prec<PREC>;
+  using VT = typename P::V;
+  using MT = typename P::M;
+  using AccT = typename P::Acc;
+  constexpr int W = 4, BM = TM * 16;
+  constexpr int E = PREC == 0 ? 8 : 16;  // columns per lane per chunk
+  constexpr int KC = 4 * E;              // columns per chunk
+  constexpr int QA = 16 / (int)sizeof(MT), QV = 16 / (int)sizeof(VT);
+  constexpr int NA = E / QA, NV = E / QV;  // 16-byte pieces per lane per chunk
+  constexpr int NSPLIT = PREC == 2 ? 2 : 1;
+  typedef MT aq __attribute__((ext_vector_type(QA)));
+  typedef VT vq __attribute__((ext_vector_type(QV)));
+  static_assert(TM <= W, "one epilogue tile per wave");
+
+  __shared__ AccT red[W][TM][64];
+
+  const int total = mtiles * ntiles;
+  const int L = xcd_band(blockIdx.x, (total + 7) / 8 * 8);
+  if (L >= total) return;
+  const int mt = L % mtiles, nt = L / mtiles;
+  const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, rl = lane & 15;
+
+  // Rows past d read row 0: column n of the product depends on row n of A
+  // only, and the epilogue drops columns n >= d.
+  const int64_t nrow = n0 + rl < d ? n0 + rl : 0;
+  const MT* arow[NSPLIT];
+#pragma unroll
+  for (int h = 0; h < NSPLIT; ++h) arow[h] = static_cast<const MT*>(h ? A1 : A0) + nrow * lda;
+  const VT* vrow[TM];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) vrow[a] = vk + (m0 + a * 16 + rl) * d;
+
+  AccT acc[TM];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) acc[a] = AccT{};
+
+  aq ra[NSPLIT][NA], xa[NSPLIT][NA];
+  vq rv[TM][NV], xv[TM][NV];
+  auto load = [&](int64_t c, aq (&ta)[NSPLIT][NA], vq (&tv)[TM][NV]) {
+    const int64_t k = c * KC + g * E;
+#pragma unroll
+    for (int h = 0; h < NSPLIT; ++h)
+#pragma unroll
+      for (int p = 0; p < NA; ++p) ta[h][p] = *reinterpret_cast<const aq*>(arow[h] + k + p * QA);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int p = 0; p < NV; ++p) tv[a][p] = *reinterpret_cast<const vq*>(vrow[a] + k + p * QV);
+  };
+  auto compute = [&](const aq (&ta)[NSPLIT][NA], const vq (&tv)[TM][NV]) {
+    if constexpr (PREC == 2) {
+#pragma unroll
+      for (int t = 0; t < E / 8; ++t) {
+        const bf8 bh = ta[0][t], bl = ta[1][t];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          bf8 vh, vl;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            __bf16 hi, lo;
+            split_bf16(tv[a][(8 * t + q) / QV][(8 * t + q) % QV], hi, lo);
+            vh[q] = hi;
+            vl[q] = lo;
+          }
+          acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, bh, acc[a], 0, 0, 0);
+          acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, bl, acc[a], 0, 0, 0);
+          acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, bh, acc[a], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < E; ++t) {
+        const MT b = ta[0][t / QA][t % QA];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          const VT x = tv[a][t / QV][t % QV];
+          if constexpr (PREC == 0)
+            acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, b, acc[a], 0, 0, 0);
+          else
+            acc[a] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b, acc[a], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  // Two register buffers in turn: chunk i + 1 streams into one while chunk i
+  // is on the matrix cores from the other.  After each load group, an empty
+  // asm with a memory clobber keeps the compiler from merging the two loads
+  // that feed a loop-carried buffer into one load at the top of the loop,
+  // and a scheduling barrier keeps the instruction scheduler from sinking
+  // the loads down to their uses (either would turn the prefetch back into
+  // load-then-use).
+  const int64_t nfull = d / KC;
+  const int64_t mine = wave < nfull ? (nfull - wave + W - 1) / W : 0;  // chunks of this wave
+  auto chunk = [&](int64_t i) { return (int64_t)wave + i * W; };
+  if (mine > 0) {
+    load(chunk(0), ra, rv);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    int64_t i = 0;
+    for (; i + 2 <= mine; i += 2) {
+      load(chunk(i + 1), xa, xv);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      compute(ra, rv);
+      // past the last chunk this re-reads it (a cache hit), so every load
+      // in the loop is unconditional
+      load(chunk(i + 2 < mine ? i + 2 : mine - 1), ra, rv);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xa, xv);
+    }
+    if (i < mine) compute(ra, rv);
+  }
+  // ragged tail [nfull * KC, d): element loads, zero past d in both operands
+  if (nfull * KC < d && wave == (int)(nfull % W)) {
+    const int64_t k0 = nfull * KC + g * E;
+#pragma unroll
+    for (int h = 0; h < NSPLIT; ++h)
+#pragma unroll
+      for (int p = 0; p < NA; ++p)
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+          const int64_t k = k0 + p * QA + q;
+          ra[h][p][q] = k < d ? arow[h][k] : MT(0.f);
+        }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int p = 0; p < NV; ++p)
+#pragma unroll
+        for (int q = 0; q < QV; ++q) {
+          const int64_t k = k0 + p * QV + q;
+          rv[a][p][q] = k < d ? vrow[a][k] : VT(0);
+        }
+    compute(ra, rv);
+  }
+
+#pragma unroll
+  for (int a = 0; a < TM; ++a) red[wave][a][lane] = acc[a];
+  __syncthreads();
+  if (wave >= TM) return;
+
+  // ---- epilogue of probe tile a = wave: recurrence in place, partials ----
+  const int a = wave;
+  AccT sum = red[0][a][lane];
+#pragma unroll
+  for (int w = 1; w < W; ++w) sum += red[w][a][lane];
+  const int64_t n = n0 + rl;
+  double p1[4], p2[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    p1[r] = p2[r] = 0.0;
+    const int64_t j = m0 + a * 16 + acc_row<PREC>(lane, r);
+    if (n >= d) continue;
+    const int64_t idx = j * d + n;
+    const VT x = vk[idx];
+    VT vn = ca * (VT)sum[r] + cb * x;
+    if (HAS_PREV) vn -= vm[idx];
+    vm[idx] = vn;
+    if (ZMODE == 0) {
+      p1[r] = (double)x * (double)vn;
+      p2[r] = (double)vn * (double)vn;
+    } else if (ZMODE == 1) {
+      const uint64_t key = sm_output(src.seed, (uint64_t)(src.first_id + j));
+      p1[r] = sign_from_word<double>(sm_output(key, (uint64_t)(n >> 6)), n) * (double)vn;
+    } else {
+      const double z = j < src.active ? (double)src.entries[n * src.ld + src.first_id + j] : 0.0;
+      p1[r] = z * (double)vn;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      p1[r] += __shfl_xor(p1[r], o, 64);
+      p2[r] += __shfl_xor(p2[r], o, 64);
+    }
+  if (rl == 0) {
+    const int64_t width = (int64_t)mtiles * BM;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = m0 + a * 16 + acc_row<PREC>(lane, r);
+      part[(int64_t)nt * width + j] = p1[r];
+      part[((int64_t)ntiles + nt) * width + j] = p2[r];
+    }
+  }
+}
+
 // V0^T[j][n] = z_n^(j) for j < active (0 for padding rows) and the moment
 // mu_0 = z.z per probe (one workgroup per probe row, fixed-order sum).
 template <typename VT>
@@ -439,30 +649,74 @@ hipError_t launch_dense_cfg(hipStream_t s, const DenseStepArgs& a) {
   return hipGetLastError();
 }
 
+template <int PREC, int TM>
+hipError_t launch_skinny_cfg(hipStream_t s, const DenseStepArgs& a) {
+  using VT = typename Prec<PREC>::V;
+  const int mtiles = (int)(a.bpad / (TM * 16));
+  const int ntiles = (int)((a.d + 15) / 16);
+  const int grid = (mtiles * ntiles + 7) / 8 * 8;
+  const VT ca = (VT)a.ca, cb = (VT)a.cb;
+  const VT* vk = static_cast<const VT*>(a.vk);
+  VT* vm = static_cast<VT*>(a.vm);
+#define MLCT_SKINNY_LAUNCH(Z, HP)                                                            \
+  dense_skinny_kernel<PREC, TM, Z, HP><<<grid, 256, 0, s>>>(a.A0, a.A1, a.lda, a.d, vk, vm, ca, \
+                                                          cb, a.src, mtiles, ntiles, a.part)
+  if (a.has_prev) {
+    if (a.zmode == 0) MLCT_SKINNY_LAUNCH(0, true);
+    else if (a.zmode == 1) MLCT_SKINNY_LAUNCH(1, true);
+    else MLCT_SKINNY_LAUNCH(2, true);
+  } else {
+    if (a.zmode == 0) MLCT_SKINNY_LAUNCH(0, false);
+    else if (a.zmode == 1) MLCT_SKINNY_LAUNCH(1, false);
+    else MLCT_SKINNY_LAUNCH(2, false);
+  }
+#undef MLCT_SKINNY_LAUNCH
+  return hipGetLastError();
+}
+
 }  // namespace
 
-DenseTile dense_tile(int prec, int64_t d, int64_t bpad, int force) {
-  // The largest tile that still gives a few hundred workgroups: 128 x 128,
-  // then 64 x 64, else 32 x 32 (small problems are latency-bound; more
-  // workgroups win).  force: 0 = 32, 1 = 128, 2 = 64 (when bpad allows it).
-  (void)prec;
+DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) {
+  // Blocks of at most 64 probes take the skinny split-K kernel (16-row
+  // tiles) when rows are 16-byte aligned.  Otherwise the largest square tile
+  // that still gives a few hundred workgroups: 128 x 128, then 64 x 64, else
+  // 32 x 32 (small problems are latency-bound; more workgroups win).
+  // force: 0 = 32, 1 = 128, 2 = 64, 3 = skinny (when the block allows it).
+  const int qv = prec == MLCT_FP64 ? 2 : 4, qa = prec == MLCT_FP64 ? 2 : (prec == MLCT_FP32 ? 4 : 8);
+  const bool skinny_ok = d % qv == 0 && lda % qa == 0;
   const int64_t n128 = (bpad / 128) * ((d + 127) / 128);
   const int64_t n64 = (bpad / 64) * ((d + 63) / 64);
+  DenseTile t;
+  t.skinny = false;
   int size = 32;
-  if (force == 1 && bpad % 128 == 0) size = 128;
+  if (force == 3 && skinny_ok) t.skinny = true;
+  else if (force == 1 && bpad % 128 == 0) size = 128;
   else if (force == 2 && bpad % 64 == 0) size = 64;
   else if (force < 0) {
-    if (bpad % 128 == 0 && n128 >= 256) size = 128;
+    if (bpad <= 64 && skinny_ok) t.skinny = true;
+    else if (bpad % 128 == 0 && n128 >= 256) size = 128;
     else if (bpad % 64 == 0 && n64 >= 256) size = 64;
   }
-  DenseTile t;
+  if (t.skinny) {
+    t.large = false;
+    t.bm = bpad % 64 == 0 ? 64 : 32;
+    t.bn = 16;
+    return t;
+  }
   t.large = size == 128;
   t.bm = t.bn = size;
   return t;
 }
 
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a) {
-  const DenseTile t = dense_tile(prec, a.d, a.bpad, a.tile_force);
+  const DenseTile t = dense_tile(prec, a.d, a.lda, a.bpad, a.tile_force);
+  if (t.skinny) {
+    if (prec == MLCT_FP64)
+      return t.bm == 64 ? launch_skinny_cfg<0, 4>(s, a) : launch_skinny_cfg<0, 2>(s, a);
+    if (prec == MLCT_FP32)
+      return t.bm == 64 ? launch_skinny_cfg<1, 4>(s, a) : launch_skinny_cfg<1, 2>(s, a);
+    return t.bm == 64 ? launch_skinny_cfg<2, 4>(s, a) : launch_skinny_cfg<2, 2>(s, a);
+  }
   if (prec == MLCT_FP64) {
     if (t.bm == 128) return launch_dense_cfg<0, 2, 2, 4, 4, 16>(s, a);
     if (t.bm == 64) return launch_dense_cfg<0, 2, 2, 2, 2, 16>(s, a);

@@ -1,6 +1,7 @@
-// Learned control-variate level: an MLP g(x) = w3 . tanh(W2 tanh(W1 x + b1)
-// + b2) + b3 with 64 hidden units per layer, mapping the cheap moments of a
-// probe to a prediction of its fine-level quadratic form (the control-variate
+// Learned control-variate level: the cheap truncation of the fine-level
+// quadratic form plus an MLP correction, g = q_c + mu_0 (ybar + ysd * net(x)),
+// net(x) = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3 with 64 hidden units per
+// layer, x = the cheap moments of the probe (the control-variate
 // idea of Section 5.5 with a learned map, used as an extra multilevel term in
 // the sense of Section 2.3).
 //
@@ -164,9 +165,11 @@ __global__ void mlp_to_bf16_kernel(const float* __restrict__ theta, int P, __bf1
 
 __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 
-// g for rows of a moment table: x_f = mu_f / mu_0 (f < F), network output
-// scaled back: g = mu_0 (ybar + ysd * out).  One wave per 64-row slice.
+// g for rows of a moment table: the cheap truncation q_c = sum_{f<F} c_f mu_f
+// plus the network's correction, g = q_c + mu_0 (ybar + ysd * out), with
+// inputs x_f = mu_f / mu_0.  One wave per 64-row slice.
 __global__ __launch_bounds__(64) void mlp_infer_kernel(const __bf16* __restrict__ w, int F,
+                                                       const double* __restrict__ coef,
                                                        const double* __restrict__ mu,
                                                        int64_t ldmu, int64_t rows, double ybar,
                                                        double ysd, double* __restrict__ g) {
@@ -193,7 +196,11 @@ __global__ __launch_bounds__(64) void mlp_infer_kernel(const __bf16* __restrict_
     for (int k = 0; k < H; ++k) a2 = fmaf(w2r[k], read_lane(h1, k), a2);
     const float h2 = bf(tanhf(a2));
     const float out = wave_sum_f(w3 * h2) + b3;
-    if (l == 0) g[i] = r[0] * (ybar + ysd * (double)out);
+    if (l == 0) {
+      double qc = 0.0;
+      for (int f = 0; f < F; ++f) qc += coef[f] * r[f];
+      g[i] = qc + r[0] * (ybar + ysd * (double)out);
+    }
   }
 }
 
@@ -223,22 +230,32 @@ __device__ double rsum(double v, double* sh) {
   return r;
 }
 
-// Training set from the pilot: X = mu[0..F-1] / mu_0 (float), targets
-// standardised, y = (q / mu_0 - ybar) / ysd with ybar, ysd over the training
-// rows; stats[0..1] = ybar, ysd.  One workgroup, fixed-order sums.
+// Training set from the pilot: X = mu[0..F-1] / mu_0 (float) and the
+// standardised residual of the cheap truncation,
+// y = ((q - q_c) / mu_0 - ybar) / ysd, q_c = sum_{f<F} c_f mu_f, with ybar,
+// ysd over the training rows; stats[0..1] = ybar, ysd.  One workgroup,
+// fixed-order sums.
+__device__ __forceinline__ double resid_target(const double* r, double q, const double* c, int F) {
+  double qc = 0.0;
+  for (int f = 0; f < F; ++f) qc += c[f] * r[f];
+  return (q - qc) / r[0];
+}
+
 __global__ __launch_bounds__(kRT) void mlp_prepare_kernel(const double* __restrict__ mu,
                                                           int64_t ldmu,
-                                                          const double* __restrict__ q, int F,
+                                                          const double* __restrict__ q,
+                                                          const double* __restrict__ coef, int F,
                                                           int ntrain, float* __restrict__ X,
                                                           float* __restrict__ y,
                                                           double* __restrict__ stats) {
   __shared__ double sh[kRT];
   double s = 0.0;
-  for (int i = threadIdx.x; i < ntrain; i += kRT) s += q[i] / mu[(int64_t)i * ldmu];
+  for (int i = threadIdx.x; i < ntrain; i += kRT)
+    s += resid_target(mu + (int64_t)i * ldmu, q[i], coef, F);
   const double mean = rsum(s, sh) / ntrain;
   double ss = 0.0;
   for (int i = threadIdx.x; i < ntrain; i += kRT) {
-    const double t = q[i] / mu[(int64_t)i * ldmu] - mean;
+    const double t = resid_target(mu + (int64_t)i * ldmu, q[i], coef, F) - mean;
     ss += t * t;
   }
   double sd = sqrt(rsum(ss, sh) / (ntrain > 1 ? ntrain - 1 : 1));
@@ -246,7 +263,7 @@ __global__ __launch_bounds__(kRT) void mlp_prepare_kernel(const double* __restri
   for (int i = threadIdx.x; i < ntrain; i += kRT) {
     const double* r = mu + (int64_t)i * ldmu;
     for (int f = 0; f < F; ++f) X[(int64_t)i * F + f] = (float)(r[f] / r[0]);
-    y[i] = (float)((q[i] / r[0] - mean) / sd);
+    y[i] = (float)((resid_target(r, q[i], coef, F) - mean) / sd);
   }
   if (threadIdx.x == 0) {
     stats[0] = mean;
@@ -340,11 +357,12 @@ hipError_t launch_mlp_to_bf16(hipStream_t s, const float* theta, int F, void* w)
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_infer(hipStream_t s, const void* w, int F, const double* mu, int64_t ldmu,
-                            int64_t rows, double ybar, double ysd, double* g) {
+hipError_t launch_mlp_infer(hipStream_t s, const void* w, int F, const double* coef,
+                            const double* mu, int64_t ldmu, int64_t rows, double ybar, double ysd,
+                            double* g) {
   if (rows <= 0) return hipSuccess;
-  mlp_infer_kernel<<<(int)((rows + 63) / 64), 64, 0, s>>>(static_cast<const __bf16*>(w), F, mu,
-                                                          ldmu, rows, ybar, ysd, g);
+  mlp_infer_kernel<<<(int)((rows + 63) / 64), 64, 0, s>>>(static_cast<const __bf16*>(w), F, coef,
+                                                          mu, ldmu, rows, ybar, ysd, g);
   return hipGetLastError();
 }
 
@@ -356,8 +374,9 @@ hipError_t launch_qvals(hipStream_t s, const double* mu, int64_t ldmu, const dou
 }
 
 hipError_t launch_mlp_prepare(hipStream_t s, const double* mu, int64_t ldmu, const double* q,
-                              int F, int ntrain, float* X, float* y, double* stats) {
-  mlp_prepare_kernel<<<1, kRT, 0, s>>>(mu, ldmu, q, F, ntrain, X, y, stats);
+                              const double* coef, int F, int ntrain, float* X, float* y,
+                              double* stats) {
+  mlp_prepare_kernel<<<1, kRT, 0, s>>>(mu, ldmu, q, coef, F, ntrain, X, y, stats);
   return hipGetLastError();
 }
 

@@ -62,8 +62,12 @@ def test_hadamard_exact_trace_dense_512(ctx):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("mode", ["direct", "doubling"])
-@pytest.mark.parametrize("d,m", [(200, 100), (96, 33)])
+@pytest.mark.parametrize("d,m", [(200, 100), (96, 33), (96, 20), (101, 40)])
 def test_dense_moments_match_oracle(ctx, prec, mode, d, m):
+    """Block shapes: 100 probes take square tiles; 33 and 20 the skinny
+    split-K kernel (64- and 32-probe tiles, padding rows, a ragged k tail at
+    d = 200 or 96 for some precisions); d = 101 rows are not 16-byte aligned,
+    so 40 probes fall back to square tiles."""
     from paper_2103_10516_amd import mlct
 
     A, lam = wl.random_symmetric(d, 17, -2.0, 3.0)
@@ -84,6 +88,32 @@ def test_dense_moments_match_oracle(ctx, prec, mode, d, m):
     assert worst <= 1.0
     if prec == "fp64":
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-10 * d)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_dense_explicit_probes_skinny(ctx, prec):
+    """Explicit probe columns (40 of a 256-column Rademacher matrix, offset
+    into the matrix) in direct form on the skinny kernel, against the
+    oracle's direct moments of the same columns."""
+    import torch
+
+    from paper_2103_10516_amd import mlct
+
+    d, n = 200, 17
+    A, lam = wl.random_symmetric(d, 23, -1.0, 2.0)
+    a, b = -1.2, 2.2
+    op = _dense(ctx, A, np.float64 if prec == "fp64" else np.float32)
+    Zall = probes.rademacher(d, np.arange(256), 77).T  # d x 256
+    E = torch.from_numpy(np.ascontiguousarray(Zall.astype(np.int8))).cuda()
+    got = mlct.mlct_moments(ctx, op, a, b, n, mlct.explicit_probes(E, m=40, first_id=100),
+                            _prec(prec), mlct.MLCT_DIRECT)
+    alpha, beta = cheb.affine_map(a, b)
+    Aop = A if prec == "fp64" else A.astype(np.float32).astype(np.float64)
+    want = moments.moments_direct(Aop, Zall[:, 100:140], alpha, beta, n)
+    kappa = float(np.max(np.abs(alpha * Aop + beta * np.eye(d)).sum(axis=1)))
+    u = {"fp64": U64, "fp32": U32, "bf16x3": U_BF16X3}[prec]
+    tol = moment_tol(n, d, u, d, kappa)
+    assert float(np.max(np.abs(got - want) / tol[None, :])) <= 1.0
 
 
 def test_dense_estimate_full_config_fp64(ctx):
@@ -189,7 +219,7 @@ def test_large_tile_block_full_size_sampled(ctx):
     Z = probes.rademacher(d, ids, seed).T
     want = moments.moments_direct(A, Z, alpha, beta, n)
     np.testing.assert_allclose(mu[ids], want, rtol=0, atol=1e-9 * d)
-    # blocks of 320 and 64 probes take the 64 x 64 and 32 x 32 tile shapes
+    # blocks of 320 and 64 probes take the 64 x 64 tiles and the skinny kernel
     for m in (320, 64):
         mu = mlct.mlct_moments(ctx, op, a, b, n, mlct.rademacher_probes(seed, m),
                                mlct.MLCT_FP64, mlct.MLCT_DOUBLING)

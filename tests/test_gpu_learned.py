@@ -103,8 +103,9 @@ def test_learned_estimator_unbiased(ctx, lap3d_fit):
     # the same budget spent on the plain estimator at the fine degree
     plain = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, 0.01, 12.01, [64],
                                [2048 * 4 // 32 + 32], 77, mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
-    print(f"learned var {np.mean([x[1] for x in vals]):.4g} vs plain (equal matvecs) "
-          f"{plain['est_var']:.4g}")
+    lvar = np.mean([x[1] for x in vals])
+    print(f"learned var {lvar:.4g} vs plain (equal matvecs) {plain['est_var']:.4g}")
+    assert lvar < 0.5 * plain["est_var"]
 
 
 def _bf16(x):
@@ -134,11 +135,14 @@ def test_inference_matches_oracle_forward(ctx, lap3d_fit):
     h1 = _bf16(np.tanh(x @ P.W1.T + P.b1))
     h2 = _bf16(np.tanh(h1 @ P.W2.T + P.b2))
     out = h2 @ P.w3 + P.b3
-    gv = mu[:, 0] * (info["ybar"] + info["ysd"] * out)
+    qc = mu[:, :9] @ c[:9]  # the cheap truncation the network corrects
+    gv = qc + mu[:, 0] * (info["ybar"] + info["ysd"] * out)
     var_q = np.var(q, ddof=1)
     var_r = np.var(q - gv, ddof=1)
     assert info["var_q"] == pytest.approx(var_q, rel=1e-3)
     assert info["var_resid"] == pytest.approx(var_r, rel=0.1, abs=1e-3 * var_q)
+    # the network's correction beats the bare cheap truncation on held-out probes
+    assert var_r < 0.5 * np.var(q - qc, ddof=1)
 
 
 def test_untrained_network_falls_back(ctx):
