@@ -251,6 +251,9 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
   T* buf[2] = {static_cast<T*>(v0), static_cast<T*>(v1)};
   double* P = static_cast<double*>(part);
   hipStream_t s = ctx->stream;
+  void* hub = nullptr;
+  if (op->hub_n > 0)
+    CHECK(ws_get(ctx, WS_HUB, (size_t)op->hub_chunks * kBlockProbes * sizeof(T), &hub));
   HIPCHK(ctx, launch_probe_init<T>(s, buf[0], op->d, src, plan, P));
   const int zdirect = src.entries ? 2 : 1;
   for (int k = 1; k <= S; ++k) {
@@ -262,7 +265,8 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
     const T cb = (T)(first ? beta : 2.0 * beta);
     const int zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
     LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
-    HIPCHK(ctx, launch_csr_step<T>(s, op, vk, vm, ca, cb, !first, zmode, src, plan, P + pstep * k));
+    HIPCHK(ctx, launch_csr_step<T>(s, op, vk, vm, ca, cb, !first, zmode, src, plan, hub,
+                                   P + pstep * k));
     tm.done();
   }
   HIPCHK(ctx, launch_reduce_partials(s, P, S + 1, 2, plan.ngroups, kBlockProbes,
@@ -275,6 +279,68 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
 // Matrix operand of a dense operator in the arithmetic ``prec``: the
 // caller's A when it already has that type, else a converted or bf16-split
 // copy built once and owned by the operator.
+// Hub table of a CSR operator (rows longer than kHubLen): found on the
+// device, sorted by row on the host, cut into chunks of kHubChunk entries.
+// At most nnz / (kHubLen + 1) rows qualify, which bounds the search output.
+mlct_status build_hubs(mlct_ctx* ctx, mlct_op* op) {
+  const int cap = (int)(op->nnz / (kHubLen + 1) + 1);
+  void* tmp;
+  CHECK(ws_get(ctx, WS_HUB, (size_t)(3 * (int64_t)cap + 1) * sizeof(int32_t), &tmp));
+  int32_t* trip = static_cast<int32_t*>(tmp);
+  int32_t* count = trip + 3 * (int64_t)cap;
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, hipMemsetAsync(count, 0, sizeof(int32_t), s));
+  HIPCHK(ctx, launch_hub_find(s, op->rowptr, op->d, trip, count, cap));
+  int32_t n = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&n, count, sizeof n, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (n <= 0 || n > cap) return fail(ctx, MLCT_EDEVICE, "hub row search returned %d rows", n);
+  std::vector<int32_t> h((size_t)3 * n);
+  HIPCHK(ctx, hipMemcpyAsync(h.data(), trip, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return h[3 * x] < h[3 * y]; });
+  std::vector<int32_t> rows(n), c0(n + 1), cs, ce;
+  for (int k = 0; k < n; ++k) {
+    const int32_t* t = &h[3 * (size_t)order[k]];
+    rows[k] = t[0];
+    c0[k] = (int32_t)cs.size();
+    for (int32_t a = t[1]; a < t[2]; a += kHubChunk) {
+      cs.push_back(a);
+      ce.push_back(std::min<int32_t>(a + kHubChunk, t[2]));
+    }
+  }
+  c0[n] = (int32_t)cs.size();
+  const size_t nch = cs.size();
+  const size_t words = (size_t)n + (n + 1) + 2 * nch;
+  void* mem = nullptr;
+  if (hipMalloc(&mem, words * sizeof(int32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MLCT_ENOMEM, "no memory for the hub table");
+  }
+  std::vector<int32_t> all;
+  all.reserve(words);
+  all.insert(all.end(), rows.begin(), rows.end());
+  all.insert(all.end(), c0.begin(), c0.end());
+  all.insert(all.end(), cs.begin(), cs.end());
+  all.insert(all.end(), ce.begin(), ce.end());
+  const hipError_t e = hipMemcpy(mem, all.data(), words * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return fail(ctx, MLCT_EDEVICE, "hub table upload: %s", hipGetErrorString(e));
+  }
+  int32_t* base = static_cast<int32_t*>(mem);
+  op->hub_mem = mem;
+  op->hub_rows = base;
+  op->hub_c0 = base + n;
+  op->hub_cs = base + n + (n + 1);
+  op->hub_ce = op->hub_cs + nch;
+  op->hub_n = n;
+  op->hub_chunks = (int)nch;
+  return MLCT_OK;
+}
+
 mlct_status dense_operand(mlct_ctx* ctx, const mlct_op* cop, int prec, const void** a0,
                           const void** a1, int64_t* lda) {
   mlct_op* op = const_cast<mlct_op*>(cop);
@@ -332,6 +398,7 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
     CHECK(ws_get(ctx, WS_V1, (size_t)op->d * kBlockProbes * tsz, &tmp));
     CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * (S + 1) * sizeof(double), &tmp));
     CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &tmp));
+    if (op->hub_n > 0) CHECK(ws_get(ctx, WS_HUB, (size_t)op->hub_chunks * kBlockProbes * tsz, &tmp));
     return MLCT_OK;
   }
   const int64_t bpad = dense_bpad(block);
@@ -547,6 +614,13 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   op->dtype = dtype;
   op->max_row_nnz = hf[1];
   op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
+  if (op->max_row_nnz > kHubLen) {
+    const mlct_status st = build_hubs(ctx, op);
+    if (st != MLCT_OK) {
+      delete op;
+      return st;
+    }
+  }
   *out = op;
   return MLCT_OK;
 }
@@ -554,7 +628,7 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
 mlct_status mlct_op_destroy(mlct_op* op) {
   if (!op) return MLCT_EINVAL;
   (void)hipSetDevice(op->device);
-  void* owned[] = {op->owned, op->split_hi, op->split_lo, op->a32, op->a64};
+  void* owned[] = {op->owned, op->split_hi, op->split_lo, op->a32, op->a64, op->hub_mem};
   for (void* p : owned)
     if (p) (void)hipFree(p);
   delete op;
@@ -858,6 +932,9 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
   CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * sizeof(long long), &part));
   CHECK(ws_get(ctx, WS_TRI, (size_t)m * 3 * sizeof(long long), &w));
   CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_tri_result), &res));
+  void* hub = nullptr;
+  if (op->hub_n > 0)
+    CHECK(ws_get(ctx, WS_HUB, (size_t)op->hub_chunks * kBlockProbes * sizeof(int32_t), &hub));
   hipStream_t s = ctx->stream;
   long long* P = static_cast<long long*>(part);
   long long* W = static_cast<long long*>(w);
@@ -870,13 +947,13 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
     {
       LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
       HIPCHK(ctx, launch_tri_step(s, op, 1, plan, static_cast<int32_t*>(z),
-                                  static_cast<int32_t*>(y), P));
+                                  static_cast<int32_t*>(y), hub, P));
       tm.done();
     }
     HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 1, W, p0));
     {
       LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
-      HIPCHK(ctx, launch_tri_step(s, op, 2, plan, static_cast<int32_t*>(y), nullptr, P));
+      HIPCHK(ctx, launch_tri_step(s, op, 2, plan, static_cast<int32_t*>(y), nullptr, hub, P));
       tm.done();
     }
     HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 2, W, p0));

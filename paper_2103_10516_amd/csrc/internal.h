@@ -14,6 +14,10 @@ namespace mlct {
 
 // Width of a probe block in the CSR recurrence: one probe per wavefront lane.
 constexpr int kBlockProbes = 64;
+// CSR rows with more entries than kHubLen are reduced in chunks of at most
+// kHubChunk entries by a separate launch before each step.
+constexpr int kHubLen = 256;
+constexpr int kHubChunk = 256;
 
 enum OpKind { OP_CSR = 0, OP_DENSE = 1, OP_GRAM = 2 };
 
@@ -60,6 +64,13 @@ struct mlct_op {
   const int32_t* col = nullptr;
   const void* val = nullptr;  // nullptr = pattern
   int max_row_nnz = 0;
+  // rows longer than kHubLen (sorted), their chunk ranges, chunk extents
+  int32_t* hub_rows = nullptr;  // [hub_n]
+  int32_t* hub_c0 = nullptr;    // [hub_n + 1]
+  int32_t* hub_cs = nullptr;    // [hub_chunks] first entry of each chunk
+  int32_t* hub_ce = nullptr;    // [hub_chunks] one past its last entry
+  int hub_n = 0, hub_chunks = 0;
+  void* hub_mem = nullptr;      // one allocation holding the four arrays
   int tuned_groups = 0;      // CSR: workgroup cap chosen by mlct_autotune (0 = default)
   int tuned_dense = -1;      // dense: 1 = 128x128, 2 = 64x64, 0 = 32x32 tiles, 3 = skinny, -1 = default rule
   // dense / Gram (row-major d x d)
@@ -98,7 +109,7 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -173,16 +184,22 @@ hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, int nbl
                                    int zmode);
 // zmode: 0 = dots with V_k (symmetric form), 1 = regenerated Rademacher z,
 // 2 = explicit z entries.  has_prev = false for the first step (no V_prev).
+// hub_part: workspace of op->hub_chunks x 64 elements of T (unused without
+// hub rows); the step first launches the hub chunk reduction into it.
 template <typename T>
 hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
-                           double* part);
+                           void* hub_part, double* part);
+// Rows longer than kHubLen as (row, start, end) triples, unordered; count is
+// incremented once per such row (entries past cap are not written).
+hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
+                           int32_t* count, int cap);
 
 // ---- integer triangle moments (k_tri.hip) ----------------------------------
 hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
                            const CsrStepPlan& plan, int32_t* z);
 hipError_t launch_tri_step(hipStream_t s, const mlct_op* op, int pass, const CsrStepPlan& plan,
-                           const int32_t* vin, int32_t* vout, long long* part);
+                           const int32_t* vin, int32_t* vout, void* hub_part, long long* part);
 hipError_t launch_tri_reduce(hipStream_t s, const long long* part, int ngroups, int active,
                              int pass, long long* w, int64_t p0);
 hipError_t launch_tri_cv(hipStream_t s, const long long* w, int64_t m, int64_t nnz,

@@ -13,6 +13,19 @@
 // Each workgroup owns a contiguous band of rows and writes one partial sum
 // per probe and slot; partials are reduced later in a fixed order, so the
 // moments are bitwise reproducible.
+//
+// The same row machinery runs the integer passes of triangle counting
+// (T = int32, pattern rows, int64 partials): only the per-row epilogue
+// differs, so it is a policy type (RecEpi, TriEpi).
+//
+// Long rows (more than kHubLen entries, the hubs of power-law graphs) would
+// leave one wave walking tens of thousands of gathers while the rest of the
+// device idles.  Their entries are cut into chunks of kHubChunk that a
+// separate launch (csr_hub_kernel) reduces first, one wave per chunk; the
+// step kernel then sums a hub row's chunk partials in chunk order.
+#include <algorithm>
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace mlct {
@@ -22,16 +35,16 @@ namespace {
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * 64;
 
-template <typename T>
-__device__ __forceinline__ void store_partials(double a1, double a2, int g, int ngroups,
-                                               double* __restrict__ part) {
-  __shared__ double sh[2][kWaves][64];
+template <typename P>
+__device__ __forceinline__ void store_partials(P a1, P a2, int g, int ngroups,
+                                               P* __restrict__ part) {
+  __shared__ P sh[2][kWaves][64];
   const int lane = lane_id(), wave = wave_id();
   sh[0][wave][lane] = a1;
   sh[1][wave][lane] = a2;
   __syncthreads();
   if (wave == 0) {
-    double s1 = sh[0][0][lane], s2 = sh[1][0][lane];
+    P s1 = sh[0][0][lane], s2 = sh[1][0][lane];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) {
       s1 += sh[0][w][lane];
@@ -72,7 +85,7 @@ __device__ __forceinline__ void probe_init_wg(T* __restrict__ v0, int64_t d, con
     v0[i * 64 + lane] = z;
     acc += (double)z * (double)z;
   }
-  store_partials<T>(acc, 0.0, g, ngroups, part);
+  store_partials<double>(acc, 0.0, g, ngroups, part);
 }
 
 template <typename T>
@@ -83,30 +96,82 @@ __global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0
   probe_init_wg<T>(v0, d, src, rows_per_group, ngroups, part, blockIdx.x);
 }
 
-// Per-row epilogue: V_new = ca*acc + cb*V_k[i] (- V_prev[i]), written over
-// V_prev with a non-temporal store, and the lane's moment partials.
+// Per-row epilogue of the recurrence: V_new = ca*acc + cb*V_k[i] (- V_prev[i]),
+// written over V_prev with a non-temporal store, and the lane's moment
+// partials (FP64).
 template <typename T, int ZMODE, bool HAS_PREV>
-__device__ __forceinline__ void finish_row(int64_t i, T acc, T xi, T xp, T ca, T cb,
-                                           T* __restrict__ vm, const ProbeSrc& src, bool act,
-                                           uint64_t key, int64_t& cached, uint64_t& word,
-                                           double& acc1, double& acc2) {
-  const int lane = lane_id();
-  T vn = ca * acc + cb * xi;
-  if (HAS_PREV) vn -= xp;
-  __builtin_nontemporal_store(vn, vm + i * 64 + lane);
-  if (ZMODE == 0) {
-    acc1 += (double)xi * (double)vn;
-    acc2 += (double)vn * (double)vn;
-  } else if (ZMODE == 1) {
-    const int64_t c = i >> 6;
-    if (c != cached) {
-      word = sm_output(key, (uint64_t)c);
-      cached = c;
+struct RecEpi {
+  using Part = double;
+  T ca, cb;
+  T* vm;
+  ProbeSrc src;
+  bool act;
+  uint64_t key = 0;
+  int64_t cached = -1;
+  uint64_t word = 0;
+  double a1 = 0.0, a2 = 0.0;
+  __device__ RecEpi(T ca_, T cb_, T* vm_, const ProbeSrc& s) : ca(ca_), cb(cb_), vm(vm_), src(s) {
+    const int lane = lane_id();
+    act = lane < src.active;
+    if (ZMODE == 1) key = sm_output(src.seed, (uint64_t)(src.first_id + lane));
+  }
+  __device__ __forceinline__ T prev(int64_t i) const {
+    return HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane_id()) : T(0);
+  }
+  __device__ __forceinline__ void finish(int64_t i, T acc, T xi, T xp) {
+    const int lane = lane_id();
+    T vn = ca * acc + cb * xi;
+    if (HAS_PREV) vn -= xp;
+    __builtin_nontemporal_store(vn, vm + i * 64 + lane);
+    if (ZMODE == 0) {
+      a1 += (double)xi * (double)vn;
+      a2 += (double)vn * (double)vn;
+    } else if (ZMODE == 1) {
+      const int64_t c = i >> 6;
+      if (c != cached) {
+        word = sm_output(key, (uint64_t)c);
+        cached = c;
+      }
+      a1 += sign_from_word<double>(word, i) * (double)vn;
+    } else {
+      const double z = act ? (double)src.entries[i * src.ld + src.first_id + lane] : 0.0;
+      a1 += z * (double)vn;
     }
-    acc1 += sign_from_word<double>(word, i) * (double)vn;
+  }
+};
+
+// Per-row epilogue of the triangle passes (int32 vectors, exact int64 sums):
+//   PASS 1: y = A z stored, slot 0 = z.y, slot 1 = y.y
+//   PASS 2: w = A y not stored, slot 0 = y.w.
+// |y_i| <= deg(i) and |w_i| <= nnz < 2^31, so int32 holds every entry.
+template <int PASS>
+struct TriEpi {
+  using Part = long long;
+  int32_t* vout;
+  long long a1 = 0, a2 = 0;
+  __device__ explicit TriEpi(int32_t* v) : vout(v) {}
+  __device__ __forceinline__ int32_t prev(int64_t) const { return 0; }
+  __device__ __forceinline__ void finish(int64_t i, int32_t acc, int32_t own, int32_t) {
+    if (PASS == 1) {
+      vout[i * 64 + lane_id()] = acc;
+      a1 += (long long)own * acc;
+      a2 += (long long)acc * acc;
+    } else {
+      a1 += (long long)own * acc;
+    }
+  }
+};
+
+// One gathered entry into a row sum: weight w (ignored for patterns) times x,
+// or nothing when on is false.
+template <typename T, bool PATTERN>
+__device__ __forceinline__ T accum(T acc, float w, bool on, T x) {
+  if constexpr (std::is_integral<T>::value) {
+    return acc + (on ? x : T(0));
   } else {
-    const double z = act ? (double)src.entries[i * src.ld + src.first_id + lane] : 0.0;
-    acc1 += z * (double)vn;
+    const float onf = on ? 1.f : 0.f;
+    const float ww = PATTERN ? onf : w * onf;
+    return fma((T)ww, x, acc);
   }
 }
 
@@ -128,53 +193,81 @@ struct RowReader {
     }
   }
   __device__ __forceinline__ T operator()(int64_t j, int lane) const {
-    if (OFF32) {
+    if constexpr (OFF32) {
+      static_assert(sizeof(T) == 4, "32-bit offsets are for 4-byte elements");
       const uint32_t bits = __builtin_amdgcn_raw_buffer_load_b32(
           rsrc, lane_off, (int)((uint32_t)j * (uint32_t)(64 * sizeof(T))), 0);
-      return __uint_as_float(bits);
+      if constexpr (std::is_integral<T>::value) return (T)bits;
+      else return __uint_as_float(bits);
+    } else {
+      return base[j * 64 + lane];
     }
-    return base[j * 64 + lane];
   }
 };
 
-// Generic row: loop over 64-entry chunks of the row's columns.
-template <typename T, bool PATTERN>
+// Generic row: 64-entry chunks of the row's columns, each loaded in one
+// coalesced read, then gathered 16 at a time (all 16 in flight before the
+// first is consumed; slots past the end gather the chunk's last row with
+// weight 0).
+constexpr int kGen = 16;
+
+template <typename T, bool PATTERN, class RD>
 __device__ __forceinline__ T row_dot_generic(const int32_t* __restrict__ col,
-                                             const float* __restrict__ val,
-                                             const T* __restrict__ vk, int s, int e) {
+                                             const float* __restrict__ val, const RD& rd,
+                                             int64_t s, int64_t e) {
   const int lane = lane_id();
   T acc = T(0);
-  for (int base = s; base < e; base += 64) {
-    const int c = min(64, e - base);
-    int cj = 0;
-    float av = 0.f;
-    if (lane < c) {
-      cj = col[base + lane];
-      if (!PATTERN) av = val[base + lane];
-    }
-    int t = 0;
-    for (; t + 4 <= c; t += 4) {
-      const T x0 = vk[(int64_t)read_lane(cj, t) * 64 + lane];
-      const T x1 = vk[(int64_t)read_lane(cj, t + 1) * 64 + lane];
-      const T x2 = vk[(int64_t)read_lane(cj, t + 2) * 64 + lane];
-      const T x3 = vk[(int64_t)read_lane(cj, t + 3) * 64 + lane];
-      if (PATTERN) {
-        acc += (x0 + x1) + (x2 + x3);
-      } else {
-        acc = fma((T)read_lane(av, t), x0, acc);
-        acc = fma((T)read_lane(av, t + 1), x1, acc);
-        acc = fma((T)read_lane(av, t + 2), x2, acc);
-        acc = fma((T)read_lane(av, t + 3), x3, acc);
-      }
-    }
-    for (; t < c; ++t) {
-      const T x = vk[(int64_t)read_lane(cj, t) * 64 + lane];
-      if (PATTERN)
-        acc += x;
-      else
-        acc = fma((T)read_lane(av, t), x, acc);
+  for (int64_t base = s; base < e; base += 64) {
+    const int c = (int)min<int64_t>(64, e - base);
+    const int64_t ce = base + min(lane, c - 1);
+    const int cj = col[ce];
+    const float av = PATTERN ? 1.f : val[ce];
+    for (int t = 0; t < c; t += kGen) {
+      T x[kGen];
+#pragma unroll
+      for (int u = 0; u < kGen; ++u) x[u] = rd(read_lane(cj, min(t + u, c - 1)), lane);
+#pragma unroll
+      for (int u = 0; u < kGen; ++u)
+        acc = accum<T, PATTERN>(acc, PATTERN ? 1.f : read_lane(av, min(t + u, c - 1)),
+                                t + u < c, x[u]);
     }
   }
+  return acc;
+}
+
+// A row as consecutive chunks of kHubChunk entries, each reduced on its own
+// and the chunk sums added in order: the association the hub path uses, so a
+// row's sum is bitwise the same whether or not its chunks ran as a hub.
+template <typename T, bool PATTERN, class RD>
+__device__ __forceinline__ T row_dot_chunked(const int32_t* __restrict__ col,
+                                             const float* __restrict__ val, const RD& rd,
+                                             int64_t s, int64_t e) {
+  T acc = T(0);
+  for (int64_t c0 = s; c0 < e; c0 += kHubChunk)
+    acc += row_dot_generic<T, PATTERN>(col, val, rd, c0, min<int64_t>(c0 + kHubChunk, e));
+  return acc;
+}
+
+// Hub rows: sorted row ids, the first chunk of each (hub_c0[k] .. hub_c0[k+1]),
+// and the chunk partials of the current step (chunk-major, 64 lanes each).
+struct HubView {
+  const int32_t* rows;
+  const int32_t* c0;
+  int n;
+  const void* part;
+};
+
+template <typename T>
+__device__ __forceinline__ T hub_sum(const HubView& h, int64_t i) {
+  int lo = 0, hi = h.n - 1;  // the row is in the table
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (h.rows[mid] < i) lo = mid + 1; else hi = mid;
+  }
+  const int c0 = h.c0[lo], c1 = h.c0[lo + 1];
+  const T* p = static_cast<const T*>(h.part);
+  T acc = T(0);
+  for (int c = c0; c < c1; ++c) acc += p[(int64_t)c * 64 + lane_id()];
   return acc;
 }
 
@@ -213,25 +306,20 @@ __device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int q, 
 // load, issued while the previous group's gathers are in flight.  When every
 // row of a group has at most MAXNZ entries its gathers are straight-line code
 // (unused slots gather some valid row with weight 0), all in flight before
-// the first is consumed; other groups take the generic loop.
-template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
+// the first is consumed; other groups take the generic loop, or with HUBS
+// the chunk partials of rows longer than kHubLen.
+template <typename T, bool PATTERN, int MAXNZ, bool OFF32, bool HUBS, class Epi>
 __device__ __forceinline__ void csr_step_wg(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
-    T* __restrict__ vm, T ca, T cb, const ProbeSrc& src, int rows_per_group, int ngroups,
-    double* __restrict__ part, int bid) {
+    const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk, Epi& epi,
+    const HubView& hub, int rows_per_group, int ngroups, typename Epi::Part* __restrict__ part,
+    int bid) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
   constexpr int GPB = 64 / ROWS;  // groups per batch
   const int lane = lane_id(), wave = wave_id();
   const int g = xcd_band(bid, ngroups);
   const int64_t r0 = (int64_t)g * rows_per_group;
   const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
-  const bool act = lane < src.active;
-  uint64_t key = 0;
-  if (ZMODE == 1) key = sm_output(src.seed, (uint64_t)(src.first_id + lane));
-  int64_t cached = -1;
-  uint64_t word = 0;
-  double acc1 = 0.0, acc2 = 0.0;
 
   const int64_t ngrp = r1 > r0 ? (r1 - r0 + ROWS - 1) / ROWS : 0;  // groups in the band
   const int64_t nk = ngrp > wave ? (ngrp - wave + kWaves - 1) / kWaves : 0;  // this wave's
@@ -278,7 +366,7 @@ __device__ __forceinline__ void csr_step_wg(
 #pragma unroll
           for (int t = 0; t < MAXNZ; ++t) x[r][t] = rd(read_lane(cj, min(cur.off[r] + t, 63)), lane);
           xi[r] = rd(i, lane);
-          xp[r] = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
+          xp[r] = epi.prev(i);
         }
       }
       // next group: extent and column prefetch
@@ -299,26 +387,23 @@ __device__ __forceinline__ void csr_step_wg(
         for (int r = 0; r < ROWS; ++r) {
           T acc = T(0);
 #pragma unroll
-          for (int t = 0; t < MAXNZ; ++t) {
-            const float on = (t < cur.len[r]) ? 1.f : 0.f;
-            const float w = PATTERN ? on : read_lane(av, min(cur.off[r] + t, 63)) * on;
-            acc = fma((T)w, x[r][t], acc);
-          }
-          if (r < cur.nr)
-            finish_row<T, ZMODE, HAS_PREV>(row0 + r, acc, xi[r], xp[r], ca, cb, vm, src, act,
-                                           key, cached, word, acc1, acc2);
+          for (int t = 0; t < MAXNZ; ++t)
+            acc = accum<T, PATTERN>(acc, PATTERN ? 1.f : read_lane(av, min(cur.off[r] + t, 63)),
+                                    t < cur.len[r], x[r][t]);
+          if (r < cur.nr) epi.finish(row0 + r, acc, xi[r], xp[r]);
         }
       } else {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {  // static indices: cur stays in registers
           if (r < cur.nr) {
             const int64_t i = row0 + r;
-            const int s0 = cur.gs + cur.off[r];
-            const T acc = row_dot_generic<T, PATTERN>(col, val, vk, s0, s0 + cur.len[r]);
-            const T xi1 = vk[i * 64 + lane];
-            const T xp1 = HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane) : T(0);
-            finish_row<T, ZMODE, HAS_PREV>(i, acc, xi1, xp1, ca, cb, vm, src, act, key, cached,
-                                           word, acc1, acc2);
+            const int64_t s0 = (int64_t)cur.gs + cur.off[r];
+            T acc;
+            if (HUBS && cur.len[r] > kHubLen)
+              acc = hub_sum<T>(hub, i);
+            else
+              acc = row_dot_chunked<T, PATTERN>(col, val, rd, s0, s0 + cur.len[r]);
+            epi.finish(i, acc, rd(i, lane), epi.prev(i));
           }
         }
       }
@@ -335,18 +420,65 @@ __device__ __forceinline__ void csr_step_wg(
       av = avn;
     }
   }
-  store_partials<T>(acc1, acc2, g, ngroups, part);
+  store_partials<typename Epi::Part>(epi.a1, epi.a2, g, ngroups, part);
 }
 
-template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
+template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32, bool HUBS>
 __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
-    T* __restrict__ vm, T ca, T cb, ProbeSrc src, int rows_per_group, int ngroups,
+    T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub, int rows_per_group, int ngroups,
     double* __restrict__ part) {
-  csr_step_wg<T, PATTERN, ZMODE, HAS_PREV, MAXNZ, OFF32>(rowptr, col, val, d, nnz, vk, vm, ca,
-                                                         cb, src, rows_per_group, ngroups, part,
-                                                         blockIdx.x);
+  RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
+  csr_step_wg<T, PATTERN, MAXNZ, OFF32, HUBS>(rowptr, col, val, d, nnz, vk, epi, hub,
+                                              rows_per_group, ngroups, part, blockIdx.x);
+}
+
+// Integer pass of triangle counting over a pattern CSR: vin = z (PASS 1,
+// y = A z written to vout) or y (PASS 2).
+template <int PASS, int MAXNZ, bool OFF32, bool HUBS>
+__global__ __launch_bounds__(kThreads) void tri_step_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t d, int64_t nnz,
+    const int32_t* __restrict__ vin, int32_t* __restrict__ vout, HubView hub,
+    int rows_per_group, int ngroups, long long* __restrict__ part) {
+  TriEpi<PASS> epi(vout);
+  csr_step_wg<int32_t, true, MAXNZ, OFF32, HUBS>(rowptr, col, nullptr, d, nnz, vin, epi, hub,
+                                                 rows_per_group, ngroups, part, blockIdx.x);
+}
+
+// Chunk partials of the hub rows: one wave per chunk of at most kHubChunk
+// entries, sum over the chunk of A[i][j] V_k[j] (exact for int32).
+template <typename T, bool PATTERN, bool OFF32>
+__global__ __launch_bounds__(256) void csr_hub_kernel(const int32_t* __restrict__ col,
+                                                      const float* __restrict__ val, int64_t d,
+                                                      const T* __restrict__ vk,
+                                                      const int32_t* __restrict__ cs,
+                                                      const int32_t* __restrict__ ce,
+                                                      int nchunks, T* __restrict__ out) {
+  const int c = blockIdx.x * 4 + wave_id();
+  if (c >= nchunks) return;
+  const int lane = lane_id();
+  const RowReader<T, OFF32> rd(vk, d, lane);
+  out[(int64_t)c * 64 + lane] = row_dot_generic<T, PATTERN>(col, val, rd, cs[c], ce[c]);
+}
+
+// Rows longer than kHubLen: (row, start, end) triples in any order; the host
+// sorts them by row.
+__global__ __launch_bounds__(256) void hub_find_kernel(const int32_t* __restrict__ rowptr,
+                                                       int64_t d, int32_t* __restrict__ out,
+                                                       int32_t* __restrict__ count, int cap) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * 256) {
+    const int32_t s = rowptr[i], e = rowptr[i + 1];
+    if (e - s > kHubLen) {
+      const int slot = atomicAdd(count, 1);
+      if (slot < cap) {
+        out[3 * (int64_t)slot] = (int32_t)i;
+        out[3 * (int64_t)slot + 1] = s;
+        out[3 * (int64_t)slot + 2] = e;
+      }
+    }
+  }
 }
 
 // ---- batches of probe blocks over many operators -----------------------------
@@ -373,9 +505,11 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   float* vm = s & 1 ? B.v1 : B.v0;
   const float ca = (float)(HAS_PREV ? 2.0 * B.alpha : B.alpha);
   const float cb = (float)(HAS_PREV ? 2.0 * B.beta : B.beta);
-  csr_step_wg<float, PATTERN, ZMODE, HAS_PREV, MAXNZ, true>(
-      B.rowptr, B.col, B.val, B.d, B.nnz, vk, vm, ca, cb, B.src, B.rows_per_group, B.ngroups,
-      B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+  RecEpi<float, ZMODE, HAS_PREV> epi(ca, cb, vm, B.src);
+  const HubView nohub{nullptr, nullptr, 0, nullptr};
+  csr_step_wg<float, PATTERN, MAXNZ, true, false>(B.rowptr, B.col, B.val, B.d, B.nnz, vk, epi,
+                                                  nohub, B.rows_per_group, B.ngroups,
+                                                  B.part + (size_t)s * 2 * B.ngroups * 64, bid);
 }
 
 __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
@@ -386,53 +520,110 @@ __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
   probe_init_wg<float>(B.v0, B.d, B.src, B.rows_per_group, B.ngroups, B.part, bid);
 }
 
-template <typename T, bool PATTERN, int ZMODE, int MAXNZ, bool OFF32>
+template <typename T, bool PATTERN, int ZMODE, int MAXNZ, bool OFF32, bool HUBS>
 hipError_t launch_step_t(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
-                         bool has_prev, ProbeSrc src, const CsrStepPlan& plan, double* part) {
+                         bool has_prev, ProbeSrc src, const CsrStepPlan& plan, const HubView& hub,
+                         double* part) {
   const dim3 grid(plan.ngroups), block(kThreads);
   const float* val = static_cast<const float*>(op->val);
   if (has_prev)
-    csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32><<<grid, block, 0, s>>>(
-        op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, plan.rows_per_group,
+    csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32, HUBS><<<grid, block, 0, s>>>(
+        op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
         plan.ngroups, part);
   else
-    csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32><<<grid, block, 0, s>>>(
-        op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, plan.rows_per_group,
+    csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32, HUBS><<<grid, block, 0, s>>>(
+        op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
         plan.ngroups, part);
   return hipGetLastError();
 }
 
+// Whether a block's gathers can use 32-bit offsets (4-byte elements, block
+// under 4 GiB).
+template <typename T>
+bool block_off32(const mlct_op* op) {
+  return sizeof(T) == 4 && (uint64_t)op->d * 64 * sizeof(T) <= 0xFFFFFFFFull;
+}
+
+// Hub chunk partials of vk for this step (a no-op without hub rows).
+template <typename T, bool PATTERN>
+hipError_t launch_hubs(hipStream_t s, const mlct_op* op, const T* vk, void* hub_part) {
+  if (op->hub_n == 0) return hipSuccess;
+  const int grid = (op->hub_chunks + 3) / 4;
+  const float* val = static_cast<const float*>(op->val);
+  T* out = static_cast<T*>(hub_part);
+  if constexpr (sizeof(T) == 4) {
+    if (block_off32<T>(op)) {
+      csr_hub_kernel<T, PATTERN, true><<<grid, 256, 0, s>>>(op->col, val, op->d, vk, op->hub_cs,
+                                                           op->hub_ce, op->hub_chunks, out);
+      return hipGetLastError();
+    }
+  }
+  csr_hub_kernel<T, PATTERN, false><<<grid, 256, 0, s>>>(op->col, val, op->d, vk, op->hub_cs,
+                                                        op->hub_ce, op->hub_chunks, out);
+  return hipGetLastError();
+}
+
 // Row capacity of the straight-line path: the smallest of {4, 5, 8} that
-// holds the longest row, else 8 (longer rows then take the generic loop).
-// FP32 blocks under 4 GiB use 32-bit gather offsets; FP64 (a verification
-// precision) uses one general instantiation.
+// holds the longest row, else 8 (longer rows then take the generic loop, and
+// rows past kHubLen the hub partials).  FP32 blocks under 4 GiB use 32-bit
+// gather offsets; FP64 (a verification precision) uses one general
+// instantiation.
 template <typename T, bool PATTERN, int ZMODE>
 hipError_t launch_step_nz(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
-                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, double* part) {
-  const bool off32 = (uint64_t)op->d * 64 * sizeof(T) <= 0xFFFFFFFFull;
-  if (sizeof(T) == 4 && off32) {
-    if (op->max_row_nnz <= 4)
-      return launch_step_t<T, PATTERN, ZMODE, 4, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-    if (op->max_row_nnz <= 5)
-      return launch_step_t<T, PATTERN, ZMODE, 5, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-    return launch_step_t<T, PATTERN, ZMODE, 8, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, void* hub_part,
+                          double* part) {
+  const HubView hub{op->hub_rows, op->hub_c0, op->hub_n, hub_part};
+  if (op->hub_n > 0) {
+    const hipError_t e = launch_hubs<T, PATTERN>(s, op, vk, hub_part);
+    if (e != hipSuccess) return e;
   }
-  return launch_step_t<T, PATTERN, ZMODE, 8, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+  if constexpr (sizeof(T) == 4) {
+    if (block_off32<T>(op)) {
+      if (op->hub_n > 0)
+        return launch_step_t<T, PATTERN, ZMODE, 8, true, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
+      if (op->max_row_nnz <= 4)
+        return launch_step_t<T, PATTERN, ZMODE, 4, true, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
+      if (op->max_row_nnz <= 5)
+        return launch_step_t<T, PATTERN, ZMODE, 5, true, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
+      return launch_step_t<T, PATTERN, ZMODE, 8, true, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
+    }
+  }
+  if (op->hub_n > 0)
+    return launch_step_t<T, PATTERN, ZMODE, 8, false, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
+  return launch_step_t<T, PATTERN, ZMODE, 8, false, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
 }
 
 template <typename T>
 hipError_t launch_step_any(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
-                           double* part) {
+                           void* hub_part, double* part) {
   const bool pat = op->val == nullptr;
   if (pat) {
-    if (zmode == 0) return launch_step_nz<T, true, 0>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-    if (zmode == 1) return launch_step_nz<T, true, 1>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-    return launch_step_nz<T, true, 2>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+    if (zmode == 0) return launch_step_nz<T, true, 0>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+    if (zmode == 1) return launch_step_nz<T, true, 1>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+    return launch_step_nz<T, true, 2>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
   }
-  if (zmode == 0) return launch_step_nz<T, false, 0>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-  if (zmode == 1) return launch_step_nz<T, false, 1>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
-  return launch_step_nz<T, false, 2>(s, op, vk, vm, ca, cb, has_prev, src, plan, part);
+  if (zmode == 0) return launch_step_nz<T, false, 0>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+  if (zmode == 1) return launch_step_nz<T, false, 1>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+  return launch_step_nz<T, false, 2>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+}
+
+template <int PASS, bool OFF32>
+hipError_t launch_tri_pass(hipStream_t s, const mlct_op* op, const CsrStepPlan& plan,
+                           const int32_t* vin, int32_t* vout, const HubView& hub,
+                           long long* part) {
+  const dim3 grid(plan.ngroups), block(kThreads);
+#define MLCT_TRI(M, H)                                                                        \
+  tri_step_kernel<PASS, M, OFF32, H><<<grid, block, 0, s>>>(op->rowptr, op->col, op->d,        \
+                                                            op->nnz, vin, vout, hub,          \
+                                                            plan.rows_per_group, plan.ngroups, \
+                                                            part)
+  if (op->hub_n > 0) MLCT_TRI(8, true);
+  else if (op->max_row_nnz <= 4) MLCT_TRI(4, false);
+  else if (op->max_row_nnz <= 5) MLCT_TRI(5, false);
+  else MLCT_TRI(8, false);
+#undef MLCT_TRI
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -460,8 +651,30 @@ hipError_t launch_probe_init(hipStream_t s, T* v0, int64_t d, ProbeSrc src,
 template <typename T>
 hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
-                           double* part) {
-  return launch_step_any<T>(s, op, vk, vm, ca, cb, has_prev, zmode, src, plan, part);
+                           void* hub_part, double* part) {
+  return launch_step_any<T>(s, op, vk, vm, ca, cb, has_prev, zmode, src, plan, hub_part, part);
+}
+
+hipError_t launch_tri_step(hipStream_t s, const mlct_op* op, int pass, const CsrStepPlan& plan,
+                           const int32_t* vin, int32_t* vout, void* hub_part, long long* part) {
+  const HubView hub{op->hub_rows, op->hub_c0, op->hub_n, hub_part};
+  if (op->hub_n > 0) {
+    const hipError_t e = launch_hubs<int32_t, true>(s, op, vin, hub_part);
+    if (e != hipSuccess) return e;
+  }
+  const bool off32 = block_off32<int32_t>(op);
+  if (pass == 1)
+    return off32 ? launch_tri_pass<1, true>(s, op, plan, vin, vout, hub, part)
+                 : launch_tri_pass<1, false>(s, op, plan, vin, vout, hub, part);
+  return off32 ? launch_tri_pass<2, true>(s, op, plan, vin, nullptr, hub, part)
+               : launch_tri_pass<2, false>(s, op, plan, vin, nullptr, hub, part);
+}
+
+hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
+                           int32_t* count, int cap) {
+  const int64_t blocks = std::min<int64_t>((d + 255) / 256, 4096);
+  hub_find_kernel<<<(int)blocks, 256, 0, s>>>(rowptr, d, out, count, cap);
+  return hipGetLastError();
 }
 
 hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
@@ -496,9 +709,9 @@ template hipError_t launch_probe_init<double>(hipStream_t, double*, int64_t, Pro
                                               const CsrStepPlan&, double*);
 template hipError_t launch_csr_step<float>(hipStream_t, const mlct_op*, const float*, float*,
                                            float, float, bool, int, ProbeSrc,
-                                           const CsrStepPlan&, double*);
+                                           const CsrStepPlan&, void*, double*);
 template hipError_t launch_csr_step<double>(hipStream_t, const mlct_op*, const double*,
                                             double*, double, double, bool, int, ProbeSrc,
-                                            const CsrStepPlan&, double*);
+                                            const CsrStepPlan&, void*, double*);
 
 }  // namespace mlct

@@ -295,16 +295,15 @@ __global__ __launch_bounds__(64 * WM * WN) void dense_step_kernel(
 // one load in flight, so the step would be latency-bound.  Here a workgroup
 // owns all BM probes of its tile against only 16 matrix rows, and its four
 // waves split the k range between them (split-K inside the workgroup):
-// wave w takes chunks w, w+4, ... of KC = 4E columns, with lane group
-// g = lane / 16 covering E contiguous columns of its row (64 bytes of V and
-// of each part of A per lane), the next chunk prefetched into registers
-// while the current one is on the matrix cores.  No LDS staging: the MFMA
+// wave w takes chunks w, w+4, ... of KC = 4E columns, each lane loading E
+// columns of its row (64 bytes of V), the next chunks prefetched into
+// registers while the current one is on the matrix cores.  No LDS staging: the MFMA
 // operands come straight from the registers the loads filled, since the
 // assignment of columns to an MFMA's k slots only has to agree between the
 // two operands.  The four partial accumulators are summed through LDS in a
 // fixed wave order, and wave a runs the epilogue of probe tile a.
-template <int PREC, int TM, int ZMODE, bool HAS_PREV>
-__global__ __launch_bounds__(256) void dense_skinny_kernel(
+template <int PREC, int TM, int W, int ZMODE, bool HAS_PREV>
+__global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
     const void* __restrict__ A0, const void* __restrict__ A1, int64_t lda, int64_t d,
     const typename Prec<PREC>::V* __restrict__ vk, typename Prec<PREC>::V* __restrict__ vm,
     typename Prec<PREC>::V ca, typename Prec<PREC>::V cb, ProbeSrc src, int mtiles, int ntiles,
@@ -313,11 +312,19 @@ __global__ __launch_bounds__(256) void dense_skinny_kernel(
   using VT = typename P::V;
   using MT = typename P::M;
   using AccT = typename P::Acc;
-  constexpr int W = 4, BM = TM * 16;
+  constexpr int BM = TM * 16;
   constexpr int E = PREC == 0 ? 8 : 16;  // columns per lane per chunk
   constexpr int KC = 4 * E;              // columns per chunk
-  constexpr int QA = 16 / (int)sizeof(MT), QV = 16 / (int)sizeof(VT);
-  constexpr int NA = E / QA, NV = E / QV;  // 16-byte pieces per lane per chunk
+  // Each lane loads its E columns as pieces of Q elements (16 bytes of V;
+  // 16 bytes of A, 8 for bf16), and piece p of lane group g holds columns
+  // kbase + 4Qp + Qg + [0, Q): the four lanes that share a row read
+  // 4Q contiguous columns per load instruction (64 bytes of V), so one
+  // instruction touches 16 rows x one 64-byte segment rather than four.
+  // Element e = pQ + q of a lane is the same column in A and in V, which is
+  // all the MFMA k-slot assignment needs.
+  constexpr int Q = 16 / (int)sizeof(VT);
+  constexpr int QA = Q, QV = Q;
+  constexpr int NA = E / QA, NV = E / QV;  // pieces per lane per chunk
   constexpr int NSPLIT = PREC == 2 ? 2 : 1;
   typedef MT aq __attribute__((ext_vector_type(QA)));
   typedef VT vq __attribute__((ext_vector_type(QV)));
@@ -343,28 +350,37 @@ __global__ __launch_bounds__(256) void dense_skinny_kernel(
 #pragma unroll
   for (int a = 0; a < TM; ++a) vrow[a] = vk + (m0 + a * 16 + rl) * d;
 
-  AccT acc[TM];
+  // NS accumulators per probe tile, so that consecutive MFMAs of one wave
+  // are independent (a chain of dependent MFMAs issues at a fraction of the
+  // matrix-core rate): bf16x3 keeps one per product (hi*hi, hi*lo, lo*hi),
+  // FP32 and FP64 one per k slot modulo NS.  Summed in a fixed order.
+  constexpr int NS = PREC == 2 ? 3 : (PREC == 1 ? 2 : 1);
+  AccT acc[TM][NS];
 #pragma unroll
-  for (int a = 0; a < TM; ++a) acc[a] = AccT{};
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int q = 0; q < NS; ++q) acc[a][q] = AccT{};
 
   aq ra[NSPLIT][NA], xa[NSPLIT][NA];
   vq rv[TM][NV], xv[TM][NV];
   auto load = [&](int64_t c, aq (&ta)[NSPLIT][NA], vq (&tv)[TM][NV]) {
-    const int64_t k = c * KC + g * E;
+    const int64_t k = c * KC + g * Q;
 #pragma unroll
     for (int h = 0; h < NSPLIT; ++h)
 #pragma unroll
-      for (int p = 0; p < NA; ++p) ta[h][p] = *reinterpret_cast<const aq*>(arow[h] + k + p * QA);
+      for (int p = 0; p < NA; ++p)
+        ta[h][p] = *reinterpret_cast<const aq*>(arow[h] + k + p * 4 * Q);
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
-      for (int p = 0; p < NV; ++p) tv[a][p] = *reinterpret_cast<const vq*>(vrow[a] + k + p * QV);
+      for (int p = 0; p < NV; ++p) tv[a][p] = *reinterpret_cast<const vq*>(vrow[a] + k + p * 4 * Q);
   };
   auto compute = [&](const aq (&ta)[NSPLIT][NA], const vq (&tv)[TM][NV]) {
     if constexpr (PREC == 2) {
 #pragma unroll
       for (int t = 0; t < E / 8; ++t) {
-        const bf8 bh = ta[0][t], bl = ta[1][t];
+        const bf8 bh = __builtin_shufflevector(ta[0][2 * t], ta[0][2 * t + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        const bf8 bl = __builtin_shufflevector(ta[1][2 * t], ta[1][2 * t + 1], 0, 1, 2, 3, 4, 5, 6, 7);
 #pragma unroll
         for (int a = 0; a < TM; ++a) {
           bf8 vh, vl;
@@ -375,9 +391,9 @@ __global__ __launch_bounds__(256) void dense_skinny_kernel(
             vh[q] = hi;
             vl[q] = lo;
           }
-          acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, bh, acc[a], 0, 0, 0);
-          acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, bl, acc[a], 0, 0, 0);
-          acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, bh, acc[a], 0, 0, 0);
+          acc[a][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, bh, acc[a][0], 0, 0, 0);
+          acc[a][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, bl, acc[a][1], 0, 0, 0);
+          acc[a][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, bh, acc[a][2], 0, 0, 0);
         }
       }
     } else {
@@ -388,24 +404,25 @@ __global__ __launch_bounds__(256) void dense_skinny_kernel(
         for (int a = 0; a < TM; ++a) {
           const VT x = tv[a][t / QV][t % QV];
           if constexpr (PREC == 0)
-            acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, b, acc[a], 0, 0, 0);
+            acc[a][t % NS] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, b, acc[a][t % NS], 0, 0, 0);
           else
-            acc[a] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b, acc[a], 0, 0, 0);
+            acc[a][t % NS] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b, acc[a][t % NS], 0, 0, 0);
         }
       }
     }
   };
 
-  // Two register buffers in turn: chunk i + 1 streams into one while chunk i
-  // is on the matrix cores from the other.  After each load group, an empty
-  // asm with a memory clobber keeps the compiler from merging the two loads
-  // that feed a loop-carried buffer into one load at the top of the loop,
-  // and a scheduling barrier keeps the instruction scheduler from sinking
-  // the loads down to their uses (either would turn the prefetch back into
-  // load-then-use).
+  // Two register buffers in turn: chunk i + 1 streams into one while chunk
+  // i is on the matrix cores from the other.  After each load group, an
+  // empty asm with a memory clobber keeps the compiler from merging the
+  // loads that feed a loop-carried buffer into one load at the top of the
+  // loop, and a scheduling barrier keeps the instruction scheduler from
+  // sinking the loads down to their uses (either would turn the prefetch
+  // back into load-then-use).  Past the last chunk a load re-reads that
+  // chunk (a cache hit), so every load in the loop is unconditional.
   const int64_t nfull = d / KC;
   const int64_t mine = wave < nfull ? (nfull - wave + W - 1) / W : 0;  // chunks of this wave
-  auto chunk = [&](int64_t i) { return (int64_t)wave + i * W; };
+  auto chunk = [&](int64_t i) { return (int64_t)wave + (i < mine ? i : mine - 1) * W; };
   if (mine > 0) {
     load(chunk(0), ra, rv);
     asm volatile("" ::: "memory");
@@ -416,9 +433,7 @@ __global__ __launch_bounds__(256) void dense_skinny_kernel(
       asm volatile("" ::: "memory");
       __builtin_amdgcn_sched_barrier(0);
       compute(ra, rv);
-      // past the last chunk this re-reads it (a cache hit), so every load
-      // in the loop is unconditional
-      load(chunk(i + 2 < mine ? i + 2 : mine - 1), ra, rv);
+      load(chunk(i + 2), ra, rv);
       asm volatile("" ::: "memory");
       __builtin_amdgcn_sched_barrier(0);
       compute(xa, xv);
@@ -427,14 +442,14 @@ __global__ __launch_bounds__(256) void dense_skinny_kernel(
   }
   // ragged tail [nfull * KC, d): element loads, zero past d in both operands
   if (nfull * KC < d && wave == (int)(nfull % W)) {
-    const int64_t k0 = nfull * KC + g * E;
+    const int64_t k0 = nfull * KC + g * Q;
 #pragma unroll
     for (int h = 0; h < NSPLIT; ++h)
 #pragma unroll
       for (int p = 0; p < NA; ++p)
 #pragma unroll
-        for (int q = 0; q < QA; ++q) {
-          const int64_t k = k0 + p * QA + q;
+        for (int q = 0; q < Q; ++q) {
+          const int64_t k = k0 + p * 4 * Q + q;
           ra[h][p][q] = k < d ? arow[h][k] : MT(0.f);
         }
 #pragma unroll
@@ -442,15 +457,20 @@ __global__ __launch_bounds__(256) void dense_skinny_kernel(
 #pragma unroll
       for (int p = 0; p < NV; ++p)
 #pragma unroll
-        for (int q = 0; q < QV; ++q) {
-          const int64_t k = k0 + p * QV + q;
+        for (int q = 0; q < Q; ++q) {
+          const int64_t k = k0 + p * 4 * Q + q;
           rv[a][p][q] = k < d ? vrow[a][k] : VT(0);
         }
     compute(ra, rv);
   }
 
 #pragma unroll
-  for (int a = 0; a < TM; ++a) red[wave][a][lane] = acc[a];
+  for (int a = 0; a < TM; ++a) {
+    AccT t = acc[a][0];
+#pragma unroll
+    for (int q = 1; q < NS; ++q) t += acc[a][q];
+    red[wave][a][lane] = t;
+  }
   __syncthreads();
   if (wave >= TM) return;
 
@@ -649,7 +669,7 @@ hipError_t launch_dense_cfg(hipStream_t s, const DenseStepArgs& a) {
   return hipGetLastError();
 }
 
-template <int PREC, int TM>
+template <int PREC, int TM, int W>
 hipError_t launch_skinny_cfg(hipStream_t s, const DenseStepArgs& a) {
   using VT = typename Prec<PREC>::V;
   const int mtiles = (int)(a.bpad / (TM * 16));
@@ -659,8 +679,8 @@ hipError_t launch_skinny_cfg(hipStream_t s, const DenseStepArgs& a) {
   const VT* vk = static_cast<const VT*>(a.vk);
   VT* vm = static_cast<VT*>(a.vm);
 #define MLCT_SKINNY_LAUNCH(Z, HP)                                                            \
-  dense_skinny_kernel<PREC, TM, Z, HP><<<grid, 256, 0, s>>>(a.A0, a.A1, a.lda, a.d, vk, vm, ca, \
-                                                          cb, a.src, mtiles, ntiles, a.part)
+  dense_skinny_kernel<PREC, TM, W, Z, HP><<<grid, 64 * W, 0, s>>>(                            \
+      a.A0, a.A1, a.lda, a.d, vk, vm, ca, cb, a.src, mtiles, ntiles, a.part)
   if (a.has_prev) {
     if (a.zmode == 0) MLCT_SKINNY_LAUNCH(0, true);
     else if (a.zmode == 1) MLCT_SKINNY_LAUNCH(1, true);
@@ -682,8 +702,8 @@ DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) 
   // that still gives a few hundred workgroups: 128 x 128, then 64 x 64, else
   // 32 x 32 (small problems are latency-bound; more workgroups win).
   // force: 0 = 32, 1 = 128, 2 = 64, 3 = skinny (when the block allows it).
-  const int qv = prec == MLCT_FP64 ? 2 : 4, qa = prec == MLCT_FP64 ? 2 : (prec == MLCT_FP32 ? 4 : 8);
-  const bool skinny_ok = d % qv == 0 && lda % qa == 0;
+  const int q = prec == MLCT_FP64 ? 2 : 4;  // elements per piece of the skinny kernel's loads
+  const bool skinny_ok = d % q == 0 && lda % q == 0;
   const int64_t n128 = (bpad / 128) * ((d + 127) / 128);
   const int64_t n64 = (bpad / 64) * ((d + 63) / 64);
   DenseTile t;
@@ -711,11 +731,12 @@ DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) 
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a) {
   const DenseTile t = dense_tile(prec, a.d, a.lda, a.bpad, a.tile_force);
   if (t.skinny) {
+    constexpr int W = 4;
     if (prec == MLCT_FP64)
-      return t.bm == 64 ? launch_skinny_cfg<0, 4>(s, a) : launch_skinny_cfg<0, 2>(s, a);
+      return t.bm == 64 ? launch_skinny_cfg<0, 4, W>(s, a) : launch_skinny_cfg<0, 2, W>(s, a);
     if (prec == MLCT_FP32)
-      return t.bm == 64 ? launch_skinny_cfg<1, 4>(s, a) : launch_skinny_cfg<1, 2>(s, a);
-    return t.bm == 64 ? launch_skinny_cfg<2, 4>(s, a) : launch_skinny_cfg<2, 2>(s, a);
+      return t.bm == 64 ? launch_skinny_cfg<1, 4, W>(s, a) : launch_skinny_cfg<1, 2, W>(s, a);
+    return t.bm == 64 ? launch_skinny_cfg<2, 4, W>(s, a) : launch_skinny_cfg<2, 2, W>(s, a);
   }
   if (prec == MLCT_FP64) {
     if (t.bm == 128) return launch_dense_cfg<0, 2, 2, 4, 4, 16>(s, a);

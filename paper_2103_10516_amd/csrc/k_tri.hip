@@ -2,11 +2,10 @@
 // and footnote, Section 5.5).  Per probe z, two integer SpMMs:
 //   pass 1: y = A z   (int32, stored), w1 += z_i y_i, w2 += y_i^2   (int64)
 //   pass 2: w = A y   (int32, never stored), w3 += y_i w_i           (int64)
-// |y_i| <= deg(i) and |w_i| <= sum of degrees = nnz < 2^31, so int32 holds
-// every vector entry and int64 every product and sum exactly.
+// The passes run on the CSR step machinery (k_csr.hip, launch_tri_step);
+// this file holds the probe fill, the reduction of the int64 partials and
+// the control-variate fit.
 // Layout as in the FP recurrence: blocks are row-major d x 64, lane = probe.
-// Every workgroup owns a contiguous band of rows and writes one int64
-// partial per probe and slot; the partials are summed afterwards.
 #include "device.hpp"
 
 namespace mlct {
@@ -15,25 +14,6 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * 64;
-
-__device__ __forceinline__ void store_partials_i64(long long a1, long long a2, int g,
-                                                   int ngroups, long long* __restrict__ part) {
-  __shared__ long long sh[2][kWaves][64];
-  const int lane = lane_id(), wave = wave_id();
-  sh[0][wave][lane] = a1;
-  sh[1][wave][lane] = a2;
-  __syncthreads();
-  if (wave == 0) {
-    long long s1 = 0, s2 = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      s1 += sh[0][w][lane];
-      s2 += sh[1][w][lane];
-    }
-    part[(size_t)g * 64 + lane] = s1;
-    part[((size_t)ngroups + g) * 64 + lane] = s2;
-  }
-}
 
 __global__ __launch_bounds__(kThreads) void tri_init_kernel(int32_t* __restrict__ z, int64_t d,
                                                             ProbeSrc src, int rows_per_group,
@@ -58,64 +38,6 @@ __global__ __launch_bounds__(kThreads) void tri_init_kernel(int32_t* __restrict_
     }
     z[i * 64 + lane] = v;
   }
-}
-
-// Row sum of a pattern row over a block: sum_{j in row} vin[j][lane].
-__device__ __forceinline__ int32_t pattern_row_sum(const int32_t* __restrict__ col,
-                                                   const int32_t* __restrict__ vin, int s, int e) {
-  const int lane = lane_id();
-  int32_t acc = 0;
-  for (int base = s; base < e; base += 64) {
-    const int c = min(64, e - base);
-    const int cj = lane < c ? col[base + lane] : 0;
-    int t = 0;
-    for (; t + 4 <= c; t += 4) {
-      const int32_t x0 = vin[(int64_t)read_lane(cj, t) * 64 + lane];
-      const int32_t x1 = vin[(int64_t)read_lane(cj, t + 1) * 64 + lane];
-      const int32_t x2 = vin[(int64_t)read_lane(cj, t + 2) * 64 + lane];
-      const int32_t x3 = vin[(int64_t)read_lane(cj, t + 3) * 64 + lane];
-      acc += (x0 + x1) + (x2 + x3);
-    }
-    for (; t < c; ++t) acc += vin[(int64_t)read_lane(cj, t) * 64 + lane];
-  }
-  return acc;
-}
-
-// PASS 1: vin = z, vout = y; slot 0 = z.y, slot 1 = y.y.
-// PASS 2: vin = y, vout unused; slot 0 = y.(A y), slot 1 = 0.
-template <int PASS>
-__global__ __launch_bounds__(kThreads) void tri_step_kernel(const int32_t* __restrict__ rowptr,
-                                                            const int32_t* __restrict__ col,
-                                                            int64_t d,
-                                                            const int32_t* __restrict__ vin,
-                                                            int32_t* __restrict__ vout,
-                                                            int rows_per_group, int ngroups,
-                                                            long long* __restrict__ part) {
-  const int lane = lane_id(), wave = wave_id();
-  const int g = xcd_band(blockIdx.x, ngroups);
-  const int64_t r0 = (int64_t)g * rows_per_group;
-  const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
-  long long a1 = 0, a2 = 0;
-  for (int64_t b0 = r0 + (int64_t)wave * 64; b0 < r1; b0 += kWaves * 64) {
-    const int nb = (int)min<int64_t>(64, r1 - b0);
-    const int64_t rl = b0 + min(lane, nb - 1);
-    const int rs = rowptr[rl];
-    const int re = rowptr[rl + 1];
-    for (int r = 0; r < nb; ++r) {
-      const int64_t i = b0 + r;
-      const int32_t s = read_lane(rs, r), e = read_lane(re, r);
-      const int32_t v = pattern_row_sum(col, vin, s, e);
-      const int32_t own = vin[i * 64 + lane];
-      if (PASS == 1) {
-        vout[i * 64 + lane] = v;
-        a1 += (long long)own * v;
-        a2 += (long long)v * v;
-      } else {
-        a1 += (long long)own * v;
-      }
-    }
-  }
-  store_partials_i64(a1, a2, g, ngroups, part);
 }
 
 // w[(p0 + p) * 3 + slot_out] = sum over groups of the partials.
@@ -217,18 +139,6 @@ hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
                            const CsrStepPlan& plan, int32_t* z) {
   tri_init_kernel<<<plan.ngroups, kThreads, 0, s>>>(z, op->d, src, plan.rows_per_group,
                                                     plan.ngroups);
-  return hipGetLastError();
-}
-
-hipError_t launch_tri_step(hipStream_t s, const mlct_op* op, int pass, const CsrStepPlan& plan,
-                           const int32_t* vin, int32_t* vout, long long* part) {
-  if (pass == 1)
-    tri_step_kernel<1><<<plan.ngroups, kThreads, 0, s>>>(op->rowptr, op->col, op->d, vin, vout,
-                                                         plan.rows_per_group, plan.ngroups, part);
-  else
-    tri_step_kernel<2><<<plan.ngroups, kThreads, 0, s>>>(op->rowptr, op->col, op->d, vin,
-                                                         nullptr, plan.rows_per_group,
-                                                         plan.ngroups, part);
   return hipGetLastError();
 }
 

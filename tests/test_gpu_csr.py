@@ -57,6 +57,9 @@ CASES = [
     ("lap2d_45", lambda: wl.laplacian_2d(45), 0.01, 8.01),
     ("random_ragged", lambda: wl.random_csr(301, 0.03, 4), -7.0, 7.0),
     ("chung_lu_pattern", lambda: wl.chung_lu(3000, seed=11), -60.0, 90.0),
+    # hub rows (45 rows past 256 entries, the longest 3896): chunked reduction
+    ("chung_lu_hubs", lambda: wl.chung_lu(8000, avg_degree=24, exponent=2.0, seed=31),
+     -3900.0, 3900.0),
 ]
 
 
@@ -70,6 +73,9 @@ def test_moments_match_oracle(ctx, torch_dev, name, builder, a, b, prec, mode):
     if name == "chung_lu_pattern":
         lam = np.linalg.eigvalsh(g.to_dense())
         assert a < lam.min() and lam.max() < b
+    if name == "chung_lu_hubs":  # Gershgorin: |lambda| <= the largest degree
+        deg = np.diff(g.rowptr)
+        assert deg.max() > 1000 and np.sum(deg > 256) > 10 and deg.max() < b
     n, m, seed, first = 37, 100, 12345, 7
     op = _op(ctx, torch_dev, g)
     P = mlct.MLCT_FP64 if prec == "fp64" else mlct.MLCT_FP32
