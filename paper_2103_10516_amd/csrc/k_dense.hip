@@ -315,15 +315,10 @@ __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
   constexpr int BM = TM * 16;
   constexpr int E = PREC == 0 ? 8 : 16;  // columns per lane per chunk
   constexpr int KC = 4 * E;              // columns per chunk
-  // Each lane loads its E columns as pieces of Q elements (16 bytes of V;
-  // 16 bytes of A, 8 for bf16), and piece p of lane group g holds columns
-  // kbase + 4Qp + Qg + [0, Q): the four lanes that share a row read
-  // 4Q contiguous columns per load instruction (64 bytes of V), so one
-  // instruction touches 16 rows x one 64-byte segment rather than four.
-  // Element e = pQ + q of a lane is the same column in A and in V, which is
-  // all the MFMA k-slot assignment needs.
-  constexpr int Q = 16 / (int)sizeof(VT);
-  constexpr int QA = Q, QV = Q;
+  // Lane group g = lane / 16 loads columns [g E, g E + E) of each chunk, as
+  // 16-byte pieces (QA elements of A, QV of V): element e of a lane is the
+  // same column in A and in V, which is all the MFMA k-slot assignment needs.
+  constexpr int QA = 16 / (int)sizeof(MT), QV = 16 / (int)sizeof(VT);
   constexpr int NA = E / QA, NV = E / QV;  // pieces per lane per chunk
   constexpr int NSPLIT = PREC == 2 ? 2 : 1;
   typedef MT aq __attribute__((ext_vector_type(QA)));
@@ -364,23 +359,21 @@ __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
   aq ra[NSPLIT][NA], xa[NSPLIT][NA];
   vq rv[TM][NV], xv[TM][NV];
   auto load = [&](int64_t c, aq (&ta)[NSPLIT][NA], vq (&tv)[TM][NV]) {
-    const int64_t k = c * KC + g * Q;
+    const int64_t k = c * KC + g * E;
 #pragma unroll
     for (int h = 0; h < NSPLIT; ++h)
 #pragma unroll
-      for (int p = 0; p < NA; ++p)
-        ta[h][p] = *reinterpret_cast<const aq*>(arow[h] + k + p * 4 * Q);
+      for (int p = 0; p < NA; ++p) ta[h][p] = *reinterpret_cast<const aq*>(arow[h] + k + p * QA);
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
-      for (int p = 0; p < NV; ++p) tv[a][p] = *reinterpret_cast<const vq*>(vrow[a] + k + p * 4 * Q);
+      for (int p = 0; p < NV; ++p) tv[a][p] = *reinterpret_cast<const vq*>(vrow[a] + k + p * QV);
   };
   auto compute = [&](const aq (&ta)[NSPLIT][NA], const vq (&tv)[TM][NV]) {
     if constexpr (PREC == 2) {
 #pragma unroll
       for (int t = 0; t < E / 8; ++t) {
-        const bf8 bh = __builtin_shufflevector(ta[0][2 * t], ta[0][2 * t + 1], 0, 1, 2, 3, 4, 5, 6, 7);
-        const bf8 bl = __builtin_shufflevector(ta[1][2 * t], ta[1][2 * t + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+        const bf8 bh = ta[0][t], bl = ta[1][t];
 #pragma unroll
         for (int a = 0; a < TM; ++a) {
           bf8 vh, vl;
@@ -442,14 +435,14 @@ __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
   }
   // ragged tail [nfull * KC, d): element loads, zero past d in both operands
   if (nfull * KC < d && wave == (int)(nfull % W)) {
-    const int64_t k0 = nfull * KC + g * Q;
+    const int64_t k0 = nfull * KC + g * E;
 #pragma unroll
     for (int h = 0; h < NSPLIT; ++h)
 #pragma unroll
       for (int p = 0; p < NA; ++p)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int64_t k = k0 + p * 4 * Q + q;
+        for (int q = 0; q < QA; ++q) {
+          const int64_t k = k0 + p * QA + q;
           ra[h][p][q] = k < d ? arow[h][k] : MT(0.f);
         }
 #pragma unroll
@@ -457,8 +450,8 @@ __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
 #pragma unroll
       for (int p = 0; p < NV; ++p)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int64_t k = k0 + p * 4 * Q + q;
+        for (int q = 0; q < QV; ++q) {
+          const int64_t k = k0 + p * QV + q;
           rv[a][p][q] = k < d ? vrow[a][k] : VT(0);
         }
     compute(ra, rv);
@@ -702,8 +695,9 @@ DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) 
   // that still gives a few hundred workgroups: 128 x 128, then 64 x 64, else
   // 32 x 32 (small problems are latency-bound; more workgroups win).
   // force: 0 = 32, 1 = 128, 2 = 64, 3 = skinny (when the block allows it).
-  const int q = prec == MLCT_FP64 ? 2 : 4;  // elements per piece of the skinny kernel's loads
-  const bool skinny_ok = d % q == 0 && lda % q == 0;
+  // the skinny kernel's 16-byte loads need 16-byte aligned rows of V and A
+  const int qv = prec == MLCT_FP64 ? 2 : 4, qa = prec == MLCT_FP64 ? 2 : (prec == MLCT_FP32 ? 4 : 8);
+  const bool skinny_ok = d % qv == 0 && lda % qa == 0;
   const int64_t n128 = (bpad / 128) * ((d + 127) / 128);
   const int64_t n64 = (bpad / 64) * ((d + 63) / 64);
   DenseTile t;

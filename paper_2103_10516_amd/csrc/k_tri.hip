@@ -40,22 +40,27 @@ __global__ __launch_bounds__(kThreads) void tri_init_kernel(int32_t* __restrict_
   }
 }
 
-// w[(p0 + p) * 3 + slot_out] = sum over groups of the partials.
-__global__ void tri_reduce_kernel(const long long* __restrict__ part, int ngroups, int active,
-                                  int pass, long long* __restrict__ w, int64_t p0) {
-  const int p = threadIdx.x;
-  if (p >= active) return;
-  long long s0 = 0, s1 = 0;
-  for (int g = 0; g < ngroups; ++g) {
-    s0 += part[(size_t)g * 64 + p];
-    s1 += part[((size_t)ngroups + g) * 64 + p];
+// w[(p0 + p) * 3 + slot_out] = sum over groups of the partials: one
+// workgroup per (probe, slot), a strided sum per thread and a tree in LDS
+// (int64, exact in any order).
+constexpr int kRedThreads = 256;
+
+__global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
+    const long long* __restrict__ part, int ngroups, int active, int pass,
+    long long* __restrict__ w, int64_t p0) {
+  __shared__ long long sh[kRedThreads];
+  const int p = blockIdx.x >> 1, slot = blockIdx.x & 1;
+  if (pass == 2 && slot == 1) return;
+  long long acc = 0;
+  for (int g = threadIdx.x; g < ngroups; g += kRedThreads)
+    acc += part[((size_t)slot * ngroups + g) * 64 + p];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
   }
-  if (pass == 1) {
-    w[(p0 + p) * 3 + 0] = s0;
-    w[(p0 + p) * 3 + 1] = s1;
-  } else {
-    w[(p0 + p) * 3 + 2] = s0;
-  }
+  if (threadIdx.x == 0) w[(p0 + p) * 3 + (pass == 1 ? slot : 2)] = sh[0];
 }
 
 // Control variates of Section 5.5: ordinary least squares of w3 on
@@ -144,7 +149,8 @@ hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
 
 hipError_t launch_tri_reduce(hipStream_t s, const long long* part, int ngroups, int active,
                              int pass, long long* w, int64_t p0) {
-  tri_reduce_kernel<<<1, 64, 0, s>>>(part, ngroups, active, pass, w, p0);
+  if (active <= 0) return hipSuccess;
+  tri_reduce_kernel<<<2 * active, kRedThreads, 0, s>>>(part, ngroups, active, pass, w, p0);
   return hipGetLastError();
 }
 
