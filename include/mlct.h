@@ -243,6 +243,60 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
                           const mlct_levels* levels, uint64_t seed, int32_t prec,
                           int32_t mode, mlct_result* out);
 
+/* Automatic level selection (Section 3.2, Theorem thm:levels).
+ *
+ * From a pilot table of per-probe terms t_j = c_j z^T T_j(A_hat) z
+ * (j = 0..n), the variance V_{l'l} of each level variable Q_{l'l}
+ * (eq. def:qlevels) is the pilot sample variance of sum_{j=l'+1}^{l} t_j; a
+ * sample of Q_{l'l} costs C(l) = l matvecs (MLCT_DIRECT) or ceil(l/2)
+ * (MLCT_DOUBLING), Section 3.1.  The levels minimise
+ * sum_k sqrt(V_{l_{k-1} l_k} C(l_k)) by the dynamic programme of Theorem
+ * thm:levels (eq. eqn:costrecurrence), with the top level n chosen under the
+ * condition of Section 3.2 that the allocation of eqs. eqn:optSamples /
+ * eqn:optMu recommends at least min_top samples for it.  Ties go to the
+ * smaller second-highest level; with no admissible choice the single level
+ * {n} is returned.  The j = 0 term belongs to the first level (its variance
+ * is zero for Rademacher probes).  Sample sizes are rounded up, at least 2.
+ *
+ * target_kind MLCT_TARGET_VARIANCE: target = eps^2, a variance of
+ * mlct_result.value (the estimate without its exp log_scale factor);
+ * MLCT_TARGET_BUDGET: target = total matvecs sum_k m_k C(l_k). */
+#define MLCT_TARGET_VARIANCE 0
+#define MLCT_TARGET_BUDGET 1
+#define MLCT_MAX_PLAN_DEGREE 1024
+
+typedef struct {
+  int32_t L;                          /* levels chosen                     */
+  int32_t degree[MLCT_MAX_LEVELS];    /* l_1 < ... < l_L = n               */
+  int64_t m[MLCT_MAX_LEVELS];         /* recommended samples per level     */
+  double var[MLCT_MAX_LEVELS];        /* pilot V_{l_{k-1} l_k}             */
+  double cost[MLCT_MAX_LEVELS];       /* C(l_k), matvecs per sample        */
+  double m_real[MLCT_MAX_LEVELS];     /* allocation before rounding        */
+  double opt_total;                   /* sum_k sqrt(V_k C_k) of the plan   */
+  double single_total;                /* sqrt(V_{0n} C(n)): single level   */
+  double predicted_var;               /* sum_k var_k / m_k                 */
+  double predicted_cost;              /* sum_k m_k cost_k                  */
+} mlct_level_plan;
+
+/* Plan from a given pilot term table.  terms: host, m_pilot x (n+1) FP64
+ * row-major; 1 <= n <= MLCT_MAX_PLAN_DEGREE; m_pilot >= 2; target > 0;
+ * mode MLCT_DIRECT or MLCT_DOUBLING (sets C(l)).  Errors: EINVAL for
+ * arguments, ERANGE if the optimum has more than MLCT_MAX_LEVELS levels. */
+mlct_status mlct_plan_levels(mlct_ctx* ctx, const double* terms, int64_t m_pilot, int32_t n,
+                             int32_t mode, double target, int32_t target_kind,
+                             int64_t min_top, mlct_level_plan* out);
+
+/* Pilot and plan: m_pilot Rademacher probes (ids 0 .. m_pilot-1 of seed) at
+ * degree n in arithmetic prec and form mode, then mlct_plan_levels with
+ * min_top = m_pilot.  Use another seed for the estimate itself so that its
+ * probes are independent of the pilot's.  a = b = NaN: the interval from
+ * mlct_bounds as in mlct_estimate.  mu_out (host, may be NULL): the pilot
+ * moments, m_pilot x (n+1). */
+mlct_status mlct_select_levels(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a,
+                               double b, int32_t n, int64_t m_pilot, uint64_t seed,
+                               int32_t prec, int32_t mode, double target, int32_t target_kind,
+                               mlct_level_plan* out, double* mu_out);
+
 /* Autotuner: times the candidate launch shapes of the recurrence for this
  * operator on the device and keeps the fastest in the operator (CSR: the cap
  * on workgroups per step, 512 / 1024 / 2048 / 4096, FP32, 64 probes;

@@ -1523,6 +1523,119 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   return MLCT_OK;
 }
 
+// ---- automatic level selection ----------------------------------------------
+namespace {
+
+// V, DP and plan on the device for a pilot table already on the device
+// (mu rows of n+1 values, multiplied by coef when given).
+mlct_status plan_on_device(mlct_ctx* ctx, const double* mu, int64_t ldmu, const double* coef,
+                           int64_t m, int n, int mode, double target, int target_kind,
+                           int64_t min_top, mlct_level_plan* out) {
+  const size_t nS = (size_t)m * (n + 1), nV = (size_t)(n + 2) * (n + 1);
+  void* w;
+  CHECK(ws_get(ctx, WS_PLAN, (nS + (n + 1) + nV) * sizeof(double) + sizeof(LevelPlanDev) + 256, &w));
+  double* S = static_cast<double*>(w);
+  double* mean = S + nS;
+  double* V = mean + (n + 1);
+  LevelPlanDev* pd = reinterpret_cast<LevelPlanDev*>(
+      (reinterpret_cast<uintptr_t>(V + nV) + 255) & ~(uintptr_t)255);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_level_plan(s, mu, ldmu, coef, n, m, S, mean, V, mode == MLCT_DOUBLING ? 1 : 0,
+                                target, target_kind == MLCT_TARGET_BUDGET ? 1 : 0, min_top, pd));
+  LevelPlanDev h;
+  HIPCHK(ctx, hipMemcpyAsync(&h, pd, sizeof h, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  if (h.L > MLCT_MAX_LEVELS)
+    return fail(ctx, MLCT_ERANGE, "the optimal plan has %d levels (at most %d are supported)", h.L,
+                MLCT_MAX_LEVELS);
+  mlct_level_plan r{};
+  r.L = h.L;
+  r.opt_total = h.opt_total;
+  r.single_total = h.single_total;
+  for (int k = 0; k < h.L; ++k) {
+    r.degree[k] = h.degree[k];
+    r.m[k] = h.m[k];
+    r.var[k] = h.var[k];
+    r.cost[k] = h.cost[k];
+    r.m_real[k] = h.m_real[k];
+    r.predicted_var += h.var[k] / (double)h.m[k];
+    r.predicted_cost += (double)h.m[k] * h.cost[k];
+  }
+  *out = r;
+  return MLCT_OK;
+}
+
+mlct_status check_plan_args(mlct_ctx* ctx, int64_t m, int n, int mode, double target, int kind,
+                            const void* out) {
+  if (!out) return fail(ctx, MLCT_EINVAL, "out is required");
+  if (n < 1 || n > kMaxPlanDegree)
+    return fail(ctx, MLCT_EINVAL, "plan degree must be in [1, %d]", kMaxPlanDegree);
+  if (m < 2) return fail(ctx, MLCT_EINVAL, "a pilot needs at least 2 probes");
+  if (mode != MLCT_DIRECT && mode != MLCT_DOUBLING)
+    return fail(ctx, MLCT_EINVAL, "mode must be MLCT_DIRECT or MLCT_DOUBLING");
+  if (kind != MLCT_TARGET_VARIANCE && kind != MLCT_TARGET_BUDGET)
+    return fail(ctx, MLCT_EINVAL, "unknown target kind %d", kind);
+  if (!(target > 0.0) || !std::isfinite(target))
+    return fail(ctx, MLCT_EINVAL, "target must be positive and finite");
+  return MLCT_OK;
+}
+
+}  // namespace
+
+extern "C" mlct_status mlct_plan_levels(mlct_ctx* ctx, const double* terms, int64_t m_pilot,
+                                        int32_t n, int32_t mode, double target,
+                                        int32_t target_kind, int64_t min_top,
+                                        mlct_level_plan* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!terms) return fail(ctx, MLCT_EINVAL, "terms is required");
+  CHECK(check_plan_args(ctx, m_pilot, n, mode, target, target_kind, out));
+  CHECK(set_device(ctx));
+  void* t;
+  CHECK(ws_get(ctx, WS_MU, (size_t)m_pilot * (n + 1) * sizeof(double), &t));
+  HIPCHK(ctx, hipMemcpyAsync(t, terms, (size_t)m_pilot * (n + 1) * sizeof(double),
+                             hipMemcpyHostToDevice, ctx->stream));
+  return plan_on_device(ctx, static_cast<const double*>(t), n + 1, nullptr, m_pilot, n, mode,
+                        target, target_kind, min_top, out);
+}
+
+extern "C" mlct_status mlct_select_levels(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a,
+                                          double b, int32_t n, int64_t m_pilot, uint64_t seed,
+                                          int32_t prec, int32_t mode, double target,
+                                          int32_t target_kind, mlct_level_plan* out,
+                                          double* mu_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op) return fail(ctx, MLCT_EINVAL, "op is required");
+  CHECK(check_plan_args(ctx, m_pilot, n, mode, target, target_kind, out));
+  CHECK(check_mode_prec(ctx, mode, prec));
+  if (std::isnan(a) && std::isnan(b)) {
+    const int steps = op->d < 64 ? (int)op->d : 64;
+    CHECK(mlct_bounds(ctx, op, steps, seed + kGamma, 0.01, &a, &b));
+  }
+  CHECK(check_func(ctx, f, a, b));
+  CHECK(set_device(ctx));
+  void *mu, *coef;
+  CHECK(ws_get(ctx, WS_MU, (size_t)m_pilot * (n + 1) * sizeof(double), &mu));
+  CHECK(ws_get(ctx, WS_COEF, (size_t)(n + 2) * sizeof(double), &coef));
+  CHECK(reserve_block_ws(ctx, op, prec, mode, n, m_pilot < kDenseMaxBlock ? m_pilot : kDenseMaxBlock));
+  double* cd = static_cast<double*>(coef);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_cheb_dct(s, f.kind, f.power, a, b, n, cd, cd + n + 1));
+  const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  mlct_probes pr{};
+  pr.kind = MLCT_PROBE_RADEMACHER;
+  pr.seed = seed;
+  pr.first_id = 0;
+  pr.m = m_pilot;
+  double* mud = static_cast<double*>(mu);
+  CHECK(run_probe_set(ctx, op, alpha, beta, n, mode, prec, &pr, mud, n + 1));
+  if (mu_out)
+    HIPCHK(ctx, hipMemcpyAsync(mu_out, mud, (size_t)m_pilot * (n + 1) * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+  return plan_on_device(ctx, mud, n + 1, cd, m_pilot, n, mode, target, target_kind, m_pilot, out);
+}
+
 extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t prec,
                                      int32_t* choice_out) {
   if (!ctx) return MLCT_EINVAL;

@@ -109,7 +109,7 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -194,6 +194,22 @@ hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm,
 // incremented once per such row (entries past cap are not written).
 hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
                            int32_t* count, int cap);
+
+// ---- automatic level selection (k_levels.hip) ------------------------------
+constexpr int kMaxPlanDegree = 1024;
+struct LevelPlanDev {
+  int L;  // number of levels (may exceed MLCT_MAX_LEVELS: then only L is set)
+  int degree[MLCT_MAX_LEVELS];
+  int64_t m[MLCT_MAX_LEVELS];
+  double var[MLCT_MAX_LEVELS], cost[MLCT_MAX_LEVELS], m_real[MLCT_MAX_LEVELS];
+  double opt_total, single_total;
+};
+// mu: pilot moments m x (n+1) (row stride ldmu); coef: c_0..c_n or null (the
+// rows are the terms themselves).  Scratch S (m x (n+1)), mean (n+1),
+// V ((n+2) x (n+1)).  target: eps^2 (budget = 0) or a matvec budget.
+hipError_t launch_level_plan(hipStream_t s, const double* mu, int64_t ldmu, const double* coef,
+                             int n, int64_t m, double* S, double* mean, double* V, int doubling,
+                             double target, int budget, int64_t min_top, LevelPlanDev* out);
 
 // ---- integer triangle moments (k_tri.hip) ----------------------------------
 hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,

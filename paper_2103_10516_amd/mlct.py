@@ -480,3 +480,62 @@ def mlct_autotune(ctx: Context, op: Op, B_max: int = 64, prec: int = MLCT_FP32) 
     c = C.c_int32()
     _check(ctx, h.mlct_autotune(ctx.handle, op.handle, B_max, prec, C.byref(c)))
     return c.value
+
+
+# ---- automatic level selection ------------------------------------------------
+MLCT_TARGET_VARIANCE = 0
+MLCT_TARGET_BUDGET = 1
+MLCT_MAX_PLAN_DEGREE = 1024
+
+
+class mlct_level_plan(C.Structure):
+    _fields_ = [("L", C.c_int32), ("degree", C.c_int32 * MLCT_MAX_LEVELS),
+                ("m", C.c_int64 * MLCT_MAX_LEVELS), ("var", C.c_double * MLCT_MAX_LEVELS),
+                ("cost", C.c_double * MLCT_MAX_LEVELS), ("m_real", C.c_double * MLCT_MAX_LEVELS),
+                ("opt_total", C.c_double), ("single_total", C.c_double),
+                ("predicted_var", C.c_double), ("predicted_cost", C.c_double)]
+
+
+def _plan_dict(p: mlct_level_plan) -> dict:
+    L = p.L
+    return {"L": L, "degrees": list(p.degree[:L]), "m": list(p.m[:L]),
+            "var": np.array(p.var[:L]), "cost": np.array(p.cost[:L]),
+            "m_real": np.array(p.m_real[:L]), "opt_total": p.opt_total,
+            "single_total": p.single_total, "predicted_var": p.predicted_var,
+            "predicted_cost": p.predicted_cost}
+
+
+def mlct_plan_levels(ctx: Context, terms: np.ndarray, mode: int, target: float,
+                     target_kind: int = MLCT_TARGET_VARIANCE, min_top: int = 0) -> dict:
+    """terms: host FP64 array m_pilot x (n+1)."""
+    t = np.ascontiguousarray(terms, dtype=np.float64)
+    m, n1 = t.shape
+    h = lib()
+    h.mlct_plan_levels.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                   C.c_double, C.c_int32, C.c_int64, C.POINTER(mlct_level_plan)]
+    h.mlct_plan_levels.restype = C.c_int
+    p = mlct_level_plan()
+    _check(ctx, h.mlct_plan_levels(ctx.handle, t.ctypes.data, m, n1 - 1, mode, target,
+                                   target_kind, min_top, C.byref(p)))
+    return _plan_dict(p)
+
+
+def mlct_select_levels(ctx: Context, op: Op, kind: int, a: float, b: float, n: int,
+                       m_pilot: int, seed: int, prec: int = MLCT_FP32,
+                       mode: int = MLCT_DOUBLING, target: float = 1.0,
+                       target_kind: int = MLCT_TARGET_VARIANCE, power: float = 1.0,
+                       return_moments: bool = False):
+    h = lib()
+    h.mlct_select_levels.argtypes = [C.c_void_p, C.c_void_p, mlct_func, C.c_double, C.c_double,
+                                     C.c_int32, C.c_int64, C.c_uint64, C.c_int32, C.c_int32,
+                                     C.c_double, C.c_int32, C.POINTER(mlct_level_plan),
+                                     C.c_void_p]
+    h.mlct_select_levels.restype = C.c_int
+    p = mlct_level_plan()
+    mu = np.empty((m_pilot, n + 1), dtype=np.float64) if return_moments else None
+    _check(ctx, h.mlct_select_levels(ctx.handle, op.handle, mlct_func(kind, power), a, b, n,
+                                     m_pilot, seed & ((1 << 64) - 1), prec, mode, target,
+                                     target_kind, C.byref(p),
+                                     mu.ctypes.data if mu is not None else None))
+    d = _plan_dict(p)
+    return (d, mu) if return_moments else d
