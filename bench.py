@@ -222,10 +222,12 @@ def extra_graph_batch(mlct, dev):
 
 def extra_time_to_eps(mlct, dev):
     """Time to a relative standard error eps of tr p_n(A_hat) for the plain
-    single-level estimator, 2-level MLMC (8 | 256) and MLMC with the learned
-    level, on the 3D Laplacian 64^3 + 0.01 I, f = log, n = 256.  Sample sizes
-    from the measured (pilot) variances by the optimal allocation; the timed
-    part is the estimator call; pilot / training time is reported apart."""
+    single-level estimator, 2-level MLMC (8 | 256), MLMC with the learned
+    level, and the levels chosen automatically by Theorem thm:levels from a
+    256-probe pilot, on the 3D Laplacian 64^3 + 0.01 I, f = log, n = 256.
+    Sample sizes from the measured (pilot) variances by the optimal
+    allocation; the timed part is the estimator call; pilot / training time
+    is reported apart."""
     import torch
 
     from paper_2103_10516_amd import workloads as wl
@@ -273,14 +275,23 @@ def extra_time_to_eps(mlct, dev):
         tm, rm = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, [nc, n], m_ml, 12,
                                                   mlct.MLCT_FP32, mlct.MLCT_DOUBLING))
         tl, rl = timed(lambda: mlct.mlct_estimate_learned(ctx, op, net, m_l[0], m_l[1], 13))
+        # automatic levels: pilot (reused as the top level's first samples),
+        # plan and estimate in one call; its time includes the pilot
+        ta, (ra, plan) = timed(lambda: mlct.mlct_estimate_auto(
+            ctx, op, mlct.MLCT_LOG, a, b, n, 256, 14, mlct.MLCT_FP32, mlct.MLCT_DOUBLING, tgt))
         rse = lambda r: math.sqrt(r["est_var"]) / T  # estimated relative standard error
         rows.append({"eps": eps,
                      "plain": {"m": m_plain, "s": tp, "rel_se": rse(rp), "value": rp["value"]},
                      "mlmc": {"m": m_ml, "s": tm, "rel_se": rse(rm), "value": rm["value"]},
-                     "learned": {"m": m_l, "s": tl, "rel_se": rse(rl), "value": rl["value"]}})
+                     "learned": {"m": m_l, "s": tl, "rel_se": rse(rl), "value": rl["value"]},
+                     "auto_levels": {"degrees": plan["degrees"], "m": plan["m"], "s": ta,
+                                     "rel_se": rse(ra), "value": ra["value"]}})
     out = {"workload": "3D Laplacian 64^3 + 0.01 I, log, n=256, cheap level 8, learned MLP "
                        "9-64-64-1 trained on 2048 pilot probes",
-           "fit_s": t_fit, "pilot_s": t_pilot, "var_q": info["var_q"], "var_g": info["var_g"],
+           "fit_s": t_fit, "pilot_s": t_pilot,
+           "auto_levels_note": "one call: 256-probe pilot (included in s) reused by the top "
+                               "level, levels by Theorem thm:levels",
+           "var_q": info["var_q"], "var_g": info["var_g"],
            "var_resid": info["var_resid"], "mlmc_level_var": list(pil["level_var"]),
            "rows": rows}
     net.close()

@@ -297,6 +297,20 @@ mlct_status mlct_select_levels(mlct_ctx* ctx, const mlct_op* op, mlct_func f, do
                                int32_t prec, int32_t mode, double target, int32_t target_kind,
                                mlct_level_plan* out, double* mu_out);
 
+/* Pilot, automatic levels and the estimate in one call (Section 3.2: the
+ * pilot samples are reused).  The pilot's m_pilot probes (ids 0 ..
+ * m_pilot-1 of seed, degree n) are the first samples of the top level,
+ * which is what the plan's condition (at least m_pilot samples at the top)
+ * pays for; the top level takes max(m_L, m_pilot) samples, its remaining
+ * probes and every lower level use fresh ids of the same seed, disjoint
+ * across levels.  out->matvecs counts the pilot.  plan_out (may be NULL):
+ * the plan, with the top level's m as used.  Other arguments and errors as
+ * in mlct_select_levels and mlct_estimate. */
+mlct_status mlct_estimate_auto(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a,
+                               double b, int32_t n, int64_t m_pilot, uint64_t seed,
+                               int32_t prec, int32_t mode, double target, int32_t target_kind,
+                               mlct_level_plan* plan_out, mlct_result* out);
+
 /* Autotuner: times the candidate launch shapes of the recurrence for this
  * operator on the device and keeps the fastest in the operator (CSR: the cap
  * on workgroups per step, 512 / 1024 / 2048 / 4096, FP32, 64 probes;

@@ -1636,6 +1636,93 @@ extern "C" mlct_status mlct_select_levels(mlct_ctx* ctx, const mlct_op* op, mlct
   return plan_on_device(ctx, mud, n + 1, cd, m_pilot, n, mode, target, target_kind, m_pilot, out);
 }
 
+extern "C" mlct_status mlct_estimate_auto(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a,
+                                          double b, int32_t n, int64_t m_pilot, uint64_t seed,
+                                          int32_t prec, int32_t mode, double target,
+                                          int32_t target_kind, mlct_level_plan* plan_out,
+                                          mlct_result* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !out) return fail(ctx, MLCT_EINVAL, "op and out are required");
+  mlct_level_plan plan{};
+  CHECK(check_plan_args(ctx, m_pilot, n, mode, target, target_kind, &plan));
+  CHECK(check_mode_prec(ctx, mode, prec));
+  if (std::isnan(a) && std::isnan(b)) {
+    const int steps = op->d < 64 ? (int)op->d : 64;
+    CHECK(mlct_bounds(ctx, op, steps, seed + kGamma, 0.01, &a, &b));
+  }
+  CHECK(check_func(ctx, f, a, b));
+  CHECK(set_device(ctx));
+  const int64_t ldmu = n + 1;
+  void *pil, *coef, *res;
+  CHECK(ws_get(ctx, WS_MU2, (size_t)m_pilot * ldmu * sizeof(double), &pil));
+  CHECK(ws_get(ctx, WS_COEF, (size_t)(n + 2) * sizeof(double), &coef));
+  CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_result), &res));
+  CHECK(reserve_block_ws(ctx, op, prec, mode, n, kDenseMaxBlock));
+  double* cd = static_cast<double*>(coef);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_cheb_dct(s, f.kind, f.power, a, b, n, cd, cd + n + 1));
+  const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  auto run = [&](int64_t first, int64_t m, int degree, double* rows) -> mlct_status {
+    mlct_probes pr{};
+    pr.kind = MLCT_PROBE_RADEMACHER;
+    pr.seed = seed;
+    pr.first_id = first;
+    pr.m = m;
+    return run_probe_set(ctx, op, alpha, beta, degree, mode, prec, &pr, rows, ldmu);
+  };
+  double* pd = static_cast<double*>(pil);
+  CHECK(run(0, m_pilot, n, pd));
+  CHECK(plan_on_device(ctx, pd, ldmu, cd, m_pilot, n, mode, target, target_kind, m_pilot, &plan));
+  // Row layout of the moment table: the top level first (its first m_pilot
+  // rows are the pilot's, probe ids = row index), then the lower levels.
+  const int L = plan.L;
+  LevelDesc lv{};
+  lv.L = L;
+  lv.coef_stride = n + 1;
+  const int64_t mtop = plan.m[L - 1] > m_pilot ? plan.m[L - 1] : m_pilot;
+  int64_t total = mtop, mv = 0, pdeg = 0;
+  for (int k = 0; k < L; ++k) {
+    lv.degree[k] = plan.degree[k];
+    lv.m[k] = k == L - 1 ? mtop : plan.m[k];
+    if (k < L - 1) {
+      lv.off[k] = total;
+      total += lv.m[k];
+    } else {
+      lv.off[k] = 0;
+    }
+    mv += lv.m[k] * (int64_t)(mode == MLCT_DOUBLING ? (lv.degree[k] + 1) / 2 : lv.degree[k]);
+    pdeg += lv.m[k] * (int64_t)lv.degree[k];
+  }
+  void *mu, *qstat;
+  CHECK(ws_get(ctx, WS_MU, (size_t)total * ldmu * sizeof(double), &mu));
+  CHECK(ws_get(ctx, WS_QSTAT, ((size_t)total + 3 * MLCT_MAX_LEVELS) * sizeof(double), &qstat));
+  double* mud = static_cast<double*>(mu);
+  HIPCHK(ctx, hipMemcpyAsync(mud, pd, (size_t)m_pilot * ldmu * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+  if (mtop > m_pilot) CHECK(run(m_pilot, mtop - m_pilot, n, mud + m_pilot * ldmu));
+  for (int k = 0; k < L - 1; ++k) CHECK(run(lv.off[k], lv.m[k], lv.degree[k], mud + lv.off[k] * ldmu));
+  double* q = static_cast<double*>(qstat);
+  HIPCHK(ctx, launch_level_combine(s, mud, ldmu, cd, cd + n + 1, lv, q, q + total,
+                                   static_cast<mlct_result*>(res)));
+  mlct_result h;
+  HIPCHK(ctx, hipMemcpyAsync(&h, res, sizeof h, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  if (!(h.max_moment_ratio <= 1.0 + 1e-3))
+    return fail(ctx, MLCT_ESPECTRUM,
+                "max |mu_j|/|z|^2 = %g > 1: the spectrum is not inside [a, b] = [%g, %g]",
+                h.max_moment_ratio, a, b);
+  h.matvecs = mv;
+  h.probe_degrees = pdeg;
+  h.interval_a = a;
+  h.interval_b = b;
+  if (prec == MLCT_BF16X3) h.flags |= MLCT_FLAG_BF16;
+  plan.m[L - 1] = mtop;
+  if (plan_out) *plan_out = plan;
+  *out = h;
+  return MLCT_OK;
+}
+
 extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t prec,
                                      int32_t* choice_out) {
   if (!ctx) return MLCT_EINVAL;

@@ -539,3 +539,28 @@ def mlct_select_levels(ctx: Context, op: Op, kind: int, a: float, b: float, n: i
                                      mu.ctypes.data if mu is not None else None))
     d = _plan_dict(p)
     return (d, mu) if return_moments else d
+
+
+def mlct_estimate_auto(ctx: Context, op: Op, kind: int, a: float, b: float, n: int, m_pilot: int,
+                       seed: int, prec: int = MLCT_FP32, mode: int = MLCT_DOUBLING,
+                       target: float = 1.0, target_kind: int = MLCT_TARGET_VARIANCE,
+                       power: float = 1.0):
+    """(result dict, plan dict)."""
+    h = lib()
+    h.mlct_estimate_auto.argtypes = [C.c_void_p, C.c_void_p, mlct_func, C.c_double, C.c_double,
+                                     C.c_int32, C.c_int64, C.c_uint64, C.c_int32, C.c_int32,
+                                     C.c_double, C.c_int32, C.POINTER(mlct_level_plan),
+                                     C.POINTER(mlct_result)]
+    h.mlct_estimate_auto.restype = C.c_int
+    p = mlct_level_plan()
+    r = mlct_result()
+    _check(ctx, h.mlct_estimate_auto(ctx.handle, op.handle, mlct_func(kind, power), a, b, n,
+                                     m_pilot, seed & ((1 << 64) - 1), prec, mode, target,
+                                     target_kind, C.byref(p), C.byref(r)))
+    L = p.L
+    res = {"estimate": r.estimate, "value": r.value, "log_scale": r.log_scale,
+           "est_var": r.est_var, "level_mean": np.array(r.level_mean[:L]),
+           "level_var": np.array(r.level_var[:L]), "matvecs": r.matvecs,
+           "probe_degrees": r.probe_degrees, "max_moment_ratio": r.max_moment_ratio,
+           "interval": (r.interval_a, r.interval_b), "flags": r.flags}
+    return res, _plan_dict(p)
