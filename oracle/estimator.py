@@ -64,14 +64,33 @@ def matvec_cost(degree: int, doubling: bool) -> int:
     return mom.doubling_steps(degree) if doubling else degree
 
 
+def exact_low_traces(A, d: int, alpha: float, beta: float):
+    """tr T_0(A_hat), tr T_1(A_hat), tr T_2(A_hat) for A_hat = alpha A + beta I,
+    A symmetric: d, alpha tr A + beta d and 2 ||A_hat||_F^2 - d with
+    ||A_hat||_F^2 = alpha^2 ||A||_F^2 + 2 alpha beta tr A + beta^2 d (the
+    exactly computable low-degree traces remarked on at the end of Section
+    5.5)."""
+    if hasattr(A, "toarray"):
+        trA = float(A.diagonal().sum())
+        fro2 = float(A.multiply(A).sum())
+    else:
+        A = np.asarray(A, dtype=np.float64)
+        trA = float(np.trace(A))
+        fro2 = float(np.sum(A * A))
+    fro_hat = alpha * alpha * fro2 + 2.0 * alpha * beta * trA + beta * beta * d
+    return np.array([float(d), alpha * trA + beta * d, 2.0 * fro_hat - d])
+
+
 def estimate(A, d: int, kind: int, a: float, b: float, degrees, m, seed: int,
              power: float = 1.0, doubling: bool = False,
-             level_interp: bool = False, probe_fn=None) -> Result:
+             level_interp: bool = False, probe_fn=None, exact_low: bool = False) -> Result:
     """Multilevel estimate of tr f(A) in FP64.
 
     ``degrees`` = (l_1 < ... < l_L), ``m`` = samples per level.  Probe p of
     level k is Rademacher probe id off_k + p (``probe_fn(ids)`` may override
-    and must return a [d, len(ids)] array)."""
+    and must return a [d, len(ids)] array).  ``exact_low``: the terms j <= 2
+    leave the level variables and enter exactly, sum_{j<=2} c_j tr T_j(A_hat)
+    with the top interpolant's c_j."""
     degrees = [int(x) for x in degrees]
     m = [int(x) for x in m]
     if len(degrees) != len(m) or not degrees:
@@ -98,15 +117,23 @@ def estimate(A, d: int, kind: int, a: float, b: float, degrees, m, seed: int,
             c_hi = cheb.coefficients(kind, a, b, lk, power)[0] if lk > 0 else None
             c_lo = (None if prev < 0 else
                     cheb.coefficients(kind, a, b, prev, power)[0])
-            q = level_values_interp(mu, c_lo, c_hi)
+            if exact_low:
+                c_hi = None if c_hi is None else np.where(np.arange(len(c_hi)) <= 2, 0.0, c_hi)
+                c_lo = None if c_lo is None else np.where(np.arange(len(c_lo)) <= 2, 0.0, c_lo)
+            q = (level_values_interp(mu, c_lo, c_hi) if c_hi is not None
+                 else np.zeros(mu.shape[0]))
         else:
-            q = level_values(mu, c, prev, lk)
+            lo = max(prev, 2) if exact_low else prev
+            q = level_values(mu, c, lo, lk) if lk > lo else np.zeros(mu.shape[0])
         qs.append(q)
         mus.append(mu)
         means.append(float(np.mean(q)))
         vars_.append(float(np.var(q, ddof=1)) if mk > 1 else float("nan"))
         prev = lk
     value = float(np.sum(means))
+    if exact_low:
+        t = exact_low_traces(A, d, alpha, beta)
+        value += float(np.dot(c[: min(3, n + 1)], t[: min(3, n + 1)]))
     est_var = float(np.sum(np.asarray(vars_) / np.asarray(m)))
     return Result(value * math.exp(log_scale), value, log_scale, est_var,
                   np.asarray(means), np.asarray(vars_), mv, qs, mus)

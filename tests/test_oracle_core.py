@@ -292,3 +292,41 @@ def test_paper_level_table_matvec_count():
     assert dbl == 8161
     assert abs(direct - t["stated_matvecs"]) < 0.01 * t["budget"]
     assert abs(dbl - t["stated_matvecs"]) > 0.4 * t["budget"]
+
+
+def test_exact_low_traces_against_explicit_polynomials():
+    """tr T_1(A_hat), tr T_2(A_hat) from tr A and ||A||_F against the traces
+    of the explicitly formed matrices A_hat and 2 A_hat^2 - I."""
+    from oracle import estimator
+    from paper_2103_10516_amd import workloads as wl
+
+    A, _ = wl.random_symmetric(40, 3, -2.0, 3.0)
+    alpha, beta = cheb.affine_map(-2.5, 3.5)
+    Ah = alpha * A + beta * np.eye(40)
+    t = estimator.exact_low_traces(A, 40, alpha, beta)
+    assert t[0] == 40
+    assert t[1] == pytest.approx(np.trace(Ah), rel=1e-13)
+    assert t[2] == pytest.approx(np.trace(2 * Ah @ Ah - np.eye(40)), rel=1e-12, abs=1e-11)
+    # the sparse path gives the same numbers
+    import scipy.sparse as sp
+    t2 = estimator.exact_low_traces(sp.csr_matrix(A), 40, alpha, beta)
+    np.testing.assert_allclose(t2, t, rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("level_interp", [False, True])
+def test_exact_low_makes_quadratics_exact(level_interp):
+    """f(x) = x^2 has p_n = f for n >= 2, so with the j <= 2 terms exact the
+    estimate is tr A^2 = ||A||_F^2 with (numerically) no variance, whatever
+    the probes; f(x) = x gives tr A."""
+    from oracle import estimator
+    from paper_2103_10516_amd import workloads as wl
+
+    A, lam = wl.dense_spd(64)
+    for power, truth in ((2.0, float(np.sum(lam ** 2))), (1.0, float(np.sum(lam)))):
+        r = estimator.estimate(A, 64, cheb.POW, 0.1, 1.0, [4, 9], [3, 2], 7, power=power,
+                               level_interp=level_interp, exact_low=True)
+        assert r.value == pytest.approx(truth, rel=1e-12)
+        assert r.est_var < 1e-20 * truth ** 2
+        plain = estimator.estimate(A, 64, cheb.POW, 0.1, 1.0, [4, 9], [3, 2], 7, power=power,
+                                   level_interp=level_interp)
+        assert plain.est_var > 1e-6 * truth ** 2  # the exact terms carry the variance
