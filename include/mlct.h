@@ -79,6 +79,13 @@ typedef enum {
   MLCT_DOUBLING = 1
 } mlct_mode;
 #define MLCT_LEVEL_INTERP 0x10
+/* OR'ed into the mode of mlct_estimate / mlct_estimate_batch: the terms
+ * j <= 2 leave the level variables and enter exactly as
+ * sum_{j<=2} c_j tr T_j(A_hat), with tr T_0 = d, tr T_1 = alpha tr A + beta d
+ * and tr T_2 = 2 ||A_hat||_F^2 - d (A symmetric), from tr A and ||A||_F^2
+ * computed once per operator (the exactly computable low-degree traces
+ * remarked on at the end of Section 5.5).  c_j are the top interpolant's. */
+#define MLCT_EXACT_LOW 0x20
 
 typedef enum {
   MLCT_DT_F32 = 0,

@@ -341,6 +341,33 @@ mlct_status build_hubs(mlct_ctx* ctx, mlct_op* op) {
   return MLCT_OK;
 }
 
+// tr T_j(A_hat) for j = 0, 1, 2 with A_hat = alpha A + beta I (A symmetric):
+// d, alpha tr A + beta d, 2 ||A_hat||_F^2 - d, from tr A and ||A||_F^2
+// (computed once per operator on the device, then kept).
+mlct_status low_traces(mlct_ctx* ctx, const mlct_op* cop, double alpha, double beta,
+                       double t[3]) {
+  mlct_op* op = const_cast<mlct_op*>(cop);
+  if (!op->stats_ready) {
+    void* w;
+    CHECK(ws_get(ctx, WS_STATS, (2 * (size_t)kStatsGroups + 2) * sizeof(double), &w));
+    double* part = static_cast<double*>(w);
+    HIPCHK(ctx, launch_op_stats(ctx->stream, op, part, part + 2 * kStatsGroups));
+    double h[2];
+    HIPCHK(ctx, hipMemcpyAsync(h, part + 2 * kStatsGroups, sizeof h, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    CHECK(sync_stream(ctx));
+    op->tr_a = h[0];
+    op->fro2 = h[1];
+    op->stats_ready = true;
+  }
+  const double d = (double)op->d;
+  const double fro_hat = alpha * alpha * op->fro2 + 2.0 * alpha * beta * op->tr_a + beta * beta * d;
+  t[0] = d;
+  t[1] = alpha * op->tr_a + beta * d;
+  t[2] = 2.0 * fro_hat - d;
+  return MLCT_OK;
+}
+
 mlct_status dense_operand(mlct_ctx* ctx, const mlct_op* cop, int prec, const void** a0,
                           const void** a1, int64_t* lda) {
   mlct_op* op = const_cast<mlct_op*>(cop);
@@ -687,7 +714,8 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   ctx->err.clear();
   if (!op || !levels || !out) return fail(ctx, MLCT_EINVAL, "op, levels and out are required");
   const int interp = (mode & MLCT_LEVEL_INTERP) ? 1 : 0;
-  mode &= ~MLCT_LEVEL_INTERP;
+  const int exact_low = (mode & MLCT_EXACT_LOW) ? 1 : 0;
+  mode &= ~(MLCT_LEVEL_INTERP | MLCT_EXACT_LOW);
   CHECK(check_mode_prec(ctx, mode, prec));
   if (std::isnan(a) && std::isnan(b)) {
     const int steps = op->d < 64 ? (int)op->d : 64;
@@ -718,6 +746,10 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   if (n < 1) return fail(ctx, MLCT_EINVAL, "top degree must be >= 1");
   CHECK(set_device(ctx));
   const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  if (exact_low) {
+    lv.jmin = 3;
+    CHECK(low_traces(ctx, op, alpha, beta, lv.low_tr));
+  }
   const int64_t ldmu = n + 1;
   const int ncoef = interp ? L : 1;
   lv.coef_stride = n + 1;
@@ -1319,7 +1351,8 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   ctx->err.clear();
   if (nitems < 1 || !items || !outs) return fail(ctx, MLCT_EINVAL, "need items and outs");
   const int interp = (mode & MLCT_LEVEL_INTERP) ? 1 : 0;
-  mode &= ~MLCT_LEVEL_INTERP;
+  const int exact_low = (mode & MLCT_EXACT_LOW) ? 1 : 0;
+  mode &= ~(MLCT_LEVEL_INTERP | MLCT_EXACT_LOW);
   if (prec != MLCT_FP32) return fail(ctx, MLCT_EUNSUPPORTED, "batched estimates run in MLCT_FP32");
   CHECK(check_mode_prec(ctx, mode, prec));
   // ---- validate items, build level descriptors and blocks ----
@@ -1356,6 +1389,12 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     top[i] = lv.degree[L - 1];
     if (top[i] < 1) return fail(ctx, MLCT_EINVAL, "item %d: top degree must be >= 1", i);
     lv.coef_stride = top[i] + 1;
+    if (exact_low) {
+      CHECK(set_device(ctx));
+      lv.jmin = 3;
+      const double al = 2.0 / (it.b - it.a), be = -(it.a + it.b) / (it.b - it.a);
+      CHECK(low_traces(ctx, it.op, al, be, lv.low_tr));
+    }
     const bool pat = it.op->val == nullptr;
     const int mz = it.op->max_row_nnz <= 4 ? 4 : it.op->max_row_nnz <= 5 ? 5 : 8;
     int var = -1;

@@ -64,6 +64,9 @@ struct mlct_op {
   const int32_t* col = nullptr;
   const void* val = nullptr;  // nullptr = pattern
   int max_row_nnz = 0;
+  // tr A and ||A||_F^2 (exact low-degree traces), computed on first use
+  bool stats_ready = false;
+  double tr_a = 0.0, fro2 = 0.0;
   // rows longer than kHubLen (sorted), their chunk ranges, chunk extents
   int32_t* hub_rows = nullptr;  // [hub_n]
   int32_t* hub_c0 = nullptr;    // [hub_n + 1]
@@ -109,7 +112,7 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -144,7 +147,13 @@ struct LevelDesc {
   int32_t L;
   int32_t interp;     // separate interpolant per level
   int32_t coef_stride;
+  int32_t jmin = 0;   // first degree in the level variables (3: j <= 2 exact)
+  double low_tr[3] = {0.0, 0.0, 0.0};  // tr T_j(A_hat), j <= 2, when jmin = 3
 };
+// tr A and ||A||_F^2 of an operator (FP64, fixed-order sums) into out[0..1];
+// partial: scratch of 2 * kStatsGroups doubles.
+constexpr int kStatsGroups = 1024;
+hipError_t launch_op_stats(hipStream_t s, const mlct_op* op, double* partial, double* out);
 hipError_t launch_level_combine(hipStream_t s, const double* mu, int64_t ldmu,
                                 const double* coef, const double* log_scale,
                                 const LevelDesc& lv, double* q_dev, double* stats_dev,

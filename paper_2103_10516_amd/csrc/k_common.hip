@@ -174,12 +174,12 @@ __global__ __launch_bounds__(kCombThreads) void level_stats_kernel(
     const double* r = mu + (o + p) * ldmu;
     double qv = 0.0;
     if (!lv.interp) {
-      for (int j = lo + 1; j <= hi; ++j) qv += ch[j] * r[j];
+      for (int j = max(lo + 1, lv.jmin); j <= hi; ++j) qv += ch[j] * r[j];
     } else {
-      for (int j = 0; j <= hi; ++j) qv += ch[j] * r[j];
+      for (int j = lv.jmin; j <= hi; ++j) qv += ch[j] * r[j];
       if (cl) {
         double ql = 0.0;
-        for (int j = 0; j <= lo; ++j) ql += cl[j] * r[j];
+        for (int j = lv.jmin; j <= lo; ++j) ql += cl[j] * r[j];
         qv -= ql;
       }
     }
@@ -206,11 +206,16 @@ __global__ __launch_bounds__(kCombThreads) void level_stats_kernel(
 // Multilevel estimator (eq. eqn:multiEstimator): Gamma = sum_k mean_k and
 // its variance estimate sum_k s_k^2 / m_k, summed over k in order.
 __global__ void level_finalize_kernel(const double* __restrict__ stats, LevelDesc lv,
+                                      const double* __restrict__ coef,
                                       const double* __restrict__ log_scale,
                                       mlct_result* __restrict__ out) {
   if (threadIdx.x != 0) return;
   double v = 0.0, var = 0.0, mr = 0.0;
   uint32_t flags = 0;
+  // exact low-degree terms with the top interpolant's coefficients
+  const int n = lv.degree[lv.L - 1];
+  const double* ctop = lv.interp ? coef + (int64_t)(lv.L - 1) * lv.coef_stride : coef;
+  for (int j = 0; j < lv.jmin && j <= n; ++j) v += ctop[j] * lv.low_tr[j];
   for (int k = 0; k < lv.L; ++k) {
     v += stats[3 * k];
     if (lv.m[k] > 1) var += stats[3 * k + 1] / (double)lv.m[k];
@@ -275,7 +280,81 @@ hipError_t launch_level_combine(hipStream_t s, const double* mu, int64_t ldmu,
   level_stats_kernel<<<lv.L, kCombThreads, 0, s>>>(mu, ldmu, coef, lv, q_dev, stats_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  level_finalize_kernel<<<1, 64, 0, s>>>(stats_dev, lv, log_scale, result_dev);
+  level_finalize_kernel<<<1, 64, 0, s>>>(stats_dev, lv, coef, log_scale, result_dev);
+  return hipGetLastError();
+}
+
+namespace {
+
+constexpr int kST = 256;
+
+// Per-workgroup partial sums of diag(A) and of A_ij^2 over rows g, g + G, ...
+// of one workgroup per row block (one thread per row, FP64).
+__global__ __launch_bounds__(kST) void op_stats_kernel(const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const float* __restrict__ val,
+                                                       const void* __restrict__ A, int dtype,
+                                                       int64_t lda, int64_t d,
+                                                       double* __restrict__ partial) {
+  __shared__ double s1[kST], s2[kST];
+  double tr = 0.0, fr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kST + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * kST) {
+    if (rowptr) {
+      for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const double a = val ? (double)val[e] : 1.0;
+        if (col[e] == i) tr += a;
+        fr += a * a;
+      }
+    } else {
+      for (int64_t j = 0; j < d; ++j) {
+        const double a = dtype == MLCT_DT_F64 ? static_cast<const double*>(A)[i * lda + j]
+                                              : (double)static_cast<const float*>(A)[i * lda + j];
+        if (j == i) tr += a;
+        fr += a * a;
+      }
+    }
+  }
+  s1[threadIdx.x] = tr;
+  s2[threadIdx.x] = fr;
+  __syncthreads();
+  for (int st = kST / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+      s2[threadIdx.x] += s2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = s1[0];
+    partial[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+__global__ void op_stats_reduce_kernel(const double* __restrict__ partial, int g,
+                                       double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double tr = 0.0, fr = 0.0;
+  for (int b = 0; b < g; ++b) {
+    tr += partial[2 * b];
+    fr += partial[2 * b + 1];
+  }
+  out[0] = tr;
+  out[1] = fr;
+}
+
+}  // namespace
+
+hipError_t launch_op_stats(hipStream_t s, const mlct_op* op, double* partial, double* out) {
+  const int64_t want = (op->d + kST - 1) / kST;
+  const int g = (int)(want < kStatsGroups ? want : kStatsGroups);
+  const bool csr = op->kind == OP_CSR;
+  op_stats_kernel<<<g, kST, 0, s>>>(csr ? op->rowptr : nullptr, csr ? op->col : nullptr,
+                                    csr ? static_cast<const float*>(op->val) : nullptr,
+                                    csr ? nullptr : op->A, op->dtype, op->lda, op->d, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  op_stats_reduce_kernel<<<1, 64, 0, s>>>(partial, g, out);
   return hipGetLastError();
 }
 

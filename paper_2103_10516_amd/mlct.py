@@ -29,6 +29,7 @@ MLCT_LEVEL_INTERP = 0x10
 MLCT_DT_F32, MLCT_DT_F64, MLCT_DT_PATTERN = 0, 1, 2
 MLCT_PROBE_RADEMACHER, MLCT_PROBE_EXPLICIT = 0, 1
 MLCT_MAX_LEVELS = 32
+MLCT_EXACT_LOW = 0x20
 MLCT_FLAG_FEW_SAMPLES, MLCT_FLAG_OVERFLOW, MLCT_FLAG_BF16 = 0x1, 0x2, 0x4
 MLCT_KERNEL_CSR_STEP, MLCT_KERNEL_DENSE_STEP, MLCT_KERNEL_TRI_STEP, MLCT_KERNEL_GRAM = 0, 1, 2, 3
 
