@@ -197,6 +197,24 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
  * float64 (MLCT_DT_F64) or float32 (MLCT_DT_F32). */
 mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t d, const void* A_dev, int64_t lda,
                           int32_t dtype, mlct_op** out);
+/* Sparse Gram operator A = X^T X + lambda I, applied matrix-free as two
+ * sparse products per recurrence step (W = X V, then X^T W), for nuclear
+ * norms (f = sqrt, lambda = 0) and regularised log-determinants of sparse or
+ * rectangular X without forming X^T X (the Gram footnote of Section 1 and
+ * the nuclear-norm experiments of Section 5).  X: device CSR, rows x cols
+ * (rowptr int32[rows+1], col int32[nnz] in [0, cols), val float32[nnz] or
+ * NULL for a 0/1 pattern), borrowed for the operator's lifetime.  X^T is
+ * built at creation (a stable counting sort on the host, so every sum over
+ * it has a fixed order) and owned.  The operator's dimension is cols;
+ * precisions MLCT_FP32 and MLCT_FP64.  a = b = NaN in mlct_estimate finds
+ * the interval by Lanczos through the two products.  Not usable with
+ * mlct_triangles, mlct_estimate_batch or MLCT_EXACT_LOW (EINVAL /
+ * EUNSUPPORTED).  Errors: EINVAL (shape, CSR structure, lambda < 0),
+ * ENOMEM. */
+mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t nnz,
+                             const int32_t* rowptr_dev, const int32_t* col_dev,
+                             const float* val_dev, double lambda, mlct_op** out);
+
 /* A = X^T X for X row-major rows x cols (leading dimension ldx >= cols),
  * float32.  The Gram matrix (cols x cols) is formed once on the device, in
  * the arithmetic ``prec`` (MLCT_FP32 or MLCT_BF16X3), and owned by the op. */

@@ -133,9 +133,10 @@ mlct_status sync_stream(mlct_ctx* ctx) {
 // ---- autotune cache (plain text, one decision per line) -------------------
 std::string tune_key(const mlct_op* op, int prec, int64_t bpad) {
   char buf[160];
-  if (op->kind == OP_CSR)
-    snprintf(buf, sizeof buf, "csr d=%lld nnz=%lld maxrow=%d pattern=%d", (long long)op->d,
-             (long long)op->nnz, op->max_row_nnz, op->val == nullptr ? 1 : 0);
+  if (op->kind == OP_CSR || op->kind == OP_GRAM_CSR)
+    snprintf(buf, sizeof buf, "%s d=%lld nnz=%lld maxrow=%d pattern=%d",
+             op->kind == OP_CSR ? "csr" : "gramcsr", (long long)op->d, (long long)op->csr.nnz,
+             op->csr.max_row_nnz, op->csr.val == nullptr ? 1 : 0);
   else
     snprintf(buf, sizeof buf, "dense d=%lld prec=%d bpad=%lld", (long long)op->d, prec,
              (long long)bpad);
@@ -252,8 +253,8 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
   double* P = static_cast<double*>(part);
   hipStream_t s = ctx->stream;
   void* hub = nullptr;
-  if (op->hub_n > 0)
-    CHECK(ws_get(ctx, WS_HUB, (size_t)op->hub_chunks * kBlockProbes * sizeof(T), &hub));
+  if (op->csr.hub_n > 0)
+    CHECK(ws_get(ctx, WS_HUB, (size_t)op->csr.hub_chunks * kBlockProbes * sizeof(T), &hub));
   HIPCHK(ctx, launch_probe_init<T>(s, buf[0], op->d, src, plan, P));
   const int zdirect = src.entries ? 2 : 1;
   for (int k = 1; k <= S; ++k) {
@@ -265,8 +266,55 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
     const T cb = (T)(first ? beta : 2.0 * beta);
     const int zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
     LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
-    HIPCHK(ctx, launch_csr_step<T>(s, op, vk, vm, ca, cb, !first, zmode, src, plan, hub,
+    HIPCHK(ctx, launch_csr_step<T>(s, op->csr, vk, vm, ca, cb, !first, zmode, src, plan, hub,
                                    P + pstep * k));
+    tm.done();
+  }
+  HIPCHK(ctx, launch_reduce_partials(s, P, S + 1, 2, plan.ngroups, kBlockProbes,
+                                     static_cast<double*>(dots)));
+  HIPCHK(ctx, launch_assemble_moments(s, static_cast<double*>(dots), S + 1, kBlockProbes,
+                                      src.active, mode, degree, mu_rows, ldmu));
+  return MLCT_OK;
+}
+
+// One probe block through the sparse Gram operator A = X^T X + lambda I:
+// per step W = X V_k (rows x 64 scratch), then the recurrence over X^T W
+// (the shift enters cb as ca * lambda).
+template <typename T>
+mlct_status run_block_gram_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
+                               int degree, int mode, ProbeSrc src, double* mu_rows,
+                               int64_t ldmu) {
+  const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
+  const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
+  const CsrStepPlan plan_r = plan_csr(op->csrx.nrows, op->tuned_groups);
+  const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(T);
+  const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;
+  void *v0, *v1, *part, *dots, *wb, *hubs = nullptr;
+  CHECK(ws_get(ctx, WS_V0, vbytes, &v0));
+  CHECK(ws_get(ctx, WS_V1, vbytes, &v1));
+  CHECK(ws_get(ctx, WS_PART, pstep * (S + 1) * sizeof(double), &part));
+  CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &dots));
+  CHECK(ws_get(ctx, WS_GRAMW, (size_t)op->csrx.nrows * kBlockProbes * sizeof(T), &wb));
+  const size_t hx = (size_t)op->csrx.hub_chunks * kBlockProbes, ht = (size_t)op->csr.hub_chunks * kBlockProbes;
+  if (hx + ht > 0) CHECK(ws_get(ctx, WS_HUB, (hx + ht) * sizeof(T), &hubs));
+  T* hubx = static_cast<T*>(hubs);
+  T* hubt = hubx ? hubx + hx : nullptr;
+  T* buf[2] = {static_cast<T*>(v0), static_cast<T*>(v1)};
+  T* W = static_cast<T*>(wb);
+  double* P = static_cast<double*>(part);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_probe_init<T>(s, buf[0], op->d, src, plan, P));
+  const int zdirect = src.entries ? 2 : 1;
+  for (int k = 1; k <= S; ++k) {
+    const T* vk = buf[(k - 1) & 1];
+    T* vm = buf[k & 1];
+    const bool first = (k == 1);
+    const double ca = first ? alpha : 2.0 * alpha;
+    const double cb = (first ? beta : 2.0 * beta) + ca * op->gram_lambda;
+    const int zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
+    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
+    HIPCHK(ctx, launch_gram_csr_step<T>(s, op->csrx, op->csr, vk, vm, W, (T)ca, (T)cb, !first,
+                                        zmode, src, plan_r, plan, hubx, hubt, P + pstep * k));
     tm.done();
   }
   HIPCHK(ctx, launch_reduce_partials(s, P, S + 1, 2, plan.ngroups, kBlockProbes,
@@ -282,15 +330,15 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
 // Hub table of a CSR operator (rows longer than kHubLen): found on the
 // device, sorted by row on the host, cut into chunks of kHubChunk entries.
 // At most nnz / (kHubLen + 1) rows qualify, which bounds the search output.
-mlct_status build_hubs(mlct_ctx* ctx, mlct_op* op) {
-  const int cap = (int)(op->nnz / (kHubLen + 1) + 1);
+mlct_status build_hubs(mlct_ctx* ctx, mlct::CsrMat& mat, void** mem_out) {
+  const int cap = (int)(mat.nnz / (kHubLen + 1) + 1);
   void* tmp;
   CHECK(ws_get(ctx, WS_HUB, (size_t)(3 * (int64_t)cap + 1) * sizeof(int32_t), &tmp));
   int32_t* trip = static_cast<int32_t*>(tmp);
   int32_t* count = trip + 3 * (int64_t)cap;
   hipStream_t s = ctx->stream;
   HIPCHK(ctx, hipMemsetAsync(count, 0, sizeof(int32_t), s));
-  HIPCHK(ctx, launch_hub_find(s, op->rowptr, op->d, trip, count, cap));
+  HIPCHK(ctx, launch_hub_find(s, mat.rowptr, mat.nrows, trip, count, cap));
   int32_t n = 0;
   HIPCHK(ctx, hipMemcpyAsync(&n, count, sizeof n, hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
@@ -331,13 +379,13 @@ mlct_status build_hubs(mlct_ctx* ctx, mlct_op* op) {
     return fail(ctx, MLCT_EDEVICE, "hub table upload: %s", hipGetErrorString(e));
   }
   int32_t* base = static_cast<int32_t*>(mem);
-  op->hub_mem = mem;
-  op->hub_rows = base;
-  op->hub_c0 = base + n;
-  op->hub_cs = base + n + (n + 1);
-  op->hub_ce = op->hub_cs + nch;
-  op->hub_n = n;
-  op->hub_chunks = (int)nch;
+  *mem_out = mem;
+  mat.hub_rows = base;
+  mat.hub_c0 = base + n;
+  mat.hub_cs = base + n + (n + 1);
+  mat.hub_ce = mat.hub_cs + nch;
+  mat.hub_n = n;
+  mat.hub_chunks = (int)nch;
   return MLCT_OK;
 }
 
@@ -418,14 +466,17 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
                              int64_t block) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
   void* tmp;
-  if (op->kind == OP_CSR) {
+  if (op->kind == OP_CSR || op->kind == OP_GRAM_CSR) {
     const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
     const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
     CHECK(ws_get(ctx, WS_V0, (size_t)op->d * kBlockProbes * tsz, &tmp));
     CHECK(ws_get(ctx, WS_V1, (size_t)op->d * kBlockProbes * tsz, &tmp));
     CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * (S + 1) * sizeof(double), &tmp));
     CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &tmp));
-    if (op->hub_n > 0) CHECK(ws_get(ctx, WS_HUB, (size_t)op->hub_chunks * kBlockProbes * tsz, &tmp));
+    const size_t hubs = (size_t)op->csr.hub_chunks + (op->kind == OP_GRAM_CSR ? op->csrx.hub_chunks : 0);
+    if (hubs > 0) CHECK(ws_get(ctx, WS_HUB, hubs * kBlockProbes * tsz, &tmp));
+    if (op->kind == OP_GRAM_CSR)
+      CHECK(ws_get(ctx, WS_GRAMW, (size_t)op->csrx.nrows * kBlockProbes * tsz, &tmp));
     return MLCT_OK;
   }
   const int64_t bpad = dense_bpad(block);
@@ -499,6 +550,13 @@ mlct_status run_block(mlct_ctx* ctx, const mlct_op* op, double alpha, double bet
       return run_block_csr<double>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
     return fail(ctx, MLCT_EUNSUPPORTED, "CSR operators support MLCT_FP32 and MLCT_FP64");
   }
+  if (op->kind == OP_GRAM_CSR) {
+    if (prec == MLCT_FP32)
+      return run_block_gram_csr<float>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
+    if (prec == MLCT_FP64)
+      return run_block_gram_csr<double>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
+    return fail(ctx, MLCT_EUNSUPPORTED, "sparse Gram operators support MLCT_FP32 and MLCT_FP64");
+  }
   return run_block_dense(ctx, op, alpha, beta, degree, mode, prec, src, mu_rows, ldmu);
 }
 
@@ -506,7 +564,8 @@ mlct_status run_block(mlct_ctx* ctx, const mlct_op* op, double alpha, double bet
 mlct_status run_probe_set(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                           int degree, int mode, int prec, const mlct_probes* pr, double* mu_dev,
                           int64_t ldmu) {
-  const int64_t width = op->kind == OP_CSR ? kBlockProbes : kDenseMaxBlock;
+  const bool sparse = op->kind == OP_CSR || op->kind == OP_GRAM_CSR;
+  const int64_t width = sparse ? kBlockProbes : kDenseMaxBlock;
   for (int64_t p0 = 0; p0 < pr->m; p0 += width) {
     ProbeSrc src;
     src.seed = pr->seed;
@@ -621,7 +680,7 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   void* flags;
   CHECK(ws_get(ctx, WS_MISC, 64, &flags));
   HIPCHK(ctx, hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), ctx->stream));
-  HIPCHK(ctx, launch_csr_validate(ctx->stream, rowptr_dev, col_dev, d, nnz,
+  HIPCHK(ctx, launch_csr_validate(ctx->stream, rowptr_dev, col_dev, d, d, nnz,
                                   static_cast<int32_t*>(flags)));
   int32_t hf[2] = {0, 0};
   HIPCHK(ctx, hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, ctx->stream));
@@ -634,15 +693,16 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   op->device = ctx->device;
   op->kind = OP_CSR;
   op->d = d;
-  op->nnz = nnz;
-  op->rowptr = rowptr_dev;
-  op->col = col_dev;
-  op->val = dtype == MLCT_DT_F32 ? val_dev : nullptr;
+  op->csr.nnz = nnz;
+  op->csr.nrows = op->csr.ncols = d;
+  op->csr.rowptr = rowptr_dev;
+  op->csr.col = col_dev;
+  op->csr.val = dtype == MLCT_DT_F32 ? static_cast<const float*>(val_dev) : nullptr;
   op->dtype = dtype;
-  op->max_row_nnz = hf[1];
+  op->csr.max_row_nnz = hf[1];
   op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
-  if (op->max_row_nnz > kHubLen) {
-    const mlct_status st = build_hubs(ctx, op);
+  if (op->csr.max_row_nnz > kHubLen) {
+    const mlct_status st = build_hubs(ctx, op->csr, &op->hub_mem);
     if (st != MLCT_OK) {
       delete op;
       return st;
@@ -652,10 +712,113 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   return MLCT_OK;
 }
 
+mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t nnz,
+                             const int32_t* rowptr_dev, const int32_t* col_dev,
+                             const float* val_dev, double lambda, mlct_op** out) {
+  if (!ctx || !out) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (rows < 1 || cols < 1 || rows > INT32_MAX || cols > INT32_MAX)
+    return fail(ctx, MLCT_EINVAL, "bad shape %lld x %lld", (long long)rows, (long long)cols);
+  if (nnz < 0 || nnz > INT32_MAX) return fail(ctx, MLCT_EINVAL, "bad nnz=%lld", (long long)nnz);
+  if (!rowptr_dev || (nnz > 0 && !col_dev))
+    return fail(ctx, MLCT_EINVAL, "rowptr/col must be device pointers");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda))
+    return fail(ctx, MLCT_EINVAL, "lambda must be finite and >= 0");
+  CHECK(set_device(ctx));
+  hipStream_t s = ctx->stream;
+  void* flags;
+  CHECK(ws_get(ctx, WS_MISC, 64, &flags));
+  HIPCHK(ctx, hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s));
+  HIPCHK(ctx, launch_csr_validate(s, rowptr_dev, col_dev, rows, cols, nnz,
+                                  static_cast<int32_t*>(flags)));
+  int32_t hf[2] = {0, 0};
+  HIPCHK(ctx, hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  if (hf[0])
+    return fail(ctx, MLCT_EINVAL, "invalid CSR structure of X (flags 0x%x)", hf[0]);
+  // X^T by a stable counting sort on the host: entries of a column keep
+  // their row order, so the transpose (and every sum over it) is fixed.
+  std::vector<int32_t> rp(rows + 1), cl(nnz), rpt(cols + 1, 0), clt(nnz);
+  std::vector<float> vl(val_dev ? nnz : 0), vlt(val_dev ? nnz : 0);
+  HIPCHK(ctx, hipMemcpy(rp.data(), rowptr_dev, (rows + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (nnz > 0) {
+    HIPCHK(ctx, hipMemcpy(cl.data(), col_dev, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (val_dev)
+      HIPCHK(ctx, hipMemcpy(vl.data(), val_dev, nnz * sizeof(float), hipMemcpyDeviceToHost));
+  }
+  for (int64_t e = 0; e < nnz; ++e) ++rpt[cl[e] + 1];
+  int maxt = 0;
+  for (int64_t j = 0; j < cols; ++j) {
+    maxt = std::max(maxt, rpt[j + 1]);
+    rpt[j + 1] += rpt[j];
+  }
+  {
+    std::vector<int32_t> next(rpt.begin(), rpt.end() - 1);
+    for (int64_t i = 0; i < rows; ++i)
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t k = next[cl[e]]++;
+        clt[k] = (int32_t)i;
+        if (val_dev) vlt[k] = vl[e];
+      }
+  }
+  const size_t words = (size_t)(cols + 1) + nnz + (val_dev ? nnz : 0);
+  void* mem = nullptr;
+  if (hipMalloc(&mem, words * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MLCT_ENOMEM, "no memory for X^T");
+  }
+  int32_t* base = static_cast<int32_t*>(mem);
+  hipError_t e1 = hipMemcpy(base, rpt.data(), (cols + 1) * 4, hipMemcpyHostToDevice);
+  if (e1 == hipSuccess && nnz > 0) e1 = hipMemcpy(base + cols + 1, clt.data(), nnz * 4, hipMemcpyHostToDevice);
+  if (e1 == hipSuccess && val_dev && nnz > 0)
+    e1 = hipMemcpy(base + cols + 1 + nnz, vlt.data(), nnz * 4, hipMemcpyHostToDevice);
+  if (e1 != hipSuccess) {
+    (void)hipFree(mem);
+    return fail(ctx, MLCT_EDEVICE, "upload of X^T: %s", hipGetErrorString(e1));
+  }
+  mlct_op* op = new (std::nothrow) mlct_op();
+  if (!op) {
+    (void)hipFree(mem);
+    return fail(ctx, MLCT_ENOMEM, "out of host memory");
+  }
+  op->ctx = ctx;
+  op->device = ctx->device;
+  op->kind = OP_GRAM_CSR;
+  op->d = cols;
+  op->dtype = val_dev ? MLCT_DT_F32 : MLCT_DT_PATTERN;
+  op->gram_lambda = lambda;
+  op->gram_mem = mem;
+  op->csrx.rowptr = rowptr_dev;
+  op->csrx.col = col_dev;
+  op->csrx.val = val_dev;
+  op->csrx.nrows = rows;
+  op->csrx.ncols = cols;
+  op->csrx.nnz = nnz;
+  op->csrx.max_row_nnz = hf[1];
+  op->csr.rowptr = base;
+  op->csr.col = base + cols + 1;
+  op->csr.val = val_dev ? reinterpret_cast<const float*>(base + cols + 1 + nnz) : nullptr;
+  op->csr.nrows = cols;
+  op->csr.ncols = rows;
+  op->csr.nnz = nnz;
+  op->csr.max_row_nnz = maxt;
+  op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
+  mlct_status st = MLCT_OK;
+  if (op->csrx.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csrx, &op->hubx_mem);
+  if (st == MLCT_OK && op->csr.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csr, &op->hub_mem);
+  if (st != MLCT_OK) {
+    mlct_op_destroy(op);
+    return st;
+  }
+  *out = op;
+  return MLCT_OK;
+}
+
 mlct_status mlct_op_destroy(mlct_op* op) {
   if (!op) return MLCT_EINVAL;
   (void)hipSetDevice(op->device);
-  void* owned[] = {op->owned, op->split_hi, op->split_lo, op->a32, op->a64, op->hub_mem};
+  void* owned[] = {op->owned,   op->split_hi, op->split_lo, op->a32,
+                   op->a64,     op->hub_mem,  op->hubx_mem, op->gram_mem};
   for (void* p : owned)
     if (p) (void)hipFree(p);
   delete op;
@@ -747,6 +910,8 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   CHECK(set_device(ctx));
   const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
   if (exact_low) {
+    if (op->kind == OP_GRAM_CSR)
+      return fail(ctx, MLCT_EUNSUPPORTED, "MLCT_EXACT_LOW needs ||A||_F, not formed for sparse Gram operators");
     lv.jmin = 3;
     CHECK(low_traces(ctx, op, alpha, beta, lv.low_tr));
   }
@@ -827,7 +992,7 @@ mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t d, const void* A_dev, int64_t l
 mlct_status mlct_op_read_dense(mlct_ctx* ctx, const mlct_op* op, double* out_host) {
   if (!ctx) return MLCT_EINVAL;
   ctx->err.clear();
-  if (!op || !out_host || op->kind == OP_CSR)
+  if (!op || !out_host || op->kind == OP_CSR || op->kind == OP_GRAM_CSR)
     return fail(ctx, MLCT_EINVAL, "need a dense or Gram operator and an output array");
   CHECK(set_device(ctx));
   const void *a0, *a1;
@@ -900,10 +1065,12 @@ mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64
   const void* a64 = nullptr;
   const void* unused;
   int64_t lda = 0;
-  if (op->kind != OP_CSR) CHECK(dense_operand(ctx, op, MLCT_FP64, &a64, &unused, &lda));
+  if (op->kind != OP_CSR && op->kind != OP_GRAM_CSR)
+    CHECK(dense_operand(ctx, op, MLCT_FP64, &a64, &unused, &lda));
   const int64_t nb = (d + 255) / 256 < 1024 ? (d + 255) / 256 : 1024;
+  const int64_t xrows = op->kind == OP_GRAM_CSR ? op->csrx.nrows : 0;
   void *q, *misc;
-  CHECK(ws_get(ctx, WS_LANCZOS, (size_t)(steps + 2) * d * sizeof(double), &q));
+  CHECK(ws_get(ctx, WS_LANCZOS, ((size_t)(steps + 2) * d + xrows) * sizeof(double), &q));
   const size_t misc_bytes = sizeof(LanczosState) + (size_t)(kLanczosMaxSteps + 1) * nb * 8 +
                             (kLanczosMaxSteps + 1) * 8 + 64 * 8;
   CHECK(ws_get(ctx, WS_DENSE, misc_bytes, &misc));
@@ -914,7 +1081,7 @@ mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64
   double* h = part + (size_t)(kLanczosMaxSteps + 1) * nb;
   double* out = h + kLanczosMaxSteps + 1;
   HIPCHK(ctx, launch_lanczos(ctx->stream, op, a64, lda, steps, seed, rel_margin, Q, w, h, part,
-                             st, out));
+                             st, out, xrows ? w + d : nullptr));
   LanczosState hs;
   double ho[8];
   HIPCHK(ctx, hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
@@ -944,6 +1111,9 @@ mlct_status mlct_bounds(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64_
   CHECK(mlct_lanczos(ctx, op, steps, seed, rel_margin, nullptr, nullptr, nullptr, info));
   *a_out = info[4];
   *b_out = info[5];
+  // Gram operators are known to be >= lambda I (lambda = 0 for X^T X)
+  if (op->kind == OP_GRAM && *a_out < 0.0) *a_out = 0.0;
+  if (op->kind == OP_GRAM_CSR && *a_out < op->gram_lambda) *a_out = op->gram_lambda;
   return MLCT_OK;
 }
 
@@ -952,7 +1122,7 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
   if (!ctx) return MLCT_EINVAL;
   ctx->err.clear();
   if (!op || !out) return fail(ctx, MLCT_EINVAL, "op and out are required");
-  if (op->kind != OP_CSR || op->val != nullptr)
+  if (op->kind != OP_CSR || op->csr.val != nullptr)
     return fail(ctx, MLCT_EINVAL, "triangle counting needs a 0/1 pattern CSR operator");
   if (m < 1) return fail(ctx, MLCT_EINVAL, "need m >= 1 probes");
   CHECK(set_device(ctx));
@@ -965,8 +1135,8 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
   CHECK(ws_get(ctx, WS_TRI, (size_t)m * 3 * sizeof(long long), &w));
   CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_tri_result), &res));
   void* hub = nullptr;
-  if (op->hub_n > 0)
-    CHECK(ws_get(ctx, WS_HUB, (size_t)op->hub_chunks * kBlockProbes * sizeof(int32_t), &hub));
+  if (op->csr.hub_n > 0)
+    CHECK(ws_get(ctx, WS_HUB, (size_t)op->csr.hub_chunks * kBlockProbes * sizeof(int32_t), &hub));
   hipStream_t s = ctx->stream;
   long long* P = static_cast<long long*>(part);
   long long* W = static_cast<long long*>(w);
@@ -978,19 +1148,19 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
     HIPCHK(ctx, launch_tri_init(s, op, src, plan, static_cast<int32_t*>(z)));
     {
       LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
-      HIPCHK(ctx, launch_tri_step(s, op, 1, plan, static_cast<int32_t*>(z),
+      HIPCHK(ctx, launch_tri_step(s, op->csr, 1, plan, static_cast<int32_t*>(z),
                                   static_cast<int32_t*>(y), hub, P));
       tm.done();
     }
     HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 1, W, p0));
     {
       LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
-      HIPCHK(ctx, launch_tri_step(s, op, 2, plan, static_cast<int32_t*>(y), nullptr, hub, P));
+      HIPCHK(ctx, launch_tri_step(s, op->csr, 2, plan, static_cast<int32_t*>(y), nullptr, hub, P));
       tm.done();
     }
     HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 2, W, p0));
   }
-  HIPCHK(ctx, launch_tri_cv(s, W, m, op->nnz, static_cast<mlct_tri_result*>(res)));
+  HIPCHK(ctx, launch_tri_cv(s, W, m, op->csr.nnz, static_cast<mlct_tri_result*>(res)));
   mlct_tri_result h;
   HIPCHK(ctx, hipMemcpyAsync(&h, res, sizeof h, hipMemcpyDeviceToHost, s));
   if (w_out)
@@ -1395,8 +1565,8 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
       const double al = 2.0 / (it.b - it.a), be = -(it.a + it.b) / (it.b - it.a);
       CHECK(low_traces(ctx, it.op, al, be, lv.low_tr));
     }
-    const bool pat = it.op->val == nullptr;
-    const int mz = it.op->max_row_nnz <= 4 ? 4 : it.op->max_row_nnz <= 5 ? 5 : 8;
+    const bool pat = it.op->csr.val == nullptr;
+    const int mz = it.op->csr.max_row_nnz <= 4 ? 4 : it.op->csr.max_row_nnz <= 5 ? 5 : 8;
     int var = -1;
     for (size_t v = 0; v < variants.size(); ++v)
       if (variants[v] == std::make_pair(pat, mz)) var = (int)v;
@@ -1451,11 +1621,11 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     const mlct_op* op = items[hb.item].op;
     const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
     BatchBlock& B = tab[bi];
-    B.rowptr = op->rowptr;
-    B.col = op->col;
-    B.val = static_cast<const float*>(op->val);
+    B.rowptr = op->csr.rowptr;
+    B.col = op->csr.col;
+    B.val = op->csr.val;
     B.d = op->d;
-    B.nnz = op->nnz;
+    B.nnz = op->csr.nnz;
     B.v0 = cv.take<float>((size_t)op->d * 64);
     B.v1 = cv.take<float>((size_t)op->d * 64);
     B.part = cv.take<double>((size_t)(hb.steps + 1) * 2 * plan.ngroups * 64);
@@ -1768,7 +1938,7 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   ctx->err.clear();
   if (!op) return fail(ctx, MLCT_EINVAL, "op is required");
   CHECK(set_device(ctx));
-  const bool csr = op->kind == OP_CSR;
+  const bool csr = op->kind == OP_CSR || op->kind == OP_GRAM_CSR;
   if (csr) prec = MLCT_FP32;
   CHECK(check_mode_prec(ctx, MLCT_DIRECT, prec));
   const int64_t block = csr ? kBlockProbes : std::max<int64_t>(32, std::min<int64_t>(B_max, kDenseMaxBlock));

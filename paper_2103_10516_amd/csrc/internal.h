@@ -19,7 +19,24 @@ constexpr int kBlockProbes = 64;
 constexpr int kHubLen = 256;
 constexpr int kHubChunk = 256;
 
-enum OpKind { OP_CSR = 0, OP_DENSE = 1, OP_GRAM = 2 };
+// OP_GRAM_CSR: A = X^T X + lambda I with X sparse rows x cols, applied as two
+// SpMMs per step (X, then X^T).
+enum OpKind { OP_CSR = 0, OP_DENSE = 1, OP_GRAM = 2, OP_GRAM_CSR = 3 };
+
+// A CSR matrix as the step kernels see it (device arrays, borrowed or owned
+// by the operator), with its hub table (rows longer than kHubLen).
+struct CsrMat {
+  const int32_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const float* val = nullptr;  // nullptr = 0/1 pattern
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  int max_row_nnz = 0;
+  int32_t* hub_rows = nullptr;  // [hub_n] sorted
+  int32_t* hub_c0 = nullptr;    // [hub_n + 1]
+  int32_t* hub_cs = nullptr;    // [hub_chunks] first entry of each chunk
+  int32_t* hub_ce = nullptr;    // [hub_chunks] one past its last entry
+  int hub_n = 0, hub_chunks = 0;
+};
 
 struct DevBuf {
   void* ptr = nullptr;
@@ -58,22 +75,16 @@ struct mlct_op {
   int device = 0;
   int kind = mlct::OP_CSR;
   int64_t d = 0;
-  // CSR
-  int64_t nnz = 0;
-  const int32_t* rowptr = nullptr;
-  const int32_t* col = nullptr;
-  const void* val = nullptr;  // nullptr = pattern
-  int max_row_nnz = 0;
+  // CSR: the matrix (OP_CSR), or X^T (cols x rows) for OP_GRAM_CSR, the pass
+  // that carries the recurrence; csrx = X (rows x cols) for OP_GRAM_CSR
+  mlct::CsrMat csr, csrx;
+  double gram_lambda = 0.0;    // OP_GRAM_CSR: the shift lambda
+  void* hub_mem = nullptr;     // hub table of csr (one allocation)
+  void* hubx_mem = nullptr;    // hub table of csrx
+  void* gram_mem = nullptr;    // OP_GRAM_CSR: the X^T arrays (owned)
   // tr A and ||A||_F^2 (exact low-degree traces), computed on first use
   bool stats_ready = false;
   double tr_a = 0.0, fro2 = 0.0;
-  // rows longer than kHubLen (sorted), their chunk ranges, chunk extents
-  int32_t* hub_rows = nullptr;  // [hub_n]
-  int32_t* hub_c0 = nullptr;    // [hub_n + 1]
-  int32_t* hub_cs = nullptr;    // [hub_chunks] first entry of each chunk
-  int32_t* hub_ce = nullptr;    // [hub_chunks] one past its last entry
-  int hub_n = 0, hub_chunks = 0;
-  void* hub_mem = nullptr;      // one allocation holding the four arrays
   int tuned_groups = 0;      // CSR: workgroup cap chosen by mlct_autotune (0 = default)
   int tuned_dense = -1;      // dense: 1 = 128x128, 2 = 64x64, 0 = 32x32 tiles, 3 = skinny, -1 = default rule
   // dense / Gram (row-major d x d)
@@ -112,7 +123,7 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -133,7 +144,7 @@ struct ProbeSrc {
 hipError_t launch_cheb_dct(hipStream_t s, int kind, double power, double a, double b,
                            int n, double* c_dev, double* log_scale_dev);
 hipError_t launch_csr_validate(hipStream_t s, const int32_t* rowptr, const int32_t* col,
-                               int64_t d, int64_t nnz, int32_t* flags_dev);
+                               int64_t nrows, int64_t ncols, int64_t nnz, int32_t* flags_dev);
 hipError_t launch_reduce_partials(hipStream_t s, const double* part, int steps, int nslots,
                                   int ngroups, int width, double* dots);
 hipError_t launch_assemble_moments(hipStream_t s, const double* dots, int steps, int width,
@@ -196,9 +207,17 @@ hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, int nbl
 // hub_part: workspace of op->hub_chunks x 64 elements of T (unused without
 // hub rows); the step first launches the hub chunk reduction into it.
 template <typename T>
-hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
+hipError_t launch_csr_step(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T ca, T cb,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
                            void* hub_part, double* part);
+// Gram operator A = X^T X + lambda I, one step: W = X V_k (rows x 64), then
+// V_new = ca X^T W + cb V_k [- V_prev] with the moments (cb includes
+// ca * lambda).  plan_rows / plan_cols: bands over X's rows / columns.
+template <typename T>
+hipError_t launch_gram_csr_step(hipStream_t s, const CsrMat& X, const CsrMat& XT, const T* vk,
+                                T* vm, T* W, T ca, T cb, bool has_prev, int zmode, ProbeSrc src,
+                                const CsrStepPlan& plan_rows, const CsrStepPlan& plan_cols,
+                                void* hubx_part, void* hubt_part, double* part);
 // Rows longer than kHubLen as (row, start, end) triples, unordered; count is
 // incremented once per such row (entries past cap are not written).
 hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
@@ -223,7 +242,7 @@ hipError_t launch_level_plan(hipStream_t s, const double* mu, int64_t ldmu, cons
 // ---- integer triangle moments (k_tri.hip) ----------------------------------
 hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
                            const CsrStepPlan& plan, int32_t* z);
-hipError_t launch_tri_step(hipStream_t s, const mlct_op* op, int pass, const CsrStepPlan& plan,
+hipError_t launch_tri_step(hipStream_t s, const CsrMat& m, int pass, const CsrStepPlan& plan,
                            const int32_t* vin, int32_t* vout, void* hub_part, long long* part);
 hipError_t launch_tri_reduce(hipStream_t s, const long long* part, int ngroups, int active,
                              int pass, long long* w, int64_t p0);
@@ -276,7 +295,8 @@ struct LanczosState {
 // out[0..6] = a, b, theta_min, theta_max, r_min, r_max, k
 hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int64_t lda,
                           int steps, uint64_t seed, double margin, double* Q, double* w,
-                          double* h, double* part, LanczosState* st, double* out);
+                          double* h, double* part, LanczosState* st, double* out,
+                          double* tmp);  // tmp: X-row scratch (OP_GRAM_CSR)
 
 // ---- learned control-variate level (k_mlp.hip) -----------------------------
 constexpr int kMlpHidden = 64;

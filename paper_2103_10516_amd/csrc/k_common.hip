@@ -52,8 +52,8 @@ __global__ __launch_bounds__(256) void cheb_dct_kernel(int kind, double power, d
 // flags[0]: bit0 rowptr[0] != 0, bit1 decreasing rowptr, bit2 rowptr[d] != nnz,
 // bit3 column out of range.  flags[1]: longest row.
 __global__ void csr_validate_kernel(const int32_t* __restrict__ rowptr,
-                                    const int32_t* __restrict__ col, int64_t d, int64_t nnz,
-                                    int32_t* __restrict__ flags) {
+                                    const int32_t* __restrict__ col, int64_t d, int64_t ncols,
+                                    int64_t nnz, int32_t* __restrict__ flags) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int bad = 0, longest = 0;
@@ -68,7 +68,7 @@ __global__ void csr_validate_kernel(const int32_t* __restrict__ rowptr,
   }
   for (int64_t t = tid; t < nnz; t += stride) {
     const int32_t j = col[t];
-    if (j < 0 || (int64_t)j >= d) bad |= 8;
+    if (j < 0 || (int64_t)j >= ncols) bad |= 8;
   }
   if (bad) atomicOr(&flags[0], bad);
   if (longest) atomicMax(&flags[1], longest);
@@ -250,12 +250,12 @@ hipError_t launch_cheb_dct(hipStream_t s, int kind, double power, double a, doub
 }
 
 hipError_t launch_csr_validate(hipStream_t s, const int32_t* rowptr, const int32_t* col,
-                               int64_t d, int64_t nnz, int32_t* flags_dev) {
+                               int64_t d, int64_t ncols, int64_t nnz, int32_t* flags_dev) {
   const int64_t work = d > nnz ? d : nnz;
   int64_t blocks = (work + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  csr_validate_kernel<<<(int)blocks, 256, 0, s>>>(rowptr, col, d, nnz, flags_dev);
+  csr_validate_kernel<<<(int)blocks, 256, 0, s>>>(rowptr, col, d, ncols, nnz, flags_dev);
   return hipGetLastError();
 }
 
@@ -349,9 +349,9 @@ hipError_t launch_op_stats(hipStream_t s, const mlct_op* op, double* partial, do
   const int64_t want = (op->d + kST - 1) / kST;
   const int g = (int)(want < kStatsGroups ? want : kStatsGroups);
   const bool csr = op->kind == OP_CSR;
-  op_stats_kernel<<<g, kST, 0, s>>>(csr ? op->rowptr : nullptr, csr ? op->col : nullptr,
-                                    csr ? static_cast<const float*>(op->val) : nullptr,
-                                    csr ? nullptr : op->A, op->dtype, op->lda, op->d, partial);
+  op_stats_kernel<<<g, kST, 0, s>>>(csr ? op->csr.rowptr : nullptr, csr ? op->csr.col : nullptr,
+                                    csr ? op->csr.val : nullptr, csr ? nullptr : op->A, op->dtype,
+                                    op->lda, op->d, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   op_stats_reduce_kernel<<<1, 64, 0, s>>>(partial, g, out);

@@ -102,6 +102,8 @@ __global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0
 template <typename T, int ZMODE, bool HAS_PREV>
 struct RecEpi {
   using Part = double;
+  static constexpr bool kOwn = true;    // needs V_k[i] of its own row
+  static constexpr bool kParts = true;  // writes moment partials
   T ca, cb;
   T* vm;
   ProbeSrc src;
@@ -147,6 +149,8 @@ struct RecEpi {
 template <int PASS>
 struct TriEpi {
   using Part = long long;
+  static constexpr bool kOwn = true;
+  static constexpr bool kParts = true;
   int32_t* vout;
   long long a1 = 0, a2 = 0;
   __device__ explicit TriEpi(int32_t* v) : vout(v) {}
@@ -160,6 +164,20 @@ struct TriEpi {
       a1 += (long long)own * acc;
     }
   }
+};
+
+// First product of a Gram step: the row sums are stored (W = X V_k), no
+// recurrence, no partials.
+template <typename T>
+struct StoreEpi {
+  using Part = double;
+  static constexpr bool kOwn = false;
+  static constexpr bool kParts = false;
+  T* out;
+  double a1 = 0.0, a2 = 0.0;
+  __device__ explicit StoreEpi(T* o) : out(o) {}
+  __device__ __forceinline__ T prev(int64_t) const { return T(0); }
+  __device__ __forceinline__ void finish(int64_t i, T acc, T, T) { out[i * 64 + lane_id()] = acc; }
 };
 
 // One gathered entry into a row sum: weight w (ignored for patterns) times x,
@@ -308,12 +326,16 @@ __device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int q, 
 // (unused slots gather some valid row with weight 0), all in flight before
 // the first is consumed; other groups take the generic loop, or with HUBS
 // the chunk partials of rows longer than kHubLen.
-template <typename T, bool PATTERN, int MAXNZ, bool OFF32, bool HUBS, class Epi>
+//
+// d: rows processed; dv: rows of the gathered block vk.  SEP: the own-row
+// value V_k[i] the epilogue needs comes from vown instead of vk (the second
+// product of a Gram step gathers from W but recurs on V_k).
+template <typename T, bool PATTERN, int MAXNZ, bool OFF32, bool HUBS, bool SEP, class Epi>
 __device__ __forceinline__ void csr_step_wg(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk, Epi& epi,
-    const HubView& hub, int rows_per_group, int ngroups, typename Epi::Part* __restrict__ part,
-    int bid) {
+    const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ vk,
+    const T* __restrict__ vown, Epi& epi, const HubView& hub, int rows_per_group, int ngroups,
+    typename Epi::Part* __restrict__ part, int bid) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
   constexpr int GPB = 64 / ROWS;  // groups per batch
   const int lane = lane_id(), wave = wave_id();
@@ -323,7 +345,12 @@ __device__ __forceinline__ void csr_step_wg(
 
   const int64_t ngrp = r1 > r0 ? (r1 - r0 + ROWS - 1) / ROWS : 0;  // groups in the band
   const int64_t nk = ngrp > wave ? (ngrp - wave + kWaves - 1) / kWaves : 0;  // this wave's
-  const RowReader<T, OFF32> rd(vk, d, lane);
+  const RowReader<T, OFF32> rd(vk, dv, lane);
+  auto own = [&](int64_t i) -> T {
+    if constexpr (!Epi::kOwn) return T(0);
+    else if constexpr (SEP) return vown[i * 64 + lane];
+    else return rd(i, lane);
+  };
   // first row of this wave's k-th group, and its number of rows
   auto grp_row0 = [&](int64_t k) { return r0 + (k * kWaves + wave) * ROWS; };
   auto grp_rows = [&](int64_t k) { return (int)min<int64_t>(ROWS, r1 - grp_row0(k)); };
@@ -365,7 +392,7 @@ __device__ __forceinline__ void csr_step_wg(
           const int64_t i = row0 + min(r, cur.nr - 1);
 #pragma unroll
           for (int t = 0; t < MAXNZ; ++t) x[r][t] = rd(read_lane(cj, min(cur.off[r] + t, 63)), lane);
-          xi[r] = rd(i, lane);
+          xi[r] = own(i);
           xp[r] = epi.prev(i);
         }
       }
@@ -403,7 +430,7 @@ __device__ __forceinline__ void csr_step_wg(
               acc = hub_sum<T>(hub, i);
             else
               acc = row_dot_chunked<T, PATTERN>(col, val, rd, s0, s0 + cur.len[r]);
-            epi.finish(i, acc, rd(i, lane), epi.prev(i));
+            epi.finish(i, acc, own(i), epi.prev(i));
           }
         }
       }
@@ -420,7 +447,7 @@ __device__ __forceinline__ void csr_step_wg(
       av = avn;
     }
   }
-  store_partials<typename Epi::Part>(epi.a1, epi.a2, g, ngroups, part);
+  if constexpr (Epi::kParts) store_partials<typename Epi::Part>(epi.a1, epi.a2, g, ngroups, part);
 }
 
 template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32, bool HUBS>
@@ -430,8 +457,36 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub, int rows_per_group, int ngroups,
     double* __restrict__ part) {
   RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
-  csr_step_wg<T, PATTERN, MAXNZ, OFF32, HUBS>(rowptr, col, val, d, nnz, vk, epi, hub,
-                                              rows_per_group, ngroups, part, blockIdx.x);
+  csr_step_wg<T, PATTERN, MAXNZ, OFF32, HUBS, false>(rowptr, col, val, d, d, nnz, vk, nullptr,
+                                                     epi, hub, rows_per_group, ngroups, part,
+                                                     blockIdx.x);
+}
+
+// Gram step, first product: W = X V_k over X's rows (V_k has dv = X's
+// column count rows).
+template <typename T, bool PATTERN, int MAXNZ, bool OFF32, bool HUBS>
+__global__ __launch_bounds__(kThreads) void gram_pass1_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ vk,
+    T* __restrict__ W, HubView hub, int rows_per_group, int ngroups) {
+  StoreEpi<T> epi(W);
+  csr_step_wg<T, PATTERN, MAXNZ, OFF32, HUBS, false>(rowptr, col, val, d, dv, nnz, vk, nullptr,
+                                                     epi, hub, rows_per_group, ngroups, nullptr,
+                                                     blockIdx.x);
+}
+
+// Gram step, second product with the recurrence: V_new = ca X^T W + cb V_k
+// [- V_prev] over X^T's rows, gathering from W, own rows from V_k.
+template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32, bool HUBS>
+__global__ __launch_bounds__(kThreads) void gram_pass2_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ W,
+    const T* __restrict__ vk, T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub,
+    int rows_per_group, int ngroups, double* __restrict__ part) {
+  RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
+  csr_step_wg<T, PATTERN, MAXNZ, OFF32, HUBS, true>(rowptr, col, val, d, dv, nnz, W, vk, epi,
+                                                    hub, rows_per_group, ngroups, part,
+                                                    blockIdx.x);
 }
 
 // Integer pass of triangle counting over a pattern CSR: vin = z (PASS 1,
@@ -442,8 +497,9 @@ __global__ __launch_bounds__(kThreads) void tri_step_kernel(
     const int32_t* __restrict__ vin, int32_t* __restrict__ vout, HubView hub,
     int rows_per_group, int ngroups, long long* __restrict__ part) {
   TriEpi<PASS> epi(vout);
-  csr_step_wg<int32_t, true, MAXNZ, OFF32, HUBS>(rowptr, col, nullptr, d, nnz, vin, epi, hub,
-                                                 rows_per_group, ngroups, part, blockIdx.x);
+  csr_step_wg<int32_t, true, MAXNZ, OFF32, HUBS, false>(rowptr, col, nullptr, d, d, nnz, vin,
+                                                        nullptr, epi, hub, rows_per_group,
+                                                        ngroups, part, blockIdx.x);
 }
 
 // Chunk partials of the hub rows: one wave per chunk of at most kHubChunk
@@ -507,9 +563,9 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   const float cb = (float)(HAS_PREV ? 2.0 * B.beta : B.beta);
   RecEpi<float, ZMODE, HAS_PREV> epi(ca, cb, vm, B.src);
   const HubView nohub{nullptr, nullptr, 0, nullptr};
-  csr_step_wg<float, PATTERN, MAXNZ, true, false>(B.rowptr, B.col, B.val, B.d, B.nnz, vk, epi,
-                                                  nohub, B.rows_per_group, B.ngroups,
-                                                  B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+  csr_step_wg<float, PATTERN, MAXNZ, true, false, false>(
+      B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, B.rows_per_group,
+      B.ngroups, B.part + (size_t)s * 2 * B.ngroups * 64, bid);
 }
 
 __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
@@ -521,45 +577,48 @@ __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
 }
 
 template <typename T, bool PATTERN, int ZMODE, int MAXNZ, bool OFF32, bool HUBS>
-hipError_t launch_step_t(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
+hipError_t launch_step_t(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T ca, T cb,
                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, const HubView& hub,
                          double* part) {
   const dim3 grid(plan.ngroups), block(kThreads);
-  const float* val = static_cast<const float*>(op->val);
   if (has_prev)
     csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32, HUBS><<<grid, block, 0, s>>>(
-        op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
+        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
         plan.ngroups, part);
   else
     csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32, HUBS><<<grid, block, 0, s>>>(
-        op->rowptr, op->col, val, op->d, op->nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
+        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
         plan.ngroups, part);
   return hipGetLastError();
 }
 
-// Whether a block's gathers can use 32-bit offsets (4-byte elements, block
-// under 4 GiB).
+// Whether gathers from a block of dv rows can use 32-bit offsets (4-byte
+// elements, block under 4 GiB).
 template <typename T>
-bool block_off32(const mlct_op* op) {
-  return sizeof(T) == 4 && (uint64_t)op->d * 64 * sizeof(T) <= 0xFFFFFFFFull;
+bool block_off32(int64_t dv) {
+  return sizeof(T) == 4 && (uint64_t)dv * 64 * sizeof(T) <= 0xFFFFFFFFull;
 }
 
-// Hub chunk partials of vk for this step (a no-op without hub rows).
+HubView hub_view(const CsrMat& m, void* hub_part) {
+  return HubView{m.hub_rows, m.hub_c0, m.hub_n, hub_part};
+}
+
+// Hub chunk partials of the gathered block v (dv rows) for this step (a
+// no-op without hub rows).
 template <typename T, bool PATTERN>
-hipError_t launch_hubs(hipStream_t s, const mlct_op* op, const T* vk, void* hub_part) {
-  if (op->hub_n == 0) return hipSuccess;
-  const int grid = (op->hub_chunks + 3) / 4;
-  const float* val = static_cast<const float*>(op->val);
+hipError_t launch_hubs(hipStream_t s, const CsrMat& m, const T* v, int64_t dv, void* hub_part) {
+  if (m.hub_n == 0) return hipSuccess;
+  const int grid = (m.hub_chunks + 3) / 4;
   T* out = static_cast<T*>(hub_part);
   if constexpr (sizeof(T) == 4) {
-    if (block_off32<T>(op)) {
-      csr_hub_kernel<T, PATTERN, true><<<grid, 256, 0, s>>>(op->col, val, op->d, vk, op->hub_cs,
-                                                           op->hub_ce, op->hub_chunks, out);
+    if (block_off32<T>(dv)) {
+      csr_hub_kernel<T, PATTERN, true><<<grid, 256, 0, s>>>(m.col, m.val, dv, v, m.hub_cs,
+                                                           m.hub_ce, m.hub_chunks, out);
       return hipGetLastError();
     }
   }
-  csr_hub_kernel<T, PATTERN, false><<<grid, 256, 0, s>>>(op->col, val, op->d, vk, op->hub_cs,
-                                                        op->hub_ce, op->hub_chunks, out);
+  csr_hub_kernel<T, PATTERN, false><<<grid, 256, 0, s>>>(m.col, m.val, dv, v, m.hub_cs, m.hub_ce,
+                                                        m.hub_chunks, out);
   return hipGetLastError();
 }
 
@@ -567,63 +626,102 @@ hipError_t launch_hubs(hipStream_t s, const mlct_op* op, const T* vk, void* hub_
 // holds the longest row, else 8 (longer rows then take the generic loop, and
 // rows past kHubLen the hub partials).  FP32 blocks under 4 GiB use 32-bit
 // gather offsets; FP64 (a verification precision) uses one general
-// instantiation.
-template <typename T, bool PATTERN, int ZMODE>
-hipError_t launch_step_nz(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
-                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, void* hub_part,
-                          double* part) {
-  const HubView hub{op->hub_rows, op->hub_c0, op->hub_n, hub_part};
-  if (op->hub_n > 0) {
-    const hipError_t e = launch_hubs<T, PATTERN>(s, op, vk, hub_part);
-    if (e != hipSuccess) return e;
-  }
+// instantiation.  F(MAXNZ, OFF32, HUBS) launches one instantiation.
+template <typename T, class F>
+hipError_t dispatch_shape(const CsrMat& m, int64_t dv, F&& f) {
   if constexpr (sizeof(T) == 4) {
-    if (block_off32<T>(op)) {
-      if (op->hub_n > 0)
-        return launch_step_t<T, PATTERN, ZMODE, 8, true, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
-      if (op->max_row_nnz <= 4)
-        return launch_step_t<T, PATTERN, ZMODE, 4, true, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
-      if (op->max_row_nnz <= 5)
-        return launch_step_t<T, PATTERN, ZMODE, 5, true, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
-      return launch_step_t<T, PATTERN, ZMODE, 8, true, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
+    if (block_off32<T>(dv)) {
+      if (m.hub_n > 0) return f(std::integral_constant<int, 8>(), std::true_type(), std::true_type());
+      if (m.max_row_nnz <= 4) return f(std::integral_constant<int, 4>(), std::true_type(), std::false_type());
+      if (m.max_row_nnz <= 5) return f(std::integral_constant<int, 5>(), std::true_type(), std::false_type());
+      return f(std::integral_constant<int, 8>(), std::true_type(), std::false_type());
     }
   }
-  if (op->hub_n > 0)
-    return launch_step_t<T, PATTERN, ZMODE, 8, false, true>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
-  return launch_step_t<T, PATTERN, ZMODE, 8, false, false>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub, part);
+  if (m.hub_n > 0) return f(std::integral_constant<int, 8>(), std::false_type(), std::true_type());
+  return f(std::integral_constant<int, 8>(), std::false_type(), std::false_type());
+}
+
+template <typename T, bool PATTERN, int ZMODE>
+hipError_t launch_step_nz(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T ca, T cb,
+                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, void* hub_part,
+                          double* part) {
+  const HubView hub = hub_view(m, hub_part);
+  if (m.hub_n > 0) {
+    const hipError_t e = launch_hubs<T, PATTERN>(s, m, vk, m.ncols, hub_part);
+    if (e != hipSuccess) return e;
+  }
+  return dispatch_shape<T>(m, m.ncols, [&](auto mz, auto off32, auto hubs) {
+    return launch_step_t<T, PATTERN, ZMODE, decltype(mz)::value, decltype(off32)::value,
+                         decltype(hubs)::value>(s, m, vk, vm, ca, cb, has_prev, src, plan, hub,
+                                                part);
+  });
 }
 
 template <typename T>
-hipError_t launch_step_any(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
+hipError_t launch_step_any(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T ca, T cb,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
                            void* hub_part, double* part) {
-  const bool pat = op->val == nullptr;
+  const bool pat = m.val == nullptr;
   if (pat) {
-    if (zmode == 0) return launch_step_nz<T, true, 0>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
-    if (zmode == 1) return launch_step_nz<T, true, 1>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
-    return launch_step_nz<T, true, 2>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+    if (zmode == 0) return launch_step_nz<T, true, 0>(s, m, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+    if (zmode == 1) return launch_step_nz<T, true, 1>(s, m, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+    return launch_step_nz<T, true, 2>(s, m, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
   }
-  if (zmode == 0) return launch_step_nz<T, false, 0>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
-  if (zmode == 1) return launch_step_nz<T, false, 1>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
-  return launch_step_nz<T, false, 2>(s, op, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+  if (zmode == 0) return launch_step_nz<T, false, 0>(s, m, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+  if (zmode == 1) return launch_step_nz<T, false, 1>(s, m, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
+  return launch_step_nz<T, false, 2>(s, m, vk, vm, ca, cb, has_prev, src, plan, hub_part, part);
 }
 
 template <int PASS, bool OFF32>
-hipError_t launch_tri_pass(hipStream_t s, const mlct_op* op, const CsrStepPlan& plan,
+hipError_t launch_tri_pass(hipStream_t s, const CsrMat& m, const CsrStepPlan& plan,
                            const int32_t* vin, int32_t* vout, const HubView& hub,
                            long long* part) {
   const dim3 grid(plan.ngroups), block(kThreads);
 #define MLCT_TRI(M, H)                                                                        \
-  tri_step_kernel<PASS, M, OFF32, H><<<grid, block, 0, s>>>(op->rowptr, op->col, op->d,        \
-                                                            op->nnz, vin, vout, hub,          \
+  tri_step_kernel<PASS, M, OFF32, H><<<grid, block, 0, s>>>(m.rowptr, m.col, m.nrows, m.nnz,  \
+                                                            vin, vout, hub,                   \
                                                             plan.rows_per_group, plan.ngroups, \
                                                             part)
-  if (op->hub_n > 0) MLCT_TRI(8, true);
-  else if (op->max_row_nnz <= 4) MLCT_TRI(4, false);
-  else if (op->max_row_nnz <= 5) MLCT_TRI(5, false);
+  if (m.hub_n > 0) MLCT_TRI(8, true);
+  else if (m.max_row_nnz <= 4) MLCT_TRI(4, false);
+  else if (m.max_row_nnz <= 5) MLCT_TRI(5, false);
   else MLCT_TRI(8, false);
 #undef MLCT_TRI
   return hipGetLastError();
+}
+
+// The two products of a Gram step for one pattern/valued and z-mode choice.
+template <typename T, bool PATTERN, int ZMODE>
+hipError_t launch_gram_z(hipStream_t s, const CsrMat& X, const CsrMat& XT, const T* vk, T* vm,
+                         T* W, T ca, T cb, bool has_prev, ProbeSrc src,
+                         const CsrStepPlan& pr, const CsrStepPlan& pc, void* hubx_part,
+                         void* hubt_part, double* part) {
+  hipError_t e = launch_hubs<T, PATTERN>(s, X, vk, X.ncols, hubx_part);
+  if (e != hipSuccess) return e;
+  const HubView hx = hub_view(X, hubx_part), ht = hub_view(XT, hubt_part);
+  e = dispatch_shape<T>(X, X.ncols, [&](auto mz, auto off32, auto hubs) {
+    gram_pass1_kernel<T, PATTERN, decltype(mz)::value, decltype(off32)::value,
+                      decltype(hubs)::value><<<pr.ngroups, kThreads, 0, s>>>(
+        X.rowptr, X.col, X.val, X.nrows, X.ncols, X.nnz, vk, W, hx, pr.rows_per_group,
+        pr.ngroups);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  e = launch_hubs<T, PATTERN>(s, XT, W, XT.ncols, hubt_part);
+  if (e != hipSuccess) return e;
+  return dispatch_shape<T>(XT, XT.ncols, [&](auto mz, auto off32, auto hubs) {
+    if (has_prev)
+      gram_pass2_kernel<T, PATTERN, ZMODE, true, decltype(mz)::value, decltype(off32)::value,
+                        decltype(hubs)::value><<<pc.ngroups, kThreads, 0, s>>>(
+          XT.rowptr, XT.col, XT.val, XT.nrows, XT.ncols, XT.nnz, W, vk, vm, ca, cb, src, ht,
+          pc.rows_per_group, pc.ngroups, part);
+    else
+      gram_pass2_kernel<T, PATTERN, ZMODE, false, decltype(mz)::value, decltype(off32)::value,
+                        decltype(hubs)::value><<<pc.ngroups, kThreads, 0, s>>>(
+          XT.rowptr, XT.col, XT.val, XT.nrows, XT.ncols, XT.nnz, W, vk, vm, ca, cb, src, ht,
+          pc.rows_per_group, pc.ngroups, part);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace
@@ -649,25 +747,44 @@ hipError_t launch_probe_init(hipStream_t s, T* v0, int64_t d, ProbeSrc src,
 }
 
 template <typename T>
-hipError_t launch_csr_step(hipStream_t s, const mlct_op* op, const T* vk, T* vm, T ca, T cb,
+hipError_t launch_csr_step(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T ca, T cb,
                            bool has_prev, int zmode, ProbeSrc src, const CsrStepPlan& plan,
                            void* hub_part, double* part) {
-  return launch_step_any<T>(s, op, vk, vm, ca, cb, has_prev, zmode, src, plan, hub_part, part);
+  return launch_step_any<T>(s, m, vk, vm, ca, cb, has_prev, zmode, src, plan, hub_part, part);
 }
 
-hipError_t launch_tri_step(hipStream_t s, const mlct_op* op, int pass, const CsrStepPlan& plan,
+template <typename T>
+hipError_t launch_gram_csr_step(hipStream_t s, const CsrMat& X, const CsrMat& XT, const T* vk,
+                                T* vm, T* W, T ca, T cb, bool has_prev, int zmode, ProbeSrc src,
+                                const CsrStepPlan& plan_rows, const CsrStepPlan& plan_cols,
+                                void* hubx_part, void* hubt_part, double* part) {
+#define MLCT_GZ(P, Z)                                                                       \
+  return launch_gram_z<T, P, Z>(s, X, XT, vk, vm, W, ca, cb, has_prev, src, plan_rows,      \
+                                plan_cols, hubx_part, hubt_part, part)
+  if (X.val == nullptr) {
+    if (zmode == 0) MLCT_GZ(true, 0);
+    if (zmode == 1) MLCT_GZ(true, 1);
+    MLCT_GZ(true, 2);
+  }
+  if (zmode == 0) MLCT_GZ(false, 0);
+  if (zmode == 1) MLCT_GZ(false, 1);
+  MLCT_GZ(false, 2);
+#undef MLCT_GZ
+}
+
+hipError_t launch_tri_step(hipStream_t s, const CsrMat& m, int pass, const CsrStepPlan& plan,
                            const int32_t* vin, int32_t* vout, void* hub_part, long long* part) {
-  const HubView hub{op->hub_rows, op->hub_c0, op->hub_n, hub_part};
-  if (op->hub_n > 0) {
-    const hipError_t e = launch_hubs<int32_t, true>(s, op, vin, hub_part);
+  const HubView hub = hub_view(m, hub_part);
+  if (m.hub_n > 0) {
+    const hipError_t e = launch_hubs<int32_t, true>(s, m, vin, m.ncols, hub_part);
     if (e != hipSuccess) return e;
   }
-  const bool off32 = block_off32<int32_t>(op);
+  const bool off32 = block_off32<int32_t>(m.ncols);
   if (pass == 1)
-    return off32 ? launch_tri_pass<1, true>(s, op, plan, vin, vout, hub, part)
-                 : launch_tri_pass<1, false>(s, op, plan, vin, vout, hub, part);
-  return off32 ? launch_tri_pass<2, true>(s, op, plan, vin, nullptr, hub, part)
-               : launch_tri_pass<2, false>(s, op, plan, vin, nullptr, hub, part);
+    return off32 ? launch_tri_pass<1, true>(s, m, plan, vin, vout, hub, part)
+                 : launch_tri_pass<1, false>(s, m, plan, vin, vout, hub, part);
+  return off32 ? launch_tri_pass<2, true>(s, m, plan, vin, nullptr, hub, part)
+               : launch_tri_pass<2, false>(s, m, plan, vin, nullptr, hub, part);
 }
 
 hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
@@ -707,11 +824,19 @@ template hipError_t launch_probe_init<float>(hipStream_t, float*, int64_t, Probe
                                              const CsrStepPlan&, double*);
 template hipError_t launch_probe_init<double>(hipStream_t, double*, int64_t, ProbeSrc,
                                               const CsrStepPlan&, double*);
-template hipError_t launch_csr_step<float>(hipStream_t, const mlct_op*, const float*, float*,
+template hipError_t launch_csr_step<float>(hipStream_t, const CsrMat&, const float*, float*,
                                            float, float, bool, int, ProbeSrc,
                                            const CsrStepPlan&, void*, double*);
-template hipError_t launch_csr_step<double>(hipStream_t, const mlct_op*, const double*,
+template hipError_t launch_csr_step<double>(hipStream_t, const CsrMat&, const double*,
                                             double*, double, double, bool, int, ProbeSrc,
                                             const CsrStepPlan&, void*, double*);
+template hipError_t launch_gram_csr_step<float>(hipStream_t, const CsrMat&, const CsrMat&,
+                                                const float*, float*, float*, float, float, bool,
+                                                int, ProbeSrc, const CsrStepPlan&,
+                                                const CsrStepPlan&, void*, void*, double*);
+template hipError_t launch_gram_csr_step<double>(hipStream_t, const CsrMat&, const CsrMat&,
+                                                 const double*, double*, double*, double, double,
+                                                 bool, int, ProbeSrc, const CsrStepPlan&,
+                                                 const CsrStepPlan&, void*, void*, double*);
 
 }  // namespace mlct

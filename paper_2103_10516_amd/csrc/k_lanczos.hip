@@ -47,9 +47,11 @@ __global__ void lz_start_kernel(double* __restrict__ q0, int64_t d, uint64_t see
 }
 
 // w = A q (CSR, FP64 arithmetic on FP32 or implicit-1 values): one thread per row.
+// w = A q (+ shift * qs when qs is given): one thread per row.
 __global__ void lz_spmv_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                const float* __restrict__ val, int64_t d,
                                const double* __restrict__ q, double* __restrict__ w,
+                               double shift, const double* __restrict__ qs,
                                const LanczosState* st) {
   if (st->stopped) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
@@ -57,6 +59,7 @@ __global__ void lz_spmv_kernel(const int32_t* __restrict__ rowptr, const int32_t
     double s = 0.0;
     for (int t = rowptr[i]; t < rowptr[i + 1]; ++t)
       s += (val ? (double)val[t] : 1.0) * q[col[t]];
+    if (qs) s += shift * qs[i];
     w[i] = s;
   }
 }
@@ -221,17 +224,24 @@ __global__ void lz_interval_kernel(LanczosState* st, double margin, double* out)
 
 hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int64_t lda,
                           int steps, uint64_t seed, double margin, double* Q, double* w,
-                          double* h, double* part, LanczosState* st, double* out) {
+                          double* h, double* part, LanczosState* st, double* out, double* tmp) {
   const int64_t d = op->d;
   const int nb = (int)((d + kT - 1) / kT < 1024 ? (d + kT - 1) / kT : 1024);
   const int grid = nb;
   lz_start_kernel<<<grid, kT, 0, s>>>(Q, d, seed, st);
   for (int j = 0; j < steps; ++j) {
     const double* qj = Q + (int64_t)j * d;
-    if (op->kind == OP_CSR)
-      lz_spmv_kernel<<<grid, kT, 0, s>>>(op->rowptr, op->col, static_cast<const float*>(op->val),
-                                         d, qj, w, st);
-    else
+    if (op->kind == OP_CSR) {
+      lz_spmv_kernel<<<grid, kT, 0, s>>>(op->csr.rowptr, op->csr.col, op->csr.val, d, qj, w, 0.0,
+                                         nullptr, st);
+    } else if (op->kind == OP_GRAM_CSR) {  // w = X^T (X q) + lambda q
+      const CsrMat& X = op->csrx;
+      const CsrMat& XT = op->csr;
+      lz_spmv_kernel<<<grid, kT, 0, s>>>(X.rowptr, X.col, X.val, X.nrows, qj, tmp, 0.0, nullptr,
+                                         st);
+      lz_spmv_kernel<<<grid, kT, 0, s>>>(XT.rowptr, XT.col, XT.val, d, tmp, w, op->gram_lambda,
+                                         qj, st);
+    } else
       lz_gemv_kernel<<<grid, kT, 0, s>>>(static_cast<const double*>(a64), lda, d, qj, w, st);
     for (int pass = 0; pass < 2; ++pass) {
       lz_dots_kernel<<<dim3(nb, j + 1), kT, 0, s>>>(Q, d, w, j + 1, part, st);

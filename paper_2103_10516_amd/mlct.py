@@ -565,3 +565,18 @@ def mlct_estimate_auto(ctx: Context, op: Op, kind: int, a: float, b: float, n: i
            "probe_degrees": r.probe_degrees, "max_moment_ratio": r.max_moment_ratio,
            "interval": (r.interval_a, r.interval_b), "flags": r.flags}
     return res, _plan_dict(p)
+
+
+def mlct_op_gram_csr(ctx: Context, rowptr, col, val, cols: int, lam: float = 0.0) -> Op:
+    """A = X^T X + lam I for X a device CSR (rowptr int32[rows+1], col
+    int32[nnz] in [0, cols), val float32[nnz] or None for a pattern)."""
+    rows = rowptr.numel() - 1
+    nnz = col.numel()
+    h = lib()
+    h.mlct_op_gram_csr.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_void_p)]
+    h.mlct_op_gram_csr.restype = C.c_int
+    hd = C.c_void_p()
+    _check(ctx, h.mlct_op_gram_csr(ctx.handle, rows, cols, nnz, _ptr(rowptr), _ptr(col),
+                                   _ptr(val), lam, C.byref(hd)))
+    return Op(ctx, hd, (rowptr, col, val), cols)
