@@ -268,6 +268,28 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
                           const mlct_levels* levels, uint64_t seed, int32_t prec,
                           int32_t mode, mlct_result* out);
 
+/* Stochastic Lanczos quadrature (the Lanczos-based alternative to
+ * Chebyshev interpolation of the paper's introduction).  Per probe z, k
+ * Lanczos steps from z/|z| (FP64, no reorthogonalisation; a probe whose
+ * Krylov space is exhausted, |w_{j+1}| <= 1e-12 max|a_i|, stops early)
+ * give the Jacobi matrix T_j, and Gauss quadrature gives
+ * q = |z|^2 sum_i S_{1i}^2 f(theta_i) with T_j = S diag(theta) S^T (exact
+ * for polynomials of degree <= 2j - 1).  CSR operators; 1 <= k <= 256;
+ * probes in blocks of 64.  q_out: host, probes->m values.  EUNSUPPORTED for
+ * dense or Gram operators. */
+mlct_status mlct_slq_quadforms(mlct_ctx* ctx, const mlct_op* op, mlct_func f, int32_t k,
+                               const mlct_probes* probes, double* q_out);
+
+/* Two-level estimator with a Lanczos-quadrature fine level (Sections 2.3
+ * and 4 with SLQ as the level-n approximator): level 0 = z^T p_l(A_hat) z
+ * with the degree-l interpolant (l = cheb_degree, arithmetic prec / mode as
+ * in mlct_estimate) on probe ids [0, m0); level 1 = q_SLQ,k - z^T p_l z on
+ * ids [m0, m0 + m1).  Unbiased for E[q_SLQ,k].  out->level_mean/var hold the
+ * two levels; matvecs counts both parts; a = b = NaN uses mlct_bounds. */
+mlct_status mlct_estimate_slq(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a,
+                              double b, int32_t cheb_degree, int64_t m0, int32_t k, int64_t m1,
+                              uint64_t seed, int32_t prec, int32_t mode, mlct_result* out);
+
 /* Automatic level selection (Section 3.2, Theorem thm:levels).
  *
  * From a pilot table of per-probe terms t_j = c_j z^T T_j(A_hat) z

@@ -1732,6 +1732,157 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   return MLCT_OK;
 }
 
+// ---- stochastic Lanczos quadrature -------------------------------------------
+namespace {
+
+// SLQ values of the src.active probes of one block (CSR operators, FP64),
+// into q_dev[0..active).
+mlct_status run_block_slq(mlct_ctx* ctx, const mlct_op* op, int k, mlct_func f,
+                          double log_scale, ProbeSrc src, double* q_dev) {
+  const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
+  const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(double);
+  void *w0, *w1, *w, *part, *dots, *hub = nullptr;
+  CHECK(ws_get(ctx, WS_V0, vbytes, &w0));
+  CHECK(ws_get(ctx, WS_V1, vbytes, &w1));
+  const size_t state_off = (vbytes + 255) & ~(size_t)255;
+  const size_t scratch_off = (state_off + sizeof(SlqState) + 255) & ~(size_t)255;
+  CHECK(ws_get(ctx, WS_SLQ, scratch_off + (size_t)3 * k * 64 * sizeof(double), &w));
+  CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * sizeof(double), &part));
+  CHECK(ws_get(ctx, WS_MISC, (size_t)2 * kBlockProbes * sizeof(double), &dots));
+  if (op->csr.hub_n > 0)
+    CHECK(ws_get(ctx, WS_HUB, (size_t)op->csr.hub_chunks * kBlockProbes * sizeof(double), &hub));
+  double* W0 = static_cast<double*>(w0);
+  double* W1 = static_cast<double*>(w1);
+  double* U = static_cast<double*>(w);
+  SlqState* st = reinterpret_cast<SlqState*>(static_cast<char*>(w) + state_off);
+  double* scratch = reinterpret_cast<double*>(static_cast<char*>(w) + scratch_off);
+  double* P = static_cast<double*>(part);
+  double* D = static_cast<double*>(dots);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_probe_init<double>(s, W1, op->d, src, plan, P));
+  HIPCHK(ctx, launch_reduce_partials(s, P, 1, 2, plan.ngroups, kBlockProbes, D));
+  HIPCHK(ctx, hipMemsetAsync(W0, 0, vbytes, s));
+  HIPCHK(ctx, launch_slq_init(s, D, k, st));
+  for (int j = 0; j < k; ++j) {
+    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
+    HIPCHK(ctx, launch_slq_spmm(s, op->csr, W1, U, st->s_cur, plan, hub, P));
+    tm.done();
+    HIPCHK(ctx, launch_reduce_partials(s, P, 1, 2, plan.ngroups, kBlockProbes, D));
+    HIPCHK(ctx, launch_slq_alpha(s, D, j, st));
+    HIPCHK(ctx, launch_slq_update(s, U, W1, W0, st, j, op->d, plan, P));
+    HIPCHK(ctx, launch_reduce_partials(s, P, 1, 2, plan.ngroups, kBlockProbes, D));
+    HIPCHK(ctx, launch_slq_beta(s, D, j, k, st));
+    double* t = W0;  // rotate: w_{j-1} <- w_j <- w_{j+1}
+    W0 = W1;
+    W1 = U;
+    U = t;
+  }
+  HIPCHK(ctx, launch_slq_quadrature(s, st, k, f.kind, f.power, log_scale, src.active, scratch,
+                                    q_dev));
+  return MLCT_OK;
+}
+
+mlct_status check_slq_args(mlct_ctx* ctx, const mlct_op* op, int k) {
+  if (!op) return fail(ctx, MLCT_EINVAL, "op is required");
+  if (op->kind != OP_CSR)
+    return fail(ctx, MLCT_EUNSUPPORTED, "Lanczos quadrature runs on CSR operators");
+  if (k < 1 || k > kSlqMaxSteps)
+    return fail(ctx, MLCT_EINVAL, "Lanczos steps must be in [1, %d]", kSlqMaxSteps);
+  return MLCT_OK;
+}
+
+}  // namespace
+
+extern "C" mlct_status mlct_slq_quadforms(mlct_ctx* ctx, const mlct_op* op, mlct_func f,
+                                          int32_t k, const mlct_probes* probes,
+                                          double* q_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  CHECK(check_slq_args(ctx, op, k));
+  if (!q_out) return fail(ctx, MLCT_EINVAL, "q_out is required");
+  if (f.kind < MLCT_LOG || f.kind > MLCT_POW) return fail(ctx, MLCT_EINVAL, "unknown function");
+  CHECK(check_probes(ctx, op, probes));
+  CHECK(set_device(ctx));
+  void* q;
+  CHECK(ws_get(ctx, WS_SLQQ, (size_t)probes->m * sizeof(double), &q));
+  double* qd = static_cast<double*>(q);
+  for (int64_t p0 = 0; p0 < probes->m; p0 += kBlockProbes) {
+    ProbeSrc src;
+    src.seed = probes->seed;
+    src.first_id = probes->first_id + p0;
+    src.entries = probes->kind == MLCT_PROBE_EXPLICIT ? probes->entries_dev : nullptr;
+    src.ld = probes->ld_entries;
+    src.active = (int32_t)std::min<int64_t>(kBlockProbes, probes->m - p0);
+    CHECK(run_block_slq(ctx, op, k, f, 0.0, src, qd + p0));
+  }
+  HIPCHK(ctx, hipMemcpyAsync(q_out, qd, (size_t)probes->m * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  return sync_stream(ctx);
+}
+
+extern "C" mlct_status mlct_estimate_slq(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a,
+                                         double b, int32_t cheb_degree, int64_t m0, int32_t k,
+                                         int64_t m1, uint64_t seed, int32_t prec, int32_t mode,
+                                         mlct_result* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  CHECK(check_slq_args(ctx, op, k));
+  if (!out) return fail(ctx, MLCT_EINVAL, "out is required");
+  if (m0 < 1 || m1 < 1) return fail(ctx, MLCT_EINVAL, "both levels need samples");
+  if (cheb_degree < 1 || cheb_degree > kMaxDegree)
+    return fail(ctx, MLCT_EINVAL, "Chebyshev degree must be in [1, %d]", kMaxDegree);
+  CHECK(check_mode_prec(ctx, mode, prec));
+  if (std::isnan(a) && std::isnan(b)) {
+    const int steps = op->d < 64 ? (int)op->d : 64;
+    CHECK(mlct_bounds(ctx, op, steps, seed + kGamma, 0.01, &a, &b));
+  }
+  CHECK(check_func(ctx, f, a, b));
+  CHECK(set_device(ctx));
+  const int n = cheb_degree;
+  const int64_t ldmu = n + 1, total = m0 + m1;
+  void *mu, *coef, *q, *res;
+  CHECK(ws_get(ctx, WS_MU, (size_t)total * ldmu * sizeof(double), &mu));
+  CHECK(ws_get(ctx, WS_COEF, (size_t)(n + 2) * sizeof(double), &coef));
+  CHECK(ws_get(ctx, WS_SLQQ, (size_t)m1 * sizeof(double), &q));
+  CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_result), &res));
+  CHECK(reserve_block_ws(ctx, op, prec, mode, n, kBlockProbes));
+  double* cd = static_cast<double*>(coef);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_cheb_dct(s, f.kind, f.power, a, b, n, cd, cd + n + 1));
+  const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  const double ls = f.kind == MLCT_EXP ? 0.5 * (a + b) : 0.0;
+  mlct_probes pr{};
+  pr.kind = MLCT_PROBE_RADEMACHER;
+  pr.seed = seed;
+  pr.first_id = 0;
+  pr.m = total;
+  double* mud = static_cast<double*>(mu);
+  CHECK(run_probe_set(ctx, op, alpha, beta, n, mode, prec, &pr, mud, ldmu));
+  double* qd = static_cast<double*>(q);
+  for (int64_t p0 = 0; p0 < m1; p0 += kBlockProbes) {
+    ProbeSrc src{};
+    src.seed = seed;
+    src.first_id = m0 + p0;
+    src.active = (int32_t)std::min<int64_t>(kBlockProbes, m1 - p0);
+    CHECK(run_block_slq(ctx, op, k, f, ls, src, qd + p0));
+  }
+  HIPCHK(ctx, launch_slq_combine(s, mud, ldmu, cd, n, m0, m1, qd, ls,
+                                 static_cast<mlct_result*>(res)));
+  mlct_result h;
+  HIPCHK(ctx, hipMemcpyAsync(&h, res, sizeof h, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  if (!(h.max_moment_ratio <= 1.0 + 1e-3))
+    return fail(ctx, MLCT_ESPECTRUM,
+                "max |mu_j|/|z|^2 = %g > 1: the spectrum is not inside [a, b] = [%g, %g]",
+                h.max_moment_ratio, a, b);
+  h.matvecs = total * (int64_t)(mode == MLCT_DOUBLING ? (n + 1) / 2 : n) + m1 * (int64_t)k;
+  h.probe_degrees = total * (int64_t)n + m1 * (int64_t)k;
+  h.interval_a = a;
+  h.interval_b = b;
+  *out = h;
+  return MLCT_OK;
+}
+
 // ---- automatic level selection ----------------------------------------------
 namespace {
 

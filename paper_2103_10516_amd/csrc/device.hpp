@@ -42,6 +42,18 @@ __device__ __forceinline__ int wave_id() {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// The functions f of tr f(A) (mlct_func_kind).
+__device__ __forceinline__ double eval_f(int kind, double power, double t) {
+  switch (kind) {
+    case MLCT_LOG: return log(t);
+    case MLCT_SQRT: return sqrt(t);
+    case MLCT_EXP: return exp(t);
+    case MLCT_CUBE: return t * t * t;
+    case MLCT_INV: return 1.0 / t;
+    default: return pow(t, power);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T read_lane(T v, int l);
 

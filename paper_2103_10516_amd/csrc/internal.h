@@ -123,7 +123,7 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -238,6 +238,31 @@ struct LevelPlanDev {
 hipError_t launch_level_plan(hipStream_t s, const double* mu, int64_t ldmu, const double* coef,
                              int n, int64_t m, double* S, double* mean, double* V, int doubling,
                              double target, int budget, int64_t min_top, LevelPlanDev* out);
+
+// ---- stochastic Lanczos quadrature (k_slq.hip, slq_spmm in k_csr.hip) ------
+constexpr int kSlqMaxSteps = 256;
+// Per-block Lanczos state, lane = probe: the Jacobi matrices and scales.
+struct SlqState {
+  double alpha[kSlqMaxSteps * 64];        // a_j, j-major
+  double beta[(kSlqMaxSteps + 1) * 64];   // b_j (j >= 1 couples j-1 and j)
+  double s_cur[64], s_prev[64], b_cur[64], amax[64], znorm2[64];
+  int kend[64];                           // diagonal entries kept per probe
+};
+hipError_t launch_slq_spmm(hipStream_t s, const CsrMat& m, const double* w, double* u,
+                           const double* sdev, const CsrStepPlan& plan, void* hub_part,
+                           double* part);
+hipError_t launch_slq_update(hipStream_t s, double* U, const double* W1, const double* W0,
+                             const SlqState* st, int j, int64_t d, const CsrStepPlan& plan,
+                             double* part);
+hipError_t launch_slq_init(hipStream_t s, const double* z2, int k, SlqState* st);
+hipError_t launch_slq_alpha(hipStream_t s, const double* dots, int j, SlqState* st);
+hipError_t launch_slq_beta(hipStream_t s, const double* dots, int j, int k, SlqState* st);
+hipError_t launch_slq_quadrature(hipStream_t s, const SlqState* st, int kmax, int kind,
+                                 double power, double log_scale, int active, double* scratch,
+                                 double* out);
+hipError_t launch_slq_combine(hipStream_t s, const double* mu, int64_t ldmu, const double* c,
+                              int n, int64_t m0, int64_t m1, const double* qslq,
+                              double log_scale, mlct_result* out);
 
 // ---- integer triangle moments (k_tri.hip) ----------------------------------
 hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,

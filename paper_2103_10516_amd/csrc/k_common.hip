@@ -9,17 +9,6 @@ namespace mlct {
 
 namespace {
 
-__device__ double eval_f(int kind, double power, double t) {
-  switch (kind) {
-    case MLCT_LOG: return log(t);
-    case MLCT_SQRT: return sqrt(t);
-    case MLCT_EXP: return exp(t);
-    case MLCT_CUBE: return t * t * t;
-    case MLCT_INV: return 1.0 / t;
-    default: return pow(t, power);
-  }
-}
-
 // Coefficients of the degree-n interpolant at x_k = cos(k pi / n)
 // (Section 2.2): c_j = (2/n) sum''_k f~(x_k) cos(pi (j k mod 2n) / n), with
 // the end terms of the sum and c_0, c_n halved.  For exp the factor

@@ -180,6 +180,24 @@ struct StoreEpi {
   __device__ __forceinline__ void finish(int64_t i, T acc, T, T) { out[i * 64 + lane_id()] = acc; }
 };
 
+// SpMM of a Lanczos step (FP64, lane = probe): u = s (A w_j) stored, with
+// s = 1 / |w_j| per probe, and partials of (s w_j) . u (the Jacobi diagonal).
+struct SlqEpi {
+  using Part = double;
+  static constexpr bool kOwn = true;
+  static constexpr bool kParts = true;
+  double* out;
+  double s;
+  double a1 = 0.0, a2 = 0.0;
+  __device__ SlqEpi(double* o, const double* sdev) : out(o), s(sdev[lane_id()]) {}
+  __device__ __forceinline__ double prev(int64_t) const { return 0.0; }
+  __device__ __forceinline__ void finish(int64_t i, double acc, double xi, double) {
+    const double u = s * acc;
+    out[i * 64 + lane_id()] = u;
+    a1 += (s * xi) * u;
+  }
+};
+
 // One gathered entry into a row sum: weight w (ignored for patterns) times x,
 // or nothing when on is false.
 template <typename T, bool PATTERN>
@@ -489,6 +507,18 @@ __global__ __launch_bounds__(kThreads) void gram_pass2_kernel(
                                                     blockIdx.x);
 }
 
+template <bool PATTERN, int MAXNZ, bool HUBS>
+__global__ __launch_bounds__(kThreads) void slq_spmm_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const float* __restrict__ val, int64_t d, int64_t nnz, const double* __restrict__ w,
+    double* __restrict__ u, const double* __restrict__ sdev, HubView hub, int rows_per_group,
+    int ngroups, double* __restrict__ part) {
+  SlqEpi epi(u, sdev);
+  csr_step_wg<double, PATTERN, MAXNZ, false, HUBS, false>(rowptr, col, val, d, d, nnz, w, nullptr,
+                                                          epi, hub, rows_per_group, ngroups, part,
+                                                          blockIdx.x);
+}
+
 // Integer pass of triangle counting over a pattern CSR: vin = z (PASS 1,
 // y = A z written to vout) or y (PASS 2).
 template <int PASS, int MAXNZ, bool OFF32, bool HUBS>
@@ -785,6 +815,30 @@ hipError_t launch_tri_step(hipStream_t s, const CsrMat& m, int pass, const CsrSt
                  : launch_tri_pass<1, false>(s, m, plan, vin, vout, hub, part);
   return off32 ? launch_tri_pass<2, true>(s, m, plan, vin, nullptr, hub, part)
                : launch_tri_pass<2, false>(s, m, plan, vin, nullptr, hub, part);
+}
+
+hipError_t launch_slq_spmm(hipStream_t s, const CsrMat& m, const double* w, double* u,
+                           const double* sdev, const CsrStepPlan& plan, void* hub_part,
+                           double* part) {
+  const bool pat = m.val == nullptr;
+  if (m.hub_n > 0) {
+    const hipError_t e = pat ? launch_hubs<double, true>(s, m, w, m.ncols, hub_part)
+                             : launch_hubs<double, false>(s, m, w, m.ncols, hub_part);
+    if (e != hipSuccess) return e;
+  }
+  const HubView hub = hub_view(m, hub_part);
+  const dim3 grid(plan.ngroups), block(kThreads);
+#define MLCT_SLQ(P, H)                                                                          \
+  slq_spmm_kernel<P, 8, H><<<grid, block, 0, s>>>(m.rowptr, m.col, m.val, m.nrows, m.nnz, w, u, \
+                                                 sdev, hub, plan.rows_per_group, plan.ngroups,  \
+                                                 part)
+  if (pat) {
+    if (m.hub_n > 0) MLCT_SLQ(true, true); else MLCT_SLQ(true, false);
+  } else {
+    if (m.hub_n > 0) MLCT_SLQ(false, true); else MLCT_SLQ(false, false);
+  }
+#undef MLCT_SLQ
+  return hipGetLastError();
 }
 
 hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,

@@ -580,3 +580,35 @@ def mlct_op_gram_csr(ctx: Context, rowptr, col, val, cols: int, lam: float = 0.0
     _check(ctx, h.mlct_op_gram_csr(ctx.handle, rows, cols, nnz, _ptr(rowptr), _ptr(col),
                                    _ptr(val), lam, C.byref(hd)))
     return Op(ctx, hd, (rowptr, col, val), cols)
+
+
+# ---- stochastic Lanczos quadrature ------------------------------------------------
+def mlct_slq_quadforms(ctx: Context, op: Op, kind: int, k: int, probes: mlct_probes,
+                       power: float = 1.0) -> np.ndarray:
+    h = lib()
+    h.mlct_slq_quadforms.argtypes = [C.c_void_p, C.c_void_p, mlct_func, C.c_int32,
+                                     C.POINTER(mlct_probes), C.c_void_p]
+    h.mlct_slq_quadforms.restype = C.c_int
+    q = np.empty(probes.m, dtype=np.float64)
+    _check(ctx, h.mlct_slq_quadforms(ctx.handle, op.handle, mlct_func(kind, power), k,
+                                     C.byref(probes), q.ctypes.data))
+    return q
+
+
+def mlct_estimate_slq(ctx: Context, op: Op, kind: int, a: float, b: float, cheb_degree: int,
+                      m0: int, k: int, m1: int, seed: int, prec: int = MLCT_FP64,
+                      mode: int = MLCT_DOUBLING, power: float = 1.0) -> dict:
+    h = lib()
+    h.mlct_estimate_slq.argtypes = [C.c_void_p, C.c_void_p, mlct_func, C.c_double, C.c_double,
+                                    C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_uint64,
+                                    C.c_int32, C.c_int32, C.POINTER(mlct_result)]
+    h.mlct_estimate_slq.restype = C.c_int
+    r = mlct_result()
+    _check(ctx, h.mlct_estimate_slq(ctx.handle, op.handle, mlct_func(kind, power), a, b,
+                                    cheb_degree, m0, k, m1, seed & ((1 << 64) - 1), prec, mode,
+                                    C.byref(r)))
+    return {"estimate": r.estimate, "value": r.value, "log_scale": r.log_scale,
+            "est_var": r.est_var, "level_mean": np.array(r.level_mean[:2]),
+            "level_var": np.array(r.level_var[:2]), "matvecs": r.matvecs,
+            "probe_degrees": r.probe_degrees, "interval": (r.interval_a, r.interval_b),
+            "flags": r.flags}
