@@ -374,10 +374,11 @@ mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t pre
 /* Many estimates in shared launches: every (item, level, block of 64
  * probes) of all items advances one recurrence step per launch, so the
  * number of launches is the largest step count, not the sum over items.
- * Items must use CSR operators (valued or pattern, any sizes); precision
- * MLCT_FP32; mode MLCT_DIRECT or MLCT_DOUBLING (optionally with
- * MLCT_LEVEL_INTERP).  Each item's result equals what mlct_estimate returns
- * for it.  outs: host, nitems results.  Fails with MLCT_ESPECTRUM if any item's
+ * Items must use square CSR operators (valued or pattern, any sizes; not
+ * sparse Gram operators); precision MLCT_FP32; mode MLCT_DIRECT or
+ * MLCT_DOUBLING (optionally with MLCT_LEVEL_INTERP and / or MLCT_EXACT_LOW).
+ * Each item's result equals what mlct_estimate returns for it, bit for bit
+ * (rows longer than 256 entries are summed in the same 256-entry chunks).  outs: host, nitems results.  Fails with MLCT_ESPECTRUM if any item's
  * moments leave [-|z|^2, |z|^2] (that item's result is still written). */
 typedef struct {
   const mlct_op* op;

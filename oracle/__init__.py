@@ -26,6 +26,8 @@ Everything is NumPy/SciPy in float64, written from the paper's equations:
 * ``lanczos``    Lanczos spectral interval (needed for the affine map of
                  Section 2.2; the paper gives no procedure).
 * ``mlp``        the learned control-variate level (a project addition).
+* ``slq``        stochastic Lanczos quadrature and the two-level Chebyshev +
+                 Lanczos-quadrature estimator.
 
 Parity pins: see ``tests/test_oracle_*.py``.  Functions without an
 independent pin say "parity unpinned" in their docstring.
