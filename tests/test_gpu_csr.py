@@ -52,9 +52,28 @@ def _oracle_mu(g, a, b, n, ids, seed, doubling=False):
     return fn(g.to_scipy(), Z, alpha, beta, n)
 
 
+def _lap1d(n: int, shift: float = 0.01) -> wl.CSR:
+    """Tridiagonal 1D Dirichlet Laplacian (at most 3 entries per row)."""
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j, w in ((i - 1, -1.0), (i, 2.0 + shift), (i + 1, -1.0)):
+            if 0 <= j < n:
+                rows.append(i)
+                cols.append(j)
+                vals.append(w)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, np.asarray(rows) + 1, 1)
+    return wl.CSR(n, np.cumsum(rowptr).astype(np.int32), np.asarray(cols, dtype=np.int32),
+                  np.asarray(vals, dtype=np.float32))
+
+
 CASES = [
-    # (name, graph builder, a, b)
+    # (name, graph builder, a, b); the row lengths pick the straight-line
+    # capacity: <= 4 (lap1d), <= 5 (lap2d), <= 8 (lap3d), longer rows
+    # (random, Chung-Lu) the generic loop, past 256 entries the hub chunks
+    ("lap1d_777", lambda: _lap1d(777), 0.01, 4.01),
     ("lap2d_45", lambda: wl.laplacian_2d(45), 0.01, 8.01),
+    ("lap3d_11", lambda: wl.laplacian_3d(11), 0.01, 12.01),
     ("random_ragged", lambda: wl.random_csr(301, 0.03, 4), -7.0, 7.0),
     ("chung_lu_pattern", lambda: wl.chung_lu(3000, seed=11), -60.0, 90.0),
     # hub rows (45 rows past 256 entries, the longest 3896): chunked reduction
