@@ -45,11 +45,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of a kernel ("csr_step", "csr_fused2") measured by
-    rocprofv3 PMC runs (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel
-    calibration), if still current."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+def stored_traffic(workload: str):
+    """HBM bytes per launch measured by rocprofv3 PMC runs (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy-kernel calibration), if still current."""
+    path = os.path.join(ROOT, "profiles", f"csr_step_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -360,28 +359,16 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     mlct.mlct_timing(ctx, False)
-    n1, ms1 = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_CSR_STEP)
-    n2, ms2 = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_CSR_FUSED)
+    launches, kms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_CSR_STEP)
     print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
 
     pd = res["probe_degrees"] * args.steps
     mv = res["matvecs"] * args.steps
     width = 64
-    # algorithmic bytes: the matrix once, V_k read once, V_{k-1} read, V_{k+1}
-    # written (single step); a two-step launch reads V_{k-1}, V_k and writes
-    # V_{k+1}, V_{k+2} once each and takes the matrix once
-    mat = 8 * g.nnz + 4 * (g.d + 1)
-    step_bytes = mat + 12 * g.d * width
-    fused_bytes = mat + 16 * g.d * width
-    if ms2 > ms1:  # the dominant kernel
-        kname, tag, launches, kms, bytes_launch = (
-            "csr_fused2_kernel<valued,symmetric,5>", "csr_fused2", n2, ms2, fused_bytes)
-    else:
-        kname, tag, launches, kms, bytes_launch = (
-            "csr_step_kernel<float,valued,...>", "csr_step", n1, ms1, step_bytes)
+    bytes_launch = 8 * g.nnz + 4 * (g.d + 1) + 12 * g.d * width
     avg_s = kms / 1e3 / max(launches, 1)
     achieved = bytes_launch / avg_s / 1e9
-    traffic = stored_traffic(tag, w["name"])
+    traffic = stored_traffic(w["name"])
     out = {
         "metric": "probe*degree matvecs/s",
         "value": pd / dt,
@@ -401,16 +388,9 @@ def main():
         "estimate_last_step": res["estimate"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": kname,
+                     "traffic": traffic, "kernel": "csr_step_kernel<float,valued,...>",
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "avg_launch_ms": avg_s * 1e3, "launches": launches,
-                     "single_steps": {"launches": n1, "avg_launch_ms": ms1 / max(n1, 1),
-                                      "algorithmic_bytes_per_launch": step_bytes},
-                     "two_step_launches": {"launches": n2, "avg_launch_ms": ms2 / max(n2, 1),
-                                           "algorithmic_bytes_per_launch": fused_bytes,
-                                           "single_step_bytes_equivalent_gbs":
-                                               (2 * step_bytes / (ms2 / n2 / 1e3) / 1e9
-                                                if n2 else None)}},
+                     "avg_launch_ms": avg_s * 1e3, "launches": launches},
     }
     op.close()
     ctx.close()

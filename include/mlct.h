@@ -174,7 +174,6 @@ typedef enum {
   MLCT_KERNEL_TRI_STEP = 2,   /* one integer triangle-moment SpMM          */
   MLCT_KERNEL_GRAM = 3,       /* Gram matrix formation                     */
   MLCT_KERNEL_BATCH_STEP = 4, /* one batched recurrence step (all blocks)  */
-  MLCT_KERNEL_CSR_FUSED = 5,  /* two recurrence steps over a banded CSR operator */
   MLCT_NUM_KERNEL_IDS = 8
 } mlct_kernel_id;
 mlct_status mlct_timing(mlct_ctx* ctx, int32_t enable);
@@ -222,21 +221,6 @@ mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t 
 mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t rows, int64_t cols, const void* X_dev,
                          int64_t ldx, int32_t dtype, int32_t prec, mlct_op** out);
 mlct_status mlct_op_destroy(mlct_op* op);
-/* Recurrence steps per kernel launch for a CSR operator (the three-term
- * recurrence of Section 2.2 applied to a probe block), 1 or 2 (default 1).
- * With 2, FP32 blocks of at least three steps take two steps per launch when
- * the operator qualifies: every row at most 8 entries, bandwidth
- * max |i - j| at most 31 tiles of 512 rows and at most an eighth of the rows
- * one XCD handles, no row longer than the hub threshold.  Row i of V_{k+2}
- * needs V_{k+1} only within the bandwidth, so one launch reads V_{k-1} and
- * V_k once and V_{k+1} from the caches (16 d B instead of 24 d B bytes of
- * vectors per two steps).  The moments are bitwise those of single steps
- * over the same 512-row tiles.  A two-step launch that reports an error (a
- * wait that timed out, an XCD left unserved) makes the block run again one
- * step per launch, and the operator stays at one step from then on; calling
- * this function again with 2 re-enables it.  Errors: EINVAL (op NULL or
- * not a CSR operator, steps not 1 or 2). */
-mlct_status mlct_op_set_steps_per_launch(mlct_op* op, int32_t steps);
 /* Copy the d x d matrix of a dense or Gram operator to the host as float64,
  * row-major (out_host: d*d doubles).  EINVAL for CSR operators. */
 mlct_status mlct_op_read_dense(mlct_ctx* ctx, const mlct_op* op, double* out_host);

@@ -234,116 +234,13 @@ mlct_status check_probes(mlct_ctx* ctx, const mlct_op* op, const mlct_probes* pr
 }
 
 // ---- one probe block through the recurrence ------------------------------
-// The XCDs this context's workgroups run on (once per context).
-mlct_status probe_xcc(mlct_ctx* ctx) {
-  if (ctx->xcc_mask >= 0) return MLCT_OK;
-  int cus = 0;
-  HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-  void* m;
-  CHECK(ws_get(ctx, WS_MISC, 64, &m));
-  HIPCHK(ctx, hipMemsetAsync(m, 0, sizeof(int32_t), ctx->stream));
-  HIPCHK(ctx, launch_xcc_probe(ctx->stream, static_cast<int*>(m), 8 * std::max(cus, 8)));
-  int32_t mask = 0;
-  HIPCHK(ctx, hipMemcpyAsync(&mask, m, sizeof mask, hipMemcpyDeviceToHost, ctx->stream));
-  CHECK(sync_stream(ctx));
-  ctx->xcc_mask = mask;
-  ctx->cu_count = cus;
-  return MLCT_OK;
-}
-
-constexpr int kFusedTileRows = 512;
-
-// One probe block with two recurrence steps per launch (plan_fused): V_1 as
-// a single step, then pairs of steps, and a last single step when the
-// number of steps is even.  Four vector blocks rotate (the pair reads two
-// and writes the other two).  *failed is set when a fused launch reported
-// an error; the block's moments are then not valid.
-mlct_status run_block_csr_fused(mlct_ctx* ctx, const mlct_op* op, const FusedPlan& fp,
-                                double alpha, double beta, int degree, int mode, ProbeSrc src,
-                                double* mu_rows, int64_t ldmu, bool* failed) {
-  const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
-  const CsrStepPlan plan{fp.ntiles, fp.rows_per_tile};
-  const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(float);
-  const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;
-  const size_t nflags = (size_t)fp.nbands * fp.fstride;
-  void *b0, *b1, *b2, *b3, *part, *dots, *fmem;
-  CHECK(ws_get(ctx, WS_V0, vbytes, &b0));
-  CHECK(ws_get(ctx, WS_V1, vbytes, &b1));
-  CHECK(ws_get(ctx, WS_V2, vbytes, &b2));
-  CHECK(ws_get(ctx, WS_V3, vbytes, &b3));
-  CHECK(ws_get(ctx, WS_PART, pstep * (S + 1) * sizeof(double), &part));
-  CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &dots));
-  CHECK(ws_get(ctx, WS_FUSE, (kMaxBands + 64 + nflags) * sizeof(int), &fmem));
-  int* tickets = static_cast<int*>(fmem);
-  int* err = tickets + kMaxBands;   // own 256-byte line
-  int* flags = tickets + kMaxBands + 64;
-  float* prev = static_cast<float*>(b0);
-  float* cur = static_cast<float*>(b1);
-  float* f0 = static_cast<float*>(b2);
-  float* f1 = static_cast<float*>(b3);
-  double* P = static_cast<double*>(part);
-  hipStream_t s = ctx->stream;
-  HIPCHK(ctx, launch_probe_init<float>(s, prev, op->d, src, plan, P));
-  {
-    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
-    HIPCHK(ctx, launch_csr_step<float>(s, op->csr, prev, cur, (float)alpha, (float)beta, false,
-                                       0, src, plan, nullptr, P + pstep));
-    tm.done();
-  }
-  const int zmode = mode == MLCT_DOUBLING ? 0 : (src.entries ? 2 : 1);
-  const float ca = (float)(2.0 * alpha), cb = (float)(2.0 * beta);
-  int k = 2, epoch = 0;
-  for (; k + 1 <= S; k += 2) {
-    // v_k, v_{k+1} from v_{k-2} (prev), v_{k-1} (cur)
-    HIPCHK(ctx, launch_fused_ctl(s, fp, epoch > 0, epoch == 0, tickets, flags, err));
-    ++epoch;
-    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_FUSED);
-    HIPCHK(ctx, launch_csr_fused2(s, op->csr, prev, cur, f0, f1, ca, cb, zmode, src, fp, epoch,
-                                  tickets, flags, err, P + pstep * k, P + pstep * (k + 1)));
-    tm.done();
-    std::swap(prev, f0);
-    std::swap(cur, f1);
-  }
-  HIPCHK(ctx, launch_fused_ctl(s, fp, epoch > 0, 0, tickets, flags, err));
-  if (k == S) {  // v_S over v_{S-2}
-    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
-    HIPCHK(ctx, launch_csr_step<float>(s, op->csr, cur, prev, ca, cb, true, zmode, src, plan,
-                                       nullptr, P + pstep * k));
-    tm.done();
-  }
-  HIPCHK(ctx, launch_reduce_partials(s, P, S + 1, 2, plan.ngroups, kBlockProbes,
-                                     static_cast<double*>(dots)));
-  HIPCHK(ctx, launch_assemble_moments(s, static_cast<double*>(dots), S + 1, kBlockProbes,
-                                      src.active, mode, degree, mu_rows, ldmu));
-  int32_t herr = 0;
-  HIPCHK(ctx, hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, s));
-  CHECK(sync_stream(ctx));
-  *failed = herr != 0;
-  return MLCT_OK;
-}
-
 // Runs ``degree`` (direct) or ceil(degree/2) (symmetric form) steps on the
 // ``src.active`` probes of one block and writes their moments mu_0..mu_n
-// (n = degree) into mu_rows (device, row stride ldmu).  FP32 blocks of a
-// banded operator take two steps per launch (run_block_csr_fused) unless
-// that is switched off or has failed on this operator.
+// (n = degree) into mu_rows (device, row stride ldmu).
 template <typename T>
 mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                           int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
-  if constexpr (std::is_same<T, float>::value) {
-    if (S >= 3 && op->kind == OP_CSR && op->steps_per_launch >= 2 && !op->fuse_failed) {
-      CHECK(probe_xcc(ctx));
-      FusedPlan fp;
-      if (plan_fused(op->csr, ctx->xcc_mask, ctx->cu_count, kFusedTileRows, &fp)) {
-        bool failed = false;
-        CHECK(run_block_csr_fused(ctx, op, fp, alpha, beta, degree, mode, src, mu_rows, ldmu,
-                                  &failed));
-        if (!failed) return MLCT_OK;
-        op->fuse_failed = true;  // this block again, one step per launch
-      }
-    }
-  }
   const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
   const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(T);
   const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;  // doubles per step
@@ -782,10 +679,10 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   CHECK(set_device(ctx));
   void* flags;
   CHECK(ws_get(ctx, WS_MISC, 64, &flags));
-  HIPCHK(ctx, hipMemsetAsync(flags, 0, 3 * sizeof(int32_t), ctx->stream));
+  HIPCHK(ctx, hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), ctx->stream));
   HIPCHK(ctx, launch_csr_validate(ctx->stream, rowptr_dev, col_dev, d, d, nnz,
                                   static_cast<int32_t*>(flags)));
-  int32_t hf[3] = {0, 0, 0};
+  int32_t hf[2] = {0, 0};
   HIPCHK(ctx, hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   if (hf[0])
@@ -803,7 +700,6 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   op->csr.val = dtype == MLCT_DT_F32 ? static_cast<const float*>(val_dev) : nullptr;
   op->dtype = dtype;
   op->csr.max_row_nnz = hf[1];
-  op->csr.bandwidth = hf[2];
   op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
   if (op->csr.max_row_nnz > kHubLen) {
     const mlct_status st = build_hubs(ctx, op->csr, &op->hub_mem);
@@ -832,10 +728,10 @@ mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t 
   hipStream_t s = ctx->stream;
   void* flags;
   CHECK(ws_get(ctx, WS_MISC, 64, &flags));
-  HIPCHK(ctx, hipMemsetAsync(flags, 0, 3 * sizeof(int32_t), s));
+  HIPCHK(ctx, hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), s));
   HIPCHK(ctx, launch_csr_validate(s, rowptr_dev, col_dev, rows, cols, nnz,
                                   static_cast<int32_t*>(flags)));
-  int32_t hf[3] = {0, 0, 0};
+  int32_t hf[2] = {0, 0};
   HIPCHK(ctx, hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
   CHECK(sync_stream(ctx));
   if (hf[0])
@@ -915,13 +811,6 @@ mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t 
     return st;
   }
   *out = op;
-  return MLCT_OK;
-}
-
-mlct_status mlct_op_set_steps_per_launch(mlct_op* op, int32_t steps) {
-  if (!op || op->kind != OP_CSR || (steps != 1 && steps != 2)) return MLCT_EINVAL;
-  op->steps_per_launch = steps;
-  op->fuse_failed = false;
   return MLCT_OK;
 }
 

@@ -36,12 +36,6 @@ __device__ __forceinline__ int xcd_band(int b, int ngroups) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Index of the accelerator complex die (XCD) the wave runs on, bits [3:0]
-// of the XCC_ID hardware register.  The CUs of one XCD share one L2.
-__device__ __forceinline__ int xcc_id() {
-  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;
-}
-
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }

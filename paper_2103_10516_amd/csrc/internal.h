@@ -31,7 +31,6 @@ struct CsrMat {
   const float* val = nullptr;  // nullptr = 0/1 pattern
   int64_t nrows = 0, ncols = 0, nnz = 0;
   int max_row_nnz = 0;
-  int bandwidth = 0;            // max |i - j| over the entries
   int32_t* hub_rows = nullptr;  // [hub_n] sorted
   int32_t* hub_c0 = nullptr;    // [hub_n + 1]
   int32_t* hub_cs = nullptr;    // [hub_chunks] first entry of each chunk
@@ -66,8 +65,6 @@ struct mlct_ctx {
   std::vector<mlct::DevBuf> slots;  // grow-only named workspace slots
   void* host_pinned = nullptr;      // staging for small D2H results
   size_t host_pinned_bytes = 0;
-  int xcc_mask = -1;                // XCDs that run this context's workgroups (-1 = not probed)
-  int cu_count = 0;
   std::string tune_path;            // autotune cache file ("" = none)
   std::vector<std::string> tune_lines;  // cached decisions, one per operator shape
 };
@@ -89,8 +86,6 @@ struct mlct_op {
   bool stats_ready = false;
   double tr_a = 0.0, fro2 = 0.0;
   int tuned_groups = 0;      // CSR: workgroup cap chosen by mlct_autotune (0 = default)
-  int steps_per_launch = 1;  // CSR: 2 = two-step launches where the operator qualifies
-  mutable bool fuse_failed = false;  // a two-step launch reported an error: single steps from now on
   int tuned_dense = -1;      // dense: 1 = 128x128, 2 = 64x64, 0 = 32x32 tiles, 3 = skinny, -1 = default rule
   // dense / Gram (row-major d x d)
   const void* A = nullptr;
@@ -128,8 +123,7 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ,
-  WS_V2, WS_V3, WS_FUSE, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -181,29 +175,6 @@ struct CsrStepPlan {
   int ngroups;        // workgroups per step (= partial-sum slots)
   int rows_per_group; // contiguous rows per workgroup
 };
-
-// Two recurrence steps per launch over a banded CSR operator (every row at
-// most 8 entries, |i - j| <= bandwidth, no hub rows, FP32).  Tiles of
-// rows_per_tile rows are the partial-sum groups (ngroups = ntiles, so the
-// single steps of the same block share the layout).  Band b (one per XCD in
-// use; band_of maps an XCC id to its band or -1) owns tiles [own0, own1) and
-// computes the first step on [h0, h1), its own tiles and hb halo tiles.
-constexpr int kMaxBands = 16;
-constexpr int kFusedMaxHalo = 31;  // 2 hb + 1 flags checked by one wave
-struct FusedPlan {
-  int ntiles, rows_per_tile, hb, lag, nbands, fstride, grid;
-  int band_of[kMaxBands];
-  int own0[kMaxBands], own1[kMaxBands], h0[kMaxBands], h1[kMaxBands];
-};
-// False when the operator does not qualify (the caller runs single steps).
-bool plan_fused(const CsrMat& m, int xcc_mask, int cus, int rows_per_tile, FusedPlan* out);
-hipError_t launch_xcc_probe(hipStream_t s, int* mask, int blocks);
-hipError_t launch_fused_ctl(hipStream_t s, const FusedPlan& fp, int check, int reset,
-                            int* tickets, int* flags, int* err);
-hipError_t launch_csr_fused2(hipStream_t s, const CsrMat& m, const float* v0, const float* v1,
-                             float* w1, float* w2, float ca, float cb, int zmode, ProbeSrc src,
-                             const FusedPlan& fp, int epoch, int* tickets, int* flags, int* err,
-                             double* part1, double* part2);
 // Workgroups per step: one per 256 rows, a multiple of 8 (one band per XCD),
 // at most max_groups (0 = the default cap of 2048; the autotuner's choice
 // otherwise).

@@ -39,27 +39,17 @@ __global__ __launch_bounds__(256) void cheb_dct_kernel(int kind, double power, d
 }
 
 // flags[0]: bit0 rowptr[0] != 0, bit1 decreasing rowptr, bit2 rowptr[d] != nnz,
-// bit3 column out of range.  flags[1]: longest row.  flags[2]: bandwidth
-// max |i - j| (rows whose extent lies inside [0, nnz)).
+// bit3 column out of range.  flags[1]: longest row.
 __global__ void csr_validate_kernel(const int32_t* __restrict__ rowptr,
                                     const int32_t* __restrict__ col, int64_t d, int64_t ncols,
                                     int64_t nnz, int32_t* __restrict__ flags) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int bad = 0, longest = 0;
-  int64_t bw = 0;
   for (int64_t i = tid; i < d; i += stride) {
     const int32_t s = rowptr[i], e = rowptr[i + 1];
-    if (e < s) {
-      bad |= 2;
-    } else {
-      longest = max(longest, e - s);
-      if (s >= 0 && (int64_t)e <= nnz)
-        for (int32_t t = s; t < e; ++t) {
-          const int64_t j = col[t];
-          bw = max(bw, j > i ? j - i : i - j);
-        }
-    }
+    if (e < s) bad |= 2;
+    else longest = max(longest, e - s);
   }
   if (tid == 0) {
     if (rowptr[0] != 0) bad |= 1;
@@ -71,7 +61,6 @@ __global__ void csr_validate_kernel(const int32_t* __restrict__ rowptr,
   }
   if (bad) atomicOr(&flags[0], bad);
   if (longest) atomicMax(&flags[1], longest);
-  if (bw) atomicMax(&flags[2], (int32_t)min<int64_t>(bw, INT32_MAX));
 }
 
 // dots[s][slot][p] = sum_{g = 0..ngroups-1} part[s][slot][g][p].  One

@@ -48,7 +48,7 @@ __device__ __forceinline__ void store_partials(P a1, P a2, int g, int ngroups,
   sh[0][wave][lane] = a1;
   sh[1][wave][lane] = a2;
   __syncthreads();
-  if (wave == 0 && part) {
+  if (wave == 0) {
     P s1 = sh[0][0][lane], s2 = sh[1][0][lane];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) {
@@ -102,8 +102,8 @@ __global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0
 }
 
 // Per-row epilogue of the recurrence: V_new = ca*acc + cb*V_k[i] (- V_prev[i]),
-// written over V_prev (or to a separate block vm when V_prev is read from
-// vp) with a non-temporal store, and the lane's moment partials (FP64).
+// written over V_prev with a non-temporal store, and the lane's moment
+// partials (FP64).
 template <typename T, int ZMODE, bool HAS_PREV>
 struct RecEpi {
   using Part = double;
@@ -111,21 +111,19 @@ struct RecEpi {
   static constexpr bool kParts = true;  // writes moment partials
   T ca, cb;
   T* vm;
-  const T* vp;
   ProbeSrc src;
   bool act;
   uint64_t key = 0;
   int64_t cached = -1;
   uint64_t word = 0;
   double a1 = 0.0, a2 = 0.0;
-  __device__ RecEpi(T ca_, T cb_, T* vm_, const ProbeSrc& s, const T* vp_ = nullptr)
-      : ca(ca_), cb(cb_), vm(vm_), vp(vp_ ? vp_ : vm_), src(s) {
+  __device__ RecEpi(T ca_, T cb_, T* vm_, const ProbeSrc& s) : ca(ca_), cb(cb_), vm(vm_), src(s) {
     const int lane = lane_id();
     act = lane < src.active;
     if (ZMODE == 1) key = sm_output(src.seed, (uint64_t)(src.first_id + lane));
   }
   __device__ __forceinline__ T prev(int64_t i) const {
-    return HAS_PREV ? __builtin_nontemporal_load(vp + i * 64 + lane_id()) : T(0);
+    return HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane_id()) : T(0);
   }
   __device__ __forceinline__ void finish(int64_t i, T acc, T xi, T xp) {
     const int lane = lane_id();
@@ -362,11 +360,12 @@ __device__ __forceinline__ void csr_step_wg(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ vk,
     const T* __restrict__ vown, Epi& epi, const HubView& hub, int rows_per_group, int ngroups,
-    typename Epi::Part* __restrict__ part, int g) {
+    typename Epi::Part* __restrict__ part, int bid) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
   constexpr int GPB = 64 / ROWS;  // groups per batch
   constexpr bool HUBS = TAIL == kTailHubs;
   const int lane = lane_id(), wave = wave_id();
+  const int g = xcd_band(bid, ngroups);
   const int64_t r0 = (int64_t)g * rows_per_group;
   const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
 
@@ -487,7 +486,7 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
   RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
   csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, d, nnz, vk, nullptr,
                                                      epi, hub, rows_per_group, ngroups, part,
-                                                     xcd_band(blockIdx.x, ngroups));
+                                                     blockIdx.x);
 }
 
 // Gram step, first product: W = X V_k over X's rows (V_k has dv = X's
@@ -500,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void gram_pass1_kernel(
   StoreEpi<T> epi(W);
   csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, dv, nnz, vk, nullptr,
                                                      epi, hub, rows_per_group, ngroups, nullptr,
-                                                     xcd_band(blockIdx.x, ngroups));
+                                                     blockIdx.x);
 }
 
 // Gram step, second product with the recurrence: V_new = ca X^T W + cb V_k
@@ -514,7 +513,7 @@ __global__ __launch_bounds__(kThreads) void gram_pass2_kernel(
   RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
   csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, true>(rowptr, col, val, d, dv, nnz, W, vk, epi,
                                                     hub, rows_per_group, ngroups, part,
-                                                    xcd_band(blockIdx.x, ngroups));
+                                                    blockIdx.x);
 }
 
 template <bool PATTERN, int MAXNZ, int TAIL>
@@ -526,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void slq_spmm_kernel(
   SlqEpi epi(u, sdev);
   csr_step_wg<double, PATTERN, MAXNZ, false, TAIL, false>(rowptr, col, val, d, d, nnz, w, nullptr,
                                                           epi, hub, rows_per_group, ngroups, part,
-                                                          xcd_band(blockIdx.x, ngroups));
+                                                          blockIdx.x);
 }
 
 // Integer pass of triangle counting over a pattern CSR: vin = z (PASS 1,
@@ -539,8 +538,7 @@ __global__ __launch_bounds__(kThreads) void tri_step_kernel(
   TriEpi<PASS> epi(vout);
   csr_step_wg<int32_t, true, MAXNZ, OFF32, TAIL, false>(rowptr, col, nullptr, d, d, nnz, vin,
                                                         nullptr, epi, hub, rows_per_group,
-                                                        ngroups, part,
-                                                        xcd_band(blockIdx.x, ngroups));
+                                                        ngroups, part, blockIdx.x);
 }
 
 // Chunk partials of the hub rows: one wave per chunk of at most kHubChunk
@@ -578,135 +576,6 @@ __global__ __launch_bounds__(256) void hub_find_kernel(const int32_t* __restrict
   }
 }
 
-// ---- two recurrence steps per launch (banded operators) ---------------------
-// For a matrix whose entries satisfy |i - j| <= bw, row i of V_{k+2} needs
-// V_{k+1} only on rows i - bw .. i + bw.  One launch therefore computes
-//     V_{k+1} = ca A V_k + cb V_k - V_{k-1}   (into w1)
-//     V_{k+2} = ca A V_{k+1} + cb V_{k+1} - V_k   (into w2)
-// reading V_{k-1} and V_k once from HBM and V_{k+1} back while it is still
-// in the caches: 16 d B bytes of vectors per two steps instead of 24 d B.
-//
-// Rows are cut into tiles (the partial-sum groups of the plan).  Each XCD in
-// use is a band that owns a contiguous range of tiles and works through a
-// queue of items: first-step tiles (its own and hb halo tiles on each side,
-// recomputed rather than taken from the neighbouring XCD) and second-step
-// tiles of its own range, issued `lag` first-step tiles behind.  Workgroups
-// take items in queue order from a per-band ticket counter, so an item only
-// ever waits for items with smaller tickets, which are already held by
-// running workgroups: the queue cannot deadlock.  A second-step tile waits
-// until the first-step tiles within hb tiles of it have been published.
-//
-// Publication stays inside one XCD, whose CUs share an L2: the producer
-// waits until its stores are complete (they have reached the L2), then sets
-// the tile's flag to the launch epoch with a device-scope atomic; the
-// consumer reads the flags with device-scope atomic loads.  The vector
-// caches (L1) cannot hold stale copies of V_{k+1}: a line of it is read in
-// this launch only after it was written.  Halo tiles are written by both
-// neighbouring bands with bitwise identical values (same tile, same code).
-//
-// Waits are bounded: after kFusedSpin polls the workgroup goes on, and sets
-// bit 1 of err; a band no workgroup served sets bit 0 (fused_ctl_kernel).
-// The host then discards the block and recomputes it one step per launch.
-constexpr int kFusedSpin = 1 << 15;  // about 50 ms of polling
-
-template <bool PATTERN, int ZMODE, int MAXNZ>
-__global__ __launch_bounds__(kThreads) void csr_fused2_kernel(
-    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const float* __restrict__ val, int64_t d, int64_t nnz, const float* __restrict__ v0,
-    const float* __restrict__ v1, float* __restrict__ w1, float* __restrict__ w2, float ca,
-    float cb, ProbeSrc src, FusedPlan fp, int epoch, int* __restrict__ tickets,
-    int* __restrict__ flags, int* __restrict__ err, double* __restrict__ part1,
-    double* __restrict__ part2) {
-  __shared__ int sh_t;
-  const int band = fp.band_of[xcc_id()];
-  if (band < 0) return;  // an XCD without a band in this plan
-  const int own0 = fp.own0[band], own1 = fp.own1[band];
-  const int h0 = fp.h0[band], n1 = fp.h1[band] - h0, n2 = own1 - own0;
-  const int lag = min(fp.lag, n1);
-  int* bflags = flags + (size_t)band * fp.fstride;
-  const HubView nohub{nullptr, nullptr, 0, nullptr};
-  const int lane = lane_id(), wave = wave_id();
-  for (;;) {
-    if (threadIdx.x == 0) sh_t = atomicAdd(&tickets[band], 1);
-    __syncthreads();
-    const int t = sh_t;
-    if (t >= n1 + n2) break;
-    // queue order: first-step items 0 .. lag-1, then pairs (first-step
-    // lag + j, second-step j), then the remaining second-step items
-    bool second;
-    int idx;
-    if (t < lag) {
-      second = false;
-      idx = t;
-    } else if (t < lag + 2 * (n1 - lag)) {
-      const int q = t - lag;
-      second = q & 1;
-      idx = second ? q >> 1 : lag + (q >> 1);
-    } else {
-      second = true;
-      idx = (n1 - lag) + (t - lag - 2 * (n1 - lag));
-    }
-    if (!second) {
-      const int g = h0 + idx;
-      RecEpi<float, ZMODE, true> epi(ca, cb, w1, src, v0);
-      csr_step_wg<float, PATTERN, MAXNZ, true, kTailNone, false>(
-          rowptr, col, val, d, d, nnz, v1, nullptr, epi, nohub, fp.rows_per_tile, fp.ntiles,
-          g >= own0 && g < own1 ? part1 : nullptr, g);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are in the L2
-      __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_store(&bflags[idx], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const int g = own0 + idx;
-      if (wave == 0) {
-        const int lo = max(g - fp.hb, 0), hi = min(g + fp.hb, fp.ntiles - 1);
-        bool ok = lane > hi - lo;
-        const int* f = bflags + (lo - h0) + (ok ? 0 : lane);
-        for (int it = 0;; ++it) {
-          if (!ok) ok = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-          if (__all(ok)) break;
-          if (it >= kFusedSpin) {
-            if (lane == 0) atomicOr(err, 2);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-        }
-      }
-      __syncthreads();
-      RecEpi<float, ZMODE, true> epi(ca, cb, w2, src, v1);
-      csr_step_wg<float, PATTERN, MAXNZ, true, kTailNone, false>(
-          rowptr, col, val, d, d, nnz, w1, nullptr, epi, nohub, fp.rows_per_tile, fp.ntiles,
-          part2, g);
-    }
-    __syncthreads();  // sh_t and the partial staging are reused
-  }
-}
-
-// Before a fused launch: with check, bit 0 of err if a band's queue of the
-// previous launch was not exhausted; the band tickets reset; with reset, err
-// and the publication flags cleared (the epochs restart at 1).
-__global__ __launch_bounds__(256) void fused_ctl_kernel(FusedPlan fp, int check, int reset,
-                                                        int* __restrict__ tickets,
-                                                        int* __restrict__ flags,
-                                                        int* __restrict__ err) {
-  const int tid = threadIdx.x;
-  if (tid < fp.nbands) {
-    const int total = fp.h1[tid] - fp.h0[tid] + fp.own1[tid] - fp.own0[tid];
-    if (check && tickets[tid] < total) atomicOr(err, 1);
-    tickets[tid] = 0;
-  }
-  if (reset) {
-    if (tid == 0) *err = 0;
-    const int n = fp.nbands * fp.fstride;
-    for (int i = tid; i < n; i += 256) flags[i] = 0;
-  }
-}
-
-// The XCDs that run workgroups of this process: bit x of mask for XCC id x.
-__global__ __launch_bounds__(64) void xcc_probe_kernel(int* __restrict__ mask) {
-  if (threadIdx.x == 0) atomicOr(mask, 1 << xcc_id());
-}
-
 // ---- batches of probe blocks over many operators -----------------------------
 // One launch covers step s of every block in a table (blocks sorted by their
 // number of steps, so the blocks still running at step s are a prefix).  Each
@@ -735,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   const HubView nohub{nullptr, nullptr, 0, nullptr};
   csr_step_wg<float, PATTERN, MAXNZ, true, kTailGen, false>(
       B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, B.rows_per_group,
-      B.ngroups, B.part + (size_t)s * 2 * B.ngroups * 64, xcd_band(bid, B.ngroups));
+      B.ngroups, B.part + (size_t)s * 2 * B.ngroups * 64, bid);
 }
 
 __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
@@ -795,10 +664,10 @@ hipError_t launch_hubs(hipStream_t s, const CsrMat& m, const T* v, int64_t dv, v
 // Row capacity of the straight-line path: the smallest of {4, 5, 8} that
 // holds the longest row.  When one does, every group takes the straight-line
 // path and the generic loop is not compiled in (kTailNone: it would hold
-// registers the straight-line path can use for occupancy); else MAXNZ = 8
-// and longer rows take the generic loop (kTailGen), and rows past kHubLen
-// the hub partials (kTailHubs).  FP32 blocks under 4 GiB use 32-bit gather
-// offsets; FP64 (a verification precision) uses one general instantiation.
+// registers the straight-line path can use); else MAXNZ = 8 and longer rows
+// take the generic loop (kTailGen), and rows past kHubLen the hub partials
+// (kTailHubs).  FP32 blocks under 4 GiB use 32-bit gather offsets; FP64 (a
+// verification precision) uses one general instantiation.
 // F(MAXNZ, OFF32, TAIL) launches one instantiation.
 template <typename T, class F>
 hipError_t dispatch_shape(const CsrMat& m, int64_t dv, F&& f) {
@@ -989,74 +858,6 @@ hipError_t launch_slq_spmm(hipStream_t s, const CsrMat& m, const double* w, doub
     if (m.hub_n > 0) MLCT_SLQ(false, kTailHubs); else MLCT_SLQ(false, kTailGen);
   }
 #undef MLCT_SLQ
-  return hipGetLastError();
-}
-
-bool plan_fused(const CsrMat& m, int xcc_mask, int cus, int rows_per_tile, FusedPlan* out) {
-  if (m.nnz <= 0 || m.max_row_nnz > 8 || m.hub_n > 0 || m.nrows != m.ncols) return false;
-  if (!block_off32<float>(m.nrows) || xcc_mask <= 0 || cus <= 0 || rows_per_tile < 64) return false;
-  FusedPlan fp{};
-  fp.rows_per_tile = rows_per_tile;
-  const int64_t tiles = (m.nrows + rows_per_tile - 1) / rows_per_tile;
-  fp.ntiles = (int)((tiles + 7) / 8 * 8);
-  fp.hb = (int)(((int64_t)m.bandwidth + rows_per_tile - 1) / rows_per_tile);
-  if (fp.hb > kFusedMaxHalo) return false;
-  int nb = 0;
-  for (int x = 0; x < kMaxBands; ++x) {
-    fp.band_of[x] = (xcc_mask >> x) & 1 ? nb++ : -1;
-  }
-  fp.nbands = nb;
-  // halo work at most a quarter of a band's own first-step work
-  const int per = fp.ntiles / nb;
-  if (per < 16 || 8 * fp.hb > per) return false;
-  fp.grid = 2 * cus;
-  fp.fstride = 0;
-  for (int b = 0; b < nb; ++b) {
-    fp.own0[b] = (int)((int64_t)fp.ntiles * b / nb);
-    fp.own1[b] = (int)((int64_t)fp.ntiles * (b + 1) / nb);
-    fp.h0[b] = std::max(fp.own0[b] - fp.hb, 0);
-    fp.h1[b] = std::min(fp.own1[b] + fp.hb, fp.ntiles);
-    fp.fstride = std::max(fp.fstride, fp.h1[b] - fp.h0[b]);
-  }
-  // second-step items trail by the dependency reach (2 hb) plus about half
-  // a band's workgroups in flight, so they rarely wait
-  fp.lag = 2 * fp.hb + std::max(4, fp.grid / nb / 2) + 2;
-  *out = fp;
-  return true;
-}
-
-hipError_t launch_xcc_probe(hipStream_t s, int* mask, int blocks) {
-  xcc_probe_kernel<<<blocks, 64, 0, s>>>(mask);
-  return hipGetLastError();
-}
-
-hipError_t launch_fused_ctl(hipStream_t s, const FusedPlan& fp, int check, int reset,
-                            int* tickets, int* flags, int* err) {
-  fused_ctl_kernel<<<1, 256, 0, s>>>(fp, check, reset, tickets, flags, err);
-  return hipGetLastError();
-}
-
-hipError_t launch_csr_fused2(hipStream_t s, const CsrMat& m, const float* v0, const float* v1,
-                             float* w1, float* w2, float ca, float cb, int zmode, ProbeSrc src,
-                             const FusedPlan& fp, int epoch, int* tickets, int* flags, int* err,
-                             double* part1, double* part2) {
-#define MLCT_F(P, Z, M)                                                                      \
-  csr_fused2_kernel<P, Z, M><<<fp.grid, kThreads, 0, s>>>(m.rowptr, m.col, m.val, m.nrows,   \
-                                                         m.nnz, v0, v1, w1, w2, ca, cb, src, \
-                                                         fp, epoch, tickets, flags, err,     \
-                                                         part1, part2)
-#define MLCT_FM(P, Z)                   \
-  if (m.max_row_nnz <= 4) MLCT_F(P, Z, 4); \
-  else if (m.max_row_nnz <= 5) MLCT_F(P, Z, 5); \
-  else MLCT_F(P, Z, 8)
-#define MLCT_FZ(P)                  \
-  if (zmode == 0) { MLCT_FM(P, 0); } \
-  else if (zmode == 1) { MLCT_FM(P, 1); } \
-  else { MLCT_FM(P, 2); }
-  if (m.val == nullptr) { MLCT_FZ(true); } else { MLCT_FZ(false); }
-#undef MLCT_FZ
-#undef MLCT_FM
-#undef MLCT_F
   return hipGetLastError();
 }
 

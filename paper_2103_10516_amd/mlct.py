@@ -32,7 +32,6 @@ MLCT_MAX_LEVELS = 32
 MLCT_EXACT_LOW = 0x20
 MLCT_FLAG_FEW_SAMPLES, MLCT_FLAG_OVERFLOW, MLCT_FLAG_BF16 = 0x1, 0x2, 0x4
 MLCT_KERNEL_CSR_STEP, MLCT_KERNEL_DENSE_STEP, MLCT_KERNEL_TRI_STEP, MLCT_KERNEL_GRAM = 0, 1, 2, 3
-MLCT_KERNEL_BATCH_STEP, MLCT_KERNEL_CSR_FUSED = 4, 5
 
 
 class mlct_func(C.Structure):
@@ -91,7 +90,6 @@ def lib() -> C.CDLL:
             "mlct_op_dense": [P, I64, P, I64, I32, C.POINTER(P)],
             "mlct_op_gram": [P, I64, I64, P, I64, I32, I32, C.POINTER(P)],
             "mlct_op_destroy": [P],
-            "mlct_op_set_steps_per_launch": [P, I32],
             "mlct_op_read_dense": [P, P, P],
             "mlct_cheb_coeffs": [P, mlct_func, D, D, I32, P, C.POINTER(D)],
             "mlct_moments": [P, P, D, D, I32, C.POINTER(mlct_probes), I32, I32, P],
@@ -207,13 +205,6 @@ def mlct_op_csr(ctx: Context, rowptr, col, val=None) -> Op:
     _check(ctx, lib().mlct_op_csr(ctx.handle, d, nnz, _ptr(rowptr), _ptr(col), _ptr(val), dt,
                                   C.byref(h)))
     return Op(ctx, h, (rowptr, col, val), d)
-
-
-def mlct_op_set_steps_per_launch(op: Op, steps: int) -> None:
-    """Recurrence steps per launch for a CSR operator (1 or 2)."""
-    st = lib().mlct_op_set_steps_per_launch(op.handle, int(steps))
-    if st != MLCT_OK:
-        raise MlctError(st, f"mlct_op_set_steps_per_launch({steps}) failed")
 
 
 def mlct_cheb_coeffs(ctx: Context, kind: int, a: float, b: float, n: int, power: float = 1.0):
