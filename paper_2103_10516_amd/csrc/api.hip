@@ -462,6 +462,27 @@ int64_t dense_bpad(int64_t active) { return (active + 31) / 32 * 32; }
 
 // Device workspace of one probe block (taken before any launch, so that
 // growth never frees a buffer still in use).
+// The bf16 split of A packed for the skinny kernel (built once per operator).
+mlct_status dense_packed_a(mlct_ctx* ctx, const mlct_op* cop, const void* hi, const void* lo,
+                           const void** phi, const void** plo) {
+  mlct_op* op = const_cast<mlct_op*>(cop);
+  if (!op->pack_hi) {
+    const size_t bytes = dense_pack_bytes(op->d, op->d);
+    void *h = nullptr, *l = nullptr;
+    if (hipMalloc(&h, bytes) != hipSuccess || hipMalloc(&l, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      if (h) (void)hipFree(h);
+      return fail(ctx, MLCT_ENOMEM, "no memory for the packed bf16 split of A");
+    }
+    HIPCHK(ctx, launch_dense_pack_a(ctx->stream, hi, lo, op->d, h, l));
+    op->pack_hi = h;
+    op->pack_lo = l;
+  }
+  *phi = op->pack_hi;
+  *plo = op->pack_lo;
+  return MLCT_OK;
+}
+
 mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mode, int degree,
                              int64_t block) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
@@ -486,6 +507,8 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
   CHECK(ws_get(ctx, WS_V1, (size_t)bpad * op->d * tsz, &tmp));
   CHECK(ws_get(ctx, WS_PART, (size_t)2 * ntiles * bpad * (S + 1) * sizeof(double), &tmp));
   CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * bpad * sizeof(double), &tmp));
+  if (prec == MLCT_BF16X3 && dense_tile(prec, op->d, op->d, bpad, op->tuned_dense).skinny)
+    CHECK(ws_get(ctx, WS_DPACK, 4 * dense_pack_bytes(bpad, op->d), &tmp));
   return MLCT_OK;
 }
 
@@ -512,6 +535,22 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
   const size_t pstep = (size_t)2 * ntiles * bpad;
   hipStream_t s = ctx->stream;
   HIPCHK(ctx, launch_dense_probe_init(s, prec, buf[0], d, bpad, src, D));
+  // BF16X3 skinny blocks read A and V_k packed; two packed V blocks alternate
+  // (V_0 packed here, V_new packed by each step's epilogue; their padding
+  // stays zero)
+  const bool packed = prec == MLCT_BF16X3 && t.skinny;
+  const void *pa_hi = nullptr, *pa_lo = nullptr;
+  char* vpk[4] = {nullptr, nullptr, nullptr, nullptr};  // (hi, lo) of blocks 0 and 1
+  if (packed) {
+    CHECK(dense_packed_a(ctx, op, a0, a1, &pa_hi, &pa_lo));
+    const size_t pb = dense_pack_bytes(bpad, d);
+    void* w;
+    CHECK(ws_get(ctx, WS_DPACK, 4 * pb, &w));
+    for (int i = 0; i < 4; ++i) vpk[i] = static_cast<char*>(w) + i * pb;
+    HIPCHK(ctx, launch_dense_pack_v(s, static_cast<const float*>(buf[0]), bpad, d, vpk[0],
+                                    vpk[1]));
+    HIPCHK(ctx, hipMemsetAsync(vpk[2], 0, 2 * pb, s));
+  }
   const int zdirect = src.entries ? 2 : 1;
   for (int k = 1; k <= S; ++k) {
     const bool first = (k == 1);
@@ -530,6 +569,15 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
     a.src = src;
     a.part = P + pstep * (k - 1);
     a.tile_force = op->tuned_dense;
+    if (packed) {
+      const int in = (k - 1) & 1, out = k & 1;
+      a.pk_a_hi = pa_hi;
+      a.pk_a_lo = pa_lo;
+      a.pk_v_hi = vpk[2 * in];
+      a.pk_v_lo = vpk[2 * in + 1];
+      a.pk_o_hi = vpk[2 * out];
+      a.pk_o_lo = vpk[2 * out + 1];
+    }
     LaunchTimer tm(ctx, MLCT_KERNEL_DENSE_STEP);
     HIPCHK(ctx, launch_dense_step(s, prec, a));
     tm.done();
@@ -817,8 +865,8 @@ mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t 
 mlct_status mlct_op_destroy(mlct_op* op) {
   if (!op) return MLCT_EINVAL;
   (void)hipSetDevice(op->device);
-  void* owned[] = {op->owned,   op->split_hi, op->split_lo, op->a32,
-                   op->a64,     op->hub_mem,  op->hubx_mem, op->gram_mem};
+  void* owned[] = {op->owned,   op->split_hi, op->split_lo, op->pack_hi, op->pack_lo,
+                   op->a32,     op->a64,      op->hub_mem,  op->hubx_mem, op->gram_mem};
   for (void* p : owned)
     if (p) (void)hipFree(p);
   delete op;

@@ -94,6 +94,8 @@ struct mlct_op {
   void* owned = nullptr;      // Gram matrix or other op-owned memory
   void* split_hi = nullptr;   // bf16 hi part of A (lazily built)
   void* split_lo = nullptr;   // bf16 lo part of A
+  void* pack_hi = nullptr;    // the split packed for the skinny kernel (lazily built)
+  void* pack_lo = nullptr;
   void* a32 = nullptr;        // FP32 copy of an FP64 dense A (lazily built)
   void* a64 = nullptr;        // FP64 copy of an FP32 dense A (lazily built)
 };
@@ -123,7 +125,8 @@ namespace mlct {
 // Workspace slot indices (each slot grows independently).
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
-  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ, WS_NSLOTS
+  WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ,
+  WS_DPACK, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -289,6 +292,14 @@ struct DenseStepArgs {
   ProbeSrc src;
   double* part;  // [2][ntiles][bpad] for this step
   int tile_force;  // see dense_tile
+  // BF16X3 skinny blocks: A and V_k packed in the MFMA lane layout
+  // (launch_dense_pack_*), V_new packed by the epilogue; null = unpacked
+  const void* pk_a_hi = nullptr;
+  const void* pk_a_lo = nullptr;
+  const void* pk_v_hi = nullptr;
+  const void* pk_v_lo = nullptr;
+  void* pk_o_hi = nullptr;
+  void* pk_o_lo = nullptr;
 };
 struct DenseTile {
   bool large;
@@ -301,6 +312,14 @@ DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force =
 hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a);
 hipError_t launch_dense_probe_init(hipStream_t s, int prec, void* v0, int64_t d, int64_t bpad,
                                    ProbeSrc src, double* dots0);
+// Packed operands of the skinny BF16X3 kernel: bytes of one part (hi or lo)
+// for rows x d, and the packing of A's bf16 split (d x d, row-major) and of
+// an FP32 probe block (rows x d, probe-major).
+size_t dense_pack_bytes(int64_t rows, int64_t d);
+hipError_t launch_dense_pack_a(hipStream_t s, const void* hi, const void* lo, int64_t d,
+                               void* out_hi, void* out_lo);
+hipError_t launch_dense_pack_v(hipStream_t s, const float* v, int64_t rows, int64_t d,
+                               void* out_hi, void* out_lo);
 hipError_t launch_dense_split(hipStream_t s, const void* a, int dtype, int64_t d, int64_t lda,
                               void* hi, void* lo);
 hipError_t launch_dense_convert(hipStream_t s, const void* a, int src_dtype, int64_t d,

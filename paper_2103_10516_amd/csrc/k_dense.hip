@@ -28,6 +28,26 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// Packed bf16 operands of the skinny BF16x3 kernel.  A (rows x d) is cut
+// into tiles of 16 rows and k blocks of 32 columns; block (t, kb) holds the
+// 64 lanes' operands of one 16x16x32 MFMA in lane order, 8 values per lane:
+// lane l = (row % 16) + 16 g carries columns kb*32 + 8 g .. + 7.  Rows and
+// columns past the matrix are zero.  The same layout serves a probe block
+// (rows = probes) and the matrix (rows = matrix rows).
+__host__ __device__ inline int64_t pk_kblocks(int64_t d) { return (d + 31) / 32; }
+__host__ __device__ inline int64_t pk_index(int64_t row, int64_t k, int64_t kblocks) {
+  const int64_t lane = (row & 15) + 16 * ((k & 31) >> 3);
+  return (((row >> 4) * kblocks + (k >> 5)) * 64 + lane) * 8 + (k & 7);
+}
+struct PackedOps {
+  const bf8* a_hi;  // matrix, packed
+  const bf8* a_lo;
+  const bf8* v_hi;  // V_k, packed
+  const bf8* v_lo;
+  __bf16* o_hi;     // V_new, packed (written by the epilogue)
+  __bf16* o_lo;
+};
+
 template <int PREC>
 struct Prec;
 template <>
@@ -302,12 +322,19 @@ __global__ __launch_bounds__(64 * WM * WN) void dense_step_kernel(
 // assignment of columns to an MFMA's k slots only has to agree between the
 // two operands.  The four partial accumulators are summed through LDS in a
 // fixed wave order, and wave a runs the epilogue of probe tile a.
-template <int PREC, int TM, int W, int ZMODE, bool HAS_PREV>
+//
+// PK (BF16x3 only): both operands come pre-split and pre-packed in the lane
+// layout of the 16x16x32 bf16 MFMA (see the packed layout below), so each
+// 16-byte load of a wave covers 1 KB of contiguous memory instead of 16
+// rows' worth of scattered pieces; the epilogue writes V_new packed for the
+// next step as well.  The number of distinct cache lines per load, not the
+// bytes, bounds the unpacked form.
+template <int PREC, int TM, int W, int ZMODE, bool HAS_PREV, bool PK = false>
 __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
     const void* __restrict__ A0, const void* __restrict__ A1, int64_t lda, int64_t d,
     const typename Prec<PREC>::V* __restrict__ vk, typename Prec<PREC>::V* __restrict__ vm,
     typename Prec<PREC>::V ca, typename Prec<PREC>::V cb, ProbeSrc src, int mtiles, int ntiles,
-    double* __restrict__ part) {
+    double* __restrict__ part, PackedOps pk) {
   using P = Prec<PREC>;
   using VT = typename P::V;
   using MT = typename P::M;
@@ -413,6 +440,53 @@ __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
   // sinking the loads down to their uses (either would turn the prefetch
   // back into load-then-use).  Past the last chunk a load re-reads that
   // chunk (a cache hit), so every load in the loop is unconditional.
+  if constexpr (PK) {
+    static_assert(PREC == 2, "packed operands are bf16 hi / lo");
+    // k blocks of 32: wave w takes blocks w, w + W, ...; two register sets
+    // in turn, as below.  Padding (k >= d, rows >= d) is zero in both.
+    const int64_t KB = pk_kblocks(d);
+    const bf8* ph = pk.a_hi + ((int64_t)nt * KB) * 64 + lane;
+    const bf8* pl = pk.a_lo + ((int64_t)nt * KB) * 64 + lane;
+    const bf8* qh = pk.v_hi + ((int64_t)(m0 / 16) * KB) * 64 + lane;
+    const bf8* ql = pk.v_lo + ((int64_t)(m0 / 16) * KB) * 64 + lane;
+    const int64_t nk = KB > wave ? (KB - wave + W - 1) / W : 0;
+    auto kbof = [&](int64_t i) { return (int64_t)wave + (i < nk ? i : nk - 1) * W; };
+    bf8 b0h, b0l, b1h, b1l, x0h[TM], x0l[TM], x1h[TM], x1l[TM];
+    auto ld = [&](int64_t kb, bf8& bh, bf8& bl, bf8 (&xh)[TM], bf8 (&xl)[TM]) {
+      bh = ph[kb * 64];
+      bl = pl[kb * 64];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        xh[a] = qh[(a * KB + kb) * 64];
+        xl[a] = ql[(a * KB + kb) * 64];
+      }
+    };
+    auto mm = [&](const bf8& bh, const bf8& bl, const bf8 (&xh)[TM], const bf8 (&xl)[TM]) {
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        acc[a][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], bh, acc[a][0], 0, 0, 0);
+        acc[a][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[a], bl, acc[a][1], 0, 0, 0);
+        acc[a][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[a], bh, acc[a][2], 0, 0, 0);
+      }
+    };
+    if (nk > 0) {
+      ld(kbof(0), b0h, b0l, x0h, x0l);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      int64_t i = 0;
+      for (; i + 2 <= nk; i += 2) {
+        ld(kbof(i + 1), b1h, b1l, x1h, x1l);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        mm(b0h, b0l, x0h, x0l);
+        ld(kbof(i + 2), b0h, b0l, x0h, x0l);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        mm(b1h, b1l, x1h, x1l);
+      }
+      if (i < nk) mm(b0h, b0l, x0h, x0l);
+    }
+  } else {
   const int64_t nfull = d / KC;
   const int64_t mine = wave < nfull ? (nfull - wave + W - 1) / W : 0;  // chunks of this wave
   auto chunk = [&](int64_t i) { return (int64_t)wave + (i < mine ? i : mine - 1) * W; };
@@ -456,6 +530,7 @@ __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
         }
     compute(ra, rv);
   }
+  }  // unpacked operands
 
 #pragma unroll
   for (int a = 0; a < TM; ++a) {
@@ -484,6 +559,13 @@ __global__ __launch_bounds__(64 * W) void dense_skinny_kernel(
     VT vn = ca * (VT)sum[r] + cb * x;
     if (HAS_PREV) vn -= vm[idx];
     vm[idx] = vn;
+    if constexpr (PK) {
+      __bf16 h, lo;
+      split_bf16((float)vn, h, lo);
+      const int64_t q = pk_index(j, n, pk_kblocks(d));
+      pk.o_hi[q] = h;
+      pk.o_lo[q] = lo;
+    }
     if (ZMODE == 0) {
       p1[r] = (double)x * (double)vn;
       p2[r] = (double)vn * (double)vn;
@@ -545,6 +627,36 @@ __global__ __launch_bounds__(256) void dense_probe_init_kernel(VT* __restrict__ 
 }
 
 // A_hi = bf16(A), A_lo = bf16(A - A_hi), from FP32 or FP64 A (row-major).
+// Pack rows x d values (row stride ld; FP32 split into bf16 hi / lo, or
+// bf16 hi and lo given apart) into the skinny kernel's lane layout, zero
+// past the rows and columns (all of ceil(rows / 16) * 16 x ceil(d / 32) * 32).
+template <typename ST>
+__global__ __launch_bounds__(256) void pack_kernel(const ST* __restrict__ hi_or_val,
+                                                   const ST* __restrict__ lo, int64_t rows,
+                                                   int64_t d, int64_t ld,
+                                                   __bf16* __restrict__ out_hi,
+                                                   __bf16* __restrict__ out_lo) {
+  const int64_t KB = pk_kblocks(d);
+  const int64_t rp = (rows + 15) / 16 * 16, cols = KB * 32;
+  const int64_t total = rp * cols;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t r = t / cols, k = t % cols;
+    __bf16 h = (__bf16)0.f, l = (__bf16)0.f;
+    if (r < rows && k < d) {
+      if constexpr (std::is_same<ST, float>::value) {
+        split_bf16(hi_or_val[r * ld + k], h, l);
+      } else {
+        h = hi_or_val[r * ld + k];
+        l = lo[r * ld + k];
+      }
+    }
+    const int64_t q = pk_index(r, k, KB);
+    out_hi[q] = h;
+    out_lo[q] = l;
+  }
+}
+
 template <typename ST>
 __global__ void split_kernel(const ST* __restrict__ a, int64_t d, int64_t lda,
                              __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
@@ -671,9 +783,17 @@ hipError_t launch_skinny_cfg(hipStream_t s, const DenseStepArgs& a) {
   const VT ca = (VT)a.ca, cb = (VT)a.cb;
   const VT* vk = static_cast<const VT*>(a.vk);
   VT* vm = static_cast<VT*>(a.vm);
-#define MLCT_SKINNY_LAUNCH(Z, HP)                                                            \
-  dense_skinny_kernel<PREC, TM, W, Z, HP><<<grid, 64 * W, 0, s>>>(                            \
-      a.A0, a.A1, a.lda, a.d, vk, vm, ca, cb, a.src, mtiles, ntiles, a.part)
+  const PackedOps pk{static_cast<const bf8*>(a.pk_a_hi), static_cast<const bf8*>(a.pk_a_lo),
+                     static_cast<const bf8*>(a.pk_v_hi), static_cast<const bf8*>(a.pk_v_lo),
+                     static_cast<__bf16*>(a.pk_o_hi), static_cast<__bf16*>(a.pk_o_lo)};
+  const bool packed = PREC == 2 && a.pk_a_hi != nullptr;
+#define MLCT_SKINNY_LAUNCH(Z, HP)                                                             \
+  if (packed)                                                                                 \
+    dense_skinny_kernel<PREC, TM, W, Z, HP, PREC == 2><<<grid, 64 * W, 0, s>>>(                \
+        a.A0, a.A1, a.lda, a.d, vk, vm, ca, cb, a.src, mtiles, ntiles, a.part, pk);            \
+  else                                                                                        \
+    dense_skinny_kernel<PREC, TM, W, Z, HP><<<grid, 64 * W, 0, s>>>(                           \
+        a.A0, a.A1, a.lda, a.d, vk, vm, ca, cb, a.src, mtiles, ntiles, a.part, pk)
   if (a.has_prev) {
     if (a.zmode == 0) MLCT_SKINNY_LAUNCH(0, true);
     else if (a.zmode == 1) MLCT_SKINNY_LAUNCH(1, true);
@@ -764,6 +884,26 @@ hipError_t launch_dense_split(hipStream_t s, const void* a, int dtype, int64_t d
   else
     split_kernel<float><<<2048, 256, 0, s>>>(static_cast<const float*>(a), d, lda,
                                               static_cast<__bf16*>(hi), static_cast<__bf16*>(lo));
+  return hipGetLastError();
+}
+
+size_t dense_pack_bytes(int64_t rows, int64_t d) {
+  return (size_t)((rows + 15) / 16) * (size_t)pk_kblocks(d) * 64 * 8 * sizeof(__bf16);
+}
+
+hipError_t launch_dense_pack_a(hipStream_t s, const void* hi, const void* lo, int64_t d,
+                               void* out_hi, void* out_lo) {
+  pack_kernel<__bf16><<<2048, 256, 0, s>>>(static_cast<const __bf16*>(hi),
+                                           static_cast<const __bf16*>(lo), d, d, d,
+                                           static_cast<__bf16*>(out_hi),
+                                           static_cast<__bf16*>(out_lo));
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_pack_v(hipStream_t s, const float* v, int64_t rows, int64_t d,
+                               void* out_hi, void* out_lo) {
+  pack_kernel<float><<<512, 256, 0, s>>>(v, nullptr, rows, d, d, static_cast<__bf16*>(out_hi),
+                                         static_cast<__bf16*>(out_lo));
   return hipGetLastError();
 }
 
