@@ -460,8 +460,6 @@ mlct_status dense_operand(mlct_ctx* ctx, const mlct_op* cop, int prec, const voi
 
 int64_t dense_bpad(int64_t active) { return (active + 31) / 32 * 32; }
 
-// Device workspace of one probe block (taken before any launch, so that
-// growth never frees a buffer still in use).
 // The bf16 split of A packed for the skinny kernel (built once per operator).
 mlct_status dense_packed_a(mlct_ctx* ctx, const mlct_op* cop, const void* hi, const void* lo,
                            const void** phi, const void** plo) {
@@ -483,6 +481,8 @@ mlct_status dense_packed_a(mlct_ctx* ctx, const mlct_op* cop, const void* hi, co
   return MLCT_OK;
 }
 
+// Device workspace of one probe block (taken before any launch, so that
+// growth never frees a buffer still in use).
 mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mode, int degree,
                              int64_t block) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;

@@ -810,8 +810,8 @@ hipError_t launch_skinny_cfg(hipStream_t s, const DenseStepArgs& a) {
 }  // namespace
 
 DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) {
-  // Blocks of at most 64 probes take the skinny split-K kernel (16-row
-  // tiles) when rows are 16-byte aligned.  Otherwise the largest square tile
+  // Blocks of at most 64 probes (512 for BF16x3) take the skinny split-K
+  // kernel (16-row tiles) when rows are 16-byte aligned.  Otherwise the largest square tile
   // that still gives a few hundred workgroups: 128 x 128, then 64 x 64, else
   // 32 x 32 (small problems are latency-bound; more workgroups win).
   // force: 0 = 32, 1 = 128, 2 = 64, 3 = skinny (when the block allows it).
@@ -827,7 +827,11 @@ DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) 
   else if (force == 1 && bpad % 128 == 0) size = 128;
   else if (force == 2 && bpad % 64 == 0) size = 64;
   else if (force < 0) {
-    if (bpad <= 64 && skinny_ok) t.skinny = true;
+    // BF16x3 reads packed operands on the skinny kernel, which beats square
+    // tiles up to 512 probes (d = 4096: 69 vs 124 us at 320, 108 vs 119 at
+    // 512); FP64 and FP32 read row-major arrays and keep it to 64
+    const int64_t skinny_max = prec == MLCT_BF16X3 ? 512 : 64;
+    if (bpad <= skinny_max && skinny_ok) t.skinny = true;
     else if (bpad % 128 == 0 && n128 >= 256) size = 128;
     else if (bpad % 64 == 0 && n64 >= 256) size = 64;
   }
