@@ -304,6 +304,11 @@ mlct_status mlct_estimate_slq(mlct_ctx* ctx, const mlct_op* op, mlct_func f, dou
  * smaller second-highest level; with no admissible choice the single level
  * {n} is returned.  The j = 0 term belongs to the first level (its variance
  * is zero for Rademacher probes).  Sample sizes are rounded up, at least 2.
+ * A plan holds at most MLCT_MAX_LEVELS levels: when the optimum has more
+ * (noisy pilots of slowly converging expansions can ask for dozens of
+ * levels that each save little), the plan is the optimum over plans of at
+ * most MLCT_MAX_LEVELS levels, by the same recurrence indexed by the number
+ * of levels (its cost opt_total is then at least the unconstrained one).
  *
  * target_kind MLCT_TARGET_VARIANCE: target = eps^2, a variance of
  * mlct_result.value (the estimate without its exp log_scale factor);
@@ -328,7 +333,7 @@ typedef struct {
 /* Plan from a given pilot term table.  terms: host, m_pilot x (n+1) FP64
  * row-major; 1 <= n <= MLCT_MAX_PLAN_DEGREE; m_pilot >= 2; target > 0;
  * mode MLCT_DIRECT or MLCT_DOUBLING (sets C(l)).  Errors: EINVAL for
- * arguments, ERANGE if the optimum has more than MLCT_MAX_LEVELS levels. */
+ * arguments. */
 mlct_status mlct_plan_levels(mlct_ctx* ctx, const double* terms, int64_t m_pilot, int32_t n,
                              int32_t mode, double target, int32_t target_kind,
                              int64_t min_top, mlct_level_plan* out);

@@ -25,6 +25,16 @@ part of the first level (l_0 = -1), which leaves its variance unchanged for
 Rademacher probes since t_0 is the same for every probe; the recommended
 sample sizes are rounded up and at least 2 (a level variance needs two
 samples).
+
+A plan may hold at most MAX_LEVELS levels (the fixed-size level arrays of
+the library's interface).  When the optimum of the recurrence above has more,
+the reading taken is the optimum over plans of at most MAX_LEVELS levels: the
+same recurrence indexed by the number of levels,
+    H_0(0) = 0, H_0(l > 0) = inf,
+    H_k(0) = 0, H_k(l) = min_{0 <= l' < l} H_{k-1}(l') + sqrt(V_{l'l} C(l)),
+so that H_k(l) is the least cost of at most k levels topped by l, and the
+top level takes T(l') = H_{MAX_LEVELS - 1}(l') + sqrt(V_{l'n} C(n)) with the
+same condition, ties and fallback.
 """
 from __future__ import annotations
 
@@ -33,6 +43,8 @@ import itertools
 import math
 
 import numpy as np
+
+MAX_LEVELS = 32
 
 
 def level_cost(l: int, doubling: bool) -> int:
@@ -74,11 +86,32 @@ def _alloc(var, cost, target: float, budget: bool):
     return [mu * math.sqrt(v / c) if c > 0 else 0.0 for v, c in zip(var, cost)]
 
 
+def _top(cbar, Vl, C, n, target, budget, m_pilot, single):
+    """Second-highest level under the top-level condition (None: single)."""
+    chosen, chosen_total = None, math.inf
+    for lp in range(n):
+        vt = max(Vl(lp, n), 0.0)
+        tot = cbar[lp] + math.sqrt(vt * C[n])
+        if not tot > 0.0:
+            continue
+        if budget:
+            mL = target * math.sqrt(vt / C[n]) / tot
+        else:
+            mL = tot * math.sqrt(vt / C[n]) / target
+        if mL >= m_pilot and tot < chosen_total:
+            chosen, chosen_total = lp, tot
+    if chosen is None:
+        return 0, single
+    return chosen, chosen_total
+
+
 def select(V: np.ndarray, n: int, doubling: bool, target: float, budget: bool,
-           m_pilot: int) -> Plan:
+           m_pilot: int, max_levels: int = MAX_LEVELS) -> Plan:
     """Levels and sample sizes by the dynamic programme of Theorem thm:levels
     with the top-level condition of Section 3.2.  ``target`` is eps^2
-    (budget = False) or the matvec budget B (budget = True)."""
+    (budget = False) or the matvec budget B (budget = True).  Plans of more
+    than ``max_levels`` levels are replaced by the best of at most that many
+    (module docstring)."""
     C = [level_cost(l, doubling) for l in range(n + 1)]
     Vl = lambda lp, l: float(V[lp + 1, l])  # noqa: E731
     cbar = np.zeros(n)
@@ -91,25 +124,34 @@ def select(V: np.ndarray, n: int, doubling: bool, target: float, budget: bool,
                 best, arg = v, lp
         cbar[l], prev[l] = best, arg
     single = math.sqrt(max(Vl(0, n), 0.0) * C[n])
-    chosen, chosen_total = None, math.inf
-    for lp in range(n):
-        vt = max(Vl(lp, n), 0.0)
-        tot = cbar[lp] + math.sqrt(vt * C[n])
-        if tot <= 0.0:
-            continue
-        if budget:
-            mL = target * math.sqrt(vt / C[n]) / tot
-        else:
-            mL = tot * math.sqrt(vt / C[n]) / target
-        if mL >= m_pilot and tot < chosen_total:
-            chosen, chosen_total = lp, tot
-    if chosen is None:
-        chosen, chosen_total = 0, single
+    chosen, chosen_total = _top(cbar, Vl, C, n, target, budget, m_pilot, single)
     chain = [n]
     lp = chosen
     while lp > 0:
         chain.append(lp)
         lp = int(prev[lp])
+    if len(chain) > max_levels:
+        # H_k(l): at most k levels topped by l; H_k(0) = 0
+        K = max_levels - 1
+        H = np.full((K + 1, n), math.inf)
+        H[:, 0] = 0.0
+        prevk = np.zeros((K + 1, n), dtype=np.int64)
+        for k in range(1, K + 1):
+            for l in range(1, n):
+                best, arg = math.inf, 0
+                for lp in range(l):
+                    if H[k - 1, lp] == math.inf:
+                        continue
+                    v = H[k - 1, lp] + math.sqrt(max(Vl(lp, l), 0.0) * C[l])
+                    if v < best:
+                        best, arg = v, lp
+                H[k, l], prevk[k, l] = best, arg
+        chosen, chosen_total = _top(H[K], Vl, C, n, target, budget, m_pilot, single)
+        chain = [n]
+        lp, k = chosen, K
+        while lp > 0:
+            chain.append(lp)
+            lp, k = int(prevk[k, lp]), k - 1
     degrees = chain[::-1]
     lo = [0] + degrees[:-1]
     var = [max(Vl(a, b), 0.0) for a, b in zip(lo, degrees)]
@@ -135,6 +177,30 @@ def brute_cbar(V: np.ndarray, n: int, doubling: bool) -> np.ndarray:
                 best = min(best, tot)
         out[l] = best
     return out
+
+
+def brute_force_capped(V: np.ndarray, n: int, doubling: bool, target: float, budget: bool,
+                       m_pilot: int, max_levels: int):
+    """Every level set of at most max_levels levels topped by n (small n
+    only): (least total, its degrees) among those meeting the top-level
+    condition, else the single level."""
+    C = [level_cost(l, doubling) for l in range(n + 1)]
+    best, best_deg = math.inf, None
+    for r in range(0, max_levels):
+        for inner in itertools.combinations(range(1, n), r):
+            degrees = list(inner) + [n]
+            lo = [0] + degrees[:-1]
+            tot = sum(math.sqrt(max(float(V[a + 1, b]), 0.0) * C[b]) for a, b in zip(lo, degrees))
+            vt = max(float(V[lo[-1] + 1, n]), 0.0)
+            if not tot > 0.0:
+                continue
+            mL = (target * math.sqrt(vt / C[n]) / tot if budget
+                  else tot * math.sqrt(vt / C[n]) / target)
+            if mL >= m_pilot and tot < best:
+                best, best_deg = tot, degrees
+    if best_deg is None:
+        return math.sqrt(max(float(V[1, n]), 0.0) * C[n]), [n]
+    return best, best_deg
 
 
 def brute_force_budget(V: np.ndarray, n: int, doubling: bool, budget: float, m_pilot: int):

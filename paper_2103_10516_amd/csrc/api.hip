@@ -1941,15 +1941,21 @@ mlct_status plan_on_device(mlct_ctx* ctx, const double* mu, int64_t ldmu, const 
                            int64_t min_top, mlct_level_plan* out) {
   const size_t nS = (size_t)m * (n + 1), nV = (size_t)(n + 2) * (n + 1);
   void* w;
-  CHECK(ws_get(ctx, WS_PLAN, (nS + (n + 1) + nV) * sizeof(double) + sizeof(LevelPlanDev) + 256, &w));
+  const size_t nP = (size_t)MLCT_MAX_LEVELS * (n + 1);
+  CHECK(ws_get(ctx, WS_PLAN,
+               (nS + (n + 1) + nV) * sizeof(double) + sizeof(LevelPlanDev) + 256 +
+                   nP * sizeof(int),
+               &w));
   double* S = static_cast<double*>(w);
   double* mean = S + nS;
   double* V = mean + (n + 1);
   LevelPlanDev* pd = reinterpret_cast<LevelPlanDev*>(
       (reinterpret_cast<uintptr_t>(V + nV) + 255) & ~(uintptr_t)255);
+  int* prevk = reinterpret_cast<int*>(pd + 1);
   hipStream_t s = ctx->stream;
   HIPCHK(ctx, launch_level_plan(s, mu, ldmu, coef, n, m, S, mean, V, mode == MLCT_DOUBLING ? 1 : 0,
-                                target, target_kind == MLCT_TARGET_BUDGET ? 1 : 0, min_top, pd));
+                                target, target_kind == MLCT_TARGET_BUDGET ? 1 : 0, min_top, prevk,
+                                pd));
   LevelPlanDev h;
   HIPCHK(ctx, hipMemcpyAsync(&h, pd, sizeof h, hipMemcpyDeviceToHost, s));
   CHECK(sync_stream(ctx));

@@ -237,10 +237,12 @@ struct LevelPlanDev {
 };
 // mu: pilot moments m x (n+1) (row stride ldmu); coef: c_0..c_n or null (the
 // rows are the terms themselves).  Scratch S (m x (n+1)), mean (n+1),
-// V ((n+2) x (n+1)).  target: eps^2 (budget = 0) or a matvec budget.
+// V ((n+2) x (n+1)), prevk (MLCT_MAX_LEVELS x (n+1) ints).  target: eps^2
+// (budget = 0) or a matvec budget.
 hipError_t launch_level_plan(hipStream_t s, const double* mu, int64_t ldmu, const double* coef,
                              int n, int64_t m, double* S, double* mean, double* V, int doubling,
-                             double target, int budget, int64_t min_top, LevelPlanDev* out);
+                             double target, int budget, int64_t min_top, int* prevk,
+                             LevelPlanDev* out);
 
 // ---- stochastic Lanczos quadrature (k_slq.hip, slq_spmm in k_csr.hip) ------
 constexpr int kSlqMaxSteps = 256;

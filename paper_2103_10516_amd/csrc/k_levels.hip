@@ -9,6 +9,11 @@
 // eqs. eqn:optSamples / eqn:optMu must recommend at least min_top samples
 // for it).  Readings: ties go to the smaller l'; with no admissible l' the
 // single level {n} is used; sample sizes are rounded up and at least 2.
+// A plan holds at most MLCT_MAX_LEVELS levels: when the optimum has more,
+// the recurrence is run again indexed by the number of levels,
+// H_k(l) = min_{l' < l} H_{k-1}(l') + sqrt(V_{l'l} C(l)) with H_k(0) = 0 and
+// H_0(l > 0) = inf (the least cost of at most k levels topped by l), and the
+// top level is chosen over H_{MLCT_MAX_LEVELS - 1} with the same condition.
 // All arithmetic is FP64 with sums in a fixed order.
 #include <cfloat>
 
@@ -91,14 +96,39 @@ __device__ __forceinline__ void wave_argmin(double& v, int& i) {
   }
 }
 
-// The dynamic programme and the plan; one wave.
+// Second-highest level over h (cbar, or H of the capped recurrence) with
+// the top-level condition: (arg, total), arg = INT32_MAX when none qualifies.
+template <class VF>
+__device__ void top_level(const double* h, VF Vat, int n, int doubling, double target,
+                          int budget, int64_t min_top, int& arg, double& best) {
+  const int lane = threadIdx.x;
+  const double cn = level_c(n, doubling);
+  best = DBL_MAX;
+  arg = INT32_MAX;
+  for (int lp = lane; lp < n; lp += 64) {
+    const double vt = Vat(lp, n);
+    const double tot = h[lp] + sqrt(vt * cn);
+    if (!(tot > 0.0)) continue;
+    const double mL = budget ? target * sqrt(vt / cn) / tot : tot * sqrt(vt / cn) / target;
+    if (mL >= (double)min_top && tot < best) {
+      best = tot;
+      arg = lp;
+    }
+  }
+  wave_argmin(best, arg);
+}
+
+// The dynamic programme and the plan; one wave.  prevk: scratch of
+// MLCT_MAX_LEVELS * (n + 1) ints for the capped recurrence.
 __global__ __launch_bounds__(64) void level_dp_kernel(const double* __restrict__ V, int n,
                                                       int doubling, double target, int budget,
-                                                      int64_t min_top,
+                                                      int64_t min_top, int* __restrict__ prevk,
                                                       LevelPlanDev* __restrict__ out) {
   __shared__ double cbar[kMaxPlanDegree + 1];
+  __shared__ double hcur[kMaxPlanDegree + 1];
   __shared__ int prev[kMaxPlanDegree + 1];
   __shared__ int chain[kMaxPlanDegree + 1];
+  __shared__ int nlev;
   const int lane = threadIdx.x;
   auto Vat = [&](int lp, int l) { return fmax(V[(int64_t)(lp + 1) * (n + 1) + l], 0.0); };
   if (lane == 0) {
@@ -126,20 +156,9 @@ __global__ __launch_bounds__(64) void level_dp_kernel(const double* __restrict__
   }
   const double cn = level_c(n, doubling);
   const double single = sqrt(Vat(0, n) * cn);
-  double best = DBL_MAX;
-  int arg = INT32_MAX;
-  for (int lp = lane; lp < n; lp += 64) {
-    const double vt = Vat(lp, n);
-    const double tot = cbar[lp] + sqrt(vt * cn);
-    if (!(tot > 0.0)) continue;
-    const double mL = budget ? target * sqrt(vt / cn) / tot : tot * sqrt(vt / cn) / target;
-    if (mL >= (double)min_top && tot < best) {
-      best = tot;
-      arg = lp;
-    }
-  }
-  wave_argmin(best, arg);
-  if (lane != 0) return;
+  double best;
+  int arg;
+  top_level(cbar, Vat, n, doubling, target, budget, min_top, arg, best);
   int chosen = arg;
   double total = best;
   if (arg == INT32_MAX) {
@@ -147,9 +166,65 @@ __global__ __launch_bounds__(64) void level_dp_kernel(const double* __restrict__
     total = single;
   }
   // levels from the top down, then reversed
-  int L = 0;
-  chain[L++] = n;
-  for (int lp = chosen; lp > 0; lp = prev[lp]) chain[L++] = lp;
+  if (lane == 0) {
+    int L = 0;
+    chain[L++] = n;
+    for (int lp = chosen; lp > 0; lp = prev[lp]) chain[L++] = lp;
+    nlev = L;
+  }
+  __syncthreads();
+  if (nlev > MLCT_MAX_LEVELS) {
+    // at most K + 1 levels: H_K over the l' below the top
+    constexpr int K = MLCT_MAX_LEVELS - 1;
+    double* hp = cbar;
+    double* hc = hcur;
+    for (int l = lane; l < n; l += 64) hp[l] = l == 0 ? 0.0 : __builtin_inf();
+    __syncthreads();
+    for (int k = 1; k <= K; ++k) {
+      if (lane == 0) hc[0] = 0.0;
+      for (int l = 1; l < n; ++l) {
+        const double cl = level_c(l, doubling);
+        double b = __builtin_inf();
+        int a = INT32_MAX;
+        for (int lp = lane; lp < l; lp += 64) {
+          const double h = hp[lp];
+          if (h == __builtin_inf()) continue;
+          const double v = h + sqrt(Vat(lp, l) * cl);
+          if (v < b) {
+            b = v;
+            a = lp;
+          }
+        }
+        wave_argmin(b, a);
+        if (lane == 0) {
+          hc[l] = b;
+          prevk[(int64_t)k * (n + 1) + l] = a == INT32_MAX ? 0 : a;
+        }
+      }
+      __syncthreads();
+      double* t = hp;
+      hp = hc;
+      hc = t;
+    }
+    top_level(hp, Vat, n, doubling, target, budget, min_top, arg, best);
+    chosen = arg;
+    total = best;
+    if (arg == INT32_MAX) {
+      chosen = 0;
+      total = single;
+    }
+    if (lane == 0) {
+      int L = 0;
+      chain[L++] = n;
+      for (int lp = chosen, k = K; lp > 0; --k) {
+        chain[L++] = lp;
+        lp = prevk[(int64_t)k * (n + 1) + lp];
+      }
+      nlev = L;
+    }
+  }
+  if (lane != 0) return;
+  const int L = nlev;
   out->L = L;
   out->opt_total = total;
   out->single_total = single;
@@ -176,7 +251,8 @@ __global__ __launch_bounds__(64) void level_dp_kernel(const double* __restrict__
 
 hipError_t launch_level_plan(hipStream_t s, const double* mu, int64_t ldmu, const double* coef,
                              int n, int64_t m, double* S, double* mean, double* V, int doubling,
-                             double target, int budget, int64_t min_top, LevelPlanDev* out) {
+                             double target, int budget, int64_t min_top, int* prevk,
+                             LevelPlanDev* out) {
   level_prefix_kernel<<<(int)((m + kPT - 1) / kPT), kPT, 0, s>>>(mu, ldmu, coef, n, m, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -185,7 +261,7 @@ hipError_t launch_level_plan(hipStream_t s, const double* mu, int64_t ldmu, cons
   const int64_t npairs = (int64_t)(n + 1) * (n + 2) / 2;
   level_var_kernel<<<(int)((npairs + kPT - 1) / kPT), kPT, 0, s>>>(S, mean, n, m, V);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  level_dp_kernel<<<1, 64, 0, s>>>(V, n, doubling, target, budget, min_top, out);
+  level_dp_kernel<<<1, 64, 0, s>>>(V, n, doubling, target, budget, min_top, prevk, out);
   return hipGetLastError();
 }
 

@@ -61,6 +61,43 @@ def test_plan_matches_oracle(ctx, doubling, kind, target, min_top, seed):
                                                  rel=1e-10)
 
 
+def _many_level_terms(m, seed, n=256, d=4096):
+    """Pilot terms c_j z^T T_j(A_hat) z of a spectrum i^-1.4 (d = 4096, the
+    nuclear-norm workload's) on [1e-6, 1], f = sqrt, written in the
+    eigenbasis with Gaussian probe weights: their optimal plan has about 50
+    levels, more than a plan can hold."""
+    lam = np.arange(1, d + 1) ** -1.4
+    a, b = 1e-6, 1.0
+    c, _ = cheb.coefficients(cheb.SQRT, a, b, n)
+    x = (2.0 * lam - (a + b)) / (b - a)
+    Tm = np.cos(np.outer(np.arccos(np.clip(x, -1.0, 1.0)), np.arange(n + 1)))
+    w = np.random.default_rng(seed).standard_normal((m, d)) ** 2
+    return (w @ Tm) * c[None, :]
+
+
+@pytest.mark.parametrize("m,kind,target,min_top", [(64, "variance", 1e-2, 16),
+                                                   (256, "variance", 1e-2, 16),
+                                                   (64, "budget", 1e7, 64)])
+def test_plan_capped_at_max_levels_matches_oracle(ctx, m, kind, target, min_top):
+    """Plans whose optimum has more than MLCT_MAX_LEVELS levels: the capped
+    recurrence on the device against the oracle's."""
+    from paper_2103_10516_amd import mlct
+
+    t = _many_level_terms(m, 7)
+    n = t.shape[1] - 1
+    V = levelsel.level_variances(t)
+    free = levelsel.select(V, n, True, target, kind == "budget", min_top, max_levels=10 ** 6)
+    want = levelsel.select(V, n, True, target, kind == "budget", min_top)
+    tk = mlct.MLCT_TARGET_BUDGET if kind == "budget" else mlct.MLCT_TARGET_VARIANCE
+    got = mlct.mlct_plan_levels(ctx, t, mlct.MLCT_DOUBLING, target, tk, min_top)
+    print(f"{kind} m={m}: optimum {len(free.degrees)} levels, capped {len(got['degrees'])}")
+    assert len(free.degrees) > mlct.MLCT_MAX_LEVELS >= len(want.degrees)
+    assert got["degrees"] == want.degrees
+    assert got["m"] == want.m
+    assert got["opt_total"] == pytest.approx(want.opt_total, rel=1e-12)
+    assert got["opt_total"] >= free.opt_total * (1 - 1e-12)
+
+
 def test_plan_variance_table_ragged_and_degenerate(ctx):
     """Two pilot rows (closed-form variances), n = 1, and a constant table
     (zero variance everywhere: the single level, 2 samples)."""

@@ -117,3 +117,39 @@ def test_sample_sizes_follow_the_optimal_allocation():
     assert p.m == [max(2, math.ceil(x)) for x in mk]
     # the achieved variance meets the target
     assert sum(v / m for v, m in zip(p.var, p.m)) <= eps2 * (1 + 1e-12)
+
+
+def _capped_case(seed):
+    rng = np.random.default_rng(seed)
+    n, m = 9, 400
+    base = rng.standard_normal((m, n + 1)) * (0.75 ** np.arange(n + 1))
+    t = base + 0.4 * np.roll(base, 1, axis=1)
+    t[:, 0] = 3.0
+    return levelsel.level_variances(t), n
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("budget,target,m_pilot", [(False, 1e-5, 0), (False, 1e-5, 3000),
+                                                   (True, 3e4, 50)])
+def test_level_count_cap_matches_enumeration(seed, budget, target, m_pilot):
+    """Plans limited to at most K levels (the fixed-size level arrays): the
+    capped recurrence against every level set of at most K levels."""
+    V, n = _capped_case(seed)
+    free = levelsel.select(V, n, True, target, budget, m_pilot, max_levels=10 ** 6)
+    for K in range(1, len(free.degrees)):
+        p = levelsel.select(V, n, True, target, budget, m_pilot, max_levels=K)
+        tot, deg = levelsel.brute_force_capped(V, n, True, target, budget, m_pilot, K)
+        assert len(p.degrees) <= K
+        assert p.degrees == deg
+        assert p.opt_total == pytest.approx(tot, rel=1e-13)
+        assert p.opt_total >= free.opt_total * (1 - 1e-13)
+
+
+def test_level_count_cap_not_binding_keeps_the_optimum():
+    V, n = _capped_case(7)
+    free = levelsel.select(V, n, True, 1e-5, False, 0, max_levels=10 ** 6)
+    for K in (len(free.degrees), len(free.degrees) + 3):
+        p = levelsel.select(V, n, True, 1e-5, False, 0, max_levels=K)
+        assert p.degrees == free.degrees and p.m == free.m
+    # the default cap is the library's level-array size
+    assert levelsel.MAX_LEVELS == 32
