@@ -300,6 +300,87 @@ def extra_time_to_eps(mlct, dev):
     return out
 
 
+def extra_time_to_eps_dense(mlct, dev):
+    """Time to a relative standard error eps of tr p_256(A_hat) for the
+    nuclear norm (X 8192 x 4096, sigma_i = i^-0.7, A = X^T X, f = sqrt on
+    [1e-6, 1], BF16x3): plain single level, 3-level MLMC 16/64/256, the
+    learned level (MLP on mu_0..mu_8 trained on 2048 pilot probes) and the
+    levels of Theorem thm:levels (256-probe pilot, included in its time).
+    Sample sizes from pilot variances by the optimal allocation.  The
+    realized error is against sum_i p_256(sigma_i^2), the polynomial of the
+    library's own coefficients evaluated on the host at the singular values
+    the matrix was built from (its FP32 rounding moves them by ~1e-7)."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    X, sig = wl.nuclear_x()
+    ctx = mlct.mlct_create(0)
+    op = mlct.mlct_op_gram(ctx, torch.from_numpy(X).to(dev))
+    a, b, n, prec, mode = 1e-6, 1.0, 256, mlct.MLCT_BF16X3, mlct.MLCT_DOUBLING
+    c, ls = mlct.mlct_cheb_coeffs(ctx, mlct.MLCT_SQRT, a, b, n)
+    xh = (2.0 * sig.astype(np.float64) ** 2 - (a + b)) / (b - a)
+    ref = float(np.sum(np.polynomial.chebyshev.chebval(xh, c))) * math.exp(ls)
+    _sync()
+    t0 = time.perf_counter()
+    net = mlct.mlct_learned_fit(ctx, op, mlct.MLCT_SQRT, a, b, n_fine=n, n_cheap=8,
+                                m_pilot=2048, seed=5, prec=prec, epochs=1500)
+    _sync()
+    t_fit = time.perf_counter() - t0
+    info = mlct.mlct_mlp_info_get(net)
+    degs = [16, 64, n]
+    t0 = time.perf_counter()
+    pil = mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, degs, [256, 256, 256], 6, prec, mode)
+    _sync()
+    t_pilot = time.perf_counter() - t0
+    T = abs(ref)
+    cost = [(k + 1) // 2 for k in degs]
+    rows = []
+
+    def timed(fn):
+        _sync()
+        t = time.perf_counter()
+        r = fn()
+        _sync()
+        return time.perf_counter() - t, r
+
+    for eps in (1e-3, 3e-4):
+        tgt = (eps * T) ** 2
+        m_plain = max(2, math.ceil(info["var_q"] / tgt))
+        V = list(pil["level_var"])
+        s_ml = sum(math.sqrt(v * cc) for v, cc in zip(V, cost))
+        m_ml = [max(2, math.ceil(s_ml * math.sqrt(v / cc) / tgt)) for v, cc in zip(V, cost)]
+        Vl = [info["var_g"], info["var_resid"]]
+        cl = [(8 + 1) // 2, cost[-1]]
+        s_l = sum(math.sqrt(v * cc) for v, cc in zip(Vl, cl))
+        m_l = [max(2, math.ceil(s_l * math.sqrt(v / cc) / tgt)) for v, cc in zip(Vl, cl)]
+        tp, rp = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, [n], [m_plain],
+                                                  11, prec, mode))
+        tm, rm = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, degs, m_ml, 12,
+                                                  prec, mode))
+        tl, rl = timed(lambda: mlct.mlct_estimate_learned(ctx, op, net, m_l[0], m_l[1], 13))
+        ta, (ra, plan) = timed(lambda: mlct.mlct_estimate_auto(
+            ctx, op, mlct.MLCT_SQRT, a, b, n, 256, 14, prec, mode, tgt))
+
+        def row(m, t, r):
+            return {"m": m, "s": t, "rel_se": math.sqrt(r["est_var"]) / T,
+                    "realized_rel_err": abs(r["estimate"] - ref) / T, "estimate": r["estimate"]}
+
+        rows.append({"eps": eps, "plain": row(m_plain, tp, rp), "mlmc": row(m_ml, tm, rm),
+                     "learned": row(m_l, tl, rl),
+                     "auto_levels": dict(row(plan["m"], ta, ra), degrees=plan["degrees"])})
+    out = {"workload": "nuclear norm, X 8192x4096 sigma_i=i^-0.7 (FP32), A=X^T X, sqrt on "
+                       "[1e-6,1], n=256, BF16x3; MLMC 16/64/256; learned MLP 9-64-64-1 on "
+                       "mu_0..mu_8, 2048 pilot probes",
+           "tr_p256_reference": ref, "fit_s": t_fit, "pilot_s": t_pilot,
+           "var_q": info["var_q"], "var_g": info["var_g"], "var_resid": info["var_resid"],
+           "mlmc_level_var": list(pil["level_var"]), "rows": rows}
+    net.close()
+    op.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,7 +388,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=2048, help="2D grid edge (default 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="dense,triangles,batch,time_to_eps",
+    ap.add_argument("--extras", default="dense,triangles,batch,time_to_eps,time_to_eps_dense",
                     help="comma list of secondary measurements to add ('' for none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device copies of 1 GiB (a plain copy kernel of known "
@@ -395,7 +476,8 @@ def main():
     op.close()
     ctx.close()
     extras = {"dense": extra_nuclear_dense, "triangles": extra_triangles,
-              "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps}
+              "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps,
+              "time_to_eps_dense": extra_time_to_eps_dense}
     secondary = {}
     for name in [e for e in args.extras.split(",") if e]:
         print(f"# secondary measurement: {name}", file=sys.stderr, flush=True)
