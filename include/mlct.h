@@ -412,9 +412,13 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
 /* ---- learned control-variate level (not in the paper) -------------------
  * g predicts a probe's fine-level value q = z^T p_{n_fine}(A_hat) z from its
  * cheap moments: the truncation q_c = sum_{j <= n_cheap} c_j mu_j plus a
- * small MLP correction (F = n_cheap + 1 inputs x_f = mu_f / mu_0, two hidden
- * tanh layers of 64 units, one output) trained on the residual q - q_c.  It is trained on pilot
- * probes, then used as one more multilevel term (Section 2.3, eq.
+ * correction of the standardised residual (q - q_c)/mu_0 in two stages, a
+ * linear least-squares fit on the standardised inputs u_f (mu_f / mu_0 for
+ * f = 1..n_cheap, centred and scaled over the training probes; the linear
+ * control variate of Section 5.5) and a small MLP (F = n_cheap + 1 inputs,
+ * two hidden tanh layers of 64 units, one output) trained on what the linear
+ * fit leaves:  g = q_c + mu_0 (ybar + ysd (beta . u + net(u))).  It is
+ * trained on pilot probes, then used as one more multilevel term (Section 2.3, eq.
  * eqn:telescope; the control-variate form of Section 5.5):
  *   Gamma = (1/M0) sum_{S0} g + (1/M1) sum_{S1} (q - g),
  * S0 at degree n_cheap, S1 at degree n_fine, probe sets disjoint from each
@@ -442,6 +446,9 @@ typedef struct {
   int32_t fallback;   /* 1 if the learned level is not used                */
   int32_t n_features, n_cheap, n_fine;
   int64_t ntrain, nval, nparams;
+  double x_mean[16];  /* input standardisation: u_f = (mu_f/mu_0 - x_mean_f) */
+  double x_sd[16];    /*   / x_sd_f (0 for f = 0 and constant inputs)       */
+  double lin[16];     /* linear stage beta_f (beta_0 = 0)                   */
 } mlct_mlp_info;
 
 #define MLCT_FLAG_LEARNED_FALLBACK 0x8u /* learned level disabled: plain used */

@@ -12,10 +12,14 @@ L = (1/N) sum_i (out_i - y_i)^2.  Gradients are derived by hand
 (tanh' = 1 - tanh^2).  Optimiser: Adam (Kingma & Ba 2015) with bias
 correction.
 
-The library's g adds this network's output to the cheap truncation
-q_c = sum_{j<=c} c_j mu_j as a skip connection, g = q_c + mu_0 (ybar + ysd out),
-so the network learns the standardised residual of the truncation; the tests
-rebuild that composite from ``forward`` and the oracle's moments.
+The library's g corrects the cheap truncation q_c = sum_{j<=c} c_j mu_j in
+two stages on the standardised residual t = ((q - q_c)/mu_0 - ybar)/ysd:
+inputs u_f = (mu_f/mu_0 - xmean_f)/xsd_f (f >= 1; ``standardize``), a
+linear least-squares fit beta of t on u (``linear_stage``; the linear
+control variate of Section 5.5), and the network on t - u.beta:
+    g = q_c + mu_0 (ybar + ysd (u.beta + out(u))).
+The tests rebuild that composite from these functions and the oracle's
+moments.
 
 Estimator (unbiased for any fixed g): with disjoint probe sets S0 (cheap
 degree, M0 probes) and S1 (fine degree, M1 probes), both disjoint from the
@@ -54,6 +58,43 @@ class Params:
         b2 = v[o:o + H]; o += H
         w3 = v[o:o + H]; o += H
         return Params(W1.copy(), b1.copy(), W2.copy(), b2.copy(), w3.copy(), float(v[o]))
+
+
+def standardize(Xraw: np.ndarray):
+    """Column means and unbiased standard deviations of the raw inputs
+    (rows = training probes); column 0 (mu_0 / mu_0 = 1) and constant
+    columns get standard deviation 0, which maps them to 0."""
+    Xraw = np.asarray(Xraw, dtype=np.float64)
+    mean = Xraw.mean(axis=0)
+    sd = Xraw.std(axis=0, ddof=1) if Xraw.shape[0] > 1 else np.zeros(Xraw.shape[1])
+    mean[0], sd[0] = 0.0, 0.0
+    sd = np.where(sd > 0.0, sd, 0.0)
+    return mean, sd
+
+
+def standardized(Xraw: np.ndarray, mean: np.ndarray, sd: np.ndarray) -> np.ndarray:
+    Xraw = np.asarray(Xraw, dtype=np.float64)
+    U = np.zeros_like(Xraw)
+    ok = sd > 0.0
+    U[:, ok] = (Xraw[:, ok] - mean[ok]) / sd[ok]
+    return U
+
+
+def linear_stage(U: np.ndarray, t: np.ndarray, ridge_rel: float = 1e-12) -> np.ndarray:
+    """beta minimising |t - U beta|^2 over the inputs f >= 1 (beta_0 = 0),
+    from the normal equations with a ridge of ridge_rel * trace / K on the
+    diagonal (K = number of inputs), which leaves well-posed fits unchanged
+    to rounding and makes constant (all-zero) inputs get beta = 0."""
+    U = np.asarray(U, dtype=np.float64)[:, 1:]
+    t = np.asarray(t, dtype=np.float64)
+    K = U.shape[1]
+    beta = np.zeros(K + 1)
+    if K == 0:
+        return beta
+    G = U.T @ U
+    G[np.diag_indices(K)] += ridge_rel * np.trace(G) / K + 1e-300
+    beta[1:] = np.linalg.solve(G, U.T @ t)
+    return beta
 
 
 def n_params(F: int, H: int) -> int:

@@ -1293,7 +1293,7 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
                          m_pilot < kDenseMaxBlock ? m_pilot : kDenseMaxBlock));
   const size_t sbytes = align8(m_pilot * 8) + align8(ntrain * F * 4) + align8(ntrain * 4) +
                         align8((size_t)kMlpWaves * P * 4) + align8(kMlpWaves * 4) +
-                        align8((size_t)epochs * 4) + 64 + align8(nval * 8) + 128 + 256;
+                        align8((size_t)epochs * 4) + align8(kMlpStats * 8) + align8(nval * 8) + 128 + 256;
   CHECK(ws_get(ctx, WS_MLP, sbytes, &scratch));
   Carver cv{static_cast<char*>(scratch)};
   double* q = cv.take<double>(m_pilot);
@@ -1302,7 +1302,7 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
   float* part = cv.take<float>((size_t)kMlpWaves * P);
   float* loss_part = cv.take<float>(kMlpWaves);
   float* loss_hist = cv.take<float>(epochs);
-  double* stats = cv.take<double>(4);
+  double* stats = cv.take<double>(kMlpStats);
   double* gval = cv.take<double>(nval > 0 ? nval : 1);
   double* comb = cv.take<double>(8);
 
@@ -1366,15 +1366,22 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
                             loss_part, (int)ntrain, loss_hist));
   }
   MLP_HIP(launch_mlp_to_bf16(s, m->theta, F, m->wbf16));
-  double hstats[2];
+  double hstats[kMlpStats];
   MLP_HIP(hipMemcpyAsync(hstats, stats, sizeof hstats, hipMemcpyDeviceToHost, s));
   MLP_TRY(sync_stream(ctx));
   m->ybar = hstats[0];
   m->ysd = hstats[1];
+  m->aff.ybar = hstats[0];
+  m->aff.ysd = hstats[1];
+  for (int f = 0; f < 16; ++f) {
+    m->aff.xmean[f] = hstats[2 + f];
+    m->aff.xsd[f] = hstats[2 + 16 + f];
+    m->aff.lin[f] = hstats[2 + 32 + f];
+  }
   // held-out pilot probes: variance of q and of q - g
   if (nval >= 2) {
     const double* muv = static_cast<double*>(mu) + ntrain * ldmu;
-    MLP_HIP(launch_mlp_infer(s, m->wbf16, F, m->coef, muv, ldmu, nval, m->ybar, m->ysd, gval));
+    MLP_HIP(launch_mlp_infer(s, m->wbf16, F, m->coef, muv, ldmu, nval, m->aff, gval));
     MLP_HIP(launch_mlp_combine(s, q + ntrain, nval, q + ntrain, gval, nval, comb));
     MLP_HIP(launch_mlp_combine(s, gval, nval, gval, nullptr, 0, comb + 4));
     double hc[8];
@@ -1432,8 +1439,8 @@ mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_m
     pr.m = M0u;
     CHECK(run_probe_set(ctx, op, alpha, beta, nc, MLCT_DOUBLING, m->prec, &pr,
                         static_cast<double*>(mu0), nc + 1));
-    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu0), nc + 1, M0u, m->ybar,
-                                 m->ysd, g0));
+    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu0), nc + 1, M0u,
+                                 m->aff, g0));
   }
   pr.first_id = M0u;
   pr.m = M1;
@@ -1441,8 +1448,8 @@ mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_m
                       static_cast<double*>(mu1), n + 1));
   HIPCHK(ctx, launch_qvals(s, static_cast<double*>(mu1), n + 1, m->coef, n, M1, q1));
   if (learned)
-    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu1), n + 1, M1, m->ybar,
-                                 m->ysd, g1));
+    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu1), n + 1, M1,
+                                 m->aff, g1));
   HIPCHK(ctx, launch_mlp_combine(s, g0, M0u, q1, learned ? g1 : nullptr, M1, comb));
   double hc[4];
   HIPCHK(ctx, hipMemcpyAsync(hc, comb, sizeof hc, hipMemcpyDeviceToHost, s));
@@ -1475,6 +1482,11 @@ mlct_status mlct_mlp_info_get(const mlct_mlp* m, mlct_mlp_info* out) {
   out->var_g = m->var_g;
   out->ybar = m->ybar;
   out->ysd = m->ysd;
+  for (int f = 0; f < 16; ++f) {
+    out->x_mean[f] = m->aff.xmean[f];
+    out->x_sd[f] = m->aff.xsd[f];
+    out->lin[f] = m->aff.lin[f];
+  }
   out->final_loss = m->loss_hist.empty() ? NAN : m->loss_hist.back();
   out->fallback = m->fallback;
   out->n_features = m->F;

@@ -43,6 +43,14 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// The affine parts of the learned level (k_mlp.hip): target standardisation,
+// input standardisation and the linear least-squares stage.
+constexpr int kMlpStats = 2 + 3 * 16;  // doubles written by the training-set kernel
+struct MlpAffine {
+  double ybar = 0.0, ysd = 1.0;
+  double xmean[16] = {}, xsd[16] = {}, lin[16] = {};
+};
+
 }  // namespace mlct
 
 struct mlct_timed_launch {
@@ -115,6 +123,7 @@ struct mlct_mlp {
   void* wbf16 = nullptr;   // bf16 inference weights (device)
   double* coef = nullptr;  // c_0..c_{n_fine} (device)
   double ybar = 0.0, ysd = 1.0;
+  mlct::MlpAffine aff;
   double var_q = 0.0, var_resid = 0.0, mean_resid = 0.0, var_g = 0.0;
   int fallback = 0;
   std::vector<float> loss_hist;
@@ -359,7 +368,7 @@ hipError_t launch_mlp_adam(hipStream_t s, float* theta, float* m, float* v, cons
                            float* loss_hist);
 hipError_t launch_mlp_to_bf16(hipStream_t s, const float* theta, int F, void* w);
 hipError_t launch_mlp_infer(hipStream_t s, const void* w, int F, const double* coef,
-                            const double* mu, int64_t ldmu, int64_t rows, double ybar, double ysd,
+                            const double* mu, int64_t ldmu, int64_t rows, const MlpAffine& aff,
                             double* g);
 hipError_t launch_qvals(hipStream_t s, const double* mu, int64_t ldmu, const double* c, int n,
                         int64_t rows, double* q);

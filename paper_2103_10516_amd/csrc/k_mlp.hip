@@ -1,9 +1,14 @@
 // Learned control-variate level: the cheap truncation of the fine-level
-// quadratic form plus an MLP correction, g = q_c + mu_0 (ybar + ysd * net(x)),
-// net(x) = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3 with 64 hidden units per
-// layer, x = the cheap moments of the probe (the control-variate
-// idea of Section 5.5 with a learned map, used as an extra multilevel term in
-// the sense of Section 2.3).
+// quadratic form plus a learned correction,
+//     g = q_c + mu_0 (ybar + ysd (beta . u + net(u))),
+// u = the probe's cheap moments mu_f / mu_0 (f = 1..F-1) standardised over
+// the training probes, beta the least-squares fit of the standardised
+// target on u (the linear control variate of Section 5.5), and
+// net(u) = w3 . tanh(W2 tanh(W1 u + b1) + b2) + b3 (64 hidden units per
+// layer) trained on what the linear fit leaves; used as an extra multilevel
+// term in the sense of Section 2.3.  Standardising matters: the moments of
+// different probes differ by ~1/sqrt(d) relative, far below bf16's
+// resolution, so raw inputs would be rounded to constants at inference.
 //
 // Training (FP32): one wavefront per slice of samples, lane = hidden unit.
 // Each lane keeps its row of W1, its row AND column of W2 in registers, so
@@ -171,8 +176,8 @@ __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 __global__ __launch_bounds__(64) void mlp_infer_kernel(const __bf16* __restrict__ w, int F,
                                                        const double* __restrict__ coef,
                                                        const double* __restrict__ mu,
-                                                       int64_t ldmu, int64_t rows, double ybar,
-                                                       double ysd, double* __restrict__ g) {
+                                                       int64_t ldmu, int64_t rows, MlpAffine aff,
+                                                       double* __restrict__ g) {
   const Off o(F);
   const int l = threadIdx.x;
   float w1[FMAX], w2r[H];
@@ -187,9 +192,15 @@ __global__ __launch_bounds__(64) void mlp_infer_kernel(const __bf16* __restrict_
     const double* r = mu + i * ldmu;
     const double inv0 = 1.0 / r[0];
     float a1 = b1;
+    double lin = 0.0;
 #pragma unroll
     for (int f = 0; f < FMAX; ++f)
-      if (f < F) a1 = fmaf(w1[f], bf((float)(r[f] * inv0)), a1);
+      if (f < F) {
+        const double sd = aff.xsd[f];
+        const double u = sd > 0.0 ? (r[f] * inv0 - aff.xmean[f]) / sd : 0.0;
+        lin += aff.lin[f] * u;
+        a1 = fmaf(w1[f], bf((float)u), a1);
+      }
     const float h1 = bf(tanhf(a1));
     float a2 = b2;
 #pragma unroll
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(64) void mlp_infer_kernel(const __bf16* __restrict_
     if (l == 0) {
       double qc = 0.0;
       for (int f = 0; f < F; ++f) qc += coef[f] * r[f];
-      g[i] = qc + r[0] * (ybar + ysd * (double)out);
+      g[i] = qc + r[0] * (aff.ybar + aff.ysd * (lin + (double)out));
     }
   }
 }
@@ -230,10 +241,14 @@ __device__ double rsum(double v, double* sh) {
   return r;
 }
 
-// Training set from the pilot: X = mu[0..F-1] / mu_0 (float) and the
-// standardised residual of the cheap truncation,
-// y = ((q - q_c) / mu_0 - ybar) / ysd, q_c = sum_{f<F} c_f mu_f, with ybar,
-// ysd over the training rows; stats[0..1] = ybar, ysd.  One workgroup,
+// Training set from the pilot.  Target t = ((q - q_c) / mu_0 - ybar) / ysd,
+// the standardised residual of the cheap truncation q_c = sum_{f<F} c_f mu_f;
+// inputs u_f = (mu_f / mu_0 - xmean_f) / xsd_f for f >= 1 (0 for f = 0 and
+// for constant features), means and unbiased standard deviations over the
+// training rows.  beta = argmin |t - U beta|^2 from the normal equations
+// (Cholesky, ridge 1e-12 trace / K), and y = t - U beta, what the network
+// learns.  X = u (float), y (float); stats: [0] ybar, [1] ysd, [2 + f]
+// xmean, [2 + FMAX + f] xsd, [2 + 2 FMAX + f] beta.  One workgroup, FP64,
 // fixed-order sums.
 __device__ __forceinline__ double resid_target(const double* r, double q, const double* c, int F) {
   double qc = 0.0;
@@ -249,25 +264,108 @@ __global__ __launch_bounds__(kRT) void mlp_prepare_kernel(const double* __restri
                                                           float* __restrict__ y,
                                                           double* __restrict__ stats) {
   __shared__ double sh[kRT];
+  __shared__ double xm[FMAX], xs[FMAX], beta[FMAX], G[FMAX][FMAX], rhs[FMAX];
+  const int tid = threadIdx.x;
+  const double den = ntrain > 1 ? ntrain - 1 : 1;
   double s = 0.0;
-  for (int i = threadIdx.x; i < ntrain; i += kRT)
-    s += resid_target(mu + (int64_t)i * ldmu, q[i], coef, F);
+  for (int i = tid; i < ntrain; i += kRT) s += resid_target(mu + (int64_t)i * ldmu, q[i], coef, F);
   const double mean = rsum(s, sh) / ntrain;
   double ss = 0.0;
-  for (int i = threadIdx.x; i < ntrain; i += kRT) {
+  for (int i = tid; i < ntrain; i += kRT) {
     const double t = resid_target(mu + (int64_t)i * ldmu, q[i], coef, F) - mean;
     ss += t * t;
   }
-  double sd = sqrt(rsum(ss, sh) / (ntrain > 1 ? ntrain - 1 : 1));
+  double sd = sqrt(rsum(ss, sh) / den);
   if (!(sd > 0.0)) sd = 1.0;
-  for (int i = threadIdx.x; i < ntrain; i += kRT) {
+  auto xf = [&](int i, int f) {
     const double* r = mu + (int64_t)i * ldmu;
-    for (int f = 0; f < F; ++f) X[(int64_t)i * F + f] = (float)(r[f] / r[0]);
-    y[i] = (float)((resid_target(r, q[i], coef, F) - mean) / sd);
+    return r[f] / r[0];
+  };
+  if (tid < FMAX) xm[tid] = xs[tid] = beta[tid] = 0.0;
+  __syncthreads();
+  for (int f = 1; f < F; ++f) {
+    double a = 0.0;
+    for (int i = tid; i < ntrain; i += kRT) a += xf(i, f);
+    const double m = rsum(a, sh) / ntrain;
+    double b = 0.0;
+    for (int i = tid; i < ntrain; i += kRT) {
+      const double e = xf(i, f) - m;
+      b += e * e;
+    }
+    const double v = sqrt(rsum(b, sh) / den);
+    if (tid == 0) {
+      xm[f] = m;
+      xs[f] = v > 0.0 ? v : 0.0;
+    }
+    __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  auto u = [&](int i, int f) { return xs[f] > 0.0 ? (xf(i, f) - xm[f]) / xs[f] : 0.0; };
+  auto tgt = [&](int i) {
+    return (resid_target(mu + (int64_t)i * ldmu, q[i], coef, F) - mean) / sd;
+  };
+  // normal equations over f = 1..F-1
+  const int K = F - 1;
+  for (int a = 1; a < F; ++a) {
+    for (int b = a; b < F; ++b) {
+      double acc = 0.0;
+      for (int i = tid; i < ntrain; i += kRT) acc += u(i, a) * u(i, b);
+      const double v = rsum(acc, sh);
+      if (tid == 0) G[a][b] = G[b][a] = v;
+    }
+    double acc = 0.0;
+    for (int i = tid; i < ntrain; i += kRT) acc += u(i, a) * tgt(i);
+    const double v = rsum(acc, sh);
+    if (tid == 0) rhs[a] = v;
+  }
+  __syncthreads();
+  if (tid == 0 && K > 0) {
+    double tr = 0.0;
+    for (int a = 1; a < F; ++a) tr += G[a][a];
+    const double ridge = 1e-12 * tr / K + 1e-300;
+    for (int a = 1; a < F; ++a) G[a][a] += ridge;
+    // Cholesky G = L L^T in place (lower triangle), then two triangular solves
+    for (int j = 1; j < F; ++j) {
+      double d = G[j][j];
+      for (int k = 1; k < j; ++k) d -= G[j][k] * G[j][k];
+      d = sqrt(d > 0.0 ? d : 1e-300);
+      G[j][j] = d;
+      for (int i = j + 1; i < F; ++i) {
+        double e = G[i][j];
+        for (int k = 1; k < j; ++k) e -= G[i][k] * G[j][k];
+        G[i][j] = e / d;
+      }
+    }
+    double z[FMAX];
+    for (int i = 1; i < F; ++i) {
+      double e = rhs[i];
+      for (int k = 1; k < i; ++k) e -= G[i][k] * z[k];
+      z[i] = e / G[i][i];
+    }
+    for (int i = F - 1; i >= 1; --i) {
+      double e = z[i];
+      for (int k = i + 1; k < F; ++k) e -= G[k][i] * beta[k];
+      beta[i] = e / G[i][i];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < ntrain; i += kRT) {
+    double lin = 0.0;
+    X[(int64_t)i * F] = 0.f;
+    for (int f = 1; f < F; ++f) {
+      const double uf = u(i, f);
+      X[(int64_t)i * F + f] = (float)uf;
+      lin += beta[f] * uf;
+    }
+    y[i] = (float)(tgt(i) - lin);
+  }
+  if (tid == 0) {
     stats[0] = mean;
     stats[1] = sd;
+  }
+  if (tid < FMAX) {
+    stats[2 + tid] = xm[tid];
+    stats[2 + FMAX + tid] = xs[tid];
+    stats[2 + 2 * FMAX + tid] = beta[tid];
   }
 }
 
@@ -358,11 +456,11 @@ hipError_t launch_mlp_to_bf16(hipStream_t s, const float* theta, int F, void* w)
 }
 
 hipError_t launch_mlp_infer(hipStream_t s, const void* w, int F, const double* coef,
-                            const double* mu, int64_t ldmu, int64_t rows, double ybar, double ysd,
+                            const double* mu, int64_t ldmu, int64_t rows, const MlpAffine& aff,
                             double* g) {
   if (rows <= 0) return hipSuccess;
   mlp_infer_kernel<<<(int)((rows + 63) / 64), 64, 0, s>>>(static_cast<const __bf16*>(w), F, coef,
-                                                          mu, ldmu, rows, ybar, ysd, g);
+                                                          mu, ldmu, rows, aff, g);
   return hipGetLastError();
 }
 

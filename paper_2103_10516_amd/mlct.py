@@ -323,7 +323,8 @@ class mlct_mlp_info(C.Structure):
                 ("var_g", C.c_double), ("ybar", C.c_double), ("ysd", C.c_double), ("final_loss", C.c_double),
                 ("fallback", C.c_int32), ("n_features", C.c_int32), ("n_cheap", C.c_int32),
                 ("n_fine", C.c_int32), ("ntrain", C.c_int64), ("nval", C.c_int64),
-                ("nparams", C.c_int64)]
+                ("nparams", C.c_int64), ("x_mean", C.c_double * 16), ("x_sd", C.c_double * 16),
+                ("lin", C.c_double * 16)]
 
 
 MLCT_FLAG_LEARNED_FALLBACK = 0x8
@@ -401,7 +402,8 @@ def mlct_mlp_info_get(mlp: Mlp) -> dict:
     st = _mlp_lib().mlct_mlp_info_get(mlp.handle, C.byref(i))
     if st != MLCT_OK:
         raise MlctError(st, "mlct_mlp_info_get failed")
-    return {k: getattr(i, k) for k, _ in mlct_mlp_info._fields_}
+    return {k: (np.array(getattr(i, k)) if k in ("x_mean", "x_sd", "lin") else getattr(i, k))
+            for k, _ in mlct_mlp_info._fields_}
 
 
 def mlct_mlp_loss_history(mlp: Mlp) -> np.ndarray:

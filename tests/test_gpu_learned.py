@@ -62,14 +62,15 @@ def test_training_gradient_matches_oracle(ctx):
 
 @pytest.fixture(scope="module")
 def lap3d_fit(ctx):
-    """3D Laplacian 24^3 + 0.01 I, log, fine degree 64, cheap degree 8."""
+    """3D Laplacian 24^3 + 0.01 I, log, fine degree 64, cheap degree 8 (FP64
+    pilot, so that the affine stages can be compared with the oracle's)."""
     from paper_2103_10516_amd import mlct
 
     n = 24
     g = wl.laplacian_3d(n)
     op = _csr_op(ctx, g)
     net = mlct.mlct_learned_fit(ctx, op, mlct.MLCT_LOG, 0.01, 12.01, n_fine=64, n_cheap=8,
-                                m_pilot=1024, seed=11, epochs=1500)
+                                m_pilot=1024, seed=11, epochs=1500, prec=mlct.MLCT_FP64)
     return n, g, op, net
 
 
@@ -115,10 +116,37 @@ def _bf16(x):
     return a.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def test_affine_stages_match_oracle(ctx, lap3d_fit):
+    """Target standardisation, input standardisation and the linear
+    least-squares stage, recomputed by the oracle from its own moments of the
+    training probes."""
+    from paper_2103_10516_amd import mlct
+
+    n, g, op, net = lap3d_fit
+    info = mlct.mlct_mlp_info_get(net)
+    ids = np.arange(info["ntrain"])
+    Z = probes.rademacher(g.d, ids, 11).T
+    alpha, beta = cheb.affine_map(0.01, 12.01)
+    mu = moments.moments_doubling(g.to_scipy(), Z, alpha, beta, 64)
+    c, _ = cheb.coefficients(cheb.LOG, 0.01, 12.01, 64)
+    r = (mu @ c - mu[:, :9] @ c[:9]) / mu[:, 0]
+    ybar, ysd = r.mean(), r.std(ddof=1)
+    assert info["ybar"] == pytest.approx(ybar, rel=1e-9, abs=1e-12 * abs(ysd))
+    assert info["ysd"] == pytest.approx(ysd, rel=1e-8)
+    Xraw = mu[:, :9] / mu[:, :1]
+    xm, xs = omlp.standardize(Xraw)
+    np.testing.assert_allclose(info["x_mean"][:9], xm, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(info["x_sd"][:9], xs, rtol=1e-8, atol=1e-15)
+    want = omlp.linear_stage(omlp.standardized(Xraw, xm, xs), (r - ybar) / ysd)
+    print("beta", np.round(info["lin"][:9], 4))
+    np.testing.assert_allclose(info["lin"][:9], want, rtol=1e-6, atol=1e-8 * np.max(np.abs(want)))
+    assert np.all(info["lin"][9:] == 0.0)
+
+
 def test_inference_matches_oracle_forward(ctx, lap3d_fit):
     """The held-out statistics the library reports are recomputed here from
-    the oracle's moments and an FP64 forward pass with bf16-rounded weights,
-    inputs and hidden activations."""
+    the oracle's moments: standardised inputs, the linear stage, and an FP64
+    forward pass with bf16-rounded weights, inputs and hidden activations."""
     from paper_2103_10516_amd import mlct
 
     n, g, op, net = lap3d_fit
@@ -131,12 +159,14 @@ def test_inference_matches_oracle_forward(ctx, lap3d_fit):
     mu = moments.moments_doubling(g.to_scipy(), Z, alpha, beta, 64)
     c, _ = cheb.coefficients(cheb.LOG, 0.01, 12.01, 64)
     q = mu @ c
-    x = _bf16(mu[:, :9] / mu[:, :1])
+    u = omlp.standardized(mu[:, :9] / mu[:, :1], info["x_mean"][:9], info["x_sd"][:9])
+    lin = u @ info["lin"][:9]
+    x = _bf16(u)
     h1 = _bf16(np.tanh(x @ P.W1.T + P.b1))
     h2 = _bf16(np.tanh(h1 @ P.W2.T + P.b2))
     out = h2 @ P.w3 + P.b3
     qc = mu[:, :9] @ c[:9]  # the cheap truncation the network corrects
-    gv = qc + mu[:, 0] * (info["ybar"] + info["ysd"] * out)
+    gv = qc + mu[:, 0] * (info["ybar"] + info["ysd"] * (lin + out))
     var_q = np.var(q, ddof=1)
     var_r = np.var(q - gv, ddof=1)
     assert info["var_q"] == pytest.approx(var_q, rel=1e-3)

@@ -92,3 +92,30 @@ def test_learned_estimator_perfect_predictor_has_no_correction_variance():
     val, var = mlp.learned_estimate(np.array([2.0, 2.5, 1.5, 2.0]), q1, q1.copy())
     assert val == pytest.approx(2.0)
     assert var == pytest.approx(np.var([2.0, 2.5, 1.5, 2.0], ddof=1) / 4)
+
+
+def test_linear_stage_recovers_exact_coefficients():
+    """Noiseless targets t = U beta: the normal-equation solve returns beta."""
+    rng = np.random.default_rng(3)
+    Xraw = np.c_[np.ones(500), rng.normal(0.3, 1e-3, (500, 8))]
+    mean, sd = mlp.standardize(Xraw)
+    U = mlp.standardized(Xraw, mean, sd)
+    beta = np.r_[0.0, rng.normal(size=8)]
+    got = mlp.linear_stage(U, U @ beta)
+    np.testing.assert_allclose(got, beta, rtol=1e-9, atol=1e-11)
+
+
+def test_linear_stage_matches_lstsq_and_standardisation():
+    rng = np.random.default_rng(4)
+    Xraw = np.c_[np.ones(300), rng.normal(size=(300, 6)), np.full(300, 2.5)]
+    mean, sd = mlp.standardize(Xraw)
+    U = mlp.standardized(Xraw, mean, sd)
+    # standardised columns: mean 0, unbiased sd 1; constant columns (incl. 0) map to 0
+    np.testing.assert_allclose(U[:, 1:7].mean(axis=0), 0.0, atol=1e-13)
+    np.testing.assert_allclose(U[:, 1:7].std(axis=0, ddof=1), 1.0, rtol=1e-12)
+    assert np.all(U[:, 0] == 0.0) and np.all(U[:, 7] == 0.0) and sd[7] == 0.0
+    t = rng.normal(size=300) + U @ np.r_[0.0, rng.normal(size=7)]
+    got = mlp.linear_stage(U, t)
+    want = np.linalg.lstsq(U[:, 1:7], t, rcond=None)[0]
+    np.testing.assert_allclose(got[1:7], want, rtol=1e-8, atol=1e-12)
+    assert got[0] == 0.0 and got[7] == 0.0
