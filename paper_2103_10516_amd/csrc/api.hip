@@ -507,7 +507,8 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
   CHECK(ws_get(ctx, WS_V1, (size_t)bpad * op->d * tsz, &tmp));
   CHECK(ws_get(ctx, WS_PART, (size_t)2 * ntiles * bpad * (S + 1) * sizeof(double), &tmp));
   CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * bpad * sizeof(double), &tmp));
-  if (prec == MLCT_BF16X3 && dense_tile(prec, op->d, op->d, bpad, op->tuned_dense).skinny)
+  const DenseTile tb = dense_tile(prec, op->d, op->d, bpad, op->tuned_dense);
+  if (prec == MLCT_BF16X3 && (tb.skinny || tb.bm == 128))
     CHECK(ws_get(ctx, WS_DPACK, 4 * dense_pack_bytes(bpad, op->d), &tmp));
   return MLCT_OK;
 }
@@ -535,10 +536,11 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
   const size_t pstep = (size_t)2 * ntiles * bpad;
   hipStream_t s = ctx->stream;
   HIPCHK(ctx, launch_dense_probe_init(s, prec, buf[0], d, bpad, src, D));
-  // BF16X3 skinny blocks read A and V_k packed; two packed V blocks alternate
+  // BF16X3 skinny and 128-wide blocks read A and V_k packed; two packed V
+  // blocks alternate
   // (V_0 packed here, V_new packed by each step's epilogue; their padding
   // stays zero)
-  const bool packed = prec == MLCT_BF16X3 && t.skinny;
+  const bool packed = prec == MLCT_BF16X3 && (t.skinny || t.bm == 128);
   const void *pa_hi = nullptr, *pa_lo = nullptr;
   char* vpk[4] = {nullptr, nullptr, nullptr, nullptr};  // (hi, lo) of blocks 0 and 1
   if (packed) {

@@ -303,7 +303,7 @@ struct DenseStepArgs {
   ProbeSrc src;
   double* part;  // [2][ntiles][bpad] for this step
   int tile_force;  // see dense_tile
-  // BF16X3 skinny blocks: A and V_k packed in the MFMA lane layout
+  // BF16X3 skinny and 128 x 128 blocks: A and V_k packed in the MFMA lane layout
   // (launch_dense_pack_*), V_new packed by the epilogue; null = unpacked
   const void* pk_a_hi = nullptr;
   const void* pk_a_lo = nullptr;

@@ -310,6 +310,179 @@ __global__ __launch_bounds__(64 * WM * WN) void dense_step_kernel(
   }
 }
 
+// Wide BF16x3 blocks (a multiple of 128 probes) on packed operands: a
+// workgroup owns 128 probes x 128 matrix rows, its four waves 64 x 64 each
+// (4 x 4 MFMA tiles, one accumulator per tile, hi*hi + hi*lo + lo*hi).  Each
+// k block of 32 columns is staged in LDS exactly in the packed lane layout
+// (8 V tiles and 8 A tiles, hi and lo, 1 KB each), so the stage is a
+// contiguous 32 KB copy and every operand read is one conflict-free 16-byte
+// LDS load per lane.  Two LDS stages and two register sets: block k + 2
+// streams from global memory into registers while block k is on the matrix
+// cores, and block k + 1 (already in registers) goes into the other stage;
+// one barrier per block.  The 48 MFMAs of a block are issued product by
+// product (all hi*hi, then hi*lo, then lo*hi) so that consecutive ones are
+// independent.  Epilogue as in dense_step_kernel, plus the packed V_new for
+// the next step.
+template <int ZMODE, bool HAS_PREV>
+__global__ __launch_bounds__(256) void dense_pk_gemm_kernel(
+    int64_t d, const float* __restrict__ vk, float* __restrict__ vm, float ca, float cb,
+    ProbeSrc src, int mtiles, int ntiles, double* __restrict__ part, PackedOps pk) {
+  constexpr int BM = 128, BN = 128, TM = 4, TN = 4, WN = 2;
+  // stage layout: [which (0 V, 1 A)][part (0 hi, 1 lo)][tile 0..7][lane] of bf8
+  __shared__ bf8 st[2][2][2][8][64];
+  __shared__ double sred[WN][2][BM];
+  const int total = mtiles * ntiles;
+  const int L = xcd_band(blockIdx.x, (total + 7) / 8 * 8);
+  if (L >= total) return;
+  const int mt = L % mtiles, nt = L / mtiles;
+  const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t KB = pk_kblocks(d);
+  // this thread's 8 pieces of a stage: piece e = tid + 256 u, decoded as
+  // (which, part, tile, lane) in the order of the stage layout
+  const bf8* src_of[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int e = tid + 256 * u;
+    const int l = e & 63, t = (e >> 6) & 7, prt = (e >> 9) & 1, which = e >> 10;
+    const bf8* base = which == 0 ? (prt ? pk.v_lo : pk.v_hi) : (prt ? pk.a_lo : pk.a_hi);
+    const int64_t tile = which == 0 ? m0 / 16 + t : n0 / 16 + t;
+    src_of[u] = base + tile * KB * 64 + l;
+  }
+  bf8 ra[8];
+  auto fetch = [&](int64_t kb, bf8 (&rg)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rg[u] = src_of[u][kb * 64];
+  };
+  auto stash = [&](int s, const bf8 (&rg)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      (&st[s][0][0][0][0])[e] = rg[u];
+    }
+  };
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  auto block = [&](int s) {
+    bf8 vh[TM], vl[TM], ah[TN], al[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      vh[a] = st[s][0][0][wm * TM + a][lane];
+      vl[a] = st[s][0][1][wm * TM + a][lane];
+    }
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      ah[b] = st[s][1][0][wn * TN + b][lane];
+      al[b] = st[s][1][1][wn * TN + b][lane];
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[a], ah[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[a], al[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl[a], ah[b], acc[a][b], 0, 0, 0);
+  };
+  fetch(0, ra);
+  stash(0, ra);
+  __syncthreads();
+  for (int64_t kb = 0; kb < KB; ++kb) {
+    const int s = (int)(kb & 1);
+    if (kb + 1 < KB) fetch(kb + 1, ra);
+    block(s);
+    if (kb + 1 < KB) stash(s ^ 1, ra);
+    __syncthreads();
+  }
+
+  // ---- epilogue: recurrence in place, packed V_new, moment partials -------
+  double p1[TM][4], p2[TM][4];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p1[a][r] = p2[a][r] = 0.0;
+#pragma unroll
+  for (int a = 0; a < TM; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = m0 + wm * TM * 16 + a * 16 + acc_row<2>(lane, r);
+      const bool jact = j < src.active;
+      uint64_t key = 0;
+      if (ZMODE == 1) key = sm_output(src.seed, (uint64_t)(src.first_id + j));
+      int64_t cached = -1;
+      uint64_t word = 0;
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int64_t n = n0 + wn * TN * 16 + b * 16 + (lane & 15);
+        if (n >= d) continue;
+        const int64_t idx = j * d + n;
+        const float xk = vk[idx];
+        float vn = ca * acc[a][b][r] + cb * xk;
+        if (HAS_PREV) vn -= vm[idx];
+        vm[idx] = vn;
+        __bf16 h, lo;
+        split_bf16(vn, h, lo);
+        const int64_t q = pk_index(j, n, KB);
+        pk.o_hi[q] = h;
+        pk.o_lo[q] = lo;
+        if (ZMODE == 0) {
+          p1[a][r] += (double)xk * (double)vn;
+          p2[a][r] += (double)vn * (double)vn;
+        } else if (ZMODE == 1) {
+          const int64_t c = n >> 6;
+          if (c != cached) {
+            word = sm_output(key, (uint64_t)c);
+            cached = c;
+          }
+          p1[a][r] += sign_from_word<double>(word, n) * (double)vn;
+        } else {
+          const double z = jact ? (double)src.entries[n * src.ld + src.first_id + j] : 0.0;
+          p1[a][r] += z * (double)vn;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        p1[a][r] += __shfl_xor(p1[a][r], o, 64);
+        p2[a][r] += __shfl_xor(p2[a][r], o, 64);
+      }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jl = wm * TM * 16 + a * 16 + acc_row<2>(lane, r);
+        sred[wn][0][jl] = p1[a][r];
+        sred[wn][1][jl] = p2[a][r];
+      }
+  }
+  __syncthreads();
+  for (int e = tid; e < 2 * BM; e += 256) {
+    const int slot = e / BM, jl = e % BM;
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < WN; ++w) sum += sred[w][slot][jl];
+    part[((int64_t)slot * ntiles + nt) * ((int64_t)mtiles * BM) + m0 + jl] = sum;
+  }
+}
+
 // Skinny blocks (32 or 64 probes per tile).  A block-square tile would give
 // a few hundred single-wave workgroups that each walk the whole k range with
 // one load in flight, so the step would be latency-bound.  Here a workgroup
@@ -628,16 +801,16 @@ __global__ __launch_bounds__(256) void dense_probe_init_kernel(VT* __restrict__ 
 
 // A_hi = bf16(A), A_lo = bf16(A - A_hi), from FP32 or FP64 A (row-major).
 // Pack rows x d values (row stride ld; FP32 split into bf16 hi / lo, or
-// bf16 hi and lo given apart) into the skinny kernel's lane layout, zero
-// past the rows and columns (all of ceil(rows / 16) * 16 x ceil(d / 32) * 32).
+// bf16 hi and lo given apart) into the packed lane layout, zero past the
+// rows and columns (all of rp x ceil(d / 32) * 32, rp a multiple of 16).
 template <typename ST>
 __global__ __launch_bounds__(256) void pack_kernel(const ST* __restrict__ hi_or_val,
                                                    const ST* __restrict__ lo, int64_t rows,
-                                                   int64_t d, int64_t ld,
+                                                   int64_t rp, int64_t d, int64_t ld,
                                                    __bf16* __restrict__ out_hi,
                                                    __bf16* __restrict__ out_lo) {
   const int64_t KB = pk_kblocks(d);
-  const int64_t rp = (rows + 15) / 16 * 16, cols = KB * 32;
+  const int64_t cols = KB * 32;
   const int64_t total = rp * cols;
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * 256) {
@@ -807,6 +980,32 @@ hipError_t launch_skinny_cfg(hipStream_t s, const DenseStepArgs& a) {
   return hipGetLastError();
 }
 
+// The packed wide kernel for BF16x3 blocks of 128-probe tiles.
+hipError_t launch_pk_gemm(hipStream_t s, const DenseStepArgs& a) {
+  const int mtiles = (int)(a.bpad / 128), ntiles = (int)((a.d + 127) / 128);
+  const int grid = (mtiles * ntiles + 7) / 8 * 8;
+  const PackedOps pk{static_cast<const bf8*>(a.pk_a_hi), static_cast<const bf8*>(a.pk_a_lo),
+                     static_cast<const bf8*>(a.pk_v_hi), static_cast<const bf8*>(a.pk_v_lo),
+                     static_cast<__bf16*>(a.pk_o_hi), static_cast<__bf16*>(a.pk_o_lo)};
+  const float* vk = static_cast<const float*>(a.vk);
+  float* vm = static_cast<float*>(a.vm);
+  const float ca = (float)a.ca, cb = (float)a.cb;
+#define MLCT_PKG(Z, HP)                                                                    \
+  dense_pk_gemm_kernel<Z, HP><<<grid, 256, 0, s>>>(a.d, vk, vm, ca, cb, a.src, mtiles, ntiles, \
+                                                   a.part, pk)
+  if (a.has_prev) {
+    if (a.zmode == 0) MLCT_PKG(0, true);
+    else if (a.zmode == 1) MLCT_PKG(1, true);
+    else MLCT_PKG(2, true);
+  } else {
+    if (a.zmode == 0) MLCT_PKG(0, false);
+    else if (a.zmode == 1) MLCT_PKG(1, false);
+    else MLCT_PKG(2, false);
+  }
+#undef MLCT_PKG
+  return hipGetLastError();
+}
+
 }  // namespace
 
 DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) {
@@ -866,7 +1065,10 @@ hipError_t launch_dense_step(hipStream_t s, int prec, const DenseStepArgs& a) {
     if (t.bm == 64) return launch_dense_cfg<1, 2, 2, 2, 2, 16>(s, a);
     return launch_dense_cfg<1, 1, 1, 2, 2, 16>(s, a);
   }
-  if (t.bm == 128) return launch_dense_cfg<2, 2, 2, 4, 4, 64>(s, a);
+  if (t.bm == 128) {
+    if (a.pk_a_hi) return launch_pk_gemm(s, a);
+    return launch_dense_cfg<2, 2, 2, 4, 4, 64>(s, a);
+  }
   if (t.bm == 64) return launch_dense_cfg<2, 2, 2, 2, 2, 64>(s, a);
   return launch_dense_cfg<2, 1, 1, 2, 2, 32>(s, a);
 }
@@ -891,14 +1093,17 @@ hipError_t launch_dense_split(hipStream_t s, const void* a, int dtype, int64_t d
   return hipGetLastError();
 }
 
+// Packed rows are padded to a multiple of 128 (the wide kernel's tile).
+static int64_t pk_rows(int64_t rows) { return (rows + 127) / 128 * 128; }
+
 size_t dense_pack_bytes(int64_t rows, int64_t d) {
-  return (size_t)((rows + 15) / 16) * (size_t)pk_kblocks(d) * 64 * 8 * sizeof(__bf16);
+  return (size_t)(pk_rows(rows) / 16) * (size_t)pk_kblocks(d) * 64 * 8 * sizeof(__bf16);
 }
 
 hipError_t launch_dense_pack_a(hipStream_t s, const void* hi, const void* lo, int64_t d,
                                void* out_hi, void* out_lo) {
   pack_kernel<__bf16><<<2048, 256, 0, s>>>(static_cast<const __bf16*>(hi),
-                                           static_cast<const __bf16*>(lo), d, d, d,
+                                           static_cast<const __bf16*>(lo), d, pk_rows(d), d, d,
                                            static_cast<__bf16*>(out_hi),
                                            static_cast<__bf16*>(out_lo));
   return hipGetLastError();
@@ -906,7 +1111,8 @@ hipError_t launch_dense_pack_a(hipStream_t s, const void* hi, const void* lo, in
 
 hipError_t launch_dense_pack_v(hipStream_t s, const float* v, int64_t rows, int64_t d,
                                void* out_hi, void* out_lo) {
-  pack_kernel<float><<<512, 256, 0, s>>>(v, nullptr, rows, d, d, static_cast<__bf16*>(out_hi),
+  pack_kernel<float><<<512, 256, 0, s>>>(v, nullptr, rows, pk_rows(rows), d, d,
+                                         static_cast<__bf16*>(out_hi),
                                          static_cast<__bf16*>(out_lo));
   return hipGetLastError();
 }

@@ -90,6 +90,31 @@ def test_dense_moments_match_oracle(ctx, prec, mode, d, m):
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-10 * d)
 
 
+@pytest.mark.parametrize("mode", ["direct", "doubling"])
+@pytest.mark.parametrize("d,m", [(2048, 2048), (2000, 2048)])
+def test_dense_bf16x3_wide_blocks(ctx, mode, d, m):
+    """Blocks wide enough for 128 x 128 tiles at BF16x3 (the packed wide
+    kernel; d = 2000 leaves a ragged row tile and a ragged k block): 12
+    probes spread over the block against the oracle."""
+    from paper_2103_10516_amd import mlct
+
+    A, lam = wl.random_symmetric(d, 29, -1.0, 2.0)
+    a, b, n, seed = -1.2, 2.2, 13, 5
+    op = _dense(ctx, A, np.float32)
+    M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    got = mlct.mlct_moments(ctx, op, a, b, n, mlct.rademacher_probes(seed, m), mlct.MLCT_BF16X3, M)
+    sel = np.r_[0:4, m // 2:m // 2 + 4, m - 4:m]
+    alpha, beta = cheb.affine_map(a, b)
+    Aop = A.astype(np.float32).astype(np.float64)
+    Z = probes.rademacher(d, sel, seed).T
+    want = moments.moments_direct(Aop, Z, alpha, beta, n)
+    kappa = float(np.max(np.abs(alpha * Aop + beta * np.eye(d)).sum(axis=1)))
+    tol = moment_tol(n, d, U_BF16X3, d, kappa)
+    worst = float(np.max(np.abs(got[sel] - want) / tol[None, :]))
+    print(f"wide bf16x3 {mode} d={d} m={m}: worst err/tol {worst:.3g}")
+    assert worst <= 1.0
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_dense_explicit_probes_skinny(ctx, prec):
     """Explicit probe columns (40 of a 256-column Rademacher matrix, offset
