@@ -254,3 +254,36 @@ def test_error_paths(ctx, torch_dev):
     ctx2.close()
     r = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, 0.01, 8.01, [3, 10], [1, 5], 1)
     assert r["flags"] & mlct.MLCT_FLAG_FEW_SAMPLES and math.isnan(r["est_var"])
+
+
+def test_realized_rms_matches_requested_accuracy(ctx, torch_dev):
+    """The allocation of eqs. eqn:optSamples / eqn:optMu, fed by pilot level
+    variances, delivers the requested accuracy: over R = 60 independent
+    repetitions the realized RMS error against tr p_n (closed-form spectrum)
+    is eps to within the sampling spread of an RMS over 60 draws."""
+    from paper_2103_10516_amd import mlct
+
+    n2 = 48
+    g = wl.laplacian_2d(n2)
+    a, b, deg = 0.01, 8.01, [8, 32]
+    op = _op(ctx, torch_dev, g)
+    c, _ = cheb.coefficients(cheb.LOG, a, b, deg[-1])
+    truth = cheb.trace_poly(c, wl.laplacian_2d_eigs(n2), a, b)
+    pil = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, deg, [400, 400], 7, mlct.MLCT_FP32,
+                             mlct.MLCT_DOUBLING)
+    eps = 2e-4 * abs(truth)
+    cost = [(k + 1) // 2 for k in deg]
+    V = list(pil["level_var"])
+    mk, _ = estimator.optimal_samples(V, cost, eps)
+    m = [max(2, math.ceil(x)) for x in mk]
+    errs = []
+    for rep in range(60):
+        r = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, deg, m, 1000 + rep,
+                               mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
+        errs.append(r["value"] - truth)
+    rms = math.sqrt(np.mean(np.square(errs)))
+    print(f"m = {m}: realized RMS / eps = {rms / eps:.3f}, mean error / eps = "
+          f"{np.mean(errs) / eps:.3f}")
+    # an RMS over 60 draws has a relative spread of about 1/sqrt(120) = 9 %
+    assert 0.65 < rms / eps < 1.35
+    assert abs(np.mean(errs)) < 4 * eps / math.sqrt(60)
