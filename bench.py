@@ -381,6 +381,81 @@ def extra_time_to_eps_dense(mlct, dev):
     return out
 
 
+def extra_learned_batch(mlct, dev):
+    """The learned level on the batch of 32 shifted 3D Laplacians
+    n_i = round(32 * 4^(i/31)) (d = 32^3 .. 128^3, + 0.01 I, [0.01, 12.01]),
+    f = log and sqrt, n = 256, cheap degree 8, MLP trained on 2,048 pilot
+    probes per matrix: summed over the batch, the time to a relative standard
+    error eps of each tr p_256 for plain, 2-level MLMC (8 | 256) and the
+    learned level, sample sizes from pilot variances by the optimal
+    allocation.  Fits and pilots are timed apart.  Not in the default run
+    (about two minutes)."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    a, b, n, nc = 0.01, 12.01, 256, 8
+    eps_list = (1e-3, 1e-4, 1e-5)
+    Cc, Cf = (nc + 1) // 2, (n + 1) // 2
+    ctx = mlct.mlct_create(0)
+    out = {"workload": "32 shifted 3D Laplacians n=32..128 (d=32^3..128^3) + 0.01 I, "
+                       "[0.01,12.01], n=256, cheap 8, MLP 9-64-64-1, 2048 pilot probes each",
+           "sizes": wl.laplacian_3d_batch_sizes()}
+
+    def timed(fn):
+        _sync()
+        t = time.perf_counter()
+        r = fn()
+        _sync()
+        return time.perf_counter() - t, r
+
+    for fname, kind in (("log", mlct.MLCT_LOG), ("sqrt", mlct.MLCT_SQRT)):
+        tot = {eps: {"plain": 0.0, "mlmc": 0.0, "learned": 0.0} for eps in eps_list}
+        fit_s = pilot_s = 0.0
+        ratios = []
+        for i, n3 in enumerate(wl.laplacian_3d_batch_sizes()):
+            g = wl.laplacian_3d(n3)
+            op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev),
+                                  torch.from_numpy(g.col).to(dev),
+                                  torch.from_numpy(g.val).to(dev))
+            tf, net = timed(lambda: mlct.mlct_learned_fit(ctx, op, kind, a, b, n_fine=n,
+                                                          n_cheap=nc, m_pilot=2048, seed=1000 + i,
+                                                          epochs=1500))
+            info = mlct.mlct_mlp_info_get(net)
+            tp, pil = timed(lambda: mlct.mlct_estimate(ctx, op, kind, a, b, [nc, n], [256, 256],
+                                                       100 + i, mlct.MLCT_FP32,
+                                                       mlct.MLCT_DOUBLING))
+            fit_s += tf
+            pilot_s += tp
+            T = abs(pil["value"])
+            ratios.append({"n": n3, "var_q": info["var_q"], "mlmc_var1": pil["level_var"][1],
+                           "learned_resid": info["var_resid"], "fallback": info["fallback"]})
+            for eps in eps_list:
+                tgt = (eps * T) ** 2
+                m_plain = max(2, math.ceil(info["var_q"] / tgt))
+                V = list(pil["level_var"])
+                s_ml = sum(math.sqrt(v * c) for v, c in zip(V, (Cc, Cf)))
+                m_ml = [max(2, math.ceil(s_ml * math.sqrt(v / c) / tgt)) for v, c in zip(V, (Cc, Cf))]
+                Vl = [info["var_g"], info["var_resid"]]
+                s_l = sum(math.sqrt(v * c) for v, c in zip(Vl, (Cc, Cf)))
+                m_l = [max(2, math.ceil(s_l * math.sqrt(v / c) / tgt)) for v, c in zip(Vl, (Cc, Cf))]
+                tot[eps]["plain"] += timed(lambda: mlct.mlct_estimate(
+                    ctx, op, kind, a, b, [n], [m_plain], 11, mlct.MLCT_FP32,
+                    mlct.MLCT_DOUBLING))[0]
+                tot[eps]["mlmc"] += timed(lambda: mlct.mlct_estimate(
+                    ctx, op, kind, a, b, [nc, n], m_ml, 12, mlct.MLCT_FP32,
+                    mlct.MLCT_DOUBLING))[0]
+                tot[eps]["learned"] += timed(lambda: mlct.mlct_estimate_learned(
+                    ctx, op, net, m_l[0], m_l[1], 13))[0]
+            net.close()
+            op.close()
+            print(f"# learned batch {fname}: n={n3} done", file=sys.stderr, flush=True)
+        out[fname] = {"fit_s": fit_s, "pilot_s": pilot_s,
+                      "time_s": {str(e): v for e, v in tot.items()}, "per_matrix": ratios}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -477,7 +552,7 @@ def main():
     ctx.close()
     extras = {"dense": extra_nuclear_dense, "triangles": extra_triangles,
               "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps,
-              "time_to_eps_dense": extra_time_to_eps_dense}
+              "time_to_eps_dense": extra_time_to_eps_dense, "learned_batch": extra_learned_batch}
     secondary = {}
     for name in [e for e in args.extras.split(",") if e]:
         print(f"# secondary measurement: {name}", file=sys.stderr, flush=True)
