@@ -166,7 +166,9 @@ def extra_triangles(mlct, dev):
     _sync()
     dt = time.perf_counter() - t0
     n, ms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_TRI_STEP)
-    by = 4 * g.nnz + 4 * (g.d + 1) + 8 * g.d * 64  # matrix, read block, write/reuse
+    # pass 1 reads the pattern and z, writes y; pass 2 reads the pattern and
+    # y, writes nothing: the average of the two per launch
+    by = 4 * g.nnz + 4 * (g.d + 1) + 6 * g.d * 64
     ach = by / (ms / n / 1e3) / 1e9
     out = {"workload": f"triangles, Chung-Lu d=1e6 nnz={g.nnz}, 1024 probes, int32/int64",
            "probe_matvecs_per_s": 2 * 1024 / dt, "ms": dt * 1e3, "estimate": res["estimate"],
@@ -456,6 +458,116 @@ def extra_learned_batch(mlct, dev):
     return out
 
 
+def sparse_x(rows: int, cols: int, per_row: int, seed: int):
+    """Rectangular sparse X with per_row entries in every row, one in each
+    of per_row equal column bands (so distinct and sorted), N(0, 1) values;
+    a seeded stand-in for the paper's sparse rectangular nuclear-norm
+    matrices."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    band = cols // per_row
+    col = (rng.integers(0, band, size=(rows, per_row), dtype=np.int64)
+           + band * np.arange(per_row)).astype(np.int32).ravel()
+    val = rng.standard_normal(rows * per_row).astype(np.float32)
+    rowptr = (np.arange(rows + 1, dtype=np.int64) * per_row).astype(np.int32)
+    return rowptr, col, val
+
+
+def extra_gram_csr(mlct, dev):
+    """Matrix-free sparse Gram operator: tr sqrt(X^T X) for X sparse
+    4,194,304 x 2,097,152 with 8 entries per row (nnz = 33.5M), FP32, one
+    level n = 64, 256 probes, doubling; HBM roofline of the two-product step
+    (W = X V_k, then the recurrence over X^T W)."""
+    import torch
+
+    R, Cn, k = 1 << 22, 1 << 21, 8
+    rp, cl, vl = sparse_x(R, Cn, k, seed=17)
+    nnz = cl.size
+    ctx = mlct.mlct_create(0)
+    op = mlct.mlct_op_gram_csr(ctx, torch.from_numpy(rp).to(dev), torch.from_numpy(cl).to(dev),
+                               torch.from_numpy(vl).to(dev), Cn, 0.0)
+    lo, hi = mlct.mlct_bounds(ctx, op, 30, 3)
+    a, b = max(lo, 1e-3), hi
+    n, m, width = 64, 256, 64
+
+    def run(seed):
+        return mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, [n], [m], seed, mlct.MLCT_FP32,
+                                  mlct.MLCT_DOUBLING)
+
+    run(1)
+    mlct.mlct_timing(ctx, True)
+    _sync()
+    t0 = time.perf_counter()
+    r = run(2)
+    _sync()
+    dt = time.perf_counter() - t0
+    mlct.mlct_timing(ctx, False)
+    launches, ms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_GRAM_CSR_STEP)
+    blocks = m // width
+    # product 1: X (rowptr, col, val), V_k gathered, W written; product 2: X^T,
+    # W gathered, V_k, V_{k-1} (not on a block's first step), V_{k+1} written
+    vec = 4 * width
+    by_full = (2 * (8 * nnz) + 4 * (R + 1) + 4 * (Cn + 1)
+               + vec * (Cn + R) + vec * (R + 3 * Cn))
+    by = by_full - vec * Cn * blocks / launches
+    ach = by / (ms / launches / 1e3) / 1e9
+    out = {"workload": f"tr sqrt(X^T X), X sparse {R}x{Cn}, {k} per row (nnz={nnz}), FP32, "
+                       f"[a,b]=[{a:.4g},{hi:.4g}] from Lanczos, n={n}, {m} probes, doubling",
+           "ms": dt * 1e3, "probe_matvecs_per_s": r["matvecs"] / dt, "estimate": r["estimate"],
+           "roofline": {"bound": "hbm", "kernel": "gram_pass1_kernel + gram_pass2_kernel",
+                        "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by,
+                        "avg_launch_ms": ms / launches, "launches": launches}}
+    op.close()
+    ctx.close()
+    return out
+
+
+def extra_slq(mlct, dev):
+    """Lanczos-quadrature level on the 2D Laplacian 2048^2 + 0.01 I, log:
+    level 0 Chebyshev n = 25 on 384 probes, level 1 SLQ (k = 50 Lanczos
+    steps, FP64) minus Chebyshev on 64 probes; HBM rooflines of the Lanczos
+    product and of the three-term update."""
+    import torch
+
+    w = laplace2d_workload()
+    g = w["graph"]
+    ctx = mlct.mlct_create(0)
+    op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.col).to(dev),
+                          torch.from_numpy(g.val).to(dev))
+
+    def run(seed):
+        return mlct.mlct_estimate_slq(ctx, op, mlct.MLCT_LOG, w["a"], w["b"], 25, 384, 50, 64,
+                                      seed, mlct.MLCT_FP64, mlct.MLCT_DOUBLING)
+
+    run(1)
+    mlct.mlct_timing(ctx, True)
+    _sync()
+    t0 = time.perf_counter()
+    r = run(2)
+    _sync()
+    dt = time.perf_counter() - t0
+    mlct.mlct_timing(ctx, False)
+    ns, ms_s = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_SLQ_SPMM)
+    nu, ms_u = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_SLQ_UPDATE)
+    vec = 8 * 64 * g.d
+    by_s = 8 * g.nnz + 4 * (g.d + 1) + 2 * vec   # A, w_j read, u written
+    by_u = 4 * vec                               # u, w_j, w_{j-1} read, u written
+    roof = lambda by, n, ms, kern: {
+        "bound": "hbm", "kernel": kern, "achieved": by / (ms / n / 1e3) / 1e9,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": by / (ms / n / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_launch": by, "avg_launch_ms": ms / n, "launches": n}
+    out = {"workload": w["desc"].split(", [a,b]")[0] + "; level 0 Chebyshev n=25 x 384 probes, "
+                       "level 1 SLQ k=50 (FP64) - Chebyshev x 64 probes",
+           "ms": dt * 1e3, "value": r["value"], "level_var": list(r["level_var"]),
+           "roofline_spmm": roof(by_s, ns, ms_s, "slq_spmm_kernel<double>"),
+           "roofline_update": roof(by_u, nu, ms_u, "slq_update_kernel")}
+    op.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -463,7 +575,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=2048, help="2D grid edge (default 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="dense,triangles,batch,time_to_eps,time_to_eps_dense",
+    ap.add_argument("--extras", default="dense,triangles,batch,time_to_eps,time_to_eps_dense,gram_csr,slq",
                     help="comma list of secondary measurements to add ('' for none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device copies of 1 GiB (a plain copy kernel of known "
@@ -521,7 +633,11 @@ def main():
     pd = res["probe_degrees"] * args.steps
     mv = res["matvecs"] * args.steps
     width = 64
-    bytes_launch = 8 * g.nnz + 4 * (g.d + 1) + 12 * g.d * width
+    # every launch reads A and v_k and writes v_{k+1}; all but the first step
+    # of a probe block also read v_{k-1}
+    blocks = args.steps * sum(-(-m // width) for m in w["m"])
+    bytes_launch = (8 * g.nnz + 4 * (g.d + 1) + 8 * g.d * width
+                    + 4 * g.d * width * (launches - blocks) / max(launches, 1))
     avg_s = kms / 1e3 / max(launches, 1)
     achieved = bytes_launch / avg_s / 1e9
     traffic = stored_traffic(w["name"])
@@ -552,7 +668,8 @@ def main():
     ctx.close()
     extras = {"dense": extra_nuclear_dense, "triangles": extra_triangles,
               "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps,
-              "time_to_eps_dense": extra_time_to_eps_dense, "learned_batch": extra_learned_batch}
+              "time_to_eps_dense": extra_time_to_eps_dense, "learned_batch": extra_learned_batch,
+              "gram_csr": extra_gram_csr, "slq": extra_slq}
     secondary = {}
     for name in [e for e in args.extras.split(",") if e]:
         print(f"# secondary measurement: {name}", file=sys.stderr, flush=True)

@@ -174,6 +174,10 @@ typedef enum {
   MLCT_KERNEL_TRI_STEP = 2,   /* one integer triangle-moment SpMM          */
   MLCT_KERNEL_GRAM = 3,       /* Gram matrix formation                     */
   MLCT_KERNEL_BATCH_STEP = 4, /* one batched recurrence step (all blocks)  */
+  MLCT_KERNEL_GRAM_CSR_STEP = 5, /* one step over X^T X + lambda I, X CSR:
+                                    W = X V_k, then the recurrence over X^T W */
+  MLCT_KERNEL_SLQ_SPMM = 6,   /* Lanczos product u = A w_j with the alpha dots */
+  MLCT_KERNEL_SLQ_UPDATE = 7, /* Lanczos three-term update with the beta dots  */
   MLCT_NUM_KERNEL_IDS = 8
 } mlct_kernel_id;
 mlct_status mlct_timing(mlct_ctx* ctx, int32_t enable);

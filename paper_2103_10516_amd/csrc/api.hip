@@ -312,7 +312,7 @@ mlct_status run_block_gram_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, d
     const double ca = first ? alpha : 2.0 * alpha;
     const double cb = (first ? beta : 2.0 * beta) + ca * op->gram_lambda;
     const int zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
-    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
+    LaunchTimer tm(ctx, MLCT_KERNEL_GRAM_CSR_STEP);
     HIPCHK(ctx, launch_gram_csr_step<T>(s, op->csrx, op->csr, vk, vm, W, (T)ca, (T)cb, !first,
                                         zmode, src, plan_r, plan, hubx, hubt, P + pstep * k));
     tm.done();
@@ -636,6 +636,33 @@ mlct_status check_mode_prec(mlct_ctx* ctx, int mode, int prec) {
   return MLCT_OK;
 }
 
+// Equal-work row bands of the operator's CSR matrices for the workgroup count
+// of its current plan; only matrices with very uneven rows get them.  Built
+// on the context stream, so steps already enqueued keep the bands they read.
+constexpr int kMaxBandGroups = 8192;
+
+mlct_status refresh_bands(mlct_ctx* ctx, mlct_op* op) {
+  CsrMat* mats[2] = {&op->csr, op->kind == OP_GRAM_CSR ? &op->csrx : nullptr};
+  for (int k = 0; k < 2; ++k) {
+    CsrMat* m = mats[k];
+    if (!m) continue;
+    const CsrStepPlan p = plan_csr(m->nrows, op->tuned_groups);
+    if (!csr_uneven(*m) || p.ngroups > kMaxBandGroups) {
+      m->band = nullptr;
+      m->band_groups = 0;
+      continue;
+    }
+    if (m->band && m->band_groups == p.ngroups) continue;
+    if (!op->band_mem)
+      HIPCHK(ctx, hipMalloc(&op->band_mem, 2 * (size_t)(kMaxBandGroups + 1) * sizeof(int32_t)));
+    int32_t* band = static_cast<int32_t*>(op->band_mem) + k * (kMaxBandGroups + 1);
+    HIPCHK(ctx, launch_csr_bands(ctx->stream, m->rowptr, m->nrows, p.ngroups, band));
+    m->band = band;
+    m->band_groups = p.ngroups;
+  }
+  return MLCT_OK;
+}
+
 }  // namespace
 
 // =========================================================================
@@ -751,12 +778,12 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   op->dtype = dtype;
   op->csr.max_row_nnz = hf[1];
   op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
-  if (op->csr.max_row_nnz > kHubLen) {
-    const mlct_status st = build_hubs(ctx, op->csr, &op->hub_mem);
-    if (st != MLCT_OK) {
-      delete op;
-      return st;
-    }
+  mlct_status st = MLCT_OK;
+  if (op->csr.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csr, &op->hub_mem);
+  if (st == MLCT_OK) st = refresh_bands(ctx, op);
+  if (st != MLCT_OK) {
+    mlct_op_destroy(op);
+    return st;
   }
   *out = op;
   return MLCT_OK;
@@ -856,6 +883,7 @@ mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t 
   mlct_status st = MLCT_OK;
   if (op->csrx.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csrx, &op->hubx_mem);
   if (st == MLCT_OK && op->csr.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csr, &op->hub_mem);
+  if (st == MLCT_OK) st = refresh_bands(ctx, op);
   if (st != MLCT_OK) {
     mlct_op_destroy(op);
     return st;
@@ -868,7 +896,8 @@ mlct_status mlct_op_destroy(mlct_op* op) {
   if (!op) return MLCT_EINVAL;
   (void)hipSetDevice(op->device);
   void* owned[] = {op->owned,   op->split_hi, op->split_lo, op->pack_hi, op->pack_lo,
-                   op->a32,     op->a64,      op->hub_mem,  op->hubx_mem, op->gram_mem};
+                   op->a32,     op->a64,      op->hub_mem,  op->hubx_mem, op->gram_mem,
+                   op->band_mem};
   for (void* p : owned)
     if (p) (void)hipFree(p);
   delete op;
@@ -1699,6 +1728,7 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     B.steps = hb.steps;
     B.ngroups = plan.ngroups;
     B.rows_per_group = plan.rows_per_group;
+    B.band = op->csr.band && op->csr.band_groups == plan.ngroups ? op->csr.band : nullptr;
   }
   std::vector<double*> mu(nitems), coef(nitems), qst(nitems);
   for (int i = 0; i < nitems; ++i) {
@@ -1826,12 +1856,14 @@ mlct_status run_block_slq(mlct_ctx* ctx, const mlct_op* op, int k, mlct_func f,
   HIPCHK(ctx, hipMemsetAsync(W0, 0, vbytes, s));
   HIPCHK(ctx, launch_slq_init(s, D, k, st));
   for (int j = 0; j < k; ++j) {
-    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
+    LaunchTimer tm(ctx, MLCT_KERNEL_SLQ_SPMM);
     HIPCHK(ctx, launch_slq_spmm(s, op->csr, W1, U, st->s_cur, plan, hub, P));
     tm.done();
     HIPCHK(ctx, launch_reduce_partials(s, P, 1, 2, plan.ngroups, kBlockProbes, D));
     HIPCHK(ctx, launch_slq_alpha(s, D, j, st));
+    LaunchTimer tu(ctx, MLCT_KERNEL_SLQ_UPDATE);
     HIPCHK(ctx, launch_slq_update(s, U, W1, W0, st, j, op->d, plan, P));
+    tu.done();
     HIPCHK(ctx, launch_reduce_partials(s, P, 1, 2, plan.ngroups, kBlockProbes, D));
     HIPCHK(ctx, launch_slq_beta(s, D, j, k, st));
     double* t = W0;  // rotate: w_{j-1} <- w_j <- w_{j+1}
@@ -2181,8 +2213,12 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   for (int c : cands) {
     if (!csr && c == 1 && dense_bpad(block) % 128) continue;  // 128-tiles need bpad % 128 == 0
     if (!csr && c == 2 && dense_bpad(block) % 64) continue;
-    if (csr) op->tuned_groups = c;
-    else op->tuned_dense = c;
+    if (csr) {
+      op->tuned_groups = c;
+      CHECK(refresh_bands(ctx, op));
+    } else {
+      op->tuned_dense = c;
+    }
     float tmin = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
       HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
@@ -2204,6 +2240,7 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   if (csr) {
     op->tuned_groups = choice;
     op->tuned_dense = saved_t;
+    CHECK(refresh_bands(ctx, op));
   } else {
     op->tuned_dense = choice;
     op->tuned_groups = saved_g;

@@ -36,7 +36,20 @@ struct CsrMat {
   int32_t* hub_cs = nullptr;    // [hub_chunks] first entry of each chunk
   int32_t* hub_ce = nullptr;    // [hub_chunks] one past its last entry
   int hub_n = 0, hub_chunks = 0;
+  // Row bands of equal work for matrices with very uneven rows (owned by the
+  // operator): band[g] .. band[g + 1] - 1 are workgroup g's rows when a step
+  // runs band_groups workgroups.
+  const int32_t* band = nullptr;
+  int band_groups = 0;
 };
+// Per-row cost of a band, in units of one entry's gather: the row pointer,
+// the own-row read and the result write.
+constexpr int kBandRowCost = 2;
+// Rows uneven enough for equal-work bands: the longest row exceeds four times
+// the mean plus eight.
+inline bool csr_uneven(const CsrMat& m) {
+  return m.nrows > 0 && m.max_row_nnz > 4 * (m.nnz / m.nrows) + 8;
+}
 
 struct DevBuf {
   void* ptr = nullptr;
@@ -90,6 +103,7 @@ struct mlct_op {
   void* hub_mem = nullptr;     // hub table of csr (one allocation)
   void* hubx_mem = nullptr;    // hub table of csrx
   void* gram_mem = nullptr;    // OP_GRAM_CSR: the X^T arrays (owned)
+  void* band_mem = nullptr;    // equal-work row bands of csr and csrx (owned)
   // tr A and ||A||_F^2 (exact low-degree traces), computed on first use
   bool stats_ready = false;
   double tr_a = 0.0, fro2 = 0.0;
@@ -185,7 +199,8 @@ hipError_t launch_level_combine(hipStream_t s, const double* mu, int64_t ldmu,
 // ---- CSR recurrence (k_csr.hip) -------------------------------------------
 struct CsrStepPlan {
   int ngroups;        // workgroups per step (= partial-sum slots)
-  int rows_per_group; // contiguous rows per workgroup
+  int rows_per_group; // contiguous rows per workgroup (without bands)
+  const int32_t* band = nullptr;  // [ngroups + 1] first row of each workgroup, or none
 };
 // Workgroups per step: one per 256 rows, a multiple of 8 (one band per XCD),
 // at most max_groups (0 = the default cap of 2048; the autotuner's choice
@@ -206,6 +221,7 @@ struct BatchBlock {
   ProbeSrc src;
   double alpha, beta;
   int steps, ngroups, rows_per_group;
+  const int32_t* band;  // the operator's row bands for ngroups, or nullptr
   int64_t group_base;  // first workgroup of this block in the launch grid
 };
 hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
@@ -232,6 +248,11 @@ hipError_t launch_gram_csr_step(hipStream_t s, const CsrMat& X, const CsrMat& XT
                                 void* hubx_part, void* hubt_part, double* part);
 // Rows longer than kHubLen as (row, start, end) triples, unordered; count is
 // incremented once per such row (entries past cap are not written).
+// Equal-work row bands: band[g] = the first row r with
+// rowptr[r] + kBandRowCost * r >= g * (nnz + kBandRowCost * d) / ngroups,
+// g = 0 .. ngroups (band[0] = 0, band[ngroups] = d).
+hipError_t launch_csr_bands(hipStream_t s, const int32_t* rowptr, int64_t d, int ngroups,
+                            int32_t* band);
 hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
                            int32_t* count, int cap);
 

@@ -251,6 +251,9 @@ struct RowReader {
 // first is consumed; slots past the end gather the chunk's last row with
 // weight 0).
 constexpr int kGen = 16;
+// Gathers in flight per wave in the sequence form of a group (below).
+template <typename T>
+constexpr int kFlatOf = sizeof(T) == 8 ? 16 : 32;
 
 template <typename T, bool PATTERN, class RD>
 __device__ __forceinline__ T row_dot_generic(const int32_t* __restrict__ col,
@@ -359,15 +362,18 @@ template <typename T, bool PATTERN, int MAXNZ, bool OFF32, int TAIL, bool SEP, c
 __device__ __forceinline__ void csr_step_wg(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ vk,
-    const T* __restrict__ vown, Epi& epi, const HubView& hub, int rows_per_group, int ngroups,
+    const T* __restrict__ vown, Epi& epi, const HubView& hub, const CsrStepPlan& plan,
     typename Epi::Part* __restrict__ part, int bid) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
   constexpr int GPB = 64 / ROWS;  // groups per batch
   constexpr bool HUBS = TAIL == kTailHubs;
+  constexpr int kFlat = kFlatOf<T>;
   const int lane = lane_id(), wave = wave_id();
+  const int ngroups = plan.ngroups;
   const int g = xcd_band(bid, ngroups);
-  const int64_t r0 = (int64_t)g * rows_per_group;
-  const int64_t r1 = min<int64_t>(r0 + rows_per_group, d);
+  const int64_t r0 = plan.band ? (int64_t)plan.band[g] : (int64_t)g * plan.rows_per_group;
+  const int64_t r1 = plan.band ? (int64_t)plan.band[g + 1]
+                               : min<int64_t>(r0 + plan.rows_per_group, d);
 
   const int64_t ngrp = r1 > r0 ? (r1 - r0 + ROWS - 1) / ROWS : 0;  // groups in the band
   const int64_t nk = ngrp > wave ? (ngrp - wave + kWaves - 1) / kWaves : 0;  // this wave's
@@ -447,6 +453,71 @@ __device__ __forceinline__ void csr_step_wg(
           if (r < cur.nr) epi.finish(row0 + r, acc, xi[r], xp[r]);
         }
       } else if constexpr (TAIL != kTailNone) {
+        if (cur.maxlen <= kHubChunk) {
+          // the group's entries as one sequence: 64-entry chunks of column
+          // indices (the first already loaded), gathered kFlat at a time and
+          // summed in column order into a running sum that is handed to its
+          // row's accumulator at the row's last entry (rows are contiguous)
+          T acc[ROWS];
+#pragma unroll
+          for (int r = 0; r < ROWS; ++r) {
+            const int64_t i = row0 + min(r, cur.nr - 1);
+            acc[r] = T(0);
+            xi[r] = own(i);
+            xp[r] = epi.prev(i);
+          }
+          // current row rc (uniform) and the position of its last entry
+          auto last_of = [&](int rr) {
+            int e = -1;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+              if (r == rr && cur.len[r] > 0) e = cur.off[r] + cur.len[r] - 1;
+            return e;
+          };
+          auto next_row = [&](int rr) {  // first row after rr with an entry
+            int nx = ROWS;
+#pragma unroll
+            for (int r = ROWS - 1; r >= 0; --r)
+              if (r > rr && cur.len[r] > 0) nx = r;
+            return nx;
+          };
+          int rc = next_row(-1);
+          int rend = last_of(rc);
+          T run = T(0);
+          for (int base = 0; base < cur.cnt; base += 64) {
+            int cjc = cj;
+            float avc = av;
+            if (base > 0) {
+              const int64_t ce = min<int64_t>((int64_t)cur.gs + base + lane, nnz - 1);
+              cjc = col[ce];
+              avc = PATTERN ? 1.f : val[ce];
+            }
+            const int c = min(64, cur.cnt - base);
+            for (int t = 0; t < c; t += kFlat) {
+              T xg[kFlat];
+#pragma unroll
+              for (int u = 0; u < kFlat; ++u) xg[u] = rd(read_lane(cjc, min(t + u, c - 1)), lane);
+#pragma unroll
+              for (int u = 0; u < kFlat; ++u) {
+                if (t + u < c) {
+                  const float w = PATTERN ? 1.f : read_lane(avc, t + u);
+                  run = accum<T, PATTERN>(run, w, true, xg[u]);
+                  if (base + t + u == rend) {
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r)
+                      if (r == rc) acc[r] = run;
+                    run = T(0);
+                    rc = next_row(rc);
+                    rend = last_of(rc);
+                  }
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < ROWS; ++r)
+            if (r < cur.nr) epi.finish(row0 + r, acc[r], xi[r], xp[r]);
+        } else {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {  // static indices: cur stays in registers
           if (r < cur.nr) {
@@ -459,6 +530,7 @@ __device__ __forceinline__ void csr_step_wg(
               acc = row_dot_chunked<T, PATTERN>(col, val, rd, s0, s0 + cur.len[r]);
             epi.finish(i, acc, own(i), epi.prev(i));
           }
+        }
         }
       }
       if (!has_next) break;
@@ -481,12 +553,11 @@ template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OF
 __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
-    T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub, int rows_per_group, int ngroups,
+    T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub, CsrStepPlan plan,
     double* __restrict__ part) {
   RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
   csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, d, nnz, vk, nullptr,
-                                                     epi, hub, rows_per_group, ngroups, part,
-                                                     blockIdx.x);
+                                                     epi, hub, plan, part, blockIdx.x);
 }
 
 // Gram step, first product: W = X V_k over X's rows (V_k has dv = X's
@@ -495,11 +566,10 @@ template <typename T, bool PATTERN, int MAXNZ, bool OFF32, int TAIL>
 __global__ __launch_bounds__(kThreads) void gram_pass1_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ vk,
-    T* __restrict__ W, HubView hub, int rows_per_group, int ngroups) {
+    T* __restrict__ W, HubView hub, CsrStepPlan plan) {
   StoreEpi<T> epi(W);
   csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, dv, nnz, vk, nullptr,
-                                                     epi, hub, rows_per_group, ngroups, nullptr,
-                                                     blockIdx.x);
+                                                     epi, hub, plan, nullptr, blockIdx.x);
 }
 
 // Gram step, second product with the recurrence: V_new = ca X^T W + cb V_k
@@ -509,23 +579,21 @@ __global__ __launch_bounds__(kThreads) void gram_pass2_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ W,
     const T* __restrict__ vk, T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub,
-    int rows_per_group, int ngroups, double* __restrict__ part) {
+    CsrStepPlan plan, double* __restrict__ part) {
   RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
   csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, true>(rowptr, col, val, d, dv, nnz, W, vk, epi,
-                                                    hub, rows_per_group, ngroups, part,
-                                                    blockIdx.x);
+                                                    hub, plan, part, blockIdx.x);
 }
 
 template <bool PATTERN, int MAXNZ, int TAIL>
 __global__ __launch_bounds__(kThreads) void slq_spmm_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const double* __restrict__ w,
-    double* __restrict__ u, const double* __restrict__ sdev, HubView hub, int rows_per_group,
-    int ngroups, double* __restrict__ part) {
+    double* __restrict__ u, const double* __restrict__ sdev, HubView hub, CsrStepPlan plan,
+    double* __restrict__ part) {
   SlqEpi epi(u, sdev);
   csr_step_wg<double, PATTERN, MAXNZ, false, TAIL, false>(rowptr, col, val, d, d, nnz, w, nullptr,
-                                                          epi, hub, rows_per_group, ngroups, part,
-                                                          blockIdx.x);
+                                                          epi, hub, plan, part, blockIdx.x);
 }
 
 // Integer pass of triangle counting over a pattern CSR: vin = z (PASS 1,
@@ -533,12 +601,11 @@ __global__ __launch_bounds__(kThreads) void slq_spmm_kernel(
 template <int PASS, int MAXNZ, bool OFF32, int TAIL>
 __global__ __launch_bounds__(kThreads) void tri_step_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t d, int64_t nnz,
-    const int32_t* __restrict__ vin, int32_t* __restrict__ vout, HubView hub,
-    int rows_per_group, int ngroups, long long* __restrict__ part) {
+    const int32_t* __restrict__ vin, int32_t* __restrict__ vout, HubView hub, CsrStepPlan plan,
+    long long* __restrict__ part) {
   TriEpi<PASS> epi(vout);
   csr_step_wg<int32_t, true, MAXNZ, OFF32, TAIL, false>(rowptr, col, nullptr, d, d, nnz, vin,
-                                                        nullptr, epi, hub, rows_per_group,
-                                                        ngroups, part, blockIdx.x);
+                                                        nullptr, epi, hub, plan, part, blockIdx.x);
 }
 
 // Chunk partials of the hub rows: one wave per chunk of at most kHubChunk
@@ -555,6 +622,24 @@ __global__ __launch_bounds__(256) void csr_hub_kernel(const int32_t* __restrict_
   const int lane = lane_id();
   const RowReader<T, OFF32> rd(vk, d, lane);
   out[(int64_t)c * 64 + lane] = row_dot_generic<T, PATTERN>(col, val, rd, cs[c], ce[c]);
+}
+
+// Equal-work row bands by binary search on rowptr[r] + kBandRowCost * r.
+__global__ __launch_bounds__(256) void csr_band_kernel(const int32_t* __restrict__ rowptr,
+                                                       int64_t d, int ngroups,
+                                                       int32_t* __restrict__ band) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g > ngroups) return;
+  const int64_t base = rowptr[0];
+  const int64_t work = (int64_t)rowptr[d] - base + kBandRowCost * d;
+  const int64_t target = work * g / ngroups;
+  int64_t lo = 0, hi = d;  // f(d) = work >= target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)rowptr[mid] - base + kBandRowCost * mid >= target) hi = mid;
+    else lo = mid + 1;
+  }
+  band[g] = (int32_t)lo;
 }
 
 // Rows longer than kHubLen: (row, start, end) triples in any order; the host
@@ -602,9 +687,10 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   const float cb = (float)(HAS_PREV ? 2.0 * B.beta : B.beta);
   RecEpi<float, ZMODE, HAS_PREV> epi(ca, cb, vm, B.src);
   const HubView nohub{nullptr, nullptr, 0, nullptr};
+  const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
   csr_step_wg<float, PATTERN, MAXNZ, true, kTailGen, false>(
-      B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, B.rows_per_group,
-      B.ngroups, B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+      B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, plan,
+      B.part + (size_t)s * 2 * B.ngroups * 64, bid);
 }
 
 __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
@@ -615,6 +701,13 @@ __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
   probe_init_wg<float>(B.v0, B.d, B.src, B.rows_per_group, B.ngroups, B.part, bid);
 }
 
+// The plan with the matrix's equal-work row bands when they were built for
+// this number of workgroups, else with equal row counts.
+CsrStepPlan banded(const CsrMat& m, CsrStepPlan p) {
+  p.band = (m.band != nullptr && m.band_groups == p.ngroups) ? m.band : nullptr;
+  return p;
+}
+
 template <typename T, bool PATTERN, int ZMODE, int MAXNZ, bool OFF32, int TAIL>
 hipError_t launch_step_t(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T ca, T cb,
                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, const HubView& hub,
@@ -622,12 +715,10 @@ hipError_t launch_step_t(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T c
   const dim3 grid(plan.ngroups), block(kThreads);
   if (has_prev)
     csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32, TAIL><<<grid, block, 0, s>>>(
-        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
-        plan.ngroups, part);
+        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, banded(m, plan), part);
   else
     csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32, TAIL><<<grid, block, 0, s>>>(
-        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, plan.rows_per_group,
-        plan.ngroups, part);
+        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, banded(m, plan), part);
   return hipGetLastError();
 }
 
@@ -687,6 +778,9 @@ hipError_t dispatch_shape(const CsrMat& m, int64_t dv, F&& f) {
     }
   }
   if (m.hub_n > 0) return f(I8(), std::false_type(), Hubs());
+  if (m.nnz > 0 && m.max_row_nnz <= 4) return f(I4(), std::false_type(), None());
+  if (m.nnz > 0 && m.max_row_nnz <= 5) return f(I5(), std::false_type(), None());
+  if (m.nnz > 0 && m.max_row_nnz <= 8) return f(I8(), std::false_type(), None());
   return f(I8(), std::false_type(), Gen());
 }
 
@@ -728,8 +822,7 @@ hipError_t launch_tri_pass(hipStream_t s, const CsrMat& m, const CsrStepPlan& pl
   const dim3 grid(plan.ngroups), block(kThreads);
 #define MLCT_TRI(M, H)                                                                        \
   tri_step_kernel<PASS, M, OFF32, H><<<grid, block, 0, s>>>(m.rowptr, m.col, m.nrows, m.nnz,  \
-                                                            vin, vout, hub,                   \
-                                                            plan.rows_per_group, plan.ngroups, \
+                                                            vin, vout, hub, banded(m, plan),  \
                                                             part)
   if (m.hub_n > 0) MLCT_TRI(8, kTailHubs);
   else if (m.nnz > 0 && m.max_row_nnz <= 4) MLCT_TRI(4, kTailNone);
@@ -752,8 +845,7 @@ hipError_t launch_gram_z(hipStream_t s, const CsrMat& X, const CsrMat& XT, const
   e = dispatch_shape<T>(X, X.ncols, [&](auto mz, auto off32, auto tail) {
     gram_pass1_kernel<T, PATTERN, decltype(mz)::value, decltype(off32)::value,
                       decltype(tail)::value><<<pr.ngroups, kThreads, 0, s>>>(
-        X.rowptr, X.col, X.val, X.nrows, X.ncols, X.nnz, vk, W, hx, pr.rows_per_group,
-        pr.ngroups);
+        X.rowptr, X.col, X.val, X.nrows, X.ncols, X.nnz, vk, W, hx, banded(X, pr));
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -764,12 +856,12 @@ hipError_t launch_gram_z(hipStream_t s, const CsrMat& X, const CsrMat& XT, const
       gram_pass2_kernel<T, PATTERN, ZMODE, true, decltype(mz)::value, decltype(off32)::value,
                         decltype(tail)::value><<<pc.ngroups, kThreads, 0, s>>>(
           XT.rowptr, XT.col, XT.val, XT.nrows, XT.ncols, XT.nnz, W, vk, vm, ca, cb, src, ht,
-          pc.rows_per_group, pc.ngroups, part);
+          banded(XT, pc), part);
     else
       gram_pass2_kernel<T, PATTERN, ZMODE, false, decltype(mz)::value, decltype(off32)::value,
                         decltype(tail)::value><<<pc.ngroups, kThreads, 0, s>>>(
           XT.rowptr, XT.col, XT.val, XT.nrows, XT.ncols, XT.nnz, W, vk, vm, ca, cb, src, ht,
-          pc.rows_per_group, pc.ngroups, part);
+          banded(XT, pc), part);
     return hipGetLastError();
   });
 }
@@ -847,17 +939,21 @@ hipError_t launch_slq_spmm(hipStream_t s, const CsrMat& m, const double* w, doub
     if (e != hipSuccess) return e;
   }
   const HubView hub = hub_view(m, hub_part);
-  const dim3 grid(plan.ngroups), block(kThreads);
-#define MLCT_SLQ(P, H)                                                                          \
-  slq_spmm_kernel<P, 8, H><<<grid, block, 0, s>>>(m.rowptr, m.col, m.val, m.nrows, m.nnz, w, u, \
-                                                 sdev, hub, plan.rows_per_group, plan.ngroups,  \
-                                                 part)
-  if (pat) {
-    if (m.hub_n > 0) MLCT_SLQ(true, kTailHubs); else MLCT_SLQ(true, kTailGen);
-  } else {
-    if (m.hub_n > 0) MLCT_SLQ(false, kTailHubs); else MLCT_SLQ(false, kTailGen);
-  }
-#undef MLCT_SLQ
+  return dispatch_shape<double>(m, m.ncols, [&](auto mz, auto, auto tail) {
+    constexpr int MZ = decltype(mz)::value, TL = decltype(tail)::value;
+    if (pat)
+      slq_spmm_kernel<true, MZ, TL><<<plan.ngroups, kThreads, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, w, u, sdev, hub, banded(m, plan), part);
+    else
+      slq_spmm_kernel<false, MZ, TL><<<plan.ngroups, kThreads, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, w, u, sdev, hub, banded(m, plan), part);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_csr_bands(hipStream_t s, const int32_t* rowptr, int64_t d, int ngroups,
+                            int32_t* band) {
+  csr_band_kernel<<<(ngroups + 1 + 255) / 256, 256, 0, s>>>(rowptr, d, ngroups, band);
   return hipGetLastError();
 }
 

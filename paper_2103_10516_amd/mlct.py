@@ -32,6 +32,8 @@ MLCT_MAX_LEVELS = 32
 MLCT_EXACT_LOW = 0x20
 MLCT_FLAG_FEW_SAMPLES, MLCT_FLAG_OVERFLOW, MLCT_FLAG_BF16 = 0x1, 0x2, 0x4
 MLCT_KERNEL_CSR_STEP, MLCT_KERNEL_DENSE_STEP, MLCT_KERNEL_TRI_STEP, MLCT_KERNEL_GRAM = 0, 1, 2, 3
+MLCT_KERNEL_BATCH_STEP, MLCT_KERNEL_GRAM_CSR_STEP = 4, 5
+MLCT_KERNEL_SLQ_SPMM, MLCT_KERNEL_SLQ_UPDATE = 6, 7
 
 
 class mlct_func(C.Structure):
