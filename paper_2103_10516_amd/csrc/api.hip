@@ -647,7 +647,7 @@ mlct_status refresh_bands(mlct_ctx* ctx, mlct_op* op) {
     CsrMat* m = mats[k];
     if (!m) continue;
     const CsrStepPlan p = plan_csr(m->nrows, op->tuned_groups);
-    if (!csr_uneven(*m) || p.ngroups > kMaxBandGroups) {
+    if (!csr_uneven(*m) || p.ngroups < kBandMinGroups || p.ngroups > kMaxBandGroups) {
       m->band = nullptr;
       m->band_groups = 0;
       continue;
@@ -1148,8 +1148,9 @@ mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64
     CHECK(dense_operand(ctx, op, MLCT_FP64, &a64, &unused, &lda));
   const int64_t nb = (d + 255) / 256 < 1024 ? (d + 255) / 256 : 1024;
   const int64_t xrows = op->kind == OP_GRAM_CSR ? op->csrx.nrows : 0;
+  const int64_t hubc = std::max(op->csr.hub_chunks, op->csrx.hub_chunks);
   void *q, *misc;
-  CHECK(ws_get(ctx, WS_LANCZOS, ((size_t)(steps + 2) * d + xrows) * sizeof(double), &q));
+  CHECK(ws_get(ctx, WS_LANCZOS, ((size_t)(steps + 2) * d + xrows + hubc) * sizeof(double), &q));
   const size_t misc_bytes = sizeof(LanczosState) + (size_t)(kLanczosMaxSteps + 1) * nb * 8 +
                             (kLanczosMaxSteps + 1) * 8 + 64 * 8;
   CHECK(ws_get(ctx, WS_DENSE, misc_bytes, &misc));
@@ -1160,7 +1161,7 @@ mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64
   double* h = part + (size_t)(kLanczosMaxSteps + 1) * nb;
   double* out = h + kLanczosMaxSteps + 1;
   HIPCHK(ctx, launch_lanczos(ctx->stream, op, a64, lda, steps, seed, rel_margin, Q, w, h, part,
-                             st, out, xrows ? w + d : nullptr));
+                             st, out, xrows ? w + d : nullptr, w + d + xrows));
   LanczosState hs;
   double ho[8];
   HIPCHK(ctx, hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
@@ -1657,7 +1658,10 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
       CHECK(low_traces(ctx, it.op, al, be, lv.low_tr));
     }
     const bool pat = it.op->csr.val == nullptr;
-    const int mz = it.op->csr.max_row_nnz <= 4 ? 4 : it.op->csr.max_row_nnz <= 5 ? 5 : 8;
+    // row-length class: straight-line gathers up to 4 / 5 / 8 entries, or
+    // 9 = longer rows present (the generic loop)
+    const int mxr = it.op->csr.max_row_nnz;
+    const int mz = mxr <= 4 ? 4 : mxr <= 5 ? 5 : mxr <= 8 ? 8 : 9;
     int var = -1;
     for (size_t v = 0; v < variants.size(); ++v)
       if (variants[v] == std::make_pair(pat, mz)) var = (int)v;

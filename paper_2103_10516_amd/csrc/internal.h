@@ -46,10 +46,13 @@ struct CsrMat {
 // the own-row read and the result write.
 constexpr int kBandRowCost = 2;
 // Rows uneven enough for equal-work bands: the longest row exceeds four times
-// the mean plus eight.
+// the mean plus eight.  Bands are used from kBandMinGroups workgroups per step
+// on: below that a step's workgroups are short-lived and the extra dependent
+// load of the band bounds costs more than the balance gains.
 inline bool csr_uneven(const CsrMat& m) {
   return m.nrows > 0 && m.max_row_nnz > 4 * (m.nnz / m.nrows) + 8;
 }
+constexpr int kBandMinGroups = 0;
 
 struct DevBuf {
   void* ptr = nullptr;
@@ -226,7 +229,8 @@ struct BatchBlock {
 };
 hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
                                      int64_t total_groups);
-// zmode 0 or 1 (regenerated probes); step >= 1
+// zmode 0 or 1 (regenerated probes); step >= 1; maxnz: the longest row of
+// the blocks' operators (above 8: the generic loop for long rows)
 hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
                                    int64_t total_groups, int step, bool pattern, int maxnz,
                                    int zmode);
@@ -372,7 +376,8 @@ struct LanczosState {
 hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int64_t lda,
                           int steps, uint64_t seed, double margin, double* Q, double* w,
                           double* h, double* part, LanczosState* st, double* out,
-                          double* tmp);  // tmp: X-row scratch (OP_GRAM_CSR)
+                          double* tmp,        // X-row scratch (OP_GRAM_CSR)
+                          double* hub_part);  // chunk sums of long rows (hub_chunks doubles)
 
 // ---- learned control-variate level (k_mlp.hip) -----------------------------
 constexpr int kMlpHidden = 64;

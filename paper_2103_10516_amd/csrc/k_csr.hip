@@ -251,7 +251,11 @@ struct RowReader {
 // first is consumed; slots past the end gather the chunk's last row with
 // weight 0).
 constexpr int kGen = 16;
-// Gathers in flight per wave in the sequence form of a group (below).
+// Gathers in flight per wave in the sequence form of a group (below).  16
+// for FP32 lowers the batched kernel's registers to four waves per SIMD but
+// measured 3x slower on the 64-graph Chung-Lu batch (more workgroups in
+// flight over a multi-GB gather working set); single-matrix steps time the
+// same with either.
 template <typename T>
 constexpr int kFlatOf = sizeof(T) == 8 ? 16 : 32;
 
@@ -675,7 +679,7 @@ __device__ __forceinline__ int find_block(const BatchBlock* __restrict__ tab, in
   return lo;
 }
 
-template <bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ>
+template <bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, int TAIL>
 __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
     const BatchBlock* __restrict__ tab, int nblocks, int s) {
   const int bi = __builtin_amdgcn_readfirstlane(find_block(tab, nblocks, blockIdx.x));
@@ -688,7 +692,7 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   RecEpi<float, ZMODE, HAS_PREV> epi(ca, cb, vm, B.src);
   const HubView nohub{nullptr, nullptr, 0, nullptr};
   const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
-  csr_step_wg<float, PATTERN, MAXNZ, true, kTailGen, false>(
+  csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
       B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, plan,
       B.part + (size_t)s * 2 * B.ngroups * 64, bid);
 }
@@ -975,9 +979,13 @@ hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, int nbl
                                    int zmode) {
   const bool hp = step > 1;
   const unsigned grid = (unsigned)total_groups;
-#define MLCT_BATCH(P, Z, H, M) csr_step_batched_kernel<P, Z, H, M><<<grid, kThreads, 0, s>>>(tab, nblocks, step)
-#define MLCT_BATCH_M(P, Z, H) \
-  if (maxnz <= 4) MLCT_BATCH(P, Z, H, 4); else if (maxnz <= 5) MLCT_BATCH(P, Z, H, 5); else MLCT_BATCH(P, Z, H, 8)
+#define MLCT_BATCH(P, Z, H, M, T) \
+  csr_step_batched_kernel<P, Z, H, M, T><<<grid, kThreads, 0, s>>>(tab, nblocks, step)
+#define MLCT_BATCH_M(P, Z, H)                                                       \
+  if (maxnz <= 4) MLCT_BATCH(P, Z, H, 4, kTailNone);                                \
+  else if (maxnz <= 5) MLCT_BATCH(P, Z, H, 5, kTailNone);                           \
+  else if (maxnz <= 8) MLCT_BATCH(P, Z, H, 8, kTailNone);                           \
+  else MLCT_BATCH(P, Z, H, 8, kTailGen)
 #define MLCT_BATCH_H(P, Z) \
   if (hp) { MLCT_BATCH_M(P, Z, true); } else { MLCT_BATCH_M(P, Z, false); }
 #define MLCT_BATCH_Z(P) \

@@ -46,22 +46,64 @@ __global__ void lz_start_kernel(double* __restrict__ q0, int64_t d, uint64_t see
   }
 }
 
-// w = A q (CSR, FP64 arithmetic on FP32 or implicit-1 values): one thread per row.
-// w = A q (+ shift * qs when qs is given): one thread per row.
+// Sums over the chunks of the rows longer than kHubLen (the matrix's hub
+// table): one wave per chunk of at most kHubChunk entries, FP64.
+__global__ __launch_bounds__(256) void lz_hub_chunk_kernel(const int32_t* __restrict__ col,
+                                                           const float* __restrict__ val,
+                                                           const int32_t* __restrict__ cs,
+                                                           const int32_t* __restrict__ ce,
+                                                           int nchunks,
+                                                           const double* __restrict__ q,
+                                                           double* __restrict__ out,
+                                                           const LanczosState* st) {
+  if (st->stopped) return;
+  const int c = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (c >= nchunks) return;
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int t = cs[c] + lane; t < ce[c]; t += 64) s += (val ? (double)val[t] : 1.0) * q[col[t]];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) out[c] = s;
+}
+
+// w = A q (+ shift * qs when qs is given), CSR, FP64 arithmetic on FP32 or
+// implicit-1 values: one thread per row; a row longer than kHubLen adds its
+// chunk sums (lz_hub_chunk_kernel) in chunk order.
 __global__ void lz_spmv_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                const float* __restrict__ val, int64_t d,
                                const double* __restrict__ q, double* __restrict__ w,
                                double shift, const double* __restrict__ qs,
-                               const LanczosState* st) {
+                               const int32_t* __restrict__ hub_rows,
+                               const int32_t* __restrict__ hub_c0, int hub_n,
+                               const double* __restrict__ hub_part, const LanczosState* st) {
   if (st->stopped) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
        i += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int t = rowptr[i]; t < rowptr[i + 1]; ++t)
-      s += (val ? (double)val[t] : 1.0) * q[col[t]];
+    const int t0 = rowptr[i], t1 = rowptr[i + 1];
+    if (hub_n > 0 && t1 - t0 > kHubLen) {
+      int lo = 0, hi = hub_n - 1;  // the row is in the table
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (hub_rows[mid] < i) lo = mid + 1; else hi = mid;
+      }
+      for (int c = hub_c0[lo]; c < hub_c0[lo + 1]; ++c) s += hub_part[c];
+    } else {
+      for (int t = t0; t < t1; ++t) s += (val ? (double)val[t] : 1.0) * q[col[t]];
+    }
     if (qs) s += shift * qs[i];
     w[i] = s;
   }
+}
+
+// w = M q (+ shift * qs) for one CSR matrix M, long rows through the chunks.
+void lz_csr_product(hipStream_t s, const CsrMat& m, int grid, const double* q, double* w,
+                    double shift, const double* qs, double* hub_part, const LanczosState* st) {
+  if (m.hub_n > 0)
+    lz_hub_chunk_kernel<<<(m.hub_chunks + 3) / 4, 256, 0, s>>>(m.col, m.val, m.hub_cs, m.hub_ce,
+                                                               m.hub_chunks, q, hub_part, st);
+  lz_spmv_kernel<<<grid, kT, 0, s>>>(m.rowptr, m.col, m.val, m.nrows, q, w, shift, qs,
+                                     m.hub_rows, m.hub_c0, m.hub_n, hub_part, st);
 }
 
 // w = A q (dense FP64, row-major): one wave per row.
@@ -224,7 +266,8 @@ __global__ void lz_interval_kernel(LanczosState* st, double margin, double* out)
 
 hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int64_t lda,
                           int steps, uint64_t seed, double margin, double* Q, double* w,
-                          double* h, double* part, LanczosState* st, double* out, double* tmp) {
+                          double* h, double* part, LanczosState* st, double* out, double* tmp,
+                          double* hub_part) {
   const int64_t d = op->d;
   const int nb = (int)((d + kT - 1) / kT < 1024 ? (d + kT - 1) / kT : 1024);
   const int grid = nb;
@@ -232,15 +275,10 @@ hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int
   for (int j = 0; j < steps; ++j) {
     const double* qj = Q + (int64_t)j * d;
     if (op->kind == OP_CSR) {
-      lz_spmv_kernel<<<grid, kT, 0, s>>>(op->csr.rowptr, op->csr.col, op->csr.val, d, qj, w, 0.0,
-                                         nullptr, st);
+      lz_csr_product(s, op->csr, grid, qj, w, 0.0, nullptr, hub_part, st);
     } else if (op->kind == OP_GRAM_CSR) {  // w = X^T (X q) + lambda q
-      const CsrMat& X = op->csrx;
-      const CsrMat& XT = op->csr;
-      lz_spmv_kernel<<<grid, kT, 0, s>>>(X.rowptr, X.col, X.val, X.nrows, qj, tmp, 0.0, nullptr,
-                                         st);
-      lz_spmv_kernel<<<grid, kT, 0, s>>>(XT.rowptr, XT.col, XT.val, d, tmp, w, op->gram_lambda,
-                                         qj, st);
+      lz_csr_product(s, op->csrx, grid, qj, tmp, 0.0, nullptr, hub_part, st);
+      lz_csr_product(s, op->csr, grid, tmp, w, op->gram_lambda, qj, hub_part, st);
     } else
       lz_gemv_kernel<<<grid, kT, 0, s>>>(static_cast<const double*>(a64), lda, d, qj, w, st);
     for (int pass = 0; pass < 2; ++pass) {
