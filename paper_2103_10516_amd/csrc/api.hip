@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <array>
 #include <new>
 #include <vector>
 
@@ -1705,6 +1706,7 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     bytes += align8(((size_t)totals[i] + 3 * MLCT_MAX_LEVELS) * 8);  // Q and level stats
   }
   bytes += align8((size_t)nitems * sizeof(mlct_result));
+  bytes += align8(nb * sizeof(int32_t)) + align8(nb * sizeof(int64_t));  // XCD layout
   void* ws;
   CHECK(ws_get(ctx, WS_BATCH, bytes, &ws));
   Carver cv{static_cast<char*>(ws)};
@@ -1742,6 +1744,8 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     qst[i] = cv.take<double>((size_t)totals[i] + 3 * MLCT_MAX_LEVELS);
   }
   mlct_result* dres = cv.take<mlct_result>(nitems);
+  int32_t* dxblk = cv.take<int32_t>(nb);
+  int64_t* dxbase = cv.take<int64_t>(nb);
   // group bases per variant table (each variant's blocks are contiguous)
   std::vector<size_t> vstart(variants.size() + 1, nb);
   for (size_t bi = nb; bi-- > 0;) vstart[blocks[bi].variant] = bi;
@@ -1753,8 +1757,49 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
       base += tab[bi].ngroups;
     }
   }
+  // XCD layout of each variant's blocks for the step launches: blocks go
+  // whole to one XCD, tier by tier (a tier = blocks with the same step
+  // count, larger first), each to the XCD with the least work so far, so
+  // the blocks running at any step are balanced and a prefix of each XCD's
+  // list.  Work of a block = nnz + kBandRowCost d.
+  std::vector<int32_t> xblk(nb);
+  std::vector<int64_t> xbase(nb);
+  std::vector<std::array<size_t, 9>> xoff(variants.size());
+  for (size_t v = 0; v < variants.size(); ++v) {
+    const size_t b0 = vstart[v], b1 = vstart[v + 1];
+    std::vector<int32_t> lists[8];
+    double load[8] = {};
+    auto work = [&](size_t bi) { return (double)tab[bi].nnz + kBandRowCost * (double)tab[bi].d; };
+    for (size_t i = b0; i < b1;) {
+      size_t j = i;
+      while (j < b1 && tab[j].steps == tab[i].steps) ++j;
+      std::vector<size_t> ord;
+      for (size_t bi = i; bi < j; ++bi) ord.push_back(bi);
+      std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return work(a) > work(b); });
+      for (size_t bi : ord) {
+        const int x = (int)(std::min_element(load, load + 8) - load);
+        lists[x].push_back((int32_t)(bi - b0));
+        load[x] += work(bi);
+      }
+      i = j;
+    }
+    size_t pos = b0;
+    for (int x = 0; x < 8; ++x) {
+      xoff[v][x] = pos - b0;
+      int64_t sb = 0;
+      for (int32_t e : lists[x]) {
+        xblk[pos] = e;
+        xbase[pos] = sb;
+        sb += tab[b0 + e].ngroups;
+        ++pos;
+      }
+    }
+    xoff[v][8] = pos - b0;
+  }
   hipStream_t s = ctx->stream;
   HIPCHK(ctx, hipMemcpyAsync(dtab, tab.data(), nb * sizeof(BatchBlock), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(dxblk, xblk.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(dxbase, xbase.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, s));
   // ---- coefficients ----
   for (int i = 0; i < nitems; ++i) {
     const int n = top[i];
@@ -1779,15 +1824,24 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   }
   for (int st = 1; st <= max_steps; ++st) {
     for (size_t v = 0; v < variants.size(); ++v) {
-      size_t cnt = 0;
-      while (vstart[v] + cnt < vstart[v + 1] && tab[vstart[v] + cnt].steps >= st) ++cnt;
-      if (!cnt) continue;
       const size_t b0 = vstart[v];
-      const int64_t groups = tab[b0 + cnt - 1].group_base + tab[b0 + cnt - 1].ngroups;
+      XcdLaunch xl;
+      int64_t most = 0;
+      for (int x = 0; x < 8; ++x) {
+        const size_t e0 = b0 + xoff[v][x], e1 = b0 + xoff[v][x + 1];
+        size_t e = e0;
+        int64_t slots = 0;
+        while (e < e1 && tab[b0 + xblk[e]].steps >= st) slots += tab[b0 + xblk[e++]].ngroups;
+        xl.first[x] = (int)(e0 - b0);
+        xl.count[x] = (int)(e - e0);
+        xl.slots[x] = slots;
+        most = std::max(most, slots);
+      }
+      if (!most) continue;
       const int zmode = (st == 1 || mode == MLCT_DOUBLING) ? 0 : 1;
       LaunchTimer tm(ctx, MLCT_KERNEL_BATCH_STEP);
-      HIPCHK(ctx, launch_csr_step_batched(s, dtab + b0, (int)cnt, groups, st, variants[v].first,
-                                          variants[v].second, zmode));
+      HIPCHK(ctx, launch_csr_step_batched(s, dtab + b0, dxblk + b0, dxbase + b0, xl, 8 * most, st,
+                                          variants[v].first, variants[v].second, zmode));
       tm.done();
     }
   }

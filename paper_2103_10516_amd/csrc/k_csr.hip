@@ -681,10 +681,22 @@ __device__ __forceinline__ int find_block(const BatchBlock* __restrict__ tab, in
 
 template <bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, int TAIL>
 __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
-    const BatchBlock* __restrict__ tab, int nblocks, int s) {
-  const int bi = __builtin_amdgcn_readfirstlane(find_block(tab, nblocks, blockIdx.x));
+    const BatchBlock* __restrict__ tab, const int32_t* __restrict__ xblk,
+    const int64_t* __restrict__ xbase, XcdLaunch xl, int s) {
+  const int x = blockIdx.x & 7;
+  const int64_t slot = blockIdx.x >> 3;
+  if (slot >= xl.slots[x]) return;  // this XCD has no more work in the launch
+  int lo = xl.first[x], hi = xl.first[x] + xl.count[x] - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (xbase[mid] <= slot) lo = mid; else hi = mid - 1;
+  }
+  const int bi = __builtin_amdgcn_readfirstlane(xblk[lo]);
   const BatchBlock& B = tab[bi];
-  const int bid = (int)(blockIdx.x - B.group_base);
+  // band g of the block; bid is the index whose xcd_band is g
+  const int g = (int)(slot - xbase[lo]);
+  const int per = B.ngroups >> 3;
+  const int bid = (g % per) * 8 + g / per;
   const float* vk = (s - 1) & 1 ? B.v1 : B.v0;
   float* vm = s & 1 ? B.v1 : B.v0;
   const float ca = (float)(HAS_PREV ? 2.0 * B.alpha : B.alpha);
@@ -974,13 +986,13 @@ hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int n
   return hipGetLastError();
 }
 
-hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, int nblocks,
-                                   int64_t total_groups, int step, bool pattern, int maxnz,
-                                   int zmode) {
+hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, const int32_t* xblk,
+                                   const int64_t* xbase, const XcdLaunch& xl, int64_t groups,
+                                   int step, bool pattern, int maxnz, int zmode) {
   const bool hp = step > 1;
-  const unsigned grid = (unsigned)total_groups;
+  const unsigned grid = (unsigned)groups;
 #define MLCT_BATCH(P, Z, H, M, T) \
-  csr_step_batched_kernel<P, Z, H, M, T><<<grid, kThreads, 0, s>>>(tab, nblocks, step)
+  csr_step_batched_kernel<P, Z, H, M, T><<<grid, kThreads, 0, s>>>(tab, xblk, xbase, xl, step)
 #define MLCT_BATCH_M(P, Z, H)                                                       \
   if (maxnz <= 4) MLCT_BATCH(P, Z, H, 4, kTailNone);                                \
   else if (maxnz <= 5) MLCT_BATCH(P, Z, H, 5, kTailNone);                           \
