@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import math
 import os
 import sys
@@ -36,13 +37,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources that define the CSR step kernel; HBM counter
-    figures stored under profiles/ are only reported while it matches."""
+    """Hash of the code (comments and blank space removed) of the sources
+    that define the CSR step kernels; HBM counter figures stored under
+    profiles/ are only reported while it matches."""
     h = hashlib.sha256()
     for f in ("k_csr.hip", "device.hpp"):
-        with open(os.path.join(ROOT, "paper_2103_10516_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2103_10516_amd", "csrc", f)) as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
+
+
+def code_only(text: str) -> str:
+    """C++ source without // and /* */ comments and with runs of blank space
+    collapsed, so that comment edits leave the kernel hash unchanged."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
 
 
 def stored_traffic(name: str):

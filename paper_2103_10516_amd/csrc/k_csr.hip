@@ -346,18 +346,20 @@ __device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int q, 
   return e;
 }
 
-// Work split: a workgroup owns a contiguous band of rows cut into groups of
-// ROWS rows; wave w takes groups w, w + kWaves, w + 2 kWaves, ..., so the
-// waves of a workgroup sweep the band side by side.  A wave fetches the row
-// extents of its next 64/ROWS groups in one load (a "batch", prefetched one
-// batch ahead) and the column indices and values of a group in one coalesced
-// load, issued while the previous group's gathers are in flight.  When every
-// row of a group has at most MAXNZ entries its gathers are straight-line code
-// (unused slots gather some valid row with weight 0), all in flight before
-// the first is consumed; other groups take the generic loop (TAIL kTailGen),
-// or for rows longer than kHubLen their chunk partials (kTailHubs).  With
-// kTailNone the caller guarantees that no row is longer than MAXNZ (and
-// ROWS * MAXNZ <= 64), so every group is straight-line.
+// Work split: a workgroup owns a contiguous band of rows (equal row counts,
+// or the plan's equal-work bands) cut into groups of ROWS rows; wave w takes
+// groups w, w + kWaves, w + 2 kWaves, ..., so the waves of a workgroup sweep
+// the band side by side.  A wave fetches the row extents of its next 64/ROWS
+// groups in one load (a "batch", prefetched one batch ahead) and the column
+// indices and values of a group in one coalesced load, issued while the
+// previous group's gathers are in flight.  When every row of a group has at
+// most MAXNZ entries its gathers are straight-line code (unused slots gather
+// some valid row with weight 0), all in flight before the first is consumed.
+// Other groups (TAIL kTailGen / kTailHubs) are gathered as one sequence of
+// entries when no row exceeds kHubChunk, else row by row, rows longer than
+// kHubLen through their chunk partials (kTailHubs).  With kTailNone the
+// caller guarantees that no row is longer than MAXNZ (and ROWS * MAXNZ <=
+// 64), so every group is straight-line.
 //
 // d: rows processed; dv: rows of the gathered block vk.  SEP: the own-row
 // value V_k[i] the epilogue needs comes from vown instead of vk (the second

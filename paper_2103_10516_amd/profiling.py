@@ -25,6 +25,7 @@ from __future__ import annotations
 import csv
 import hashlib
 import json
+import re
 import os
 import statistics
 import sys
@@ -34,11 +35,21 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_source_hash() -> str:
+    """Hash of the code (comments and blank space removed) of k_csr.hip and
+    device.hpp, stored with the counter figures."""
     h = hashlib.sha256()
     for f in ("k_csr.hip", "device.hpp"):
-        with open(os.path.join(ROOT, "paper_2103_10516_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2103_10516_amd", "csrc", f)) as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
+
+
+def code_only(text: str) -> str:
+    """C++ source without // and /* */ comments and with runs of blank space
+    collapsed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
 
 
 def stats_summary(path: str, command: str, top: int = 12) -> str:
