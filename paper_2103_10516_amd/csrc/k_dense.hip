@@ -857,8 +857,11 @@ __global__ void convert_kernel(const ST* __restrict__ a, int64_t d, int64_t lda,
 
 // Gram matrix G = X^T X (X row-major rows x cols, FP32) on FP32 MFMA.  Only
 // tiles with nt >= mt are computed; each writes G[i][j] and G[j][i] from the
-// same accumulator, so G is exactly symmetric.
-template <int WM, int WN, int TM, int TN, int BK>
+// same accumulator, so G is exactly symmetric.  Slices of BK rows of both
+// column panels go through two LDS stages: the next slice's global loads
+// (16-byte when VEC: cols and ldx multiples of 4, X 16-byte aligned) are in
+// flight in registers while the current slice is on the matrix cores.
+template <int WM, int WN, int TM, int TN, int BK, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN) void gram_kernel(const float* __restrict__ X,
                                                             int64_t rows, int64_t cols,
                                                             int64_t ldx, float* __restrict__ G,
@@ -866,7 +869,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gram_kernel(const float* __restr
   constexpr int NT = 64 * WM * WN;
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
   static_assert(BM == BN, "square tiles");
-  __shared__ float sX[2][BK][BM + 4];
+  constexpr int PER = BK * BM / NT;  // elements of each panel per thread per slice
+  static_assert(PER % 4 == 0, "slices in 4-element pieces");
+  __shared__ float sX[2][2][BK][BM + 4];  // [stage][panel]
   // upper-triangular tile pair (mt <= nt) from the linear index
   int L = blockIdx.x, mt = 0;
   while (L >= tiles - mt) {
@@ -882,28 +887,65 @@ __global__ __launch_bounds__(64 * WM * WN) void gram_kernel(const float* __restr
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = f4{};
-  for (int64_t r0 = 0; r0 < rows; r0 += BK) {
-    for (int e = tid; e < BK * BM; e += NT) {
+  // thread piece q covers slice element e = (q NT + tid) 4 .. +3 of a panel
+  float ra[PER], rb[PER];
+  auto gload = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < PER / 4; ++q) {
+      const int e = (q * NT + tid) * 4;
       const int k = e / BM, c = e % BM;
       const int64_t r = r0 + k;
-      sX[0][k][c] = (r < rows && i0 + c < cols) ? X[r * ldx + i0 + c] : 0.f;
-      sX[1][k][c] = (r < rows && j0 + c < cols) ? X[r * ldx + j0 + c] : 0.f;
+      if constexpr (VEC) {
+        float4 va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
+        if (r < rows && i0 + c < cols) va = *reinterpret_cast<const float4*>(X + r * ldx + i0 + c);
+        if (r < rows && j0 + c < cols) vb = *reinterpret_cast<const float4*>(X + r * ldx + j0 + c);
+        ra[4 * q] = va.x; ra[4 * q + 1] = va.y; ra[4 * q + 2] = va.z; ra[4 * q + 3] = va.w;
+        rb[4 * q] = vb.x; rb[4 * q + 1] = vb.y; rb[4 * q + 2] = vb.z; rb[4 * q + 3] = vb.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ra[4 * q + u] = (r < rows && i0 + c + u < cols) ? X[r * ldx + i0 + c + u] : 0.f;
+          rb[4 * q + u] = (r < rows && j0 + c + u < cols) ? X[r * ldx + j0 + c + u] : 0.f;
+        }
+      }
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < PER / 4; ++q) {
+      const int e = (q * NT + tid) * 4;
+      const int k = e / BM, c = e % BM;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sX[st][0][k][c + u] = ra[4 * q + u];
+        sX[st][1][k][c + u] = rb[4 * q + u];
+      }
+    }
+  };
+  const int64_t nit = (rows + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t it = 0; it < nit; ++it) {
+    const int st = (int)(it & 1);
+    if (it + 1 < nit) gload((it + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       float av[TM], bv[TN];
       const int k = kk + (lane >> 4);
 #pragma unroll
-      for (int a = 0; a < TM; ++a) av[a] = sX[0][k][wm * TM * 16 + a * 16 + (lane & 15)];
+      for (int a = 0; a < TM; ++a) av[a] = sX[st][0][k][wm * TM * 16 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < TN; ++b) bv[b] = sX[1][k][wn * TN * 16 + b * 16 + (lane & 15)];
+      for (int b = 0; b < TN; ++b) bv[b] = sX[st][1][k][wn * TN * 16 + b * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+    // the other stage was last read in the previous iteration, before the
+    // barrier that ended it
+    if (it + 1 < nit) sstore(st ^ 1);
     __syncthreads();
   }
 #pragma unroll
@@ -1133,7 +1175,9 @@ hipError_t launch_gram(hipStream_t s, const float* X, int64_t rows, int64_t cols
   constexpr int T = 128;
   const int tiles = (int)((cols + T - 1) / T);
   const int grid = tiles * (tiles + 1) / 2;
-  gram_kernel<2, 2, 4, 4, 16><<<grid, 256, 0, s>>>(X, rows, cols, ldx, G, tiles);
+  const bool vec = cols % 4 == 0 && ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  if (vec) gram_kernel<2, 2, 4, 4, 16, true><<<grid, 256, 0, s>>>(X, rows, cols, ldx, G, tiles);
+  else gram_kernel<2, 2, 4, 4, 16, false><<<grid, 256, 0, s>>>(X, rows, cols, ldx, G, tiles);
   return hipGetLastError();
 }
 
