@@ -249,9 +249,10 @@ def extra_graph_batch(mlct, dev):
     from paper_2103_10516_amd import workloads as wl
 
     ctx = mlct.mlct_create(0)
-    items = []
+    items, shapes = [], []
     for i, d in enumerate(wl.chung_lu_batch_sizes()):
         g = wl.chung_lu(d, seed=wl.SEED_BASE + 4 + i)
+        shapes.append((g.d, g.nnz))
         op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev),
                               torch.from_numpy(g.col).to(dev))
         a, b = mlct.mlct_bounds(ctx, op, 64, 7 + i, 0.01)
@@ -274,10 +275,29 @@ def extra_graph_batch(mlct, dev):
         _sync()
         ts = min(ts, time.perf_counter() - t0)
     pd = sum(r["probe_degrees"] for r in res)
+    # HBM roofline of the batched step kernel: unique bytes of every launch
+    # (pattern matrix, V_k, V_new; V_prev after a block's first step) over
+    # its event-timed duration
+    mlct.mlct_timing(ctx, True)
+    mlct.mlct_estimate_batch(ctx, items)
+    _sync()
+    mlct.mlct_timing(ctx, False)
+    nl, kms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_BATCH_STEP)
+    vec = 4 * 64
+    by = 0
+    for d, nnz in shapes:
+        for deg, m in zip([10, 30, 60], [768, 192, 64]):
+            steps, blocks = (deg + 1) // 2, -(-m // 64)
+            by += blocks * (steps * (4 * nnz + 4 * (d + 1) + 2 * vec * d) + (steps - 1) * vec * d)
+    ach = by / (kms / 1e3) / 1e9
     out = {"workload": "Estrada index, 64 Chung-Lu graphs d=2048..65536, levels 10/30/60, "
                        "probes 768/192/64 per graph",
            "batched_ms": tb * 1e3, "one_by_one_ms": ts * 1e3, "speedup": ts / tb,
-           "probe_degree_per_s": pd / tb}
+           "probe_degree_per_s": pd / tb,
+           "roofline": {"bound": "hbm", "kernel": "csr_step_batched_kernel", "achieved": ach,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                        "algorithmic_bytes_per_batch": by, "step_kernel_ms": kms,
+                        "launches": nl}}
     for it in items:
         it["op"].close()
     ctx.close()
