@@ -58,6 +58,15 @@ mlct_status ws_get(mlct_ctx* ctx, int slot, size_t bytes, void** out) {
   if (ctx->ws_limit && new_total > ctx->ws_limit)
     return fail(ctx, MLCT_ENOMEM, "workspace of %llu bytes exceeds the limit of %llu",
                 (unsigned long long)new_total, (unsigned long long)ctx->ws_limit);
+  // a slot that grows again grows by at least half its size (2 MiB granules),
+  // so a run of calls on ever larger operators reallocates a few times
+  // rather than on every call; never past the limit
+  size_t want = bytes;
+  if (b.bytes) {
+    want = std::max(bytes, b.bytes + b.bytes / 2);
+    want = (want + ((size_t)1 << 21) - 1) & ~(((size_t)1 << 21) - 1);
+    if (ctx->ws_limit && ctx->ws_total - b.bytes + want > ctx->ws_limit) want = bytes;
+  }
   if (b.ptr) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipFree(b.ptr));
@@ -66,13 +75,17 @@ mlct_status ws_get(mlct_ctx* ctx, int slot, size_t bytes, void** out) {
     b.bytes = 0;
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  if (hipMalloc(&p, want) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(ctx, MLCT_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    if (want == bytes || hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, MLCT_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    }
+    want = bytes;
   }
   b.ptr = p;
-  b.bytes = bytes;
-  ctx->ws_total += bytes;
+  b.bytes = want;
+  ctx->ws_total += want;
   *out = p;
   return MLCT_OK;
 }
@@ -233,6 +246,11 @@ mlct_status check_probes(mlct_ctx* ctx, const mlct_op* op, const mlct_probes* pr
   }
   return fail(ctx, MLCT_EINVAL, "unknown probe kind %d", pr->kind);
 }
+
+// CSR steps with fewer workgroups than this leave the device partly idle
+// (two 512-thread workgroups per CU on 256 CUs).
+constexpr int kSmallGroups = 512;
+constexpr int kSharedBlocks = 4;
 
 // ---- one probe block through the recurrence ------------------------------
 // Runs ``degree`` (direct) or ceil(degree/2) (symmetric form) steps on the
@@ -956,6 +974,7 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   if (!ctx) return MLCT_EINVAL;
   ctx->err.clear();
   if (!op || !levels || !out) return fail(ctx, MLCT_EINVAL, "op, levels and out are required");
+  const int32_t mode_flags = mode;
   const int interp = (mode & MLCT_LEVEL_INTERP) ? 1 : 0;
   const int exact_low = (mode & MLCT_EXACT_LOW) ? 1 : 0;
   mode &= ~(MLCT_LEVEL_INTERP | MLCT_EXACT_LOW);
@@ -963,6 +982,24 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   if (std::isnan(a) && std::isnan(b)) {
     const int steps = op->d < 64 ? (int)op->d : 64;
     CHECK(mlct_bounds(ctx, op, steps, seed + kGamma, 0.01, &a, &b));
+  }
+  // A CSR operator too small to fill the device with one probe block per
+  // launch (fewer than kSmallGroups workgroups per step) and without rows
+  // longer than kHubLen runs its probe blocks in shared launches (the
+  // batched path, whose results equal this function's bit for bit) when
+  // there are at least kSharedBlocks of them; fewer gain less than the
+  // batched path's set-up costs.
+  if (op->kind == OP_CSR && prec == MLCT_FP32 && op->csr.hub_n == 0 &&
+      (mode == MLCT_DIRECT || mode == MLCT_DOUBLING) && levels->L >= 1 &&
+      levels->L <= MLCT_MAX_LEVELS && levels->m &&
+      (uint64_t)op->d * 64 * 4 <= 0xFFFFFFFFull &&
+      plan_csr(op->d, op->tuned_groups).ngroups < kSmallGroups) {
+    int64_t blocks = 0;
+    for (int k = 0; k < levels->L; ++k) blocks += (levels->m[k] + kBlockProbes - 1) / kBlockProbes;
+    if (blocks >= kSharedBlocks) {
+      const mlct_batch_item it{op, f, a, b, *levels, seed};
+      return mlct_estimate_batch(ctx, 1, &it, prec, mode_flags, out);
+    }
   }
   CHECK(check_func(ctx, f, a, b));
   const int L = levels->L;
@@ -1706,7 +1743,7 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     bytes += align8(((size_t)totals[i] + 3 * MLCT_MAX_LEVELS) * 8);  // Q and level stats
   }
   bytes += align8((size_t)nitems * sizeof(mlct_result));
-  bytes += align8(nb * sizeof(int32_t)) + align8(nb * sizeof(int64_t));  // XCD layout
+  bytes += 2 * align8(8 * nb * sizeof(int32_t)) + align8(8 * nb * sizeof(int64_t));  // XCD layout
   void* ws;
   CHECK(ws_get(ctx, WS_BATCH, bytes, &ws));
   Carver cv{static_cast<char*>(ws)};
@@ -1744,8 +1781,9 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     qst[i] = cv.take<double>((size_t)totals[i] + 3 * MLCT_MAX_LEVELS);
   }
   mlct_result* dres = cv.take<mlct_result>(nitems);
-  int32_t* dxblk = cv.take<int32_t>(nb);
-  int64_t* dxbase = cv.take<int64_t>(nb);
+  int32_t* dxblk = cv.take<int32_t>(8 * nb);
+  int32_t* dxg0 = cv.take<int32_t>(8 * nb);
+  int64_t* dxbase = cv.take<int64_t>(8 * nb);
   // group bases per variant table (each variant's blocks are contiguous)
   std::vector<size_t> vstart(variants.size() + 1, nb);
   for (size_t bi = nb; bi-- > 0;) vstart[blocks[bi].variant] = bi;
@@ -1761,45 +1799,68 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   // whole to one XCD, tier by tier (a tier = blocks with the same step
   // count, larger first), each to the XCD with the least work so far, so
   // the blocks running at any step are balanced and a prefix of each XCD's
-  // list.  Work of a block = nnz + kBandRowCost d.
-  std::vector<int32_t> xblk(nb);
-  std::vector<int64_t> xbase(nb);
+  // list.  A tier with fewer than four blocks per XCD has each block cut
+  // into eight pieces of ngroups / 8 bands, one per XCD, so that the XCDs
+  // stay evenly loaded.  Work of
+  // a block = nnz + kBandRowCost d.  Entries of variant v sit at 8 vstart[v]
+  // onwards (at most eight per block).
+  struct XEntry {
+    int32_t blk, g0, cnt;
+  };
+  std::vector<int32_t> xblk(8 * nb), xg0(8 * nb), xcnt(8 * nb);
+  std::vector<int64_t> xbase(8 * nb);
   std::vector<std::array<size_t, 9>> xoff(variants.size());
+  std::vector<std::vector<int>> xsteps(variants.size());  // step count of each entry
   for (size_t v = 0; v < variants.size(); ++v) {
     const size_t b0 = vstart[v], b1 = vstart[v + 1];
-    std::vector<int32_t> lists[8];
+    std::vector<XEntry> lists[8];
     double load[8] = {};
     auto work = [&](size_t bi) { return (double)tab[bi].nnz + kBandRowCost * (double)tab[bi].d; };
     for (size_t i = b0; i < b1;) {
       size_t j = i;
       while (j < b1 && tab[j].steps == tab[i].steps) ++j;
-      std::vector<size_t> ord;
-      for (size_t bi = i; bi < j; ++bi) ord.push_back(bi);
-      std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return work(a) > work(b); });
-      for (size_t bi : ord) {
-        const int x = (int)(std::min_element(load, load + 8) - load);
-        lists[x].push_back((int32_t)(bi - b0));
-        load[x] += work(bi);
+      if (j - i < 32) {
+        for (size_t bi = i; bi < j; ++bi) {
+          const int32_t per = tab[bi].ngroups / 8;
+          for (int x = 0; x < 8; ++x) {
+            lists[x].push_back({(int32_t)(bi - b0), x * per, per});
+            load[x] += work(bi) / 8;
+          }
+        }
+      } else {
+        std::vector<size_t> ord;
+        for (size_t bi = i; bi < j; ++bi) ord.push_back(bi);
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](size_t a, size_t b) { return work(a) > work(b); });
+        for (size_t bi : ord) {
+          const int x = (int)(std::min_element(load, load + 8) - load);
+          lists[x].push_back({(int32_t)(bi - b0), 0, tab[bi].ngroups});
+          load[x] += work(bi);
+        }
       }
       i = j;
     }
-    size_t pos = b0;
+    size_t pos = 8 * b0;
     for (int x = 0; x < 8; ++x) {
-      xoff[v][x] = pos - b0;
+      xoff[v][x] = pos - 8 * b0;
       int64_t sb = 0;
-      for (int32_t e : lists[x]) {
-        xblk[pos] = e;
+      for (const XEntry& e : lists[x]) {
+        xblk[pos] = e.blk;
+        xg0[pos] = e.g0;
+        xcnt[pos] = e.cnt;
         xbase[pos] = sb;
-        sb += tab[b0 + e].ngroups;
+        xsteps[v].push_back(tab[b0 + e.blk].steps);
+        sb += e.cnt;
         ++pos;
       }
     }
-    xoff[v][8] = pos - b0;
+    xoff[v][8] = pos - 8 * b0;
   }
   hipStream_t s = ctx->stream;
   HIPCHK(ctx, hipMemcpyAsync(dtab, tab.data(), nb * sizeof(BatchBlock), hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(dxblk, xblk.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipMemcpyAsync(dxbase, xbase.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(dxblk, xblk.data(), 8 * nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(dxg0, xg0.data(), 8 * nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(dxbase, xbase.data(), 8 * nb * sizeof(int64_t), hipMemcpyHostToDevice, s));
   // ---- coefficients ----
   for (int i = 0; i < nitems; ++i) {
     const int n = top[i];
@@ -1827,21 +1888,24 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
       const size_t b0 = vstart[v];
       XcdLaunch xl;
       int64_t most = 0;
+      const size_t x0 = 8 * b0;  // this variant's entries
       for (int x = 0; x < 8; ++x) {
-        const size_t e0 = b0 + xoff[v][x], e1 = b0 + xoff[v][x + 1];
+        const size_t e0 = xoff[v][x], e1 = xoff[v][x + 1];
         size_t e = e0;
-        int64_t slots = 0;
-        while (e < e1 && tab[b0 + xblk[e]].steps >= st) slots += tab[b0 + xblk[e++]].ngroups;
-        xl.first[x] = (int)(e0 - b0);
+        while (e < e1 && xsteps[v][e] >= st) ++e;
+        xl.first[x] = (int)e0;
         xl.count[x] = (int)(e - e0);
+        // slots of the running entries: up to the end of the last of them
+        const int64_t slots = e > e0 ? xbase[x0 + e - 1] + xcnt[x0 + e - 1] : 0;
         xl.slots[x] = slots;
         most = std::max(most, slots);
       }
       if (!most) continue;
       const int zmode = (st == 1 || mode == MLCT_DOUBLING) ? 0 : 1;
       LaunchTimer tm(ctx, MLCT_KERNEL_BATCH_STEP);
-      HIPCHK(ctx, launch_csr_step_batched(s, dtab + b0, dxblk + b0, dxbase + b0, xl, 8 * most, st,
-                                          variants[v].first, variants[v].second, zmode));
+      HIPCHK(ctx, launch_csr_step_batched(s, dtab + b0, dxblk + x0, dxg0 + x0, dxbase + x0, xl,
+                                          8 * most, st, variants[v].first, variants[v].second,
+                                          zmode));
       tm.done();
     }
   }

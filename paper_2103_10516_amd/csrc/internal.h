@@ -231,10 +231,11 @@ hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int n
                                      int64_t total_groups);
 // Placement of a batched step launch on the 8 XCDs (workgroup w runs on XCD
 // w mod 8): XCD x takes slots 0 .. slots[x] - 1 (workgroups 8 slot + x),
-// which belong to the blocks xblk[first[x] .. first[x] + count[x]) in that
-// order, block xblk[e] holding slots xbase[e] .. xbase[e] + ngroups - 1.
-// Every workgroup of a block runs on one XCD, so the block's vectors are
-// gathered through one L2.
+// which belong to the entries first[x] .. first[x] + count[x] - 1 in that
+// order; entry e is bands xg0[e], xg0[e] + 1, ... of block xblk[e], from
+// slot xbase[e] on.  An entry is a whole block (its vectors gathered
+// through one L2) or, for steps with fewer blocks than XCDs, an eighth of
+// one.
 struct XcdLaunch {
   int first[8];
   int count[8];
@@ -244,8 +245,9 @@ struct XcdLaunch {
 // the blocks' operators (above 8: the generic loop for long rows); grid =
 // 8 x max slots[x]
 hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, const int32_t* xblk,
-                                   const int64_t* xbase, const XcdLaunch& xl, int64_t grid,
-                                   int step, bool pattern, int maxnz, int zmode);
+                                   const int32_t* xg0, const int64_t* xbase,
+                                   const XcdLaunch& xl, int64_t grid, int step, bool pattern,
+                                   int maxnz, int zmode);
 // zmode: 0 = dots with V_k (symmetric form), 1 = regenerated Rademacher z,
 // 2 = explicit z entries.  has_prev = false for the first step (no V_prev).
 // hub_part: workspace of op->hub_chunks x 64 elements of T (unused without

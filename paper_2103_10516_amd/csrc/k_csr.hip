@@ -684,7 +684,7 @@ __device__ __forceinline__ int find_block(const BatchBlock* __restrict__ tab, in
 template <bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, int TAIL>
 __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
     const BatchBlock* __restrict__ tab, const int32_t* __restrict__ xblk,
-    const int64_t* __restrict__ xbase, XcdLaunch xl, int s) {
+    const int32_t* __restrict__ xg0, const int64_t* __restrict__ xbase, XcdLaunch xl, int s) {
   const int x = blockIdx.x & 7;
   const int64_t slot = blockIdx.x >> 3;
   if (slot >= xl.slots[x]) return;  // this XCD has no more work in the launch
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   const int bi = __builtin_amdgcn_readfirstlane(xblk[lo]);
   const BatchBlock& B = tab[bi];
   // band g of the block; bid is the index whose xcd_band is g
-  const int g = (int)(slot - xbase[lo]);
+  const int g = xg0[lo] + (int)(slot - xbase[lo]);
   const int per = B.ngroups >> 3;
   const int bid = (g % per) * 8 + g / per;
   const float* vk = (s - 1) & 1 ? B.v1 : B.v0;
@@ -989,12 +989,13 @@ hipError_t launch_probe_init_batched(hipStream_t s, const BatchBlock* tab, int n
 }
 
 hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, const int32_t* xblk,
-                                   const int64_t* xbase, const XcdLaunch& xl, int64_t groups,
-                                   int step, bool pattern, int maxnz, int zmode) {
+                                   const int32_t* xg0, const int64_t* xbase,
+                                   const XcdLaunch& xl, int64_t groups, int step, bool pattern,
+                                   int maxnz, int zmode) {
   const bool hp = step > 1;
   const unsigned grid = (unsigned)groups;
 #define MLCT_BATCH(P, Z, H, M, T) \
-  csr_step_batched_kernel<P, Z, H, M, T><<<grid, kThreads, 0, s>>>(tab, xblk, xbase, xl, step)
+  csr_step_batched_kernel<P, Z, H, M, T><<<grid, kThreads, 0, s>>>(tab, xblk, xg0, xbase, xl, step)
 #define MLCT_BATCH_M(P, Z, H)                                                       \
   if (maxnz <= 4) MLCT_BATCH(P, Z, H, 4, kTailNone);                                \
   else if (maxnz <= 5) MLCT_BATCH(P, Z, H, 5, kTailNone);                           \
