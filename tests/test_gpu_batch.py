@@ -94,3 +94,55 @@ def test_graph_batch_full_sizes(ctx):
     print(f"64-graph batch: {t_batch * 1e3:.1f} ms batched vs {t_single * 1e3:.1f} ms one by one")
     for r, o in zip(res, single):
         assert r["value"] == o["value"]
+
+
+def _random_sym(d, per_row, seed):
+    """Sparse symmetric d x d with about 2 per_row + 1 entries per row at
+    random columns, values N(0, 1) / 4, unit diagonal; CSR arrays for the
+    library (int32 / float32)."""
+    import types
+
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    r = np.repeat(np.arange(d), per_row)
+    c = rng.integers(0, d, size=r.size)
+    A = sp.coo_matrix((rng.standard_normal(r.size) / 4, (r, c)), shape=(d, d)).tocsr()
+    A = (A + A.T + sp.identity(d)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return types.SimpleNamespace(rowptr=A.indptr.astype(np.int32), col=A.indices.astype(np.int32),
+                                 val=A.data.astype(np.float32), d=d)
+
+
+@pytest.mark.parametrize("mode", ["doubling", "direct"])
+def test_batch_equals_block_by_block_on_large_operators(ctx, mode):
+    """Operators with 512 or more workgroups per step keep the one-block-at-a-
+    time path in mlct_estimate (smaller ones share launches, i.e. take the
+    batched path themselves): there the two paths must still agree bit for
+    bit, for each row-length class of the batched kernel (5-point stencil,
+    9-entry rows, longer rows through the generic loop)."""
+    from paper_2103_10516_amd import mlct
+
+    md = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    graphs = [wl.laplacian_2d(384),             # d = 147,456: 576 workgroups, rows <= 5
+              _random_sym(140_000, 9, seed=7),   # rows of ~19 entries: the generic loop
+              wl.laplacian_2d(400, shift=0.5)]
+    items = []
+    for i, g in enumerate(graphs):
+        op = _op(ctx, g)
+        if i == 1:
+            a, b = mlct.mlct_bounds(ctx, op, 40, 3, 0.01)
+        else:  # the Laplacians' spectra lie in [shift, shift + 8]
+            shift = 0.01 if i == 0 else 0.5
+            a, b = shift, shift + 8.0
+        items.append(dict(op=op, kind=mlct.MLCT_LOG if i != 1 else mlct.MLCT_EXP, a=a, b=b,
+                          degrees=[7, 22], m=[130, 64], seed=500 + i))
+    res = mlct.mlct_estimate_batch(ctx, items, prec=mlct.MLCT_FP32, mode=md)
+    for it, r in zip(items, res):
+        one = mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"],
+                                 it["m"], it["seed"], mlct.MLCT_FP32, md)
+        assert r["value"] == one["value"] and r["est_var"] == one["est_var"]
+        np.testing.assert_array_equal(r["level_mean"], one["level_mean"])
+    for it in items:
+        it["op"].close()
