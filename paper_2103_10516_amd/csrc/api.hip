@@ -1801,9 +1801,8 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   // the blocks running at any step are balanced and a prefix of each XCD's
   // list.  A tier with fewer than four blocks per XCD has each block cut
   // into eight pieces of ngroups / 8 bands, one per XCD, so that the XCDs
-  // stay evenly loaded.  Work of
-  // a block = nnz + kBandRowCost d.  Entries of variant v sit at 8 vstart[v]
-  // onwards (at most eight per block).
+  // stay evenly loaded.  Work of a block = nnz + kBandRowCost d.  Entries
+  // of variant v sit at 8 vstart[v] onwards (at most eight per block).
   struct XEntry {
     int32_t blk, g0, cnt;
   };
