@@ -123,6 +123,7 @@ def extra_nuclear_dense(mlct, dev):
     X, sig = wl.nuclear_x()
     Xd = torch.from_numpy(X).to(dev)
     ctx = mlct.mlct_create(0)
+    mlct.mlct_op_gram(ctx, Xd).close()  # first launch loads the kernel: not timed
     mlct.mlct_timing(ctx, True)
     op = mlct.mlct_op_gram(ctx, Xd)
     _, gram_ms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_GRAM)
@@ -146,7 +147,8 @@ def extra_nuclear_dense(mlct, dev):
            "probe_degree_per_s": r["probe_degrees"] / dt, "ms_per_estimate": dt * 1e3,
            "estimate": r["estimate"], "exact_sum_sigma": float(np.sum(sig)),
            "gram_ms": gram_ms, "gram_tflops": 8192 * 4096.0 * 4096 / (gram_ms / 1e3) / 1e12,
-           "roofline": {"bound": "mfma", "kernel": "dense_step_kernel<bf16x3>",
+           "roofline": {"bound": "mfma",
+                        "kernel": "dense_pk_gemm_kernel + dense_skinny_kernel (bf16x3, packed)",
                         "achieved": ach, "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
                         "frac": ach / BF16_PEAK_TFS,
                         "issued_bf16_frac": 3 * ach / BF16_PEAK_TFS,
