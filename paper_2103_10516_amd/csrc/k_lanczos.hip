@@ -67,32 +67,44 @@ __global__ __launch_bounds__(256) void lz_hub_chunk_kernel(const int32_t* __rest
 }
 
 // w = A q (+ shift * qs when qs is given), CSR, FP64 arithmetic on FP32 or
-// implicit-1 values: one thread per row; a row longer than kHubLen adds its
-// chunk sums (lz_hub_chunk_kernel) in chunk order.
-__global__ void lz_spmv_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                               const float* __restrict__ val, int64_t d,
-                               const double* __restrict__ q, double* __restrict__ w,
-                               double shift, const double* __restrict__ qs,
-                               const int32_t* __restrict__ hub_rows,
-                               const int32_t* __restrict__ hub_c0, int hub_n,
-                               const double* __restrict__ hub_part, const LanczosState* st) {
+// implicit-1 values: 16 lanes per row (4 rows per wave), the row's entries
+// strided over its lanes (coalesced index and value loads) and added in a
+// fixed shuffle tree; a row longer than kHubLen adds its chunk sums
+// (lz_hub_chunk_kernel) in chunk order.
+__global__ __launch_bounds__(kT) void lz_spmv_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const float* __restrict__ val, int64_t d, const double* __restrict__ q,
+    double* __restrict__ w, double shift, const double* __restrict__ qs,
+    const int32_t* __restrict__ hub_rows, const int32_t* __restrict__ hub_c0, int hub_n,
+    const double* __restrict__ hub_part, const LanczosState* st) {
   if (st->stopped) return;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63, sub = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i0 = wave * 4; i0 < d; i0 += nw * 4) {  // uniform over the wave
+    const int64_t i = i0 + (lane >> 4);
     double s = 0.0;
-    const int t0 = rowptr[i], t1 = rowptr[i + 1];
-    if (hub_n > 0 && t1 - t0 > kHubLen) {
-      int lo = 0, hi = hub_n - 1;  // the row is in the table
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (hub_rows[mid] < i) lo = mid + 1; else hi = mid;
-      }
-      for (int c = hub_c0[lo]; c < hub_c0[lo + 1]; ++c) s += hub_part[c];
-    } else {
-      for (int t = t0; t < t1; ++t) s += (val ? (double)val[t] : 1.0) * q[col[t]];
+    bool hub = false;
+    if (i < d) {
+      const int t0 = rowptr[i], t1 = rowptr[i + 1];
+      hub = hub_n > 0 && t1 - t0 > kHubLen;
+      if (!hub)
+        for (int t = t0 + sub; t < t1; t += 16) s += (val ? (double)val[t] : 1.0) * q[col[t]];
     }
-    if (qs) s += shift * qs[i];
-    w[i] = s;
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);  // within the 16 lanes
+    if (sub == 0 && i < d) {
+      if (hub) {
+        int lo = 0, hi = hub_n - 1;  // the row is in the table
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (hub_rows[mid] < i) lo = mid + 1; else hi = mid;
+        }
+        s = 0.0;
+        for (int c = hub_c0[lo]; c < hub_c0[lo + 1]; ++c) s += hub_part[c];
+      }
+      if (qs) s += shift * qs[i];
+      w[i] = s;
+    }
   }
 }
 
@@ -139,18 +151,30 @@ __global__ __launch_bounds__(kT) void lz_dots_kernel(const double* __restrict__ 
   if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = s;
 }
 
-// h[c] = sum_b part[c][b] in fixed order.  mode 0: first pass (alpha_j =
-// h_j); mode 1: second pass (alpha_j += h_j).
-__global__ void lz_dots_reduce_kernel(const double* __restrict__ part, int nb, int ncols,
-                                      double* __restrict__ h, int mode, int j,
-                                      LanczosState* st) {
-  if (st->stopped) return;
-  const int c = threadIdx.x;
-  if (c >= ncols) return;
+// Sum of part[0 .. nb) by one wave in a fixed order: lane l adds entries
+// l, l + 64, ..., then a shuffle tree.  Every lane returns the total.
+__device__ double wave_sum_fixed(const double* __restrict__ part, int nb) {
+  const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)c * nb + b];
-  h[c] = s;
-  if (c == j) st->alpha[j] = (mode == 0) ? s : st->alpha[j] + s;
+  for (int b = lane; b < nb; b += 64) s += part[b];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s;
+}
+
+// h[c] = sum_b part[c][b], one wave (workgroup) per column c.  mode 0: first
+// pass (alpha_j = h_j); mode 1: second pass (alpha_j += h_j).
+__global__ __launch_bounds__(64) void lz_dots_reduce_kernel(const double* __restrict__ part,
+                                                            int nb, int ncols,
+                                                            double* __restrict__ h, int mode,
+                                                            int j, LanczosState* st) {
+  if (st->stopped) return;
+  const int c = blockIdx.x;
+  if (c >= ncols) return;
+  const double s = wave_sum_fixed(part + (int64_t)c * nb, nb);
+  if (threadIdx.x == 0) {
+    h[c] = s;
+    if (c == j) st->alpha[j] = (mode == 0) ? s : st->alpha[j] + s;
+  }
 }
 
 // w -= sum_c h[c] Q[c]
@@ -167,11 +191,11 @@ __global__ void lz_update_kernel(const double* __restrict__ Q, int64_t d, int nc
 }
 
 // beta_j = |w| from the partials of w.w; q_{j+1} = w / beta_j, or stop.
-__global__ void lz_norm_reduce_kernel(const double* __restrict__ part, int nb, int j,
-                                      LanczosState* st) {
-  if (st->stopped || threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[b];
+__global__ __launch_bounds__(64) void lz_norm_reduce_kernel(const double* __restrict__ part,
+                                                            int nb, int j, LanczosState* st) {
+  if (st->stopped) return;
+  const double s = wave_sum_fixed(part, nb);
+  if (threadIdx.x != 0) return;
   const double beta = sqrt(s);
   st->beta[j] = beta;
   st->k = j + 1;
@@ -283,7 +307,7 @@ hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int
       lz_gemv_kernel<<<grid, kT, 0, s>>>(static_cast<const double*>(a64), lda, d, qj, w, st);
     for (int pass = 0; pass < 2; ++pass) {
       lz_dots_kernel<<<dim3(nb, j + 1), kT, 0, s>>>(Q, d, w, j + 1, part, st);
-      lz_dots_reduce_kernel<<<1, kLanczosMaxSteps + 1, 0, s>>>(part, nb, j + 1, h, pass, j, st);
+      lz_dots_reduce_kernel<<<j + 1, 64, 0, s>>>(part, nb, j + 1, h, pass, j, st);
       lz_update_kernel<<<grid, kT, 0, s>>>(Q, d, j + 1, h, w, st);
     }
     lz_dots_kernel<<<dim3(nb, 1), kT, 0, s>>>(w, d, w, 1, part, st);
