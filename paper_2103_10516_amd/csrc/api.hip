@@ -2320,14 +2320,31 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   else cands = {0, 2, 1, 3};
   // workspace for the largest candidate
   const int saved_g = op->tuned_groups, saved_t = op->tuned_dense;
+  // on every early return the operator keeps the launch shape it had
+  struct Guard {
+    mlct_ctx* ctx;
+    mlct_op* op;
+    int g, t;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool restore = true;
+    ~Guard() {
+      if (restore) {
+        op->tuned_groups = g;
+        op->tuned_dense = t;
+        (void)refresh_bands(ctx, op);
+      }
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } guard{ctx, op, saved_g, saved_t};
   op->tuned_groups = 4096;
   void* mu;
   CHECK(ws_get(ctx, WS_MU, (size_t)block * (degree + 1) * 8, &mu));
   CHECK(reserve_block_ws(ctx, op, prec, MLCT_DIRECT, degree, block));
   op->tuned_groups = saved_g;
-  hipEvent_t e0, e1;
-  HIPCHK(ctx, hipEventCreate(&e0));
-  HIPCHK(ctx, hipEventCreate(&e1));
+  HIPCHK(ctx, hipEventCreate(&guard.e0));
+  HIPCHK(ctx, hipEventCreate(&guard.e1));
+  hipEvent_t e0 = guard.e0, e1 = guard.e1;
   ProbeSrc src{0x5EEDull, 0, nullptr, 0, (int32_t)block};
   float best = 1e30f;
   int choice = csr ? 2048 : -1;
@@ -2356,8 +2373,7 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
       choice = c;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  guard.restore = false;
   if (csr) {
     op->tuned_groups = choice;
     op->tuned_dense = saved_t;
