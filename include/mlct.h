@@ -267,7 +267,11 @@ mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64
  * degree-n interpolant (eq. def:qlevels) unless MLCT_LEVEL_INTERP is set.
  * Returns MLCT_ESPECTRUM if some |mu_j| exceeds |z|^2 (1 + 1e-3).
  * If a and b are both NaN the interval is found first by mlct_bounds with
- * min(64, d) steps, margin 0.01 and seed (seed + 0x9E3779B97F4A7C15). */
+ * min(64, d) steps, margin 0.01 and seed (seed + 0x9E3779B97F4A7C15).
+ * A CSR operator with fewer than 512 workgroups per step (about d < 131072),
+ * no row longer than 256 entries, MLCT_FP32 and at least four probe blocks
+ * runs as a one-item mlct_estimate_batch (all blocks in shared launches);
+ * the result is the same bit for bit. */
 mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
                           const mlct_levels* levels, uint64_t seed, int32_t prec,
                           int32_t mode, mlct_result* out);
