@@ -1,4 +1,4 @@
-"""Error model used by the GPU parity tests (derivation in the design doc).
+"""Error model used by the GPU parity tests.
 
 The recurrence v_{k+1} = 2 A_hat v_k - v_{k-1} evaluated in precision u
 commits per step a local error delta_k with, row by row,
