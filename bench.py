@@ -105,6 +105,27 @@ BF16_PEAK_TFS = 2500.0   # MI355X dense bf16 MFMA
 FP32_PEAK_TFS = 157.3    # MI355X FP32 MFMA
 
 
+def copy_bandwidth(dev, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """GB/s of a plain device-to-device copy of nbytes (read + write counted),
+    best of reps after a warm-up: the practical streaming ceiling the step
+    kernel's bandwidth is also compared with."""
+    import torch
+
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del x, y
+    return 2 * nbytes / best / 1e9
+
+
 def _sync():
     import torch
 
@@ -755,6 +776,9 @@ def main():
     }
     op.close()
     ctx.close()
+    cbw = copy_bandwidth(dev)
+    out["roofline"]["copy_GBs"] = cbw
+    out["roofline"]["frac_of_copy"] = achieved / cbw
     extras = {"dense": extra_nuclear_dense, "triangles": extra_triangles, "estrada": extra_estrada,
               "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps,
               "time_to_eps_dense": extra_time_to_eps_dense, "learned_batch": extra_learned_batch,
