@@ -84,7 +84,7 @@ typedef enum {
  * sum_{j<=2} c_j tr T_j(A_hat), with tr T_0 = d, tr T_1 = alpha tr A + beta d
  * and tr T_2 = 2 ||A_hat||_F^2 - d (A symmetric), from tr A and ||A||_F^2
  * computed once per operator (the exactly computable low-degree traces
- * remarked on at the end of Section 5.5).  c_j are the top interpolant's. */
+ * remarked on at the end of Section 5.4).  c_j are the top interpolant's. */
 #define MLCT_EXACT_LOW 0x20
 
 typedef enum {
@@ -178,7 +178,8 @@ typedef enum {
                                     W = X V_k, then the recurrence over X^T W */
   MLCT_KERNEL_SLQ_SPMM = 6,   /* Lanczos product u = A w_j with the alpha dots */
   MLCT_KERNEL_SLQ_UPDATE = 7, /* Lanczos three-term update with the beta dots  */
-  MLCT_NUM_KERNEL_IDS = 8
+  MLCT_KERNEL_CALLBACK_STEP = 8, /* recurrence update after a callback product */
+  MLCT_NUM_KERNEL_IDS = 9
 } mlct_kernel_id;
 mlct_status mlct_timing(mlct_ctx* ctx, int32_t enable);
 mlct_status mlct_timing_read(const mlct_ctx* ctx, int32_t kernel, int64_t* launches,
@@ -224,6 +225,28 @@ mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t 
  * the arithmetic ``prec`` (MLCT_FP32 or MLCT_BF16X3), and owned by the op. */
 mlct_status mlct_op_gram(mlct_ctx* ctx, int64_t rows, int64_t cols, const void* X_dev,
                          int64_t ldx, int32_t dtype, int32_t prec, mlct_op** out);
+/* Matrix-free symmetric operator: the library touches A only through
+ * products with blocks of probe vectors, which is all the estimator needs
+ * (Section 2.1: each sample costs matrix-vector products; Section 3.1
+ * counts cost in them).  Each recurrence step calls
+ *   apply(user, V_dev, AV_dev, B, hip_stream)
+ * which must enqueue AV = A V on hip_stream (the context's stream) and
+ * return 0; V_dev and AV_dev are device float32 arrays, row-major d x B
+ * (probe index fastest, leading dimension B; B = 64, columns past the
+ * block's probes are zero), owned by the library and valid for the call
+ * only; the function must not read or write outside them.  A non-zero
+ * return fails the call with MLCT_EDEVICE.  Precision MLCT_FP32 (FP32
+ * vectors, FP64 moment sums); mlct_moments, mlct_estimate (without
+ * MLCT_EXACT_LOW), mlct_select_levels, mlct_estimate_auto and the learned
+ * level accept it; the interval [a, b] must be given (no Lanczos on FP32
+ * products): a = b = NaN, mlct_bounds, mlct_lanczos, mlct_autotune and the
+ * CSR-only calls fail with MLCT_EUNSUPPORTED.  The function is called from
+ * the thread that makes the library call.  Errors: EINVAL (d < 1, no
+ * function). */
+typedef int32_t (*mlct_apply_fn)(void* user, const float* V_dev, float* AV_dev, int64_t B,
+                                 void* hip_stream);
+mlct_status mlct_op_callback(mlct_ctx* ctx, int64_t d, mlct_apply_fn apply, void* user,
+                             mlct_op** out);
 mlct_status mlct_op_destroy(mlct_op* op);
 /* Copy the d x d matrix of a dense or Gram operator to the host as float64,
  * row-major (out_host: d*d doubles).  EINVAL for CSR operators. */
@@ -405,12 +428,12 @@ mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems, const mlct_batch_
                                 int32_t prec, int32_t mode, mlct_result* outs);
 
 /* Triangle count tr(A^3)/6 of a 0/1 pattern CSR graph (Section 2.1 example,
- * Section 5.5): per probe, exact int32 y = A z and w = A y with int64
+ * Section 5.4): per probe, exact int32 y = A z and w = A y with int64
  * w1 = z.y, w2 = y.y, w3 = y.w.  w_out (host, m x 3 int64, may be NULL). */
 typedef struct {
   int64_t sum_w3;
   double estimate;     /* sum w3 / (6 m) */
-  double estimate_cv;  /* control-variate estimate (Section 5.5)           */
+  double estimate_cv;  /* control-variate estimate (Section 5.4)           */
   double a1, a2;       /* regression coefficients of w3 on (w1, w2)        */
 } mlct_tri_result;
 
@@ -423,11 +446,11 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
  * correction of the standardised residual (q - q_c)/mu_0 in two stages, a
  * linear least-squares fit on the standardised inputs u_f (mu_f / mu_0 for
  * f = 1..n_cheap, centred and scaled over the training probes; the linear
- * control variate of Section 5.5) and a small MLP (F = n_cheap + 1 inputs,
+ * control variate of Section 5.4) and a small MLP (F = n_cheap + 1 inputs,
  * two hidden tanh layers of 64 units, one output) trained on what the linear
  * fit leaves:  g = q_c + mu_0 (ybar + ysd (beta . u + net(u))).  It is
  * trained on pilot probes, then used as one more multilevel term (Section 2.3, eq.
- * eqn:telescope; the control-variate form of Section 5.5):
+ * eqn:telescope; the control-variate form of Section 5.4):
  *   Gamma = (1/M0) sum_{S0} g + (1/M1) sum_{S1} (q - g),
  * S0 at degree n_cheap, S1 at degree n_fine, probe sets disjoint from each
  * other and from the pilot, so Gamma is unbiased for tr p_{n_fine}(A_hat)
@@ -464,16 +487,60 @@ typedef struct {
 /* Pilot: Rademacher probes [0, m_pilot) of ``seed`` at degree n_fine
  * (symmetric moment form, arithmetic ``prec``), then training.  [a, b] as in
  * mlct_estimate (NaN, NaN = Lanczos).  1 <= n_cheap <= 15, n_cheap < n_fine,
- * m_pilot >= 8.  cfg may be NULL (defaults). */
+ * m_pilot >= 8.  The first max(2, train_fraction * m_pilot) probes train the
+ * network; the rest are held out (their moments are kept in the handle for
+ * mlct_learned_plan) and there must be at least 2 of them, else EINVAL.
+ * cfg may be NULL (defaults). */
 mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a, double b,
                              int32_t n_fine, int32_t n_cheap, int64_t m_pilot, uint64_t seed,
                              int32_t prec, const mlct_mlp_cfg* cfg, mlct_mlp** out);
 /* Estimate with the learned level: S0 = probe ids [0, M0), S1 = ids
  * [M0, M0 + M1) of ``seed`` (seed must differ from the fit seed).  In the
  * result, level_mean/var[0] describe g over S0 and [1] describe q - g over
- * S1 (plain fallback: [1] = q over S1, M0 unused). */
+ * S1 (plain fallback: [1] = q over S1, M0 unused).  max_moment_ratio covers
+ * both sets; above 1 + 1e-3 the call fails with MLCT_ESPECTRUM, as
+ * mlct_estimate does. */
 mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* mlp,
                                   int64_t M0, int64_t M1, uint64_t seed, mlct_result* out);
+
+/* Per-probe values of the learned level on the given probes (arithmetic
+ * and form of the fit): fine = 0 runs the recurrence to n_cheap and returns
+ * g; fine = 1 runs it to n_fine and returns g (from the same probes' cheap
+ * moments) and q = z^T p_{n_fine}(A_hat) z in q_out.  g_out: host,
+ * probes->m doubles; q_out: host, probes->m doubles, or NULL (required
+ * NULL when fine = 0).  The network is used whatever the fallback flag says.
+ * Errors: EINVAL (arguments), ESPECTRUM as mlct_estimate. */
+mlct_status mlct_learned_eval(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* mlp,
+                              const mlct_probes* probes, int32_t fine, double* g_out,
+                              double* q_out);
+
+/* The learned level inside the multilevel estimator (Section 2.3, eq.
+ * eqn:telescope; Section 4, eq. eqn:multiEstimator).  With
+ * S(l) = z^T p^{(l)} z the truncation of the degree-n_fine interpolant to
+ * degree l (eq. def:qlevels), except S(n_cheap) = g, and S(-1) = 0, level k
+ * of levels {l_1 < ... < l_L = n_fine} is Q_k = S(l_k) - S(l_{k-1}) on its
+ * own m_k probes (ids [off_k, off_k + m_k) of ``seed``, off_k the sum of the
+ * earlier m).  The levels telescope to S(n_fine) = z^T p_{n_fine} z, so the
+ * estimate is unbiased for tr p_{n_fine}(A_hat) whichever levels are used:
+ * {n_cheap, n_fine} is mlct_estimate_learned's two-term estimator, any set
+ * without n_cheap is the plain multilevel estimator, and a set with n_cheap
+ * puts g in the chain with the Chebyshev levels above it (or below it).  A
+ * sample of level k costs ceil(l_k / 2) matvecs.  The network is used
+ * whatever the fallback flag says.  Result as mlct_estimate (level_mean/var
+ * per level, max_moment_ratio, ESPECTRUM). */
+mlct_status mlct_estimate_learned_ml(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* mlp,
+                                     const mlct_levels* levels, uint64_t seed,
+                                     mlct_result* out);
+
+/* Levels and samples for mlct_estimate_learned_ml by the dynamic programme
+ * of Theorem thm:levels (as mlct_plan_levels, min_top 0, symmetric-form
+ * costs) on the fit's held-out pilot probes, with the per-probe terms
+ * chosen so that their prefix sums are the S(l) above: the plan chooses
+ * whether g enters the chain and which Chebyshev levels surround it.
+ * target / target_kind as in mlct_plan_levels (a variance of the value, or
+ * a matvec budget).  Errors: EINVAL (arguments, n_fine > 1024). */
+mlct_status mlct_learned_plan(mlct_ctx* ctx, const mlct_mlp* mlp, double target,
+                              int32_t target_kind, mlct_level_plan* out);
 mlct_status mlct_mlp_info_get(const mlct_mlp* mlp, mlct_mlp_info* out);
 /* Training loss after each epoch (standardised units): up to max values. */
 mlct_status mlct_mlp_loss_history(const mlct_mlp* mlp, float* out, int32_t max, int32_t* n_out);

@@ -22,7 +22,7 @@ Everything is NumPy/SciPy in float64, written from the paper's equations:
 * ``levelsel``   automatic level selection by dynamic programming
                  (Theorem thm:levels, eq. eqn:costrecurrence).
 * ``triangles``  triangle counting tr(A^3)/6 with the control variates of
-                 Section 5.5.
+                 Section 5.4.
 * ``lanczos``    Lanczos spectral interval (needed for the affine map of
                  Section 2.2; the paper gives no procedure).
 * ``mlp``        the learned control-variate level (a project addition).

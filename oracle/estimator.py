@@ -69,7 +69,7 @@ def exact_low_traces(A, d: int, alpha: float, beta: float):
     A symmetric: d, alpha tr A + beta d and 2 ||A_hat||_F^2 - d with
     ||A_hat||_F^2 = alpha^2 ||A||_F^2 + 2 alpha beta tr A + beta^2 d (the
     exactly computable low-degree traces remarked on at the end of Section
-    5.5)."""
+    5.4)."""
     if hasattr(A, "toarray"):
         trA = float(A.diagonal().sum())
         fro2 = float(A.multiply(A).sum())

@@ -1,7 +1,7 @@
 """Learned control-variate level: a small MLP g that predicts the fine-level
 quadratic form z^T p_n(A_hat) z from the cheap moments mu_0..mu_c of the same
 probe (a project addition, not in the paper; it is the control-variate idea
-of Section 5.5 with a learned instead of a linear map, used as one more
+of Section 5.4 with a learned instead of a linear map, used as one more
 multilevel term in the sense of Section 2.3).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).  FP64 throughout.
@@ -16,16 +16,24 @@ The library's g corrects the cheap truncation q_c = sum_{j<=c} c_j mu_j in
 two stages on the standardised residual t = ((q - q_c)/mu_0 - ybar)/ysd:
 inputs u_f = (mu_f/mu_0 - xmean_f)/xsd_f (f >= 1; ``standardize``), a
 linear least-squares fit beta of t on u (``linear_stage``; the linear
-control variate of Section 5.5), and the network on t - u.beta:
+control variate of Section 5.4), and the network on t - u.beta:
     g = q_c + mu_0 (ybar + ysd (u.beta + out(u))).
-The tests rebuild that composite from these functions and the oracle's
-moments.
+``fit_affine`` builds the affine stages from training moments and
+``composite_g`` evaluates g (FP64, or with the inference's bfloat16
+roundings of inputs, weights and hidden activations).
 
 Estimator (unbiased for any fixed g): with disjoint probe sets S0 (cheap
 degree, M0 probes) and S1 (fine degree, M1 probes), both disjoint from the
 pilot that trained g,
     Gamma = (1/M0) sum_{S0} g(x) + (1/M1) sum_{S1} (q - g(x)),
     Var   = s0^2 / M0 + s1^2 / M1.
+More generally g is one more level of the multilevel chain (Section 2.3,
+eq. eqn:telescope): with S(l) the truncation of the fine interpolant to
+degree l (eq. def:qlevels), except S(n_cheap) = g and S(-1) = 0, the level
+variables S(l_k) - S(l_{k-1}) over independent probe sets telescope to
+S(n_fine) = q (``chain_value``, ``learned_ml_estimate``), and
+``learned_terms`` gives the pilot table on which the level-selection
+programme of Theorem thm:levels places g among the Chebyshev levels.
 """
 from __future__ import annotations
 
@@ -176,3 +184,90 @@ def learned_estimate(g_s0: np.ndarray, q_s1: np.ndarray, g_s1: np.ndarray):
     val = float(np.mean(g_s0) + np.mean(d1))
     var = float(np.var(g_s0, ddof=1) / M0 + np.var(d1, ddof=1) / M1)
     return val, var
+
+
+# ---- the library's composite g and the learned multilevel chain -------------
+
+def bf16_round(x) -> np.ndarray:
+    """Round to bfloat16 (8 significant bits, round to nearest, ties to even)
+    through float32, returned as float64: the rounding the inference applies
+    to its inputs, weights and hidden activations."""
+    a = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    a = ((a + 0x7FFF + ((a >> 16) & 1)) >> 16) << 16
+    return a.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@dataclasses.dataclass
+class Affine:
+    """Target and input standardisation and the linear stage of g."""
+    ybar: float
+    ysd: float
+    xmean: np.ndarray  # [F]
+    xsd: np.ndarray    # [F]
+    lin: np.ndarray    # [F], lin[0] = 0
+
+
+def fit_affine(mu: np.ndarray, c: np.ndarray, F: int) -> Affine:
+    """The affine stages from the training probes' moments mu [N, n+1] and
+    the fine interpolant's coefficients c [n+1]: t = (q - q_c)/mu_0
+    standardised by its mean and unbiased standard deviation, inputs
+    mu_f/mu_0 standardised by ``standardize``, and the linear fit of the
+    standardised t on them (``linear_stage``)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    r = (mu @ c - mu[:, :F] @ c[:F]) / mu[:, 0]
+    ybar, ysd = float(r.mean()), float(r.std(ddof=1))
+    Xraw = mu[:, :F] / mu[:, :1]
+    xm, xs = standardize(Xraw)
+    lin = linear_stage(standardized(Xraw, xm, xs), (r - ybar) / ysd)
+    return Affine(ybar, ysd, xm, xs, lin)
+
+
+def composite_g(mu: np.ndarray, c: np.ndarray, F: int, aff: Affine, p: Params,
+                bf16: bool = True) -> np.ndarray:
+    """g = q_c + mu_0 (ybar + ysd (u.beta + out(u))) per row of mu, with
+    q_c = sum_{j<F} c_j mu_j and u the standardised inputs.  With bf16 the
+    network's inputs, weights and hidden activations are rounded to bfloat16
+    as the inference does (the affine parts stay FP64)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    u = standardized(mu[:, :F] / mu[:, :1], aff.xmean[:F], aff.xsd[:F])
+    lin = u @ aff.lin[:F]
+    if bf16:
+        r = bf16_round
+        x = r(u)
+        h1 = r(np.tanh(x @ r(p.W1).T + r(p.b1)))
+        h2 = r(np.tanh(h1 @ r(p.W2).T + r(p.b2)))
+        out = h2 @ r(p.w3) + float(r(p.b3))
+    else:
+        out, _ = forward(p, u)
+    qc = mu[:, :F] @ c[:F]
+    return qc + mu[:, 0] * (aff.ybar + aff.ysd * (lin + out))
+
+
+def chain_value(mu: np.ndarray, c: np.ndarray, level: int, n_cheap: int,
+                g: np.ndarray) -> np.ndarray:
+    """S(l) per row: the truncation sum_{j<=l} c_j mu_j of the fine
+    interpolant (eq. def:qlevels), except S(n_cheap) = g and S(-1) = 0."""
+    mu = np.asarray(mu, dtype=np.float64)
+    if level < 0:
+        return np.zeros(mu.shape[0])
+    if level == n_cheap:
+        return np.asarray(g, dtype=np.float64)
+    return mu[:, :level + 1] @ c[:level + 1]
+
+
+def learned_ml_estimate(level_values):
+    """(Gamma, Var) of the multilevel estimator (eq. eqn:multiEstimator) from
+    the per-probe level variables S(l_k) - S(l_{k-1}) of each level."""
+    val = float(sum(np.mean(q) for q in level_values))
+    var = float(sum(np.var(q, ddof=1) / len(q) for q in level_values))
+    return val, var
+
+
+def learned_terms(mu: np.ndarray, c: np.ndarray, n_cheap: int, g: np.ndarray) -> np.ndarray:
+    """Per-probe terms whose prefix sums are the chain values S(0..n), the
+    pilot table on which the level-selection programme (Theorem thm:levels)
+    decides where g enters the chain."""
+    mu = np.asarray(mu, dtype=np.float64)
+    n = mu.shape[1] - 1
+    S = np.stack([chain_value(mu, c, l, n_cheap, g) for l in range(n + 1)], axis=1)
+    return np.diff(np.concatenate([np.zeros((mu.shape[0], 1)), S], axis=1), axis=1)

@@ -1,4 +1,4 @@
-"""Triangle counting by trace estimation (Section 2.1 example, Section 5.5).
+"""Triangle counting by trace estimation (Section 2.1 example, Section 5.4).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
@@ -10,7 +10,7 @@ integers from two matvecs (the symmetric form of the Section 2.1 footnote):
 
 Plain estimate: sum(w3) / (6 m).
 
-Control variates (Section 5.5): for any a1, a2,
+Control variates (Section 5.4): for any a1, a2,
 tr(A^3) = E[z^T (A^3 - a2 A^2 - a1 A) z] + a1 tr(A) + a2 tr(A^2), and for a
 symmetric 0/1 matrix without self-loops tr(A) = 0, tr(A^2) = nnz(A).  The
 paper picks a1, a2 "through linear regression" on the stored moments; here

@@ -157,13 +157,22 @@ std::string tune_key(const mlct_op* op, int prec, int64_t bpad) {
   return buf;
 }
 
-int tune_lookup(const mlct_ctx* ctx, const std::string& key) {
+// A cached decision, or -1 when there is none or the file holds a value the
+// autotuner could not have chosen (a hand-edited or foreign cache).
+int tune_lookup(const mlct_ctx* ctx, const std::string& key, const std::vector<int>& allowed) {
   for (const std::string& l : ctx->tune_lines)
     if (l.compare(0, key.size(), key) == 0 && l.size() > key.size() + 3 &&
-        l.compare(key.size(), 3, " = ") == 0)
-      return std::atoi(l.c_str() + key.size() + 3);
+        l.compare(key.size(), 3, " = ") == 0) {
+      const int v = std::atoi(l.c_str() + key.size() + 3);
+      for (int a : allowed)
+        if (v == a) return v;
+      return -1;
+    }
   return -1;
 }
+// The autotuner's candidates: CSR workgroup caps and dense tile choices.
+const std::vector<int> kCsrGroupCands = {512, 1024, 2048, 4096};
+const std::vector<int> kDenseTileCands = {0, 2, 1, 3};
 
 void tune_store(mlct_ctx* ctx, const std::string& key, int value) {
   const std::string line = key + " = " + std::to_string(value);
@@ -228,7 +237,7 @@ mlct_status check_func(mlct_ctx* ctx, mlct_func f, double a, double b) {
   return MLCT_OK;
 }
 
-constexpr int kMaxDegree = 4096;  // DCT samples live in 32 KB of LDS
+constexpr int kMaxDegree = 4096;  // DCT samples and cosines live in 48 KB of LDS
 
 mlct_status check_probes(mlct_ctx* ctx, const mlct_op* op, const mlct_probes* pr) {
   if (!pr) return fail(ctx, MLCT_EINVAL, "probes is NULL");
@@ -256,24 +265,44 @@ constexpr int kSharedBlocks = 4;
 // Runs ``degree`` (direct) or ceil(degree/2) (symmetric form) steps on the
 // ``src.active`` probes of one block and writes their moments mu_0..mu_n
 // (n = degree) into mu_rows (device, row stride ldmu).
-template <typename T>
-mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
-                          int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu) {
+// Device buffers of one CSR probe block: the two vector buffers, the moment
+// partials of every step, the reduced dots and the hub chunk sums.
+struct CsrBlockBufs {
+  void* v0 = nullptr;
+  void* v1 = nullptr;
+  double* part = nullptr;
+  double* dots = nullptr;
+  void* hub = nullptr;
+  bool timed = true;  // record kernel timing events (these may allocate)
+};
+
+// Bytes of each buffer for a block of degree ``degree`` in form ``mode``.
+struct CsrBlockSizes {
+  size_t v, part, dots, hub;
+};
+CsrBlockSizes csr_block_sizes(const mlct_op* op, size_t tsz, int mode, int degree) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
   const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
-  const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(T);
+  CsrBlockSizes z;
+  z.v = (size_t)op->d * kBlockProbes * tsz;
+  z.part = (size_t)2 * plan.ngroups * kBlockProbes * (S + 1) * sizeof(double);
+  z.dots = (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double);
+  z.hub = op->csr.hub_n > 0 ? (size_t)op->csr.hub_chunks * kBlockProbes * tsz : 0;
+  return z;
+}
+
+template <typename T>
+mlct_status run_block_csr_in(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
+                             int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu,
+                             const CsrBlockBufs& bb) {
+  const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
+  const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
   const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;  // doubles per step
-  void *v0, *v1, *part, *dots;
-  CHECK(ws_get(ctx, WS_V0, vbytes, &v0));
-  CHECK(ws_get(ctx, WS_V1, vbytes, &v1));
-  CHECK(ws_get(ctx, WS_PART, pstep * (S + 1) * sizeof(double), &part));
-  CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &dots));
-  T* buf[2] = {static_cast<T*>(v0), static_cast<T*>(v1)};
-  double* P = static_cast<double*>(part);
+  T* buf[2] = {static_cast<T*>(bb.v0), static_cast<T*>(bb.v1)};
+  double* P = bb.part;
+  void* dots = bb.dots;
+  void* hub = bb.hub;
   hipStream_t s = ctx->stream;
-  void* hub = nullptr;
-  if (op->csr.hub_n > 0)
-    CHECK(ws_get(ctx, WS_HUB, (size_t)op->csr.hub_chunks * kBlockProbes * sizeof(T), &hub));
   HIPCHK(ctx, launch_probe_init<T>(s, buf[0], op->d, src, plan, P));
   const int zdirect = src.entries ? 2 : 1;
   for (int k = 1; k <= S; ++k) {
@@ -284,9 +313,76 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
     const T ca = (T)(first ? alpha : 2.0 * alpha);
     const T cb = (T)(first ? beta : 2.0 * beta);
     const int zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
-    LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
-    HIPCHK(ctx, launch_csr_step<T>(s, op->csr, vk, vm, ca, cb, !first, zmode, src, plan, hub,
-                                   P + pstep * k));
+    if (bb.timed) {
+      LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP);
+      HIPCHK(ctx, launch_csr_step<T>(s, op->csr, vk, vm, ca, cb, !first, zmode, src, plan, hub,
+                                     P + pstep * k));
+      tm.done();
+    } else {
+      HIPCHK(ctx, launch_csr_step<T>(s, op->csr, vk, vm, ca, cb, !first, zmode, src, plan, hub,
+                                     P + pstep * k));
+    }
+  }
+  HIPCHK(ctx, launch_reduce_partials(s, P, S + 1, 2, plan.ngroups, kBlockProbes,
+                                     static_cast<double*>(dots)));
+  HIPCHK(ctx, launch_assemble_moments(s, static_cast<double*>(dots), S + 1, kBlockProbes,
+                                      src.active, mode, degree, mu_rows, ldmu));
+  return MLCT_OK;
+}
+
+template <typename T>
+mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
+                          int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu) {
+  const CsrBlockSizes z = csr_block_sizes(op, sizeof(T), mode, degree);
+  CsrBlockBufs bb;
+  void* part;
+  void* dots;
+  CHECK(ws_get(ctx, WS_V0, z.v, &bb.v0));
+  CHECK(ws_get(ctx, WS_V1, z.v, &bb.v1));
+  CHECK(ws_get(ctx, WS_PART, z.part, &part));
+  CHECK(ws_get(ctx, WS_MISC, z.dots, &dots));
+  if (z.hub) CHECK(ws_get(ctx, WS_HUB, z.hub, &bb.hub));
+  bb.part = static_cast<double*>(part);
+  bb.dots = static_cast<double*>(dots);
+  return run_block_csr_in<T>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu, bb);
+}
+
+// One probe block through the sparse Gram operator A = X^T X + lambda I:
+// per step W = X V_k (rows x 64 scratch), then the recurrence over X^T W
+// (the shift enters cb as ca * lambda).
+// One probe block of a callback operator: per step the caller's function
+// writes W = A V_k, then the update kernel forms V_new and the partials.
+mlct_status run_block_callback(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
+                               int degree, int mode, ProbeSrc src, double* mu_rows,
+                               int64_t ldmu) {
+  const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
+  const CsrStepPlan plan = plan_csr(op->d, 0);
+  const size_t vb = (size_t)op->d * kBlockProbes * sizeof(float);
+  const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;
+  void *v0, *v1, *w, *part, *dots;
+  CHECK(ws_get(ctx, WS_V0, vb, &v0));
+  CHECK(ws_get(ctx, WS_V1, vb, &v1));
+  CHECK(ws_get(ctx, WS_CBW, vb, &w));
+  CHECK(ws_get(ctx, WS_PART, pstep * (S + 1) * sizeof(double), &part));
+  CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &dots));
+  float* buf[2] = {static_cast<float*>(v0), static_cast<float*>(v1)};
+  double* P = static_cast<double*>(part);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_probe_init<float>(s, buf[0], op->d, src, plan, P));
+  const int zdirect = src.entries ? 2 : 1;
+  for (int k = 1; k <= S; ++k) {
+    const float* vk = buf[(k - 1) & 1];
+    float* vm = buf[k & 1];
+    const bool first = (k == 1);
+    const float ca = (float)(first ? alpha : 2.0 * alpha);
+    const float cb = (float)(first ? beta : 2.0 * beta);
+    const int zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
+    const int32_t rc = op->cb_apply(op->cb_user, vk, static_cast<float*>(w), kBlockProbes,
+                                    static_cast<void*>(s));
+    if (rc != 0) return fail(ctx, MLCT_EDEVICE, "the operator's apply function returned %d", rc);
+    LaunchTimer tm(ctx, MLCT_KERNEL_CALLBACK_STEP);
+    HIPCHK(ctx, launch_callback_step(s, static_cast<const float*>(w), vk, vm, ca, cb, !first,
+                                     zmode, src, op->d, plan, P + pstep * k));
     tm.done();
   }
   HIPCHK(ctx, launch_reduce_partials(s, P, S + 1, 2, plan.ngroups, kBlockProbes,
@@ -296,9 +392,6 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
   return MLCT_OK;
 }
 
-// One probe block through the sparse Gram operator A = X^T X + lambda I:
-// per step W = X V_k (rows x 64 scratch), then the recurrence over X^T W
-// (the shift enters cb as ca * lambda).
 template <typename T>
 mlct_status run_block_gram_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                                int degree, int mode, ProbeSrc src, double* mu_rows,
@@ -506,6 +599,16 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
                              int64_t block) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
   void* tmp;
+  if (op->kind == OP_CALLBACK) {
+    const CsrStepPlan plan = plan_csr(op->d, 0);
+    const size_t vb = (size_t)op->d * kBlockProbes * sizeof(float);
+    CHECK(ws_get(ctx, WS_V0, vb, &tmp));
+    CHECK(ws_get(ctx, WS_V1, vb, &tmp));
+    CHECK(ws_get(ctx, WS_CBW, vb, &tmp));
+    CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * (S + 1) * sizeof(double), &tmp));
+    CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * kBlockProbes * sizeof(double), &tmp));
+    return MLCT_OK;
+  }
   if (op->kind == OP_CSR || op->kind == OP_GRAM_CSR) {
     const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
     const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
@@ -619,6 +722,11 @@ mlct_status run_block(mlct_ctx* ctx, const mlct_op* op, double alpha, double bet
       return run_block_csr<double>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
     return fail(ctx, MLCT_EUNSUPPORTED, "CSR operators support MLCT_FP32 and MLCT_FP64");
   }
+  if (op->kind == OP_CALLBACK) {
+    if (prec != MLCT_FP32)
+      return fail(ctx, MLCT_EUNSUPPORTED, "callback operators run in MLCT_FP32");
+    return run_block_callback(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
+  }
   if (op->kind == OP_GRAM_CSR) {
     if (prec == MLCT_FP32)
       return run_block_gram_csr<float>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu);
@@ -633,7 +741,7 @@ mlct_status run_block(mlct_ctx* ctx, const mlct_op* op, double alpha, double bet
 mlct_status run_probe_set(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                           int degree, int mode, int prec, const mlct_probes* pr, double* mu_dev,
                           int64_t ldmu) {
-  const bool sparse = op->kind == OP_CSR || op->kind == OP_GRAM_CSR;
+  const bool sparse = op->kind == OP_CSR || op->kind == OP_GRAM_CSR || op->kind == OP_CALLBACK;
   const int64_t width = sparse ? kBlockProbes : kDenseMaxBlock;
   for (int64_t p0 = 0; p0 < pr->m; p0 += width) {
     ProbeSrc src;
@@ -796,7 +904,7 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   op->csr.val = dtype == MLCT_DT_F32 ? static_cast<const float*>(val_dev) : nullptr;
   op->dtype = dtype;
   op->csr.max_row_nnz = hf[1];
-  op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
+  op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64), kCsrGroupCands));
   mlct_status st = MLCT_OK;
   if (op->csr.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csr, &op->hub_mem);
   if (st == MLCT_OK) st = refresh_bands(ctx, op);
@@ -898,7 +1006,7 @@ mlct_status mlct_op_gram_csr(mlct_ctx* ctx, int64_t rows, int64_t cols, int64_t 
   op->csr.ncols = rows;
   op->csr.nnz = nnz;
   op->csr.max_row_nnz = maxt;
-  op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64)));
+  op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64), kCsrGroupCands));
   mlct_status st = MLCT_OK;
   if (op->csrx.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csrx, &op->hubx_mem);
   if (st == MLCT_OK && op->csr.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csr, &op->hub_mem);
@@ -1027,8 +1135,9 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   CHECK(set_device(ctx));
   const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
   if (exact_low) {
-    if (op->kind == OP_GRAM_CSR)
-      return fail(ctx, MLCT_EUNSUPPORTED, "MLCT_EXACT_LOW needs ||A||_F, not formed for sparse Gram operators");
+    if (op->kind == OP_GRAM_CSR || op->kind == OP_CALLBACK)
+      return fail(ctx, MLCT_EUNSUPPORTED,
+                  "MLCT_EXACT_LOW needs tr A and ||A||_F, not available for this operator");
     lv.jmin = 3;
     CHECK(low_traces(ctx, op, alpha, beta, lv.low_tr));
   }
@@ -1106,10 +1215,29 @@ mlct_status mlct_op_dense(mlct_ctx* ctx, int64_t d, const void* A_dev, int64_t l
   return MLCT_OK;
 }
 
+mlct_status mlct_op_callback(mlct_ctx* ctx, int64_t d, mlct_apply_fn apply, void* user,
+                             mlct_op** out) {
+  if (!ctx || !out) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!apply) return fail(ctx, MLCT_EINVAL, "apply function is required");
+  if (d < 1 || d > ((int64_t)1 << 31) - 1) return fail(ctx, MLCT_EINVAL, "need 1 <= d < 2^31");
+  mlct_op* op = new (std::nothrow) mlct_op();
+  if (!op) return fail(ctx, MLCT_ENOMEM, "out of host memory");
+  op->ctx = ctx;
+  op->device = ctx->device;
+  op->kind = OP_CALLBACK;
+  op->d = d;
+  op->dtype = MLCT_DT_F32;
+  op->cb_apply = apply;
+  op->cb_user = user;
+  *out = op;
+  return MLCT_OK;
+}
+
 mlct_status mlct_op_read_dense(mlct_ctx* ctx, const mlct_op* op, double* out_host) {
   if (!ctx) return MLCT_EINVAL;
   ctx->err.clear();
-  if (!op || !out_host || op->kind == OP_CSR || op->kind == OP_GRAM_CSR)
+  if (!op || !out_host || (op->kind != OP_DENSE && op->kind != OP_GRAM))
     return fail(ctx, MLCT_EINVAL, "need a dense or Gram operator and an output array");
   CHECK(set_device(ctx));
   const void *a0, *a1;
@@ -1173,6 +1301,9 @@ mlct_status mlct_lanczos(mlct_ctx* ctx, const mlct_op* op, int32_t steps, uint64
   if (!ctx) return MLCT_EINVAL;
   ctx->err.clear();
   if (!op) return fail(ctx, MLCT_EINVAL, "op is required");
+  if (op->kind == OP_CALLBACK)
+    return fail(ctx, MLCT_EUNSUPPORTED,
+                "no FP64 products through a callback operator: give the interval [a, b]");
   if (steps < 1 || steps > kLanczosMaxSteps)
     return fail(ctx, MLCT_EINVAL, "steps must be in [1, %d]", kLanczosMaxSteps);
   if (!(rel_margin >= 0.0) || !std::isfinite(rel_margin))
@@ -1311,7 +1442,7 @@ struct Carver {
 };
 
 void mlp_free(mlct_mlp* m) {
-  void* ps[] = {m->theta, m->adam_m, m->adam_v, m->wbf16, m->coef};
+  void* ps[] = {m->theta, m->adam_m, m->adam_v, m->wbf16, m->coef, m->val_mu};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
@@ -1356,6 +1487,10 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
   const int64_t ldmu = n_fine + 1;
   const int64_t ntrain = std::max<int64_t>(2, (int64_t)(frac * m_pilot));
   const int64_t nval = m_pilot - ntrain;
+  if (nval < 2)
+    return fail(ctx, MLCT_EINVAL,
+                "train_fraction %g of %lld pilot probes leaves %lld held out (need >= 2)", frac,
+                (long long)m_pilot, (long long)nval);
   // workspace (all before the first launch)
   void *mu, *scratch;
   CHECK(ws_get(ctx, WS_MU, (size_t)m_pilot * ldmu * sizeof(double), &mu));
@@ -1414,6 +1549,8 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
   MLP_TRY(mlp_malloc(ctx, (void**)&m->adam_v, (size_t)P * 4));
   MLP_TRY(mlp_malloc(ctx, &m->wbf16, (size_t)P * 2));
   MLP_TRY(mlp_malloc(ctx, (void**)&m->coef, (size_t)(n_fine + 2) * 8));
+  MLP_TRY(mlp_malloc(ctx, (void**)&m->val_mu, (size_t)nval * ldmu * 8));
+  m->nval = nval;
   hipStream_t s = ctx->stream;
   const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
   // pilot moments and fine-level values q
@@ -1448,9 +1585,11 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
     m->aff.xsd[f] = hstats[2 + 16 + f];
     m->aff.lin[f] = hstats[2 + 32 + f];
   }
-  // held-out pilot probes: variance of q and of q - g
-  if (nval >= 2) {
+  // held-out pilot probes: variance of q and of q - g; their moments stay
+  // with the handle for the level planner
+  {
     const double* muv = static_cast<double*>(mu) + ntrain * ldmu;
+    MLP_HIP(hipMemcpyAsync(m->val_mu, muv, (size_t)nval * ldmu * 8, hipMemcpyDeviceToDevice, s));
     MLP_HIP(launch_mlp_infer(s, m->wbf16, F, m->coef, muv, ldmu, nval, m->aff, gval));
     MLP_HIP(launch_mlp_combine(s, q + ntrain, nval, q + ntrain, gval, nval, comb));
     MLP_HIP(launch_mlp_combine(s, gval, nval, gval, nullptr, 0, comb + 4));
@@ -1476,71 +1615,165 @@ mlct_status mlct_learned_fit(mlct_ctx* ctx, const mlct_op* op, mlct_func f, doub
   return MLCT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The learned multilevel chain: level k of L holds S(deg[k]) - S(deg[k-1])
+// over its own probes (ids off_k .. off_k + m_k - 1 of seed), where
+// S(l) = z^T p^{(l)} z (the truncation of the degree-n_fine interpolant),
+// S(n_cheap) = g and S(-1) = 0.  The levels telescope to S(n_fine).
+mlct_status learned_chain(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* m, int L,
+                          const int32_t* deg, const int64_t* mk, uint64_t seed,
+                          mlct_result* out) {
+  if (!op || !m || !out || !deg || !mk) return fail(ctx, MLCT_EINVAL, "op, mlp, levels and out are required");
+  if (L < 1 || L > MLCT_MAX_LEVELS) return fail(ctx, MLCT_EINVAL, "need 1 <= L <= %d", MLCT_MAX_LEVELS);
+  if (seed == m->seed) return fail(ctx, MLCT_EINVAL, "use a seed different from the pilot's");
+  if (op->d <= 0) return fail(ctx, MLCT_EINVAL, "empty operator");
+  const int nc = m->n_cheap, n = m->n_fine, F = m->F;
+  int64_t mmax = 0, rows_deg = 0;
+  for (int k = 0; k < L; ++k) {
+    if (deg[k] < 0 || (k && deg[k] <= deg[k - 1]))
+      return fail(ctx, MLCT_EINVAL, "level degrees must increase from 0");
+    if (mk[k] < 1 || mk[k] > ((int64_t)1 << 32)) return fail(ctx, MLCT_EINVAL, "level %d: need 1 <= m <= 2^32", k);
+    mmax = std::max(mmax, mk[k]);
+    rows_deg = std::max(rows_deg, mk[k] * (deg[k] + 1));
+  }
+  if (deg[L - 1] != n) return fail(ctx, MLCT_EINVAL, "the top level must be the fit's n_fine = %d", n);
+  CHECK(set_device(ctx));
+  const double alpha = 2.0 / (m->b - m->a), beta = -(m->a + m->b) / (m->b - m->a);
+  void *mu, *scratch;
+  CHECK(ws_get(ctx, WS_MU, (size_t)rows_deg * 8, &mu));
+  CHECK(reserve_block_ws(ctx, op, m->prec, MLCT_DOUBLING, n, mmax < kDenseMaxBlock ? mmax : kDenseMaxBlock));
+  CHECK(ws_get(ctx, WS_MLP, 2 * align8(mmax * 8) + align8((size_t)5 * L * 8) + 64, &scratch));
+  Carver cv{static_cast<char*>(scratch)};
+  double* g = cv.take<double>(mmax);
+  double* q = cv.take<double>(mmax);
+  double* st = cv.take<double>((size_t)5 * L);  // per level: 4 combine outputs + ratio
+  hipStream_t s = ctx->stream;
+  double* mud = static_cast<double*>(mu);
+  int64_t off = 0;
+  for (int k = 0; k < L; ++k) {
+    const int hi = deg[k], lo = k ? deg[k - 1] : -1;
+    mlct_probes pr{};
+    pr.kind = MLCT_PROBE_RADEMACHER;
+    pr.seed = seed;
+    pr.first_id = off;
+    pr.m = mk[k];
+    CHECK(run_probe_set(ctx, op, alpha, beta, hi, MLCT_DOUBLING, m->prec, &pr, mud, hi + 1));
+    const bool with_g = hi == nc || lo == nc;  // hi >= nc then, so mu holds F columns
+    if (with_g) HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, mud, hi + 1, mk[k], m->aff, g));
+    HIPCHK(ctx, launch_learned_level_q(s, mud, hi + 1, m->coef, hi, lo, nc, with_g ? g : nullptr,
+                                       mk[k], q));
+    HIPCHK(ctx, launch_mlp_combine(s, nullptr, 0, q, nullptr, mk[k], st + 4 * k));
+    HIPCHK(ctx, launch_moment_ratio(s, mud, hi + 1, hi + 1, mk[k], st + 4 * L + k));
+    off += mk[k];
+  }
+  std::vector<double> h((size_t)5 * L);
+  HIPCHK(ctx, hipMemcpyAsync(h.data(), st, h.size() * 8, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  mlct_result r{};
+  double mr = 0.0;
+  for (int k = 0; k < L; ++k) {
+    r.value += h[4 * k + 2];
+    r.level_mean[k] = h[4 * k + 2];
+    r.level_var[k] = h[4 * k + 3];
+    if (mk[k] > 1) r.est_var += h[4 * k + 3] / (double)mk[k];
+    else r.flags |= MLCT_FLAG_FEW_SAMPLES;
+    r.matvecs += mk[k] * ((deg[k] + 1) / 2);
+    r.probe_degrees += mk[k] * deg[k];
+    mr = std::max(mr, h[4 * L + k]);
+  }
+  if (r.flags & MLCT_FLAG_FEW_SAMPLES) r.est_var = NAN;
+  if (!(mr <= 1.0 + 1e-3))
+    return fail(ctx, MLCT_ESPECTRUM,
+                "max |mu_j|/|z|^2 = %g > 1: the spectrum is not inside [a, b] = [%g, %g]", mr,
+                m->a, m->b);
+  r.max_moment_ratio = mr;
+  r.log_scale = m->log_scale;
+  r.estimate = r.value * std::exp(r.log_scale);
+  r.interval_a = m->a;
+  r.interval_b = m->b;
+  if (m->prec == MLCT_BF16X3) r.flags |= MLCT_FLAG_BF16;
+  if (!std::isfinite(r.estimate)) r.flags |= MLCT_FLAG_OVERFLOW;
+  *out = r;
+  return MLCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 mlct_status mlct_estimate_learned(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* m,
                                   int64_t M0, int64_t M1, uint64_t seed, mlct_result* out) {
   if (!ctx) return MLCT_EINVAL;
   ctx->err.clear();
   if (!op || !m || !out) return fail(ctx, MLCT_EINVAL, "op, mlp and out are required");
-  if (seed == m->seed) return fail(ctx, MLCT_EINVAL, "use a seed different from the pilot's");
   const bool learned = !m->fallback;
   if (M1 < 2 || (learned && M0 < 2)) return fail(ctx, MLCT_EINVAL, "need M0, M1 >= 2");
-  CHECK(set_device(ctx));
-  const int nc = m->n_cheap, n = m->n_fine, F = m->F;
-  const double alpha = 2.0 / (m->b - m->a), beta = -(m->a + m->b) / (m->b - m->a);
-  const int64_t M0u = learned ? M0 : 0;
-  void *mu0, *mu1, *scratch, *res;
-  CHECK(ws_get(ctx, WS_MU2, (size_t)(M0u > 0 ? M0u : 1) * (nc + 1) * 8, &mu0));
-  CHECK(ws_get(ctx, WS_MU, (size_t)M1 * (n + 1) * 8, &mu1));
-  const int64_t mx = std::max(M0u, M1);
-  CHECK(reserve_block_ws(ctx, op, m->prec, MLCT_DOUBLING, n, mx < kDenseMaxBlock ? mx : kDenseMaxBlock));
-  CHECK(ws_get(ctx, WS_MLP, align8((M0u + 1) * 8) + 2 * align8(M1 * 8) + 64, &scratch));
-  CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_result), &res));
-  Carver cv{static_cast<char*>(scratch)};
-  double* g0 = cv.take<double>(M0u + 1);
-  double* g1 = cv.take<double>(M1);
-  double* q1 = cv.take<double>(M1);
-  double* comb = cv.take<double>(4);
-  hipStream_t s = ctx->stream;
-  mlct_probes pr{};
-  pr.kind = MLCT_PROBE_RADEMACHER;
-  pr.seed = seed;
   if (learned) {
-    pr.first_id = 0;
-    pr.m = M0u;
-    CHECK(run_probe_set(ctx, op, alpha, beta, nc, MLCT_DOUBLING, m->prec, &pr,
-                        static_cast<double*>(mu0), nc + 1));
-    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu0), nc + 1, M0u,
-                                 m->aff, g0));
+    const int32_t deg[2] = {m->n_cheap, m->n_fine};
+    const int64_t mk[2] = {M0, M1};
+    return learned_chain(ctx, op, m, 2, deg, mk, seed, out);
   }
-  pr.first_id = M0u;
-  pr.m = M1;
-  CHECK(run_probe_set(ctx, op, alpha, beta, n, MLCT_DOUBLING, m->prec, &pr,
-                      static_cast<double*>(mu1), n + 1));
-  HIPCHK(ctx, launch_qvals(s, static_cast<double*>(mu1), n + 1, m->coef, n, M1, q1));
-  if (learned)
-    HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, F, m->coef, static_cast<double*>(mu1), n + 1, M1,
-                                 m->aff, g1));
-  HIPCHK(ctx, launch_mlp_combine(s, g0, M0u, q1, learned ? g1 : nullptr, M1, comb));
-  double hc[4];
-  HIPCHK(ctx, hipMemcpyAsync(hc, comb, sizeof hc, hipMemcpyDeviceToHost, s));
-  CHECK(sync_stream(ctx));
-  mlct_result r{};
-  r.value = (learned ? hc[0] : 0.0) + hc[2];
-  r.est_var = (learned ? hc[1] / M0u : 0.0) + hc[3] / M1;
-  r.log_scale = m->log_scale;
-  r.estimate = r.value * std::exp(r.log_scale);
-  r.level_mean[0] = learned ? hc[0] : 0.0;
-  r.level_var[0] = learned ? hc[1] : 0.0;
-  r.level_mean[1] = hc[2];
-  r.level_var[1] = hc[3];
-  r.matvecs = M0u * ((nc + 1) / 2) + M1 * ((n + 1) / 2);
-  r.probe_degrees = M0u * nc + M1 * n;
-  r.interval_a = m->a;
-  r.interval_b = m->b;
-  r.max_moment_ratio = 0.0;
-  r.flags = learned ? 0u : MLCT_FLAG_LEARNED_FALLBACK;
-  if (!std::isfinite(r.estimate)) r.flags |= MLCT_FLAG_OVERFLOW;
+  // plain fallback: q over ids [0, M1), reported as level 1
+  const int32_t deg[1] = {m->n_fine};
+  const int64_t mk[1] = {M1};
+  mlct_result r;
+  CHECK(learned_chain(ctx, op, m, 1, deg, mk, seed, &r));
+  r.level_mean[1] = r.level_mean[0];
+  r.level_var[1] = r.level_var[0];
+  r.level_mean[0] = r.level_var[0] = 0.0;
+  r.flags |= MLCT_FLAG_LEARNED_FALLBACK;
   *out = r;
+  return MLCT_OK;
+}
+
+mlct_status mlct_estimate_learned_ml(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* m,
+                                     const mlct_levels* levels, uint64_t seed,
+                                     mlct_result* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!levels) return fail(ctx, MLCT_EINVAL, "levels are required");
+  return learned_chain(ctx, op, m, levels->L, levels->degree, levels->m, seed, out);
+}
+
+mlct_status mlct_learned_eval(mlct_ctx* ctx, const mlct_op* op, const mlct_mlp* m,
+                              const mlct_probes* probes, int32_t fine, double* g_out,
+                              double* q_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !m || !probes || !g_out) return fail(ctx, MLCT_EINVAL, "op, mlp, probes and g_out are required");
+  if (fine != 0 && fine != 1) return fail(ctx, MLCT_EINVAL, "fine must be 0 or 1");
+  if (!fine && q_out) return fail(ctx, MLCT_EINVAL, "q_out needs fine = 1");
+  CHECK(check_probes(ctx, op, probes));
+  CHECK(set_device(ctx));
+  const int deg = fine ? m->n_fine : m->n_cheap;
+  const int64_t rows = probes->m, ld = deg + 1;
+  const double alpha = 2.0 / (m->b - m->a), beta = -(m->a + m->b) / (m->b - m->a);
+  void *mu, *scratch;
+  CHECK(ws_get(ctx, WS_MU, (size_t)rows * ld * 8, &mu));
+  CHECK(reserve_block_ws(ctx, op, m->prec, MLCT_DOUBLING, deg, rows < kDenseMaxBlock ? rows : kDenseMaxBlock));
+  CHECK(ws_get(ctx, WS_MLP, 2 * align8(rows * 8) + 64, &scratch));
+  Carver cv{static_cast<char*>(scratch)};
+  double* g = cv.take<double>(rows);
+  double* q = cv.take<double>(rows);
+  double* ratio = cv.take<double>(1);
+  hipStream_t s = ctx->stream;
+  double* mud = static_cast<double*>(mu);
+  CHECK(run_probe_set(ctx, op, alpha, beta, deg, MLCT_DOUBLING, m->prec, probes, mud, ld));
+  HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, m->F, m->coef, mud, ld, rows, m->aff, g));
+  if (fine) HIPCHK(ctx, launch_qvals(s, mud, ld, m->coef, deg, rows, q));
+  HIPCHK(ctx, launch_moment_ratio(s, mud, ld, deg + 1, rows, ratio));
+  double mr = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(&mr, ratio, 8, hipMemcpyDeviceToHost, s));
+  CHECK(sync_stream(ctx));
+  if (!(mr <= 1.0 + 1e-3))
+    return fail(ctx, MLCT_ESPECTRUM,
+                "max |mu_j|/|z|^2 = %g > 1: the spectrum is not inside [a, b] = [%g, %g]", mr,
+                m->a, m->b);
+  HIPCHK(ctx, hipMemcpy(g_out, g, (size_t)rows * 8, hipMemcpyDeviceToHost));
+  if (q_out) HIPCHK(ctx, hipMemcpy(q_out, q, (size_t)rows * 8, hipMemcpyDeviceToHost));
   return MLCT_OK;
 }
 
@@ -2180,6 +2413,26 @@ extern "C" mlct_status mlct_plan_levels(mlct_ctx* ctx, const double* terms, int6
                         target, target_kind, min_top, out);
 }
 
+extern "C" mlct_status mlct_learned_plan(mlct_ctx* ctx, const mlct_mlp* m, double target,
+                                         int32_t target_kind, mlct_level_plan* out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!m) return fail(ctx, MLCT_EINVAL, "mlp is required");
+  const int n = m->n_fine;
+  CHECK(check_plan_args(ctx, m->nval, n, MLCT_DOUBLING, target, target_kind, out));
+  CHECK(set_device(ctx));
+  void *t, *scratch;
+  CHECK(ws_get(ctx, WS_MU, (size_t)m->nval * (n + 1) * sizeof(double), &t));
+  CHECK(ws_get(ctx, WS_MLP, align8(m->nval * 8) + 64, &scratch));
+  double* g = static_cast<double*>(scratch);
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_mlp_infer(s, m->wbf16, m->F, m->coef, m->val_mu, n + 1, m->nval, m->aff, g));
+  HIPCHK(ctx, launch_learned_terms(s, m->val_mu, n + 1, m->coef, n, m->n_cheap, g, m->nval,
+                                   static_cast<double*>(t)));
+  return plan_on_device(ctx, static_cast<const double*>(t), n + 1, nullptr, m->nval, n,
+                        MLCT_DOUBLING, target, target_kind, 0, out);
+}
+
 extern "C" mlct_status mlct_select_levels(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double a,
                                           double b, int32_t n, int64_t m_pilot, uint64_t seed,
                                           int32_t prec, int32_t mode, double target,
@@ -2309,6 +2562,8 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   if (!ctx) return MLCT_EINVAL;
   ctx->err.clear();
   if (!op) return fail(ctx, MLCT_EINVAL, "op is required");
+  if (op->kind == OP_CALLBACK)
+    return fail(ctx, MLCT_EUNSUPPORTED, "callback operators have no launch shapes to tune");
   CHECK(set_device(ctx));
   const bool csr = op->kind == OP_CSR || op->kind == OP_GRAM_CSR;
   if (csr) prec = MLCT_FP32;
@@ -2316,8 +2571,8 @@ extern "C" mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, 
   const int64_t block = csr ? kBlockProbes : std::max<int64_t>(32, std::min<int64_t>(B_max, kDenseMaxBlock));
   const int degree = 8;
   std::vector<int> cands;
-  if (csr) cands = {512, 1024, 2048, 4096};
-  else cands = {0, 2, 1, 3};
+  if (csr) cands = kCsrGroupCands;
+  else cands = kDenseTileCands;
   // workspace for the largest candidate
   const int saved_g = op->tuned_groups, saved_t = op->tuned_dense;
   // on every early return the operator keeps the launch shape it had

@@ -21,7 +21,8 @@ constexpr int kHubChunk = 256;
 
 // OP_GRAM_CSR: A = X^T X + lambda I with X sparse rows x cols, applied as two
 // SpMMs per step (X, then X^T).
-enum OpKind { OP_CSR = 0, OP_DENSE = 1, OP_GRAM = 2, OP_GRAM_CSR = 3 };
+// OP_CALLBACK: A applied by the caller's function (mlct_op_callback).
+enum OpKind { OP_CSR = 0, OP_DENSE = 1, OP_GRAM = 2, OP_GRAM_CSR = 3, OP_CALLBACK = 4 };
 
 // A CSR matrix as the step kernels see it (device arrays, borrowed or owned
 // by the operator), with its hub table (rows longer than kHubLen).
@@ -123,6 +124,9 @@ struct mlct_op {
   void* pack_lo = nullptr;
   void* a32 = nullptr;        // FP32 copy of an FP64 dense A (lazily built)
   void* a64 = nullptr;        // FP64 copy of an FP32 dense A (lazily built)
+  // callback operator: W = A V by the caller's function
+  mlct_apply_fn cb_apply = nullptr;
+  void* cb_user = nullptr;
 };
 
 // A trained learned level (mlct_learned_fit).  Device arrays are owned.
@@ -143,6 +147,9 @@ struct mlct_mlp {
   mlct::MlpAffine aff;
   double var_q = 0.0, var_resid = 0.0, mean_resid = 0.0, var_g = 0.0;
   int fallback = 0;
+  // moments of the held-out pilot probes, nval x (n_fine + 1) (device, owned)
+  double* val_mu = nullptr;
+  int64_t nval = 0;
   std::vector<float> loss_hist;
 };
 
@@ -152,7 +159,7 @@ namespace mlct {
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
   WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ,
-  WS_DPACK, WS_NSLOTS
+  WS_DPACK, WS_CBW, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -273,6 +280,13 @@ hipError_t launch_csr_bands(hipStream_t s, const int32_t* rowptr, int64_t d, int
                             int32_t* band);
 hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
                            int32_t* count, int cap);
+
+// ---- matrix-free operator (k_callback.hip) ----------------------------------
+// V_new = ca W + cb V_k (- V_prev) over the d x 64 block, W = A V_k from the
+// caller, with the moment partials of the CSR step (zmode as there).
+hipError_t launch_callback_step(hipStream_t s, const float* w, const float* vk, float* vm,
+                                float ca, float cb, bool has_prev, int zmode, ProbeSrc src,
+                                int64_t d, const CsrStepPlan& plan, double* part);
 
 // ---- automatic level selection (k_levels.hip) ------------------------------
 constexpr int kMaxPlanDegree = 1024;
@@ -417,5 +431,15 @@ hipError_t launch_mlp_prepare(hipStream_t s, const double* mu, int64_t ldmu, con
                               double* stats);
 hipError_t launch_mlp_combine(hipStream_t s, const double* a, int64_t na, const double* b,
                               const double* a2, int64_t nb, double* out);
+// Learned multilevel chain (S(l) = truncation to degree l, S(nc) = g,
+// S(-1) = 0): q = S(hi) - S(lo) per row; the planner's per-probe terms
+// (rows x (n+1), prefix sums = S); max_j |mu_j| / mu_0 over rows into out[0].
+hipError_t launch_learned_level_q(hipStream_t s, const double* mu, int64_t ldmu, const double* c,
+                                  int hi, int lo, int nc, const double* g, int64_t rows,
+                                  double* q);
+hipError_t launch_learned_terms(hipStream_t s, const double* mu, int64_t ldmu, const double* c,
+                                int n, int nc, const double* g, int64_t rows, double* t);
+hipError_t launch_moment_ratio(hipStream_t s, const double* mu, int64_t ldmu, int ncols,
+                               int64_t rows, double* out);
 
 }  // namespace mlct

@@ -12,30 +12,43 @@ namespace {
 // Coefficients of the degree-n interpolant at x_k = cos(k pi / n)
 // (Section 2.2): c_j = (2/n) sum''_k f~(x_k) cos(pi (j k mod 2n) / n), with
 // the end terms of the sum and c_0, c_n halved.  For exp the factor
-// exp((a+b)/2) is returned separately as a log-scale.
+// exp((a+b)/2) is returned separately as a log-scale.  The angle index
+// r = j k mod 2n is folded to [0, n/2] (cos(2 pi - t) = cos t,
+// cos(pi - t) = -cos t), so each workgroup evaluates n/2 + 1 cosines once
+// into LDS; workgroup w computes c_j for j = 256 w .. 256 w + 255, each as
+// one sequential sum over k with the index advanced by additions.
 __global__ __launch_bounds__(256) void cheb_dct_kernel(int kind, double power, double a,
                                                        double b, int n, double* __restrict__ c,
                                                        double* __restrict__ log_scale) {
-  extern __shared__ double fk[];
+  extern __shared__ double lds[];
+  double* fk = lds;              // n + 1 samples
+  double* cs = lds + (n + 1);    // cos(pi r / n), r = 0 .. n/2
   const double half = 0.5 * (b - a), mid = 0.5 * (a + b);
+  const int nh = n / 2;
   for (int k = threadIdx.x; k <= n; k += blockDim.x) {
     const double x = cos(M_PI * (double)k / (double)n);
     fk[k] = (kind == MLCT_EXP) ? exp(half * x) : eval_f(kind, power, half * x + mid);
   }
+  for (int r = threadIdx.x; r <= nh; r += blockDim.x) cs[r] = cos(M_PI * (double)r / (double)n);
   __syncthreads();
-  const int64_t two_n = 2 * (int64_t)n;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x) {
+  const int two_n = 2 * n;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j <= n) {
     double s = 0.0;
+    int jk = 0;  // j k mod 2n, advanced by j each step (j <= n < 2n)
     for (int k = 0; k <= n; ++k) {
-      const int64_t r = ((int64_t)j * k) % two_n;
+      const int r = jk > n ? two_n - jk : jk;
+      jk += j;
+      if (jk >= two_n) jk -= two_n;
+      const double cr = (r <= nh) ? cs[r] : -cs[n - r];
       const double w = (k == 0 || k == n) ? 0.5 : 1.0;
-      s += w * fk[k] * cos(M_PI * (double)r / (double)n);
+      s += w * fk[k] * cr;
     }
     s *= 2.0 / (double)n;
     if (j == 0 || j == n) s *= 0.5;
     c[j] = s;
   }
-  if (threadIdx.x == 0 && log_scale) *log_scale = (kind == MLCT_EXP) ? mid : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && log_scale) *log_scale = (kind == MLCT_EXP) ? mid : 0.0;
 }
 
 // flags[0]: bit0 rowptr[0] != 0, bit1 decreasing rowptr, bit2 rowptr[d] != nnz,
@@ -233,8 +246,8 @@ __global__ void level_finalize_kernel(const double* __restrict__ stats, LevelDes
 
 hipError_t launch_cheb_dct(hipStream_t s, int kind, double power, double a, double b, int n,
                            double* c_dev, double* log_scale_dev) {
-  cheb_dct_kernel<<<1, 256, (size_t)(n + 1) * sizeof(double), s>>>(kind, power, a, b, n, c_dev,
-                                                                    log_scale_dev);
+  const size_t lds = (size_t)(n + 1 + n / 2 + 1) * sizeof(double);
+  cheb_dct_kernel<<<(n + 256) / 256, 256, lds, s>>>(kind, power, a, b, n, c_dev, log_scale_dev);
   return hipGetLastError();
 }
 

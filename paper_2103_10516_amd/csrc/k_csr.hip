@@ -887,7 +887,8 @@ hipError_t launch_gram_z(hipStream_t s, const CsrMat& X, const CsrMat& XT, const
 }  // namespace
 
 CsrStepPlan plan_csr(int64_t d, int max_groups) {
-  const int64_t cap = max_groups > 0 ? max_groups : 2048;
+  // the cap is a multiple of 8 so that every XCD band gets whole workgroups
+  const int64_t cap = max_groups > 0 ? std::max<int64_t>(8, max_groups / 8 * 8) : 2048;
   int64_t g = (d + 255) / 256;
   g = (g + 7) / 8 * 8;
   if (g > cap) g = cap;

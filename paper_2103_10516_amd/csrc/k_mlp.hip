@@ -3,7 +3,7 @@
 //     g = q_c + mu_0 (ybar + ysd (beta . u + net(u))),
 // u = the probe's cheap moments mu_f / mu_0 (f = 1..F-1) standardised over
 // the training probes, beta the least-squares fit of the standardised
-// target on u (the linear control variate of Section 5.5), and
+// target on u (the linear control variate of Section 5.4), and
 // net(u) = w3 . tanh(W2 tanh(W1 u + b1) + b2) + b3 (64 hidden units per
 // layer) trained on what the linear fit leaves; used as an extra multilevel
 // term in the sense of Section 2.3.  Standardising matters: the moments of
@@ -228,6 +228,69 @@ __global__ void qvals_kernel(const double* __restrict__ mu, int64_t ldmu,
 }
 
 constexpr int kRT = 256;
+
+// Prefix values of the learned multilevel chain: S(l) = sum_{j<=l} c_j mu_j,
+// except S(nc) = g and S(-1) = 0.  q[p] = S(hi) - S(lo) of row p.
+__device__ __forceinline__ double chain_value(const double* r, const double* c, int l, int nc,
+                                              double g) {
+  if (l < 0) return 0.0;
+  if (l == nc) return g;
+  double s = 0.0;
+  for (int j = 0; j <= l; ++j) s += c[j] * r[j];
+  return s;
+}
+
+__global__ void learned_level_q_kernel(const double* __restrict__ mu, int64_t ldmu,
+                                       const double* __restrict__ c, int hi, int lo, int nc,
+                                       const double* __restrict__ g, int64_t rows,
+                                       double* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const double* r = mu + i * ldmu;
+  const double gi = g ? g[i] : 0.0;
+  q[i] = chain_value(r, c, hi, nc, gi) - chain_value(r, c, lo, nc, gi);
+}
+
+// Per-probe terms whose prefix sums are the chain values above (the pilot
+// table of the level planner): t_j = c_j mu_j, then t_nc = g - S(nc - 1) and
+// t_{nc+1} = S(nc + 1) - g.
+__global__ void learned_terms_kernel(const double* __restrict__ mu, int64_t ldmu,
+                                     const double* __restrict__ c, int n, int nc,
+                                     const double* __restrict__ g, int64_t rows,
+                                     double* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const double* r = mu + i * ldmu;
+  double* o = t + i * (int64_t)(n + 1);
+  double below = 0.0;  // S(nc - 1)
+  for (int j = 0; j <= n; ++j) {
+    o[j] = c[j] * r[j];
+    if (j < nc) below += o[j];
+  }
+  const double at = below + o[nc];  // S(nc) of the plain truncation
+  o[nc] = g[i] - below;
+  o[nc + 1] = (at + o[nc + 1]) - g[i];
+}
+
+// out[0] = max over rows and j <= ncols - 1 of |mu_j| / mu_0.  One workgroup.
+__global__ __launch_bounds__(kRT) void moment_ratio_kernel(const double* __restrict__ mu,
+                                                           int64_t ldmu, int ncols, int64_t rows,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[kRT];
+  double mr = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += kRT) {
+    const double* r = mu + i * ldmu;
+    const double inv0 = 1.0 / r[0];
+    for (int j = 0; j < ncols; ++j) mr = fmax(mr, fabs(r[j]) * inv0);
+  }
+  sh[threadIdx.x] = mr;
+  __syncthreads();
+  for (int st = kRT / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
 
 __device__ double rsum(double v, double* sh) {
   sh[threadIdx.x] = v;
@@ -475,6 +538,28 @@ hipError_t launch_mlp_prepare(hipStream_t s, const double* mu, int64_t ldmu, con
                               const double* coef, int F, int ntrain, float* X, float* y,
                               double* stats) {
   mlp_prepare_kernel<<<1, kRT, 0, s>>>(mu, ldmu, q, coef, F, ntrain, X, y, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_level_q(hipStream_t s, const double* mu, int64_t ldmu, const double* c,
+                                  int hi, int lo, int nc, const double* g, int64_t rows,
+                                  double* q) {
+  if (rows <= 0) return hipSuccess;
+  learned_level_q_kernel<<<(int)((rows + 255) / 256), 256, 0, s>>>(mu, ldmu, c, hi, lo, nc, g,
+                                                                    rows, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_terms(hipStream_t s, const double* mu, int64_t ldmu, const double* c,
+                                int n, int nc, const double* g, int64_t rows, double* t) {
+  if (rows <= 0) return hipSuccess;
+  learned_terms_kernel<<<(int)((rows + 255) / 256), 256, 0, s>>>(mu, ldmu, c, n, nc, g, rows, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_moment_ratio(hipStream_t s, const double* mu, int64_t ldmu, int ncols,
+                               int64_t rows, double* out) {
+  moment_ratio_kernel<<<1, kRT, 0, s>>>(mu, ldmu, ncols, rows, out);
   return hipGetLastError();
 }
 

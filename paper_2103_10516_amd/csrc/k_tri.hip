@@ -1,5 +1,5 @@
 // Exact triangle-count moments over a 0/1 pattern CSR (Section 2.1 example
-// and footnote, Section 5.5).  Per probe z, two integer SpMMs:
+// and footnote, Section 5.4).  Per probe z, two integer SpMMs:
 //   pass 1: y = A z   (int32, stored), w1 += z_i y_i, w2 += y_i^2   (int64)
 //   pass 2: w = A y   (int32, never stored), w3 += y_i w_i           (int64)
 // The passes run on the CSR step machinery (k_csr.hip, launch_tri_step);
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kRedThreads) void tri_reduce_kernel(
   if (threadIdx.x == 0) w[(p0 + p) * 3 + (pass == 1 ? slot : 2)] = sh[0];
 }
 
-// Control variates of Section 5.5: ordinary least squares of w3 on
+// Control variates of Section 5.4: ordinary least squares of w3 on
 // [1, w1, w2] (centred normal equations), then
 // T_cv = (mean(w3 - a1 w1 - a2 w2) + a1 tr(A) + a2 nnz) / 6 with tr(A) = 0.
 // If the centred 2x2 system is singular no control variate is used.

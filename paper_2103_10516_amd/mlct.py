@@ -34,6 +34,7 @@ MLCT_FLAG_FEW_SAMPLES, MLCT_FLAG_OVERFLOW, MLCT_FLAG_BF16 = 0x1, 0x2, 0x4
 MLCT_KERNEL_CSR_STEP, MLCT_KERNEL_DENSE_STEP, MLCT_KERNEL_TRI_STEP, MLCT_KERNEL_GRAM = 0, 1, 2, 3
 MLCT_KERNEL_BATCH_STEP, MLCT_KERNEL_GRAM_CSR_STEP = 4, 5
 MLCT_KERNEL_SLQ_SPMM, MLCT_KERNEL_SLQ_UPDATE = 6, 7
+MLCT_KERNEL_CALLBACK_STEP = 8
 
 
 class mlct_func(C.Structure):
@@ -393,10 +394,7 @@ def mlct_estimate_learned(ctx: Context, op: Op, mlp: Mlp, M0: int, M1: int, seed
     r = mlct_result()
     _check(ctx, _mlp_lib().mlct_estimate_learned(ctx.handle, op.handle, mlp.handle, M0, M1,
                                                  seed & ((1 << 64) - 1), C.byref(r)))
-    return {"estimate": r.estimate, "value": r.value, "log_scale": r.log_scale,
-            "est_var": r.est_var, "level_mean": np.array(r.level_mean[:2]),
-            "level_var": np.array(r.level_var[:2]), "matvecs": r.matvecs,
-            "probe_degrees": r.probe_degrees, "flags": r.flags}
+    return _result_dict(r, 2)
 
 
 def mlct_mlp_info_get(mlp: Mlp) -> dict:
@@ -616,3 +614,99 @@ def mlct_estimate_slq(ctx: Context, op: Op, kind: int, a: float, b: float, cheb_
             "level_var": np.array(r.level_var[:2]), "matvecs": r.matvecs,
             "probe_degrees": r.probe_degrees, "interval": (r.interval_a, r.interval_b),
             "flags": r.flags}
+
+
+def _result_dict(r: mlct_result, L: int) -> dict:
+    return {"estimate": r.estimate, "value": r.value, "log_scale": r.log_scale,
+            "est_var": r.est_var, "level_mean": np.array(r.level_mean[:L]),
+            "level_var": np.array(r.level_var[:L]), "matvecs": r.matvecs,
+            "probe_degrees": r.probe_degrees, "max_moment_ratio": r.max_moment_ratio,
+            "interval": (r.interval_a, r.interval_b), "flags": r.flags}
+
+
+def mlct_learned_eval(ctx: Context, op: Op, mlp: Mlp, probes: mlct_probes, fine: bool = False):
+    """Per-probe g (and, with fine=True, q = z^T p_n z) of the learned level.
+    Returns (g, q) with q None unless fine."""
+    h = _mlp_lib()
+    h.mlct_learned_eval.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(mlct_probes),
+                                    C.c_int32, C.c_void_p, C.c_void_p]
+    h.mlct_learned_eval.restype = C.c_int
+    g = np.empty(probes.m, dtype=np.float64)
+    q = np.empty(probes.m, dtype=np.float64) if fine else None
+    _check(ctx, h.mlct_learned_eval(ctx.handle, op.handle, mlp.handle, C.byref(probes),
+                                    1 if fine else 0, g.ctypes.data,
+                                    q.ctypes.data if fine else None))
+    return g, q
+
+
+def mlct_estimate_learned_ml(ctx: Context, op: Op, mlp: Mlp, degrees, m, seed: int) -> dict:
+    """Multilevel estimate with the learned level g at degree n_cheap in the
+    chain (see include/mlct.h)."""
+    h = _mlp_lib()
+    h.mlct_estimate_learned_ml.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.POINTER(mlct_levels), C.c_uint64,
+                                           C.POINTER(mlct_result)]
+    h.mlct_estimate_learned_ml.restype = C.c_int
+    L = len(degrees)
+    deg = (C.c_int32 * L)(*[int(x) for x in degrees])
+    mm = (C.c_int64 * L)(*[int(x) for x in m])
+    lv = mlct_levels(L, deg, mm)
+    r = mlct_result()
+    _check(ctx, h.mlct_estimate_learned_ml(ctx.handle, op.handle, mlp.handle, C.byref(lv),
+                                           seed & ((1 << 64) - 1), C.byref(r)))
+    return _result_dict(r, L)
+
+
+def mlct_learned_plan(ctx: Context, mlp: Mlp, target: float,
+                      target_kind: int = MLCT_TARGET_VARIANCE) -> dict:
+    """Levels and sample sizes for mlct_estimate_learned_ml from the fit's
+    held-out pilot probes."""
+    h = _mlp_lib()
+    h.mlct_learned_plan.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                    C.POINTER(mlct_level_plan)]
+    h.mlct_learned_plan.restype = C.c_int
+    p = mlct_level_plan()
+    _check(ctx, h.mlct_learned_plan(ctx.handle, mlp.handle, target, target_kind, C.byref(p)))
+    return _plan_dict(p)
+
+
+# int32 apply(void* user, const float* V, float* AV, int64 B, void* hip_stream)
+MLCT_APPLY_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p)
+
+
+class _DeviceArray:
+    """A borrowed device buffer presented to torch.as_tensor (no copy)."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2,
+                                         "strides": None}
+
+
+def mlct_op_callback(ctx: Context, d: int, apply) -> Op:
+    """Matrix-free operator.  ``apply(V, AV)`` receives two float32 device
+    tensors of shape (d, B) that view the library's buffers (valid during
+    the call only) and must write A @ V into AV on the current stream (the
+    context's stream).  Any exception fails the library call."""
+    import torch
+
+    def tramp(user, v_ptr, av_ptr, B, stream):
+        try:
+            V = torch.as_tensor(_DeviceArray(v_ptr, (d, B), "<f4"), device=f"cuda:{ctx.device}")
+            AV = torch.as_tensor(_DeviceArray(av_ptr, (d, B), "<f4"), device=f"cuda:{ctx.device}")
+            apply(V, AV)
+            return 0
+        except Exception:  # reported as MLCT_EDEVICE by the library
+            import traceback
+
+            traceback.print_exc()
+            return 1
+
+    fn = MLCT_APPLY_FN(tramp)
+    h = lib()
+    h.mlct_op_callback.argtypes = [C.c_void_p, C.c_int64, MLCT_APPLY_FN, C.c_void_p,
+                                   C.POINTER(C.c_void_p)]
+    h.mlct_op_callback.restype = C.c_int
+    out = C.c_void_p()
+    _check(ctx, h.mlct_op_callback(ctx.handle, d, fn, None, C.byref(out)))
+    return Op(ctx, out, (fn, apply), d)

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import cheb, estimator, moments, probes
 from paper_2103_10516_amd import workloads as wl
-from tests.tolerances import U32, U64, kappa_csr, moment_tol
+from tests.tolerances import U32, U64, fp_moment_tol, kappa_csr, moment_tol, rho_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -103,7 +103,13 @@ def test_moments_match_oracle(ctx, torch_dev, name, builder, a, b, prec, mode):
     want = _oracle_mu(g, a, b, n, np.arange(first, first + m), seed)
     alpha, beta = cheb.affine_map(a, b)
     rn = int(np.max(np.diff(g.rowptr)))
-    tol = moment_tol(n, g.d, U64 if prec == "fp64" else U32, rn, kappa_csr(g, alpha, beta))
+    kappa = kappa_csr(g, alpha, beta)
+    if prec == "fp64":
+        tol = moment_tol(n, g.d, U64, rn, kappa)
+    else:
+        tol = fp_moment_tol(n, g.d, "fp32", rn, rho_rows(g.to_scipy()), kappa, alpha, beta,
+                            mode == "doubling")
+        assert np.all(tol < 1e-2 * g.d)
     err = np.abs(got - want)
     assert np.all(got[:, 0] == g.d)
     worst = np.max(err / tol[None, :])

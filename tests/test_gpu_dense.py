@@ -7,11 +7,22 @@ import pytest
 
 from oracle import cheb, estimator, moments, probes
 from paper_2103_10516_amd import workloads as wl
-from tests.tolerances import U32, U64, moment_tol
+from tests.tolerances import U32, U64, fp_moment_tol, moment_tol, rho_rows
 
 pytestmark = pytest.mark.gpu
 
 U_BF16X3 = 2.0 ** -16  # hi+lo split: ~2^-17 per operand, lo*lo dropped
+
+
+def _tol(prec, n, d, Aop, alpha, beta, doubling):
+    """Per-degree tolerance: the worst-case model for FP64, the FP32 / BF16x3
+    model (no row-length factor beyond sqrt(d)) otherwise."""
+    kappa = float(np.max(np.abs(alpha * Aop + beta * np.eye(d)).sum(axis=1)))
+    if prec == "fp64":
+        return moment_tol(n, d, U64, d, kappa)
+    tol = fp_moment_tol(n, d, prec, d, rho_rows(Aop), kappa, alpha, beta, doubling)
+    assert np.all(tol < 1e-2 * d)
+    return tol
 
 
 @pytest.fixture(scope="module")
@@ -80,9 +91,8 @@ def test_dense_moments_match_oracle(ctx, prec, mode, d, m):
     Aop = A if prec == "fp64" else A.astype(np.float32).astype(np.float64)
     Z = probes.rademacher(d, np.arange(first, first + m), seed).T
     want = moments.moments_direct(Aop, Z, alpha, beta, n)
-    kappa = float(np.max(np.abs(alpha * Aop + beta * np.eye(d)).sum(axis=1)))
-    u = {"fp64": U64, "fp32": U32, "bf16x3": U_BF16X3}[prec]
-    tol = moment_tol(n, d, u, d, kappa)
+    tol = _tol(prec, n, d, Aop, alpha, beta, mode == "doubling")
+    assert np.all(got[:, 0] == d)
     worst = float(np.max(np.abs(got - want) / tol[None, :]))
     print(f"{prec} {mode} d={d}: worst err/tol {worst:.3g}, max err {np.max(np.abs(got - want)):.3g}")
     assert worst <= 1.0
@@ -108,10 +118,36 @@ def test_dense_bf16x3_wide_blocks(ctx, mode, d, m):
     Aop = A.astype(np.float32).astype(np.float64)
     Z = probes.rademacher(d, sel, seed).T
     want = moments.moments_direct(Aop, Z, alpha, beta, n)
-    kappa = float(np.max(np.abs(alpha * Aop + beta * np.eye(d)).sum(axis=1)))
-    tol = moment_tol(n, d, U_BF16X3, d, kappa)
+    tol = _tol("bf16x3", n, d, Aop, alpha, beta, mode == "doubling")
+    assert np.all(got[:, 0] == d)
     worst = float(np.max(np.abs(got[sel] - want) / tol[None, :]))
     print(f"wide bf16x3 {mode} d={d} m={m}: worst err/tol {worst:.3g}")
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("mode", ["direct", "doubling"])
+@pytest.mark.parametrize("m", [320, 512])
+def test_dense_skinny_wide_blocks(ctx, prec, mode, m):
+    """BF16x3 blocks of 320 and 512 probes run the packed skinny kernel (one
+    workgroup per 64 probes x 16 rows); FP32 takes square tiles.  Probes at
+    both ends and in the middle against the oracle."""
+    from paper_2103_10516_amd import mlct
+
+    d = 1024
+    A, lam = wl.random_symmetric(d, 31, -1.0, 2.0)
+    a, b, n, seed = -1.2, 2.2, 25, 9
+    op = _dense(ctx, A, np.float32)
+    M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    got = mlct.mlct_moments(ctx, op, a, b, n, mlct.rademacher_probes(seed, m), _prec(prec), M)
+    sel = np.r_[0:4, 60:68, m // 2:m // 2 + 4, m - 4:m]
+    alpha, beta = cheb.affine_map(a, b)
+    Aop = A.astype(np.float32).astype(np.float64)
+    want = moments.moments_direct(Aop, probes.rademacher(d, sel, seed).T, alpha, beta, n)
+    tol = _tol(prec, n, d, Aop, alpha, beta, mode == "doubling")
+    assert np.all(got[:, 0] == d)
+    worst = float(np.max(np.abs(got[sel] - want) / tol[None, :]))
+    print(f"skinny-wide {prec} {mode} m={m}: worst err/tol {worst:.3g}")
     assert worst <= 1.0
 
 
@@ -135,9 +171,8 @@ def test_dense_explicit_probes_skinny(ctx, prec):
     alpha, beta = cheb.affine_map(a, b)
     Aop = A if prec == "fp64" else A.astype(np.float32).astype(np.float64)
     want = moments.moments_direct(Aop, Zall[:, 100:140], alpha, beta, n)
-    kappa = float(np.max(np.abs(alpha * Aop + beta * np.eye(d)).sum(axis=1)))
-    u = {"fp64": U64, "fp32": U32, "bf16x3": U_BF16X3}[prec]
-    tol = moment_tol(n, d, u, d, kappa)
+    tol = _tol(prec, n, d, Aop, alpha, beta, False)
+    assert np.all(got[:, 0] == d)
     assert float(np.max(np.abs(got - want) / tol[None, :])) <= 1.0
 
 

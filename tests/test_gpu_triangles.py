@@ -1,6 +1,6 @@
 """GPU parity of the integer triangle path: bit-exact per-probe moments
 (w1 = z.Az, w2 = |Az|^2, w3 = (Az).A(Az)) against the oracle, and the
-control-variate estimate of Section 5.5."""
+control-variate estimate of Section 5.4."""
 import numpy as np
 import pytest
 

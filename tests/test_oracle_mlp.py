@@ -119,3 +119,103 @@ def test_linear_stage_matches_lstsq_and_standardisation():
     want = np.linalg.lstsq(U[:, 1:7], t, rcond=None)[0]
     np.testing.assert_allclose(got[1:7], want, rtol=1e-8, atol=1e-12)
     assert got[0] == 0.0 and got[7] == 0.0
+
+
+def test_bf16_round_known_values():
+    """bfloat16 keeps 8 significant bits: 1 + 2^-8 is a tie between 1 and
+    1 + 2^-7 and goes to the even one (1); 1 + 3 * 2^-9 rounds up to 1 + 2^-7;
+    values already on the bf16 grid are unchanged; signs are kept."""
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, 1.0 + 2 ** -7 + 2 ** -8, -3.0,
+                  2.0 ** -20, 0.0, 1.0 + 2 ** -9])
+    want = np.array([1.0, 1.0, 1.0 + 2 ** -7, 1.0 + 2 ** -6, -3.0, 2.0 ** -20, 0.0, 1.0])
+    np.testing.assert_array_equal(mlp.bf16_round(x), want)
+    r = np.random.default_rng(5).normal(size=1000)
+    rel = np.abs(mlp.bf16_round(r) - r) / np.abs(r)
+    assert rel.max() <= 2.0 ** -8 * (1 + 1e-6)
+
+
+def test_composite_g_reduces_to_truncation_plus_constant():
+    """With the linear stage and every network weight zero except the output
+    bias b3, g = q_c + mu_0 (ybar + ysd b3) exactly (closed form)."""
+    rng = np.random.default_rng(6)
+    F, H, n = 5, 8, 12
+    mu = rng.normal(size=(30, n + 1))
+    mu[:, 0] = 64.0
+    c = rng.normal(size=n + 1)
+    z = mlp.Params(np.zeros((H, F)), np.zeros(H), np.zeros((H, H)), np.zeros(H), np.zeros(H),
+                   0.375)
+    aff = mlp.Affine(0.25, 2.0, rng.normal(size=F), np.abs(rng.normal(size=F)), np.zeros(F))
+    want = mu[:, :F] @ c[:F] + 64.0 * (0.25 + 2.0 * 0.375)
+    for bf in (False, True):
+        np.testing.assert_allclose(mlp.composite_g(mu, c, F, aff, z, bf16=bf), want, rtol=1e-15)
+
+
+def test_composite_g_linear_stage_is_the_linear_control_variate():
+    """With the network zero (out = 0), g - q_c = mu_0 (ybar + ysd u.beta):
+    fitting the affine stages on rows whose residual is exactly affine in the
+    standardised inputs reproduces q on those rows."""
+    rng = np.random.default_rng(7)
+    F, n, N = 4, 9, 200
+    mu = np.c_[np.full(N, 50.0), rng.normal(0.0, 1.0, (N, n))]
+    c = rng.normal(size=n + 1)
+    coef = rng.normal(size=F - 1)
+    # make the tail sum_{j>=F} c_j mu_j an exact affine function of mu_f / mu_0
+    tail = 50.0 * (0.7 + (mu[:, 1:F] / 50.0) @ coef)
+    mu[:, F] = (tail - mu[:, F + 1:] @ c[F + 1:]) / c[F]
+    aff = mlp.fit_affine(mu, c, F)
+    zero = mlp.Params(np.zeros((8, F)), np.zeros(8), np.zeros((8, 8)), np.zeros(8),
+                      np.zeros(8), 0.0)
+    np.testing.assert_allclose(mlp.composite_g(mu, c, F, aff, zero, bf16=False), mu @ c,
+                               rtol=1e-9, atol=1e-9 * np.abs(mu @ c).max())
+
+
+def test_learned_chain_telescopes_and_is_unbiased_by_enumeration():
+    """Over all 2^d sign vectors (d = 8), the chain's level variables
+    S(l_k) - S(l_{k-1}) sum per probe to z^T p_n z, and their exact means sum
+    to tr p_n(A_hat), for any fixed g and level sets with or without the
+    g level (eq. eqn:telescope)."""
+    d = 8
+    A, lam = wl.random_symmetric(d, 12, 0.5, 3.0)
+    a, b, n, nc = 0.4, 3.2, 16, 4
+    c, _ = cheb.coefficients(cheb.SQRT, a, b, n)
+    alpha, beta = cheb.affine_map(a, b)
+    Z = np.array([[1.0 if (s >> i) & 1 else -1.0 for i in range(d)] for s in range(2 ** d)]).T
+    mu = moments.moments_direct(A, Z, alpha, beta, n)
+    rng = np.random.default_rng(8)
+    p = mlp.glorot_init(nc + 1, 8, rng)
+    aff = mlp.Affine(0.1, 0.5, rng.normal(size=nc + 1), np.abs(rng.normal(size=nc + 1)),
+                     np.r_[0.0, rng.normal(size=nc)])
+    g = mlp.composite_g(mu, c, nc + 1, aff, p)
+    truth = cheb.trace_poly(c, lam, a, b)
+    for levels in ([nc, n], [2, nc, 9, n], [1, 6, n], [n], [0, nc, n]):
+        vals = [mlp.chain_value(mu, c, hi, nc, g) -
+                mlp.chain_value(mu, c, levels[k - 1] if k else -1, nc, g)
+                for k, hi in enumerate(levels)]
+        np.testing.assert_allclose(np.sum(vals, axis=0), mu @ c, rtol=1e-12, atol=1e-12)
+        assert sum(float(np.mean(v)) for v in vals) == pytest.approx(truth, rel=1e-12)
+        if len(levels) > 1:
+            val, var = mlp.learned_ml_estimate(vals)
+            assert val == pytest.approx(truth, rel=1e-12)
+
+
+def test_learned_terms_prefix_sums_and_plain_case():
+    """The planner's terms have the chain values as prefix sums; with g equal
+    to the plain truncation q_{n_cheap} they are the paper's pilot terms
+    c_j mu_j (Section 3.2), so the plan is the plain one."""
+    from oracle import levelsel
+
+    rng = np.random.default_rng(9)
+    n, nc, N = 20, 5, 64
+    mu = rng.normal(size=(N, n + 1))
+    c = rng.normal(size=n + 1)
+    g = rng.normal(size=N)
+    T = mlp.learned_terms(mu, c, nc, g)
+    S = np.cumsum(T, axis=1)
+    for l in range(n + 1):
+        np.testing.assert_allclose(S[:, l], mlp.chain_value(mu, c, l, nc, g), rtol=1e-12,
+                                   atol=1e-12)
+    plain = mlp.learned_terms(mu, c, nc, mu[:, :nc + 1] @ c[:nc + 1])
+    np.testing.assert_allclose(plain, mu * c[None, :], rtol=1e-12, atol=1e-12)
+    V1 = levelsel.level_variances(plain)
+    V2 = levelsel.level_variances(mu * c[None, :])
+    np.testing.assert_allclose(V1, V2, rtol=1e-10, atol=1e-12)
