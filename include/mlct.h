@@ -268,6 +268,32 @@ mlct_status mlct_moments(mlct_ctx* ctx, const mlct_op* op, double a, double b, i
                          const mlct_probes* probes, int32_t prec, int32_t mode,
                          double* mu_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * moments of mlct_moments, written to DEVICE memory and without allocating
+ * anything.  CSR operators, MLCT_FP32 or MLCT_FP64, MLCT_DIRECT or
+ * MLCT_DOUBLING; the same kernels as mlct_moments, so the results are the
+ * same bit for bit.  mu_dev: device, m x (n+1) doubles, row-major, written
+ * on the context stream; the call returns once the work is enqueued (no
+ * synchronisation, no host copy).
+ * Scratch: a fixed device array of MLCT_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held until the process ends.  A request needs
+ * 2 d 64 s bytes (two probe vectors, s = 4 or 8) + 1024 G (S + 1) (moment
+ * partials; G workgroups per step, up to 2048; S steps) + 1024 (S + 1) + 64 s
+ * per 256-entry chunk of the rows longer than 256 entries, each part rounded
+ * up to 256; more than the array holds fails with MLCT_ENOMEM before any work
+ * (about d <= 65,536 rows in FP32 at degree 200, symmetric form).  Every
+ * buffer is written
+ * before it is read, so nothing needs clearing between calls.  All calls on
+ * one GPU share that GPU's array: calls that overlap in time on one GPU
+ * (other streams, contexts or threads) race and give wrong results.
+ * Errors: EINVAL, EUNSUPPORTED (not CSR, BF16X3), ENOMEM (scratch too
+ * small), EDEVICE. */
+#define MLCT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+mlct_status mlct_moments_noalloc(mlct_ctx* ctx, const mlct_op* op, double a, double b,
+                                 int32_t n, const mlct_probes* probes, int32_t prec,
+                                 int32_t mode, double* mu_dev);
+
 /* Spectral interval by ``steps`` FP64 Lanczos steps with full
  * reorthogonalisation from Rademacher probe 0 of ``seed``: extreme Ritz values
  * widened by their residual bounds and by rel_margin * (width). */

@@ -10,6 +10,7 @@
 #include <string>
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,7 +18,33 @@
 
 using namespace mlct;
 
+// Fixed scratch of mlct_moments_noalloc: one array per GPU in the library's
+// code object, held until the process ends.  Host code never names it in a
+// launch or copy: it uses the device address hipGetSymbolAddress returns
+// for each GPU, taken once per device by mlct_create (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[MLCT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The address of this device's scratch array (device current), looked up on
+// the first call for the device; nullptr if the lookup fails.
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
 
 mlct_status fail(mlct_ctx* ctx, mlct_status st, const char* fmt, ...) {
   if (ctx) {
@@ -816,6 +843,10 @@ mlct_status mlct_create(int device, void* hip_stream, const char* tune_cache_pat
     delete ctx;
     return MLCT_EDEVICE;
   }
+  if (device < kMaxScratchDevices && !noalloc_scratch(device)) {
+    delete ctx;
+    return MLCT_EDEVICE;
+  }
   *out = ctx;
   return MLCT_OK;
 }
@@ -1073,6 +1104,55 @@ mlct_status mlct_moments(mlct_ctx* ctx, const mlct_op* op, double a, double b, i
   HIPCHK(ctx, hipMemcpyAsync(mu_out, mu, (size_t)probes->m * ldmu * sizeof(double),
                              hipMemcpyDeviceToHost, ctx->stream));
   CHECK(sync_stream(ctx));
+  return MLCT_OK;
+}
+
+mlct_status mlct_moments_noalloc(mlct_ctx* ctx, const mlct_op* op, double a, double b,
+                                 int32_t n, const mlct_probes* probes, int32_t prec,
+                                 int32_t mode, double* mu_dev) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (!op || !mu_dev) return fail(ctx, MLCT_EINVAL, "op and mu_dev are required");
+  if (op->kind != OP_CSR) return fail(ctx, MLCT_EUNSUPPORTED, "only CSR operators");
+  if (prec != MLCT_FP32 && prec != MLCT_FP64)
+    return fail(ctx, MLCT_EUNSUPPORTED, "precision must be MLCT_FP32 or MLCT_FP64");
+  if (!finite_interval(a, b)) return fail(ctx, MLCT_EINVAL, "need finite a < b");
+  if (n < 0 || n > kMaxDegree) return fail(ctx, MLCT_EINVAL, "degree must be in [0, %d]", kMaxDegree);
+  CHECK(check_mode_prec(ctx, mode, prec));
+  CHECK(check_probes(ctx, op, probes));
+  // carve the block buffers out of the fixed scratch (256-byte aligned)
+  const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
+  const CsrBlockSizes z = csr_block_sizes(op, tsz, mode, n);
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t need = 2 * up(z.v) + up(z.part) + up(z.dots) + up(z.hub);
+  if (need > (size_t)MLCT_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, MLCT_ENOMEM,
+                "needs %zu bytes of scratch, more than the fixed %llu (fewer rows or a lower degree)",
+                need, (unsigned long long)MLCT_NOALLOC_SCRATCH_BYTES);
+  CHECK(set_device(ctx));
+  char* base = static_cast<char*>(noalloc_scratch(ctx->device));
+  if (!base) return fail(ctx, MLCT_EDEVICE, "no scratch address for device %d", ctx->device);
+  CsrBlockBufs bb;
+  bb.timed = false;
+  bb.v0 = base;
+  bb.v1 = base + up(z.v);
+  bb.part = reinterpret_cast<double*>(base + 2 * up(z.v));
+  bb.dots = reinterpret_cast<double*>(base + 2 * up(z.v) + up(z.part));
+  bb.hub = z.hub ? base + 2 * up(z.v) + up(z.part) + up(z.dots) : nullptr;
+  const double alpha = 2.0 / (b - a), beta = -(a + b) / (b - a);
+  const int64_t ldmu = n + 1;
+  for (int64_t p0 = 0; p0 < probes->m; p0 += kBlockProbes) {
+    ProbeSrc src;
+    src.seed = probes->seed;
+    src.first_id = probes->first_id + p0;
+    src.entries = probes->kind == MLCT_PROBE_EXPLICIT ? probes->entries_dev : nullptr;
+    src.ld = probes->ld_entries;
+    src.active = (int32_t)std::min<int64_t>(probes->m - p0, kBlockProbes);
+    if (prec == MLCT_FP32)
+      CHECK(run_block_csr_in<float>(ctx, op, alpha, beta, n, mode, src, mu_dev + p0 * ldmu, ldmu, bb));
+    else
+      CHECK(run_block_csr_in<double>(ctx, op, alpha, beta, n, mode, src, mu_dev + p0 * ldmu, ldmu, bb));
+  }
   return MLCT_OK;
 }
 

@@ -670,6 +670,27 @@ def mlct_learned_plan(ctx: Context, mlp: Mlp, target: float,
     return _plan_dict(p)
 
 
+def mlct_moments_noalloc(ctx: Context, op: Op, a: float, b: float, n: int, probes: mlct_probes,
+                         prec: int = MLCT_FP32, mode: int = MLCT_DIRECT, out=None):
+    """mlct_moments into a device tensor (m x (n+1) float64) without any
+    allocation inside the library; ``out`` may be given (then nothing at all
+    is allocated here either).  The work is enqueued on the context stream."""
+    import torch
+
+    h = lib()
+    h.mlct_moments_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
+                                       C.POINTER(mlct_probes), C.c_int32, C.c_int32, C.c_void_p]
+    h.mlct_moments_noalloc.restype = C.c_int
+    if out is None:
+        out = torch.empty((probes.m, n + 1), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or \
+            out.numel() < probes.m * (n + 1):
+        raise ValueError("out must be a contiguous float64 device tensor of m x (n+1)")
+    _check(ctx, h.mlct_moments_noalloc(ctx.handle, op.handle, a, b, n, C.byref(probes), prec, mode,
+                                       out.data_ptr()))
+    return out
+
+
 # int32 apply(void* user, const float* V, float* AV, int64 B, void* hip_stream)
 MLCT_APPLY_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p)
 
