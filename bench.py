@@ -18,9 +18,7 @@ sum over probes of the polynomial degree reached, divided by wall time.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
-import re
 import math
 import os
 import sys
@@ -35,24 +33,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-
-def kernel_source_hash() -> str:
-    """Hash of the code (comments and blank space removed) of the sources
-    that define the CSR step kernels; HBM counter figures stored under
-    profiles/ are only reported while it matches."""
-    h = hashlib.sha256()
-    for f in ("k_csr.hip", "device.hpp"):
-        with open(os.path.join(ROOT, "paper_2103_10516_amd", "csrc", f)) as fh:
-            h.update(code_only(fh.read()).encode())
-    return h.hexdigest()[:16]
-
-
-def code_only(text: str) -> str:
-    """C++ source without // and /* */ comments and with runs of blank space
-    collapsed, so that comment edits leave the kernel hash unchanged."""
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    return " ".join(text.split())
+# one copy of the source hash that guards the stored counter figures
+from paper_2103_10516_amd.profiling import code_only, kernel_source_hash  # noqa: E402
 
 
 def stored_traffic(name: str):
@@ -103,6 +85,7 @@ def cpu_baseline(g, a, b, seed):
 
 BF16_PEAK_TFS = 2500.0   # MI355X dense bf16 MFMA
 FP32_PEAK_TFS = 157.3    # MI355X FP32 MFMA
+FP64_PEAK_TFS = 78.6     # MI355X FP64 MFMA
 
 
 def copy_bandwidth(dev, nbytes: int = 1 << 30, reps: int = 10) -> float:
@@ -179,6 +162,90 @@ def extra_nuclear_dense(mlct, dev):
     op.close()
     ctx.close()
     return out
+
+
+def extra_dense_rungs(mlct, dev):
+    """Precision ladder of the dense recurrence on the nuclear-norm workload
+    (X 8192 x 4096, sigma_i = i^-0.7, A = X^T X formed once on the device in
+    FP32): the same estimate (levels 16/64/256, probes 3712/320/64, the same
+    probe ids) in FP64, FP32 and BF16x3 MFMA arithmetic, each timed (best of
+    two after a warm-up) with its relative difference from the FP64 rung and
+    from sum_i p_256(sigma_i^2) (the library's coefficients evaluated at the
+    singular values the matrix was built from).  Per-probe parity of every
+    rung against the FP64 oracle at this size is a GPU test
+    (tests/test_gpu_full_size.py).  Also the dense SPD log-det workload,
+    d = 512, FP64: single level 64 with 256 probes and the 2-level split
+    (8, 64) with 224/32 probes, against sum_i log(lambda_i)."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    X, sig = wl.nuclear_x()
+    ctx = mlct.mlct_create(0)
+    op = mlct.mlct_op_gram(ctx, torch.from_numpy(X).to(dev))
+    a, b, n = 1e-6, 1.0, 256
+    c, ls = mlct.mlct_cheb_coeffs(ctx, mlct.MLCT_SQRT, a, b, n)
+    xh = (2.0 * sig ** 2 - (a + b)) / (b - a)
+    ref = float(np.sum(np.polynomial.chebyshev.chebval(xh, c))) * math.exp(ls)
+    degrees, m = [16, 64, 256], [3712, 320, 64]
+    d = 4096
+    steps = {16: 8, 64: 32, 256: 128}
+    flops = sum(2.0 * d * d * mk * steps[lk] for lk, mk in zip(degrees, m))
+    rungs = {}
+    for name, prec, peak in (("fp64", mlct.MLCT_FP64, FP64_PEAK_TFS),
+                             ("fp32", mlct.MLCT_FP32, FP32_PEAK_TFS),
+                             ("bf16x3", mlct.MLCT_BF16X3, BF16_PEAK_TFS)):
+        run = lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, degrees, m, 77, prec,
+                                         mlct.MLCT_DOUBLING)
+        run()
+        best, r = float("inf"), None
+        for _ in range(2):
+            _sync()
+            t0 = time.perf_counter()
+            r = run()
+            _sync()
+            best = min(best, time.perf_counter() - t0)
+        mlct.mlct_timing(ctx, True)
+        run()
+        _sync()
+        mlct.mlct_timing(ctx, False)
+        nl, kms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_DENSE_STEP)
+        ach = flops / (kms / 1e3) / 1e12
+        rungs[name] = {"ms": best * 1e3, "estimate": r["estimate"],
+                       "rel_err_vs_sum_p256": abs(r["estimate"] - ref) / abs(ref),
+                       "step_kernels_ms": kms, "launches": nl,
+                       "mfma_tflops": ach, "peak_tflops": peak, "frac": ach / peak}
+    for name in ("fp32", "bf16x3"):
+        rungs[name]["rel_diff_vs_fp64_rung"] = (abs(rungs[name]["estimate"] - rungs["fp64"]["estimate"])
+                                                / abs(rungs["fp64"]["estimate"]))
+    op.close()
+    # dense SPD log-det, d = 512, FP64
+    A, lam = wl.dense_spd(512)
+    opd = mlct.mlct_op_dense(ctx, torch.from_numpy(A).to(dev))
+    truth = float(np.sum(np.log(lam)))
+    small = {}
+    for label, dg, mm in (("single_64", [64], [256]), ("mlmc_8_64", [8, 64], [224, 32])):
+        run = lambda: mlct.mlct_estimate(ctx, opd, mlct.MLCT_LOG, 0.1, 1.0, dg, mm, 5,
+                                         mlct.MLCT_FP64, mlct.MLCT_DOUBLING)
+        run()
+        best = float("inf")
+        for _ in range(5):
+            _sync()
+            t0 = time.perf_counter()
+            r = run()
+            _sync()
+            best = min(best, time.perf_counter() - t0)
+        small[label] = {"ms": best * 1e3, "estimate": r["estimate"],
+                        "rel_err_vs_logdet": abs(r["estimate"] - truth) / abs(truth),
+                        "rel_se": math.sqrt(r["est_var"]) / abs(truth),
+                        "probe_degree_per_s": r["probe_degrees"] / best}
+    opd.close()
+    ctx.close()
+    return {"workload": "nuclear norm X 8192x4096 (FP32), A=X^T X, sqrt on [1e-6,1], levels "
+                        "16/64/256, probes 3712/320/64, doubling; rungs FP64/FP32/BF16x3",
+            "sum_p256_reference": ref, "rungs": rungs,
+            "dense_logdet_512": {"workload": "dense SPD d=512 FP64, lambda~U[0.1,1], log on "
+                                             "[0.1,1], doubling", "logdet": truth, **small}}
 
 
 def extra_triangles(mlct, dev):
@@ -297,6 +364,8 @@ def extra_graph_batch(mlct, dev):
                                it["m"], it["seed"], mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
         _sync()
         ts = min(ts, time.perf_counter() - t0)
+    tpers = _best_of(3, lambda: mlct.mlct_estimate_batch(
+        ctx, items, mlct.MLCT_FP32, mlct.MLCT_DOUBLING | mlct.MLCT_BATCH_PERSISTENT))
     pd = sum(r["probe_degrees"] for r in res)
     # HBM roofline of the batched step kernel: unique bytes of every launch
     # (pattern matrix, V_k, V_new; V_prev after a block's first step) over
@@ -316,6 +385,7 @@ def extra_graph_batch(mlct, dev):
     out = {"workload": "Estrada index, 64 Chung-Lu graphs d=2048..65536, levels 10/30/60, "
                        "probes 768/192/64 per graph",
            "batched_ms": tb * 1e3, "one_by_one_ms": ts * 1e3, "speedup": ts / tb,
+           "persistent_ms": tpers * 1e3,
            "probe_degree_per_s": pd / tb,
            "roofline": {"bound": "hbm", "kernel": "csr_step_batched_kernel", "achieved": ach,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
@@ -327,14 +397,155 @@ def extra_graph_batch(mlct, dev):
     return out
 
 
+def _best_of(k, fn):
+    """Best wall time of k calls of fn (synchronised)."""
+    best = float("inf")
+    for _ in range(k):
+        _sync()
+        t0 = time.perf_counter()
+        fn()
+        _sync()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def extra_laplace_batch(mlct, dev):
+    """Batching on the 32 shifted 3D Laplacians n_i = round(32 * 4^(i/31))
+    (d = 32^3 .. 128^3, + 0.01 I, [0.01, 12.01]), f = log, levels 8 / 256 with
+    128 / 64 probes each: one batched call (one launch per step, and one
+    persistent launch for steps 2..S) against 32 single calls, best of
+    three each, results bit for bit equal."""
+    import torch
+
+    from paper_2103_10516_amd import workloads as wl
+
+    ctx = mlct.mlct_create(0)
+    items = []
+    for i, n3 in enumerate(wl.laplacian_3d_batch_sizes()):
+        g = wl.laplacian_3d(n3)
+        op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev),
+                              torch.from_numpy(g.col).to(dev), torch.from_numpy(g.val).to(dev))
+        items.append(dict(op=op, kind=mlct.MLCT_LOG, a=0.01, b=12.01, degrees=[8, 256],
+                          m=[128, 64], seed=500 + i))
+    mode = mlct.MLCT_DOUBLING
+    res = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, mode)
+    per = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, mode | mlct.MLCT_BATCH_PERSISTENT)
+    one = [mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"], it["m"],
+                              it["seed"], mlct.MLCT_FP32, mode) for it in items]
+    equal = all(r["value"] == o["value"] == p["value"] for r, o, p in zip(res, one, per))
+    tb = _best_of(3, lambda: mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, mode))
+    tp = _best_of(3, lambda: mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32,
+                                                      mode | mlct.MLCT_BATCH_PERSISTENT))
+    ts = _best_of(3, lambda: [mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"],
+                                                 it["degrees"], it["m"], it["seed"],
+                                                 mlct.MLCT_FP32, mode) for it in items])
+    pd = sum(r["probe_degrees"] for r in res)
+    for it in items:
+        it["op"].close()
+    ctx.close()
+    return {"workload": "32 shifted 3D Laplacians n=32..128 + 0.01 I, log, levels 8/256, "
+                        "probes 128/64 each, doubling, FP32",
+            "batched_ms": tb * 1e3, "persistent_ms": tp * 1e3, "one_by_one_ms": ts * 1e3,
+            "speedup_batched": ts / tb, "speedup_persistent": ts / tp,
+            "probe_degree_per_s_batched": pd / tb, "bitwise_equal": equal}
+
+
+def _repeat(fn, seeds, ref):
+    """Run fn(seed) once untimed, then once per seed: mean seconds per call,
+    the realized relative RMS error against ref over the repetitions, the
+    mean estimated relative standard error and the last result."""
+    fn(seeds[0] + 7919)
+    times, errs, ses, r = [], [], [], None
+    for sd in seeds:
+        _sync()
+        t0 = time.perf_counter()
+        r = fn(sd)
+        _sync()
+        times.append(time.perf_counter() - t0)
+        res = r[0] if isinstance(r, tuple) else r
+        errs.append(res["estimate"] - ref)
+        ses.append(math.sqrt(max(res["est_var"], 0.0)) * math.exp(res.get("log_scale", 0.0)))
+    return {"s": float(np.mean(times)), "reps": len(seeds),
+            "realized_rel_rms": float(math.sqrt(np.mean(np.square(errs))) / abs(ref)),
+            "mean_rel_se": float(np.mean(ses) / abs(ref))}, r
+
+
+def _time_to_eps_study(mlct, ctx, op, kind, a, b, n, nc, prec, mlmc_degrees, ref, eps_list,
+                       reps, fit_seed, fit_prec=None):
+    """Plain single level, fixed-level MLMC, automatic levels (Theorem
+    thm:levels, 256-probe pilot in every call), the two-term learned level
+    and the learned multilevel chain (g placed among the Chebyshev levels by
+    the same programme on the fit's held-out probes), each with sample sizes
+    for a variance target (eps * |ref|)^2 and repeated on fresh probe seeds.
+    Realized error is against ref, the estimator's expectation tr p_n."""
+    mode = mlct.MLCT_DOUBLING
+    fit_prec = prec if fit_prec is None else fit_prec
+    _sync()
+    t0 = time.perf_counter()
+    net = mlct.mlct_learned_fit(ctx, op, kind, a, b, n_fine=n, n_cheap=nc, m_pilot=2048,
+                                seed=fit_seed, prec=fit_prec, epochs=1500)
+    _sync()
+    t_fit = time.perf_counter() - t0
+    info = mlct.mlct_mlp_info_get(net)
+    t0 = time.perf_counter()
+    pil = mlct.mlct_estimate(ctx, op, kind, a, b, mlmc_degrees, [256] * len(mlmc_degrees), 6,
+                             prec, mode)
+    _sync()
+    t_pilot = time.perf_counter() - t0
+    cost = [(k + 1) // 2 for k in mlmc_degrees]
+    rows = []
+    for ei, eps in enumerate(eps_list):
+        tgt = (eps * abs(ref)) ** 2
+        R = reps[ei] if isinstance(reps, (list, tuple)) else reps
+        seeds = [10_000 * (ei + 1) + 31 * r for r in range(R)]
+        m_plain = max(2, math.ceil(info["var_q"] / tgt))
+        V = list(pil["level_var"])
+        s_ml = sum(math.sqrt(v * cc) for v, cc in zip(V, cost))
+        m_ml = [max(2, math.ceil(s_ml * math.sqrt(v / cc) / tgt)) for v, cc in zip(V, cost)]
+        Vl = [info["var_g"], info["var_resid"]]
+        cl = [(nc + 1) // 2, (n + 1) // 2]
+        s_l = sum(math.sqrt(v * cc) for v, cc in zip(Vl, cl))
+        m_l = [max(2, math.ceil(s_l * math.sqrt(v / cc) / tgt)) for v, cc in zip(Vl, cl)]
+        t0 = time.perf_counter()
+        plan = mlct.mlct_learned_plan(ctx, net, tgt)
+        t_plan = time.perf_counter() - t0
+        row = {"eps": eps}
+        row["plain"], _ = _repeat(lambda sd: mlct.mlct_estimate(
+            ctx, op, kind, a, b, [n], [m_plain], sd, prec, mode), seeds, ref)
+        row["plain"]["m"] = m_plain
+        row["mlmc"], _ = _repeat(lambda sd: mlct.mlct_estimate(
+            ctx, op, kind, a, b, mlmc_degrees, m_ml, sd + 1, prec, mode), seeds, ref)
+        row["mlmc"]["m"] = m_ml
+        row["auto_levels"], (_, ap) = _repeat(lambda sd: mlct.mlct_estimate_auto(
+            ctx, op, kind, a, b, n, 256, sd + 2, prec, mode, tgt), seeds, ref)
+        row["auto_levels"].update(degrees=ap["degrees"], m=ap["m"])
+        row["learned"], _ = _repeat(lambda sd: mlct.mlct_estimate_learned(
+            ctx, op, net, m_l[0], m_l[1], sd + 3), seeds, ref)
+        row["learned"]["m"] = m_l
+        row["learned_mlmc"], _ = _repeat(lambda sd: mlct.mlct_estimate_learned_ml(
+            ctx, op, net, plan["degrees"], plan["m"], sd + 4), seeds, ref)
+        row["learned_mlmc"].update(degrees=plan["degrees"], m=plan["m"], plan_s=t_plan)
+        for k in ("mlmc", "auto_levels", "learned", "learned_mlmc"):
+            row[k]["speedup_vs_plain"] = row["plain"]["s"] / row[k]["s"]
+        rows.append(row)
+        print(f"#   eps {eps}: plain {row['plain']['s'] * 1e3:.1f} ms, mlmc "
+              f"{row['mlmc']['s'] * 1e3:.1f}, auto {row['auto_levels']['s'] * 1e3:.1f}, learned "
+              f"{row['learned']['s'] * 1e3:.1f}, learned+mlmc {row['learned_mlmc']['s'] * 1e3:.1f}",
+              file=sys.stderr, flush=True)
+    out = {"fit_s": t_fit, "pilot_s": t_pilot, "var_q": info["var_q"], "var_g": info["var_g"],
+           "var_resid": info["var_resid"], "mlmc_level_var": list(pil["level_var"]),
+           "rows": rows}
+    net.close()
+    return out
+
+
 def extra_time_to_eps(mlct, dev):
-    """Time to a relative standard error eps of tr p_n(A_hat) for the plain
-    single-level estimator, 2-level MLMC (8 | 256), MLMC with the learned
-    level, and the levels chosen automatically by Theorem thm:levels from a
-    256-probe pilot, on the 3D Laplacian 64^3 + 0.01 I, f = log, n = 256.
-    Sample sizes from the measured (pilot) variances by the optimal
-    allocation; the timed part is the estimator call; pilot / training time
-    is reported apart."""
+    """Time to a relative RMS error eps of tr p_256(A_hat) on the 3D Laplacian
+    64^3 + 0.01 I, f = log: plain, 2-level MLMC (8 | 256), automatic levels,
+    the learned level and the learned multilevel chain; 20 repetitions per
+    row (10 at eps = 1e-5), realized error against sum_i p_256(lambda_i) over
+    the closed-form eigenvalues.  Training and the MLMC pilot are timed
+    apart."""
     import torch
 
     from paper_2103_10516_amd import workloads as wl
@@ -345,78 +556,28 @@ def extra_time_to_eps(mlct, dev):
     op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.col).to(dev),
                           torch.from_numpy(g.val).to(dev))
     a, b, n, nc = 0.01, 12.01, 256, 8
-    _sync()
-    t0 = time.perf_counter()
-    net = mlct.mlct_learned_fit(ctx, op, mlct.MLCT_LOG, a, b, n_fine=n, n_cheap=nc, m_pilot=2048,
-                                seed=5, epochs=1500)
-    _sync()
-    t_fit = time.perf_counter() - t0
-    info = mlct.mlct_mlp_info_get(net)
-    t0 = time.perf_counter()
-    pil = mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, [nc, n], [512, 512], 6,
-                             mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
-    _sync()
-    t_pilot = time.perf_counter() - t0
-    T = abs(pil["value"])  # only sets the scale of the target variance
-    Cc, Cf = (nc + 1) // 2, (n + 1) // 2
-    rows = []
-    for eps in (1e-3, 1e-4, 1e-5):
-        tgt = (eps * T) ** 2
-        m_plain = max(2, math.ceil(info["var_q"] / tgt))
-        V = [pil["level_var"][0], pil["level_var"][1]]
-        s_ml = sum(math.sqrt(v * cc) for v, cc in zip(V, (Cc, Cf)))
-        m_ml = [max(2, math.ceil(s_ml * math.sqrt(v / cc) / tgt)) for v, cc in zip(V, (Cc, Cf))]
-        Vl = [info["var_g"], info["var_resid"]]
-        s_l = sum(math.sqrt(v * cc) for v, cc in zip(Vl, (Cc, Cf)))
-        m_l = [max(2, math.ceil(s_l * math.sqrt(v / cc) / tgt)) for v, cc in zip(Vl, (Cc, Cf))]
-
-        def timed(fn):
-            _sync()
-            t = time.perf_counter()
-            r = fn()
-            _sync()
-            return time.perf_counter() - t, r
-
-        tp, rp = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, [n], [m_plain], 11,
-                                                  mlct.MLCT_FP32, mlct.MLCT_DOUBLING))
-        tm, rm = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_LOG, a, b, [nc, n], m_ml, 12,
-                                                  mlct.MLCT_FP32, mlct.MLCT_DOUBLING))
-        tl, rl = timed(lambda: mlct.mlct_estimate_learned(ctx, op, net, m_l[0], m_l[1], 13))
-        # automatic levels: pilot (reused as the top level's first samples),
-        # plan and estimate in one call; its time includes the pilot
-        ta, (ra, plan) = timed(lambda: mlct.mlct_estimate_auto(
-            ctx, op, mlct.MLCT_LOG, a, b, n, 256, 14, mlct.MLCT_FP32, mlct.MLCT_DOUBLING, tgt))
-        rse = lambda r: math.sqrt(r["est_var"]) / T  # estimated relative standard error
-        rows.append({"eps": eps,
-                     "plain": {"m": m_plain, "s": tp, "rel_se": rse(rp), "value": rp["value"]},
-                     "mlmc": {"m": m_ml, "s": tm, "rel_se": rse(rm), "value": rm["value"]},
-                     "learned": {"m": m_l, "s": tl, "rel_se": rse(rl), "value": rl["value"]},
-                     "auto_levels": {"degrees": plan["degrees"], "m": plan["m"], "s": ta,
-                                     "rel_se": rse(ra), "value": ra["value"]}})
+    c, ls = mlct.mlct_cheb_coeffs(ctx, mlct.MLCT_LOG, a, b, n)
+    lam = wl.laplacian_3d_eigs(n3)
+    ref = float(np.sum(np.polynomial.chebyshev.chebval((2.0 * lam - (a + b)) / (b - a), c)))
     out = {"workload": "3D Laplacian 64^3 + 0.01 I, log, n=256, cheap level 8, learned MLP "
                        "9-64-64-1 trained on 2048 pilot probes",
-           "fit_s": t_fit, "pilot_s": t_pilot,
-           "auto_levels_note": "one call: 256-probe pilot (included in s) reused by the top "
-                               "level, levels by Theorem thm:levels",
-           "var_q": info["var_q"], "var_g": info["var_g"],
-           "var_resid": info["var_resid"], "mlmc_level_var": list(pil["level_var"]),
-           "rows": rows}
-    net.close()
+           "tr_p256_reference": ref}
+    out.update(_time_to_eps_study(mlct, ctx, op, mlct.MLCT_LOG, a, b, n, nc, mlct.MLCT_FP32,
+                                  [nc, n], ref, (1e-3, 1e-4, 1e-5), (20, 20, 10), 5))
     op.close()
     ctx.close()
     return out
 
 
 def extra_time_to_eps_dense(mlct, dev):
-    """Time to a relative standard error eps of tr p_256(A_hat) for the
-    nuclear norm (X 8192 x 4096, sigma_i = i^-0.7, A = X^T X, f = sqrt on
-    [1e-6, 1], BF16x3): plain single level, 3-level MLMC 16/64/256, the
-    learned level (MLP on mu_0..mu_8 trained on 2048 pilot probes) and the
-    levels of Theorem thm:levels (256-probe pilot, included in its time).
-    Sample sizes from pilot variances by the optimal allocation.  The
-    realized error is against sum_i p_256(sigma_i^2), the polynomial of the
-    library's own coefficients evaluated on the host at the singular values
-    the matrix was built from (its FP32 rounding moves them by ~1e-7)."""
+    """The headline comparison of the learned level: time to a relative RMS
+    error eps of tr p_256(A_hat) for the nuclear norm (X 8192 x 4096,
+    sigma_i = i^-0.7, A = X^T X, f = sqrt on [1e-6, 1], BF16x3), plain single
+    level vs 3-level MLMC 16/64/256, automatic levels, the learned level and
+    the learned multilevel chain, 20 repetitions per row, realized error
+    against sum_i p_256(sigma_i^2) (the library's own coefficients evaluated
+    at the singular values the matrix was built from; its FP32 rounding
+    moves them by ~1e-7)."""
     import torch
 
     from paper_2103_10516_amd import workloads as wl
@@ -424,65 +585,16 @@ def extra_time_to_eps_dense(mlct, dev):
     X, sig = wl.nuclear_x()
     ctx = mlct.mlct_create(0)
     op = mlct.mlct_op_gram(ctx, torch.from_numpy(X).to(dev))
-    a, b, n, prec, mode = 1e-6, 1.0, 256, mlct.MLCT_BF16X3, mlct.MLCT_DOUBLING
+    a, b, n = 1e-6, 1.0, 256
     c, ls = mlct.mlct_cheb_coeffs(ctx, mlct.MLCT_SQRT, a, b, n)
     xh = (2.0 * sig.astype(np.float64) ** 2 - (a + b)) / (b - a)
     ref = float(np.sum(np.polynomial.chebyshev.chebval(xh, c))) * math.exp(ls)
-    _sync()
-    t0 = time.perf_counter()
-    net = mlct.mlct_learned_fit(ctx, op, mlct.MLCT_SQRT, a, b, n_fine=n, n_cheap=8,
-                                m_pilot=2048, seed=5, prec=prec, epochs=1500)
-    _sync()
-    t_fit = time.perf_counter() - t0
-    info = mlct.mlct_mlp_info_get(net)
-    degs = [16, 64, n]
-    t0 = time.perf_counter()
-    pil = mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, degs, [256, 256, 256], 6, prec, mode)
-    _sync()
-    t_pilot = time.perf_counter() - t0
-    T = abs(ref)
-    cost = [(k + 1) // 2 for k in degs]
-    rows = []
-
-    def timed(fn):
-        _sync()
-        t = time.perf_counter()
-        r = fn()
-        _sync()
-        return time.perf_counter() - t, r
-
-    for eps in (1e-3, 3e-4):
-        tgt = (eps * T) ** 2
-        m_plain = max(2, math.ceil(info["var_q"] / tgt))
-        V = list(pil["level_var"])
-        s_ml = sum(math.sqrt(v * cc) for v, cc in zip(V, cost))
-        m_ml = [max(2, math.ceil(s_ml * math.sqrt(v / cc) / tgt)) for v, cc in zip(V, cost)]
-        Vl = [info["var_g"], info["var_resid"]]
-        cl = [(8 + 1) // 2, cost[-1]]
-        s_l = sum(math.sqrt(v * cc) for v, cc in zip(Vl, cl))
-        m_l = [max(2, math.ceil(s_l * math.sqrt(v / cc) / tgt)) for v, cc in zip(Vl, cl)]
-        tp, rp = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, [n], [m_plain],
-                                                  11, prec, mode))
-        tm, rm = timed(lambda: mlct.mlct_estimate(ctx, op, mlct.MLCT_SQRT, a, b, degs, m_ml, 12,
-                                                  prec, mode))
-        tl, rl = timed(lambda: mlct.mlct_estimate_learned(ctx, op, net, m_l[0], m_l[1], 13))
-        ta, (ra, plan) = timed(lambda: mlct.mlct_estimate_auto(
-            ctx, op, mlct.MLCT_SQRT, a, b, n, 256, 14, prec, mode, tgt))
-
-        def row(m, t, r):
-            return {"m": m, "s": t, "rel_se": math.sqrt(r["est_var"]) / T,
-                    "realized_rel_err": abs(r["estimate"] - ref) / T, "estimate": r["estimate"]}
-
-        rows.append({"eps": eps, "plain": row(m_plain, tp, rp), "mlmc": row(m_ml, tm, rm),
-                     "learned": row(m_l, tl, rl),
-                     "auto_levels": dict(row(plan["m"], ta, ra), degrees=plan["degrees"])})
     out = {"workload": "nuclear norm, X 8192x4096 sigma_i=i^-0.7 (FP32), A=X^T X, sqrt on "
                        "[1e-6,1], n=256, BF16x3; MLMC 16/64/256; learned MLP 9-64-64-1 on "
                        "mu_0..mu_8, 2048 pilot probes",
-           "tr_p256_reference": ref, "fit_s": t_fit, "pilot_s": t_pilot,
-           "var_q": info["var_q"], "var_g": info["var_g"], "var_resid": info["var_resid"],
-           "mlmc_level_var": list(pil["level_var"]), "rows": rows}
-    net.close()
+           "tr_p256_reference": ref}
+    out.update(_time_to_eps_study(mlct, ctx, op, mlct.MLCT_SQRT, a, b, n, 8, mlct.MLCT_BF16X3,
+                                  [16, 64, n], ref, (1e-3, 3e-4), 20, 5))
     op.close()
     ctx.close()
     return out
@@ -495,8 +607,7 @@ def extra_learned_batch(mlct, dev):
     probes per matrix: summed over the batch, the time to a relative standard
     error eps of each tr p_256 for plain, 2-level MLMC (8 | 256) and the
     learned level, sample sizes from pilot variances by the optimal
-    allocation.  Fits and pilots are timed apart.  Not in the default run
-    (about two minutes)."""
+    allocation.  Fits and pilots are timed apart (about two minutes)."""
     import torch
 
     from paper_2103_10516_amd import workloads as wl
@@ -685,7 +796,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=2048, help="2D grid edge (default 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="dense,triangles,estrada,batch,time_to_eps,time_to_eps_dense,gram_csr,slq",
+    ap.add_argument("--extras", default="dense,dense_rungs,triangles,estrada,batch,laplace_batch,"
+                                        "time_to_eps,time_to_eps_dense,gram_csr,slq,learned_batch",
                     help="comma list of secondary measurements to add ('' for none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device copies of 1 GiB (a plain copy kernel of known "
@@ -779,9 +891,11 @@ def main():
     cbw = copy_bandwidth(dev)
     out["roofline"]["copy_GBs"] = cbw
     out["roofline"]["frac_of_copy"] = achieved / cbw
-    extras = {"dense": extra_nuclear_dense, "triangles": extra_triangles, "estrada": extra_estrada,
+    extras = {"dense": extra_nuclear_dense, "dense_rungs": extra_dense_rungs,
+              "triangles": extra_triangles, "estrada": extra_estrada,
               "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps,
               "time_to_eps_dense": extra_time_to_eps_dense, "learned_batch": extra_learned_batch,
+              "laplace_batch": extra_laplace_batch,
               "gram_csr": extra_gram_csr, "slq": extra_slq}
     secondary = {}
     for name in [e for e in args.extras.split(",") if e]:

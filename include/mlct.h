@@ -86,6 +86,17 @@ typedef enum {
  * computed once per operator (the exactly computable low-degree traces
  * remarked on at the end of Section 5.4).  c_j are the top interpolant's. */
 #define MLCT_EXACT_LOW 0x20
+/* OR'ed into the mode of mlct_estimate_batch: after one launch for the first
+ * step, run every later step of every probe block in one persistent launch
+ * (per row-length class of the operators), with a barrier per probe block
+ * between its steps, instead of one launch per step.  Same results bit for
+ * bit.  EDEVICE if a barrier wait exceeds two seconds (the launch then ends
+ * early; it cannot hang). */
+#define MLCT_BATCH_PERSISTENT 0x40
+/* OR'ed into the mode of mlct_estimate_batch: one launch per step.  With
+ * neither flag the context's choice is used: one launch per step unless
+ * mlct_autotune_batch found the persistent launch faster. */
+#define MLCT_BATCH_LOCKSTEP 0x80
 
 typedef enum {
   MLCT_DT_F32 = 0,
@@ -428,8 +439,11 @@ mlct_status mlct_estimate_auto(mlct_ctx* ctx, const mlct_op* op, mlct_func f, do
  * block width B_max; kept as 0, 2, 1 or 3).  Without tuning, blocks of at
  * most 64 probes take the skinny kernel and wider ones the largest square
  * tile that still fills the device.  With a cache file given to mlct_create the decision is written
- * there, keyed by the operator's shape, and operators of the same shape pick
- * it up when they are created.  choice_out (may be NULL): the value kept. */
+ * there, keyed by the operator's shape (dense: and by precision and block
+ * width); CSR operators of the same shape pick it up when they are created,
+ * dense operators whenever a block of that precision and width runs.
+ * Values in the file that the autotuner could not have chosen are ignored.
+ * choice_out (may be NULL): the value kept. */
 mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t prec,
                           int32_t* choice_out);
 
@@ -452,6 +466,15 @@ typedef struct {
 
 mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems, const mlct_batch_item* items,
                                 int32_t prec, int32_t mode, mlct_result* outs);
+
+/* Autotuner for batches: runs this batch (three times each, the first as a
+ * warm-up) with one launch per step and with the persistent launch, timed
+ * with events on the context stream, and keeps the faster as the context's
+ * launch form for batches given neither MLCT_BATCH_PERSISTENT nor
+ * MLCT_BATCH_LOCKSTEP.  choice_out (may be NULL): 1 = persistent, 0 = one
+ * launch per step.  Arguments as mlct_estimate_batch. */
+mlct_status mlct_autotune_batch(mlct_ctx* ctx, int32_t nitems, const mlct_batch_item* items,
+                                int32_t prec, int32_t mode, int32_t* choice_out);
 
 /* Triangle count tr(A^3)/6 of a 0/1 pattern CSR graph (Section 2.1 example,
  * Section 5.4): per probe, exact int32 y = A z and w = A y with int64

@@ -201,6 +201,15 @@ int tune_lookup(const mlct_ctx* ctx, const std::string& key, const std::vector<i
 const std::vector<int> kCsrGroupCands = {512, 1024, 2048, 4096};
 const std::vector<int> kDenseTileCands = {0, 2, 1, 3};
 
+// Dense tile choice: the operator's own (mlct_autotune on it), else a
+// cached decision for this shape, precision and block width, else the
+// default rule (-1).
+int dense_choice(const mlct_ctx* ctx, const mlct_op* op, int prec, int64_t bpad) {
+  if (op->tuned_dense >= 0) return op->tuned_dense;
+  if (ctx->tune_lines.empty()) return -1;
+  return tune_lookup(ctx, tune_key(op, prec, bpad), kDenseTileCands);
+}
+
 void tune_store(mlct_ctx* ctx, const std::string& key, int value) {
   const std::string line = key + " = " + std::to_string(value);
   bool found = false;
@@ -656,7 +665,7 @@ mlct_status reserve_block_ws(mlct_ctx* ctx, const mlct_op* op, int prec, int mod
   CHECK(ws_get(ctx, WS_V1, (size_t)bpad * op->d * tsz, &tmp));
   CHECK(ws_get(ctx, WS_PART, (size_t)2 * ntiles * bpad * (S + 1) * sizeof(double), &tmp));
   CHECK(ws_get(ctx, WS_MISC, (size_t)(S + 1) * 2 * bpad * sizeof(double), &tmp));
-  const DenseTile tb = dense_tile(prec, op->d, op->d, bpad, op->tuned_dense);
+  const DenseTile tb = dense_tile(prec, op->d, op->d, bpad, dense_choice(ctx, op, prec, bpad));
   if (prec == MLCT_BF16X3 && (tb.skinny || tb.bm == 128))
     CHECK(ws_get(ctx, WS_DPACK, 4 * dense_pack_bytes(bpad, op->d), &tmp));
   return MLCT_OK;
@@ -670,7 +679,8 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
   const void *a0, *a1;
   int64_t lda;
   CHECK(dense_operand(ctx, op, prec, &a0, &a1, &lda));
-  const DenseTile t = dense_tile(prec, d, lda, bpad, op->tuned_dense);
+  const int tile_choice = dense_choice(ctx, op, prec, bpad);
+  const DenseTile t = dense_tile(prec, d, lda, bpad, tile_choice);
   const int64_t ntiles = (d + t.bn - 1) / t.bn;
   CHECK(reserve_block_ws(ctx, op, prec, mode, degree, src.active));
   const size_t tsz = prec == MLCT_FP64 ? 8 : 4;
@@ -719,7 +729,7 @@ mlct_status run_block_dense(mlct_ctx* ctx, const mlct_op* op, double alpha, doub
     a.zmode = (mode == MLCT_DOUBLING || first) ? 0 : zdirect;
     a.src = src;
     a.part = P + pstep * (k - 1);
-    a.tile_force = op->tuned_dense;
+    a.tile_force = tile_choice;
     if (packed) {
       const int in = (k - 1) & 1, out = k & 1;
       a.pk_a_hi = pa_hi;
@@ -1965,7 +1975,12 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   if (nitems < 1 || !items || !outs) return fail(ctx, MLCT_EINVAL, "need items and outs");
   const int interp = (mode & MLCT_LEVEL_INTERP) ? 1 : 0;
   const int exact_low = (mode & MLCT_EXACT_LOW) ? 1 : 0;
-  mode &= ~(MLCT_LEVEL_INTERP | MLCT_EXACT_LOW);
+  if ((mode & MLCT_BATCH_PERSISTENT) && (mode & MLCT_BATCH_LOCKSTEP))
+    return fail(ctx, MLCT_EINVAL, "MLCT_BATCH_PERSISTENT and MLCT_BATCH_LOCKSTEP exclude each other");
+  const int persistent = (mode & MLCT_BATCH_PERSISTENT) ? 1
+                         : (mode & MLCT_BATCH_LOCKSTEP) ? 0
+                                                        : ctx->batch_persistent;
+  mode &= ~(MLCT_LEVEL_INTERP | MLCT_EXACT_LOW | MLCT_BATCH_PERSISTENT | MLCT_BATCH_LOCKSTEP);
   if (prec != MLCT_FP32) return fail(ctx, MLCT_EUNSUPPORTED, "batched estimates run in MLCT_FP32");
   CHECK(check_mode_prec(ctx, mode, prec));
   // ---- validate items, build level descriptors and blocks ----
@@ -2057,6 +2072,12 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   }
   bytes += align8((size_t)nitems * sizeof(mlct_result));
   bytes += 2 * align8(8 * nb * sizeof(int32_t)) + align8(8 * nb * sizeof(int64_t));  // XCD layout
+  int max_steps = 0;
+  for (const HostBlock& hb : blocks) max_steps = std::max(max_steps, hb.steps);
+  // persistent launch: running slots per (step, XCD) of every variant, the
+  // blocks' barrier counters and the abort flag
+  bytes += align8((size_t)variants.size() * (max_steps + 1) * 8 * sizeof(int64_t)) +
+           align8((nb + 1) * sizeof(int32_t)) + 64;
   void* ws;
   CHECK(ws_get(ctx, WS_BATCH, bytes, &ws));
   Carver cv{static_cast<char*>(ws)};
@@ -2097,6 +2118,9 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   int32_t* dxblk = cv.take<int32_t>(8 * nb);
   int32_t* dxg0 = cv.take<int32_t>(8 * nb);
   int64_t* dxbase = cv.take<int64_t>(8 * nb);
+  int64_t* dslots = cv.take<int64_t>(variants.size() * (max_steps + 1) * 8);
+  int32_t* dcnt = cv.take<int32_t>(nb + 1);
+  int32_t* dabort = cv.take<int32_t>(2);
   // group bases per variant table (each variant's blocks are contiguous)
   std::vector<size_t> vstart(variants.size() + 1, nb);
   for (size_t bi = nb; bi-- > 0;) vstart[blocks[bi].variant] = bi;
@@ -2187,15 +2211,79 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     }
   }
   // ---- probes, steps ----
-  int max_steps = 0;
-  for (const HostBlock& hb : blocks) max_steps = std::max(max_steps, hb.steps);
   for (size_t v = 0; v < variants.size(); ++v) {
     const size_t b0 = vstart[v], cnt = vstart[v + 1] - b0;
     if (!cnt) continue;
     const int64_t groups = tab[b0 + cnt - 1].group_base + tab[b0 + cnt - 1].ngroups;
     HIPCHK(ctx, launch_probe_init_batched(s, dtab + b0, (int)cnt, groups));
   }
-  for (int st = 1; st <= max_steps; ++st) {
+  // running slots of XCD x at step st (the running entries are a prefix of
+  // each XCD's list)
+  auto running = [&](size_t v, int st, XcdLaunch& xl) {
+    const size_t x0 = 8 * vstart[v];
+    int64_t most = 0;
+    for (int x = 0; x < 8; ++x) {
+      const size_t e0 = xoff[v][x], e1 = xoff[v][x + 1];
+      size_t e = e0;
+      while (e < e1 && xsteps[v][e] >= st) ++e;
+      xl.first[x] = (int)e0;
+      xl.count[x] = (int)(e - e0);
+      xl.slots[x] = e > e0 ? xbase[x0 + e - 1] + xcnt[x0 + e - 1] : 0;
+      most = std::max(most, xl.slots[x]);
+    }
+    return most;
+  };
+  if (persistent) {
+    // step 1 as a batched launch, then steps 2 .. S in one cooperative
+    // launch per row-length variant; the grid is what can be resident at
+    // once, so every block barrier's wait ends
+    for (size_t v = 0; v < variants.size(); ++v) {
+      XcdLaunch xl;
+      const int64_t most = running(v, 1, xl);
+      if (!most) continue;
+      const size_t x0 = 8 * vstart[v];
+      LaunchTimer tm(ctx, MLCT_KERNEL_BATCH_STEP);
+      HIPCHK(ctx, launch_csr_step_batched(s, dtab + vstart[v], dxblk + x0, dxg0 + x0,
+                                          dxbase + x0, xl, 8 * most, 1, variants[v].first,
+                                          variants[v].second, 0));
+      tm.done();
+    }
+    std::vector<int64_t> hslots(variants.size() * (max_steps + 1) * 8, 0);
+    std::vector<int> per(variants.size(), 0);
+    for (size_t v = 0; v < variants.size(); ++v) {
+      per[v] = csr_batch_persistent_per_xcd(variants[v].first, variants[v].second,
+                                            mode == MLCT_DOUBLING ? 0 : 1);
+      if (per[v] < 1) return fail(ctx, MLCT_EDEVICE, "no resident grid for the persistent batch");
+      for (int st = 1; st <= max_steps; ++st) {
+        XcdLaunch xl;
+        running(v, st, xl);
+        for (int x = 0; x < 8; ++x) hslots[(v * (max_steps + 1) + st) * 8 + x] = xl.slots[x];
+      }
+    }
+    HIPCHK(ctx, hipMemcpyAsync(dslots, hslots.data(), hslots.size() * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
+    for (size_t v = 0; v < variants.size(); ++v) {
+      const size_t b0 = vstart[v], x0 = 8 * b0, cnt = vstart[v + 1] - b0;
+      if (!cnt) continue;
+      XcdLaunch xl;
+      for (int x = 0; x < 8; ++x) {
+        xl.first[x] = (int)xoff[v][x];
+        xl.count[x] = (int)(xoff[v][x + 1] - xoff[v][x]);
+        xl.slots[x] = 0;
+      }
+      int vsteps = 0;
+      for (size_t bi = b0; bi < b0 + cnt; ++bi) vsteps = std::max(vsteps, tab[bi].steps);
+      if (vsteps < 2) continue;
+      LaunchTimer tm(ctx, MLCT_KERNEL_BATCH_STEP);
+      HIPCHK(ctx, launch_csr_batch_persistent(
+                      s, dtab + b0, dxblk + x0, dxg0 + x0, dxbase + x0, xl, vsteps,
+                      dslots + v * (max_steps + 1) * 8, dcnt, (int)cnt, dabort, per[v],
+                      variants[v].first, variants[v].second, mode == MLCT_DOUBLING ? 0 : 1,
+                      200000000LL));
+      tm.done();
+    }
+  }
+  for (int st = 1; st <= max_steps && !persistent; ++st) {
     for (size_t v = 0; v < variants.size(); ++v) {
       const size_t b0 = vstart[v];
       XcdLaunch xl;
@@ -2238,7 +2326,12 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   }
   std::vector<mlct_result> h(nitems);
   HIPCHK(ctx, hipMemcpyAsync(h.data(), dres, nitems * sizeof(mlct_result), hipMemcpyDeviceToHost, s));
+  int32_t aborted = 0;
+  if (persistent)
+    HIPCHK(ctx, hipMemcpyAsync(&aborted, dabort, sizeof aborted, hipMemcpyDeviceToHost, s));
   CHECK(sync_stream(ctx));
+  if (aborted)
+    return fail(ctx, MLCT_EDEVICE, "a block barrier of the persistent batch timed out");
   bool escaped = false;
   for (int i = 0; i < nitems; ++i) {
     int64_t mv = 0, pd = 0;
@@ -2255,6 +2348,45 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
     outs[i] = h[i];
   }
   if (escaped) return fail(ctx, MLCT_ESPECTRUM, "an item's spectrum is not inside its [a, b]");
+  return MLCT_OK;
+}
+
+// Autotuner for batches: times the two launch forms on the caller's batch
+// and keeps the faster for later batches of this context.
+extern "C" mlct_status mlct_autotune_batch(mlct_ctx* ctx, int32_t nitems,
+                                           const mlct_batch_item* items, int32_t prec,
+                                           int32_t mode, int32_t* choice_out) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (nitems < 1 || !items) return fail(ctx, MLCT_EINVAL, "need items");
+  mode &= ~(MLCT_BATCH_PERSISTENT | MLCT_BATCH_LOCKSTEP);
+  std::vector<mlct_result> outs(nitems);
+  CHECK(set_device(ctx));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Ev {
+    hipEvent_t* a;
+    hipEvent_t* b;
+    ~Ev() {
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } ev{&e0, &e1};
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  float best[2] = {1e30f, 1e30f};
+  const int32_t flag[2] = {MLCT_BATCH_LOCKSTEP, MLCT_BATCH_PERSISTENT};
+  for (int rep = 0; rep < 3; ++rep)
+    for (int f = 0; f < 2; ++f) {
+      HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+      CHECK(mlct_estimate_batch(ctx, nitems, items, prec, mode | flag[f], outs.data()));
+      HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+      HIPCHK(ctx, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) best[f] = std::min(best[f], ms);  // the first round warms up
+    }
+  ctx->batch_persistent = best[1] < best[0] ? 1 : 0;
+  if (choice_out) *choice_out = ctx->batch_persistent;
   return MLCT_OK;
 }
 

@@ -92,6 +92,7 @@ struct mlct_ctx {
   size_t host_pinned_bytes = 0;
   std::string tune_path;            // autotune cache file ("" = none)
   std::vector<std::string> tune_lines;  // cached decisions, one per operator shape
+  int batch_persistent = 0;  // launch form of batches without an explicit flag (autotuned)
 };
 
 // An operator refers to its context; destroy operators before the context.
@@ -255,6 +256,22 @@ hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, const i
                                    const int32_t* xg0, const int64_t* xbase,
                                    const XcdLaunch& xl, int64_t grid, int step, bool pattern,
                                    int maxnz, int zmode);
+// Steps 2 .. steps of a batch in one cooperative launch of 8 * per_xcd
+// workgroups (per_xcd from csr_batch_persistent_per_xcd: the resident
+// count), after step 1 ran as a batched launch; slots_at[s][x] = running
+// slots of XCD x at step s (entries as in XcdLaunch, xl.slots unused); cnt:
+// nblocks ints of scratch (zeroed here); abort_flag: one int, set if a
+// block barrier's wait exceeded spin_ticks of the 100 MHz real-time clock.
+// zmode: the moment form after the first step.
+hipError_t launch_csr_batch_persistent(hipStream_t s, const BatchBlock* tab,
+                                       const int32_t* xblk, const int32_t* xg0,
+                                       const int64_t* xbase, const XcdLaunch& xl, int steps,
+                                       const int64_t* slots_at, int* cnt, int nblocks,
+                                       int* abort_flag, int per_xcd, bool pattern, int maxnz,
+                                       int zmode, long long spin_ticks);
+// Workgroups per XCD of the persistent kernel that can be resident at once
+// on the current device (0 if the query fails).
+int csr_batch_persistent_per_xcd(bool pattern, int maxnz, int zmode);
 // zmode: 0 = dots with V_k (symmetric form), 1 = regenerated Rademacher z,
 // 2 = explicit z entries.  has_prev = false for the first step (no V_prev).
 // hub_part: workspace of op->hub_chunks x 64 elements of T (unused without

@@ -711,6 +711,105 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
       B.part + (size_t)s * 2 * B.ngroups * 64, bid);
 }
 
+// ---- one persistent launch for the steps of a batch ---------------------------
+// Step 1 of every block runs as a plain batched launch; steps 2 .. S run in
+// one launch whose grid is sized to be resident all at once (cooperative
+// launch).  The workgroups of XCD x share that XCD's slot list (the layout
+// of the batched launches): at step s, slots 0 .. slots_at[s][x] - 1 belong
+// to the blocks still running, and workgroup j of the XCD takes slots j,
+// j + P_x, ... .  Before a band of block b starts step s, every band of b
+// must have finished step s - 1 (its vector is gathered from all rows); a
+// band's arrival is counted in cnt[b] after its writes are released at
+// device scope, and the wait acquires them.  A workgroup finishes all its
+// step-(s - 1) slots before any step-s slot, so every wait ends once all
+// workgroups are resident.  A wait longer than spin_ticks of the 100 MHz
+// real-time clock (or a raised abort flag) sets the flag and ends the
+// kernel, so no wave can wait forever.
+struct PersistLaunch {
+  int first[8];            // the XCD's first entry
+  int count[8];            // its entries
+  int per_xcd;             // workgroups per XCD in the grid
+  int steps;               // largest step count
+  const int64_t* slots_at; // [steps + 1][8] running slots per XCD and step
+  int* cnt;                // [nblocks] band arrivals from step 2 on, zero at launch
+  int* abort_flag;         // set on a wait that timed out
+  long long spin_ticks;
+};
+
+__device__ __forceinline__ bool persist_wait(const PersistLaunch& pl, int blk, int target) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+    ok = 1;
+    while (__hip_atomic_load(pl.cnt + blk, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(pl.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+          (long long)__builtin_amdgcn_s_memrealtime() - t0 > pl.spin_ticks) {
+        __hip_atomic_store(pl.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// ZMODE: the moment form of steps 2 .. S (0 symmetric, 1 direct).  A
+// workgroup's consecutive slots of one block share one wait and one
+// release (its arrivals are added together before it waits on another
+// block or leaves the step).
+template <bool PATTERN, int ZMODE, int MAXNZ, int TAIL>
+__global__ __launch_bounds__(kThreads) void csr_batch_persistent_kernel(
+    const BatchBlock* __restrict__ tab, const int32_t* __restrict__ xblk,
+    const int32_t* __restrict__ xg0, const int64_t* __restrict__ xbase, PersistLaunch pl) {
+  const int x = blockIdx.x & 7;
+  const int j = blockIdx.x >> 3;
+  auto release = [&](int blk, int n) {
+    __syncthreads();  // every wave's rows and partials are written
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(pl.cnt + blk, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  for (int s = 2; s <= pl.steps; ++s) {
+    const int64_t nslots = pl.slots_at[(size_t)s * 8 + x];
+    int held = -1, pending = 0;  // block whose barrier this step has passed; arrivals owed
+    for (int64_t slot = j; slot < nslots; slot += pl.per_xcd) {
+      int lo = pl.first[x], hi = pl.first[x] + pl.count[x] - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (xbase[mid] <= slot) lo = mid; else hi = mid - 1;
+      }
+      const int bi = __builtin_amdgcn_readfirstlane(xblk[lo]);
+      const BatchBlock& B = tab[bi];
+      const int g = xg0[lo] + (int)(slot - xbase[lo]);
+      const int per = B.ngroups >> 3;
+      const int bid = (g % per) * 8 + g / per;
+      if (bi != held) {
+        if (pending) release(held, pending);
+        pending = 0;
+        if (s > 2 && !persist_wait(pl, bi, (s - 2) * B.ngroups)) return;
+        held = bi;
+      }
+      const float* vk = (s - 1) & 1 ? B.v1 : B.v0;
+      float* vm = s & 1 ? B.v1 : B.v0;
+      RecEpi<float, ZMODE, true> epi((float)(2.0 * B.alpha), (float)(2.0 * B.beta), vm, B.src);
+      const HubView nohub{nullptr, nullptr, 0, nullptr};
+      const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
+      csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
+          B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, plan,
+          B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+      __syncthreads();  // the step body's shared partial buffer is reused
+      ++pending;
+    }
+    if (pending) release(held, pending);
+  }
+}
+
+__global__ void fill_zero_i32_kernel(int* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 __global__ __launch_bounds__(kThreads) void probe_init_batched_kernel(
     const BatchBlock* __restrict__ tab, int nblocks) {
   const int bi = __builtin_amdgcn_readfirstlane(find_block(tab, nblocks, blockIdx.x));
@@ -1012,6 +1111,74 @@ hipError_t launch_csr_step_batched(hipStream_t s, const BatchBlock* tab, const i
 #undef MLCT_BATCH_M
 #undef MLCT_BATCH
   return hipGetLastError();
+}
+
+hipError_t launch_csr_batch_persistent(hipStream_t s, const BatchBlock* tab,
+                                       const int32_t* xblk, const int32_t* xg0,
+                                       const int64_t* xbase, const XcdLaunch& xl, int steps,
+                                       const int64_t* slots_at, int* cnt, int nblocks,
+                                       int* abort_flag, int per_xcd, bool pattern, int maxnz,
+                                       int zmode, long long spin_ticks) {
+  const int64_t nz = nblocks + 1;
+  fill_zero_i32_kernel<<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(cnt, nblocks);
+  fill_zero_i32_kernel<<<1, 64, 0, s>>>(abort_flag, 1);
+  PersistLaunch pl;
+  for (int x = 0; x < 8; ++x) {
+    pl.first[x] = xl.first[x];
+    pl.count[x] = xl.count[x];
+  }
+  pl.per_xcd = per_xcd;
+  pl.steps = steps;
+  pl.slots_at = slots_at;
+  pl.cnt = cnt;
+  pl.abort_flag = abort_flag;
+  pl.spin_ticks = spin_ticks;
+  void* args[] = {(void*)&tab, (void*)&xblk, (void*)&xg0, (void*)&xbase, (void*)&pl};
+  const dim3 grid((unsigned)(8 * per_xcd)), block(kThreads);
+#define MLCT_PERSIST(P, Z, M, T)                                                          \
+  return hipLaunchCooperativeKernel((const void*)csr_batch_persistent_kernel<P, Z, M, T>, \
+                                    grid, block, args, 0, s)
+#define MLCT_PERSIST_M(P, Z)                              \
+  if (maxnz <= 4) MLCT_PERSIST(P, Z, 4, kTailNone);       \
+  else if (maxnz <= 5) MLCT_PERSIST(P, Z, 5, kTailNone);  \
+  else if (maxnz <= 8) MLCT_PERSIST(P, Z, 8, kTailNone);  \
+  else MLCT_PERSIST(P, Z, 8, kTailGen)
+#define MLCT_PERSIST_Z(P) \
+  if (zmode == 0) { MLCT_PERSIST_M(P, 0); } else { MLCT_PERSIST_M(P, 1); }
+  if (pattern) { MLCT_PERSIST_Z(true); } else { MLCT_PERSIST_Z(false); }
+#undef MLCT_PERSIST_Z
+#undef MLCT_PERSIST_M
+#undef MLCT_PERSIST
+}
+
+int csr_batch_persistent_per_xcd(bool pattern, int maxnz, int zmode) {
+  int per_cu = 0;
+  hipError_t e = hipSuccess;
+#define MLCT_OCC(P, Z, M, T)                                                                \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                                         \
+      &per_cu, (const void*)csr_batch_persistent_kernel<P, Z, M, T>, kThreads, 0)
+#define MLCT_OCC_M(P, Z)                              \
+  if (maxnz <= 4) MLCT_OCC(P, Z, 4, kTailNone);       \
+  else if (maxnz <= 5) MLCT_OCC(P, Z, 5, kTailNone);  \
+  else if (maxnz <= 8) MLCT_OCC(P, Z, 8, kTailNone);  \
+  else MLCT_OCC(P, Z, 8, kTailGen)
+#define MLCT_OCC_Z(P) \
+  if (zmode == 0) { MLCT_OCC_M(P, 0); } else { MLCT_OCC_M(P, 1); }
+  if (pattern) { MLCT_OCC_Z(true); } else { MLCT_OCC_Z(false); }
+#undef MLCT_OCC_Z
+#undef MLCT_OCC_M
+#undef MLCT_OCC
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return per_cu * cus / 8;
 }
 
 template hipError_t launch_probe_init<float>(hipStream_t, float*, int64_t, ProbeSrc,

@@ -30,6 +30,8 @@ MLCT_DT_F32, MLCT_DT_F64, MLCT_DT_PATTERN = 0, 1, 2
 MLCT_PROBE_RADEMACHER, MLCT_PROBE_EXPLICIT = 0, 1
 MLCT_MAX_LEVELS = 32
 MLCT_EXACT_LOW = 0x20
+MLCT_BATCH_PERSISTENT = 0x40
+MLCT_BATCH_LOCKSTEP = 0x80
 MLCT_FLAG_FEW_SAMPLES, MLCT_FLAG_OVERFLOW, MLCT_FLAG_BF16 = 0x1, 0x2, 0x4
 MLCT_KERNEL_CSR_STEP, MLCT_KERNEL_DENSE_STEP, MLCT_KERNEL_TRI_STEP, MLCT_KERNEL_GRAM = 0, 1, 2, 3
 MLCT_KERNEL_BATCH_STEP, MLCT_KERNEL_GRAM_CSR_STEP = 4, 5
@@ -441,6 +443,35 @@ def mlct_mlp_grad(ctx: Context, mlp: Mlp, X, y):
 class mlct_batch_item(C.Structure):
     _fields_ = [("op", C.c_void_p), ("f", mlct_func), ("a", C.c_double), ("b", C.c_double),
                 ("levels", mlct_levels), ("seed", C.c_uint64)]
+
+
+def _batch_items(items):
+    n = len(items)
+    arr = (mlct_batch_item * n)()
+    keep = []
+    for i, it in enumerate(items):
+        L = len(it["degrees"])
+        deg = (C.c_int32 * L)(*[int(x) for x in it["degrees"]])
+        mm = (C.c_int64 * L)(*[int(x) for x in it["m"]])
+        keep += [deg, mm]
+        arr[i] = mlct_batch_item(it["op"].handle, mlct_func(it["kind"], it.get("power", 1.0)),
+                                 it["a"], it["b"], mlct_levels(L, deg, mm),
+                                 it["seed"] & ((1 << 64) - 1))
+    return arr, keep
+
+
+def mlct_autotune_batch(ctx: Context, items, prec: int = MLCT_FP32,
+                        mode: int = MLCT_DOUBLING) -> int:
+    """Times both batch launch forms on these items; returns 1 if the
+    persistent launch was faster (the context then uses it by default)."""
+    h = lib()
+    h.mlct_autotune_batch.argtypes = [C.c_void_p, C.c_int32, C.POINTER(mlct_batch_item),
+                                      C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    h.mlct_autotune_batch.restype = C.c_int
+    arr, keep = _batch_items(items)
+    ch = C.c_int32()
+    _check(ctx, h.mlct_autotune_batch(ctx.handle, len(items), arr, prec, mode, C.byref(ch)))
+    return ch.value
 
 
 def mlct_estimate_batch(ctx: Context, items, prec: int = MLCT_FP32, mode: int = MLCT_DOUBLING):

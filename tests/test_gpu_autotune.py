@@ -51,3 +51,35 @@ def test_autotune_dense():
     o = estimator.estimate(A, 512, cheb.LOG, 0.1, 1.0, [8, 64], [192, 64], 5, doubling=True)
     assert r["value"] == pytest.approx(o.value, rel=1e-11)
     op.close(); ctx.close()
+
+
+def test_autotune_dense_cache_is_applied(tmp_path):
+    """A dense decision written to the cache file is used by another
+    context's operator of the same shape for blocks of the tuned width and
+    precision: moments equal the tuned operator's bit for bit; a corrupt
+    cache value is ignored (the default rule runs)."""
+    import torch
+
+    from paper_2103_10516_amd import mlct
+
+    cache = tmp_path / "tune.txt"
+    A, lam = wl.random_symmetric(1024, 3, -1.0, 1.0)
+    At = torch.from_numpy(A.astype(np.float32)).cuda()
+    ctx = mlct.mlct_create(0, tune_cache=cache)
+    op = mlct.mlct_op_dense(ctx, At)
+    choice = mlct.mlct_autotune(ctx, op, 320, mlct.MLCT_BF16X3)
+    assert "dense d=1024 prec=2 bpad=320" in cache.read_text()
+    pr = mlct.rademacher_probes(4, 320)
+    m1 = mlct.mlct_moments(ctx, op, -1.1, 1.1, 20, pr, mlct.MLCT_BF16X3, mlct.MLCT_DOUBLING)
+    ctx2 = mlct.mlct_create(0, tune_cache=cache)
+    op2 = mlct.mlct_op_dense(ctx2, At)
+    m2 = mlct.mlct_moments(ctx2, op2, -1.1, 1.1, 20, pr, mlct.MLCT_BF16X3, mlct.MLCT_DOUBLING)
+    assert np.array_equal(m1, m2), choice
+    op.close(); op2.close(); ctx.close(); ctx2.close()
+    bad = tmp_path / "bad.txt"
+    bad.write_text(f"dense d=1024 prec=2 bpad=320 = 77\ncsr d=5 nnz=13 maxrow=3 pattern=0 = 100\n")
+    ctx3 = mlct.mlct_create(0, tune_cache=bad)
+    op3 = mlct.mlct_op_dense(ctx3, At)
+    m3 = mlct.mlct_moments(ctx3, op3, -1.1, 1.1, 20, pr, mlct.MLCT_BF16X3, mlct.MLCT_DOUBLING)
+    assert np.all(m3[:, 0] == 1024)
+    op3.close(); ctx3.close()

@@ -33,11 +33,15 @@ def _op(ctx, g):
     return mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.col).cuda(), vl)
 
 
+@pytest.mark.parametrize("launch", ["lockstep", "persistent"])
 @pytest.mark.parametrize("mode", ["doubling", "direct"])
-def test_batch_equals_single_calls(ctx, mode):
+def test_batch_equals_single_calls(ctx, mode, launch):
+    """Both launch forms: one launch per step, and one persistent launch per
+    row-length class with per-block barriers (three classes here)."""
     from paper_2103_10516_amd import mlct
 
     M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    BM = M | (mlct.MLCT_BATCH_PERSISTENT if launch == "persistent" else 0)
     items = []
     graphs = []
     for i, n in enumerate([7, 12, 20, 33]):
@@ -52,7 +56,7 @@ def test_batch_equals_single_calls(ctx, mode):
         lam = np.linalg.eigvalsh(g.to_dense())
         items.append(dict(op=_op(ctx, g), kind=mlct.MLCT_EXP, a=lam.min() - 1, b=lam.max() + 1,
                           degrees=[10, 30], m=[64 + 7 * i, 20], seed=90 + i))
-    res = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, M)
+    res = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, BM)
     for it, r, g in zip(items, res, graphs):
         one = mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"],
                                  it["m"], it["seed"], mlct.MLCT_FP32, M)
@@ -91,9 +95,17 @@ def test_graph_batch_full_sizes(ctx):
                                  it["m"], it["seed"], mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
               for it in items]
     t_single = time.perf_counter() - t0
-    print(f"64-graph batch: {t_batch * 1e3:.1f} ms batched vs {t_single * 1e3:.1f} ms one by one")
-    for r, o in zip(res, single):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pers = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32,
+                                    mlct.MLCT_DOUBLING | mlct.MLCT_BATCH_PERSISTENT)
+    t_pers = time.perf_counter() - t0
+    print(f"64-graph batch: {t_batch * 1e3:.1f} ms batched (launch per step), "
+          f"{t_pers * 1e3:.1f} ms persistent, {t_single * 1e3:.1f} ms one by one")
+    for r, o, p in zip(res, single, pers):
         assert r["value"] == o["value"]
+        assert p["value"] == o["value"]
+        assert np.array_equal(p["level_var"], o["level_var"])
 
 
 def _random_sym(d, per_row, seed):
@@ -144,5 +156,31 @@ def test_batch_equals_block_by_block_on_large_operators(ctx, mode):
                                  it["m"], it["seed"], mlct.MLCT_FP32, md)
         assert r["value"] == one["value"] and r["est_var"] == one["est_var"]
         np.testing.assert_array_equal(r["level_mean"], one["level_mean"])
+    for it in items:
+        it["op"].close()
+
+
+def test_autotune_batch_launch_form(ctx):
+    """The batch autotuner times both launch forms and the context then uses
+    the faster one by default; all three calls give the same results."""
+    from paper_2103_10516_amd import mlct
+
+    items = []
+    for i, n in enumerate([10, 14, 18]):
+        g = wl.laplacian_3d(n)
+        items.append(dict(op=_op(ctx, g), kind=mlct.MLCT_LOG, a=0.01, b=12.01, degrees=[6, 30],
+                          m=[130, 64], seed=70 + i))
+    choice = mlct.mlct_autotune_batch(ctx, items)
+    assert choice in (0, 1)
+    default = mlct.mlct_estimate_batch(ctx, items)
+    lock = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32,
+                                    mlct.MLCT_DOUBLING | mlct.MLCT_BATCH_LOCKSTEP)
+    pers = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32,
+                                    mlct.MLCT_DOUBLING | mlct.MLCT_BATCH_PERSISTENT)
+    for a, b, c in zip(default, lock, pers):
+        assert a["value"] == b["value"] == c["value"]
+    with pytest.raises(mlct.MlctError):
+        mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, mlct.MLCT_DOUBLING |
+                                 mlct.MLCT_BATCH_LOCKSTEP | mlct.MLCT_BATCH_PERSISTENT)
     for it in items:
         it["op"].close()
