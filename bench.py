@@ -409,6 +409,43 @@ def _best_of(k, fn):
     return best
 
 
+def extra_two_step(mlct, dev):
+    """Two recurrence steps per launch (MLCT_OPT_TWO_STEP, off by default)
+    against one, on the headline operator (2D Laplacian 2048^2): one block
+    of 64 probes to degree 400 in the symmetric form (200 steps), kernel time
+    per step of each form (best of three calls), the HBM traffic counted per
+    launch of each kernel, and the largest moment difference (FP64
+    association only: the vectors are the same)."""
+    import torch
+
+    w = laplace2d_workload(2048)
+    g = w["graph"]
+    ctx = mlct.mlct_create(0)
+    op = mlct.mlct_op_csr(ctx, torch.from_numpy(g.rowptr).to(dev),
+                          torch.from_numpy(g.col).to(dev), torch.from_numpy(g.val).to(dev))
+    pr = mlct.rademacher_probes(77, 64)
+    out, mu = {}, {}
+    for two, kid in ((0, mlct.MLCT_KERNEL_CSR_STEP), (1, mlct.MLCT_KERNEL_CSR_STEP2)):
+        mlct.mlct_set_option(ctx, mlct.MLCT_OPT_TWO_STEP, two)
+        best = None
+        for _ in range(3):
+            mlct.mlct_timing(ctx, True)
+            mu[two] = mlct.mlct_moments(ctx, op, w["a"], w["b"], 400, pr, mlct.MLCT_FP32,
+                                        mlct.MLCT_DOUBLING)
+            mlct.mlct_timing(ctx, False)
+            steps, ms = mlct.mlct_timing_read(ctx, kid)
+            best = ms / steps if best is None else min(best, ms / steps)
+        out["two_step_ms_per_step" if two else "single_step_ms_per_step"] = best
+    op.close()
+    ctx.close()
+    t1, t2 = stored_traffic("csr_step_" + w["name"]), stored_traffic("csr_fused2_" + w["name"])
+    return {"workload": "2D Laplacian 2048^2, one 64-probe block to degree 400, doubling, FP32",
+            **out, "speedup_two_step": out["single_step_ms_per_step"] / out["two_step_ms_per_step"],
+            "traffic_single_step_per_launch": t1, "traffic_two_step_per_launch": t2,
+            "traffic_two_step_per_step": t2 / 2 if t2 else None,
+            "max_moment_diff_over_d": float(np.max(np.abs(mu[1] - mu[0]))) / g.d}
+
+
 def extra_laplace_batch(mlct, dev):
     """Batching on the 32 shifted 3D Laplacians n_i = round(32 * 4^(i/31))
     (d = 32^3 .. 128^3, + 0.01 I, [0.01, 12.01]), f = log, levels 8 / 256 with
@@ -797,7 +834,7 @@ def main():
     ap.add_argument("--grid", type=int, default=2048, help="2D grid edge (default 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", default="dense,dense_rungs,triangles,estrada,batch,laplace_batch,"
-                                        "time_to_eps,time_to_eps_dense,gram_csr,slq,learned_batch",
+                                        "time_to_eps,time_to_eps_dense,gram_csr,slq,learned_batch,two_step",
                     help="comma list of secondary measurements to add ('' for none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 device copies of 1 GiB (a plain copy kernel of known "
@@ -850,19 +887,32 @@ def main():
     dt = time.perf_counter() - t0
     mlct.mlct_timing(ctx, False)
     launches, kms = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_CSR_STEP)
+    steps2, kms2 = mlct.mlct_timing_read(ctx, mlct.MLCT_KERNEL_CSR_STEP2)
     print(f"# timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
 
     pd = res["probe_degrees"] * args.steps
     mv = res["matvecs"] * args.steps
     width = 64
-    # every launch reads A and v_k and writes v_{k+1}; all but the first step
-    # of a probe block also read v_{k-1}
+    # algorithmic bytes of one recurrence step: A, v_k read and v_{k+1}
+    # written; all but the first step of a probe block also read v_{k-1}
     blocks = args.steps * sum(-(-m // width) for m in w["m"])
-    bytes_launch = (8 * g.nnz + 4 * (g.d + 1) + 8 * g.d * width
-                    + 4 * g.d * width * (launches - blocks) / max(launches, 1))
+    nsteps = launches + steps2
+    bytes_step = (8 * g.nnz + 4 * (g.d + 1) + 8 * g.d * width
+                  + 4 * g.d * width * (nsteps - blocks) / max(nsteps, 1))
+    if steps2:
+        # two steps per launch (a trailing odd step alone): the launch count
+        # follows from the levels' step counts
+        S = [(n + 1) // 2 if mode == mlct.MLCT_DOUBLING else n for n in w["degrees"]]
+        launches = args.steps * sum(-(-m // width) * ((s + 1) // 2) for m, s in zip(w["m"], S))
+        kms, units = kms2, steps2
+        kernel, prof = "csr_fused2_kernel<...> (two steps per launch)", "csr_fused2_"
+    else:
+        units = launches
+        kernel, prof = "csr_step_kernel<float,valued,...>", "csr_step_"
     avg_s = kms / 1e3 / max(launches, 1)
+    bytes_launch = bytes_step * units / max(launches, 1)
     achieved = bytes_launch / avg_s / 1e9
-    traffic = stored_traffic("csr_step_" + w["name"])
+    traffic = stored_traffic(prof + w["name"])
     out = {
         "metric": "probe*degree matvecs/s",
         "value": pd / dt,
@@ -882,9 +932,11 @@ def main():
         "estimate_last_step": res["estimate"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "csr_step_kernel<float,valued,...>",
+                     "traffic": traffic, "kernel": kernel,
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "avg_launch_ms": avg_s * 1e3, "launches": launches},
+                     "algorithmic_bytes_per_step": bytes_step, "steps_per_launch": units / max(launches, 1),
+                     "avg_launch_ms": avg_s * 1e3, "launches": launches,
+                     "traffic_rate_GBs": traffic / avg_s / 1e9 if traffic else None},
     }
     op.close()
     ctx.close()
@@ -895,7 +947,7 @@ def main():
               "triangles": extra_triangles, "estrada": extra_estrada,
               "batch": extra_graph_batch, "time_to_eps": extra_time_to_eps,
               "time_to_eps_dense": extra_time_to_eps_dense, "learned_batch": extra_learned_batch,
-              "laplace_batch": extra_laplace_batch,
+              "laplace_batch": extra_laplace_batch, "two_step": extra_two_step,
               "gram_csr": extra_gram_csr, "slq": extra_slq}
     secondary = {}
     for name in [e for e in args.extras.split(",") if e]:

@@ -173,6 +173,39 @@ const char* mlct_last_error(const mlct_ctx* ctx);
  * would exceed it fails with MLCT_ENOMEM before enqueuing any work. */
 mlct_status mlct_set_workspace_limit(mlct_ctx* ctx, uint64_t bytes);
 
+/* Context options.  MLCT_OPT_TWO_STEP (default 0): 1 runs two recurrence steps
+ * per launch where the operator allows it (CSR, FP32, at most 5 entries per
+ * row, no column farther from its row than 1/16 of the rows, Rademacher
+ * probes, and a device whose eight XCDs all receive workgroups of a launch,
+ * probed once per context); 0 runs one step per launch.  On the MI355X the
+ * two-step launch is measured slower than two single steps (its second
+ * step finds too little of the first step's output still in L2), so it is
+ * off by default.  The probe vectors
+ * are the same bit for bit either way, and so are the moments where one
+ * step's workgroups take at most 512 rows each (up to 1,048,576 rows); on
+ * larger operators the moments' FP64 sums are taken per 512-row tile
+ * instead of per workgroup band, which moves them by rounding only (about
+ * 1e-13 of |z|^2).  A two-step call whose
+ * launch left an XCD's rows unprocessed fails with MLCT_EDEVICE.  Errors:
+ * EINVAL (unknown option or value). */
+#define MLCT_OPT_TWO_STEP 1
+/* MLCT_OPT_WAIT_LIMIT_US (default 2,000,000): the longest a two-step launch
+ * waits for a neighbouring tile before it gives up; a call whose launch gave
+ * up fails with MLCT_EDEVICE (its outputs are then unspecified) and the
+ * context stays usable.  0..60,000,000. */
+#define MLCT_OPT_WAIT_LIMIT_US 2
+/* Tuning knobs of the two-step launch with no effect on the vectors (0 = the
+ * library's choice): MLCT_OPT_TWO_STEP_LAG, how many tiles the first step
+ * runs ahead of the second beyond twice the operator's bandwidth (default
+ * 64, 0..4096); MLCT_OPT_TWO_STEP_ROWS, rows per tile (default: the
+ * single-step bands up to 512 rows, else 512; a multiple of 8 up to 8192;
+ * sets the moments' summation order); MLCT_OPT_TWO_STEP_WGS, workgroups
+ * per XCD (default 64, up to 512). */
+#define MLCT_OPT_TWO_STEP_LAG 3
+#define MLCT_OPT_TWO_STEP_ROWS 4
+#define MLCT_OPT_TWO_STEP_WGS 5
+mlct_status mlct_set_option(mlct_ctx* ctx, int32_t option, int64_t value);
+
 /* Per-kernel device time of the library's own launches, measured with HIP
  * events recorded on the context stream around every launch of the kernel
  * families below while timing is enabled (used for roofline figures).
@@ -190,7 +223,10 @@ typedef enum {
   MLCT_KERNEL_SLQ_SPMM = 6,   /* Lanczos product u = A w_j with the alpha dots */
   MLCT_KERNEL_SLQ_UPDATE = 7, /* Lanczos three-term update with the beta dots  */
   MLCT_KERNEL_CALLBACK_STEP = 8, /* recurrence update after a callback product */
-  MLCT_NUM_KERNEL_IDS = 9
+  MLCT_KERNEL_CSR_STEP2 = 9,  /* two CSR recurrence steps in one launch; its
+                                 count is of steps (two per launch, one for a
+                                 trailing single step)                       */
+  MLCT_NUM_KERNEL_IDS = 10
 } mlct_kernel_id;
 mlct_status mlct_timing(mlct_ctx* ctx, int32_t enable);
 mlct_status mlct_timing_read(const mlct_ctx* ctx, int32_t kernel, int64_t* launches,

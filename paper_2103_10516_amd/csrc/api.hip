@@ -146,9 +146,14 @@ struct LaunchTimer {
       return;
     }
     (void)hipEventRecord(stop, ctx->stream);
-    ctx->pending.push_back({start, stop, kernel});
+    ctx->pending.push_back({start, stop, kernel, units});
     start = nullptr;
   }
+  void done(int n) {
+    units = n;
+    done();
+  }
+  int units = 1;
 };
 
 // Called after the context stream has been synchronised.
@@ -157,7 +162,7 @@ void collect_timing(mlct_ctx* ctx) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
       ctx->kernel_ms[t.kernel] += ms;
-      ctx->kernel_launches[t.kernel] += 1;
+      ctx->kernel_launches[t.kernel] += t.units;
     }
     ctx->event_pool.push_back(t.start);
     ctx->event_pool.push_back(t.stop);
@@ -168,6 +173,13 @@ void collect_timing(mlct_ctx* ctx) {
 mlct_status sync_stream(mlct_ctx* ctx) {
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   collect_timing(ctx);
+  if (ctx->fused_check) {
+    ctx->fused_check = false;
+    int32_t ab = 0;
+    HIPCHK(ctx, hipMemcpy(&ab, ctx->fused_abort, sizeof ab, hipMemcpyDeviceToHost));
+    if (ab == 1) return fail(ctx, MLCT_EDEVICE, "a two-step launch's tile wait timed out");
+    if (ab) return fail(ctx, MLCT_EDEVICE, "a two-step launch left an XCD's tiles unprocessed");
+  }
   return MLCT_OK;
 }
 
@@ -310,6 +322,7 @@ struct CsrBlockBufs {
   double* dots = nullptr;
   void* hub = nullptr;
   bool timed = true;  // record kernel timing events (these may allocate)
+  int* fsync = nullptr;  // two-step launches: tickets, flags and abort flag (null: single steps)
 };
 
 // Bytes of each buffer for a block of degree ``degree`` in form ``mode``.
@@ -327,12 +340,101 @@ CsrBlockSizes csr_block_sizes(const mlct_op* op, size_t tsz, int mode, int degre
   return z;
 }
 
+// Launch shape of the two-step path (csr_fused2_kernel), or ok = false where
+// it does not apply: FP32 CSR with at most 5 entries per row and a known
+// bandwidth, no hub rows, Rademacher probes, and tiles enough that each
+// XCD's range holds more than twice the window.
+constexpr int kFusedRows = 512;  // default rows per tile
+constexpr int kFusedWgs = 64;    // default workgroups per XCD (2 per CU, all resident)
+constexpr int kFusedLag = 64;    // default lag beyond twice the window, in tiles
+// Chunks of the per-launch partial reduction of a two-step block: one
+// (the single-step association) up to 2048 tiles, else 64 (a divisor: the
+// tile count is a multiple of 8, and rounded to one of 64 there).
+int fused_chunks(int ntiles) { return ntiles <= 2048 ? 1 : 64; }
+struct FusedPlan {
+  bool ok = false;
+  int rows, ntiles, window, lag, grid;
+};
+FusedPlan fused_plan(const mlct_ctx* ctx, const mlct_op* op, const ProbeSrc& src, size_t tsz) {
+  FusedPlan f;
+  if (!ctx->two_step || tsz != 4 || op->kind != OP_CSR || op->csr.max_row_nnz > 5 ||
+      op->csr.bandwidth < 0 || op->csr.nnz < 1 || op->csr.hub_n > 0 || src.entries)
+    return f;
+  // tiles: the single-step bands where these are short (then the moment
+  // sums are bitwise the single-step path's), else kFusedRows rows
+  const CsrStepPlan bands = plan_csr(op->d, op->tuned_groups);
+  int64_t nt;
+  if (ctx->two_step_rows == 0 && bands.rows_per_group <= kFusedRows) {
+    f.rows = bands.rows_per_group;
+    nt = bands.ngroups;
+  } else {
+    f.rows = ctx->two_step_rows > 0 ? ctx->two_step_rows : kFusedRows;
+    nt = ((op->d + f.rows - 1) / f.rows + 7) / 8 * 8;
+    if (nt > 2048) nt = (nt + 63) / 64 * 64;  // whole chunks of the partial reduction
+  }
+  const int64_t w = ((int64_t)op->csr.bandwidth + f.rows - 1) / f.rows;
+  if (nt > (int64_t)1 << 24 || nt / 8 <= 2 * w || nt < 64) return f;
+  f.ntiles = (int)nt;
+  f.window = (int)w;
+  f.lag = 2 * f.window + 1 + (ctx->two_step_lag > 0 ? ctx->two_step_lag : kFusedLag);
+  f.grid = 8 * (ctx->two_step_wgs > 0 ? ctx->two_step_wgs : kFusedWgs);
+  f.ok = true;
+  return f;
+}
+
 template <typename T>
 mlct_status run_block_csr_in(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                              int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu,
                              const CsrBlockBufs& bb) {
   const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
   const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
+  if (bb.fsync) {
+    // two steps per launch: the single steps' vectors; the moment partials
+    // per tile, reduced after every launch
+    const FusedPlan f = fused_plan(ctx, op, src, sizeof(T));
+    CsrStepPlan tp;
+    tp.ngroups = f.ntiles;
+    tp.rows_per_group = f.rows;
+    float* x = static_cast<float*>(bb.v1);  // V_{s-1} -> V_{s+1}
+    float* y = static_cast<float*>(bb.v0);  // V_s -> V_{s+2}
+    const size_t pstep = (size_t)2 * f.ntiles * kBlockProbes;
+    double* P = bb.part;
+    hipStream_t s = ctx->stream;
+    int* abort_flag = ctx->fused_abort;
+    // After every launch its tile partials are summed, in a fixed order, into
+    // C chunk sums per step (C = 1 where the tiles are few: then the sums
+    // are the single-step path's), and the chunks of all steps at the end.
+    const int C = fused_chunks(f.ntiles);
+    double* Q = C > 1 ? P + 2 * pstep : bb.dots;  // [S+1][2][C][64]
+    auto reduce_launch = [&](int step0, int nsteps) {
+      return launch_reduce_partials(s, P, 1, nsteps * 2 * C, f.ntiles / C, kBlockProbes,
+                                    Q + (size_t)step0 * 2 * C * kBlockProbes);
+    };
+    HIPCHK(ctx, launch_probe_init<float>(s, y, op->d, src, tp, P));
+    HIPCHK(ctx, reduce_launch(0, 1));
+    if (!ctx->fused_check) HIPCHK(ctx, launch_fill_zero_i32(s, abort_flag, 1));
+    ctx->fused_check = true;
+    int prev_total = 0;
+    for (int k = 1; k <= S; k += 2) {
+      const bool first = k == 1, two = k + 1 <= S;
+      const float ca1 = (float)(first ? alpha : 2.0 * alpha), cb1 = (float)(first ? beta : 2.0 * beta);
+      const int zm1 = (mode == MLCT_DOUBLING || first) ? 0 : 1;
+      const int zm2 = mode == MLCT_DOUBLING ? 0 : 1;
+      LaunchTimer tm(ctx, MLCT_KERNEL_CSR_STEP2);
+      HIPCHK(ctx, launch_csr_fused2(s, op->csr, x, y, ca1, cb1, !first, (float)(2.0 * alpha),
+                                    (float)(2.0 * beta), two, zm1, zm2, src, f.rows, f.ntiles,
+                                    f.window, P, P + pstep, bb.fsync, abort_flag, f.grid, f.lag,
+                                    prev_total, ctx->wait_limit_us * 100LL));
+      tm.done(two ? 2 : 1);
+      prev_total = two ? 2 * (f.ntiles / 8) : f.ntiles / 8;
+      HIPCHK(ctx, reduce_launch(k, two ? 2 : 1));
+    }
+    HIPCHK(ctx, launch_fused_sync(s, bb.fsync, 0, prev_total, abort_flag));
+    if (C > 1) HIPCHK(ctx, launch_reduce_partials(s, Q, S + 1, 2, C, kBlockProbes, bb.dots));
+    HIPCHK(ctx, launch_assemble_moments(s, bb.dots, S + 1, kBlockProbes, src.active, mode, degree,
+                                        mu_rows, ldmu));
+    return MLCT_OK;
+  }
   const size_t pstep = (size_t)2 * plan.ngroups * kBlockProbes;  // doubles per step
   T* buf[2] = {static_cast<T*>(bb.v0), static_cast<T*>(bb.v1)};
   double* P = bb.part;
@@ -366,6 +468,24 @@ mlct_status run_block_csr_in(mlct_ctx* ctx, const mlct_op* op, double alpha, dou
   return MLCT_OK;
 }
 
+// Two-step launches give each XCD one eighth of the tiles, so they need
+// every XCD to receive workgroups (true when the device dispatches
+// workgroups to its XCDs in turn; not on a partition that holds one XCD).
+// Checked once per context with a launch of the same grid.
+mlct_status probe_xcds(mlct_ctx* ctx, int* buf, int grid) {
+  HIPCHK(ctx, launch_xcc_probe(ctx->stream, buf, grid));
+  std::vector<int> ids(grid);
+  HIPCHK(ctx, hipMemcpyAsync(ids.data(), buf, grid * sizeof(int), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int v : ids) count[v & 7]++;
+  ctx->xcd_ok = 1;
+  for (int x = 0; x < 8; ++x)
+    if (count[x] == 0) ctx->xcd_ok = 0;
+  return MLCT_OK;
+}
+
 template <typename T>
 mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double beta,
                           int degree, int mode, ProbeSrc src, double* mu_rows, int64_t ldmu) {
@@ -380,6 +500,30 @@ mlct_status run_block_csr(mlct_ctx* ctx, const mlct_op* op, double alpha, double
   if (z.hub) CHECK(ws_get(ctx, WS_HUB, z.hub, &bb.hub));
   bb.part = static_cast<double*>(part);
   bb.dots = static_cast<double*>(dots);
+  const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
+  const FusedPlan f = fused_plan(ctx, op, src, sizeof(T));
+  if (f.ok) {
+    void *fs, *fa;
+    const size_t nsync = std::max<size_t>(8 + (size_t)f.ntiles, (size_t)f.grid);
+    CHECK(ws_get(ctx, WS_FSYNC, nsync * sizeof(int), &fs));
+    CHECK(ws_get(ctx, WS_FABORT, 64, &fa));  // never grows: the address stays valid
+    if (ctx->xcd_ok < 0) CHECK(probe_xcds(ctx, static_cast<int*>(fs), f.grid));
+    if (ctx->xcd_ok > 0) {
+      // partials of two steps at a time, per tile, then the chunk sums of
+      // every step
+      const int C = fused_chunks(f.ntiles);
+      const int S = (mode == MLCT_DOUBLING) ? (degree + 1) / 2 : degree;
+      const size_t fpart =
+          ((size_t)2 * 2 * f.ntiles + (C > 1 ? (size_t)(S + 1) * 2 * C : 0)) * kBlockProbes *
+          sizeof(double);
+      if (fpart > z.part) {
+        CHECK(ws_get(ctx, WS_PART, fpart, &part));
+        bb.part = static_cast<double*>(part);
+      }
+      bb.fsync = static_cast<int*>(fs);
+      ctx->fused_abort = static_cast<int*>(fa);
+    }
+  }
   return run_block_csr_in<T>(ctx, op, alpha, beta, degree, mode, src, mu_rows, ldmu, bb);
 }
 
@@ -905,6 +1049,38 @@ mlct_status mlct_set_workspace_limit(mlct_ctx* ctx, uint64_t bytes) {
   return MLCT_OK;
 }
 
+mlct_status mlct_set_option(mlct_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return MLCT_EINVAL;
+  ctx->err.clear();
+  if (option == MLCT_OPT_TWO_STEP) {
+    if (value != 0 && value != 1) return fail(ctx, MLCT_EINVAL, "MLCT_OPT_TWO_STEP takes 0 or 1");
+    ctx->two_step = (int)value;
+    return MLCT_OK;
+  }
+  if (option == MLCT_OPT_TWO_STEP_LAG) {
+    if (value < 0 || value > 4096) return fail(ctx, MLCT_EINVAL, "MLCT_OPT_TWO_STEP_LAG takes 0..4096");
+    ctx->two_step_lag = (int)value;
+    return MLCT_OK;
+  }
+  if (option == MLCT_OPT_TWO_STEP_ROWS) {
+    if (value < 0 || value > 8192 || value % 8)
+      return fail(ctx, MLCT_EINVAL, "MLCT_OPT_TWO_STEP_ROWS takes 0 or a multiple of 8 up to 8192");
+    ctx->two_step_rows = (int)value;
+    return MLCT_OK;
+  }
+  if (option == MLCT_OPT_TWO_STEP_WGS) {
+    if (value < 0 || value > 512) return fail(ctx, MLCT_EINVAL, "MLCT_OPT_TWO_STEP_WGS takes 0..512");
+    ctx->two_step_wgs = (int)value;
+    return MLCT_OK;
+  }
+  if (option == MLCT_OPT_WAIT_LIMIT_US) {
+    if (value < 0 || value > 60000000) return fail(ctx, MLCT_EINVAL, "wait limit must be in [0, 6e7] us");
+    ctx->wait_limit_us = value;
+    return MLCT_OK;
+  }
+  return fail(ctx, MLCT_EINVAL, "unknown option %d", option);
+}
+
 mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* rowptr_dev,
                         const int32_t* col_dev, const void* val_dev, int32_t dtype,
                         mlct_op** out) {
@@ -947,6 +1123,20 @@ mlct_status mlct_op_csr(mlct_ctx* ctx, int64_t d, int64_t nnz, const int32_t* ro
   op->csr.max_row_nnz = hf[1];
   op->tuned_groups = std::max(0, tune_lookup(ctx, tune_key(op, MLCT_FP32, 64), kCsrGroupCands));
   mlct_status st = MLCT_OK;
+  if (op->csr.max_row_nnz <= 5 && nnz > 0) {
+    // the bandwidth decides whether two steps fit one launch
+    hipError_t e = hipMemsetAsync(flags, 0, sizeof(int32_t), ctx->stream);
+    if (e == hipSuccess)
+      e = launch_csr_bandwidth(ctx->stream, rowptr_dev, col_dev, d, static_cast<int32_t*>(flags));
+    int32_t bw = -1;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bw, flags, sizeof bw, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      mlct_op_destroy(op);
+      return fail(ctx, MLCT_EDEVICE, "bandwidth: %s", hipGetErrorString(e));
+    }
+    op->csr.bandwidth = bw;
+  }
   if (op->csr.max_row_nnz > kHubLen) st = build_hubs(ctx, op->csr, &op->hub_mem);
   if (st == MLCT_OK) st = refresh_bands(ctx, op);
   if (st != MLCT_OK) {

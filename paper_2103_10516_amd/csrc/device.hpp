@@ -42,6 +42,13 @@ __device__ __forceinline__ int wave_id() {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// XCD (XCC) that executes the calling workgroup, from the hardware register.
+__device__ __forceinline__ int xcc_of_wg() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
+  return (int)(v & 7u);
+}
+
 // The functions f of tr f(A) (mlct_func_kind).
 __device__ __forceinline__ double eval_f(int kind, double power, double t) {
   switch (kind) {

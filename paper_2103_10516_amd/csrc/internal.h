@@ -32,6 +32,7 @@ struct CsrMat {
   const float* val = nullptr;  // nullptr = 0/1 pattern
   int64_t nrows = 0, ncols = 0, nnz = 0;
   int max_row_nnz = 0;
+  int bandwidth = -1;  // max |column - row|, found for rows of at most 5 entries (-1: unknown)
   int32_t* hub_rows = nullptr;  // [hub_n] sorted
   int32_t* hub_c0 = nullptr;    // [hub_n + 1]
   int32_t* hub_cs = nullptr;    // [hub_chunks] first entry of each chunk
@@ -73,6 +74,7 @@ struct MlpAffine {
 struct mlct_timed_launch {
   hipEvent_t start, stop;
   int kernel;
+  int units;  // recurrence steps the launch ran (1, or 2 for a two-step launch)
 };
 
 struct mlct_ctx {
@@ -93,6 +95,14 @@ struct mlct_ctx {
   std::string tune_path;            // autotune cache file ("" = none)
   std::vector<std::string> tune_lines;  // cached decisions, one per operator shape
   int batch_persistent = 0;  // launch form of batches without an explicit flag (autotuned)
+  int two_step = 0;          // two recurrence steps per launch where the operator allows (opt-in)
+  int two_step_lag = 0;      // tiles sub-step 1 runs ahead beyond twice the window (0: default)
+  int two_step_rows = 0;     // rows per tile of a two-step launch (0: default)
+  int two_step_wgs = 0;      // workgroups per XCD of a two-step launch (0: default)
+  int xcd_ok = -1;           // every XCD receives workgroups of a two-step launch (-1: not probed)
+  int64_t wait_limit_us = 2000000;  // bound on a two-step launch's tile wait
+  int* fused_abort = nullptr;  // device flag of the two-step launches since the last check
+  bool fused_check = false;    // a two-step launch ran: check the flag at the next sync
 };
 
 // An operator refers to its context; destroy operators before the context.
@@ -160,7 +170,7 @@ namespace mlct {
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
   WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ,
-  WS_DPACK, WS_CBW, WS_NSLOTS
+  WS_DPACK, WS_CBW, WS_FSYNC, WS_FABORT, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -297,6 +307,35 @@ hipError_t launch_csr_bands(hipStream_t s, const int32_t* rowptr, int64_t d, int
                             int32_t* band);
 hipError_t launch_hub_find(hipStream_t s, const int32_t* rowptr, int64_t d, int32_t* out,
                            int32_t* count, int cap);
+
+// ---- two recurrence steps per launch (csr_fused2_kernel in k_csr.hip; the
+// support kernels in k_fused.hip) ------------------------------------------------
+// CSR operators with at most 5 entries per row, FP32, Rademacher probes:
+// tiles of rows_per_tile rows (ntiles a multiple of 8), each XCD taking one
+// eighth of them in order, sub-step 2 of a tile waiting on sub-step 1 of the
+// tiles within `window` of it, issued `lag` (> 2 window) tiles ahead.  The
+// vectors are bitwise those of launch_csr_step.  x holds V_{s-1} and
+// receives V_{s+1}; y holds V_s and receives V_{s+2} (two = false: sub-step
+// 1 only).  zm1 / zm2: moment form of each sub-step (0 symmetric, 1
+// direct); part1 / part2: [2][ntiles][64] partials.  sync: 8 + ntiles ints
+// (cleared here, after checking the previous launch's counters against
+// prev_total when > 0); abort_flag: 1 if a wait exceeded spin_ticks of the
+// 100 MHz clock, 2 if an XCD's tiles were left unprocessed.
+hipError_t launch_csr_fused2(hipStream_t s, const CsrMat& m, float* x, float* y, float ca1,
+                             float cb1, bool prev1, float ca2, float cb2, bool two, int zm1,
+                             int zm2, ProbeSrc src, int rows_per_tile, int ntiles, int window,
+                             double* part1, double* part2, int* sync, int* abort_flag,
+                             int grid, int lag, int prev_total, long long spin_ticks);
+// Clears sync[0 .. n-1] after the counter check described above (n = 0:
+// the check of a block's last launch only).
+hipError_t launch_fused_sync(hipStream_t s, int* sync, int64_t n, int prev_total,
+                             int* abort_flag);
+// out[w] = XCD of workgroup w of a grid-workgroup launch.
+hipError_t launch_xcc_probe(hipStream_t s, int* out, int grid);
+hipError_t launch_csr_bandwidth(hipStream_t s, const int32_t* rowptr, const int32_t* col,
+                                int64_t d, int32_t* out);
+// p[0 .. n-1] = 0 by a kernel (safe inside a captured graph).
+hipError_t launch_fill_zero_i32(hipStream_t s, int* p, int64_t n);
 
 // ---- matrix-free operator (k_callback.hip) ----------------------------------
 // V_new = ca W + cb V_k (- V_prev) over the d x 64 block, W = A V_k from the

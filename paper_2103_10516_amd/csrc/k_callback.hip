@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kCbThreads) void callback_step_kernel(
   for (int64_t i = r0 + wave; i < r1; i += kCbWaves) {
     const int64_t e = i * 64 + lane;
     const float xi = vk[e];
-    float vn = ca * __builtin_nontemporal_load(w + e) + cb * xi;
+    float vn = fmaf(ca, __builtin_nontemporal_load(w + e), cb * xi);
     if (HAS_PREV) vn -= __builtin_nontemporal_load(vm + e);
     __builtin_nontemporal_store(vn, vm + e);
     if (ZMODE == 0) {

@@ -102,9 +102,10 @@ __global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0
 }
 
 // Per-row epilogue of the recurrence: V_new = ca*acc + cb*V_k[i] (- V_prev[i]),
-// written over V_prev with a non-temporal store, and the lane's moment
-// partials (FP64).
-template <typename T, int ZMODE, bool HAS_PREV>
+// written over V_prev (with a non-temporal store unless KEEP: a vector
+// gathered again soon is stored normally, to stay in the caches), and the
+// lane's moment partials (FP64).
+template <typename T, int ZMODE, bool HAS_PREV, bool KEEP = false>
 struct RecEpi {
   using Part = double;
   static constexpr bool kOwn = true;    // needs V_k[i] of its own row
@@ -127,9 +128,14 @@ struct RecEpi {
   }
   __device__ __forceinline__ void finish(int64_t i, T acc, T xi, T xp) {
     const int lane = lane_id();
-    T vn = ca * acc + cb * xi;
+    // one explicit contraction, so every kernel that shares this update
+    // (the two-step kernel included) rounds it the same way
+    T vn = fma(ca, acc, cb * xi);
     if (HAS_PREV) vn -= xp;
-    __builtin_nontemporal_store(vn, vm + i * 64 + lane);
+    if (KEEP)
+      vm[i * 64 + lane] = vn;
+    else
+      __builtin_nontemporal_store(vn, vm + i * 64 + lane);
     if (ZMODE == 0) {
       a1 += (double)xi * (double)vn;
       a2 += (double)vn * (double)vn;
@@ -983,6 +989,173 @@ hipError_t launch_gram_z(hipStream_t s, const CsrMat& X, const CsrMat& XT, const
   });
 }
 
+
+// ---- two recurrence steps per launch ------------------------------------------
+// For operators whose rows have at most 5 entries and whose columns lie
+// within a bandwidth of the row (every column of a row in tile j lies in
+// tiles j - w .. j + w), one launch applies the recurrence (Section 2.2, eq.
+// eqn:recurrence) twice:
+//   sub-step 1 on tile j: V_{s+1} = ca1 A V_s + cb1 V_s (- V_{s-1}) over V_{s-1}
+//   sub-step 2 on tile j: V_{s+2} = ca2 A V_{s+1} + cb2 V_{s+1} - V_s  over V_s
+// each tile through csr_step_wg, the single-step kernel's body, so every
+// vector entry is bitwise the single-step path's (only the association of
+// the FP64 moment sums follows the tiles).
+//
+// Work order: the tiles are split into eight contiguous ranges, one per XCD
+// (read from the hardware XCC_ID register), and the workgroups of an XCD
+// take tickets from that XCD's counter: sub-step 1 of its first L tiles,
+// then alternately one sub-step 2 and the sub-step 1 L tiles ahead; the
+// sub-steps 2 run from the range's tile w upward and its first w tiles come
+// last.  With L > 2 w every sub-step 2 of the range was issued after the
+// sub-steps 1 it gathers from inside the range; the first w tiles, which
+// also gather from the top of the range below, wait for it at the end.
+// Sub-steps 1 never wait, so every wait ends whether or not all workgroups
+// are resident; waits are bounded by the real-time clock and an abort flag
+// besides.  The lag L (chosen > 2 w + 64) leaves a tile's neighbours time to
+// finish before its sub-step 2 claims them; V_{s+1} and V_s are then still
+// in the memory-side cache, so the block vectors cross HBM about four times
+// per two steps instead of six.
+//
+// Coherence: within an XCD a writer's stores complete (to the XCD's L2)
+// before its tile flag is set, and a waiter polls the flags past its L1 and
+// invalidates its L1 before gathering.  Tiles read by another XCD (the
+// first and last w of a range) are released and acquired at device scope.
+struct Fused2Args {
+  const int32_t* rowptr;
+  const int32_t* col;
+  const float* val;
+  int64_t d, nnz;
+  float* x;  // V_{s-1} in, V_{s+1} out
+  float* y;  // V_s in, V_{s+2} out
+  float ca1, cb1, ca2, cb2;
+  ProbeSrc src;
+  int rows_per_tile, ntiles, window, lag;
+  int two;        // 1: both sub-steps; 0: sub-step 1 only
+  double* part1;  // [2][ntiles][64] partials of sub-step 1
+  double* part2;  // [2][ntiles][64] partials of sub-step 2
+  int* tickets;   // [8] ticket counters, zero at launch
+  int* done;      // [ntiles] sub-step 1 completion flags, zero at launch
+  int* abort_flag;
+  long long spin_ticks;
+};
+
+// Ticket k of an XCD's range of per tiles -> (sub-step, tile in the range).
+__device__ __forceinline__ void fused_ticket(int k, int per, int lag, int w, int two, int& sub,
+                                             int& t) {
+  if (!two) {
+    sub = 1;
+    t = k;
+    return;
+  }
+  const int L = min(lag, per);
+  if (k < L) {
+    sub = 1;
+    t = k;
+    return;
+  }
+  const int m = k - L;
+  const int pairs = per - L;
+  int j;
+  if (m < 2 * pairs) {
+    if (m & 1) {
+      sub = 1;
+      t = (m >> 1) + L;
+      return;
+    }
+    j = m >> 1;
+  } else {
+    j = pairs + (m - 2 * pairs);
+  }
+  sub = 2;
+  t = j + w < per ? j + w : j + w - per;
+}
+
+// Thread 0 waits for the flags of tiles t0 .. t1; far: some lie in another
+// XCD's range (acquire at device scope), else the L1 is invalidated.
+__device__ __forceinline__ bool fused_wait(const Fused2Args& a, int t0, int t1, bool far) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    ok = 1;
+    const long long c0 = (long long)__builtin_amdgcn_s_memrealtime();
+    for (int t = t0; t <= t1 && ok; ++t) {
+      while (__hip_atomic_load(a.done + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            (long long)__builtin_amdgcn_s_memrealtime() - c0 > a.spin_ticks) {
+          __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    if (far)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    else
+      asm volatile("buffer_inv sc0" ::: "memory");
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(ok) != 0;
+}
+
+template <bool PATTERN, int Z1, int Z2, bool PREV1, int MAXNZ, bool OFF32>
+__global__ __launch_bounds__(kThreads) void csr_fused2_kernel(Fused2Args a) {
+  __shared__ int tk;
+  const int xcd = xcc_of_wg();
+  const int per = a.ntiles >> 3;
+  const int base = xcd * per;
+  const int total = a.two ? 2 * per : per;
+  const int w = a.window;
+  CsrStepPlan plan;
+  plan.ngroups = a.ntiles;
+  plan.rows_per_group = a.rows_per_tile;
+  plan.band = nullptr;
+  const HubView hub{nullptr, nullptr, 0, nullptr};
+  // Thread 0 sets the flag of the sub-step-1 tile just done and claims the
+  // next ticket in one block at the loop head, and the ticket is made
+  // wave-uniform: the loop's control flow is then uniform, so no lane of
+  // wave 0 can be split off into a loop of its own (two adjacent thread-0
+  // blocks let the compiler send the other lanes straight back to the
+  // barrier, where they re-read the old ticket).
+  int pending = -1;
+  bool pending_far = false;
+  while (true) {
+    if (threadIdx.x == 0) {
+      if (pending >= 0) {
+        if (pending_far)
+          __hip_atomic_store(a.done + pending, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          __hip_atomic_store(a.done + pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      tk = atomicAdd(a.tickets + xcd, 1);
+    }
+    __syncthreads();
+    const int k = __builtin_amdgcn_readfirstlane(tk);
+    __syncthreads();  // tk is rewritten by the next claim
+    if (k >= total) break;
+    int sub, t;
+    fused_ticket(k, per, a.lag, w, a.two, sub, t);
+    const int bid = t * 8 + xcd;  // the workgroup index whose band is tile base + t
+    if (sub == 1) {
+      RecEpi<float, Z1, PREV1, true> epi(a.ca1, a.cb1, a.x, a.src);
+      csr_step_wg<float, PATTERN, MAXNZ, OFF32, kTailNone, false>(
+          a.rowptr, a.col, a.val, a.d, a.d, a.nnz, a.y, nullptr, epi, hub, plan, a.part1, bid);
+      // every wave's stores complete (in L2) before the flag is set
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      pending = base + t;
+      pending_far = t < w || t >= per - w;
+    } else {
+      pending = -1;
+      const int tile = base + t;
+      const int t0 = max(0, tile - w), t1 = min(a.ntiles - 1, tile + w);
+      if (!fused_wait(a, t0, t1, t0 < base || t1 >= base + per)) break;
+      RecEpi<float, Z2, true> epi(a.ca2, a.cb2, a.y, a.src);
+      csr_step_wg<float, PATTERN, MAXNZ, OFF32, kTailNone, false>(
+          a.rowptr, a.col, a.val, a.d, a.d, a.nnz, a.x, nullptr, epi, hub, plan, a.part2, bid);
+    }
+  }
+}
+
 }  // namespace
 
 CsrStepPlan plan_csr(int64_t d, int max_groups) {
@@ -1179,6 +1352,64 @@ int csr_batch_persistent_per_xcd(bool pattern, int maxnz, int zmode) {
     return 0;
   }
   return per_cu * cus / 8;
+}
+
+
+hipError_t launch_csr_fused2(hipStream_t s, const CsrMat& m, float* x, float* y, float ca1,
+                             float cb1, bool prev1, float ca2, float cb2, bool two, int zm1,
+                             int zm2, ProbeSrc src, int rows_per_tile, int ntiles, int window,
+                             double* part1, double* part2, int* sync, int* abort_flag,
+                             int grid, int lag, int prev_total, long long spin_ticks) {
+  // sync: [8] tickets, [ntiles] flags, cleared for every launch (after the
+  // previous launch's counters are checked)
+  hipError_t e = launch_fused_sync(s, sync, 8 + (int64_t)ntiles, prev_total, abort_flag);
+  if (e != hipSuccess) return e;
+  Fused2Args a;
+  a.rowptr = m.rowptr;
+  a.col = m.col;
+  a.val = m.val;
+  a.d = m.nrows;
+  a.nnz = m.nnz;
+  a.x = x;
+  a.y = y;
+  a.ca1 = ca1;
+  a.cb1 = cb1;
+  a.ca2 = ca2;
+  a.cb2 = cb2;
+  a.src = src;
+  a.rows_per_tile = rows_per_tile;
+  a.ntiles = ntiles;
+  a.window = window;
+  a.lag = lag;
+  a.two = two ? 1 : 0;
+  a.part1 = part1;
+  a.part2 = part2;
+  a.tickets = sync;
+  a.done = sync + 8;
+  a.abort_flag = abort_flag;
+  a.spin_ticks = spin_ticks;
+  const bool pat = m.val == nullptr;
+  const bool off32 = block_off32<float>(m.ncols);
+  const int mz = m.max_row_nnz <= 4 ? 4 : 5;
+  const dim3 g(grid), b(kThreads);
+#define MLCT_F(P, Z1, Z2, PV, M, O) csr_fused2_kernel<P, Z1, Z2, PV, M, O><<<g, b, 0, s>>>(a)
+#define MLCT_F_O(P, Z1, Z2, PV, M) \
+  if (off32) { MLCT_F(P, Z1, Z2, PV, M, true); } else { MLCT_F(P, Z1, Z2, PV, M, false); }
+#define MLCT_F_M(P, Z1, Z2, PV) \
+  if (mz == 4) { MLCT_F_O(P, Z1, Z2, PV, 4) } else { MLCT_F_O(P, Z1, Z2, PV, 5) }
+#define MLCT_F_PV(P, Z1, Z2) \
+  if (prev1) { MLCT_F_M(P, Z1, Z2, true) } else { MLCT_F_M(P, Z1, Z2, false) }
+#define MLCT_F_Z(P)                                            \
+  if (zm1 == 0 && zm2 == 0) { MLCT_F_PV(P, 0, 0) }             \
+  else if (zm1 == 0) { MLCT_F_PV(P, 0, 1) }                    \
+  else { MLCT_F_PV(P, 1, 1) }
+  if (pat) { MLCT_F_Z(true) } else { MLCT_F_Z(false) }
+#undef MLCT_F_Z
+#undef MLCT_F_PV
+#undef MLCT_F_M
+#undef MLCT_F_O
+#undef MLCT_F
+  return hipGetLastError();
 }
 
 template hipError_t launch_probe_init<float>(hipStream_t, float*, int64_t, ProbeSrc,

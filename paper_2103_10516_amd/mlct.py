@@ -37,6 +37,12 @@ MLCT_KERNEL_CSR_STEP, MLCT_KERNEL_DENSE_STEP, MLCT_KERNEL_TRI_STEP, MLCT_KERNEL_
 MLCT_KERNEL_BATCH_STEP, MLCT_KERNEL_GRAM_CSR_STEP = 4, 5
 MLCT_KERNEL_SLQ_SPMM, MLCT_KERNEL_SLQ_UPDATE = 6, 7
 MLCT_KERNEL_CALLBACK_STEP = 8
+MLCT_KERNEL_CSR_STEP2 = 9
+MLCT_OPT_TWO_STEP = 1
+MLCT_OPT_WAIT_LIMIT_US = 2
+MLCT_OPT_TWO_STEP_LAG = 3
+MLCT_OPT_TWO_STEP_ROWS = 4
+MLCT_OPT_TWO_STEP_WGS = 5
 
 
 class mlct_func(C.Structure):
@@ -198,6 +204,13 @@ def mlct_timing_read(ctx: Context, kernel: int):
 
 def mlct_set_workspace_limit(ctx: Context, nbytes: int):
     _check(ctx, lib().mlct_set_workspace_limit(ctx.handle, int(nbytes)))
+
+
+def mlct_set_option(ctx: Context, option: int, value: int):
+    h = lib()
+    h.mlct_set_option.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
+    h.mlct_set_option.restype = C.c_int
+    _check(ctx, h.mlct_set_option(ctx.handle, option, int(value)))
 
 
 def mlct_op_csr(ctx: Context, rowptr, col, val=None) -> Op:

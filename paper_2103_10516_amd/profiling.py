@@ -35,10 +35,10 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_source_hash() -> str:
-    """Hash of the code (comments and blank space removed) of k_csr.hip and
-    device.hpp, stored with the counter figures."""
+    """Hash of the code (comments and blank space removed) of k_csr.hip,
+    k_fused.hip and device.hpp, stored with the counter figures."""
     h = hashlib.sha256()
-    for f in ("k_csr.hip", "device.hpp"):
+    for f in ("k_csr.hip", "k_fused.hip", "device.hpp"):
         with open(os.path.join(ROOT, "paper_2103_10516_amd", "csrc", f)) as fh:
             h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
