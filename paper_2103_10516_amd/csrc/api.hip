@@ -1656,10 +1656,11 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
   if (m < 1) return fail(ctx, MLCT_EINVAL, "need m >= 1 probes");
   CHECK(set_device(ctx));
   const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
-  const size_t vbytes = (size_t)op->d * kBlockProbes * sizeof(int32_t);
-  void *z, *y, *part, *w, *res;
-  CHECK(ws_get(ctx, WS_V0, vbytes, &z));
-  CHECK(ws_get(ctx, WS_V1, vbytes, &y));
+  void *z, *y, *part, *w, *res, *side = nullptr;
+  CHECK(ws_get(ctx, WS_V0, (size_t)op->d * sizeof(uint64_t), &z));        // packed signs
+  CHECK(ws_get(ctx, WS_V1, (size_t)op->d * kBlockProbes * sizeof(int16_t), &y));
+  if (op->csr.hub_n > 0)
+    CHECK(ws_get(ctx, WS_TRISIDE, (size_t)op->csr.hub_n * kBlockProbes * sizeof(int32_t), &side));
   CHECK(ws_get(ctx, WS_PART, (size_t)2 * plan.ngroups * kBlockProbes * sizeof(long long), &part));
   CHECK(ws_get(ctx, WS_TRI, (size_t)m * 3 * sizeof(long long), &w));
   CHECK(ws_get(ctx, WS_RESULT, sizeof(mlct_tri_result), &res));
@@ -1674,17 +1675,18 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
     src.seed = seed;
     src.first_id = p0;
     src.active = (int32_t)((m - p0) < kBlockProbes ? (m - p0) : kBlockProbes);
-    HIPCHK(ctx, launch_tri_init(s, op, src, plan, static_cast<int32_t*>(z)));
+    HIPCHK(ctx, launch_tri_init(s, op, src, plan, static_cast<uint64_t*>(z)));
     {
       LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
-      HIPCHK(ctx, launch_tri_step(s, op->csr, 1, plan, static_cast<int32_t*>(z),
-                                  static_cast<int32_t*>(y), hub, P));
+      HIPCHK(ctx, launch_tri_step(s, op->csr, 1, plan, static_cast<uint64_t*>(z),
+                                  static_cast<int16_t*>(y), static_cast<int32_t*>(side), hub, P));
       tm.done();
     }
     HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 1, W, p0));
     {
       LaunchTimer tm(ctx, MLCT_KERNEL_TRI_STEP);
-      HIPCHK(ctx, launch_tri_step(s, op->csr, 2, plan, static_cast<int32_t*>(y), nullptr, hub, P));
+      HIPCHK(ctx, launch_tri_step(s, op->csr, 2, plan, nullptr, static_cast<int16_t*>(y),
+                                  static_cast<int32_t*>(side), hub, P));
       tm.done();
     }
     HIPCHK(ctx, launch_tri_reduce(s, P, plan.ngroups, src.active, 2, W, p0));

@@ -170,7 +170,7 @@ namespace mlct {
 enum Slot {
   WS_V0 = 0, WS_V1, WS_PART, WS_MU, WS_COEF, WS_QSTAT, WS_RESULT, WS_MISC,
   WS_TRI, WS_LANCZOS, WS_DENSE, WS_MLP, WS_MU2, WS_BATCH, WS_HUB, WS_PLAN, WS_STATS, WS_GRAMW, WS_SLQ, WS_SLQQ,
-  WS_DPACK, WS_CBW, WS_FSYNC, WS_FABORT, WS_NSLOTS
+  WS_DPACK, WS_CBW, WS_FSYNC, WS_FABORT, WS_TRISIDE, WS_NSLOTS
 };
 
 // ---- probe-generation constants (SplitMix64) ------------------------------
@@ -388,10 +388,15 @@ hipError_t launch_slq_combine(hipStream_t s, const double* mu, int64_t ldmu, con
                               double log_scale, mlct_result* out);
 
 // ---- integer triangle moments (k_tri.hip) ----------------------------------
+// z of a probe block packed one 64-bit word per row (bit p: probe p is -1).
 hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
-                           const CsrStepPlan& plan, int32_t* z);
+                           const CsrStepPlan& plan, uint64_t* zbits);
+// Pass 1 gathers zbits and writes y = A z (int16 rows [d][64]; values past
+// +-32767 as -32768 with the exact value in side[hub slot][64]); pass 2
+// gathers y.  side: [hub_n][64] int32; hub_part: the hub chunk partials.
 hipError_t launch_tri_step(hipStream_t s, const CsrMat& m, int pass, const CsrStepPlan& plan,
-                           const int32_t* vin, int32_t* vout, void* hub_part, long long* part);
+                           const uint64_t* zbits, int16_t* y, int32_t* side, void* hub_part,
+                           long long* part);
 hipError_t launch_tri_reduce(hipStream_t s, const long long* part, int ngroups, int active,
                              int pass, long long* w, int64_t p0);
 hipError_t launch_tri_cv(hipStream_t s, const long long* w, int64_t m, int64_t nnz,

@@ -153,25 +153,54 @@ struct RecEpi {
   }
 };
 
-// Per-row epilogue of the triangle passes (int32 vectors, exact int64 sums):
-//   PASS 1: y = A z stored, slot 0 = z.y, slot 1 = y.y
+// The int16 form of y (triangle passes): a value outside [-32767, 32767]
+// is stored as this sentinel, its exact value in the row of its hub (rows
+// longer than kHubLen, the only ones that can hold such a value) in a side
+// table.
+constexpr int32_t kY16Sentinel = -32768;
+struct HubSide {
+  const int32_t* rows;  // sorted hub row ids
+  int n;
+  int32_t* side;        // [n][64] exact values of the sentinel entries
+  __device__ __forceinline__ int slot(int64_t i) const {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (rows[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  }
+};
+
+// Per-row epilogue of the triangle passes (exact int64 sums):
+//   PASS 1: y = A z stored as int16 rows (a value beyond +-32767 as the
+//           sentinel, exact in the hub side table: see Y16Reader),
+//           slot 0 = z.y, slot 1 = y.y
 //   PASS 2: w = A y not stored, slot 0 = y.w.
-// |y_i| <= deg(i) and |w_i| <= nnz < 2^31, so int32 holds every entry.
+// |y_i| <= deg(i) and |w_i| <= nnz < 2^31, so int32 holds every sum.
 template <int PASS>
 struct TriEpi {
   using Part = long long;
   static constexpr bool kOwn = true;
   static constexpr bool kParts = true;
-  int32_t* vout;
+  int16_t* vout;
+  HubSide hs;
   long long a1 = 0, a2 = 0;
-  __device__ explicit TriEpi(int32_t* v) : vout(v) {}
+  __device__ TriEpi(int16_t* v, const HubSide& h) : vout(v), hs(h) {}
   __device__ __forceinline__ int32_t prev(int64_t) const { return 0; }
   __device__ __forceinline__ void finish(int64_t i, int32_t acc, int32_t own, int32_t) {
+    const int lane = lane_id();
     if (PASS == 1) {
-      vout[i * 64 + lane_id()] = acc;
+      int16_t st = (int16_t)acc;
+      if (__builtin_expect(acc < -32767 || acc > 32767, 0)) {
+        st = (int16_t)kY16Sentinel;
+        hs.side[(int64_t)hs.slot(i) * 64 + lane] = acc;
+      }
+      __builtin_nontemporal_store(st, vout + i * 64 + lane);
       a1 += (long long)own * acc;
       a2 += (long long)acc * acc;
     } else {
+      if (__builtin_expect(own == kY16Sentinel, 0)) own = hs.side[(int64_t)hs.slot(i) * 64 + lane];
       a1 += (long long)own * acc;
     }
   }
@@ -229,6 +258,8 @@ __device__ __forceinline__ T accum(T acc, float w, bool on, T x) {
 // as 0 (the resource's size is the block's size).
 template <typename T, bool OFF32>
 struct RowReader {
+  using Elem = T;  // element type of the gathered block
+  using Val = T;   // type of a gathered value
   const T* base;
   __amdgpu_buffer_rsrc_t rsrc;
   uint32_t lane_off;
@@ -250,7 +281,91 @@ struct RowReader {
       return base[j * 64 + lane];
     }
   }
+  // a gathered value as the row sum takes it (the raw value here)
+  static constexpr bool kFix = false;
+  __device__ __forceinline__ T fix(int64_t, T x) const { return x; }
 };
+
+// Triangle pass 1 gathers only Rademacher signs: one 64-bit word per row,
+// bit p set where probe p is -1.  Every lane of a wave gathers the same row:
+// lanes 0-31 load its low 32 bits and lanes 32-63 its high 32 bits by a
+// vector buffer load from a scalar row offset (one 8-byte request; vector
+// loads keep many more gathers in flight than scalar loads would).
+struct SignBitsReader {
+  using Elem = uint64_t;
+  using Val = int32_t;
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t half_off;
+  int shift;
+  __device__ __forceinline__ SignBitsReader(const uint64_t* b, int64_t d, int lane) {
+    rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint64_t*>(b), (short)0,
+                                             (int)(uint32_t)(d * sizeof(uint64_t)), 0x00020000);
+    half_off = (uint32_t)(lane >> 5) * 4;
+    shift = lane & 31;
+  }
+  __device__ __forceinline__ int32_t operator()(int64_t j, int) const {
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(
+        rsrc, half_off, (int)((uint32_t)j * (uint32_t)sizeof(uint64_t)), 0);
+    return 1 - 2 * (int32_t)((w >> shift) & 1u);
+  }
+  static constexpr bool kFix = false;
+  __device__ __forceinline__ int32_t fix(int64_t, int32_t x) const { return x; }
+};
+
+// Rows of 64 int16 values (triangle pass 2 gathers y = A z, |y_i| <= the
+// degree of row i).  A value outside [-32767, 32767], possible only on rows
+// longer than kHubLen (the hub rows), is stored as the sentinel -32768 with
+// the exact int32 value in that hub's row of a side table; fix() takes it
+// from there.  It is applied when the value is summed, after every gather
+// of the group was issued, so the check does not stall the gathers.
+template <bool OFF32>
+struct Y16Reader {
+  using Elem = int16_t;
+  using Val = int32_t;
+  const int16_t* base;
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t lane_off;
+  HubSide hs;
+  __device__ __forceinline__ Y16Reader(const int16_t* y, int64_t d, int lane, const HubSide& h)
+      : base(y), hs(h) {
+    if (OFF32) {
+      rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<int16_t*>(y), (short)0,
+                                               (int)(uint32_t)(d * 64 * sizeof(int16_t)),
+                                               0x00020000);
+      lane_off = (uint32_t)lane * sizeof(int16_t);
+    }
+  }
+  __device__ __forceinline__ int32_t operator()(int64_t j, int lane) const {
+    if constexpr (OFF32) {
+      const uint16_t bits = __builtin_amdgcn_raw_buffer_load_b16(
+          rsrc, lane_off, (int)((uint32_t)j * (uint32_t)(64 * sizeof(int16_t))), 0);
+      return (int32_t)(int16_t)bits;
+    } else {
+      return base[j * 64 + lane];
+    }
+  }
+  static constexpr bool kFix = true;
+  __device__ __forceinline__ int32_t fix(int64_t j, int32_t x) const {
+    if (__builtin_expect(x == kY16Sentinel, 0)) x = hs.side[(int64_t)hs.slot(j) * 64 + lane_id()];
+    return x;
+  }
+};
+
+// Applies rd.fix to n gathered values (x[u] from column col(u)) with one
+// test per batch: the sentinel is the smallest int16, so a batch holds one
+// only if its minimum equals it (rare: only hub rows' extreme sums).
+template <class RD, int N, class X, class C>
+__device__ __forceinline__ void fix_batch(const RD& rd, X* x, C col) {
+  if constexpr (RD::kFix) {
+    int32_t m = x[0];
+#pragma unroll
+    for (int u = 1; u < N; ++u) m = min(m, (int32_t)x[u]);
+    if (__builtin_expect(m == kY16Sentinel, 0)) {
+#pragma unroll
+      for (int u = 0; u < N; ++u) x[u] = rd.fix(col(u), x[u]);
+    }
+  }
+}
 
 // Generic row: 64-entry chunks of the row's columns, each loaded in one
 // coalesced read, then gathered 16 at a time (all 16 in flight before the
@@ -280,6 +395,7 @@ __device__ __forceinline__ T row_dot_generic(const int32_t* __restrict__ col,
       T x[kGen];
 #pragma unroll
       for (int u = 0; u < kGen; ++u) x[u] = rd(read_lane(cj, min(t + u, c - 1)), lane);
+      fix_batch<RD, kGen>(rd, x, [&](int u) { return read_lane(cj, min(t + u, c - 1)); });
 #pragma unroll
       for (int u = 0; u < kGen; ++u)
         acc = accum<T, PATTERN>(acc, PATTERN ? 1.f : read_lane(av, min(t + u, c - 1)),
@@ -370,10 +486,11 @@ __device__ __forceinline__ GroupExt<ROWS> group_extent(int rs, int rlen, int q, 
 // d: rows processed; dv: rows of the gathered block vk.  SEP: the own-row
 // value V_k[i] the epilogue needs comes from vown instead of vk (the second
 // product of a Gram step gathers from W but recurs on V_k).
-template <typename T, bool PATTERN, int MAXNZ, bool OFF32, int TAIL, bool SEP, class Epi>
+template <typename T, bool PATTERN, int MAXNZ, bool OFF32, int TAIL, bool SEP, class Epi,
+          class RD = RowReader<T, OFF32>>
 __device__ __forceinline__ void csr_step_wg(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ vk,
+    const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const RD& rd,
     const T* __restrict__ vown, Epi& epi, const HubView& hub, const CsrStepPlan& plan,
     typename Epi::Part* __restrict__ part, int bid) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
@@ -389,7 +506,6 @@ __device__ __forceinline__ void csr_step_wg(
 
   const int64_t ngrp = r1 > r0 ? (r1 - r0 + ROWS - 1) / ROWS : 0;  // groups in the band
   const int64_t nk = ngrp > wave ? (ngrp - wave + kWaves - 1) / kWaves : 0;  // this wave's
-  const RowReader<T, OFF32> rd(vk, dv, lane);
   auto own = [&](int64_t i) -> T {
     if constexpr (!Epi::kOwn) return T(0);
     else if constexpr (SEP) return vown[i * 64 + lane];
@@ -455,6 +571,12 @@ __device__ __forceinline__ void csr_step_wg(
         if (nnz > 0) load_cols(nxt, cjn, avn);
       }
       if (fast) {
+        if constexpr (RD::kFix) {
+#pragma unroll
+          for (int r = 0; r < ROWS; ++r)
+            fix_batch<RD, (MAXNZ > 0 ? MAXNZ : 1)>(
+                rd, x[r], [&](int t) { return read_lane(cj, min(cur.off[r] + t, 63)); });
+        }
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
           T acc = T(0);
@@ -509,6 +631,7 @@ __device__ __forceinline__ void csr_step_wg(
               T xg[kFlat];
 #pragma unroll
               for (int u = 0; u < kFlat; ++u) xg[u] = rd(read_lane(cjc, min(t + u, c - 1)), lane);
+              fix_batch<RD, kFlat>(rd, xg, [&](int u) { return read_lane(cjc, min(t + u, c - 1)); });
 #pragma unroll
               for (int u = 0; u < kFlat; ++u) {
                 if (t + u < c) {
@@ -568,8 +691,9 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub, CsrStepPlan plan,
     double* __restrict__ part) {
   RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
-  csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, d, nnz, vk, nullptr,
-                                                     epi, hub, plan, part, blockIdx.x);
+  csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, d, nnz,
+                                                     RowReader<T, OFF32>(vk, d, lane_id()),
+                                                     nullptr, epi, hub, plan, part, blockIdx.x);
 }
 
 // Gram step, first product: W = X V_k over X's rows (V_k has dv = X's
@@ -580,8 +704,9 @@ __global__ __launch_bounds__(kThreads) void gram_pass1_kernel(
     const float* __restrict__ val, int64_t d, int64_t dv, int64_t nnz, const T* __restrict__ vk,
     T* __restrict__ W, HubView hub, CsrStepPlan plan) {
   StoreEpi<T> epi(W);
-  csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, dv, nnz, vk, nullptr,
-                                                     epi, hub, plan, nullptr, blockIdx.x);
+  csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, dv, nnz,
+                                                     RowReader<T, OFF32>(vk, dv, lane_id()),
+                                                     nullptr, epi, hub, plan, nullptr, blockIdx.x);
 }
 
 // Gram step, second product with the recurrence: V_new = ca X^T W + cb V_k
@@ -593,8 +718,9 @@ __global__ __launch_bounds__(kThreads) void gram_pass2_kernel(
     const T* __restrict__ vk, T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub,
     CsrStepPlan plan, double* __restrict__ part) {
   RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
-  csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, true>(rowptr, col, val, d, dv, nnz, W, vk, epi,
-                                                    hub, plan, part, blockIdx.x);
+  csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, true>(rowptr, col, val, d, dv, nnz,
+                                                    RowReader<T, OFF32>(W, dv, lane_id()), vk,
+                                                    epi, hub, plan, part, blockIdx.x);
 }
 
 template <bool PATTERN, int MAXNZ, int TAIL>
@@ -604,20 +730,48 @@ __global__ __launch_bounds__(kThreads) void slq_spmm_kernel(
     double* __restrict__ u, const double* __restrict__ sdev, HubView hub, CsrStepPlan plan,
     double* __restrict__ part) {
   SlqEpi epi(u, sdev);
-  csr_step_wg<double, PATTERN, MAXNZ, false, TAIL, false>(rowptr, col, val, d, d, nnz, w, nullptr,
-                                                          epi, hub, plan, part, blockIdx.x);
+  csr_step_wg<double, PATTERN, MAXNZ, false, TAIL, false>(
+      rowptr, col, val, d, d, nnz, RowReader<double, false>(w, d, lane_id()), nullptr, epi, hub,
+      plan, part, blockIdx.x);
 }
 
-// Integer pass of triangle counting over a pattern CSR: vin = z (PASS 1,
-// y = A z written to vout) or y (PASS 2).
-template <int PASS, int MAXNZ, bool OFF32, int TAIL>
+// Integer pass of triangle counting over a pattern CSR: PASS 1 gathers the
+// packed signs of z (y = A z written to yout), PASS 2 gathers y (int16).
+template <int PASS, int MAXNZ, int TAIL, bool OFF32>
 __global__ __launch_bounds__(kThreads) void tri_step_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, int64_t d, int64_t nnz,
-    const int32_t* __restrict__ vin, int32_t* __restrict__ vout, HubView hub, CsrStepPlan plan,
+    const uint64_t* __restrict__ zbits, const int16_t* __restrict__ yin,
+    int16_t* __restrict__ yout, HubSide hs, HubView hub, CsrStepPlan plan,
     long long* __restrict__ part) {
-  TriEpi<PASS> epi(vout);
-  csr_step_wg<int32_t, true, MAXNZ, OFF32, TAIL, false>(rowptr, col, nullptr, d, d, nnz, vin,
-                                                        nullptr, epi, hub, plan, part, blockIdx.x);
+  TriEpi<PASS> epi(yout, hs);
+  if constexpr (PASS == 1)
+    csr_step_wg<int32_t, true, MAXNZ, false, TAIL, false>(
+        rowptr, col, nullptr, d, d, nnz, SignBitsReader(zbits, d, lane_id()), nullptr, epi, hub,
+        plan, part, blockIdx.x);
+  else
+    csr_step_wg<int32_t, true, MAXNZ, false, TAIL, false>(
+        rowptr, col, nullptr, d, d, nnz, Y16Reader<OFF32>(yin, d, lane_id(), hs), nullptr, epi,
+        hub, plan, part, blockIdx.x);
+}
+
+// Chunk partials of the hub rows for the triangle passes (as csr_hub_kernel).
+template <int PASS, bool OFF32>
+__global__ __launch_bounds__(256) void tri_hub_kernel(const int32_t* __restrict__ col, int64_t d,
+                                                      const uint64_t* __restrict__ zbits,
+                                                      const int16_t* __restrict__ yin,
+                                                      HubSide hs, const int32_t* __restrict__ cs,
+                                                      const int32_t* __restrict__ ce,
+                                                      int nchunks, int32_t* __restrict__ out) {
+  const int c = blockIdx.x * 4 + wave_id();
+  if (c >= nchunks) return;
+  const int lane = lane_id();
+  int32_t v;
+  if constexpr (PASS == 1)
+    v = row_dot_generic<int32_t, true>(col, nullptr, SignBitsReader(zbits, d, lane), cs[c], ce[c]);
+  else
+    v = row_dot_generic<int32_t, true>(col, nullptr, Y16Reader<OFF32>(yin, d, lane, hs), cs[c],
+                                       ce[c]);
+  out[(int64_t)c * 64 + lane] = v;
 }
 
 // Chunk partials of the hub rows: one wave per chunk of at most kHubChunk
@@ -713,8 +867,8 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   const HubView nohub{nullptr, nullptr, 0, nullptr};
   const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
   csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
-      B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, plan,
-      B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+      B.rowptr, B.col, B.val, B.d, B.d, B.nnz, RowReader<float, true>(vk, B.d, lane_id()),
+      nullptr, epi, nohub, plan, B.part + (size_t)s * 2 * B.ngroups * 64, bid);
 }
 
 // ---- one persistent launch for the steps of a batch ---------------------------
@@ -802,8 +956,8 @@ __global__ __launch_bounds__(kThreads) void csr_batch_persistent_kernel(
       const HubView nohub{nullptr, nullptr, 0, nullptr};
       const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
       csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
-          B.rowptr, B.col, B.val, B.d, B.d, B.nnz, vk, nullptr, epi, nohub, plan,
-          B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+          B.rowptr, B.col, B.val, B.d, B.d, B.nnz, RowReader<float, true>(vk, B.d, lane_id()),
+          nullptr, epi, nohub, plan, B.part + (size_t)s * 2 * B.ngroups * 64, bid);
       __syncthreads();  // the step body's shared partial buffer is reused
       ++pending;
     }
@@ -940,13 +1094,13 @@ hipError_t launch_step_any(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T
 
 template <int PASS, bool OFF32>
 hipError_t launch_tri_pass(hipStream_t s, const CsrMat& m, const CsrStepPlan& plan,
-                           const int32_t* vin, int32_t* vout, const HubView& hub,
-                           long long* part) {
+                           const uint64_t* zbits, const int16_t* yin, int16_t* yout,
+                           const HubSide& hs, const HubView& hub, long long* part) {
   const dim3 grid(plan.ngroups), block(kThreads);
-#define MLCT_TRI(M, H)                                                                        \
-  tri_step_kernel<PASS, M, OFF32, H><<<grid, block, 0, s>>>(m.rowptr, m.col, m.nrows, m.nnz,  \
-                                                            vin, vout, hub, banded(m, plan),  \
-                                                            part)
+#define MLCT_TRI(M, H)                                                                      \
+  tri_step_kernel<PASS, M, H, OFF32><<<grid, block, 0, s>>>(m.rowptr, m.col, m.nrows, m.nnz, \
+                                                            zbits, yin, yout, hs, hub,      \
+                                                            banded(m, plan), part)
   if (m.hub_n > 0) MLCT_TRI(8, kTailHubs);
   else if (m.nnz > 0 && m.max_row_nnz <= 4) MLCT_TRI(4, kTailNone);
   else if (m.nnz > 0 && m.max_row_nnz <= 5) MLCT_TRI(5, kTailNone);
@@ -1138,7 +1292,8 @@ __global__ __launch_bounds__(kThreads) void csr_fused2_kernel(Fused2Args a) {
     if (sub == 1) {
       RecEpi<float, Z1, PREV1, true> epi(a.ca1, a.cb1, a.x, a.src);
       csr_step_wg<float, PATTERN, MAXNZ, OFF32, kTailNone, false>(
-          a.rowptr, a.col, a.val, a.d, a.d, a.nnz, a.y, nullptr, epi, hub, plan, a.part1, bid);
+          a.rowptr, a.col, a.val, a.d, a.d, a.nnz, RowReader<float, OFF32>(a.y, a.d, lane_id()),
+          nullptr, epi, hub, plan, a.part1, bid);
       // every wave's stores complete (in L2) before the flag is set
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
@@ -1151,7 +1306,8 @@ __global__ __launch_bounds__(kThreads) void csr_fused2_kernel(Fused2Args a) {
       if (!fused_wait(a, t0, t1, t0 < base || t1 >= base + per)) break;
       RecEpi<float, Z2, true> epi(a.ca2, a.cb2, a.y, a.src);
       csr_step_wg<float, PATTERN, MAXNZ, OFF32, kTailNone, false>(
-          a.rowptr, a.col, a.val, a.d, a.d, a.nnz, a.x, nullptr, epi, hub, plan, a.part2, bid);
+          a.rowptr, a.col, a.val, a.d, a.d, a.nnz, RowReader<float, OFF32>(a.x, a.d, lane_id()),
+          nullptr, epi, hub, plan, a.part2, bid);
     }
   }
 }
@@ -1206,18 +1362,27 @@ hipError_t launch_gram_csr_step(hipStream_t s, const CsrMat& X, const CsrMat& XT
 }
 
 hipError_t launch_tri_step(hipStream_t s, const CsrMat& m, int pass, const CsrStepPlan& plan,
-                           const int32_t* vin, int32_t* vout, void* hub_part, long long* part) {
+                           const uint64_t* zbits, int16_t* y, int32_t* side, void* hub_part,
+                           long long* part) {
   const HubView hub = hub_view(m, hub_part);
+  const HubSide hs{m.hub_rows, m.hub_n, side};
+  const bool off32 = (uint64_t)m.ncols * 64 * sizeof(int16_t) <= 0xFFFFFFFFull;
   if (m.hub_n > 0) {
-    const hipError_t e = launch_hubs<int32_t, true>(s, m, vin, m.ncols, hub_part);
+    const int grid = (m.hub_chunks + 3) / 4;
+    int32_t* out = static_cast<int32_t*>(hub_part);
+#define MLCT_TH(P, O)                                                                          \
+  tri_hub_kernel<P, O><<<grid, 256, 0, s>>>(m.col, m.ncols, zbits, y, hs, m.hub_cs, m.hub_ce, \
+                                            m.hub_chunks, out)
+    if (pass == 1) MLCT_TH(1, true);
+    else if (off32) MLCT_TH(2, true);
+    else MLCT_TH(2, false);
+#undef MLCT_TH
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const bool off32 = block_off32<int32_t>(m.ncols);
-  if (pass == 1)
-    return off32 ? launch_tri_pass<1, true>(s, m, plan, vin, vout, hub, part)
-                 : launch_tri_pass<1, false>(s, m, plan, vin, vout, hub, part);
-  return off32 ? launch_tri_pass<2, true>(s, m, plan, vin, nullptr, hub, part)
-               : launch_tri_pass<2, false>(s, m, plan, vin, nullptr, hub, part);
+  if (pass == 1) return launch_tri_pass<1, true>(s, m, plan, zbits, nullptr, y, hs, hub, part);
+  return off32 ? launch_tri_pass<2, true>(s, m, plan, nullptr, y, nullptr, hs, hub, part)
+               : launch_tri_pass<2, false>(s, m, plan, nullptr, y, nullptr, hs, hub, part);
 }
 
 hipError_t launch_slq_spmm(hipStream_t s, const CsrMat& m, const double* w, double* u,

@@ -15,9 +15,12 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * 64;
 
-__global__ __launch_bounds__(kThreads) void tri_init_kernel(int32_t* __restrict__ z, int64_t d,
-                                                            ProbeSrc src, int rows_per_group,
-                                                            int ngroups) {
+__global__ __launch_bounds__(kThreads) void tri_init_kernel(uint64_t* __restrict__ zbits,
+                                                            int64_t d, ProbeSrc src,
+                                                            int rows_per_group, int ngroups) {
+  // z packed one word per row: bit p set where probe p is -1 (lane p finds
+  // its sign, a ballot gathers the wave's 64 bits); probes past src.active
+  // get +1, which only their own, discarded, sums see
   const int lane = lane_id(), wave = wave_id();
   const int g = xcd_band(blockIdx.x, ngroups);
   const int64_t r0 = (int64_t)g * rows_per_group;
@@ -27,16 +30,17 @@ __global__ __launch_bounds__(kThreads) void tri_init_kernel(int32_t* __restrict_
   int64_t cached = -1;
   uint64_t word = 0;
   for (int64_t i = r0 + wave; i < r1; i += kWaves) {
-    int32_t v = 0;
+    bool neg = false;
     if (act) {
       const int64_t c = i >> 6;
       if (c != cached) {
         word = sm_output(key, (uint64_t)c);
         cached = c;
       }
-      v = sign_from_word<int32_t>(word, i);
+      neg = sign_from_word<int32_t>(word, i) < 0;
     }
-    z[i * 64 + lane] = v;
+    const uint64_t bits = __ballot(neg);
+    if (lane == 0) zbits[i] = bits;
   }
 }
 
@@ -141,8 +145,8 @@ __global__ __launch_bounds__(kCvThreads) void tri_cv_kernel(const long long* __r
 }  // namespace
 
 hipError_t launch_tri_init(hipStream_t s, const mlct_op* op, ProbeSrc src,
-                           const CsrStepPlan& plan, int32_t* z) {
-  tri_init_kernel<<<plan.ngroups, kThreads, 0, s>>>(z, op->d, src, plan.rows_per_group,
+                           const CsrStepPlan& plan, uint64_t* zbits) {
+  tri_init_kernel<<<plan.ngroups, kThreads, 0, s>>>(zbits, op->d, src, plan.rows_per_group,
                                                     plan.ngroups);
   return hipGetLastError();
 }

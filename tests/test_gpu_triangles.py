@@ -87,3 +87,45 @@ def test_triangles_rejects_valued_matrix(ctx):
     with pytest.raises(mlct.MlctError) as e:
         mlct.mlct_triangles(ctx, op, 4, 1)
     assert e.value.status == mlct.MLCT_EINVAL
+
+
+def _signed_star(seed, d=140000, leaves=32800, extra=20000):
+    """Pattern graph whose row 0 is joined to `leaves` rows j that probe 0
+    sees as +1 and probe 1 as -1 (from the oracle's generator), plus random
+    edges among the other rows: y_0 = (A z)_0 is +leaves for probe 0 and
+    -leaves for probe 1, past the int16 range of the stored y."""
+    import scipy.sparse as sp
+
+    Z = probes.rademacher(d, np.arange(2), seed)
+    cand = np.nonzero((Z[0] > 0) & (Z[1] < 0))[0]
+    cand = cand[cand > 0][:leaves]
+    assert cand.size == leaves
+    rng = np.random.default_rng(seed)
+    u = rng.integers(1, d, size=extra)
+    v = rng.integers(1, d, size=extra)
+    keep = u != v
+    r = np.concatenate([np.zeros(leaves, dtype=np.int64), u[keep]])
+    c = np.concatenate([cand, v[keep]])
+    A = sp.coo_matrix((np.ones(2 * r.size), (np.r_[r, c], np.r_[c, r])), shape=(d, d)).tocsr()
+    A.data[:] = 1.0
+    A.sort_indices()
+    return wl.CSR(d, A.indptr.astype(np.int32), A.indices.astype(np.int32), None)
+
+
+def test_triangle_moments_beyond_int16(ctx):
+    """A row whose y leaves the int16 range (+32800 and -32800 on two probes)
+    goes through the sentinel and the hub side table: moments bit-exact."""
+    from paper_2103_10516_amd import mlct
+
+    seed = 777
+    g = _signed_star(seed)
+    assert np.diff(g.rowptr)[0] == 32800
+    op = _op(ctx, g)
+    m = 70
+    res, w = mlct.mlct_triangles(ctx, op, m, seed)
+    Z = probes.rademacher(g.d, np.arange(m), seed).T.astype(np.int64)
+    y0 = Z[g.col[g.rowptr[0]:g.rowptr[1]], :2].sum(axis=0)
+    assert list(y0) == [32800, -32800]
+    want = triangles.probe_moments(g.rowptr, g.col, Z)
+    np.testing.assert_array_equal(w, want)
+    op.close()
