@@ -284,6 +284,20 @@ struct RowReader {
   // a gathered value as the row sum takes it (the raw value here)
   static constexpr bool kFix = false;
   __device__ __forceinline__ T fix(int64_t, T x) const { return x; }
+  // gathers by a byte offset precomputed as column * kRowBytes (buffer form)
+  // (raw load, then conversion: the sequence form issues every load of a
+  // batch before it converts the first)
+  static constexpr bool kScaled = OFF32 && sizeof(T) == 4;
+  static constexpr uint32_t kRowBytes = 64 * sizeof(T);
+  using Raw = uint32_t;
+  __device__ __forceinline__ uint32_t raw(uint32_t soff) const {
+    if constexpr (kScaled) return __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane_off, (int)soff, 0);
+    else return 0u;
+  }
+  __device__ __forceinline__ T cvt(uint32_t bits) const {
+    if constexpr (std::is_integral<T>::value) return (T)bits;
+    else return __uint_as_float(bits);
+  }
 };
 
 // Triangle pass 1 gathers only Rademacher signs: one 64-bit word per row,
@@ -304,9 +318,16 @@ struct SignBitsReader {
     shift = lane & 31;
   }
   __device__ __forceinline__ int32_t operator()(int64_t j, int) const {
-    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(
-        rsrc, half_off, (int)((uint32_t)j * (uint32_t)sizeof(uint64_t)), 0);
-    return 1 - 2 * (int32_t)((w >> shift) & 1u);
+    return cvt(raw((uint32_t)j * (uint32_t)sizeof(uint64_t)));
+  }
+  static constexpr bool kScaled = true;
+  static constexpr uint32_t kRowBytes = sizeof(uint64_t);
+  using Raw = uint32_t;
+  __device__ __forceinline__ uint32_t raw(uint32_t soff) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(rsrc, half_off, (int)soff, 0);
+  }
+  __device__ __forceinline__ int32_t cvt(uint32_t w) const {
+    return 1 - 2 * (int32_t)__builtin_amdgcn_ubfe(w, (uint32_t)shift, 1u);
   }
   static constexpr bool kFix = false;
   __device__ __forceinline__ int32_t fix(int64_t, int32_t x) const { return x; }
@@ -337,13 +358,19 @@ struct Y16Reader {
   }
   __device__ __forceinline__ int32_t operator()(int64_t j, int lane) const {
     if constexpr (OFF32) {
-      const uint16_t bits = __builtin_amdgcn_raw_buffer_load_b16(
-          rsrc, lane_off, (int)((uint32_t)j * (uint32_t)(64 * sizeof(int16_t))), 0);
-      return (int32_t)(int16_t)bits;
+      return cvt(raw((uint32_t)j * kRowBytes));
     } else {
       return base[j * 64 + lane];
     }
   }
+  static constexpr bool kScaled = OFF32;
+  static constexpr uint32_t kRowBytes = 64 * sizeof(int16_t);
+  using Raw = uint16_t;
+  __device__ __forceinline__ uint16_t raw(uint32_t soff) const {
+    if constexpr (OFF32) return __builtin_amdgcn_raw_buffer_load_b16(rsrc, lane_off, (int)soff, 0);
+    else return 0;
+  }
+  __device__ __forceinline__ int32_t cvt(uint16_t bits) const { return (int32_t)(int16_t)bits; }
   static constexpr bool kFix = true;
   __device__ __forceinline__ int32_t fix(int64_t j, int32_t x) const {
     if (__builtin_expect(x == kY16Sentinel, 0)) x = hs.side[(int64_t)hs.slot(j) * 64 + lane_id()];
@@ -627,26 +654,54 @@ __device__ __forceinline__ void csr_step_wg(
               avc = PATTERN ? 1.f : val[ce];
             }
             const int c = min(64, cur.cnt - base);
-            for (int t = 0; t < c; t += kFlat) {
+            // lanes past the chunk's end repeat its last column (a valid row,
+            // not summed), and the reader's row offsets are formed once per
+            // chunk, so a gather is one lane read and one load
+            const int cl = lane < c ? cjc : read_lane(cjc, c - 1);
+            const int off = (int)((uint32_t)cl * RD::kRowBytes);
+#pragma unroll
+            for (int h = 0; h < 64 / kFlat; ++h) {
+              const int t = h * kFlat;
+              if (t >= c) break;
               T xg[kFlat];
+              if constexpr (RD::kScaled) {
+                typename RD::Raw xr[kFlat];
 #pragma unroll
-              for (int u = 0; u < kFlat; ++u) xg[u] = rd(read_lane(cjc, min(t + u, c - 1)), lane);
-              fix_batch<RD, kFlat>(rd, xg, [&](int u) { return read_lane(cjc, min(t + u, c - 1)); });
+                for (int u = 0; u < kFlat; ++u) xr[u] = rd.raw((uint32_t)read_lane(off, t + u));
+                // every load of the batch is in flight before the first is used
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-              for (int u = 0; u < kFlat; ++u) {
-                if (t + u < c) {
+                for (int u = 0; u < kFlat; ++u) xg[u] = rd.cvt(xr[u]);
+              } else {
+#pragma unroll
+                for (int u = 0; u < kFlat; ++u) xg[u] = rd(read_lane(cl, t + u), lane);
+              }
+              fix_batch<RD, kFlat>(rd, xg, [&](int u) { return read_lane(cl, t + u); });
+              const int lim = c - t;         // entries of this batch in the group
+              int rloc = rend - (base + t);  // batch position of the current row's end
+              // summed in column order; at a row's last entry its sum goes to
+              // the row's accumulator and the next row begins
+              auto sum_batch = [&](auto full) {
+#pragma unroll
+                for (int u = 0; u < kFlat; ++u) {
+                  if (!decltype(full)::value && u >= lim) break;
                   const float w = PATTERN ? 1.f : read_lane(avc, t + u);
                   run = accum<T, PATTERN>(run, w, true, xg[u]);
-                  if (base + t + u == rend) {
+                  if (u == rloc) {
 #pragma unroll
                     for (int r = 0; r < ROWS; ++r)
                       if (r == rc) acc[r] = run;
                     run = T(0);
                     rc = next_row(rc);
                     rend = last_of(rc);
+                    rloc = rend - (base + t);
                   }
                 }
-              }
+              };
+              if (lim >= kFlat)
+                sum_batch(std::true_type());
+              else
+                sum_batch(std::false_type());
             }
           }
 #pragma unroll
