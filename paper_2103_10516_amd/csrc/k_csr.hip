@@ -24,6 +24,7 @@
 // separate launch (csr_hub_kernel) reduces first, one wave per chunk; the
 // step kernel then sums a hub row's chunk partials in chunk order.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "device.hpp"
@@ -627,23 +628,22 @@ __device__ __forceinline__ void csr_step_wg(
             xi[r] = own(i);
             xp[r] = epi.prev(i);
           }
-          // current row rc (uniform) and the position of its last entry
-          auto last_of = [&](int rr) {
-            int e = -1;
+          // per-group tables in lanes 0 .. ROWS: the position of row r's
+          // last entry (INT_MAX past the rows, so it is never reached) and
+          // the next row after r that has entries (ROWS: none); the current
+          // row rc and its end rend are uniform
+          int end_v = INT_MAX, nxt_v = ROWS;
+          int first = ROWS;
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r)
-              if (r == rr && cur.len[r] > 0) e = cur.off[r] + cur.len[r] - 1;
-            return e;
-          };
-          auto next_row = [&](int rr) {  // first row after rr with an entry
-            int nx = ROWS;
-#pragma unroll
-            for (int r = ROWS - 1; r >= 0; --r)
-              if (r > rr && cur.len[r] > 0) nx = r;
-            return nx;
-          };
-          int rc = next_row(-1);
-          int rend = last_of(rc);
+          for (int r = ROWS - 1; r >= 0; --r) {
+            if (lane == r) {
+              end_v = cur.len[r] > 0 ? cur.off[r] + cur.len[r] - 1 : INT_MAX;
+              nxt_v = first;
+            }
+            if (cur.len[r] > 0) first = r;
+          }
+          int rc = first;
+          int rend = read_lane(end_v, rc);
           T run = T(0);
           for (int base = 0; base < cur.cnt; base += 64) {
             int cjc = cj;
@@ -692,8 +692,8 @@ __device__ __forceinline__ void csr_step_wg(
                     for (int r = 0; r < ROWS; ++r)
                       if (r == rc) acc[r] = run;
                     run = T(0);
-                    rc = next_row(rc);
-                    rend = last_of(rc);
+                    rc = read_lane(nxt_v, rc);
+                    rend = read_lane(end_v, rc);
                     rloc = rend - (base + t);
                   }
                 }
