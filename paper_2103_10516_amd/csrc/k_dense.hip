@@ -1053,8 +1053,11 @@ hipError_t launch_pk_gemm(hipStream_t s, const DenseStepArgs& a) {
 DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) {
   // Blocks of at most 64 probes (512 for BF16x3) take the skinny split-K
   // kernel (16-row tiles) when rows are 16-byte aligned.  Otherwise the largest square tile
-  // that still gives a few hundred workgroups: 128 x 128, then 64 x 64, else
-  // 32 x 32 (small problems are latency-bound; more workgroups win).
+  // that still gives a few hundred workgroups: 128 x 128, then 64 x 64; a
+  // problem too small for either takes the skinny kernel over several probe
+  // tiles (it splits k over four waves: FP64 d = 512, 256 probes, degree 64
+  // in 0.61 ms against 1.52 ms on 32 x 32 tiles, d = 2048 2.8 vs 5.2 ms),
+  // else 32 x 32.
   // force: 0 = 32, 1 = 128, 2 = 64, 3 = skinny (when the block allows it).
   // the skinny kernel's 16-byte loads need 16-byte aligned rows of V and A
   const int qv = prec == MLCT_FP64 ? 2 : 4, qa = prec == MLCT_FP64 ? 2 : (prec == MLCT_FP32 ? 4 : 8);
@@ -1075,6 +1078,7 @@ DenseTile dense_tile(int prec, int64_t d, int64_t lda, int64_t bpad, int force) 
     if (bpad <= skinny_max && skinny_ok) t.skinny = true;
     else if (bpad % 128 == 0 && n128 >= 256) size = 128;
     else if (bpad % 64 == 0 && n64 >= 256) size = 64;
+    else if (skinny_ok) t.skinny = true;
   }
   if (t.skinny) {
     t.large = false;

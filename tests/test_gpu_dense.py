@@ -129,9 +129,10 @@ def test_dense_bf16x3_wide_blocks(ctx, mode, d, m):
 @pytest.mark.parametrize("mode", ["direct", "doubling"])
 @pytest.mark.parametrize("m", [320, 512])
 def test_dense_skinny_wide_blocks(ctx, prec, mode, m):
-    """BF16x3 blocks of 320 and 512 probes run the packed skinny kernel (one
-    workgroup per 64 probes x 16 rows); FP32 takes square tiles.  Probes at
-    both ends and in the middle against the oracle."""
+    """Blocks of 320 and 512 probes at d = 1024 (too few square tiles to fill
+    the device) run the skinny kernel over several 64-probe tiles: packed
+    for BF16x3, row-major for FP32.  Probes at both ends and in the middle
+    against the oracle."""
     from paper_2103_10516_amd import mlct
 
     d = 1024
