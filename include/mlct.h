@@ -204,6 +204,10 @@ mlct_status mlct_set_workspace_limit(mlct_ctx* ctx, uint64_t bytes);
 #define MLCT_OPT_TWO_STEP_LAG 3
 #define MLCT_OPT_TWO_STEP_ROWS 4
 #define MLCT_OPT_TWO_STEP_WGS 5
+/* MLCT_OPT_BATCH_SOLO_ROWS: the operator size (rows) from which an item of
+ * mlct_estimate_batch runs as a single estimate instead of sharing launches
+ * (0 = the default, 131,072); results are the same either way. */
+#define MLCT_OPT_BATCH_SOLO_ROWS 6
 mlct_status mlct_set_option(mlct_ctx* ctx, int32_t option, int64_t value);
 
 /* Per-kernel device time of the library's own launches, measured with HIP
@@ -489,9 +493,13 @@ mlct_status mlct_autotune(mlct_ctx* ctx, mlct_op* op, int32_t B_max, int32_t pre
  * Items must use square CSR operators (valued or pattern, any sizes; not
  * sparse Gram operators); precision MLCT_FP32; mode MLCT_DIRECT or
  * MLCT_DOUBLING (optionally with MLCT_LEVEL_INTERP and / or MLCT_EXACT_LOW).
- * Each item's result equals what mlct_estimate returns for it, bit for bit
- * (rows longer than 256 entries are summed in the same 256-entry chunks).  outs: host, nitems results.  Fails with MLCT_ESPECTRUM if any item's
- * moments leave [-|z|^2, |z|^2] (that item's result is still written). */
+ * Items whose operator has 131,072 rows or more (MLCT_OPT_BATCH_SOLO_ROWS)
+ * fill the device on their own and run as single estimates (then any size
+ * is accepted); the others share launches.  Each item's result equals what mlct_estimate returns
+ * for it, bit for bit (rows longer than 256 entries are summed in the same
+ * 256-entry chunks).  outs: host, nitems results.  Fails with
+ * MLCT_ESPECTRUM if any item's moments leave [-|z|^2, |z|^2] (every item's
+ * result is still written). */
 typedef struct {
   const mlct_op* op;
   mlct_func f;
@@ -513,8 +521,11 @@ mlct_status mlct_autotune_batch(mlct_ctx* ctx, int32_t nitems, const mlct_batch_
                                 int32_t prec, int32_t mode, int32_t* choice_out);
 
 /* Triangle count tr(A^3)/6 of a 0/1 pattern CSR graph (Section 2.1 example,
- * Section 5.4): per probe, exact int32 y = A z and w = A y with int64
- * w1 = z.y, w2 = y.y, w3 = y.w.  w_out (host, m x 3 int64, may be NULL). */
+ * Section 5.4): per probe, exact integer y = A z and w = A y with int64
+ * w1 = z.y, w2 = y.y, w3 = y.w.  w_out (host, m x 3 int64, may be NULL).
+ * z is held as one sign word per row and y as int16 with exact escapes
+ * (results exact for every graph); at most 536,870,911 rows, else
+ * MLCT_EUNSUPPORTED. */
 typedef struct {
   int64_t sum_w3;
   double estimate;     /* sum w3 / (6 m) */

@@ -1073,6 +1073,11 @@ mlct_status mlct_set_option(mlct_ctx* ctx, int32_t option, int64_t value) {
     ctx->two_step_wgs = (int)value;
     return MLCT_OK;
   }
+  if (option == MLCT_OPT_BATCH_SOLO_ROWS) {
+    if (value < 0) return fail(ctx, MLCT_EINVAL, "MLCT_OPT_BATCH_SOLO_ROWS takes a row count >= 0");
+    ctx->batch_solo_rows = value == 0 ? kBatchSoloRowsDefault : value;
+    return MLCT_OK;
+  }
   if (option == MLCT_OPT_WAIT_LIMIT_US) {
     if (value < 0 || value > 60000000) return fail(ctx, MLCT_EINVAL, "wait limit must be in [0, 6e7] us");
     ctx->wait_limit_us = value;
@@ -1654,6 +1659,9 @@ mlct_status mlct_triangles(mlct_ctx* ctx, const mlct_op* op, int64_t m, uint64_t
   if (op->kind != OP_CSR || op->csr.val != nullptr)
     return fail(ctx, MLCT_EINVAL, "triangle counting needs a 0/1 pattern CSR operator");
   if (m < 1) return fail(ctx, MLCT_EINVAL, "need m >= 1 probes");
+  // the packed signs are gathered through a buffer resource of 32-bit size
+  if ((uint64_t)op->d * sizeof(uint64_t) > 0xFFFFFFFFull)
+    return fail(ctx, MLCT_EUNSUPPORTED, "triangle counting supports at most 536,870,911 rows");
   CHECK(set_device(ctx));
   const CsrStepPlan plan = plan_csr(op->d, op->tuned_groups);
   void *z, *y, *part, *w, *res, *side = nullptr;
@@ -2172,9 +2180,51 @@ extern "C" mlct_status mlct_estimate_batch(mlct_ctx* ctx, int32_t nitems,
   const int persistent = (mode & MLCT_BATCH_PERSISTENT) ? 1
                          : (mode & MLCT_BATCH_LOCKSTEP) ? 0
                                                         : ctx->batch_persistent;
+  const int32_t item_mode = mode & ~(MLCT_BATCH_PERSISTENT | MLCT_BATCH_LOCKSTEP);
+  const int32_t batch_mode = mode;
   mode &= ~(MLCT_LEVEL_INTERP | MLCT_EXACT_LOW | MLCT_BATCH_PERSISTENT | MLCT_BATCH_LOCKSTEP);
   if (prec != MLCT_FP32) return fail(ctx, MLCT_EUNSUPPORTED, "batched estimates run in MLCT_FP32");
   CHECK(check_mode_prec(ctx, mode, prec));
+  // Operators with batch_solo_rows rows or more fill the device on their
+  // own with the tuned single-matrix step kernel: they run as single
+  // estimates, the others share launches.  The results are those of single
+  // calls either way.
+  {
+    std::vector<int> solo, rest;
+    for (int i = 0; i < nitems; ++i)
+      (items[i].op && items[i].op->kind == OP_CSR && items[i].op->d >= ctx->batch_solo_rows ? solo
+                                                                                            : rest)
+          .push_back(i);
+    if (!solo.empty()) {
+      // an item whose moments leave the spectrum's range still gets its
+      // result, and the call reports MLCT_ESPECTRUM after all items ran
+      std::string spectrum_msg;
+      for (int i : solo) {
+        const mlct_batch_item& it = items[i];
+        const mlct_status st = mlct_estimate(ctx, it.op, it.f, it.a, it.b, &it.levels, it.seed,
+                                             prec, item_mode, &outs[i]);
+        if (st == MLCT_ESPECTRUM && spectrum_msg.empty()) {
+          spectrum_msg = "item " + std::to_string(i) + ": " + ctx->err;
+        } else if (st != MLCT_OK && st != MLCT_ESPECTRUM) {
+          const std::string msg = ctx->err;
+          return fail(ctx, st, "item %d: %s", i, msg.c_str());
+        }
+      }
+      if (!rest.empty()) {
+        std::vector<mlct_batch_item> sub;
+        for (int i : rest) sub.push_back(items[i]);
+        std::vector<mlct_result> subo(rest.size());
+        const mlct_status st = mlct_estimate_batch(ctx, (int32_t)sub.size(), sub.data(), prec,
+                                                   batch_mode, subo.data());
+        if (st != MLCT_OK && st != MLCT_ESPECTRUM) return st;
+        for (size_t k = 0; k < rest.size(); ++k) outs[rest[k]] = subo[k];
+        if (st == MLCT_ESPECTRUM && spectrum_msg.empty()) spectrum_msg = ctx->err;
+      }
+      if (!spectrum_msg.empty()) return fail(ctx, MLCT_ESPECTRUM, "%s", spectrum_msg.c_str());
+      ctx->err.clear();
+      return MLCT_OK;
+    }
+  }
   // ---- validate items, build level descriptors and blocks ----
   std::vector<LevelDesc> lvs(nitems);
   std::vector<int64_t> totals(nitems);

@@ -77,6 +77,9 @@ struct mlct_timed_launch {
   int units;  // recurrence steps the launch ran (1, or 2 for a two-step launch)
 };
 
+// Rows from which a batch item runs as a single estimate (mlct_estimate_batch).
+constexpr int64_t kBatchSoloRowsDefault = (int64_t)1 << 17;
+
 struct mlct_ctx {
   int device = 0;
   // per-kernel timing (mlct_timing)
@@ -99,6 +102,7 @@ struct mlct_ctx {
   int two_step_lag = 0;      // tiles sub-step 1 runs ahead beyond twice the window (0: default)
   int two_step_rows = 0;     // rows per tile of a two-step launch (0: default)
   int two_step_wgs = 0;      // workgroups per XCD of a two-step launch (0: default)
+  int64_t batch_solo_rows = kBatchSoloRowsDefault;  // batch items this large run as single estimates
   int xcd_ok = -1;           // every XCD receives workgroups of a two-step launch (-1: not probed)
   int64_t wait_limit_us = 2000000;  // bound on a two-step launch's tile wait
   int* fused_abort = nullptr;  // device flag of the two-step launches since the last check

@@ -43,6 +43,7 @@ MLCT_OPT_WAIT_LIMIT_US = 2
 MLCT_OPT_TWO_STEP_LAG = 3
 MLCT_OPT_TWO_STEP_ROWS = 4
 MLCT_OPT_TWO_STEP_WGS = 5
+MLCT_OPT_BATCH_SOLO_ROWS = 6
 
 
 class mlct_func(C.Structure):

@@ -150,7 +150,13 @@ def test_batch_equals_block_by_block_on_large_operators(ctx, mode):
             a, b = shift, shift + 8.0
         items.append(dict(op=op, kind=mlct.MLCT_LOG if i != 1 else mlct.MLCT_EXP, a=a, b=b,
                           degrees=[7, 22], m=[130, 64], seed=500 + i))
-    res = mlct.mlct_estimate_batch(ctx, items, prec=mlct.MLCT_FP32, mode=md)
+    # these operators (over 131,072 rows) would run as single estimates;
+    # a larger threshold keeps them in the shared launches tested here
+    mlct.mlct_set_option(ctx, mlct.MLCT_OPT_BATCH_SOLO_ROWS, 1 << 40)
+    try:
+        res = mlct.mlct_estimate_batch(ctx, items, prec=mlct.MLCT_FP32, mode=md)
+    finally:
+        mlct.mlct_set_option(ctx, mlct.MLCT_OPT_BATCH_SOLO_ROWS, 0)
     for it, r in zip(items, res):
         one = mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"],
                                  it["m"], it["seed"], mlct.MLCT_FP32, md)
@@ -182,5 +188,34 @@ def test_autotune_batch_launch_form(ctx):
     with pytest.raises(mlct.MlctError):
         mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, mlct.MLCT_DOUBLING |
                                  mlct.MLCT_BATCH_LOCKSTEP | mlct.MLCT_BATCH_PERSISTENT)
+    for it in items:
+        it["op"].close()
+
+
+def test_batch_with_large_operators_equals_single_calls(ctx):
+    """A batch that mixes operators of 131,072 rows or more (run as single
+    estimates) with small ones (shared launches) gives every item the
+    result of its single call, bit for bit."""
+    from paper_2103_10516_amd import mlct
+
+    graphs = [wl.laplacian_2d(768), wl.chung_lu(3000, seed=3), wl.laplacian_2d(60, shift=0.5),
+              wl.laplacian_2d(730)]
+    assert graphs[0].d >= 1 << 17 and graphs[3].d >= 1 << 17 > graphs[1].d
+    items = []
+    for i, g in enumerate(graphs):
+        op = _op(ctx, g)
+        if i == 1:
+            a, b = mlct.mlct_bounds(ctx, op, 40, 3, 0.01)
+        else:
+            shift = 0.5 if i == 2 else 0.01
+            a, b = shift, shift + 8.0
+        items.append(dict(op=op, kind=mlct.MLCT_LOG if i != 1 else mlct.MLCT_EXP, a=a, b=b,
+                          degrees=[6, 19], m=[100, 64], seed=900 + i))
+    res = mlct.mlct_estimate_batch(ctx, items, prec=mlct.MLCT_FP32, mode=mlct.MLCT_DOUBLING)
+    for it, r in zip(items, res):
+        one = mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"],
+                                 it["m"], it["seed"], mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
+        assert r["value"] == one["value"] and r["est_var"] == one["est_var"]
+        np.testing.assert_array_equal(r["level_mean"], one["level_mean"])
     for it in items:
         it["op"].close()
