@@ -475,7 +475,7 @@ hipError_t launch_lanczos(hipStream_t s, const mlct_op* op, const void* a64, int
 // ---- learned control-variate level (k_mlp.hip) -----------------------------
 constexpr int kMlpHidden = 64;
 constexpr int kMlpMaxFeatures = 16;
-constexpr int kMlpWaves = 32;
+constexpr int kMlpWaves = 256;
 int mlp_nparams(int F);
 hipError_t launch_mlp_init(hipStream_t s, float* theta, float* m, float* v, int F, uint64_t seed);
 hipError_t launch_mlp_grad(hipStream_t s, const float* theta, int F, const float* X,

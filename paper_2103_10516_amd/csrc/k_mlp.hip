@@ -121,21 +121,35 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float* __restrict__ 
 }
 
 // Adam (Kingma & Ba) with bias correction; the gradient is the fixed-order
-// sum of the per-wave partials.  Also records the epoch's loss.
-__global__ void mlp_adam_kernel(float* __restrict__ theta, float* __restrict__ m,
-                                float* __restrict__ v, const float* __restrict__ part, int nparts,
-                                int P, int t, float lr, float beta1, float beta2, float eps,
-                                const float* __restrict__ loss_part, int N,
-                                float* __restrict__ loss_hist) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0) {
-    float s = 0.f;
-    for (int b = 0; b < nparts; ++b) s += loss_part[b];
-    loss_hist[t - 1] = s / (float)N;
-  }
-  if (p >= P) return;
+// sum of the per-wave partials: a workgroup takes 64 parameters, its eight
+// waves sum the partials b = c, c + 8, c + 16, ... (wave c) of each, and
+// the eight sums are added in wave order.  Wave 1 of workgroup 0 also
+// records the epoch's loss.
+constexpr int kAdamChunks = 8;
+__global__ __launch_bounds__(64 * kAdamChunks) void mlp_adam_kernel(
+    float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+    const float* __restrict__ part, int nparts, int P, int t, float lr, float beta1, float beta2,
+    float eps, const float* __restrict__ loss_part, int N, float* __restrict__ loss_hist) {
+  __shared__ float sh[kAdamChunks][64];
+  const int q = threadIdx.x & 63, c = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + q;
   float g = 0.f;
-  for (int b = 0; b < nparts; ++b) g += part[(int64_t)b * P + p];
+  if (p < P) {
+#pragma unroll 8
+    for (int b = c; b < nparts; b += kAdamChunks) g += part[(int64_t)b * P + p];
+  }
+  sh[c][q] = g;
+  if (blockIdx.x == 0 && c == 1) {
+    float s = 0.f;
+    for (int b = q; b < nparts; b += 64) s += loss_part[b];
+    s = wave_sum_f(s);
+    if (q == 0) loss_hist[t - 1] = s / (float)N;
+  }
+  __syncthreads();
+  if (c != 0 || p >= P) return;
+  g = sh[0][q];
+#pragma unroll
+  for (int k = 1; k < kAdamChunks; ++k) g += sh[k][q];
   const float mm = beta1 * m[p] + (1.f - beta1) * g;
   const float vv = beta2 * v[p] + (1.f - beta2) * g * g;
   m[p] = mm;
@@ -507,8 +521,9 @@ hipError_t launch_mlp_adam(hipStream_t s, float* theta, float* m, float* v, cons
                            int nwaves, int F, int t, float lr, const float* loss_part, int N,
                            float* loss_hist) {
   const int P = Off(F).P;
-  mlp_adam_kernel<<<(P + 255) / 256, 256, 0, s>>>(theta, m, v, part, nwaves, P, t, lr, 0.9f,
-                                                  0.999f, 1e-8f, loss_part, N, loss_hist);
+  mlp_adam_kernel<<<(P + 63) / 64, 64 * kAdamChunks, 0, s>>>(theta, m, v, part, nwaves, P, t, lr,
+                                                             0.9f, 0.999f, 1e-8f, loss_part, N,
+                                                             loss_hist);
   return hipGetLastError();
 }
 
