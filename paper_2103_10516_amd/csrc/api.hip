@@ -1381,8 +1381,10 @@ mlct_status mlct_estimate(mlct_ctx* ctx, const mlct_op* op, mlct_func f, double 
   // longer than kHubLen runs its probe blocks in shared launches (the
   // batched path, whose results equal this function's bit for bit) when
   // there are at least kSharedBlocks of them; fewer gain less than the
-  // batched path's set-up costs.
+  // batched path's set-up costs.  (Only below the batch's solo threshold,
+  // from which the batched path would hand the operator back here.)
   if (op->kind == OP_CSR && prec == MLCT_FP32 && op->csr.hub_n == 0 &&
+      op->d < ctx->batch_solo_rows &&
       (mode == MLCT_DIRECT || mode == MLCT_DOUBLING) && levels->L >= 1 &&
       levels->L <= MLCT_MAX_LEVELS && levels->m &&
       (uint64_t)op->d * 64 * 4 <= 0xFFFFFFFFull &&

@@ -219,3 +219,26 @@ def test_batch_with_large_operators_equals_single_calls(ctx):
         np.testing.assert_array_equal(r["level_mean"], one["level_mean"])
     for it in items:
         it["op"].close()
+
+
+def test_small_solo_threshold_keeps_single_calls_direct(ctx):
+    """With the solo threshold set below a small operator's size, a single
+    estimate of that operator (which shares launches across its probe blocks
+    below the threshold) runs block by block instead, with the same result,
+    and a batch of such operators still equals single calls."""
+    from paper_2103_10516_amd import mlct
+
+    g = wl.laplacian_2d(60)  # d = 3,600, no rows past the hub length
+    op = _op(ctx, g)
+    a, b = 0.01, 8.01
+    args = (op, mlct.MLCT_LOG, a, b, [5, 15], [300, 128], 77, mlct.MLCT_FP32, mlct.MLCT_DOUBLING)
+    ref = mlct.mlct_estimate(ctx, *args)
+    mlct.mlct_set_option(ctx, mlct.MLCT_OPT_BATCH_SOLO_ROWS, 1000)
+    try:
+        got = mlct.mlct_estimate(ctx, *args)
+        items = [dict(op=op, kind=mlct.MLCT_LOG, a=a, b=b, degrees=[5, 15], m=[300, 128], seed=77)]
+        bat = mlct.mlct_estimate_batch(ctx, items, mlct.MLCT_FP32, mlct.MLCT_DOUBLING)[0]
+    finally:
+        mlct.mlct_set_option(ctx, mlct.MLCT_OPT_BATCH_SOLO_ROWS, 0)
+    assert got["value"] == ref["value"] and bat["value"] == ref["value"]
+    op.close()
