@@ -908,7 +908,7 @@ def main():
         kernel, prof = "csr_fused2_kernel<...> (two steps per launch)", "csr_fused2_"
     else:
         units = launches
-        kernel, prof = "csr_step_kernel<float,valued,...>", "csr_step_"
+        kernel, prof = "csr_step_wide_kernel<valued,...> (FP32, 4 probes per lane)", "csr_step_"
     avg_s = kms / 1e3 / max(launches, 1)
     bytes_launch = bytes_step * units / max(launches, 1)
     achieved = bytes_launch / avg_s / 1e9

@@ -105,12 +105,17 @@ __global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0
 // Per-row epilogue of the recurrence: V_new = ca*acc + cb*V_k[i] (- V_prev[i]),
 // written over V_prev (with a non-temporal store unless KEEP: a vector
 // gathered again soon is stored normally, to stay in the caches), and the
-// lane's moment partials (FP64).
-template <typename T, int ZMODE, bool HAS_PREV, bool KEEP = false>
+// lane's moment partials (FP64).  With CLS = 4 (FP32, ZMODE 0, operators
+// whose rows all fit the straight-line path) the partials are kept per row
+// class (the row's index in its group, mod 4) and the classes added in
+// order at the end: the summation order of the wide step kernel, whose lane
+// quads take one class each, so both kernels give the same bits.
+template <typename T, int ZMODE, bool HAS_PREV, bool KEEP = false, int CLS = 1>
 struct RecEpi {
   using Part = double;
   static constexpr bool kOwn = true;    // needs V_k[i] of its own row
   static constexpr bool kParts = true;  // writes moment partials
+  static constexpr int kCls = (ZMODE == 0 && sizeof(T) == 4) ? CLS : 1;
   T ca, cb;
   T* vm;
   ProbeSrc src;
@@ -118,7 +123,7 @@ struct RecEpi {
   uint64_t key = 0;
   int64_t cached = -1;
   uint64_t word = 0;
-  double a1 = 0.0, a2 = 0.0;
+  double a1[kCls] = {}, a2[kCls] = {};
   __device__ RecEpi(T ca_, T cb_, T* vm_, const ProbeSrc& s) : ca(ca_), cb(cb_), vm(vm_), src(s) {
     const int lane = lane_id();
     act = lane < src.active;
@@ -127,10 +132,12 @@ struct RecEpi {
   __device__ __forceinline__ T prev(int64_t i) const {
     return HAS_PREV ? __builtin_nontemporal_load(vm + i * 64 + lane_id()) : T(0);
   }
-  __device__ __forceinline__ void finish(int64_t i, T acc, T xi, T xp) {
+  // r: the row's index in its group (a compile-time constant at every call)
+  __device__ __forceinline__ void finish(int64_t i, T acc, T xi, T xp, int r) {
     const int lane = lane_id();
+    const int c = r % kCls;
     // one explicit contraction, so every kernel that shares this update
-    // (the two-step kernel included) rounds it the same way
+    // (the two-step and wide kernels included) rounds it the same way
     T vn = fma(ca, acc, cb * xi);
     if (HAS_PREV) vn -= xp;
     if (KEEP)
@@ -138,19 +145,27 @@ struct RecEpi {
     else
       __builtin_nontemporal_store(vn, vm + i * 64 + lane);
     if (ZMODE == 0) {
-      a1 += (double)xi * (double)vn;
-      a2 += (double)vn * (double)vn;
+      a1[c] += (double)xi * (double)vn;
+      a2[c] += (double)vn * (double)vn;
     } else if (ZMODE == 1) {
-      const int64_t c = i >> 6;
-      if (c != cached) {
-        word = sm_output(key, (uint64_t)c);
-        cached = c;
+      const int64_t cw = i >> 6;
+      if (cw != cached) {
+        word = sm_output(key, (uint64_t)cw);
+        cached = cw;
       }
-      a1 += sign_from_word<double>(word, i) * (double)vn;
+      a1[c] += sign_from_word<double>(word, i) * (double)vn;
     } else {
       const double z = act ? (double)src.entries[i * src.ld + src.first_id + lane] : 0.0;
-      a1 += z * (double)vn;
+      a1[c] += z * (double)vn;
     }
+  }
+  __device__ __forceinline__ double part1() const { return class_sum(a1); }
+  __device__ __forceinline__ double part2() const { return class_sum(a2); }
+  static __device__ __forceinline__ double class_sum(const double (&a)[kCls]) {
+    double s = a[0];
+#pragma unroll
+    for (int k = 1; k < kCls; ++k) s += a[k];
+    return s;
   }
 };
 
@@ -189,7 +204,9 @@ struct TriEpi {
   long long a1 = 0, a2 = 0;
   __device__ TriEpi(int16_t* v, const HubSide& h) : vout(v), hs(h) {}
   __device__ __forceinline__ int32_t prev(int64_t) const { return 0; }
-  __device__ __forceinline__ void finish(int64_t i, int32_t acc, int32_t own, int32_t) {
+  __device__ __forceinline__ long long part1() const { return a1; }
+  __device__ __forceinline__ long long part2() const { return a2; }
+  __device__ __forceinline__ void finish(int64_t i, int32_t acc, int32_t own, int32_t, int) {
     const int lane = lane_id();
     if (PASS == 1) {
       int16_t st = (int16_t)acc;
@@ -218,7 +235,9 @@ struct StoreEpi {
   double a1 = 0.0, a2 = 0.0;
   __device__ explicit StoreEpi(T* o) : out(o) {}
   __device__ __forceinline__ T prev(int64_t) const { return T(0); }
-  __device__ __forceinline__ void finish(int64_t i, T acc, T, T) { out[i * 64 + lane_id()] = acc; }
+  __device__ __forceinline__ double part1() const { return a1; }
+  __device__ __forceinline__ double part2() const { return a2; }
+  __device__ __forceinline__ void finish(int64_t i, T acc, T, T, int) { out[i * 64 + lane_id()] = acc; }
 };
 
 // SpMM of a Lanczos step (FP64, lane = probe): u = s (A w_j) stored, with
@@ -232,7 +251,9 @@ struct SlqEpi {
   double a1 = 0.0, a2 = 0.0;
   __device__ SlqEpi(double* o, const double* sdev) : out(o), s(sdev[lane_id()]) {}
   __device__ __forceinline__ double prev(int64_t) const { return 0.0; }
-  __device__ __forceinline__ void finish(int64_t i, double acc, double xi, double) {
+  __device__ __forceinline__ double part1() const { return a1; }
+  __device__ __forceinline__ double part2() const { return a2; }
+  __device__ __forceinline__ void finish(int64_t i, double acc, double xi, double, int) {
     const double u = s * acc;
     out[i * 64 + lane_id()] = u;
     a1 += (s * xi) * u;
@@ -612,7 +633,7 @@ __device__ __forceinline__ void csr_step_wg(
           for (int t = 0; t < MAXNZ; ++t)
             acc = accum<T, PATTERN>(acc, PATTERN ? 1.f : read_lane(av, min(cur.off[r] + t, 63)),
                                     t < cur.len[r], x[r][t]);
-          if (r < cur.nr) epi.finish(row0 + r, acc, xi[r], xp[r]);
+          if (r < cur.nr) epi.finish(row0 + r, acc, xi[r], xp[r], r);
         }
       } else if constexpr (TAIL != kTailNone) {
         if (cur.maxlen <= kHubChunk) {
@@ -706,7 +727,7 @@ __device__ __forceinline__ void csr_step_wg(
           }
 #pragma unroll
           for (int r = 0; r < ROWS; ++r)
-            if (r < cur.nr) epi.finish(row0 + r, acc[r], xi[r], xp[r]);
+            if (r < cur.nr) epi.finish(row0 + r, acc[r], xi[r], xp[r], r);
         } else {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {  // static indices: cur stays in registers
@@ -718,7 +739,7 @@ __device__ __forceinline__ void csr_step_wg(
               acc = hub_sum<T>(hub, i);
             else
               acc = row_dot_chunked<T, PATTERN>(col, val, rd, s0, s0 + cur.len[r]);
-            epi.finish(i, acc, own(i), epi.prev(i));
+            epi.finish(i, acc, own(i), epi.prev(i), r);
           }
         }
         }
@@ -736,7 +757,8 @@ __device__ __forceinline__ void csr_step_wg(
       av = avn;
     }
   }
-  if constexpr (Epi::kParts) store_partials<typename Epi::Part>(epi.a1, epi.a2, g, ngroups, part);
+  if constexpr (Epi::kParts)
+    store_partials<typename Epi::Part>(epi.part1(), epi.part2(), g, ngroups, part);
 }
 
 template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32, int TAIL>
@@ -745,10 +767,213 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
     T* __restrict__ vm, T ca, T cb, ProbeSrc src, HubView hub, CsrStepPlan plan,
     double* __restrict__ part) {
-  RecEpi<T, ZMODE, HAS_PREV> epi(ca, cb, vm, src);
+  RecEpi<T, ZMODE, HAS_PREV, false, TAIL == kTailNone ? 4 : 1> epi(ca, cb, vm, src);
   csr_step_wg<T, PATTERN, MAXNZ, OFF32, TAIL, false>(rowptr, col, val, d, d, nnz,
                                                      RowReader<T, OFF32>(vk, d, lane_id()),
                                                      nullptr, epi, hub, plan, part, blockIdx.x);
+}
+
+// ---- wide form of the FP32 step ---------------------------------------------
+// For operators whose rows all fit the straight-line path (no tail), FP32,
+// and moments of the symmetric form (ZMODE 0), the same step with a lane
+// holding 4 probes: every access is 16 bytes, so one wave instruction moves
+// four rows (lanes 16q .. 16q+15 on the group's rows q and q+4) and a step
+// issues a quarter of the memory instructions of the lane = probe body.
+// The work split (bands, groups of ROWS rows, wave w on groups w, w + 8, ...),
+// the column prefetch, the row sums (entry order, one fma per entry, unused
+// slots weighted 0), the update and the moment classes are those of
+// csr_step_wg with RecEpi, so both give the same bits; a lane's row offset
+// and length are picked from the group's extent by its quad, and its column
+// indices and values come from the group's coalesced load by a lane
+// permute.
+typedef float wf4 __attribute__((ext_vector_type(4)));
+
+template <bool OFF32>
+struct WideRows {
+  const float* base;
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t lane_off;
+  __device__ __forceinline__ WideRows(const float* b, int64_t d, int sub) : base(b) {
+    if (OFF32)
+      rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(b), (short)0,
+                                               (int)(uint32_t)(d * 256), 0x00020000);
+    lane_off = (uint32_t)sub * 16;
+  }
+  // probes 4 sub .. 4 sub + 3 of block row j
+  __device__ __forceinline__ wf4 operator()(int64_t j) const {
+    if constexpr (OFF32)
+      return __builtin_bit_cast(
+          wf4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (uint32_t)j * 256u + lane_off, 0, 0));
+    else
+      return *reinterpret_cast<const wf4*>(base + j * 64 + lane_off / 4);
+  }
+};
+
+__device__ __forceinline__ int pick_quad(int q, int a, int b, int c, int d) {
+  return q == 0 ? a : q == 1 ? b : q == 2 ? c : d;
+}
+
+__device__ __forceinline__ int permute_lane(int v, int src) {
+  return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+
+template <bool PATTERN, bool HAS_PREV, int MAXNZ, bool OFF32>
+__global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const float* __restrict__ val, int64_t d, int64_t nnz, const float* __restrict__ vk,
+    float* __restrict__ vm, float ca, float cb, CsrStepPlan plan, double* __restrict__ part) {
+  constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
+  constexpr int H = ROWS / 4;     // wave instructions per group
+  constexpr int GPB = 64 / ROWS;  // groups per batch of row extents
+  static_assert(ROWS * MAXNZ <= 64, "a group's entries fit one coalesced load");
+  const int lane = lane_id(), wave = wave_id();
+  const int q = lane >> 4, sub = lane & 15;
+  const int ngroups = plan.ngroups;
+  const int g = xcd_band(blockIdx.x, ngroups);
+  const int64_t r0 = plan.band ? (int64_t)plan.band[g] : (int64_t)g * plan.rows_per_group;
+  const int64_t r1 = plan.band ? (int64_t)plan.band[g + 1]
+                               : min<int64_t>(r0 + plan.rows_per_group, d);
+  const int64_t ngrp = r1 > r0 ? (r1 - r0 + ROWS - 1) / ROWS : 0;
+  const int64_t nk = ngrp > wave ? (ngrp - wave + kWaves - 1) / kWaves : 0;
+  const WideRows<OFF32> rd(vk, d, sub);
+  float* vm_l = vm + sub * 4;
+  // moment partials of probes 4 sub + e, row class q
+  double m1[4] = {0.0, 0.0, 0.0, 0.0}, m2[4] = {0.0, 0.0, 0.0, 0.0};
+  auto grp_row0 = [&](int64_t k) { return r0 + (k * kWaves + wave) * ROWS; };
+  auto grp_rows = [&](int64_t k) { return (int)min<int64_t>(ROWS, r1 - grp_row0(k)); };
+
+  if (nk > 0) {
+    auto load_batch = [&](int64_t j, int& rs, int& rlen) {
+      const int64_t k = j * GPB + lane / ROWS;
+      const int64_t row = grp_row0(k) + lane % ROWS;
+      const bool ok = k < nk && row < r1;
+      const int64_t rr = ok ? row : r0;
+      rs = rowptr[rr];
+      rlen = ok ? rowptr[rr + 1] - rs : 0;
+    };
+    auto load_cols = [&](const GroupExt<ROWS>& e, int& cj, float& av) {
+      const int64_t ce = min<int64_t>((int64_t)e.gs + lane, nnz - 1);
+      cj = col[ce];
+      av = PATTERN ? 1.f : val[ce];
+    };
+    const int64_t nbatch = (nk + GPB - 1) / GPB;
+    int64_t j = 0;
+    int rs, rlen, rs_n = 0, rlen_n = 0;
+    load_batch(0, rs, rlen);
+    if (nbatch > 1) load_batch(1, rs_n, rlen_n);
+    int64_t k = 0;
+    GroupExt<ROWS> cur = group_extent<ROWS>(rs, rlen, 0, grp_rows(0));
+    int cj = 0;
+    float av = 0.f;
+    load_cols(cur, cj, av);
+
+    while (true) {
+      const int64_t row0 = grp_row0(k);
+      wf4 x[H][MAXNZ], xi[H], xp[H];
+      float w[H][MAXNZ];
+      int len[H];
+      int64_t row[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int rr = 4 * h + q;  // this lane's row in the group
+        const int off = pick_quad(q, cur.off[4 * h], cur.off[4 * h + 1], cur.off[4 * h + 2],
+                                  cur.off[4 * h + 3]);
+        len[h] = pick_quad(q, cur.len[4 * h], cur.len[4 * h + 1], cur.len[4 * h + 2],
+                           cur.len[4 * h + 3]);
+        row[h] = row0 + min(rr, cur.nr - 1);
+#pragma unroll
+        for (int t = 0; t < MAXNZ; ++t) {
+          const int src = min(off + t, 63);
+          x[h][t] = rd(permute_lane(cj, src));
+          w[h][t] = PATTERN ? 1.f : __int_as_float(permute_lane(__float_as_int(av), src));
+        }
+        xi[h] = rd(row[h]);
+        if constexpr (HAS_PREV)
+          xp[h] = __builtin_nontemporal_load(reinterpret_cast<const wf4*>(vm_l + row[h] * 64));
+        else
+          xp[h] = wf4{0.f, 0.f, 0.f, 0.f};
+      }
+      // next group: extent and column prefetch
+      const int64_t kn = k + 1;
+      const bool has_next = kn < nk;
+      const bool new_batch = has_next && (kn % GPB) == 0;
+      GroupExt<ROWS> nxt = cur;
+      int cjn = 0;
+      float avn = 0.f;
+      if (has_next) {
+        const int qn = (int)(kn % GPB) * ROWS;
+        nxt = new_batch ? group_extent<ROWS>(rs_n, rlen_n, 0, grp_rows(kn))
+                        : group_extent<ROWS>(rs, rlen, qn, grp_rows(kn));
+        load_cols(nxt, cjn, avn);
+      }
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < MAXNZ; ++t) {
+          const float onf = t < len[h] ? 1.f : 0.f;
+          const float ww = PATTERN ? onf : w[h][t] * onf;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[e] = fmaf(ww, x[h][t][e], acc[e]);
+        }
+        if (4 * h + q < cur.nr) {
+          wf4 vn;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float v = fmaf(ca, acc[e], cb * xi[h][e]);
+            if (HAS_PREV) v -= xp[h][e];
+            vn[e] = v;
+          }
+          __builtin_nontemporal_store(vn, reinterpret_cast<wf4*>(vm_l + row[h] * 64));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            m1[e] += (double)xi[h][e] * (double)vn[e];
+            m2[e] += (double)vn[e] * (double)vn[e];
+          }
+        }
+      }
+      if (!has_next) break;
+      if (new_batch) {
+        rs = rs_n;
+        rlen = rlen_n;
+        ++j;
+        if (j + 1 < nbatch) load_batch(j + 1, rs_n, rlen_n);
+      }
+      k = kn;
+      cur = nxt;
+      cj = cjn;
+      av = avn;
+    }
+  }
+  // per probe: each wave's classes in class order, then the waves in order
+  __shared__ double sh[2][kWaves][4][64];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    sh[0][wave][q][4 * sub + e] = m1[e];
+    sh[1][wave][q][4 * sub + e] = m2[e];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      double t1 = sh[0][w][0][lane], t2 = sh[1][w][0][lane];
+#pragma unroll
+      for (int c = 1; c < 4; ++c) {
+        t1 += sh[0][w][c][lane];
+        t2 += sh[1][w][c][lane];
+      }
+      if (w == 0) {
+        s1 = t1;
+        s2 = t2;
+      } else {
+        s1 += t1;
+        s2 += t2;
+      }
+    }
+    part[(size_t)g * 64 + lane] = s1;
+    part[((size_t)ngroups + g) * 64 + lane] = s2;
+  }
 }
 
 // Gram step, first product: W = X V_k over X's rows (V_k has dv = X's
@@ -918,7 +1143,7 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   float* vm = s & 1 ? B.v1 : B.v0;
   const float ca = (float)(HAS_PREV ? 2.0 * B.alpha : B.alpha);
   const float cb = (float)(HAS_PREV ? 2.0 * B.beta : B.beta);
-  RecEpi<float, ZMODE, HAS_PREV> epi(ca, cb, vm, B.src);
+  RecEpi<float, ZMODE, HAS_PREV, false, TAIL == kTailNone ? 4 : 1> epi(ca, cb, vm, B.src);
   const HubView nohub{nullptr, nullptr, 0, nullptr};
   const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
   csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
@@ -1007,7 +1232,8 @@ __global__ __launch_bounds__(kThreads) void csr_batch_persistent_kernel(
       }
       const float* vk = (s - 1) & 1 ? B.v1 : B.v0;
       float* vm = s & 1 ? B.v1 : B.v0;
-      RecEpi<float, ZMODE, true> epi((float)(2.0 * B.alpha), (float)(2.0 * B.beta), vm, B.src);
+      RecEpi<float, ZMODE, true, false, TAIL == kTailNone ? 4 : 1> epi(
+          (float)(2.0 * B.alpha), (float)(2.0 * B.beta), vm, B.src);
       const HubView nohub{nullptr, nullptr, 0, nullptr};
       const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
       csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
@@ -1045,12 +1271,21 @@ hipError_t launch_step_t(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T c
                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, const HubView& hub,
                          double* part) {
   const dim3 grid(plan.ngroups), block(kThreads);
-  if (has_prev)
-    csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32, TAIL><<<grid, block, 0, s>>>(
-        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, banded(m, plan), part);
-  else
-    csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32, TAIL><<<grid, block, 0, s>>>(
-        m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, banded(m, plan), part);
+  if constexpr (std::is_same<T, float>::value && ZMODE == 0 && TAIL == kTailNone) {
+    if (has_prev)
+      csr_step_wide_kernel<PATTERN, true, MAXNZ, OFF32><<<grid, block, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, banded(m, plan), part);
+    else
+      csr_step_wide_kernel<PATTERN, false, MAXNZ, OFF32><<<grid, block, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, banded(m, plan), part);
+  } else {
+    if (has_prev)
+      csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32, TAIL><<<grid, block, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, banded(m, plan), part);
+    else
+      csr_step_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32, TAIL><<<grid, block, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, hub, banded(m, plan), part);
+  }
   return hipGetLastError();
 }
 
@@ -1345,7 +1580,7 @@ __global__ __launch_bounds__(kThreads) void csr_fused2_kernel(Fused2Args a) {
     fused_ticket(k, per, a.lag, w, a.two, sub, t);
     const int bid = t * 8 + xcd;  // the workgroup index whose band is tile base + t
     if (sub == 1) {
-      RecEpi<float, Z1, PREV1, true> epi(a.ca1, a.cb1, a.x, a.src);
+      RecEpi<float, Z1, PREV1, true, 4> epi(a.ca1, a.cb1, a.x, a.src);
       csr_step_wg<float, PATTERN, MAXNZ, OFF32, kTailNone, false>(
           a.rowptr, a.col, a.val, a.d, a.d, a.nnz, RowReader<float, OFF32>(a.y, a.d, lane_id()),
           nullptr, epi, hub, plan, a.part1, bid);
@@ -1359,7 +1594,7 @@ __global__ __launch_bounds__(kThreads) void csr_fused2_kernel(Fused2Args a) {
       const int tile = base + t;
       const int t0 = max(0, tile - w), t1 = min(a.ntiles - 1, tile + w);
       if (!fused_wait(a, t0, t1, t0 < base || t1 >= base + per)) break;
-      RecEpi<float, Z2, true> epi(a.ca2, a.cb2, a.y, a.src);
+      RecEpi<float, Z2, true, false, 4> epi(a.ca2, a.cb2, a.y, a.src);
       csr_step_wg<float, PATTERN, MAXNZ, OFF32, kTailNone, false>(
           a.rowptr, a.col, a.val, a.d, a.d, a.nnz, RowReader<float, OFF32>(a.x, a.d, lane_id()),
           nullptr, epi, hub, plan, a.part2, bid);

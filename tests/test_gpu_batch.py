@@ -166,6 +166,64 @@ def test_batch_equals_block_by_block_on_large_operators(ctx, mode):
         it["op"].close()
 
 
+def _path_laplacian(d, shift=0.01):
+    """Tridiagonal 1D Laplacian + shift (rows of at most 3 entries)."""
+    import scipy.sparse as sp
+
+    A = sp.diags([-np.ones(d - 1), np.full(d, 2.0 + shift), -np.ones(d - 1)], [-1, 0, 1],
+                 format="csr")
+    A.sort_indices()
+    return wl.CSR(d, A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                  A.data.astype(np.float32))
+
+
+def _grid_adjacency(n):
+    """0/1 adjacency of the n x n grid as a pattern (rows of 2..4 entries)."""
+    g = wl.laplacian_2d(n)
+    A = g.to_scipy().tocoo()
+    keep = A.row != A.col
+    import scipy.sparse as sp
+
+    B = sp.csr_matrix((np.ones(int(keep.sum())), (A.row[keep], A.col[keep])), shape=A.shape)
+    B.sort_indices()
+    return wl.CSR(g.d, B.indptr.astype(np.int32), B.indices.astype(np.int32), None)
+
+
+@pytest.mark.parametrize("mode", ["doubling", "direct"])
+def test_wide_step_equals_lane_per_probe_body(ctx, mode):
+    """Operators whose rows all fit the straight-line path take the wide FP32
+    step kernel (4 probes per lane) in single estimates for the symmetric
+    form's moments; the batched kernel runs the lane = probe body.  Both
+    sum in the same order, so the results agree bit for bit, for each row
+    capacity (<= 4, <= 5, <= 8 entries), with values and as a pattern.  The
+    operators (over 147,000 rows) keep the one-block-at-a-time path."""
+    from paper_2103_10516_amd import mlct
+
+    md = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    cases = [(_path_laplacian(150_000), mlct.MLCT_LOG, 0.01, 4.01),
+             (wl.laplacian_2d(390), mlct.MLCT_LOG, 0.01, 8.01),
+             (wl.laplacian_3d(54), mlct.MLCT_SQRT, 0.01, 12.01),
+             (_grid_adjacency(390), mlct.MLCT_EXP, -4.01, 4.01)]
+    items = []
+    for i, (g, f, a, b) in enumerate(cases):
+        assert g.d >= 147_000
+        items.append(dict(op=_op(ctx, g), kind=f, a=a, b=b, degrees=[7, 22], m=[130, 64],
+                          seed=900 + i))
+    mlct.mlct_set_option(ctx, mlct.MLCT_OPT_BATCH_SOLO_ROWS, 1 << 40)
+    try:
+        res = mlct.mlct_estimate_batch(ctx, items, prec=mlct.MLCT_FP32, mode=md)
+    finally:
+        mlct.mlct_set_option(ctx, mlct.MLCT_OPT_BATCH_SOLO_ROWS, 0)
+    for it, r in zip(items, res):
+        one = mlct.mlct_estimate(ctx, it["op"], it["kind"], it["a"], it["b"], it["degrees"],
+                                 it["m"], it["seed"], mlct.MLCT_FP32, md)
+        assert r["value"] == one["value"] and r["est_var"] == one["est_var"]
+        np.testing.assert_array_equal(r["level_mean"], one["level_mean"])
+        np.testing.assert_array_equal(r["level_var"], one["level_var"])
+    for it in items:
+        it["op"].close()
+
+
 def test_autotune_batch_launch_form(ctx):
     """The batch autotuner times both launch forms and the context then uses
     the faster one by default; all three calls give the same results."""

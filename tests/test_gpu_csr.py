@@ -67,11 +67,23 @@ def _lap1d(n: int, shift: float = 0.01) -> wl.CSR:
                   np.asarray(vals, dtype=np.float32))
 
 
+def _grid_adjacency(n: int) -> wl.CSR:
+    """0/1 adjacency of the n x n grid as a pattern (rows of 2..4 entries)."""
+    g = wl.laplacian_2d(n)
+    A = g.to_scipy().tocsr()
+    A.setdiag(0)
+    A.eliminate_zeros()
+    A.sort_indices()
+    return wl.CSR(g.d, A.indptr.astype(np.int32), A.indices.astype(np.int32), None)
+
+
 CASES = [
     # (name, graph builder, a, b); the row lengths pick the straight-line
-    # capacity: <= 4 (lap1d), <= 5 (lap2d), <= 8 (lap3d), longer rows
-    # (random, Chung-Lu) the generic loop, past 256 entries the hub chunks
+    # capacity: <= 4 (lap1d, grid adjacency), <= 5 (lap2d), <= 8 (lap3d),
+    # longer rows (random, Chung-Lu) the generic loop, past 256 entries the
+    # hub chunks
     ("lap1d_777", lambda: _lap1d(777), 0.01, 4.01),
+    ("grid_pattern_29", lambda: _grid_adjacency(29), -4.01, 4.01),
     ("lap2d_45", lambda: wl.laplacian_2d(45), 0.01, 8.01),
     ("lap3d_11", lambda: wl.laplacian_3d(11), 0.01, 12.01),
     ("random_ragged", lambda: wl.random_csr(301, 0.03, 4), -7.0, 7.0),
@@ -114,6 +126,37 @@ def test_moments_match_oracle(ctx, torch_dev, name, builder, a, b, prec, mode):
     assert np.all(got[:, 0] == g.d)
     worst = np.max(err / tol[None, :])
     print(f"{name} {prec} {mode}: worst err/tol = {worst:.3g}")
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("mode", ["doubling", "direct"])
+def test_moments_block_over_4gib(ctx, torch_dev, mode):
+    """A path Laplacian with 16.8M rows: a 64-probe FP32 block is 4.3 GB, past
+    the 32-bit gather offsets, so the steps take the 64-bit-address forms.
+    Eight probe lanes (the first, the last, and between) against the oracle."""
+    import scipy.sparse as sp
+
+    from paper_2103_10516_amd import mlct
+
+    d, n, seed, a, b = 16_800_000, 6, 4242, 0.01, 4.01
+    A = sp.diags([-np.ones(d - 1), np.full(d, 2.01), -np.ones(d - 1)], [-1, 0, 1],
+                 format="csr")
+    A.sort_indices()
+    g = wl.CSR(d, A.indptr.astype(np.int32), A.indices.astype(np.int32),
+               A.data.astype(np.float32))
+    assert d * 64 * 4 > 2**32
+    op = _op(ctx, torch_dev, g)
+    M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    got = mlct.mlct_moments(ctx, op, a, b, n, mlct.rademacher_probes(seed, 64), mlct.MLCT_FP32, M)
+    op.close()
+    lanes = np.array([0, 9, 17, 31, 32, 45, 58, 63])
+    want = _oracle_mu(g, a, b, n, lanes, seed)
+    alpha, beta = cheb.affine_map(a, b)
+    tol = fp_moment_tol(n, d, "fp32", 3, rho_rows(g.to_scipy()), kappa_csr(g, alpha, beta),
+                        alpha, beta, mode == "doubling")
+    assert np.all(got[:, 0] == d)
+    worst = np.max(np.abs(got[lanes] - want) / tol[None, :])
+    print(f"d = {d} {mode}: worst err/tol = {worst:.3g}")
     assert worst <= 1.0
 
 
