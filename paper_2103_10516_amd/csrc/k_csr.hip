@@ -817,11 +817,16 @@ __device__ __forceinline__ int permute_lane(int v, int src) {
   return __builtin_amdgcn_ds_bpermute(src << 2, v);
 }
 
+using WidePartials = double[2][kWaves][4][64];
+
+// Band g of the wide step: its rows, then its moment partials (sh: the
+// workgroup's LDS for the partials).
 template <bool PATTERN, bool HAS_PREV, int MAXNZ, bool OFF32>
-__global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
+__device__ __forceinline__ void wide_band(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const float* __restrict__ vk,
-    float* __restrict__ vm, float ca, float cb, CsrStepPlan plan, double* __restrict__ part) {
+    float* __restrict__ vm, float ca, float cb, const CsrStepPlan& plan,
+    double* __restrict__ part, int g, WidePartials& sh) {
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
   constexpr int H = ROWS / 4;     // wave instructions per group
   constexpr int GPB = 64 / ROWS;  // groups per batch of row extents
@@ -829,7 +834,6 @@ __global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
   const int lane = lane_id(), wave = wave_id();
   const int q = lane >> 4, sub = lane & 15;
   const int ngroups = plan.ngroups;
-  const int g = xcd_band(blockIdx.x, ngroups);
   const int64_t r0 = plan.band ? (int64_t)plan.band[g] : (int64_t)g * plan.rows_per_group;
   const int64_t r1 = plan.band ? (int64_t)plan.band[g + 1]
                                : min<int64_t>(r0 + plan.rows_per_group, d);
@@ -946,7 +950,6 @@ __global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
     }
   }
   // per probe: each wave's classes in class order, then the waves in order
-  __shared__ double sh[2][kWaves][4][64];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     sh[0][wave][q][4 * sub + e] = m1[e];
@@ -974,6 +977,16 @@ __global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
     part[(size_t)g * 64 + lane] = s1;
     part[((size_t)ngroups + g) * 64 + lane] = s2;
   }
+}
+
+template <bool PATTERN, bool HAS_PREV, int MAXNZ, bool OFF32>
+__global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const float* __restrict__ val, int64_t d, int64_t nnz, const float* __restrict__ vk,
+    float* __restrict__ vm, float ca, float cb, CsrStepPlan plan, double* __restrict__ part) {
+  __shared__ WidePartials sh;
+  wide_band<PATTERN, HAS_PREV, MAXNZ, OFF32>(rowptr, col, val, d, nnz, vk, vm, ca, cb, plan, part,
+                                              xcd_band(blockIdx.x, plan.ngroups), sh);
 }
 
 // Gram step, first product: W = X V_k over X's rows (V_k has dv = X's
@@ -1143,12 +1156,20 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   float* vm = s & 1 ? B.v1 : B.v0;
   const float ca = (float)(HAS_PREV ? 2.0 * B.alpha : B.alpha);
   const float cb = (float)(HAS_PREV ? 2.0 * B.beta : B.beta);
-  RecEpi<float, ZMODE, HAS_PREV, false, TAIL == kTailNone ? 4 : 1> epi(ca, cb, vm, B.src);
-  const HubView nohub{nullptr, nullptr, 0, nullptr};
   const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
-  csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
-      B.rowptr, B.col, B.val, B.d, B.d, B.nnz, RowReader<float, true>(vk, B.d, lane_id()),
-      nullptr, epi, nohub, plan, B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+  double* part = B.part + (size_t)s * 2 * B.ngroups * 64;
+  if constexpr (ZMODE == 0 && TAIL == kTailNone) {
+    // the single-operator step's wide form (same bits)
+    __shared__ WidePartials sh;
+    wide_band<PATTERN, HAS_PREV, MAXNZ, true>(B.rowptr, B.col, B.val, B.d, B.nnz, vk, vm, ca, cb,
+                                               plan, part, g, sh);
+  } else {
+    RecEpi<float, ZMODE, HAS_PREV, false, TAIL == kTailNone ? 4 : 1> epi(ca, cb, vm, B.src);
+    const HubView nohub{nullptr, nullptr, 0, nullptr};
+    csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
+        B.rowptr, B.col, B.val, B.d, B.d, B.nnz, RowReader<float, true>(vk, B.d, lane_id()),
+        nullptr, epi, nohub, plan, part, bid);
+  }
 }
 
 // ---- one persistent launch for the steps of a batch ---------------------------
@@ -1232,13 +1253,20 @@ __global__ __launch_bounds__(kThreads) void csr_batch_persistent_kernel(
       }
       const float* vk = (s - 1) & 1 ? B.v1 : B.v0;
       float* vm = s & 1 ? B.v1 : B.v0;
-      RecEpi<float, ZMODE, true, false, TAIL == kTailNone ? 4 : 1> epi(
-          (float)(2.0 * B.alpha), (float)(2.0 * B.beta), vm, B.src);
-      const HubView nohub{nullptr, nullptr, 0, nullptr};
+      const float ca = (float)(2.0 * B.alpha), cb = (float)(2.0 * B.beta);
       const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
-      csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
-          B.rowptr, B.col, B.val, B.d, B.d, B.nnz, RowReader<float, true>(vk, B.d, lane_id()),
-          nullptr, epi, nohub, plan, B.part + (size_t)s * 2 * B.ngroups * 64, bid);
+      double* part = B.part + (size_t)s * 2 * B.ngroups * 64;
+      if constexpr (ZMODE == 0 && TAIL == kTailNone) {
+        __shared__ WidePartials sh;
+        wide_band<PATTERN, true, MAXNZ, true>(B.rowptr, B.col, B.val, B.d, B.nnz, vk, vm, ca, cb,
+                                              plan, part, g, sh);
+      } else {
+        RecEpi<float, ZMODE, true, false, TAIL == kTailNone ? 4 : 1> epi(ca, cb, vm, B.src);
+        const HubView nohub{nullptr, nullptr, 0, nullptr};
+        csr_step_wg<float, PATTERN, MAXNZ, true, TAIL, false>(
+            B.rowptr, B.col, B.val, B.d, B.d, B.nnz, RowReader<float, true>(vk, B.d, lane_id()),
+            nullptr, epi, nohub, plan, part, bid);
+      }
       __syncthreads();  // the step body's shared partial buffer is reused
       ++pending;
     }
