@@ -174,8 +174,10 @@ def extra_dense_rungs(mlct, dev):
     singular values the matrix was built from).  Per-probe parity of every
     rung against the FP64 oracle at this size is a GPU test
     (tests/test_gpu_full_size.py).  Also the dense SPD log-det workload,
-    d = 512, FP64: single level 64 with 256 probes and the 2-level split
-    (8, 64) with 224/32 probes, against sum_i log(lambda_i)."""
+    d = 512, FP64: single levels 8 / 32 / 64 with 256 probes, the 2-level
+    pairs (8, 64) and (32, 64) with 256 probes split by eq. eqn:optSamples
+    from a 32-probe pilot, against sum_i log(lambda_i), and the 512 Sylvester
+    Hadamard probes, whose estimate is tr p_n exactly."""
     import torch
 
     from paper_2103_10516_amd import workloads as wl
@@ -219,14 +221,15 @@ def extra_dense_rungs(mlct, dev):
         rungs[name]["rel_diff_vs_fp64_rung"] = (abs(rungs[name]["estimate"] - rungs["fp64"]["estimate"])
                                                 / abs(rungs["fp64"]["estimate"]))
     op.close()
-    # dense SPD log-det, d = 512, FP64
+    # dense SPD log-det, d = 512, FP64: single levels, two-level splits sized
+    # from a 32-probe pilot, and the 512 Hadamard probes (exact trace)
     A, lam = wl.dense_spd(512)
     opd = mlct.mlct_op_dense(ctx, torch.from_numpy(A).to(dev))
     truth = float(np.sum(np.log(lam)))
-    small = {}
-    for label, dg, mm in (("single_64", [64], [256]), ("mlmc_8_64", [8, 64], [224, 32])):
-        run = lambda: mlct.mlct_estimate(ctx, opd, mlct.MLCT_LOG, 0.1, 1.0, dg, mm, 5,
-                                         mlct.MLCT_FP64, mlct.MLCT_DOUBLING)
+    MD, F64 = mlct.MLCT_DOUBLING, mlct.MLCT_FP64
+
+    def timed(dg, mm):
+        run = lambda: mlct.mlct_estimate(ctx, opd, mlct.MLCT_LOG, 0.1, 1.0, dg, mm, 5, F64, MD)
         run()
         best = float("inf")
         for _ in range(5):
@@ -235,10 +238,29 @@ def extra_dense_rungs(mlct, dev):
             r = run()
             _sync()
             best = min(best, time.perf_counter() - t0)
-        small[label] = {"ms": best * 1e3, "estimate": r["estimate"],
-                        "rel_err_vs_logdet": abs(r["estimate"] - truth) / abs(truth),
-                        "rel_se": math.sqrt(r["est_var"]) / abs(truth),
-                        "probe_degree_per_s": r["probe_degrees"] / best}
+        return {"degrees": dg, "m": mm, "ms": best * 1e3, "estimate": r["estimate"],
+                "rel_err_vs_logdet": abs(r["estimate"] - truth) / abs(truth),
+                "rel_se": math.sqrt(r["est_var"]) / abs(truth),
+                "probe_degree_per_s": r["probe_degrees"] / best}
+
+    small = {f"single_{n1}": timed([n1], [256]) for n1 in (8, 32, 64)}
+    for lo in (8, 32):
+        # eq. eqn:optSamples with C_k = steps of level k, scaled to 256 probes
+        pil = mlct.mlct_estimate(ctx, opd, mlct.MLCT_LOG, 0.1, 1.0, [lo, 64], [32, 32], 11, F64, MD)
+        cost = np.array([(lo + 1) // 2, 32], dtype=np.float64)
+        w = np.sqrt(np.maximum(np.asarray(pil["level_var"][:2]), 1e-300) / cost)
+        m1 = int(min(254, max(2, round(256 * w[0] / w.sum()))))  # >= 2 per level
+        small[f"mlmc_{lo}_64"] = timed([lo, 64], [m1, 256 - m1])
+    H = torch.from_numpy(np.ascontiguousarray(wl.hadamard_signs(512).T)).to(dev)
+    had = {}
+    for n1 in (8, 32, 64):
+        mu = mlct.mlct_moments(ctx, opd, 0.1, 1.0, n1, mlct.explicit_probes(H), F64, MD)
+        c, ls = mlct.mlct_cheb_coeffs(ctx, mlct.MLCT_LOG, 0.1, 1.0, n1)
+        est = float(np.mean(mu @ c)) * math.exp(ls)
+        trp = float(np.sum(np.polynomial.chebyshev.chebval((2.0 * lam - 1.1) / 0.9, c))) * math.exp(ls)
+        had[f"n{n1}"] = {"trace_p_n": est, "rel_err_vs_sum_p_n": abs(est - trp) / abs(trp),
+                         "rel_err_vs_logdet": abs(est - truth) / abs(truth)}
+    small["hadamard_512"] = had
     opd.close()
     ctx.close()
     return {"workload": "nuclear norm X 8192x4096 (FP32), A=X^T X, sqrt on [1e-6,1], levels "
