@@ -339,6 +339,9 @@ def extra_estrada(mlct, dev):
     vec = 4 * 64 * g.d
     by = 4 * g.nnz + 4 * (g.d + 1) + 2 * vec + vec * (n - blocks) / n  # pattern: no values
     ach = by / (ms / n / 1e3) / 1e9
+    # counted HBM bytes of a V_prev-reading step: the step kernel and its hub chunks
+    t_step, t_hub = stored_traffic("csr_step_pattern_chunglu_1e6"), stored_traffic("csr_hub_chunglu_1e6")
+    traffic = t_step + t_hub if t_step and t_hub else None
     out = {"workload": f"Estrada index, Chung-Lu d=1e6 nnz={g.nnz}, Lanczos interval (64 steps), "
                        "levels 10/30/60, probes 768/192/64, doubling, FP32",
            "bounds_ms": tb * 1e3, "estimate_ms": te * 1e3, "interval": [a, b],
@@ -346,7 +349,8 @@ def extra_estrada(mlct, dev):
            "roofline": {"bound": "hbm", "kernel": "csr_step_kernel<float,pattern,...> + hub chunks",
                         "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": by,
-                        "avg_launch_ms": ms / n, "launches": n}}
+                        "avg_launch_ms": ms / n, "launches": n, "traffic": traffic,
+                        "traffic_rate_GBs": traffic / (ms / n / 1e3) / 1e9 if traffic else None}}
     op.close()
     ctx.close()
     return out
