@@ -105,8 +105,8 @@ __global__ __launch_bounds__(kThreads) void probe_init_kernel(T* __restrict__ v0
 // Per-row epilogue of the recurrence: V_new = ca*acc + cb*V_k[i] (- V_prev[i]),
 // written over V_prev (with a non-temporal store unless KEEP: a vector
 // gathered again soon is stored normally, to stay in the caches), and the
-// lane's moment partials (FP64).  With CLS = 4 (FP32, ZMODE 0, operators
-// whose rows all fit the straight-line path) the partials are kept per row
+// lane's moment partials (FP64).  With CLS = 4 (FP32, ZMODE 0 or 1,
+// operators whose rows all fit the straight-line path) the partials are kept per row
 // class (the row's index in its group, mod 4) and the classes added in
 // order at the end: the summation order of the wide step kernel, whose lane
 // quads take one class each, so both kernels give the same bits.
@@ -115,7 +115,7 @@ struct RecEpi {
   using Part = double;
   static constexpr bool kOwn = true;    // needs V_k[i] of its own row
   static constexpr bool kParts = true;  // writes moment partials
-  static constexpr int kCls = (ZMODE == 0 && sizeof(T) == 4) ? CLS : 1;
+  static constexpr int kCls = (ZMODE <= 1 && sizeof(T) == 4) ? CLS : 1;
   T ca, cb;
   T* vm;
   ProbeSrc src;
@@ -773,76 +773,107 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
                                                      nullptr, epi, hub, plan, part, blockIdx.x);
 }
 
-// ---- wide form of the FP32 step ---------------------------------------------
-// For operators whose rows all fit the straight-line path (no tail), FP32,
-// and moments of the symmetric form (ZMODE 0), the same step with a lane
-// holding 4 probes: every access is 16 bytes, so one wave instruction moves
-// four rows (lanes 16q .. 16q+15 on the group's rows q and q+4) and a step
-// issues a quarter of the memory instructions of the lane = probe body.
-// The work split (bands, groups of ROWS rows, wave w on groups w, w + 8, ...),
-// the column prefetch, the row sums (entry order, one fma per entry, unused
-// slots weighted 0), the update and the moment classes are those of
-// csr_step_wg with RecEpi, so both give the same bits; a lane's row offset
-// and length are picked from the group's extent by its quad, and its column
-// indices and values come from the group's coalesced load by a lane
-// permute.
-typedef float wf4 __attribute__((ext_vector_type(4)));
-
-template <bool OFF32>
-struct WideRows {
-  const float* base;
-  __amdgpu_buffer_rsrc_t rsrc;
-  uint32_t lane_off;
-  __device__ __forceinline__ WideRows(const float* b, int64_t d, int sub) : base(b) {
-    if (OFF32)
-      rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(b), (short)0,
-                                               (int)(uint32_t)(d * 256), 0x00020000);
-    lane_off = (uint32_t)sub * 16;
-  }
-  // probes 4 sub .. 4 sub + 3 of block row j
-  __device__ __forceinline__ wf4 operator()(int64_t j) const {
-    if constexpr (OFF32)
-      return __builtin_bit_cast(
-          wf4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (uint32_t)j * 256u + lane_off, 0, 0));
-    else
-      return *reinterpret_cast<const wf4*>(base + j * 64 + lane_off / 4);
-  }
+// ---- wide form of the step ------------------------------------------------------
+// For operators whose rows all fit the straight-line path (no tail) and
+// moments of the symmetric form (ZMODE 0) or the direct form with
+// regenerated Rademacher probes (ZMODE 1), the same step with a lane
+// holding PPL = 16 / sizeof(T) probes (4 in FP32, 2 in FP64): every access
+// is 16 bytes, so one wave instruction moves PPL rows (lane group q, of
+// 64 / PPL lanes, on the group's rows q, q + PPL, ...) and a step issues
+// 1 / PPL of the memory instructions of the lane = probe body.  The work
+// split (bands, groups of ROWS rows, wave w on groups w, w + 8, ...), the
+// column prefetch, the row sums (entry order, one fma per entry, unused
+// slots weighted 0) and the update are those of csr_step_wg with RecEpi; a
+// lane's row offset and length are picked from the group's extent by its
+// lane group, and its column indices and values come from the group's
+// coalesced load by a lane permute.  The moment partials are kept per row
+// class (row index in the group mod PPL, one class per lane group) and the
+// classes added in order; in FP32 that is the order of RecEpi with CLS = 4,
+// so this kernel and the lane = probe body give the same bits.
+template <typename T>
+struct WideVec;
+template <>
+struct WideVec<float> {
+  typedef float V __attribute__((ext_vector_type(4)));
+};
+template <>
+struct WideVec<double> {
+  typedef double V __attribute__((ext_vector_type(2)));
 };
 
-__device__ __forceinline__ int pick_quad(int q, int a, int b, int c, int d) {
-  return q == 0 ? a : q == 1 ? b : q == 2 ? c : d;
-}
+template <typename T, bool OFF32>
+struct WideRows {
+  using V = typename WideVec<T>::V;
+  const T* base;
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t lane_off;
+  __device__ __forceinline__ WideRows(const T* b, int64_t d, int sub) : base(b) {
+    if (OFF32)
+      rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(b), (short)0,
+                                               (int)(uint32_t)(d * 64 * sizeof(T)), 0x00020000);
+    lane_off = (uint32_t)sub * 16;
+  }
+  // the lane's probes of block row j
+  __device__ __forceinline__ V operator()(int64_t j) const {
+    if constexpr (OFF32)
+      return __builtin_bit_cast(
+          V, __builtin_amdgcn_raw_buffer_load_b128(
+                 rsrc, (uint32_t)j * (uint32_t)(64 * sizeof(T)) + lane_off, 0, 0));
+    else
+      return *reinterpret_cast<const V*>(base + j * 64 + lane_off / sizeof(T));
+  }
+};
 
 __device__ __forceinline__ int permute_lane(int v, int src) {
   return __builtin_amdgcn_ds_bpermute(src << 2, v);
 }
 
-using WidePartials = double[2][kWaves][4][64];
+template <typename T>
+using WidePartials = double[2][kWaves][16 / sizeof(T)][64];
 
 // Band g of the wide step: its rows, then its moment partials (sh: the
 // workgroup's LDS for the partials).
-template <bool PATTERN, bool HAS_PREV, int MAXNZ, bool OFF32>
+template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
 __device__ __forceinline__ void wide_band(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const float* __restrict__ val, int64_t d, int64_t nnz, const float* __restrict__ vk,
-    float* __restrict__ vm, float ca, float cb, const CsrStepPlan& plan,
-    double* __restrict__ part, int g, WidePartials& sh) {
+    const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
+    T* __restrict__ vm, T ca, T cb, const ProbeSrc& src, const CsrStepPlan& plan,
+    double* __restrict__ part, int g, WidePartials<T>& sh) {
+  static_assert(ZMODE == 0 || ZMODE == 1, "symmetric or regenerated direct moments");
+  using V = typename WideVec<T>::V;
+  constexpr int PPL = 16 / (int)sizeof(T);  // probes per lane = rows per wave instruction
+  constexpr int LPR = 64 / PPL;             // lanes per row
   constexpr int ROWS = MAXNZ <= 5 ? 8 : 4;
-  constexpr int H = ROWS / 4;     // wave instructions per group
+  constexpr int H = ROWS / PPL;   // wave instructions per group
   constexpr int GPB = 64 / ROWS;  // groups per batch of row extents
   static_assert(ROWS * MAXNZ <= 64, "a group's entries fit one coalesced load");
+  static_assert(ROWS % PPL == 0, "whole wave instructions per group");
   const int lane = lane_id(), wave = wave_id();
-  const int q = lane >> 4, sub = lane & 15;
+  const int q = lane / LPR, sub = lane % LPR;
   const int ngroups = plan.ngroups;
   const int64_t r0 = plan.band ? (int64_t)plan.band[g] : (int64_t)g * plan.rows_per_group;
   const int64_t r1 = plan.band ? (int64_t)plan.band[g + 1]
                                : min<int64_t>(r0 + plan.rows_per_group, d);
   const int64_t ngrp = r1 > r0 ? (r1 - r0 + ROWS - 1) / ROWS : 0;
   const int64_t nk = ngrp > wave ? (ngrp - wave + kWaves - 1) / kWaves : 0;
-  const WideRows<OFF32> rd(vk, d, sub);
-  float* vm_l = vm + sub * 4;
-  // moment partials of probes 4 sub + e, row class q
-  double m1[4] = {0.0, 0.0, 0.0, 0.0}, m2[4] = {0.0, 0.0, 0.0, 0.0};
+  const WideRows<T, OFF32> rd(vk, d, sub);
+  T* vm_l = vm + sub * PPL;
+  // moment partials of probes PPL sub + e, row class q
+  double m1[PPL], m2[PPL];
+#pragma unroll
+  for (int e = 0; e < PPL; ++e) m1[e] = m2[e] = 0.0;
+  // ZMODE 1: the lane's probe keys, the key of probe PPL sub + q, and the
+  // sign words of the lane's probes for the 64-row chunk `cached` (uniform)
+  uint64_t key[PPL], word[PPL], keyq = 0;
+  int64_t cached = -1;
+  if constexpr (ZMODE == 1) {
+#pragma unroll
+    for (int e = 0; e < PPL; ++e) {
+      key[e] = sm_output(src.seed, (uint64_t)(src.first_id + PPL * sub + e));
+      word[e] = 0;
+    }
+    keyq = sm_output(src.seed, (uint64_t)(src.first_id + PPL * sub + q));
+  }
   auto grp_row0 = [&](int64_t k) { return r0 + (k * kWaves + wave) * ROWS; };
   auto grp_rows = [&](int64_t k) { return (int)min<int64_t>(ROWS, r1 - grp_row0(k)); };
 
@@ -873,17 +904,22 @@ __device__ __forceinline__ void wide_band(
 
     while (true) {
       const int64_t row0 = grp_row0(k);
-      wf4 x[H][MAXNZ], xi[H], xp[H];
+      V x[H][MAXNZ], xi[H], xp[H];
       float w[H][MAXNZ];
       int len[H];
       int64_t row[H];
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        const int rr = 4 * h + q;  // this lane's row in the group
-        const int off = pick_quad(q, cur.off[4 * h], cur.off[4 * h + 1], cur.off[4 * h + 2],
-                                  cur.off[4 * h + 3]);
-        len[h] = pick_quad(q, cur.len[4 * h], cur.len[4 * h + 1], cur.len[4 * h + 2],
-                           cur.len[4 * h + 3]);
+        const int rr = PPL * h + q;  // this lane's row in the group
+        // its offset and length, selected with static indices (the extent
+        // stays in registers)
+        int off = cur.off[PPL * h];
+        len[h] = cur.len[PPL * h];
+#pragma unroll
+        for (int r = 1; r < PPL; ++r) {
+          off = q == r ? cur.off[PPL * h + r] : off;
+          len[h] = q == r ? cur.len[PPL * h + r] : len[h];
+        }
         row[h] = row0 + min(rr, cur.nr - 1);
 #pragma unroll
         for (int t = 0; t < MAXNZ; ++t) {
@@ -893,9 +929,9 @@ __device__ __forceinline__ void wide_band(
         }
         xi[h] = rd(row[h]);
         if constexpr (HAS_PREV)
-          xp[h] = __builtin_nontemporal_load(reinterpret_cast<const wf4*>(vm_l + row[h] * 64));
+          xp[h] = __builtin_nontemporal_load(reinterpret_cast<const V*>(vm_l + row[h] * 64));
         else
-          xp[h] = wf4{0.f, 0.f, 0.f, 0.f};
+          xp[h] = V{};
       }
       // next group: extent and column prefetch
       const int64_t kn = k + 1;
@@ -910,29 +946,61 @@ __device__ __forceinline__ void wide_band(
                         : group_extent<ROWS>(rs, rlen, qn, grp_rows(kn));
         load_cols(nxt, cjn, avn);
       }
+      // ZMODE 1, a group inside one 64-row chunk: each lane hashes the word
+      // of one probe, the lane groups exchange them (one hash per lane per
+      // chunk, as in the lane = probe body); a group across two chunks
+      // hashes per row below
+      bool one_chunk = true;
+      if constexpr (ZMODE == 1) {
+        const int64_t c0 = row0 >> 6;
+        one_chunk = ((row0 + ROWS - 1) >> 6) == c0;
+        if (one_chunk && c0 != cached) {
+          const uint64_t mine = sm_output(keyq, (uint64_t)c0);
+          const int lo = (int)(uint32_t)mine, hi = (int)(uint32_t)(mine >> 32);
+#pragma unroll
+          for (int e = 0; e < PPL; ++e) {
+            const int from = e * LPR + sub;  // lane group e holds probe PPL sub + e
+            word[e] = (uint64_t)(uint32_t)permute_lane(lo, from) |
+                      ((uint64_t)(uint32_t)permute_lane(hi, from) << 32);
+          }
+          cached = c0;
+        }
+      }
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        T acc[PPL];
+#pragma unroll
+        for (int e = 0; e < PPL; ++e) acc[e] = T(0);
 #pragma unroll
         for (int t = 0; t < MAXNZ; ++t) {
           const float onf = t < len[h] ? 1.f : 0.f;
-          const float ww = PATTERN ? onf : w[h][t] * onf;
+          const T ww = (T)(PATTERN ? onf : w[h][t] * onf);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = fmaf(ww, x[h][t][e], acc[e]);
+          for (int e = 0; e < PPL; ++e) acc[e] = fma(ww, x[h][t][e], acc[e]);
         }
-        if (4 * h + q < cur.nr) {
-          wf4 vn;
+        if (PPL * h + q < cur.nr) {
+          V vn;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float v = fmaf(ca, acc[e], cb * xi[h][e]);
+          for (int e = 0; e < PPL; ++e) {
+            T v = fma(ca, acc[e], cb * xi[h][e]);
             if (HAS_PREV) v -= xp[h][e];
             vn[e] = v;
           }
-          __builtin_nontemporal_store(vn, reinterpret_cast<wf4*>(vm_l + row[h] * 64));
+          __builtin_nontemporal_store(vn, reinterpret_cast<V*>(vm_l + row[h] * 64));
+          if constexpr (ZMODE == 0) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            m1[e] += (double)xi[h][e] * (double)vn[e];
-            m2[e] += (double)vn[e] * (double)vn[e];
+            for (int e = 0; e < PPL; ++e) {
+              m1[e] += (double)xi[h][e] * (double)vn[e];
+              m2[e] += (double)vn[e] * (double)vn[e];
+            }
+          } else {
+            uint64_t wd[PPL];
+#pragma unroll
+            for (int e = 0; e < PPL; ++e)
+              wd[e] = one_chunk ? word[e] : sm_output(key[e], (uint64_t)(row[h] >> 6));
+#pragma unroll
+            for (int e = 0; e < PPL; ++e)
+              m1[e] += sign_from_word<double>(wd[e], row[h]) * (double)vn[e];
           }
         }
       }
@@ -951,9 +1019,9 @@ __device__ __forceinline__ void wide_band(
   }
   // per probe: each wave's classes in class order, then the waves in order
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    sh[0][wave][q][4 * sub + e] = m1[e];
-    sh[1][wave][q][4 * sub + e] = m2[e];
+  for (int e = 0; e < PPL; ++e) {
+    sh[0][wave][q][PPL * sub + e] = m1[e];
+    sh[1][wave][q][PPL * sub + e] = m2[e];
   }
   __syncthreads();
   if (wave == 0) {
@@ -962,7 +1030,7 @@ __device__ __forceinline__ void wide_band(
     for (int w = 0; w < kWaves; ++w) {
       double t1 = sh[0][w][0][lane], t2 = sh[1][w][0][lane];
 #pragma unroll
-      for (int c = 1; c < 4; ++c) {
+      for (int c = 1; c < PPL; ++c) {
         t1 += sh[0][w][c][lane];
         t2 += sh[1][w][c][lane];
       }
@@ -979,14 +1047,15 @@ __device__ __forceinline__ void wide_band(
   }
 }
 
-template <bool PATTERN, bool HAS_PREV, int MAXNZ, bool OFF32>
+template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
 __global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const float* __restrict__ val, int64_t d, int64_t nnz, const float* __restrict__ vk,
-    float* __restrict__ vm, float ca, float cb, CsrStepPlan plan, double* __restrict__ part) {
-  __shared__ WidePartials sh;
-  wide_band<PATTERN, HAS_PREV, MAXNZ, OFF32>(rowptr, col, val, d, nnz, vk, vm, ca, cb, plan, part,
-                                              xcd_band(blockIdx.x, plan.ngroups), sh);
+    const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
+    T* __restrict__ vm, T ca, T cb, ProbeSrc src, CsrStepPlan plan, double* __restrict__ part) {
+  __shared__ WidePartials<T> sh;
+  wide_band<T, PATTERN, ZMODE, HAS_PREV, MAXNZ, OFF32>(rowptr, col, val, d, nnz, vk, vm, ca, cb,
+                                                        src, plan, part,
+                                                        xcd_band(blockIdx.x, plan.ngroups), sh);
 }
 
 // Gram step, first product: W = X V_k over X's rows (V_k has dv = X's
@@ -1158,11 +1227,11 @@ __global__ __launch_bounds__(kThreads) void csr_step_batched_kernel(
   const float cb = (float)(HAS_PREV ? 2.0 * B.beta : B.beta);
   const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
   double* part = B.part + (size_t)s * 2 * B.ngroups * 64;
-  if constexpr (ZMODE == 0 && TAIL == kTailNone) {
+  if constexpr (ZMODE <= 1 && TAIL == kTailNone) {
     // the single-operator step's wide form (same bits)
-    __shared__ WidePartials sh;
-    wide_band<PATTERN, HAS_PREV, MAXNZ, true>(B.rowptr, B.col, B.val, B.d, B.nnz, vk, vm, ca, cb,
-                                               plan, part, g, sh);
+    __shared__ WidePartials<float> sh;
+    wide_band<float, PATTERN, ZMODE, HAS_PREV, MAXNZ, true>(B.rowptr, B.col, B.val, B.d, B.nnz, vk,
+                                                             vm, ca, cb, B.src, plan, part, g, sh);
   } else {
     RecEpi<float, ZMODE, HAS_PREV, false, TAIL == kTailNone ? 4 : 1> epi(ca, cb, vm, B.src);
     const HubView nohub{nullptr, nullptr, 0, nullptr};
@@ -1256,10 +1325,10 @@ __global__ __launch_bounds__(kThreads) void csr_batch_persistent_kernel(
       const float ca = (float)(2.0 * B.alpha), cb = (float)(2.0 * B.beta);
       const CsrStepPlan plan{B.ngroups, B.rows_per_group, B.band};
       double* part = B.part + (size_t)s * 2 * B.ngroups * 64;
-      if constexpr (ZMODE == 0 && TAIL == kTailNone) {
-        __shared__ WidePartials sh;
-        wide_band<PATTERN, true, MAXNZ, true>(B.rowptr, B.col, B.val, B.d, B.nnz, vk, vm, ca, cb,
-                                              plan, part, g, sh);
+      if constexpr (ZMODE <= 1 && TAIL == kTailNone) {
+        __shared__ WidePartials<float> sh;
+        wide_band<float, PATTERN, ZMODE, true, MAXNZ, true>(B.rowptr, B.col, B.val, B.d, B.nnz, vk,
+                                                             vm, ca, cb, B.src, plan, part, g, sh);
       } else {
         RecEpi<float, ZMODE, true, false, TAIL == kTailNone ? 4 : 1> epi(ca, cb, vm, B.src);
         const HubView nohub{nullptr, nullptr, 0, nullptr};
@@ -1299,13 +1368,13 @@ hipError_t launch_step_t(hipStream_t s, const CsrMat& m, const T* vk, T* vm, T c
                          bool has_prev, ProbeSrc src, const CsrStepPlan& plan, const HubView& hub,
                          double* part) {
   const dim3 grid(plan.ngroups), block(kThreads);
-  if constexpr (std::is_same<T, float>::value && ZMODE == 0 && TAIL == kTailNone) {
+  if constexpr (ZMODE <= 1 && TAIL == kTailNone) {
     if (has_prev)
-      csr_step_wide_kernel<PATTERN, true, MAXNZ, OFF32><<<grid, block, 0, s>>>(
-          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, banded(m, plan), part);
+      csr_step_wide_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32><<<grid, block, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, banded(m, plan), part);
     else
-      csr_step_wide_kernel<PATTERN, false, MAXNZ, OFF32><<<grid, block, 0, s>>>(
-          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, banded(m, plan), part);
+      csr_step_wide_kernel<T, PATTERN, ZMODE, false, MAXNZ, OFF32><<<grid, block, 0, s>>>(
+          m.rowptr, m.col, m.val, m.nrows, m.nnz, vk, vm, ca, cb, src, banded(m, plan), part);
   } else {
     if (has_prev)
       csr_step_kernel<T, PATTERN, ZMODE, true, MAXNZ, OFF32, TAIL><<<grid, block, 0, s>>>(

@@ -77,6 +77,19 @@ def _grid_adjacency(n: int) -> wl.CSR:
     return wl.CSR(g.d, A.indptr.astype(np.int32), A.indices.astype(np.int32), None)
 
 
+def _with_empty_rows(g: wl.CSR, k: int) -> wl.CSR:
+    """g with row and column i removed (left empty) for every i % k == 0:
+    still symmetric, with empty rows among short ones."""
+    A = g.to_scipy().tocoo()
+    keep = (A.row % k != 0) & (A.col % k != 0)
+    import scipy.sparse as sp
+
+    B = sp.csr_matrix((A.data[keep], (A.row[keep], A.col[keep])), shape=A.shape)
+    B.sort_indices()
+    return wl.CSR(g.d, B.indptr.astype(np.int32), B.indices.astype(np.int32),
+                  B.data.astype(np.float32))
+
+
 CASES = [
     # (name, graph builder, a, b); the row lengths pick the straight-line
     # capacity: <= 4 (lap1d, grid adjacency), <= 5 (lap2d), <= 8 (lap3d),
@@ -85,6 +98,8 @@ CASES = [
     ("lap1d_777", lambda: _lap1d(777), 0.01, 4.01),
     ("grid_pattern_29", lambda: _grid_adjacency(29), -4.01, 4.01),
     ("lap2d_45", lambda: wl.laplacian_2d(45), 0.01, 8.01),
+    # every fifth row empty (eigenvalue 0 enters the interval)
+    ("lap2d_holes_31", lambda: _with_empty_rows(wl.laplacian_2d(31), 5), -0.01, 8.01),
     ("lap3d_11", lambda: wl.laplacian_3d(11), 0.01, 12.01),
     ("random_ragged", lambda: wl.random_csr(301, 0.03, 4), -7.0, 7.0),
     ("chung_lu_pattern", lambda: wl.chung_lu(3000, seed=11), -60.0, 90.0),
