@@ -789,7 +789,9 @@ __global__ __launch_bounds__(kThreads) void csr_step_kernel(
 // coalesced load by a lane permute.  The moment partials are kept per row
 // class (row index in the group mod PPL, one class per lane group) and the
 // classes added in order; in FP32 that is the order of RecEpi with CLS = 4,
-// so this kernel and the lane = probe body give the same bits.
+// so this kernel and the lane = probe body give the same bits.  With SLQ
+// the rows are the product of a Lanczos step instead (the SlqEpi epilogue:
+// u = s (A w) stored, partials of (s w) . u; FP64, no recurrence).
 template <typename T>
 struct WideVec;
 template <>
@@ -833,13 +835,15 @@ using WidePartials = double[2][kWaves][16 / sizeof(T)][64];
 
 // Band g of the wide step: its rows, then its moment partials (sh: the
 // workgroup's LDS for the partials).
-template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
+template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32,
+          bool SLQ = false>
 __device__ __forceinline__ void wide_band(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
     T* __restrict__ vm, T ca, T cb, const ProbeSrc& src, const CsrStepPlan& plan,
-    double* __restrict__ part, int g, WidePartials<T>& sh) {
+    double* __restrict__ part, int g, WidePartials<T>& sh, const double* sdev = nullptr) {
   static_assert(ZMODE == 0 || ZMODE == 1, "symmetric or regenerated direct moments");
+  static_assert(!SLQ || (ZMODE == 0 && !HAS_PREV), "the Lanczos product has no recurrence");
   using V = typename WideVec<T>::V;
   constexpr int PPL = 16 / (int)sizeof(T);  // probes per lane = rows per wave instruction
   constexpr int LPR = 64 / PPL;             // lanes per row
@@ -862,16 +866,19 @@ __device__ __forceinline__ void wide_band(
   double m1[PPL], m2[PPL];
 #pragma unroll
   for (int e = 0; e < PPL; ++e) m1[e] = m2[e] = 0.0;
-  // ZMODE 1: the lane's probe keys, the key of probe PPL sub + q, and the
-  // sign words of the lane's probes for the 64-row chunk `cached` (uniform)
-  uint64_t key[PPL], word[PPL], keyq = 0;
+  // SLQ: the lane's probe scales
+  double sc[PPL];
+  if constexpr (SLQ) {
+#pragma unroll
+    for (int e = 0; e < PPL; ++e) sc[e] = sdev[PPL * sub + e];
+  }
+  // ZMODE 1: the key of probe PPL sub + q and the sign words of the lane's
+  // probes for the 64-row chunk `cached` (uniform)
+  uint64_t word[PPL], keyq = 0;
   int64_t cached = -1;
   if constexpr (ZMODE == 1) {
 #pragma unroll
-    for (int e = 0; e < PPL; ++e) {
-      key[e] = sm_output(src.seed, (uint64_t)(src.first_id + PPL * sub + e));
-      word[e] = 0;
-    }
+    for (int e = 0; e < PPL; ++e) word[e] = 0;
     keyq = sm_output(src.seed, (uint64_t)(src.first_id + PPL * sub + q));
   }
   auto grp_row0 = [&](int64_t k) { return r0 + (k * kWaves + wave) * ROWS; };
@@ -978,7 +985,17 @@ __device__ __forceinline__ void wide_band(
 #pragma unroll
           for (int e = 0; e < PPL; ++e) acc[e] = fma(ww, x[h][t][e], acc[e]);
         }
-        if (PPL * h + q < cur.nr) {
+        if (SLQ && PPL * h + q < cur.nr) {
+          if constexpr (SLQ) {
+            V u;
+#pragma unroll
+            for (int e = 0; e < PPL; ++e) {
+              u[e] = sc[e] * acc[e];
+              m1[e] += (sc[e] * xi[h][e]) * u[e];
+            }
+            __builtin_nontemporal_store(u, reinterpret_cast<V*>(vm_l + row[h] * 64));
+          }
+        } else if (PPL * h + q < cur.nr) {
           V vn;
 #pragma unroll
           for (int e = 0; e < PPL; ++e) {
@@ -994,10 +1011,13 @@ __device__ __forceinline__ void wide_band(
               m2[e] += (double)vn[e] * (double)vn[e];
             }
           } else {
+            // (a group across two chunks: the lane's own keys, rehashed)
             uint64_t wd[PPL];
 #pragma unroll
             for (int e = 0; e < PPL; ++e)
-              wd[e] = one_chunk ? word[e] : sm_output(key[e], (uint64_t)(row[h] >> 6));
+              wd[e] = one_chunk ? word[e]
+                                : sm_output(sm_output(src.seed, (uint64_t)(src.first_id + PPL * sub + e)),
+                                            (uint64_t)(row[h] >> 6));
 #pragma unroll
             for (int e = 0; e < PPL; ++e)
               m1[e] += sign_from_word<double>(wd[e], row[h]) * (double)vn[e];
@@ -1047,8 +1067,13 @@ __device__ __forceinline__ void wide_band(
   }
 }
 
+// FP32 direct form with 32-bit gather offsets: at least 4 waves per SIMD
+// (128 VGPRs; it otherwise takes 132 and drops to 3: 0.729 against 0.673 ms
+// per step on the 2D Laplacian 2048^2; the same bound costs the symmetric
+// form 2 % and makes the 64-bit-offset form spill)
 template <typename T, bool PATTERN, int ZMODE, bool HAS_PREV, int MAXNZ, bool OFF32>
-__global__ __launch_bounds__(kThreads) void csr_step_wide_kernel(
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 && ZMODE == 1 && OFF32 ? 4 : 1) void
+csr_step_wide_kernel(
     const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, int64_t d, int64_t nnz, const T* __restrict__ vk,
     T* __restrict__ vm, T ca, T cb, ProbeSrc src, CsrStepPlan plan, double* __restrict__ part) {
@@ -1091,10 +1116,18 @@ __global__ __launch_bounds__(kThreads) void slq_spmm_kernel(
     const float* __restrict__ val, int64_t d, int64_t nnz, const double* __restrict__ w,
     double* __restrict__ u, const double* __restrict__ sdev, HubView hub, CsrStepPlan plan,
     double* __restrict__ part) {
-  SlqEpi epi(u, sdev);
-  csr_step_wg<double, PATTERN, MAXNZ, false, TAIL, false>(
-      rowptr, col, val, d, d, nnz, RowReader<double, false>(w, d, lane_id()), nullptr, epi, hub,
-      plan, part, blockIdx.x);
+  if constexpr (TAIL == kTailNone) {
+    // rows within the straight-line capacity: the wide form, 2 probes per lane
+    __shared__ WidePartials<double> sh;
+    wide_band<double, PATTERN, 0, false, MAXNZ, false, true>(
+        rowptr, col, val, d, nnz, w, u, 0.0, 0.0, ProbeSrc{}, plan, part,
+        xcd_band(blockIdx.x, plan.ngroups), sh, sdev);
+  } else {
+    SlqEpi epi(u, sdev);
+    csr_step_wg<double, PATTERN, MAXNZ, false, TAIL, false>(
+        rowptr, col, val, d, d, nnz, RowReader<double, false>(w, d, lane_id()), nullptr, epi,
+        hub, plan, part, blockIdx.x);
+  }
 }
 
 // Integer pass of triangle counting over a pattern CSR: PASS 1 gathers the
