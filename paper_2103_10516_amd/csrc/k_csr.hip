@@ -14,6 +14,11 @@
 // per probe and slot; partials are reduced later in a fixed order, so the
 // moments are bitwise reproducible.
 //
+// Operators whose rows all have at most 8 entries take a wide form of the
+// same step (csr_step_wide_kernel, ZMODE 0 and 1): a lane holds 16 bytes of
+// probes and a wave instruction moves several rows, with the same row sums,
+// update and moment summation order as the lane = probe body.
+//
 // The same row machinery runs the integer passes of triangle counting
 // (T = int32, pattern rows, int64 partials): only the per-row epilogue
 // differs, so it is a policy type (RecEpi, TriEpi).
