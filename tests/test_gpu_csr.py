@@ -175,6 +175,29 @@ def test_moments_block_over_4gib(ctx, torch_dev, mode):
     assert worst <= 1.0
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 9])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("mode", ["direct", "doubling"])
+def test_moments_tiny_operators(ctx, torch_dev, d, prec, mode):
+    """Operators of 1 to 9 rows: most workgroups own no row, the one group
+    is partly past the last row, and a lane group's row is clamped."""
+    from paper_2103_10516_amd import mlct
+
+    g = _lap1d(d)
+    n, m, seed = 9, 70, 99
+    op = _op(ctx, torch_dev, g)
+    P = mlct.MLCT_FP64 if prec == "fp64" else mlct.MLCT_FP32
+    M = mlct.MLCT_DOUBLING if mode == "doubling" else mlct.MLCT_DIRECT
+    got = mlct.mlct_moments(ctx, op, 0.01, 4.01, n, mlct.rademacher_probes(seed, m), P, M)
+    op.close()
+    want = _oracle_mu(g, 0.01, 4.01, n, np.arange(m), seed)
+    alpha, beta = cheb.affine_map(0.01, 4.01)
+    kappa = kappa_csr(g, alpha, beta)
+    tol = moment_tol(n, d, U64 if prec == "fp64" else U32, 3, kappa)
+    assert np.all(got[:, 0] == d)
+    assert np.max(np.abs(got - want) / tol[None, :]) <= 1.0
+
+
 def test_hadamard_probes_exact_trace(ctx, torch_dev):
     """Sylvester-Hadamard probes make Hutchinson exact: (1/d) sum_p h_p^T p(A) h_p = tr p(A)."""
     from paper_2103_10516_amd import mlct
